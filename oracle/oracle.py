@@ -1,0 +1,416 @@
+"""CPU FP64 oracle of the randomized-preconditioned EDA hot path.
+
+TEST INFRASTRUCTURE ONLY.  A plain, slow, direct transcription of what the
+paper defines, used to check the HIP library.  Only tests, the smoke check and
+the CPU-baseline leg of the benchmark may import it; the library never does, and
+this module imports nothing from the library.  Its model part (Lorenz-96, RK4,
+TL, AD) is plain C in l96_oracle.c; the linear algebra here uses numpy / LAPACK
+routines as single steps (matmul, FFT, QR, Cholesky, SVD, symmetric EVD).
+
+Conventions.  Matrices are in math orientation (an n x l numpy array holds l
+column vectors).  Member 0 is the control.  The paper's A is the low-rank part
+A = U_B^T G^T R^-1 G U_B; the system matrix is I + A (incremental 4D-Var with
+the control-variable transform, the "system_with_CVT" equation).
+
+Readings taken where the paper is silent (each also listed in the design notes):
+  * observation times exclude t = 0: s = obs_dt, 2 obs_dt, ..., <= N;
+  * B = sigma_b^2 C with C the cyclic Gaussian correlation exp(-d^2 / (2 len^2)),
+    d the cyclic grid distance; U_B is its symmetric square root computed from
+    the circulant spectrum with negative rounding-level eigenvalues clipped to 0,
+    and B is taken as U_B U_B;
+  * control background x^b = x^t_0 + U_B xi_0; members x^b_j = x^b + U_B xi_j,
+    y_j = y + sigma_o eta_j (ensemble-formulation section and experiment set-up);
+  * the truth is spun up from F*1 with N(0, spin_pert_std^2) added to variable 0;
+  * theta "mid" is (lambda_k(I+A) + 1)/2 with lambda_k(I+A) = 1 + d_k;
+  * PCG stops on the recurrence residual ||r|| <= rtol ||b|| from x0 = 0.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+class _Model(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nsteps", ctypes.c_int32), ("F", ctypes.c_double),
+                ("dt", ctypes.c_double), ("obs_dt", ctypes.c_int32), ("obs_dx", ctypes.c_int32),
+                ("obs_x0", ctypes.c_int32), ("sigma_o", ctypes.c_double)]
+
+
+def lib():
+    """The compiled model part; built by oracle/build.py."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIBPATH):
+            raise RuntimeError(f"{_LIBPATH} missing: run `python oracle/build.py`")
+        L = ctypes.CDLL(_LIBPATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        mp = ctypes.POINTER(_Model)
+        i, d = ctypes.c_int, ctypes.c_double
+        for name, args in {
+            "orc_l96_tendency": [i, d, dp, dp],
+            "orc_rk4_step": [i, d, d, dp, dp],
+            "orc_rk4_run": [i, d, d, i, dp],
+            "orc_nl_traj": [mp, dp, dp],
+            "orc_tl_step": [i, d, d, dp, dp, dp],
+            "orc_ad_step": [i, d, d, dp, dp, dp],
+            "orc_tl_window": [mp, dp, dp, dp],
+            "orc_ad_window": [mp, dp, dp, dp],
+            "orc_tl_window_batch": [mp, dp, i, ip, dp, dp],
+            "orc_ad_window_batch": [mp, dp, i, ip, dp, dp],
+            "orc_nl_traj_batch": [mp, i, dp, dp],
+        }.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = None
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _model(cfg) -> _Model:
+    return _Model(cfg["n"], cfg["nsteps"], cfg["F"], cfg["dt"], cfg["obs_dt"], cfg["obs_dx"],
+                  cfg["obs_x0"], cfg["sigma_o"])
+
+
+def obs_counts(cfg) -> tuple[int, int]:
+    nt = cfg["nsteps"] // cfg["obs_dt"]
+    n, x0, dx = cfg["n"], cfg["obs_x0"], cfg["obs_dx"]
+    return nt, (0 if x0 >= n else (n - 1 - x0) // dx + 1)
+
+
+# --------------------------------------------------------------------------
+# Model (numerical-experiments section: Lorenz-96, RK4)
+# --------------------------------------------------------------------------
+def tendency(x: np.ndarray, F: float) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty_like(x)
+    lib().orc_l96_tendency(x.size, F, _p(x), _p(out))
+    return out
+
+
+def rk4_step(x, F, dt):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty_like(x)
+    lib().orc_rk4_step(x.size, F, dt, _p(x), _p(out))
+    return out
+
+
+def rk4_run(x, F, dt, nsteps):
+    x = np.array(x, dtype=np.float64)
+    lib().orc_rk4_run(x.size, F, dt, nsteps, _p(x))
+    return x
+
+
+def tl_step(x, dx, F, dt):
+    x, dx = (np.ascontiguousarray(a, dtype=np.float64) for a in (x, dx))
+    out = np.empty_like(x)
+    lib().orc_tl_step(x.size, F, dt, _p(x), _p(dx), _p(out))
+    return out
+
+
+def ad_step(x, lam, F, dt):
+    x, lam = (np.ascontiguousarray(a, dtype=np.float64) for a in (x, lam))
+    out = np.empty_like(x)
+    lib().orc_ad_step(x.size, F, dt, _p(x), _p(lam), _p(out))
+    return out
+
+
+def nl_traj(cfg, x0) -> np.ndarray:
+    """(N+1) x n stored trajectory from x0."""
+    x0 = np.ascontiguousarray(x0, dtype=np.float64)
+    out = np.empty((cfg["nsteps"] + 1, cfg["n"]))
+    m = _model(cfg)
+    lib().orc_nl_traj(ctypes.byref(m), _p(x0), _p(out))
+    return out
+
+
+def observe(cfg, traj: np.ndarray) -> np.ndarray:
+    """Direct observations H x at the observation times: vector of length p,
+    ordered (time, variable)."""
+    nt, nv = obs_counts(cfg)
+    s = cfg["obs_dt"] * np.arange(1, nt + 1)
+    return traj[s][:, cfg["obs_x0"]::cfg["obs_dx"]][:, :nv].reshape(-1).copy()
+
+
+def G_apply(cfg, traj_all: np.ndarray, members, V: np.ndarray) -> np.ndarray:
+    """Columns G_m v (TL run about member m's trajectory, observed at the
+    observation times).  V: n x nb; returns p x nb."""
+    nt, nv = obs_counts(cfg)
+    members = np.ascontiguousarray(members, dtype=np.int32)
+    Vt = np.ascontiguousarray(V.T)
+    out = np.empty((Vt.shape[0], nt * nv))
+    m = _model(cfg)
+    lib().orc_tl_window_batch(ctypes.byref(m), _p(traj_all), Vt.shape[0],
+                              members.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _p(Vt), _p(out))
+    return out.T.copy()
+
+
+def GT_apply(cfg, traj_all: np.ndarray, members, W: np.ndarray) -> np.ndarray:
+    """Columns G_m^T w (AD run).  W: p x nb; returns n x nb."""
+    members = np.ascontiguousarray(members, dtype=np.int32)
+    Wt = np.ascontiguousarray(W.T)
+    out = np.empty((Wt.shape[0], cfg["n"]))
+    m = _model(cfg)
+    lib().orc_ad_window_batch(ctypes.byref(m), _p(traj_all), Wt.shape[0],
+                              members.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _p(Wt), _p(out))
+    return out.T.copy()
+
+
+# --------------------------------------------------------------------------
+# Background-error covariance (incremental 4D-Var section; experiment set-up)
+# --------------------------------------------------------------------------
+def correlation_row(n: int, len_b: float) -> np.ndarray:
+    """First row of the cyclic Gaussian correlation: c(d) = exp(-d^2/(2 len^2)),
+    d = min(i, n - i)."""
+    i = np.arange(n)
+    d = np.minimum(i, n - i).astype(np.float64)
+    return np.exp(-d * d / (2.0 * len_b * len_b))
+
+
+def ub_row(n: int, sigma_b: float, len_b: float) -> np.ndarray:
+    """First row r of U_B (U_B[i, j] = r[(i - j) mod n]): the symmetric square
+    root of sigma_b^2 C, from the circulant spectrum mu = DFT(c) with negative
+    (rounding-level) eigenvalues clipped to zero.  r(d) is taken at the cyclic
+    distance min(d, n - d), so U_B = U_B^T holds exactly."""
+    mu = np.fft.fft(correlation_row(n, len_b)).real
+    r = sigma_b * np.fft.ifft(np.sqrt(np.maximum(mu, 0.0))).real
+    i = np.arange(n)
+    return r[np.minimum(i, n - i)]
+
+
+def build_ub(n: int, sigma_b: float, len_b: float) -> np.ndarray:
+    r = ub_row(n, sigma_b, len_b)
+    i = np.arange(n)
+    return r[(i[:, None] - i[None, :]) % n]
+
+
+# --------------------------------------------------------------------------
+# EDA problem set-up (ensemble-formulation section; experiment set-up)
+# --------------------------------------------------------------------------
+class Problem:
+    """Everything eda_setup produces for one EDA problem, in FP64."""
+
+    def __init__(self, cfg, normals):
+        self.cfg = dict(cfg)
+        n, N, L = cfg["n"], cfg["nsteps"], cfg["members"]
+        nt, nv = obs_counts(cfg)
+        p = nt * nv
+        self.p = p
+        normals = np.asarray(normals, dtype=np.float64)
+        z = normals[0]
+        xi = normals[1:1 + (L + 1) * n].reshape(L + 1, n).T          # n x (L+1)
+        eta = normals[1 + (L + 1) * n:].reshape(L + 1, p).T           # p x (L+1)
+        # truth: spin-up from F*1 perturbed at variable 0, then the window run
+        x = np.full(n, cfg["F"])
+        x[0] = x[0] + cfg["spin_pert_std"] * z
+        self.xt0 = rk4_run(x, cfg["F"], cfg["dt"], cfg["spinup"])
+        self.xt_traj = nl_traj(cfg, self.xt0)
+        # observations y = H x^t + sigma_o eta_0; members y_j = y + sigma_o eta_j
+        y = observe(cfg, self.xt_traj) + cfg["sigma_o"] * eta[:, 0]
+        Y = np.empty((p, L + 1))
+        Y[:, 0] = y
+        Y[:, 1:] = y[:, None] + cfg["sigma_o"] * eta[:, 1:]
+        self.y = Y
+        # U_B and backgrounds
+        self.ub = build_ub(n, cfg["sigma_b"], cfg["len_b"])
+        UX = self.ub @ xi
+        xb = self.xt0 + UX[:, 0]
+        XB = np.empty((n, L + 1))
+        XB[:, 0] = xb
+        XB[:, 1:] = xb[:, None] + UX[:, 1:]
+        self.xb = XB
+        # member trajectories (member-major, (L+1) x (N+1) x n)
+        self.traj = np.stack([nl_traj(cfg, XB[:, j]) for j in range(L + 1)])
+        # innovations d_j = y_j - H(x_j traj) and right-hand sides
+        # b_j = U_B^T G_j^T R^-1 d_j
+        D = np.stack([Y[:, j] - observe(cfg, self.traj[j]) for j in range(L + 1)], axis=1)
+        self.d = D
+        members = np.arange(L + 1)
+        self.b = self.ub.T @ GT_apply(cfg, self.traj, members, D / cfg["sigma_o"] ** 2)
+        # constant of the quadratic cost: c_j = 1/2 d_j^T R^-1 d_j
+        self.cost_c = 0.5 * np.sum(D * D, axis=0) / cfg["sigma_o"] ** 2
+
+    # ---- operators ----
+    def A(self, X: np.ndarray, members) -> np.ndarray:
+        """Columns A_m x = U_B^T G_m^T R^-1 G_m U_B x."""
+        X = np.asarray(X, dtype=np.float64)
+        cfg = self.cfg
+        V = self.ub @ X
+        W = G_apply(cfg, self.traj, members, V) / cfg["sigma_o"] ** 2
+        return self.ub.T @ GT_apply(cfg, self.traj, members, W)
+
+    def hess(self, X: np.ndarray, members) -> np.ndarray:
+        """Columns (I + A_m) x."""
+        return X + self.A(X, members)
+
+    def gamma(self, ell: int) -> np.ndarray:
+        """RHS-difference sketch Gamma = [b_1 - b_0, ..., b_ell - b_0]
+        (sketch from the EDA structure, the Gamma equation)."""
+        return self.b[:, 1:ell + 1] - self.b[:, [0]]
+
+    def cost(self, m: int, dz: np.ndarray) -> np.ndarray:
+        """Quadratic cost J(dx) of the incremental problem with dx = U_B dz,
+        written in the control variable: 1/2 dz^T dz + 1/2 ||G U_B dz - d||^2_R^-1."""
+        cfg = self.cfg
+        Gv = G_apply(cfg, self.traj, [m] * dz.shape[1], self.ub @ dz)
+        res = Gv - self.d[:, [m]]
+        return 0.5 * np.sum(dz * dz, axis=0) + 0.5 * np.sum(res * res, axis=0) / cfg["sigma_o"] ** 2
+
+
+# --------------------------------------------------------------------------
+# Randomized low-rank approximation (the q-pass Nystrom algorithm; REVD)
+# --------------------------------------------------------------------------
+def qr_pos(Y: np.ndarray):
+    """Economic QR with a positive diagonal of R (unique for full-rank Y)."""
+    Q, R = np.linalg.qr(Y)
+    s = np.where(np.diag(R) < 0, -1.0, 1.0)
+    return Q * s, R * s[:, None]
+
+
+def fix_signs(S: np.ndarray) -> np.ndarray:
+    """Sign convention for eigenvector columns: the entry of largest magnitude
+    (lowest index on ties) is positive."""
+    idx = np.argmax(np.abs(S), axis=0)
+    s = np.where(S[idx, np.arange(S.shape[1])] < 0, -1.0, 1.0)
+    return S * s
+
+
+def nystrom(Aop, Phi: np.ndarray, k: int, q: int = 1):
+    """The q-pass Nystrom approximation (the paper's Algorithm 1) of a symmetric
+    positive semidefinite A given through Aop(X) = A X.
+
+    Returns (S_k, D_k, info): S_k n x k with orthonormal columns, D_k the k
+    largest approximate eigenvalues (descending), info = {"shift": nu}.
+    Breakdown of the Cholesky factorisation is handled by the shift of the
+    appendix on Nystrom variants: Y <- Y + nu Phi with nu = eps ||Y||_F, and
+    nu subtracted from the squared singular values.
+    """
+    Y = Aop(Phi)                                  # sketch Y = A Phi
+    Q, R = qr_pos(Y)                              # economic QR
+    for _ in range(2, q + 1):                     # power passes
+        Phi = Q
+        Y = Aop(Phi)
+        Q, R = qr_pos(Y)
+    nu = 0.0
+    W = Phi.T @ Y                                 # W = Phi^T Y
+    W = 0.5 * (W + W.T)
+    try:
+        C = np.linalg.cholesky(W).T               # W = C^T C, C upper triangular
+    except np.linalg.LinAlgError:
+        nu = np.finfo(np.float64).eps * np.linalg.norm(Y)
+        Y = Y + nu * Phi
+        Q, R = qr_pos(Y)
+        W = Phi.T @ Y
+        W = 0.5 * (W + W.T)
+        C = np.linalg.cholesky(W).T
+    T = np.linalg.solve(C.T, R.T).T               # T = R_Y C^-1
+    U, sig, _ = np.linalg.svd(T)                  # economic SVD, descending
+    S = fix_signs(Q @ U)                          # S = Q_Y U_T
+    D = np.maximum(sig * sig - nu, 0.0)           # D = Sigma_T^2
+    return S[:, :k], D[:k], {"shift": nu}
+
+
+def revd(Aop, Phi: np.ndarray, k: int):
+    """Two-stage randomized EVD with a Rayleigh-Ritz projection (randomized
+    eigendecomposition subsection): Q = orth(A Phi), T = Q^T A Q, T = V L V^T,
+    S = Q V.  Returns (S_k, D_k)."""
+    Q, _ = qr_pos(Aop(Phi))
+    Z = Aop(Q)
+    T = Q.T @ Z
+    T = 0.5 * (T + T.T)
+    lam, V = np.linalg.eigh(T)
+    order = np.argsort(-lam, kind="stable")
+    S = fix_signs(Q @ V[:, order])
+    return S[:, :k], lam[order][:k]
+
+
+def theta(D: np.ndarray, rule: str = "mid") -> float:
+    """Scaling of the spectral LMP (spectral LMP subsection; sensitivity study):
+    'mid' (lambda_k(I+A) + 1)/2, 'lamk' lambda_k(I+A), 'one' 1, with
+    lambda_k(I+A) = 1 + d_k."""
+    lk = 1.0 + float(D[-1])
+    return {"mid": 0.5 * (lk + 1.0), "lamk": lk, "one": 1.0}[rule]
+
+
+def lmp_apply(S: np.ndarray, D: np.ndarray, th: float, X: np.ndarray, which: str = "P") -> np.ndarray:
+    """P_theta X = X + S (theta (D + I)^-1 - I) S^T X, or the symmetric factor
+    U_theta X = X + S (sqrt(theta) (D + I)^-1/2 - I) S^T X (the lmp equation)."""
+    if which == "P":
+        c = th / (1.0 + D) - 1.0
+    else:
+        c = np.sqrt(th) / np.sqrt(1.0 + D) - 1.0
+    return X + S @ (c[:, None] * (S.T @ X))
+
+
+# --------------------------------------------------------------------------
+# Preconditioned conjugate gradients (solving-linear-systems section)
+# --------------------------------------------------------------------------
+CONVERGED, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
+
+
+def pcg(Hop, b: np.ndarray, Pop=None, rtol: float = 1e-6, maxit: int = 1000):
+    """PCG on (I + A) x = b from x0 = 0 with preconditioner Pop (None: identity).
+
+    Textbook recurrences: r = b, z = P r, p = z, rho = r^T z; per iteration
+    q = H p, alpha = rho / p^T q, x += alpha p, r -= alpha q, stop if
+    ||r|| <= rtol ||b||, z = P r, rho' = r^T z, p = z + (rho'/rho) p.
+    Breakdown (p^T q <= 0, rho' <= 0, or a non-finite value) stops with status 2.
+    Also returns the quadratic-cost history J_i - c = -1/2 x_i^T (b + r_i),
+    i = 0..iters (c the constant 1/2 d^T R^-1 d).
+    """
+    P = (lambda v: v) if Pop is None else Pop
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = P(r)
+    p = z.copy()
+    rho = float(r @ z)
+    bnorm = float(np.sqrt(b @ b))
+    hist = [0.0]
+    status, it = NOT_CONVERGED, 0
+    if bnorm == 0.0:
+        return x, 0, 0.0, CONVERGED, np.array(hist)
+    for it in range(1, maxit + 1):
+        q = Hop(p)
+        pq = float(p @ q)
+        if not (pq > 0.0) or not np.isfinite(pq):
+            status, it = BREAKDOWN, it - 1
+            break
+        alpha = rho / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        hist.append(-0.5 * float(x @ (b + r)))
+        rn = float(np.sqrt(r @ r))
+        if rn <= rtol * bnorm:
+            status = CONVERGED
+            break
+        z = P(r)
+        rho_new = float(r @ z)
+        if not (rho_new > 0.0) or not np.isfinite(rho_new):
+            status = BREAKDOWN
+            break
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+    relres = float(np.sqrt(r @ r)) / bnorm
+    return x, it, relres, status, np.array(hist)
+
+
+def exact_solution(prob: Problem, m: int) -> np.ndarray:
+    """The plain definition of a member's result: the exact solution of
+    (I + A_m) dz = b_m, by assembling I + A_m column by column and a Cholesky
+    solve."""
+    n = prob.cfg["n"]
+    H = prob.hess(np.eye(n), [m] * n)
+    H = 0.5 * (H + H.T)
+    Lc = np.linalg.cholesky(H)
+    return np.linalg.solve(Lc.T, np.linalg.solve(Lc, prob.b[:, m]))
