@@ -1,0 +1,225 @@
+/*
+ * eda.h -- C ABI of the MI355X (gfx950) library for the data-parallel hot path
+ * of a randomized-preconditioned ensemble of incremental 4D-Var assimilations
+ * (Dauzickaite, Gurol, Destouches, Berre, Weaver: "Accelerating an ensemble of
+ * variational data assimilations with randomized preconditioning").
+ *
+ * Problem (incremental 4D-Var with the control-variable transform, the
+ * system_with_CVT equation): every ensemble member j = 0..L (0 = control)
+ * solves   (I + A_j) dz_j = b_j,   A_j = U_B^T G_j^T R^-1 G_j U_B,
+ *          b_j = U_B^T G_j^T R^-1 d_j,
+ * where G_j is the Lorenz-96 RK4 tangent-linear model linearised about member
+ * j's own background trajectory followed by direct observation, R = sigma_o^2 I
+ * and B = U_B U_B.  A here is the paper's low-rank part; the system matrix is
+ * I + A.
+ *
+ * Conventions for every call:
+ *  - Matrices are column-major: column c of an n x nb matrix X starts at
+ *    X + c * ldx, with ldx >= n.  A contiguous torch tensor of shape [nb, n]
+ *    passes as is with ldx = n.
+ *  - Pointers named d_* are device pointers on the GPU that is current when the
+ *    context is created; h_* are host pointers.  The caller owns every buffer
+ *    it passes, including the workspace; the library never allocates device
+ *    memory on its own (it allocates small host structures only).
+ *  - All work is enqueued on the stream given to eda_setup (a hipStream_t,
+ *    passed as void*).  Calls that return values through h_* pointers
+ *    synchronise that stream before they return; the others are asynchronous.
+ *  - Return value: EDA_OK (0), a negative error code, or a positive warning.
+ *    No C++ exception crosses the ABI.  eda_strerror maps a code to static
+ *    text.  A context is bound to one stream and is not thread-safe.
+ */
+#ifndef EDA_H
+#define EDA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define EDA_OK                  0
+#define EDA_ERR_INVALID_ARG    -1  /* a size, pointer, leading dimension or option is invalid */
+#define EDA_ERR_WORKSPACE      -2  /* workspace smaller than eda_workspace_bytes reports      */
+#define EDA_ERR_HIP            -3  /* a HIP runtime call failed                                */
+#define EDA_ERR_NOT_SPD        -4  /* Cholesky of Phi^T A Phi failed even after the shift      */
+#define EDA_ERR_ORDER          -5  /* LMP requested before eda_sketch_evd built one            */
+#define EDA_ERR_UNSUPPORTED    -6  /* option not supported by this build (sizes, modes)        */
+#define EDA_WARN_NOT_CONVERGED  1  /* eda_pcg_solve: some member hit maxit or broke down      */
+
+/* ---- per-member PCG outcome (h_status of eda_pcg_solve) ---- */
+#define EDA_MEMBER_CONVERGED      0
+#define EDA_MEMBER_NOT_CONVERGED  1
+#define EDA_MEMBER_BREAKDOWN      2  /* p^T (I+A) p <= 0, r^T z <= 0 or a non-finite value */
+
+/* ---- options ---- */
+#define EDA_UB_DENSE   0   /* U_B products as dense FP64 MFMA GEMMs (n x n matrix stored)   */
+#define EDA_UB_BANDED  1   /* U_B products as a cyclic banded convolution over the taps of  */
+                           /* U_B's first row that exceed 2^-60 |r(0)|                        */
+
+#define EDA_HV_ADD_IDENTITY  1u  /* eda_hessvec returns (I + A) X instead of A X           */
+#define EDA_HV_MIXED         2u  /* FP32 tangent-linear/adjoint runs (sketch products only) */
+
+#define EDA_SKETCH_RHS_DIFF  0   /* Phi = Gamma = [b_1 - b_0, ..., b_ell - b_0] (Gamma eq.) */
+#define EDA_SKETCH_USER      1   /* Phi = d_phi (e.g. a Gaussian Psi drawn by the caller)   */
+#define EDA_SKETCH_B_PSI     2   /* Phi = U_B^T U_B Psi = B Psi, Psi = d_phi                */
+#define EDA_SKETCH_UBT_PSI   3   /* Phi = U_B^T Psi, Psi = d_phi                            */
+
+#define EDA_METHOD_NYSTROM   0   /* Algorithm 1 (q-pass Nystrom)                            */
+#define EDA_METHOD_REVD      1   /* Rayleigh-Ritz REVD: Q = orth(A Phi), eig(Q^T A Q)        */
+
+#define EDA_THETA_MID   0        /* theta = (lambda_k(I+A) + 1) / 2                          */
+#define EDA_THETA_LAMK  1        /* theta = lambda_k(I+A)                                    */
+#define EDA_THETA_ONE   2        /* theta = 1                                                */
+
+#define EDA_LMP_P  0             /* apply P_theta                                            */
+#define EDA_LMP_U  1             /* apply the symmetric factor U_theta                       */
+
+/* ---- problem description ----
+ * Lorenz-96 (numerical-experiments section): n >= 4 cyclic variables, forcing F,
+ * RK4 step dt, window of nsteps steps.  Observations (direct, R = sigma_o^2 I)
+ * at steps s = obs_dt, 2 obs_dt, ..., <= nsteps (time 0 is not observed) of the
+ * variables i = obs_x0 + q obs_dx < n.  B = sigma_b^2 C, C the cyclic Gaussian
+ * correlation exp(-d^2 / (2 len_b^2)); U_B is its symmetric root in closed form,
+ * the cyclic Gaussian r(d) = sigma_b (2/pi)^(1/4) len_b^(-1/2) exp(-d^2/len_b^2)
+ * (U_B U_B = B to 5e-9 relative for len_b >= 2, which is required).
+ * Truth: spin-up of `spinup` RK4 steps from F * 1 with spin_pert_std * z added
+ * to variable 0.  members = L perturbed members (identical-twin set-up of the
+ * experiments).  max_cols bounds the number of columns of one eda_hessvec call
+ * and of one eda_pcg_solve call (0 selects max(L + 1, 2 * max_ell)); max_ell
+ * bounds the sketch width (<= 128). */
+typedef struct {
+    int32_t n;
+    int32_t nsteps;
+    double  F;
+    double  dt;
+    int32_t spinup;
+    double  spin_pert_std;
+    int32_t obs_dt, obs_dx, obs_x0;
+    double  sigma_o;
+    double  sigma_b, len_b;
+    int32_t members;
+    int32_t max_ell;
+    int32_t max_cols;
+    int32_t ub_mode;     /* EDA_UB_DENSE or EDA_UB_BANDED */
+} eda_config;
+
+typedef struct eda_ctx eda_ctx;
+
+/* Bytes of device workspace a context for `cfg` needs (256-byte aligned
+ * sub-buffers).  Errors: EDA_ERR_INVALID_ARG for an invalid configuration. */
+int eda_workspace_bytes(const eda_config *cfg, size_t *bytes);
+
+/* Number of standard normals eda_setup consumes: 1 + (L+1)(n+p), p the number
+ * of observations. */
+int eda_normals_count(const eda_config *cfg, int64_t *count);
+
+/* Build one EDA problem on the device (ensemble-formulation section and the
+ * experiment set-up):
+ *   truth x^t: spin-up, then the window trajectory;
+ *   observations y = H x^t + sigma_o eta_0, member j: y_j = y + sigma_o eta_j;
+ *   backgrounds x^b = x^t_0 + U_B xi_0, x^b_j = x^b + U_B xi_j;
+ *   member trajectories X_j[s], s = 0..N (the linearisation states of G_j);
+ *   innovations d_j = y_j - H(X_j), right-hand sides b_j = U_B^T G_j^T R^-1 d_j;
+ *   cost constants c_j = 1/2 d_j^T R^-1 d_j.
+ * d_normals: device array of eda_normals_count doubles laid out as
+ *   [z][xi_0 .. xi_L (n each)][eta_0 .. eta_L (p each)].
+ * d_ws / ws_bytes: caller-owned device workspace of at least
+ * eda_workspace_bytes; it must outlive the context.  stream: hipStream_t.
+ * Synchronises the stream.  On success *out receives the context. */
+int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t ws_bytes,
+              void *stream, eda_ctx **out);
+
+/* Batched Hessian products (the system_with_CVT equation): column c of
+ * Y is A_m x_c, or (I + A_m) x_c with EDA_HV_ADD_IDENTITY, where m =
+ * d_col_member[c] (device int32 array of nb entries, 0 <= m <= L) selects the
+ * linearisation trajectory.  A_m x = U_B^T G_m^T R^-1 G_m U_B x: a U_B product,
+ * a TL run over the window writing the observed increments, an AD run forced
+ * by them, and a U_B^T product.  nb <= max_cols; X and Y must not overlap.
+ * EDA_HV_MIXED runs the TL/AD in FP32 (accuracy stated in the design notes;
+ * meant for sketch products only). */
+int eda_hessvec(eda_ctx *ctx, const int32_t *d_col_member, int32_t nb,
+                const double *d_X, int64_t ldx, double *d_Y, int64_t ldy, uint32_t flags);
+
+/* Randomized eigendecomposition of the control member's A (preconditioning
+ * with randomized algorithms section) and the spectral LMP built from it.
+ * kind: EDA_SKETCH_* (d_phi, ldphi: the n x ell user matrix or Psi; ignored for
+ * EDA_SKETCH_RHS_DIFF, which uses the first ell perturbed members' RHS
+ * differences, ell <= L).  method EDA_METHOD_NYSTROM runs Algorithm 1 with q
+ * passes (sketch Y = A Phi, CholQR2 of Y, W = Phi^T Y, Cholesky W = C^T C with
+ * the shift nu = 2^-52 ||Y||_F on breakdown, T = R_Y C^-1, SVD T = U Sigma V^T,
+ * S = Q_Y U, D = Sigma^2, truncation to k); EDA_METHOD_REVD runs
+ * Q = orth(A Phi), T = Q^T A Q, T = V D V^T, S = Q V (q ignored).
+ * theta_rule: EDA_THETA_*.  flags: 0 or EDA_HV_MIXED for the sketch products.
+ * The context keeps S_k, D_k and theta for eda_lmp_apply / eda_pcg_solve.
+ * h_eig (k doubles, may be NULL): D_k, descending; h_theta (may be NULL).
+ * 1 <= k <= ell <= max_ell, q >= 1.  Synchronises the stream.
+ * Errors: EDA_ERR_NOT_SPD if the shifted Cholesky fails too. */
+int eda_sketch_evd(eda_ctx *ctx, int32_t kind, const double *d_phi, int64_t ldphi,
+                   int32_t ell, int32_t k, int32_t q, int32_t method, int32_t theta_rule,
+                   uint32_t flags, double *h_eig, double *h_theta);
+
+/* Spectral LMP (the spectral LMP subsection and the lmp equation):
+ * which = EDA_LMP_P:  Y = P_theta X = X + S_k (theta (D_k + I)^-1 - I) S_k^T X;
+ * which = EDA_LMP_U:  Y = U_theta X = X + S_k (sqrt(theta) (D_k + I)^-1/2 - I) S_k^T X.
+ * nb <= max_cols; X and Y must not overlap.  EDA_ERR_ORDER before a sketch. */
+int eda_lmp_apply(eda_ctx *ctx, int32_t which, int32_t nb, const double *d_X, int64_t ldx,
+                  double *d_Y, int64_t ldy);
+
+/* Batched PCG (solving-linear-systems section) for members h_members[0..nm-1]
+ * (host array, each in 0..L, nm <= max_cols), from dz = 0, preconditioned by
+ * the context's P_theta when use_lmp != 0 (EDA_ERR_ORDER if none was built) or
+ * by the identity.  Member c stops when ||r||_2 <= rtol ||b||_2 (recurrence
+ * residual) or after maxit iterations (rtol = 0 runs exactly maxit unless a
+ * breakdown occurs).  Solutions go to column c of d_DZ (n x nm, ldz).
+ * h_iters, h_relres, h_status: nm entries each (required).  h_cost_hist: NULL
+ * or nm * (maxit + 1) doubles, row c holding J_i - c_m = -1/2 x_i^T (b + r_i)
+ * for i = 0..iters (the quadratic cost of the incremental problem minus its
+ * constant), NaN after the last iteration.  Synchronises the stream.
+ * Returns EDA_WARN_NOT_CONVERGED if any member did not converge. */
+int eda_pcg_solve(eda_ctx *ctx, const int32_t *h_members, int32_t nm, double rtol, int32_t maxit,
+                  int32_t use_lmp, double *d_DZ, int64_t ldz, int32_t *h_iters, double *h_relres,
+                  int32_t *h_status, double *h_cost_hist);
+
+/* Read-only views of what eda_setup and eda_sketch_evd stored in the
+ * workspace: byte offset into d_ws and element count (doubles).
+ *   EDA_FIELD_TRUTH  (N+1) x n truth trajectory, step-major
+ *   EDA_FIELD_XB     n x (L+1) backgrounds
+ *   EDA_FIELD_TRAJ   (L+1) x (N+1) x n member trajectories
+ *   EDA_FIELD_Y      p x (L+1) observations (time-major within a column)
+ *   EDA_FIELD_D      p x (L+1) innovations
+ *   EDA_FIELD_B      n x (L+1) right-hand sides
+ *   EDA_FIELD_COSTC  L+1 cost constants
+ *   EDA_FIELD_UBROW  n, first row of U_B
+ *   EDA_FIELD_S      n x k eigenvector estimates of the last sketch
+ *   EDA_FIELD_EIG    k eigenvalue estimates of the last sketch */
+#define EDA_FIELD_TRUTH  0
+#define EDA_FIELD_XB     1
+#define EDA_FIELD_TRAJ   2
+#define EDA_FIELD_Y      3
+#define EDA_FIELD_D      4
+#define EDA_FIELD_B      5
+#define EDA_FIELD_COSTC  6
+#define EDA_FIELD_UBROW  7
+#define EDA_FIELD_S      8
+#define EDA_FIELD_EIG    9
+int eda_field(const eda_ctx *ctx, int32_t field, size_t *byte_offset, int64_t *count);
+
+/* Opt-in timing of the tangent-linear/adjoint kernel with HIP events recorded
+ * on the context's stream around each of its launches.  eda_profile(ctx, 1)
+ * starts (and clears) the accounting; eda_profile_read synchronises and returns
+ * the number of launches and their summed duration in milliseconds. */
+int eda_profile(eda_ctx *ctx, int32_t enable);
+int eda_profile_read(eda_ctx *ctx, int64_t *launches, double *total_ms);
+
+/* Free the context's host structures (the workspace stays the caller's). */
+int eda_destroy(eda_ctx *ctx);
+
+/* Static description of a status code. */
+const char *eda_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EDA_H */

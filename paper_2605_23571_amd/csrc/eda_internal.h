@@ -1,0 +1,162 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/eda.h"
+
+namespace eda {
+
+// Device-side PCG column state.
+enum : int32_t { COL_RUNNING = -1 };
+
+// Everything a context knows; device pointers point into the caller's workspace.
+struct Layout {
+    size_t total = 0;
+    size_t take(size_t bytes) {  // 256-byte aligned sub-buffer
+        size_t off = total;
+        total += (bytes + 255) & ~size_t(255);
+        return off;
+    }
+};
+
+struct Ctx {
+    eda_config cfg{};
+    int n = 0, N = 0, L = 0, nt = 0, nv = 0, p = 0;
+    int max_cols = 0, max_ell = 0;
+    int band_lo = 0, band_hi = 0;  // tap offsets of the banded U_B product
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+
+    // problem data
+    double *ubrow = nullptr, *ub = nullptr, *truth = nullptr, *xb = nullptr, *traj = nullptr;
+    double *y = nullptr, *d = nullptr, *b = nullptr, *costc = nullptr, *forcing = nullptr;
+    // hessvec scratch
+    double *hv_v = nullptr, *hv_obs = nullptr, *hv_lam = nullptr;
+    int32_t *zero_members = nullptr;  // max_cols zeros (sketch mode)
+    // sketch scratch
+    double *sk_phi = nullptr, *sk_y = nullptr, *sk_q = nullptr, *sk_q1 = nullptr, *sk_s = nullptr;
+    double *sk_small = nullptr;  // 8 ell x ell matrices
+    double *sk_eig = nullptr, *sk_coef = nullptr, *sk_coefu = nullptr;
+    int32_t *sk_info = nullptr;
+    double *lmp_t = nullptr;   // k x max_cols LMP coefficients S_k^T X
+    double *splitk = nullptr;  // split-K partial sums
+    size_t splitk_elems = 0;
+    // pcg scratch
+    double *pc_x = nullptr, *pc_r = nullptr, *pc_z = nullptr, *pc_p = nullptr, *pc_q = nullptr;
+    double *pc_scal = nullptr;  // per column: rho, bnorm, relres, spare
+    int32_t *pc_status = nullptr, *pc_iters = nullptr, *pc_members = nullptr;
+    double *pc_hist = nullptr;
+    int hist_cap = 0;
+    int32_t *h_pinned_status = nullptr;
+
+    // LMP state
+    bool have_lmp = false;
+    int k = 0;
+    double theta = 1.0;
+
+    // profiling of the TL/AD kernel
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    int64_t prof_launches = 0;
+    size_t ev_used = 0;
+};
+
+// ---- launchers (each enqueues on s and returns hipGetLastError()) ----
+
+// Nonlinear RK4 integration, one workgroup per vector, bit-for-bit the order
+// of operations documented in l96_nl.hip.  x0: n x nvec (ld n).  If store is
+// non-null the states after steps 0..nsteps are written to store[v][s][i];
+// xend (optional) receives the final states.
+hipError_t launch_nl(hipStream_t s, int n, int nvec, int nsteps, double F, double h, double dt,
+                     double c6, const double *x0, double *store, double *xend);
+// Truth spin-up start: x = F * 1, x[0] = F + std * z[0].
+hipError_t launch_spin_init(hipStream_t s, int n, double F, double std_, const double *z, double *x);
+
+// Fused TL forward + AD backward about stored trajectories (mode 0), or AD
+// only with given forcing (mode 1).  Columns with active[c] != COL_RUNNING are
+// skipped when active is non-null.
+struct TladArgs {
+    int n, N, nb;
+    double F, dt, h, dt6, dt3;
+    int obs_dt, obs_dx, obs_x0, nt, nv;
+    double inv_s2;
+    const double *traj;
+    long long traj_stride;
+    const int32_t *col_member;
+    const int32_t *active;
+    const double *V;
+    long long ldv;
+    double *obs;          // p x nb scratch (mode 0)
+    const double *force;  // p x nb forcing (mode 1)
+    double *lam;
+    long long ldl;
+};
+hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32);
+
+// U_B first row (closed form) and dense fill.
+hipError_t launch_ub_row(hipStream_t s, int n, double sigma_b, double len_b, double *row);
+hipError_t launch_ub_fill(hipStream_t s, int n, const double *row, double *ub);
+// Y = U_B X (+ Add) with U_B circulant banded: taps o in [lo, hi], r(|o|).
+hipError_t launch_band_conv(hipStream_t s, int n, int nb, int lo, int hi, const double *row,
+                            const double *X, long long ldx, double *Y, long long ldy,
+                            const double *Add, long long ldadd, const int32_t *active);
+
+// FP64 MFMA GEMM: C = op(A) B (+ Add), col-major.  trans_a: op(A) = A^T with
+// A stored K x M.  Split-K (when work is K-long and M, N small) uses `part`
+// (>= nsplit * M * N doubles) and a deterministic ordered reduction; rowscale
+// (optional, M entries) multiplies row i of the product before Add.
+hipError_t gemm_f64(hipStream_t s, bool trans_a, int M, int N, int K, const double *A, long long lda,
+                    const double *B, long long ldb, double *C, long long ldc, const double *Add,
+                    long long ldadd, const double *rowscale, double *part, size_t part_elems);
+size_t gemm_splitk_elems(int M, int N, int K);
+
+// Setup helpers.
+hipError_t launch_obs(hipStream_t s, int n, int L, int p, int nv, int obs_dt, int obs_dx, int obs_x0,
+                      double sigma_o, const double *truth, const double *eta, double *y);
+hipError_t launch_xb(hipStream_t s, int n, int L, const double *xt0, const double *ux, double *xb);
+hipError_t launch_innov(hipStream_t s, int n, int N, int L, int p, int nv, int obs_dt, int obs_dx,
+                        int obs_x0, double s2, const double *y, const double *traj, double *d,
+                        double *force, double *costc);
+hipError_t launch_gamma(hipStream_t s, int n, int ell, const double *b, double *gam);
+
+// Small dense kernels (one workgroup, ell <= 128, matrices col-major ell x ell).
+hipError_t launch_chol_inv(hipStream_t s, int l, const double *W, double shift, double *C,
+                           double *Cinv, int32_t *info);
+hipError_t launch_sym(hipStream_t s, int l, double *W);
+hipError_t launch_small_gemm(hipStream_t s, int l, bool ta, bool tb, const double *A, const double *B,
+                             double *C);
+hipError_t launch_jacobi_svd_u(hipStream_t s, int l, double *T, double *U, double *sig);
+hipError_t launch_jacobi_eig(hipStream_t s, int l, double *T, double *Vwork, double *V, double *lam);
+hipError_t launch_fix_signs(hipStream_t s, int n, int k, double *S, long long lds);
+hipError_t launch_lmp_coef(hipStream_t s, int k, const double *sig, double nu, int square,
+                           int theta_rule, double *eig, double *coef, double *coefu, double *theta_out);
+hipError_t launch_axpy_cols(hipStream_t s, int n, int nb, double alpha, const double *X, long long ldx,
+                            double *Y, long long ldy);
+hipError_t launch_copy_cols(hipStream_t s, int n, int nb, const double *X, long long ldx, double *Y,
+                            long long ldy);
+
+// PCG kernels (one workgroup per column).
+struct PcgArgs {
+    int n, nb;
+    const int32_t *members;
+    const double *b;  // n x (L+1)
+    double *x, *r, *z, *p, *q;
+    double *scal;      // 4 per column: rho, bnorm, relres, spare
+    int32_t *status, *iters;
+    double *hist;
+    int hist_cap;
+    double rtol;
+};
+hipError_t launch_pcg_init(hipStream_t s, const PcgArgs &a);
+hipError_t launch_pcg_start(hipStream_t s, const PcgArgs &a);
+hipError_t launch_pcg_alpha(hipStream_t s, const PcgArgs &a, int it);
+hipError_t launch_pcg_beta(hipStream_t s, const PcgArgs &a);
+hipError_t launch_pcg_finish(hipStream_t s, const PcgArgs &a);
+
+}  // namespace eda

@@ -1,0 +1,384 @@
+// Small dense kernels of the randomized eigendecomposition (Algorithm 1 and the
+// REVD variant): ell x ell Cholesky with the inverse of its factor, products of
+// small matrices, one-sided Jacobi SVD, two-sided Jacobi symmetric EVD, column
+// sign normalisation and the spectral-LMP coefficients.  ell <= 128; each runs
+// on one workgroup with the working matrix in LDS.  All orderings and
+// reductions are fixed, so results are reproducible run to run.
+#include "eda_internal.h"
+
+namespace eda {
+namespace {
+
+constexpr int ST = 256;  // threads of the small kernels
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return __shfl(v, 0, 64);
+}
+
+// W = C^T C with C upper triangular (W + shift I), then Cinv = C^-1.
+// info = 0 on success, j + 1 if pivot j is not positive.
+__global__ __launch_bounds__(ST) void k_chol_inv(int l, const double *__restrict__ W, double shift,
+                                                 double *__restrict__ C, double *__restrict__ Cinv,
+                                                 int32_t *__restrict__ info) {
+    extern __shared__ double S[];  // l x l, col-major; upper triangle becomes C
+    __shared__ int fail;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < l * l; idx += ST) {
+        int i = idx % l, j = idx / l;
+        S[idx] = W[idx] + (i == j ? shift : 0.0);
+    }
+    if (tid == 0) fail = 0;
+    __syncthreads();
+    for (int j = 0; j < l; j++) {
+        if (tid == 0) {
+            double dsum = S[j + j * l];
+            for (int k = 0; k < j; k++) dsum -= S[k + j * l] * S[k + j * l];
+            if (!(dsum > 0.0) || !isfinite(dsum)) fail = j + 1;
+            else S[j + j * l] = sqrt(dsum);
+        }
+        __syncthreads();
+        if (fail) break;
+        const double piv = S[j + j * l];
+        for (int i = j + 1 + tid; i < l; i += ST) {
+            double v = S[j + i * l];
+            for (int k = 0; k < j; k++) v -= S[k + j * l] * S[k + i * l];
+            S[j + i * l] = v / piv;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *info = fail;
+    if (fail) return;
+    for (int idx = tid; idx < l * l; idx += ST) {
+        int i = idx % l, j = idx / l;
+        C[idx] = (i <= j) ? S[idx] : 0.0;
+    }
+    // column j of C^-1 by back substitution (upper triangular)
+    for (int j = tid; j < l; j += ST) {
+        double *x = Cinv + (long long)j * l;
+        for (int i = l - 1; i > j; i--) x[i] = 0.0;
+        x[j] = 1.0 / S[j + j * l];
+        for (int i = j - 1; i >= 0; i--) {
+            double v = 0.0;
+            for (int k = i + 1; k <= j; k++) v += S[i + k * l] * x[k];
+            x[i] = -v / S[i + i * l];
+        }
+    }
+}
+
+__global__ void k_sym(int l, double *W) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= l * l) return;
+    int i = idx % l, j = idx / l;
+    if (i < j) {
+        double v = 0.5 * (W[i + j * l] + W[j + i * l]);
+        W[i + j * l] = v;
+        W[j + i * l] = v;
+    }
+}
+
+// C = op(A) op(B), all l x l.
+__global__ void k_small_gemm(int l, int ta, int tb, const double *__restrict__ A, const double *__restrict__ B,
+                             double *__restrict__ C) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= l * l) return;
+    int i = idx % l, j = idx / l;
+    double v = 0.0;
+    for (int k = 0; k < l; k++) {
+        double a = ta ? A[k + i * l] : A[i + k * l];
+        double b = tb ? B[j + k * l] : B[k + j * l];
+        v += a * b;
+    }
+    C[idx] = v;
+}
+
+// Round-robin pairing of m (even) indices: round r, pair k.
+__device__ __forceinline__ void rr_pair(int m, int r, int k, int &p, int &q) {
+    auto pos = [&](int x) { return x == 0 ? 0 : ((x - 1 + r) % (m - 1)) + 1; };
+    p = pos(k);
+    q = pos(m - 1 - k);
+    if (p > q) {
+        int t = p;
+        p = q;
+        q = t;
+    }
+}
+
+// One-sided (Hestenes) Jacobi SVD of T (l x l): columns are rotated until
+// mutually orthogonal; then sigma_j = ||t_j||, U[:, rank(j)] = t_j / sigma_j
+// with ranks sorting sigma descending (ties: lower index first).
+__global__ __launch_bounds__(ST) void k_jacobi_svd(int l, const double *__restrict__ T, double *__restrict__ U,
+                                                   double *__restrict__ sig) {
+    extern __shared__ double A[];  // l x l col-major
+    __shared__ int rotated;
+    __shared__ double nrm[128];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int idx = tid; idx < l * l; idx += ST) A[idx] = T[idx];
+    __syncthreads();
+    const int m = (l + 1) & ~1;
+    const double tol = 1e-15;
+    for (int sweep = 0; sweep < 60; sweep++) {
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        for (int r = 0; r < m - 1; r++) {
+            for (int k = wave; k < m / 2; k += ST / 64) {
+                int p, q;
+                rr_pair(m, r, k, p, q);
+                if (q >= l) continue;
+                double *ap = A + p * l, *aq = A + q * l;
+                double al = 0, be = 0, ga = 0;
+                for (int i = lane; i < l; i += 64) {
+                    al += ap[i] * ap[i];
+                    be += aq[i] * aq[i];
+                    ga += ap[i] * aq[i];
+                }
+                al = wave_sum(al);
+                be = wave_sum(be);
+                ga = wave_sum(ga);
+                if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+                    double zeta = (be - al) / (2.0 * ga);
+                    double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+                    for (int i = lane; i < l; i += 64) {
+                        double x = ap[i], y = aq[i];
+                        ap[i] = c * x - sn * y;
+                        aq[i] = sn * x + c * y;
+                    }
+                    if (lane == 0) rotated = 1;
+                }
+            }
+            __syncthreads();
+        }
+        if (!rotated) break;
+        __syncthreads();
+    }
+    for (int j = wave; j < l; j += ST / 64) {
+        double v = 0;
+        for (int i = lane; i < l; i += 64) v += A[i + j * l] * A[i + j * l];
+        v = wave_sum(v);
+        if (lane == 0) nrm[j] = sqrt(v);
+    }
+    __syncthreads();
+    for (int j = tid; j < l; j += ST) {
+        double sj = nrm[j];
+        int rank = 0;
+        for (int i = 0; i < l; i++) {
+            double si = nrm[i];
+            if (si > sj || (si == sj && i < j)) rank++;
+        }
+        sig[rank] = sj;
+        double inv = sj > 0 ? 1.0 / sj : 0.0;
+        for (int i = 0; i < l; i++) U[i + (long long)rank * l] = A[i + j * l] * inv;
+    }
+}
+
+// Two-sided cyclic Jacobi EVD of symmetric T (l x l), parallel ordering:
+// T V = V diag(lam), lam descending (ties: lower index first).
+__global__ __launch_bounds__(ST) void k_jacobi_eig(int l, const double *__restrict__ T, double *__restrict__ V,
+                                                   double *__restrict__ Vout, double *__restrict__ lam) {
+    extern __shared__ double A[];  // l x l in LDS; V (l x l) is global scratch
+    __shared__ double cs[64], sn[64];
+    __shared__ int rotated;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < l * l; idx += ST) {
+        A[idx] = T[idx];
+        V[idx] = (idx % l == idx / l) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int m = (l + 1) & ~1, half = m / 2;
+    for (int sweep = 0; sweep < 60; sweep++) {
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        for (int r = 0; r < m - 1; r++) {
+            for (int k = tid; k < half; k += ST) {
+                int p, q;
+                rr_pair(m, r, k, p, q);
+                double c = 1.0, s = 0.0;
+                if (q < l) {
+                    double apq = A[p + q * l], app = A[p + p * l], aqq = A[q + q * l];
+                    if (apq != 0.0 && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
+                        double tau = (aqq - app) / (2.0 * apq);
+                        double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        s = c * t;
+                        rotated = 1;
+                    }
+                }
+                cs[k] = c;
+                sn[k] = s;
+            }
+            __syncthreads();
+            // columns: A <- A J, V <- V J
+            for (int idx = tid; idx < half * l; idx += ST) {
+                int k = idx / l, i = idx % l, p, q;
+                rr_pair(m, r, k, p, q);
+                if (q >= l || sn[k] == 0.0) continue;
+                double c = cs[k], s = sn[k];
+                double x = A[i + p * l], y = A[i + q * l];
+                A[i + p * l] = c * x - s * y;
+                A[i + q * l] = s * x + c * y;
+                x = V[i + p * l];
+                y = V[i + q * l];
+                V[i + p * l] = c * x - s * y;
+                V[i + q * l] = s * x + c * y;
+            }
+            __syncthreads();
+            // rows: A <- J^T A
+            for (int idx = tid; idx < half * l; idx += ST) {
+                int k = idx / l, j = idx % l, p, q;
+                rr_pair(m, r, k, p, q);
+                if (q >= l || sn[k] == 0.0) continue;
+                double c = cs[k], s = sn[k];
+                double x = A[p + j * l], y = A[q + j * l];
+                A[p + j * l] = c * x - s * y;
+                A[q + j * l] = s * x + c * y;
+            }
+            __syncthreads();
+        }
+        if (!rotated) break;
+        __syncthreads();
+    }
+    for (int j = tid; j < l; j += ST) {
+        double dj = A[j + j * l];
+        int rank = 0;
+        for (int i = 0; i < l; i++) {
+            double di = A[i + i * l];
+            if (di > dj || (di == dj && i < j)) rank++;
+        }
+        lam[rank] = dj;
+        for (int i = 0; i < l; i++) Vout[i + (long long)rank * l] = V[i + j * l];
+    }
+}
+
+// Column sign convention: the entry of largest magnitude (lowest index on ties)
+// is made positive.  One workgroup per column.
+__global__ __launch_bounds__(ST) void k_fix_signs(int n, double *S, long long lds) {
+    __shared__ double bv[ST];
+    __shared__ int bi[ST];
+    double *col = S + (long long)blockIdx.x * lds;
+    double best = -1.0;
+    int besti = 0x7fffffff;
+    for (int i = threadIdx.x; i < n; i += ST) {
+        double a = fabs(col[i]);
+        if (a > best) {  // strided scan visits indices in increasing order
+            best = a;
+            besti = i;
+        }
+    }
+    bv[threadIdx.x] = best;
+    bi[threadIdx.x] = besti;
+    __syncthreads();
+    for (int w = ST / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            double ov = bv[threadIdx.x + w];
+            int oi = bi[threadIdx.x + w];
+            if (ov > bv[threadIdx.x] || (ov == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+                bv[threadIdx.x] = ov;
+                bi[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    const double sgn = col[bi[0]] < 0 ? -1.0 : 1.0;
+    if (sgn < 0)
+        for (int i = threadIdx.x; i < n; i += ST) col[i] = -col[i];
+}
+
+// d_i = sigma_i^2 - nu (clipped at 0; Nystrom) or lambda_i (REVD), i < k;
+// theta from lambda_k(I + A) = 1 + d_{k-1};  coef_i = theta/(1+d_i) - 1,
+// coefu_i = sqrt(theta)/sqrt(1+d_i) - 1 (the lmp equation).
+__global__ void k_lmp_coef(int k, const double *sig, double nu, int square, int rule, double *eig, double *coef,
+                           double *coefu, double *theta_out) {
+    __shared__ double th;
+    if (threadIdx.x == 0) {
+        double s = sig[k - 1];
+        double dk = square ? fmax(s * s - nu, 0.0) : s;
+        double lk = 1.0 + dk;
+        th = rule == EDA_THETA_MID ? 0.5 * (lk + 1.0) : (rule == EDA_THETA_LAMK ? lk : 1.0);
+        *theta_out = th;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+        double s = sig[i];
+        double d = square ? fmax(s * s - nu, 0.0) : s;
+        eig[i] = d;
+        coef[i] = th / (1.0 + d) - 1.0;
+        coefu[i] = sqrt(th) / sqrt(1.0 + d) - 1.0;
+    }
+}
+
+__global__ void k_axpy_cols(int n, int nb, double alpha, const double *__restrict__ X, long long ldx,
+                            double *__restrict__ Y, long long ldy) {
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)n * nb) return;
+    int i = (int)(idx % n), c = (int)(idx / n);
+    Y[i + c * ldy] += alpha * X[i + c * ldx];
+}
+
+__global__ void k_copy_cols(int n, int nb, const double *__restrict__ X, long long ldx, double *__restrict__ Y,
+                            long long ldy) {
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)n * nb) return;
+    int i = (int)(idx % n), c = (int)(idx / n);
+    Y[i + c * ldy] = X[i + c * ldx];
+}
+
+}  // namespace
+
+hipError_t launch_chol_inv(hipStream_t s, int l, const double *W, double shift, double *C, double *Cinv,
+                           int32_t *info) {
+    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(ST), sizeof(double) * l * l, s, l, W, shift, C, Cinv, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_sym(hipStream_t s, int l, double *W) {
+    hipLaunchKernelGGL(k_sym, dim3((l * l + 255) / 256), dim3(256), 0, s, l, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_small_gemm(hipStream_t s, int l, bool ta, bool tb, const double *A, const double *B, double *C) {
+    hipLaunchKernelGGL(k_small_gemm, dim3((l * l + 255) / 256), dim3(256), 0, s, l, (int)ta, (int)tb, A, B, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_svd_u(hipStream_t s, int l, double *T, double *U, double *sig) {
+    if (l > 128) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_jacobi_svd, dim3(1), dim3(ST), sizeof(double) * l * l, s, l, T, U, sig);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_eig(hipStream_t s, int l, double *T, double *Vwork, double *V, double *lam) {
+    if (l > 128) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_jacobi_eig, dim3(1), dim3(ST), sizeof(double) * l * l, s, l, T, Vwork, V, lam);
+    return hipGetLastError();
+}
+
+hipError_t launch_fix_signs(hipStream_t s, int n, int k, double *S, long long lds) {
+    hipLaunchKernelGGL(k_fix_signs, dim3(k), dim3(ST), 0, s, n, S, lds);
+    return hipGetLastError();
+}
+
+hipError_t launch_lmp_coef(hipStream_t s, int k, const double *sig, double nu, int square, int theta_rule,
+                           double *eig, double *coef, double *coefu, double *theta_out) {
+    hipLaunchKernelGGL(k_lmp_coef, dim3(1), dim3(128), 0, s, k, sig, nu, square, theta_rule, eig, coef, coefu,
+                       theta_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_cols(hipStream_t s, int n, int nb, double alpha, const double *X, long long ldx, double *Y,
+                            long long ldy) {
+    long long tot = (long long)n * nb;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_axpy_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, nb, alpha, X, ldx, Y,
+                       ldy);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_cols(hipStream_t s, int n, int nb, const double *X, long long ldx, double *Y, long long ldy) {
+    long long tot = (long long)n * nb;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, nb, X, ldx, Y, ldy);
+    return hipGetLastError();
+}
+
+}  // namespace eda

@@ -1,0 +1,284 @@
+"""Thin Python binding of the C ABI in include/eda.h (libeda.so).
+
+Argument marshalling only: every function here forwards to the HIP library
+with raw device pointers taken from torch tensors; torch provides device
+memory and the current HIP stream.  Importing works anywhere; any call that
+needs the library raises if libeda.so is missing, and device calls raise if no
+GPU is visible -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libeda.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "eda.h")
+
+# ---- constants (values from include/eda.h) ----
+EDA_OK = 0
+EDA_ERR_INVALID_ARG = -1
+EDA_ERR_WORKSPACE = -2
+EDA_ERR_HIP = -3
+EDA_ERR_NOT_SPD = -4
+EDA_ERR_ORDER = -5
+EDA_ERR_UNSUPPORTED = -6
+EDA_WARN_NOT_CONVERGED = 1
+EDA_MEMBER_CONVERGED, EDA_MEMBER_NOT_CONVERGED, EDA_MEMBER_BREAKDOWN = 0, 1, 2
+EDA_UB_DENSE, EDA_UB_BANDED = 0, 1
+EDA_HV_ADD_IDENTITY, EDA_HV_MIXED = 1, 2
+EDA_SKETCH_RHS_DIFF, EDA_SKETCH_USER, EDA_SKETCH_B_PSI, EDA_SKETCH_UBT_PSI = 0, 1, 2, 3
+EDA_METHOD_NYSTROM, EDA_METHOD_REVD = 0, 1
+EDA_THETA_MID, EDA_THETA_LAMK, EDA_THETA_ONE = 0, 1, 2
+EDA_LMP_P, EDA_LMP_U = 0, 1
+FIELDS = dict(truth=0, xb=1, traj=2, y=3, d=4, b=5, costc=6, ubrow=7, S=8, eig=9)
+THETA_RULES = {"mid": EDA_THETA_MID, "lamk": EDA_THETA_LAMK, "one": EDA_THETA_ONE}
+
+
+class EdaError(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        super().__init__(f"{fn} failed: {code} ({strerror(code)})")
+        self.code = code
+
+
+class eda_config(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nsteps", ctypes.c_int32), ("F", ctypes.c_double),
+                ("dt", ctypes.c_double), ("spinup", ctypes.c_int32), ("spin_pert_std", ctypes.c_double),
+                ("obs_dt", ctypes.c_int32), ("obs_dx", ctypes.c_int32), ("obs_x0", ctypes.c_int32),
+                ("sigma_o", ctypes.c_double), ("sigma_b", ctypes.c_double), ("len_b", ctypes.c_double),
+                ("members", ctypes.c_int32), ("max_ell", ctypes.c_int32), ("max_cols", ctypes.c_int32),
+                ("ub_mode", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libeda.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2605_23571_amd/build.py "
+                               "(or __graft_entry__.build()); there is no fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, i32, i64, dbl, u32 = (ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64,
+                                      ctypes.c_double, ctypes.c_uint32)
+        cfgp = ctypes.POINTER(eda_config)
+        sigs = {
+            "eda_workspace_bytes": [cfgp, ctypes.POINTER(sz)],
+            "eda_normals_count": [cfgp, ctypes.POINTER(i64)],
+            "eda_setup": [cfgp, vp, vp, sz, vp, ctypes.POINTER(vp)],
+            "eda_hessvec": [vp, vp, i32, vp, i64, vp, i64, u32],
+            "eda_sketch_evd": [vp, i32, vp, i64, i32, i32, i32, i32, i32, u32, vp, vp],
+            "eda_lmp_apply": [vp, i32, i32, vp, i64, vp, i64],
+            "eda_pcg_solve": [vp, vp, i32, dbl, i32, i32, vp, i64, vp, vp, vp, vp],
+            "eda_field": [vp, i32, ctypes.POINTER(sz), ctypes.POINTER(i64)],
+            "eda_profile": [vp, i32],
+            "eda_profile_read": [vp, ctypes.POINTER(i64), ctypes.POINTER(dbl)],
+            "eda_destroy": [vp],
+            "eda_strerror": [ctypes.c_int],
+        }
+        for name, args in sigs.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_char_p if name == "eda_strerror" else ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def header_symbols() -> list[str]:
+    """Function names declared in include/eda.h."""
+    txt = open(HEADER_PATH).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(eda_\w+)\s*\(", txt, flags=re.M)))
+
+
+def strerror(code: int) -> str:
+    return lib().eda_strerror(int(code)).decode()
+
+
+def _check(fn: str, code: int, ok=(EDA_OK,)):
+    if code not in ok:
+        raise EdaError(fn, code)
+    return code
+
+
+def make_config(cfg: dict, ub_mode: str = "banded", max_ell: int | None = None, max_cols: int = 0) -> eda_config:
+    """eda_config from a workload dict (keys as in workloads.CONFIGS)."""
+    return eda_config(cfg["n"], cfg["nsteps"], cfg["F"], cfg["dt"], cfg["spinup"], cfg["spin_pert_std"],
+                      cfg["obs_dt"], cfg["obs_dx"], cfg["obs_x0"], cfg["sigma_o"], cfg["sigma_b"], cfg["len_b"],
+                      cfg["members"], int(max_ell if max_ell is not None else cfg.get("ell", 1)), int(max_cols),
+                      EDA_UB_DENSE if ub_mode == "dense" else EDA_UB_BANDED)
+
+
+def eda_workspace_bytes(c: eda_config) -> int:
+    out = ctypes.c_size_t()
+    _check("eda_workspace_bytes", lib().eda_workspace_bytes(ctypes.byref(c), ctypes.byref(out)))
+    return out.value
+
+
+def eda_normals_count(c: eda_config) -> int:
+    out = ctypes.c_int64()
+    _check("eda_normals_count", lib().eda_normals_count(ctypes.byref(c), ctypes.byref(out)))
+    return out.value
+
+
+# ---------------------------------------------------------------- device ----
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the EDA library runs on the GPU only")
+    return torch
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _dev_f64(t, rows: int):
+    """(pointer, ld) of a [cols, rows] contiguous float64 CUDA tensor."""
+    torch = _torch()
+    if not (t.is_cuda and t.dtype == torch.float64 and t.dim() == 2 and t.shape[1] == rows and t.is_contiguous()):
+        raise ValueError(f"expected a contiguous float64 CUDA tensor of shape [cols, {rows}]")
+    return ctypes.c_void_p(t.data_ptr()), rows
+
+
+def eda_setup(c: eda_config, normals, ws):
+    """Set up a problem in workspace `ws` (uint8 CUDA tensor); returns the ctx handle."""
+    torch = _torch()
+    if not (normals.is_cuda and normals.dtype == torch.float64 and normals.is_contiguous()):
+        raise ValueError("normals must be a contiguous float64 CUDA tensor")
+    if normals.numel() != eda_normals_count(c):
+        raise ValueError("normals has the wrong length")
+    ctx = ctypes.c_void_p()
+    _check("eda_setup", lib().eda_setup(ctypes.byref(c), ctypes.c_void_p(normals.data_ptr()),
+                                        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(), ctypes.byref(ctx)))
+    return ctx
+
+
+def eda_hessvec(ctx, n: int, col_member, X, Y, flags: int = 0):
+    px, ldx = _dev_f64(X, n)
+    py, ldy = _dev_f64(Y, n)
+    _check("eda_hessvec", lib().eda_hessvec(ctx, ctypes.c_void_p(col_member.data_ptr()), X.shape[0], px, ldx,
+                                            py, ldy, flags))
+    return Y
+
+
+def eda_sketch_evd(ctx, n: int, kind: int, phi, ell: int, k: int, q: int = 1, method: int = EDA_METHOD_NYSTROM,
+                   theta_rule: int = EDA_THETA_MID, flags: int = 0):
+    eig = np.zeros(k)
+    th = ctypes.c_double()
+    if phi is not None:
+        pphi, ldphi = _dev_f64(phi, n)
+    else:
+        pphi, ldphi = ctypes.c_void_p(), n
+    _check("eda_sketch_evd", lib().eda_sketch_evd(ctx, kind, pphi, ldphi, ell, k, q, method, theta_rule, flags,
+                                                  eig.ctypes.data_as(ctypes.c_void_p), ctypes.byref(th)))
+    return eig, th.value
+
+
+def eda_lmp_apply(ctx, n: int, which: int, X, Y):
+    px, ldx = _dev_f64(X, n)
+    py, ldy = _dev_f64(Y, n)
+    _check("eda_lmp_apply", lib().eda_lmp_apply(ctx, which, X.shape[0], px, ldx, py, ldy))
+    return Y
+
+
+def eda_pcg_solve(ctx, n: int, members, rtol: float, maxit: int, use_lmp: bool, DZ, history: bool = False):
+    members = np.ascontiguousarray(members, dtype=np.int32)
+    nm = members.size
+    pdz, ldz = _dev_f64(DZ, n)
+    iters = np.zeros(nm, dtype=np.int32)
+    relres = np.zeros(nm)
+    status = np.zeros(nm, dtype=np.int32)
+    hist = np.full((nm, maxit + 1), np.nan) if history else None
+    code = lib().eda_pcg_solve(ctx, members.ctypes.data_as(ctypes.c_void_p), nm, float(rtol), int(maxit),
+                               int(bool(use_lmp)), pdz, ldz, iters.ctypes.data_as(ctypes.c_void_p),
+                               relres.ctypes.data_as(ctypes.c_void_p), status.ctypes.data_as(ctypes.c_void_p),
+                               hist.ctypes.data_as(ctypes.c_void_p) if history else None)
+    _check("eda_pcg_solve", code, ok=(EDA_OK, EDA_WARN_NOT_CONVERGED))
+    return dict(iters=iters, relres=relres, status=status, hist=hist, code=code)
+
+
+def eda_field(ctx, field: int):
+    off, cnt = ctypes.c_size_t(), ctypes.c_int64()
+    _check("eda_field", lib().eda_field(ctx, field, ctypes.byref(off), ctypes.byref(cnt)))
+    return off.value, cnt.value
+
+
+def eda_profile(ctx, enable: bool):
+    _check("eda_profile", lib().eda_profile(ctx, int(bool(enable))))
+
+
+def eda_profile_read(ctx):
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    _check("eda_profile_read", lib().eda_profile_read(ctx, ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+def eda_destroy(ctx):
+    _check("eda_destroy", lib().eda_destroy(ctx))
+
+
+class Problem:
+    """One EDA problem on the GPU: owns its workspace tensor and context."""
+
+    def __init__(self, cfg: dict, normals: np.ndarray, ub_mode: str = "banded", max_ell: int | None = None,
+                 max_cols: int = 0):
+        torch = _torch()
+        self.cfg = dict(cfg)
+        self.n = cfg["n"]
+        self.c = make_config(cfg, ub_mode, max_ell, max_cols)
+        self.ws = torch.empty(eda_workspace_bytes(self.c), dtype=torch.uint8, device="cuda")
+        self.normals = torch.as_tensor(np.ascontiguousarray(normals, dtype=np.float64)).cuda()
+        self.ctx = eda_setup(self.c, self.normals, self.ws)
+        self.max_cols = self.c.max_cols if self.c.max_cols > 0 else max(cfg["members"] + 1, 2 * self.c.max_ell)
+
+    def field(self, name: str):
+        """A float64 view into the workspace (no copy)."""
+        torch = _torch()
+        off, cnt = eda_field(self.ctx, FIELDS[name])
+        return self.ws[off:off + 8 * cnt].view(torch.float64)
+
+    def hessvec(self, members, X, add_identity: bool = False, mixed: bool = False):
+        torch = _torch()
+        cols = torch.as_tensor(np.asarray(members, dtype=np.int32)).cuda()
+        Y = torch.empty_like(X)
+        flags = (EDA_HV_ADD_IDENTITY if add_identity else 0) | (EDA_HV_MIXED if mixed else 0)
+        return eda_hessvec(self.ctx, self.n, cols, X, Y, flags)
+
+    def sketch_evd(self, kind: str = "rhs_diff", ell: int | None = None, k: int | None = None, q: int = 1,
+                   method: str = "nystrom", theta: str = "mid", phi=None, mixed: bool = False):
+        kinds = dict(rhs_diff=EDA_SKETCH_RHS_DIFF, user=EDA_SKETCH_USER, b_psi=EDA_SKETCH_B_PSI,
+                     ubt_psi=EDA_SKETCH_UBT_PSI)
+        ell = ell or self.cfg["ell"]
+        k = k or self.cfg["k"]
+        return eda_sketch_evd(self.ctx, self.n, kinds[kind], phi, ell, k, q,
+                              EDA_METHOD_NYSTROM if method == "nystrom" else EDA_METHOD_REVD, THETA_RULES[theta],
+                              EDA_HV_MIXED if mixed else 0)
+
+    def lmp_apply(self, X, which: str = "P"):
+        torch = _torch()
+        Y = torch.empty_like(X)
+        return eda_lmp_apply(self.ctx, self.n, EDA_LMP_P if which == "P" else EDA_LMP_U, X, Y)
+
+    def pcg(self, members, rtol: float, maxit: int, use_lmp: bool = True, history: bool = False):
+        torch = _torch()
+        members = np.asarray(members, dtype=np.int32)
+        DZ = torch.empty((members.size, self.n), dtype=torch.float64, device="cuda")
+        out = eda_pcg_solve(self.ctx, self.n, members, rtol, maxit, use_lmp, DZ, history)
+        out["dz"] = DZ
+        return out
+
+    def close(self):
+        if self.ctx:
+            eda_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

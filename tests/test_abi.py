@@ -1,0 +1,58 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and its host-only calls behave (no GPU needed)."""
+import ctypes
+
+import pytest
+
+import workloads as W
+from paper_2605_23571_amd import eda
+
+
+def test_header_symbols_exported():
+    syms = eda.header_symbols()
+    assert len(syms) >= 12
+    L = eda.lib()
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def test_exports_only_abi_symbols():
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", eda.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line and line.split()[-1].startswith("eda_")}
+    assert exported == set(eda.header_symbols())
+
+
+@pytest.mark.parametrize("name", ["C1", "C2", "C3"])
+def test_workspace_and_normals(name):
+    cfg = W.config(name)
+    c = eda.make_config(cfg)
+    assert eda.eda_normals_count(c) == W.n_normals(cfg)
+    b_band = eda.eda_workspace_bytes(c)
+    b_dense = eda.eda_workspace_bytes(eda.make_config(cfg, ub_mode="dense"))
+    n = cfg["n"]
+    assert b_dense - b_band >= 8 * n * n  # dense U_B stored only in dense mode
+    traj = (cfg["members"] + 1) * (cfg["nsteps"] + 1) * n * 8
+    assert b_band > traj
+
+
+@pytest.mark.parametrize("bad", [dict(n=3), dict(n=5000), dict(len_b=1.0), dict(obs_x0=40), dict(sigma_o=0.0),
+                                 dict(members=0), dict(nsteps=2, obs_dt=5)])
+def test_invalid_config_rejected(bad):
+    cfg = W.config("C1", **bad)
+    c = eda.make_config(cfg)
+    out = ctypes.c_size_t()
+    assert eda.lib().eda_workspace_bytes(ctypes.byref(c), ctypes.byref(out)) == eda.EDA_ERR_INVALID_ARG
+
+
+def test_strerror_static():
+    for code in (0, -1, -2, -3, -4, -5, -6, 1, 12345):
+        assert isinstance(eda.strerror(code), str) and eda.strerror(code)
+    assert eda.strerror(-5) != eda.strerror(-4)
+
+
+def test_null_handles_rejected():
+    L = eda.lib()
+    assert L.eda_hessvec(None, None, 1, None, 40, None, 40, 0) == eda.EDA_ERR_INVALID_ARG
+    assert L.eda_destroy(None) == eda.EDA_ERR_INVALID_ARG
+    assert L.eda_profile(None, 1) == eda.EDA_ERR_INVALID_ARG
