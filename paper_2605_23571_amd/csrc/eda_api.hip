@@ -392,9 +392,11 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
 
 int eda_hessvec(eda_ctx *h, const int32_t *d_col_member, int32_t nb, const double *d_X, int64_t ldx, double *d_Y,
                 int64_t ldy, uint32_t flags) {
-    if (!h || !d_col_member || !d_X || !d_Y) return EDA_ERR_INVALID_ARG;
+    if (!h) return EDA_ERR_INVALID_ARG;
     Ctx &c = h->c;
     if (nb < 0 || nb > c.max_cols || ldx < c.n || ldy < c.n) return EDA_ERR_INVALID_ARG;
+    if (nb == 0) return EDA_OK;
+    if (!d_col_member || !d_X || !d_Y) return EDA_ERR_INVALID_ARG;
     if (flags & ~(EDA_HV_ADD_IDENTITY | EDA_HV_MIXED)) return EDA_ERR_INVALID_ARG;
     return hessvec(c, d_col_member, nb, d_X, ldx, d_Y, ldy, flags, nullptr);
 }
@@ -512,12 +514,13 @@ int lmp_apply(Ctx &c, int which, int nb, const double *X, long long ldx, double 
 extern "C" {
 
 int eda_lmp_apply(eda_ctx *h, int32_t which, int32_t nb, const double *d_X, int64_t ldx, double *d_Y, int64_t ldy) {
-    if (!h || !d_X || !d_Y) return EDA_ERR_INVALID_ARG;
+    if (!h) return EDA_ERR_INVALID_ARG;
     Ctx &c = h->c;
     if (which != EDA_LMP_P && which != EDA_LMP_U) return EDA_ERR_INVALID_ARG;
     if (nb < 0 || nb > c.max_cols || ldx < c.n || ldy < c.n) return EDA_ERR_INVALID_ARG;
     if (!c.have_lmp) return EDA_ERR_ORDER;
     if (nb == 0) return EDA_OK;
+    if (!d_X || !d_Y) return EDA_ERR_INVALID_ARG;
     return lmp_apply(c, which, nb, d_X, ldx, d_Y, ldy);
 }
 

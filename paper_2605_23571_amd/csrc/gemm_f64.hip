@@ -93,14 +93,14 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const double 
         }
     }
 
-    // D[row][col] of a 16 x 16 block: row = 4 (lane / 16) + v, col = lane % 16.
+    // D[row][col] of a 16 x 16 block: row = lane / 16 + 4 v, col = lane % 16.
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
         for (int b = 0; b < 2; b++)
 #pragma unroll
             for (int v = 0; v < 4; v++) {
-                const int row = i0 + wr * 32 + a * 16 + 4 * (lane >> 4) + v;
+                const int row = i0 + wr * 32 + a * 16 + (lane >> 4) + 4 * v;
                 const int col = j0 + wc * 32 + b * 16 + (lane & 15);
                 if (row < M && col < N) {
                     double val = acc[a][b][v];

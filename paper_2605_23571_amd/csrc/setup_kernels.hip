@@ -10,11 +10,11 @@ __device__ __forceinline__ int cyc_dist(int i, int n) { return i < n - i ? i : n
 
 // U_B first row in closed form: r(d) = sigma_b (2/pi)^(1/4) len^(-1/2) exp(-d^2/len^2),
 // the symmetric square root of sigma_b^2 exp(-d^2/(2 len^2)) (cyclic Gaussian B).
-__global__ void k_ub_row(int n, double amp, double inv_len2, double *row) {
+__global__ void k_ub_row(int n, double amp, double len2, double *row) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double d = (double)cyc_dist(i, n);
-    row[i] = amp * exp(-d * d * inv_len2);
+    row[i] = amp * exp(-d * d / len2);
 }
 
 __global__ void k_ub_fill(int n, const double *__restrict__ row, double *__restrict__ ub) {
@@ -142,7 +142,7 @@ __global__ void k_gamma(int n, int ell, const double *__restrict__ b, double *__
 
 hipError_t launch_ub_row(hipStream_t s, int n, double sigma_b, double len_b, double *row) {
     double amp = sigma_b * pow(2.0 / M_PI, 0.25) / sqrt(len_b);
-    hipLaunchKernelGGL(k_ub_row, dim3((n + 255) / 256), dim3(256), 0, s, n, amp, 1.0 / (len_b * len_b), row);
+    hipLaunchKernelGGL(k_ub_row, dim3((n + 255) / 256), dim3(256), 0, s, n, amp, len_b * len_b, row);
     return hipGetLastError();
 }
 

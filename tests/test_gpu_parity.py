@@ -147,7 +147,7 @@ def _compare_lmp(g, o, cfg, S, D, th, eig, theta_gpu, tol):
     np.testing.assert_allclose(eig, D, rtol=tol, atol=tol * D[0])
     assert abs(theta_gpu - th) <= tol * th
     n = cfg["n"]
-    V = np.random.default_rng(9).standard_normal((16, n))
+    V = np.random.default_rng(9).standard_normal((min(16, g.max_cols), n))
     Vt = torch.from_numpy(V).cuda()
     for which in ("P", "U"):
         Pg = to_np_cols(g.lmp_apply(Vt, which), n)
