@@ -97,6 +97,12 @@ struct TladArgs {
     double *lam;
     long long ldl;
 };
+// Launch geometry of the TL/AD kernel: waves per workgroup, ring segment owned
+// per wave, points per lane, time-block length and window offsets.
+struct TladGeom {
+    int waves, S, q, tb, hl_tl, hl_ad;
+};
+TladGeom tlad_geometry(int n, int waves_hint);
 hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32);
 
 // U_B first row (closed form) and dense fill.
