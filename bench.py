@@ -13,11 +13,12 @@ MFMA GEMMs.  Both are FP64 throughout.  Hessian-vector products per second
 (member mode: every column on its own trajectory; sketch mode: all on the
 control trajectory) are reported too.
 
-The roofline entry is for the fused TL/AD kernel: algorithmic bytes
-(trajectory read twice, observed increments written and read back, input and
-output vectors) per active column x active columns over the timed region,
-divided by that kernel's summed duration from HIP events recorded around each
-of its launches on the launching stream.
+The roofline entry is for the dominant kernel, the fused PCG-iteration kernel
+(banded U_B, TL run, AD run, banded U_B, vector updates, one workgroup per
+member column): algorithmic bytes per active column (pcg_kernel_bytes_per_col)
+x active member-iterations over the timed region, divided by that kernel's
+summed duration from HIP events recorded around each of its launches on the
+launching stream.
 """
 import argparse
 import json
@@ -48,10 +49,14 @@ def parse():
     return ap.parse_args()
 
 
-def tlad_bytes_per_col(cfg):
+def pcg_kernel_bytes_per_col(cfg):
+    """Algorithmic HBM bytes of one member column in one fused PCG-iteration
+    launch: the trajectory read by the TL run and again by the AD run (N states
+    of n each), the observed increments written and read back (p each), and the
+    vectors: r, z read for r^T z; z, p read and p written; x, r read and written."""
     n, N = cfg["n"], cfg["nsteps"]
     nt, nv = W.obs_counts(cfg)
-    return 8 * (2 * N * n + 2 * nt * nv + 2 * n)
+    return 8 * (2 * N * n + 2 * nt * nv + 9 * n)
 
 
 def run_form(cfg, z, ub_mode, steps, warmup, hv_reps):
@@ -104,7 +109,7 @@ def run_form(cfg, z, ub_mode, steps, warmup, hv_reps):
     res = dict(solves_per_s=(L + 1) * steps / dt, ms_per_step=1e3 * dt / steps, setup_s=setup_s, converged=conv,
                iters_median=float(np.median(it)), iters_max=int(it.max()), iters_min=int(it.min()),
                tlad_launches=launches, tlad_ms=tlad_ms, hessvec_per_s=hv,
-               active_cols=iters_total + steps * ell)
+               active_cols=iters_total)
     g.close()
     return res
 
@@ -150,7 +155,7 @@ def main():
     if not a.no_plain:
         print(f"[bench] {a.workload} plain form (dense U_B GEMMs)", file=sys.stderr, flush=True)
         plain = run_form(cfg, z, "dense", max(1, a.steps // 2), 1 if a.warmup else 0, max(2, a.hv_reps // 4))
-    bpc = tlad_bytes_per_col(cfg)
+    bpc = pcg_kernel_bytes_per_col(cfg)
     avg_ms = chosen["tlad_ms"] / max(1, chosen["tlad_launches"])
     achieved = bpc * chosen["active_cols"] / (chosen["tlad_ms"] * 1e-3) / 1e9
     nt, nv = W.obs_counts(cfg)
@@ -173,7 +178,7 @@ def main():
                    "form": "chosen (banded circulant U_B, FP64)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_tlad (fused TL forward + AD backward)",
+                     "kernel": "k_tlad<double, 9, TLAD_PCG> (fused PCG iteration: U_B, TL, AD, U_B, updates)",
                      "bytes_per_column": bpc, "avg_launch_ms": round(avg_ms, 4),
                      "launches": chosen["tlad_launches"]},
         "pcg_iterations": {"median": chosen["iters_median"], "min": chosen["iters_min"], "max": chosen["iters_max"],

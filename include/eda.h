@@ -137,8 +137,8 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
  * linearisation trajectory.  A_m x = U_B^T G_m^T R^-1 G_m U_B x: a U_B product,
  * a TL run over the window writing the observed increments, an AD run forced
  * by them, and a U_B^T product.  nb <= max_cols; X and Y must not overlap.
- * EDA_HV_MIXED runs the TL/AD in FP32 (accuracy stated in the design notes;
- * meant for sketch products only). */
+ * EDA_HV_MIXED runs the TL/AD in FP32 (relative error of order 1e-6 against
+ * FP64; meant for sketch products only). */
 int eda_hessvec(eda_ctx *ctx, const int32_t *d_col_member, int32_t nb,
                 const double *d_X, int64_t ldx, double *d_Y, int64_t ldy, uint32_t flags);
 
@@ -206,7 +206,9 @@ int eda_pcg_solve(eda_ctx *ctx, const int32_t *h_members, int32_t nm, double rto
 #define EDA_FIELD_EIG    9
 int eda_field(const eda_ctx *ctx, int32_t field, size_t *byte_offset, int64_t *count);
 
-/* Opt-in timing of the tangent-linear/adjoint kernel with HIP events recorded
+/* Opt-in timing of the tangent-linear/adjoint kernel launched by
+ * eda_pcg_solve (the fused PCG-iteration kernel with the banded U_B, the TL/AD
+ * kernel between the U_B GEMMs with the dense U_B), with HIP events recorded
  * on the context's stream around each of its launches.  eda_profile(ctx, 1)
  * starts (and clears) the accounting; eda_profile_read synchronises and returns
  * the number of launches and their summed duration in milliseconds. */

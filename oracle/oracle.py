@@ -12,7 +12,7 @@ column vectors).  Member 0 is the control.  The paper's A is the low-rank part
 A = U_B^T G^T R^-1 G U_B; the system matrix is I + A (incremental 4D-Var with
 the control-variable transform, the "system_with_CVT" equation).
 
-Readings taken where the paper is silent (each also listed in the design notes):
+Readings taken where the paper is silent:
   * observation times exclude t = 0: s = obs_dt, 2 obs_dt, ..., <= N;
   * B = sigma_b^2 C with C the cyclic Gaussian correlation exp(-d^2 / (2 len^2)),
     d the cyclic grid distance; U_B is its symmetric square root in closed form

@@ -164,12 +164,16 @@ TladArgs tlad_args(Ctx &c, int nb, const int32_t *cols, const int32_t *active) {
     a.traj_stride = (long long)(c.N + 1) * c.n;
     a.col_member = cols;
     a.active = active;
+    a.ubrow = c.ubrow;
+    a.band_lo = c.band_lo;
+    a.band_hi = c.band_hi;
     return a;
 }
 
 int run_tlad(Ctx &c, const TladArgs &a, int mode, bool fp32) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c.prof) {
+    const bool rec = c.prof && c.in_pcg;
+    if (rec) {
         if (c.ev_used + 2 > c.ev.size()) {
             for (int i = 0; i < 64; i++) {
                 hipEvent_t e;
@@ -183,17 +187,30 @@ int run_tlad(Ctx &c, const TladArgs &a, int mode, bool fp32) {
         HIP_TRY(hipEventRecord(e0, c.stream));
     }
     HIP_TRY(launch_tlad(c.stream, a, mode, fp32));
-    if (c.prof) {
+    if (rec) {
         HIP_TRY(hipEventRecord(e1, c.stream));
         c.prof_launches++;
     }
     return EDA_OK;
 }
 
-// Batched Hessian product on the context's scratch.
+// Batched Hessian product.  Banded U_B: one fused launch (U_B, TL, AD, U_B,
+// identity) per call; dense U_B: FP64 MFMA GEMM, TL/AD, GEMM.
 int hessvec(Ctx &c, const int32_t *cols, int nb, const double *X, long long ldx, double *Y, long long ldy,
             uint32_t flags, const int32_t *active) {
     if (nb <= 0) return EDA_OK;
+    const bool add = (flags & EDA_HV_ADD_IDENTITY) != 0;
+    const bool fp32 = (flags & EDA_HV_MIXED) != 0;
+    if (c.cfg.ub_mode == EDA_UB_BANDED) {
+        TladArgs a = tlad_args(c, nb, cols, active);
+        a.V = X;
+        a.ldv = ldx;
+        a.obs = c.hv_obs;
+        a.lam = Y;
+        a.ldl = ldy;
+        a.add_identity = add ? 1 : 0;
+        return run_tlad(c, a, TLAD_HV, fp32);
+    }
     EDA_TRY(ub_apply(c, nb, X, ldx, c.hv_v, c.n, nullptr, 0, active));
     TladArgs a = tlad_args(c, nb, cols, active);
     a.V = c.hv_v;
@@ -201,8 +218,7 @@ int hessvec(Ctx &c, const int32_t *cols, int nb, const double *X, long long ldx,
     a.obs = c.hv_obs;
     a.lam = c.hv_lam;
     a.ldl = c.n;
-    EDA_TRY(run_tlad(c, a, 0, (flags & EDA_HV_MIXED) != 0));
-    const bool add = (flags & EDA_HV_ADD_IDENTITY) != 0;
+    EDA_TRY(run_tlad(c, a, TLAD_RAW, fp32));
     EDA_TRY(ub_apply(c, nb, c.hv_lam, c.n, Y, ldy, add ? X : nullptr, ldx, active));
     return EDA_OK;
 }
@@ -382,7 +398,7 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
         a.force = c.forcing;
         a.lam = c.hv_lam;
         a.ldl = n;
-        if (launch_tlad(s, a, 1, false) != hipSuccess) return fail(EDA_ERR_HIP);
+        if (launch_tlad(s, a, TLAD_ADJ, false) != hipSuccess) return fail(EDA_ERR_HIP);
         if (ub_apply(c, L + 1, c.hv_lam, n, c.b, n, nullptr, 0, nullptr) != EDA_OK) return fail(EDA_ERR_HIP);
     }
     if (hipStreamSynchronize(s) != hipSuccess) return fail(EDA_ERR_HIP);
@@ -555,21 +571,59 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
     a.rtol = rtol;
     HIP_TRY(launch_pcg_init(s, a));
     if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n));
-    HIP_TRY(launch_pcg_start(s, a));
     std::vector<int32_t> st(nm);
     const int check_every = 8;
-    for (int it = 1; it <= maxit; it++) {
-        EDA_TRY(hessvec(c, c.pc_members, nm, c.pc_p, n, c.pc_q, n, EDA_HV_ADD_IDENTITY, c.pc_status));
-        HIP_TRY(launch_pcg_alpha(s, a, it));
-        if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n));
-        HIP_TRY(launch_pcg_beta(s, a));
-        if (it % check_every == 0 || it == maxit) {
-            EDA_TRY(sync_read(c, st.data(), c.pc_status, sizeof(int32_t) * nm));
-            bool running = false;
-            for (int i = 0; i < nm; i++) running |= (st[i] == COL_RUNNING);
-            if (!running) break;
+    const bool fused = c.cfg.ub_mode == EDA_UB_BANDED;
+    bool stopped_early = false;
+    if (!fused) HIP_TRY(launch_pcg_start(s, a));
+    struct InPcg {  // profile scope, also left on an error return
+        Ctx &c;
+        explicit InPcg(Ctx &cc) : c(cc) { c.in_pcg = true; }
+        ~InPcg() { c.in_pcg = false; }
+    };
+    {
+        InPcg scope(c);
+        for (int it = 1; it <= maxit; it++) {
+            if (fused) {
+                // one launch: p = z + beta p, q = (I + A) p, alpha, x, r, convergence
+                TladArgs t = tlad_args(c, nm, c.pc_members, nullptr);
+                t.obs = c.hv_obs;
+                t.pcg.members = c.pc_members;
+                t.pcg.b = c.b;
+                t.pcg.x = c.pc_x;
+                t.pcg.r = c.pc_r;
+                t.pcg.z = a.z;
+                t.pcg.p = c.pc_p;
+                t.pcg.scal = c.pc_scal;
+                t.pcg.status = c.pc_status;
+                t.pcg.iters = c.pc_iters;
+                t.pcg.hist = a.hist;
+                t.pcg.hist_cap = c.hist_cap;
+                t.pcg.rtol = rtol;
+                t.pcg.it = it;
+                t.pcg.first = it == 1 ? 1 : 0;
+                EDA_TRY(run_tlad(c, t, TLAD_PCG, false));
+                if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n));
+            } else {
+                EDA_TRY(hessvec(c, c.pc_members, nm, c.pc_p, n, c.pc_q, n, EDA_HV_ADD_IDENTITY, c.pc_status));
+                HIP_TRY(launch_pcg_alpha(s, a, it));
+                if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n));
+                HIP_TRY(launch_pcg_beta(s, a));
+            }
+            if (it % check_every == 0 || it == maxit) {
+                EDA_TRY(sync_read(c, st.data(), c.pc_status, sizeof(int32_t) * nm));
+                bool running = false;
+                for (int i = 0; i < nm; i++) running |= (st[i] == COL_RUNNING);
+                if (!running) {
+                    stopped_early = true;
+                    break;
+                }
+            }
         }
     }
+    // the fused form tests r^T z for breakdown at the start of the next
+    // iteration; after the last one that test runs here (as the textbook loop does)
+    if (fused && !stopped_early && maxit > 0) HIP_TRY(launch_pcg_beta(s, a));
     HIP_TRY(launch_pcg_finish(s, a));
     HIP_TRY(launch_copy_cols(s, n, nm, c.pc_x, n, d_DZ, ldz));
     std::vector<double> scal(4 * (size_t)nm);

@@ -60,8 +60,9 @@ struct Ctx {
     int k = 0;
     double theta = 1.0;
 
-    // profiling of the TL/AD kernel
+    // profiling of the TL/AD kernel inside eda_pcg_solve
     bool prof = false;
+    bool in_pcg = false;
     std::vector<hipEvent_t> ev;
     int64_t prof_launches = 0;
     size_t ev_used = 0;
@@ -78,9 +79,31 @@ hipError_t launch_nl(hipStream_t s, int n, int nvec, int nsteps, double F, doubl
 // Truth spin-up start: x = F * 1, x[0] = F + std * z[0].
 hipError_t launch_spin_init(hipStream_t s, int n, double F, double std_, const double *z, double *x);
 
-// Fused TL forward + AD backward about stored trajectories (mode 0), or AD
-// only with given forcing (mode 1).  Columns with active[c] != COL_RUNNING are
-// skipped when active is non-null.
+// PCG column state used by the fused PCG kernel (column c of every n-vector
+// array starts at c * n; scal holds rho, ||b||, relative residual, spare).
+struct PcgCols {
+    const int32_t *members;
+    const double *b;  // n x (L+1) right-hand sides
+    double *x, *r, *z, *p;
+    double *scal;
+    int32_t *status, *iters;
+    double *hist;
+    int hist_cap;
+    double rtol;
+    int it;     // iteration number of this launch (1-based)
+    int first;  // 1: p = z, rho = r^T z (first iteration)
+};
+
+// Tangent-linear / adjoint kernel modes.
+enum TladMode : int {
+    TLAD_RAW = 0,   // V (global) -> TL -> AD -> lambda_0 (global)
+    TLAD_ADJ = 1,   // forcing (global) -> AD -> lambda_0 (global)
+    TLAD_HV = 2,    // X -> U_B X -> TL -> AD -> U_B lambda_0 (+ X) -> Y, banded U_B in-kernel
+    TLAD_PCG = 3,   // one fused PCG iteration per member column (banded U_B), see k_tlad
+};
+
+// Arguments of the TL/AD kernel.  Columns with active[c] != COL_RUNNING are
+// skipped when active is non-null (TLAD_PCG uses pcg.status instead).
 struct TladArgs {
     int n, N, nb;
     double F, dt, h, dt6, dt3;
@@ -90,12 +113,16 @@ struct TladArgs {
     long long traj_stride;
     const int32_t *col_member;
     const int32_t *active;
-    const double *V;
+    const double *V;      // RAW: input increments; HV: input X
     long long ldv;
-    double *obs;          // p x nb scratch (mode 0)
-    const double *force;  // p x nb forcing (mode 1)
-    double *lam;
+    double *obs;          // p x nb scratch of observed increments (RAW, HV, PCG)
+    const double *force;  // ADJ: p x nb forcing
+    double *lam;          // RAW/ADJ: lambda_0; HV: output Y
     long long ldl;
+    const double *ubrow;  // HV/PCG: U_B first row and tap range
+    int band_lo, band_hi;
+    int add_identity;     // HV: Y = U_B lambda_0 + X
+    PcgCols pcg;
 };
 // Launch geometry of the TL/AD kernel: waves per workgroup, ring segment owned
 // per wave, points per lane, time-block length and window offsets.

@@ -4,7 +4,7 @@
 // Q^T A Q), Q = Y R^-1, S = Q U and the LMP's S_k^T X / X + S_k T.
 //
 // Tile 64 x 64 per 256-thread workgroup (4 waves in a 2 x 2 arrangement, each
-// wave 2 x 2 MFMA blocks of 16 x 16), K step 16 staged in LDS.  For the
+// wave 2 x 2 MFMA blocks of 16 x 16), K step 32 staged in LDS.  For the
 // K-long, M/N-small products (Gram matrices, S^T X) the K range is split over
 // workgroups; partial tiles go to a workspace and are summed in a fixed order,
 // so results do not depend on scheduling.
@@ -15,7 +15,8 @@ namespace {
 
 typedef double double4v __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BM = 64, BN = 64, BK = 32;
+constexpr int LE = BK * 64 / 256;  // elements of each operand tile loaded per thread
 
 template <bool TA>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const double *__restrict__ A, long long lda,
@@ -37,35 +38,37 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const double 
 #pragma unroll
         for (int b = 0; b < 2; b++) acc[a][b] = double4v{0.0, 0.0, 0.0, 0.0};
 
-    double ra[4], rb[4];
+    double ra[LE], rb[LE];
     auto load = [&](int k0) {
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
+        for (int e = 0; e < LE; e++) {
+            const int idx = tid + 256 * e;
             int r, kk;
             if (!TA) {
-                r = tid & 63;
-                kk = (tid >> 6) + 4 * e;
+                r = idx % BM;
+                kk = idx / BM;
             } else {
-                kk = tid & 15;
-                r = (tid >> 4) + 16 * e;
+                kk = idx % BK;
+                r = idx / BK;
             }
-            int gi = i0 + r, gk = k0 + kk;
+            const int gi = i0 + r, gk = k0 + kk;
             double v = 0.0;
             if (gi < M && gk < kend) v = TA ? A[gk + (long long)gi * lda] : A[gi + (long long)gk * lda];
             ra[e] = v;
-            int cc = (tid >> 4) + 16 * e, kb = tid & 15;
-            int gj = j0 + cc, gkb = k0 + kb;
+            const int kb = idx % BK, cc = idx / BK;
+            const int gj = j0 + cc, gkb = k0 + kb;
             rb[e] = (gj < N && gkb < kend) ? B[gkb + (long long)gj * ldb] : 0.0;
         }
     };
     auto store = [&]() {
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
+        for (int e = 0; e < LE; e++) {
+            const int idx = tid + 256 * e;
             if (!TA)
-                As[(tid >> 6) + 4 * e][tid & 63] = ra[e];
+                As[idx / BM][idx % BM] = ra[e];
             else
-                As[tid & 15][(tid >> 4) + 16 * e] = ra[e];
-            Bs[tid & 15][(tid >> 4) + 16 * e] = rb[e];
+                As[idx % BK][idx / BK] = ra[e];
+            Bs[idx % BK][idx / BK] = rb[e];
         }
     };
 
@@ -128,11 +131,13 @@ __global__ void k_splitk_reduce(int M, int N, int nsplit, const double *__restri
     C[row + (long long)col * ldc] = s;
 }
 
+// K-split for products whose output has few tiles: aim at about 512
+// workgroups, with at least 64 of K per workgroup.
 int split_count(int M, int N, int K) {
     int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-    if (tiles >= 64 || K < 512) return 1;
-    int ns = (K + 255) / 256;
-    int cap = 256 / tiles;
+    if (tiles >= 128 || K < 256) return 1;
+    int ns = 512 / tiles;
+    int cap = K / 64;
     if (ns > cap) ns = cap;
     return ns < 1 ? 1 : ns;
 }

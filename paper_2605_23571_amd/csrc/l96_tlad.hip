@@ -25,6 +25,11 @@
 //    ring buffers);
 //  * the observed increments R^-1 H dx written by the owners at observation
 //    times are read back, at every window point, as the AD forcing.
+//
+// Modes TLAD_HV and TLAD_PCG also apply the banded circulant U_B on both sides
+// inside the workgroup (the column is in LDS), and TLAD_PCG performs a whole
+// PCG iteration for its member: p = z + beta p, q = (I + A) p, alpha, x and r
+// updates, the convergence test -- one launch in place of eight.
 #include "eda_internal.h"
 
 namespace eda {
@@ -122,34 +127,145 @@ __device__ __forceinline__ int window(const TladArgs &a, int w0, int own_lo, int
     return b;
 }
 
-// MODE 0: TL then AD forced by the TL's observed increments.
-// MODE 1: AD only, forcing read from a.force.
+// Banded circulant product at this lane's Q window points:
+//   out[q] = sum_{m = 0}^{W-1} taps[m] u[(base + q - hi + m) mod n],
+// taps[m] = r(|hi - m|), u and taps in LDS.  A circular register buffer of Q
+// values keeps one LDS read per tap (Q FMAs per read, no register shifts).
+template <int Q>
+__device__ __forceinline__ void band_lane(const double *u, const double *taps, int W, int hi, int n, int base,
+                                          double (&out)[Q]) {
+    int idx = (base - hi) % n;
+    if (idx < 0) idx += n;
+    const int start = idx;
+    double B[Q];
+#pragma unroll
+    for (int j = 0; j < Q; j++) {
+        B[j] = u[idx];
+        idx = idx + 1 == n ? 0 : idx + 1;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; q++) out[q] = 0.0;
+    int m0 = 0;
+    for (; m0 + Q <= W; m0 += Q) {
+        // at entry B[j] = u[start + m0 + j]; slot mm is refilled with the next chunk after use
+#pragma unroll
+        for (int mm = 0; mm < Q; mm++) {
+            const double t = taps[m0 + mm];
+#pragma unroll
+            for (int q = 0; q < Q; q++) out[q] += t * B[(mm + q) % Q];
+            B[mm] = u[idx];
+            idx = idx + 1 == n ? 0 : idx + 1;
+        }
+    }
+    // remaining taps (fewer than Q): B[j] = u[start + m0 + j]
+#pragma unroll
+    for (int mm = 0; mm < Q - 1; mm++) {
+        if (m0 + mm < W) {
+            const double t = taps[m0 + mm];
+#pragma unroll
+            for (int q = 0; q < Q; q++) {
+                double v;
+                if (mm + q < Q) {
+                    v = B[mm + q];
+                } else {
+                    int k = (start + m0 + mm + q) % n;
+                    v = u[k];
+                }
+                out[q] += t * v;
+            }
+        }
+    }
+}
+
+// Deterministic workgroup sum (fixed shuffle tree per wave, then waves in order).
+__device__ __forceinline__ double block_sum(double v, double *red, int waves) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < waves; w++) s += red[w];
+    return s;
+}
+
 template <typename T, int Q, int MODE>
 __global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
+    constexpr bool FUSED = (MODE == TLAD_HV || MODE == TLAD_PCG);
     extern __shared__ __align__(16) unsigned char smraw[];
     const int c = blockIdx.x;
-    if (a.active && a.active[c] != COL_RUNNING) return;
     const int n = a.n, N = a.N, p = a.nt * a.nv;
-    const int wave = threadIdx.x >> 6;
-    // two ring buffers [0, n) and [n, 2n), indexed rsel * n + position (a plain
-    // offset from the LDS array keeps these accesses in the LDS address space)
-    T *ring = reinterpret_cast<T *>(smraw);
-    int *qi = reinterpret_cast<int *>(reinterpret_cast<T *>(smraw) + 2 * n) + wave * 64 * Q;
-    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x, nthr = blockDim.x;
+    if (MODE == TLAD_PCG) {
+        if (a.pcg.status[c] != COL_RUNNING) return;
+    } else if (a.active && a.active[c] != COL_RUNNING) {
+        return;
+    }
+    // LDS: [ring: 2n T][qi: waves*64*Q int][u: n double][taps: W double][red: 16 double]
+    T *ring = reinterpret_cast<T *>(smraw);  // two buffers, indexed rsel * n + position
+    int *qi = reinterpret_cast<int *>(ring + 2 * n) + wave * 64 * Q;
+    double *u = reinterpret_cast<double *>(reinterpret_cast<int *>(ring + 2 * n) + g.waves * 64 * Q);
+    double *taps = u + n;
+    const int W = a.band_hi - a.band_lo + 1;
+    double *red = taps + W;
+    double *lamd = reinterpret_cast<double *>(ring);  // ring reused as a double array for lambda_0
     const int own_lo = wave * g.S, own_hi = min(n, own_lo + g.S);
-    const int member = a.col_member ? a.col_member[c] : 0;
+    const int member = MODE == TLAD_PCG ? a.pcg.members[c] : (a.col_member ? a.col_member[c] : 0);
     const double *traj = a.traj + (long long)member * a.traj_stride;
     const T F = (T)a.F, h = (T)a.h, dt = (T)a.dt, dt6 = (T)a.dt6, dt3 = (T)a.dt3;
     unsigned ownm;
     int rsel = 0;
+    double rho = 0.0;
+    const long long cn = (long long)c * n;
 
-    if (MODE == 0) {
+    // ---------------- input vector and U_B on the way in (fused modes) ----------------
+    if (FUSED) {
+        for (int m = tid; m < W; m += nthr) {
+            int o = a.band_hi - m;
+            taps[m] = a.ubrow[o < 0 ? -o : o];
+        }
+        if (MODE == TLAD_HV) {
+            const double *x = a.V + (long long)c * a.ldv;
+            for (int i = tid; i < n; i += nthr) u[i] = x[i];
+        } else {
+            // p = z + beta p with beta = rho'/rho, rho' = r^T z; first iteration p = z
+            const double *r = a.pcg.r + cn, *z = a.pcg.z + cn;
+            double *pp = a.pcg.p + cn;
+            double rz = 0.0;
+            for (int i = tid; i < n; i += nthr) rz += r[i] * z[i];
+            rz = block_sum(rz, red, g.waves);
+            double beta = 0.0;
+            if (!a.pcg.first) {
+                if (!(rz > 0.0) || !isfinite(rz)) {
+                    if (tid == 0) a.pcg.status[c] = EDA_MEMBER_BREAKDOWN;
+                    return;
+                }
+                beta = rz / a.pcg.scal[4 * c];
+            }
+            rho = rz;
+            for (int i = tid; i < n; i += nthr) {
+                double v = a.pcg.first ? z[i] : z[i] + beta * pp[i];
+                pp[i] = v;
+                u[i] = v;
+            }
+        }
+        __syncthreads();
+    }
+
+    if (MODE != TLAD_ADJ) {
         // ---------------- TL forward run ----------------
         int base = window<Q>(a, own_lo - g.hl_tl, own_lo, own_hi, true, ownm, qi);
         T dx[Q];
-        const double *vcol = a.V + (long long)c * a.ldv;
+        if (FUSED) {
+            double v0[Q];
+            band_lane<Q>(u, taps, W, a.band_hi, n, base, v0);
 #pragma unroll
-        for (int q = 0; q < Q; q++) dx[q] = (T)vcol[wpos(base, q, n)];
+            for (int q = 0; q < Q; q++) dx[q] = (T)v0[q];
+        } else {
+            const double *vcol = a.V + (long long)c * a.ldv;
+#pragma unroll
+            for (int q = 0; q < Q; q++) dx[q] = (T)vcol[wpos(base, q, n)];
+        }
         double *obs = a.obs + (long long)c * p;
         for (int s0 = 0; s0 < N; s0 += g.tb) {
             if (s0 > 0) {
@@ -210,13 +326,12 @@ __global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
             }
         }
         __threadfence_block();  // observed increments visible to the whole workgroup
-        __syncthreads();
     }
+    __syncthreads();  // TL reads of the ring and of the observation indices are done
 
     // ---------------- AD backward run ----------------
-    __syncthreads();  // the TL phase's observation indices are no longer read
     const int base = window<Q>(a, own_lo - g.hl_ad, own_lo, own_hi, false, ownm, qi);
-    const double *force = (MODE == 0) ? a.obs + (long long)c * p : a.force + (long long)c * p;
+    const double *force = (MODE == TLAD_ADJ) ? a.force + (long long)c * p : a.obs + (long long)c * p;
     T lam[Q];
 #pragma unroll
     for (int q = 0; q < Q; q++) lam[q] = T(0);
@@ -296,20 +411,104 @@ __global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
             rsel ^= 1;
         }
     }
-    double *out = a.lam + (long long)c * a.ldl;
+
+    if (!FUSED) {
+        double *out = a.lam + (long long)c * a.ldl;
+#pragma unroll
+        for (int q = 0; q < Q; q++)
+            if (ownm & (1u << q)) out[wpos(base, q, n)] = (double)lam[q];
+        return;
+    }
+
+    // ---------------- U_B on the way out (fused modes) ----------------
+    __syncthreads();  // every wave is done reading the ring
 #pragma unroll
     for (int q = 0; q < Q; q++)
-        if (ownm & (1u << q)) out[wpos(base, q, n)] = (double)lam[q];
+        if (ownm & (1u << q)) lamd[wpos(base, q, n)] = (double)lam[q];
+    __syncthreads();
+    double y[Q];
+    band_lane<Q>(lamd, taps, W, a.band_hi, n, base, y);
+    if (MODE == TLAD_HV) {
+        double *out = a.lam + (long long)c * a.ldl;
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+            if (ownm & (1u << q)) {
+                const int ps = wpos(base, q, n);
+                out[ps] = a.add_identity ? y[q] + u[ps] : y[q];
+            }
+        }
+        return;
+    }
+
+    // ---------------- PCG update: q = (I + A) p, alpha, x, r, convergence ----------------
+    double pq = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        if (ownm & (1u << q)) {
+            const double pv = u[wpos(base, q, n)];
+            y[q] += pv;  // (I + A) p
+            pq += pv * y[q];
+        }
+    }
+    pq = block_sum(pq, red, g.waves);
+    const int it = a.pcg.it;
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (tid == 0) {
+            a.pcg.status[c] = EDA_MEMBER_BREAKDOWN;
+            a.pcg.iters[c] = it - 1;
+        }
+        return;
+    }
+    const double alpha = rho / pq;
+    double *xv = a.pcg.x + cn, *rv = a.pcg.r + cn;
+    const double *bv = a.pcg.b + (long long)member * n;
+    double rr = 0.0, xbr = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        if (ownm & (1u << q)) {
+            const int ps = wpos(base, q, n);
+            const double xi = xv[ps] + alpha * u[ps];
+            const double ri = rv[ps] - alpha * y[q];
+            xv[ps] = xi;
+            rv[ps] = ri;
+            rr += ri * ri;
+            if (a.pcg.hist) xbr += xi * (bv[ps] + ri);
+        }
+    }
+    rr = block_sum(rr, red, g.waves);
+    if (a.pcg.hist) xbr = block_sum(xbr, red, g.waves);
+    if (tid == 0) {
+        const double bnorm = a.pcg.scal[4 * c + 1];
+        const double rn = sqrt(rr);
+        a.pcg.scal[4 * c] = rho;
+        a.pcg.scal[4 * c + 2] = rn / bnorm;
+        a.pcg.iters[c] = it;
+        if (a.pcg.hist && it < a.pcg.hist_cap) a.pcg.hist[(long long)c * a.pcg.hist_cap + it] = -0.5 * xbr;
+        if (!isfinite(rn)) a.pcg.status[c] = EDA_MEMBER_BREAKDOWN;
+        else if (rn <= a.pcg.rtol * bnorm) a.pcg.status[c] = EDA_MEMBER_CONVERGED;
+    }
+}
+
+template <typename T, int Q>
+size_t lds_bytes(const TladArgs &a, const TladGeom &g, int mode) {
+    size_t b = sizeof(T) * 2 * (size_t)a.n + sizeof(int) * (size_t)g.waves * 64 * Q;
+    if (mode == TLAD_HV || mode == TLAD_PCG)
+        b += sizeof(double) * ((size_t)a.n + (size_t)(a.band_hi - a.band_lo + 1) + 16);
+    return b;
 }
 
 template <typename T, int Q>
 hipError_t launch_q(hipStream_t s, const TladArgs &a, const TladGeom &g, int mode) {
-    const size_t lds = sizeof(T) * 2 * (size_t)a.n + sizeof(int) * (size_t)g.waves * 64 * Q;
+    const size_t lds = lds_bytes<T, Q>(a, g, mode);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
     const dim3 block(64 * g.waves);
-    if (mode == 0)
-        hipLaunchKernelGGL((k_tlad<T, Q, 0>), dim3(a.nb), block, lds, s, a, g);
-    else
-        hipLaunchKernelGGL((k_tlad<T, Q, 1>), dim3(a.nb), block, lds, s, a, g);
+    switch (mode) {
+        case TLAD_RAW: hipLaunchKernelGGL((k_tlad<T, Q, TLAD_RAW>), dim3(a.nb), block, lds, s, a, g); break;
+        case TLAD_ADJ: hipLaunchKernelGGL((k_tlad<T, Q, TLAD_ADJ>), dim3(a.nb), block, lds, s, a, g); break;
+        case TLAD_HV: hipLaunchKernelGGL((k_tlad<T, Q, TLAD_HV>), dim3(a.nb), block, lds, s, a, g); break;
+        case TLAD_PCG: hipLaunchKernelGGL((k_tlad<T, Q, TLAD_PCG>), dim3(a.nb), block, lds, s, a, g); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -352,6 +551,7 @@ hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32) {
     if (a.nb <= 0) return hipSuccess;
     TladGeom g = tlad_geometry(a.n, 0);
     if (g.q > 9 || g.tb < 1) return hipErrorInvalidValue;
+    if (mode == TLAD_PCG && fp32) return hipErrorInvalidValue;  // PCG recurrences stay FP64
     return fp32 ? launch_t<float>(s, a, g, mode) : launch_t<double>(s, a, g, mode);
 }
 

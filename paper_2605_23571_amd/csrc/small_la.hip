@@ -9,7 +9,8 @@
 namespace eda {
 namespace {
 
-constexpr int ST = 256;  // threads of the small kernels
+constexpr int ST = 256;   // threads of the small kernels
+constexpr int SJ = 1024;  // threads of the Jacobi kernels (one wave per column pair)
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -107,13 +108,13 @@ __device__ __forceinline__ void rr_pair(int m, int r, int k, int &p, int &q) {
 // One-sided (Hestenes) Jacobi SVD of T (l x l): columns are rotated until
 // mutually orthogonal; then sigma_j = ||t_j||, U[:, rank(j)] = t_j / sigma_j
 // with ranks sorting sigma descending (ties: lower index first).
-__global__ __launch_bounds__(ST) void k_jacobi_svd(int l, const double *__restrict__ T, double *__restrict__ U,
+__global__ __launch_bounds__(SJ) void k_jacobi_svd(int l, const double *__restrict__ T, double *__restrict__ U,
                                                    double *__restrict__ sig) {
     extern __shared__ double A[];  // l x l col-major
     __shared__ int rotated;
     __shared__ double nrm[128];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int idx = tid; idx < l * l; idx += ST) A[idx] = T[idx];
+    for (int idx = tid; idx < l * l; idx += SJ) A[idx] = T[idx];
     __syncthreads();
     const int m = (l + 1) & ~1;
     const double tol = 1e-15;
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(ST) void k_jacobi_svd(int l, const double *__restri
         if (tid == 0) rotated = 0;
         __syncthreads();
         for (int r = 0; r < m - 1; r++) {
-            for (int k = wave; k < m / 2; k += ST / 64) {
+            for (int k = wave; k < m / 2; k += SJ / 64) {
                 int p, q;
                 rr_pair(m, r, k, p, q);
                 if (q >= l) continue;
@@ -152,14 +153,14 @@ __global__ __launch_bounds__(ST) void k_jacobi_svd(int l, const double *__restri
         if (!rotated) break;
         __syncthreads();
     }
-    for (int j = wave; j < l; j += ST / 64) {
+    for (int j = wave; j < l; j += SJ / 64) {
         double v = 0;
         for (int i = lane; i < l; i += 64) v += A[i + j * l] * A[i + j * l];
         v = wave_sum(v);
         if (lane == 0) nrm[j] = sqrt(v);
     }
     __syncthreads();
-    for (int j = tid; j < l; j += ST) {
+    for (int j = tid; j < l; j += SJ) {
         double sj = nrm[j];
         int rank = 0;
         for (int i = 0; i < l; i++) {
@@ -343,7 +344,7 @@ hipError_t launch_small_gemm(hipStream_t s, int l, bool ta, bool tb, const doubl
 
 hipError_t launch_jacobi_svd_u(hipStream_t s, int l, double *T, double *U, double *sig) {
     if (l > 128) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_jacobi_svd, dim3(1), dim3(ST), sizeof(double) * l * l, s, l, T, U, sig);
+    hipLaunchKernelGGL(k_jacobi_svd, dim3(1), dim3(SJ), sizeof(double) * l * l, s, l, T, U, sig);
     return hipGetLastError();
 }
 
