@@ -45,6 +45,8 @@ bool valid_cfg(const eda_config *c) {
 
 struct Plan {
     int n, N, L, nt, nv, p, maxc, maxl;
+    int pad_l, ext_len;
+    size_t off_trajx, off_ub16;
     size_t off_ubrow, off_ub, off_truth, off_spin, off_xb, off_traj, off_y, off_d, off_force, off_b, off_costc;
     size_t off_hv_v, off_hv_obs, off_hv_lam, off_zero;
     size_t off_phi, off_sy, off_sq, off_sq1, off_ss, off_small, off_eig, off_coef, off_coefu, off_info, off_splitk,
@@ -70,10 +72,18 @@ Plan make_plan(const eda_config *c) {
     Layout lay;
     P.off_ubrow = lay.take(n * d);
     P.off_ub = c->ub_mode == EDA_UB_DENSE ? lay.take(n * n * d) : (size_t)-1;
+    P.off_ub16 = c->ub_mode == EDA_UB_DENSE ? lay.take(n * n * sizeof(uint16_t)) : (size_t)-1;
     P.off_truth = lay.take((P.N + 1) * n * d);
     P.off_spin = lay.take(n * d);
     P.off_xb = lay.take(n * L1 * d);
     P.off_traj = lay.take(L1 * (P.N + 1) * n * d);
+    {
+        int pl, pr;
+        tlad_pads(P.n, &pl, &pr);
+        P.pad_l = pl;
+        P.ext_len = ((P.n + pl + pr + 31) / 32) * 32;
+    }
+    P.off_trajx = lay.take(L1 * (size_t)P.N * P.ext_len * d);
     P.off_y = lay.take(p * L1 * d);
     P.off_d = lay.take(p * L1 * d);
     P.off_force = lay.take(p * L1 * d);
@@ -132,10 +142,13 @@ void band_taps(int n, double len_b, int &lo, int &hi) {
     }
 }
 
-// Y = U_B X (+ Add), columns optionally masked.
+// Y = U_B X (+ Add), columns optionally masked.  lowp: the dense product runs
+// with BF16 operands and FP32 accumulation (reduced-precision sketch).
 int ub_apply(Ctx &c, int nb, const double *X, long long ldx, double *Y, long long ldy, const double *Add,
-             long long ldadd, const int32_t *active) {
-    if (c.cfg.ub_mode == EDA_UB_DENSE) {
+             long long ldadd, const int32_t *active, bool lowp = false) {
+    if (c.cfg.ub_mode == EDA_UB_DENSE && lowp) {
+        HIP_TRY(gemm_bf16(c.stream, c.n, nb, c.n, c.ub16, c.n, X, ldx, Y, ldy, Add, ldadd));
+    } else if (c.cfg.ub_mode == EDA_UB_DENSE) {
         HIP_TRY(gemm_f64(c.stream, false, c.n, nb, c.n, c.ub, c.n, X, ldx, Y, ldy, Add, ldadd, nullptr, nullptr, 0));
     } else {
         HIP_TRY(launch_band_conv(c.stream, c.n, nb, c.band_lo, c.band_hi, c.ubrow, X, ldx, Y, ldy, Add, ldadd,
@@ -160,8 +173,10 @@ TladArgs tlad_args(Ctx &c, int nb, const int32_t *cols, const int32_t *active) {
     a.nt = c.nt;
     a.nv = c.nv;
     a.inv_s2 = 1.0 / (c.cfg.sigma_o * c.cfg.sigma_o);
-    a.traj = c.traj;
-    a.traj_stride = (long long)(c.N + 1) * c.n;
+    a.trajx = c.trajx;
+    a.trajx_stride = (long long)c.N * c.ext_len;
+    a.ext_len = c.ext_len;
+    a.pad_l = c.pad_l;
     a.col_member = cols;
     a.active = active;
     a.ubrow = c.ubrow;
@@ -211,7 +226,7 @@ int hessvec(Ctx &c, const int32_t *cols, int nb, const double *X, long long ldx,
         a.add_identity = add ? 1 : 0;
         return run_tlad(c, a, TLAD_HV, fp32);
     }
-    EDA_TRY(ub_apply(c, nb, X, ldx, c.hv_v, c.n, nullptr, 0, active));
+    EDA_TRY(ub_apply(c, nb, X, ldx, c.hv_v, c.n, nullptr, 0, active, fp32));
     TladArgs a = tlad_args(c, nb, cols, active);
     a.V = c.hv_v;
     a.ldv = c.n;
@@ -219,7 +234,7 @@ int hessvec(Ctx &c, const int32_t *cols, int nb, const double *X, long long ldx,
     a.lam = c.hv_lam;
     a.ldl = c.n;
     EDA_TRY(run_tlad(c, a, TLAD_RAW, fp32));
-    EDA_TRY(ub_apply(c, nb, c.hv_lam, c.n, Y, ldy, add ? X : nullptr, ldx, active));
+    EDA_TRY(ub_apply(c, nb, c.hv_lam, c.n, Y, ldy, add ? X : nullptr, ldx, active, fp32));
     return EDA_OK;
 }
 
@@ -315,10 +330,14 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
     char *w = c.ws;
     c.ubrow = at<double>(w, P.off_ubrow);
     c.ub = P.off_ub == (size_t)-1 ? nullptr : at<double>(w, P.off_ub);
+    c.ub16 = P.off_ub16 == (size_t)-1 ? nullptr : at<uint16_t>(w, P.off_ub16);
     c.truth = at<double>(w, P.off_truth);
     double *spin = at<double>(w, P.off_spin);
     c.xb = at<double>(w, P.off_xb);
     c.traj = at<double>(w, P.off_traj);
+    c.trajx = at<double>(w, P.off_trajx);
+    c.ext_len = P.ext_len;
+    c.pad_l = P.pad_l;
     c.y = at<double>(w, P.off_y);
     c.d = at<double>(w, P.off_d);
     c.forcing = at<double>(w, P.off_force);
@@ -368,6 +387,7 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
     // U_B
     if (launch_ub_row(s, n, cfg->sigma_b, cfg->len_b, c.ubrow) != hipSuccess) return fail(EDA_ERR_HIP);
     if (c.ub && launch_ub_fill(s, n, c.ubrow, c.ub) != hipSuccess) return fail(EDA_ERR_HIP);
+    if (c.ub16 && launch_to_bf16(s, (long long)n * n, c.ub, c.ub16) != hipSuccess) return fail(EDA_ERR_HIP);
     // truth: spin-up then the window
     if (launch_spin_init(s, n, F, cfg->spin_pert_std, z, spin) != hipSuccess) return fail(EDA_ERR_HIP);
     if (cfg->spinup > 0 && launch_nl(s, n, 1, cfg->spinup, F, hh, dt, c6, spin, nullptr, spin) != hipSuccess)
@@ -382,6 +402,8 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
     if (launch_xb(s, n, L, c.truth, c.hv_v, c.xb) != hipSuccess) return fail(EDA_ERR_HIP);
     // member trajectories
     if (launch_nl(s, n, L + 1, N, F, hh, dt, c6, c.xb, c.traj, nullptr) != hipSuccess) return fail(EDA_ERR_HIP);
+    if (launch_pad_traj(s, n, N, L + 1, c.traj, c.pad_l, c.ext_len, c.trajx) != hipSuccess)
+        return fail(EDA_ERR_HIP);
     // innovations, forcing R^-1 d, cost constants
     if (launch_innov(s, n, N, L, p, c.nv, cfg->obs_dt, cfg->obs_dx, cfg->obs_x0, cfg->sigma_o * cfg->sigma_o, c.y,
                      c.traj, c.d, c.forcing, c.costc) != hipSuccess)

@@ -35,6 +35,9 @@ struct Ctx {
 
     // problem data
     double *ubrow = nullptr, *ub = nullptr, *truth = nullptr, *xb = nullptr, *traj = nullptr;
+    uint16_t *ub16 = nullptr;  // dense U_B in BF16 (reduced-precision sketch products)
+    double *trajx = nullptr;  // trajectory rows s < N, periodically padded for the TL/AD windows
+    int ext_len = 0, pad_l = 0;
     double *y = nullptr, *d = nullptr, *b = nullptr, *costc = nullptr, *forcing = nullptr;
     // hessvec scratch
     double *hv_v = nullptr, *hv_obs = nullptr, *hv_lam = nullptr;
@@ -109,8 +112,9 @@ struct TladArgs {
     double F, dt, h, dt6, dt3;
     int obs_dt, obs_dx, obs_x0, nt, nv;
     double inv_s2;
-    const double *traj;
-    long long traj_stride;
+    const double *trajx;    // padded trajectory rows (see launch_pad_traj)
+    long long trajx_stride; // per member
+    int ext_len, pad_l;     // row length and left pad of the padded rows
     const int32_t *col_member;
     const int32_t *active;
     const double *V;      // RAW: input increments; HV: input X
@@ -130,6 +134,9 @@ struct TladGeom {
     int waves, S, q, tb, hl_tl, hl_ad;
 };
 TladGeom tlad_geometry(int n, int waves_hint);
+// Pads of the periodic row extension that every wave window of the TL/AD
+// kernel fits in without wrapping: window points j in [-pad_l, n + pad_r).
+void tlad_pads(int n, int *pad_l, int *pad_r);
 hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32);
 
 // U_B first row (closed form) and dense fill.
@@ -148,6 +155,12 @@ hipError_t gemm_f64(hipStream_t s, bool trans_a, int M, int N, int K, const doub
                     const double *B, long long ldb, double *C, long long ldc, const double *Add,
                     long long ldadd, const double *rowscale, double *part, size_t part_elems);
 size_t gemm_splitk_elems(int M, int N, int K);
+// BF16-operand, FP32-accumulate GEMM C = A B (+ Add): A in BF16 (M x K,
+// column-major), B, C, Add in FP64 (B rounded to BF16 as it is staged).
+hipError_t gemm_bf16(hipStream_t s, int M, int N, int K, const unsigned short *A, long long lda, const double *B,
+                     long long ldb, double *C, long long ldc, const double *Add, long long ldadd);
+// y = bf16(x), round to nearest even.
+hipError_t launch_to_bf16(hipStream_t s, long long count, const double *x, unsigned short *y);
 
 // Setup helpers.
 hipError_t launch_obs(hipStream_t s, int n, int L, int p, int nv, int obs_dt, int obs_dx, int obs_x0,
@@ -156,6 +169,10 @@ hipError_t launch_xb(hipStream_t s, int n, int L, const double *xt0, const doubl
 hipError_t launch_innov(hipStream_t s, int n, int N, int L, int p, int nv, int obs_dt, int obs_dx,
                         int obs_x0, double s2, const double *y, const double *traj, double *d,
                         double *force, double *costc);
+// Periodic extension of trajectory rows: out[m][s][j] = traj[m][s][(j - pad_l) mod n],
+// j < ext_len, for states s < N of each of nm members (input rows N + 1 per member).
+hipError_t launch_pad_traj(hipStream_t s, int n, int N, int nm, const double *traj, int pad_l, int ext_len,
+                           double *out);
 hipError_t launch_gamma(hipStream_t s, int n, int ell, const double *b, double *gam);
 
 // Small dense kernels (one workgroup, ell <= 128, matrices col-major ell x ell).

@@ -1,0 +1,142 @@
+// BF16-input, FP32-accumulate GEMM on the matrix cores
+// (v_mfma_f32_16x16x16_bf16), column-major:  C = A B (+ Add).
+// Used for the dense U_B products of the reduced-precision sketch: A is U_B
+// held in BF16 (converted once at set-up), B is an FP64 block converted to BF16
+// (round to nearest even) as it is staged, C and Add are FP64.  Each product
+// element carries the BF16 rounding of both operands (relative 2^-9 each) and an
+// FP32 accumulation of K terms.
+//
+// Tile 64 x 64 per 256-thread workgroup (4 waves 2 x 2, each wave 2 x 2 MFMA
+// blocks of 16 x 16), K step 32 staged in LDS.  As in the FP64 GEMM the MFMA
+// is fed (B^T, A^T) so that accumulator lanes run along output rows.
+#include "eda_internal.h"
+
+namespace eda {
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float float4v __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 32;
+
+__device__ __forceinline__ unsigned short to_bf16(double d) {
+    float f = (float)d;
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);  // inf / nan kept
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__global__ void k_to_bf16(long long count, const double *__restrict__ x, unsigned short *__restrict__ y) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (long long)gridDim.x * blockDim.x)
+        y[i] = to_bf16(x[i]);
+}
+
+__global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const unsigned short *__restrict__ A,
+                                                   long long lda, const double *__restrict__ B, long long ldb,
+                                                   double *__restrict__ C, long long ldc,
+                                                   const double *__restrict__ Add, long long ldadd) {
+    // As[k][m], Bs[k][n]; rows padded by 8 bf16 against bank conflicts
+    __shared__ unsigned short As[BK][BM + 8];
+    __shared__ unsigned short Bs[BK][BN + 8];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
+
+    float4v acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++) acc[a][b] = float4v{0.f, 0.f, 0.f, 0.f};
+
+    // staging: 64 x 32 elements of each operand per K step = 8 per thread
+    unsigned short ra[8], rb[8];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int idx = tid + 256 * e;
+            const int r = idx % BM, kk = idx / BM;  // A: consecutive threads along rows (column-major)
+            const int gi = i0 + r, gk = k0 + kk;
+            ra[e] = (gi < M && gk < K) ? A[gi + (long long)gk * lda] : (unsigned short)0;
+            const int kb = idx % BK, cc = idx / BK;  // B: consecutive threads along K
+            const int gj = j0 + cc, gkb = k0 + kb;
+            rb[e] = (gj < N && gkb < K) ? to_bf16(B[gkb + (long long)gj * ldb]) : (unsigned short)0;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int idx = tid + 256 * e;
+            As[idx / BM][idx % BM] = ra[e];
+            Bs[idx % BK][idx / BK] = rb[e];
+        }
+    };
+
+    load(0);
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        store();
+        __syncthreads();
+        if (k0 + BK < K) load(k0 + BK);
+#pragma unroll
+        for (int ks = 0; ks < BK / 16; ks++) {
+            // lane l supplies k = 16 ks + 4 (l / 16) + e, e = 0..3
+            const int kb = ks * 16 + 4 * (lane >> 4);
+            bf16x4 av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; a++) {
+                const int m = wr * 32 + a * 16 + (lane & 15);
+#pragma unroll
+                for (int e = 0; e < 4; e++) av[a][e] = (short)As[kb + e][m];
+            }
+#pragma unroll
+            for (int b = 0; b < 2; b++) {
+                const int nn = wc * 32 + b * 16 + (lane & 15);
+#pragma unroll
+                for (int e = 0; e < 4; e++) bv[b][e] = (short)Bs[kb + e][nn];
+            }
+#pragma unroll
+            for (int a = 0; a < 2; a++)
+#pragma unroll
+                for (int b = 0; b < 2; b++)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bv[b], av[a], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    // element v of lane l: C[row = l % 16][col = 4 (l / 16) + v] of each block
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int row = i0 + wr * 32 + a * 16 + (lane & 15);
+                const int col = j0 + wc * 32 + b * 16 + 4 * (lane >> 4) + v;
+                if (row < M && col < N) {
+                    double val = (double)acc[a][b][v];
+                    if (Add) val += Add[row + (long long)col * ldadd];
+                    C[row + (long long)col * ldc] = val;
+                }
+            }
+}
+
+}  // namespace
+
+hipError_t launch_to_bf16(hipStream_t s, long long count, const double *x, unsigned short *y) {
+    if (count <= 0) return hipSuccess;
+    long long blocks = (count + 255) / 256;
+    if (blocks > 65535) blocks = 65535;
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)blocks), dim3(256), 0, s, count, x, y);
+    return hipGetLastError();
+}
+
+hipError_t gemm_bf16(hipStream_t s, int M, int N, int K, const unsigned short *A, long long lda, const double *B,
+                     long long ldb, double *C, long long ldc, const double *Add, long long ldadd) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN);
+    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, Add, ldadd);
+    return hipGetLastError();
+}
+
+}  // namespace eda

@@ -4,7 +4,9 @@
 // Q^T A Q), Q = Y R^-1, S = Q U and the LMP's S_k^T X / X + S_k T.
 //
 // Tile 64 x 64 per 256-thread workgroup (4 waves in a 2 x 2 arrangement, each
-// wave 2 x 2 MFMA blocks of 16 x 16), K step 32 staged in LDS.  For the
+// wave 2 x 2 MFMA blocks of 16 x 16), K step 32 staged in LDS.  The MFMA is fed
+// B^T and A^T so that accumulator lanes run along the rows of the column-major
+// output (coalesced stores).  For the
 // K-long, M/N-small products (Gram matrices, S^T X) the K range is split over
 // workgroups; partial tiles go to a workspace and are summed in a fixed order,
 // so results do not depend on scheduling.
@@ -90,21 +92,23 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const double 
                 for (int a = 0; a < 2; a++)
 #pragma unroll
                     for (int b = 0; b < 2; b++)
-                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[b], av[a], acc[a][b], 0, 0, 0);
             }
             __syncthreads();
         }
     }
 
-    // D[row][col] of a 16 x 16 block: row = lane / 16 + 4 v, col = lane % 16.
+    // The MFMA ran on (B^T, A^T), so each 16 x 16 accumulator holds the transposed
+    // block: element v of lane l is C[row = l % 16][col = l / 16 + 4 v] of the
+    // block, and every store covers 16 consecutive rows of 4 columns.
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
         for (int b = 0; b < 2; b++)
 #pragma unroll
             for (int v = 0; v < 4; v++) {
-                const int row = i0 + wr * 32 + a * 16 + (lane >> 4) + 4 * v;
-                const int col = j0 + wc * 32 + b * 16 + (lane & 15);
+                const int row = i0 + wr * 32 + a * 16 + (lane & 15);
+                const int col = j0 + wc * 32 + b * 16 + (lane >> 4) + 4 * v;
                 if (row < M && col < N) {
                     double val = acc[a][b][v];
                     if (part) {
@@ -125,19 +129,21 @@ __global__ void k_splitk_reduce(int M, int N, int nsplit, const double *__restri
     if (idx >= (long long)M * N) return;
     int row = (int)(idx % M), col = (int)(idx / M);
     double s = 0.0;
-    for (int z = 0; z < nsplit; z++) s += part[(long long)z * M * N + idx];
+#pragma unroll 8
+    for (int z = 0; z < nsplit; z++) s += part[(long long)z * M * N + idx];  // fixed order
     if (rowscale) s *= rowscale[row];
     if (Add) s += Add[row + (long long)col * ldadd];
     C[row + (long long)col * ldc] = s;
 }
 
-// K-split for products whose output has few tiles: aim at about 512
-// workgroups, with at least 64 of K per workgroup.
+// K-split for products whose output has few tiles: aim at about 256
+// workgroups, with at least 128 of K per workgroup (the partial sums cost
+// nsplit M N doubles written and read again).
 int split_count(int M, int N, int K) {
     int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
     if (tiles >= 128 || K < 256) return 1;
-    int ns = 512 / tiles;
-    int cap = K / 64;
+    int ns = 256 / tiles;
+    int cap = K / 128;
     if (ns > cap) ns = cap;
     return ns < 1 ? 1 : ns;
 }

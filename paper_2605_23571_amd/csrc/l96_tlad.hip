@@ -35,25 +35,27 @@
 namespace eda {
 namespace {
 
-// lane l receives the value of lane l - 1 (lane 0: zero; window-edge garbage)
+// lane l receives the value of lane l - 1 (wave_shr:1; lane 0 gets zero, which
+// only reaches window-edge points).  bound_ctrl writes the zero itself, so no
+// old value has to be materialised.
 __device__ __forceinline__ double from_prev(double v) {
     long long b = __double_as_longlong(v);
-    int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x138, 0xf, 0xf, false);
-    int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, false);
+    int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x138, 0xf, 0xf, true);
+    int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
-// lane l receives the value of lane l + 1
+// lane l receives the value of lane l + 1 (wave_shl:1; lane 63 gets zero)
 __device__ __forceinline__ double from_next(double v) {
     long long b = __double_as_longlong(v);
-    int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xf, 0xf, false);
-    int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, false);
+    int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xf, 0xf, true);
+    int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 __device__ __forceinline__ float from_prev(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float from_next(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
 // e[0..1] = previous lane's last two points, e[2..Q+1] = own, e[Q+2..Q+3] = next lane's first two.
@@ -97,10 +99,41 @@ __device__ __forceinline__ int wpos(int base, int q, int n) {
     return p >= n ? p - n : p;
 }
 
-template <typename T, int Q>
-__device__ __forceinline__ void load_x(const double *__restrict__ xs, int base, int n, T (&x)[Q]) {
+// Start the asynchronous copy of this wave's trajectory window -- 64 Q
+// consecutive doubles of a padded state row, from xe on -- into the wave's LDS
+// slice: 2Q direct global-to-LDS dword copies, lane l of copy i moving dword
+// 64 i + l, so slice[j] = xe[j].  No registers are held while it is in flight.
+template <int Q>
+__device__ __forceinline__ void prefetch_window(const double *xe, double *slice) {
+    const int lane = threadIdx.x & 63;
+    const char *g = reinterpret_cast<const char *>(xe) + 4 * lane;
+    char *l = reinterpret_cast<char *>(slice);
 #pragma unroll
-    for (int q = 0; q < Q; q++) x[q] = (T)xs[wpos(base, q, n)];
+    for (int i = 0; i < 2 * Q; i++)
+        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(g + 256 * i),
+                                         (void __attribute__((address_space(3))) *)(l + 256 * i), 4, 0, 0);
+}
+
+// This lane's Q window points from the wave's slice, once the copy has landed
+// (vmcnt(0)); the reads complete (lgkmcnt(0)) before the slice may be refilled.
+template <typename T, int Q>
+__device__ __forceinline__ void read_window(const double *slice, T (&x)[Q]) {
+    const int lane = threadIdx.x & 63;
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+#pragma unroll
+    for (int q = 0; q < Q; q++) x[q] = (T)slice[lane * Q + q];
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+}
+
+// Observed increments R^-1 H dx of this lane's owned observed points.
+template <typename T, int Q>
+__device__ __forceinline__ void store_obs(double *o, const int *qi, const T (&dx)[Q], double inv_s2) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        const int oi = qi[q * 64 + lane];
+        if (oi >= 0) o[oi] = (double)dx[q] * inv_s2;
+    }
 }
 
 // Window of this lane: ring position of its first point (base; the others
@@ -201,17 +234,19 @@ __global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
     } else if (a.active && a.active[c] != COL_RUNNING) {
         return;
     }
-    // LDS: [ring: 2n T][qi: waves*64*Q int][u: n double][taps: W double][red: 16 double]
+    // LDS: [ring: 2n T][qi: waves*64*Q int][xw: waves*64*Q double][u: n double][taps: W double][red: 16 double]
     T *ring = reinterpret_cast<T *>(smraw);  // two buffers, indexed rsel * n + position
     int *qi = reinterpret_cast<int *>(ring + 2 * n) + wave * 64 * Q;
-    double *u = reinterpret_cast<double *>(reinterpret_cast<int *>(ring + 2 * n) + g.waves * 64 * Q);
+    double *xw_all = reinterpret_cast<double *>(reinterpret_cast<int *>(ring + 2 * n) + g.waves * 64 * Q);
+    double *xw = xw_all + wave * 64 * Q;  // this wave's trajectory window slice
+    double *u = xw_all + g.waves * 64 * Q;
     double *taps = u + n;
     const int W = a.band_hi - a.band_lo + 1;
     double *red = taps + W;
     double *lamd = reinterpret_cast<double *>(ring);  // ring reused as a double array for lambda_0
     const int own_lo = wave * g.S, own_hi = min(n, own_lo + g.S);
     const int member = MODE == TLAD_PCG ? a.pcg.members[c] : (a.col_member ? a.col_member[c] : 0);
-    const double *traj = a.traj + (long long)member * a.traj_stride;
+    const double *trajm = a.trajx + (long long)member * a.trajx_stride + a.pad_l;  // row s: trajm + s ext_len
     const T F = (T)a.F, h = (T)a.h, dt = (T)a.dt, dt6 = (T)a.dt6, dt3 = (T)a.dt3;
     unsigned ownm;
     int rsel = 0;
@@ -254,7 +289,9 @@ __global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
 
     if (MODE != TLAD_ADJ) {
         // ---------------- TL forward run ----------------
-        int base = window<Q>(a, own_lo - g.hl_tl, own_lo, own_hi, true, ownm, qi);
+        const int w0 = own_lo - g.hl_tl;
+        prefetch_window<Q>(trajm + w0, xw);
+        int base = window<Q>(a, w0, own_lo, own_hi, true, ownm, qi);
         T dx[Q];
         if (FUSED) {
             double v0[Q];
@@ -276,7 +313,12 @@ __global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
             const int s1 = min(N, s0 + g.tb);
             for (int s = s0; s < s1; s++) {
                 T x[Q], Y[Q + 4], V[Q + 4], k[Q], dk[Q], acc[Q], ys[Q], vs[Q];
-                load_x<T, Q>(traj + (long long)s * n, base, n, x);
+                read_window<T, Q>(xw, x);
+                // observed increment of time s, stored here (after the wait on
+                // the window copy) so that no store is pending at the next wait
+                if (s > 0 && s % a.obs_dt == 0)
+                    store_obs<T, Q>(obs + (long long)(s / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
+                if (s + 1 < N) prefetch_window<Q>(trajm + (long long)(s + 1) * a.ext_len + w0, xw);
                 ext<T, Q>(x, Y);
                 ext<T, Q>(dx, V);
                 tl_stage<T, Q, true>(Y, V, F, k, dk);
@@ -309,14 +351,6 @@ __global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
                 tl_stage<T, Q, false>(Y, V, F, k, dk);
 #pragma unroll
                 for (int j = 0; j < Q; j++) dx[j] = dx[j] + dt6 * (acc[j] + dk[j]);
-                if ((s + 1) % a.obs_dt == 0) {
-                    double *o = obs + (long long)((s + 1) / a.obs_dt - 1) * a.nv;
-#pragma unroll
-                    for (int q = 0; q < Q; q++) {
-                        const int oi = qi[q * 64 + lane];
-                        if (oi >= 0) o[oi] = (double)dx[q] * a.inv_s2;
-                    }
-                }
             }
             if (s1 < N) {
 #pragma unroll
@@ -325,12 +359,15 @@ __global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
                 rsel ^= 1;
             }
         }
+        if (N % a.obs_dt == 0) store_obs<T, Q>(obs + (long long)(N / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
         __threadfence_block();  // observed increments visible to the whole workgroup
     }
     __syncthreads();  // TL reads of the ring and of the observation indices are done
 
     // ---------------- AD backward run ----------------
-    const int base = window<Q>(a, own_lo - g.hl_ad, own_lo, own_hi, false, ownm, qi);
+    const int w0 = own_lo - g.hl_ad;
+    prefetch_window<Q>(trajm + (long long)(N - 1) * a.ext_len + w0, xw);
+    const int base = window<Q>(a, w0, own_lo, own_hi, false, ownm, qi);
     const double *force = (MODE == TLAD_ADJ) ? a.force + (long long)c * p : a.obs + (long long)c * p;
     T lam[Q];
 #pragma unroll
@@ -351,9 +388,9 @@ __global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
                     if (oi >= 0) lam[q] += (T)f[oi];
                 }
             }
-            const double *xs = traj + (long long)(s - 1) * n;
             T x[Q], Y2[Q + 4], Y3[Q + 4], Y4[Q + 4], M[Q + 4], k[Q], ys[Q];
-            load_x<T, Q>(xs, base, n, x);
+            read_window<T, Q>(xw, x);  // X[s - 1]
+            if (s >= 2) prefetch_window<Q>(trajm + (long long)(s - 2) * a.ext_len + w0, xw);
             {
                 T Y1[Q + 4];
                 ext<T, Q>(x, Y1);
@@ -491,7 +528,7 @@ __global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
 
 template <typename T, int Q>
 size_t lds_bytes(const TladArgs &a, const TladGeom &g, int mode) {
-    size_t b = sizeof(T) * 2 * (size_t)a.n + sizeof(int) * (size_t)g.waves * 64 * Q;
+    size_t b = sizeof(T) * 2 * (size_t)a.n + (sizeof(int) + sizeof(double)) * (size_t)g.waves * 64 * Q;
     if (mode == TLAD_HV || mode == TLAD_PCG)
         b += sizeof(double) * ((size_t)a.n + (size_t)(a.band_hi - a.band_lo + 1) + 16);
     return b;
@@ -545,6 +582,16 @@ TladGeom tlad_geometry(int n, int waves_hint) {
     g.hl_tl = 8 * g.tb;
     g.hl_ad = 4 * g.tb + 8;
     return g;
+}
+
+void tlad_pads(int n, int *pad_l, int *pad_r) {
+    const TladGeom g = tlad_geometry(n, 0);
+    const int hmax = g.hl_tl > g.hl_ad ? g.hl_tl : g.hl_ad;
+    const int hmin = g.hl_tl < g.hl_ad ? g.hl_tl : g.hl_ad;
+    // window of wave w: [w S - hl, w S - hl + 64 Q)
+    const int right = (g.waves - 1) * g.S - hmin + 64 * g.q - n;
+    *pad_l = hmax;
+    *pad_r = right > 0 ? right : 0;
 }
 
 hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32) {

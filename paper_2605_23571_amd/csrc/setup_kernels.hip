@@ -138,7 +138,26 @@ __global__ void k_gamma(int n, int ell, const double *__restrict__ b, double *__
     g[idx] = b[(long long)(j + 1) * n + i] - b[i];
 }
 
+__global__ void k_pad_traj(int n, int N, int pad_l, int ext_len, const double *__restrict__ traj,
+                           double *__restrict__ out) {
+    const int m = blockIdx.y, st = blockIdx.z;
+    const double *row = traj + ((long long)m * (N + 1) + st) * n;
+    double *o = out + ((long long)m * N + st) * ext_len;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ext_len; j += gridDim.x * blockDim.x) {
+        int i = (j - pad_l) % n;
+        o[j] = row[i < 0 ? i + n : i];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_pad_traj(hipStream_t s, int n, int N, int nm, const double *traj, int pad_l, int ext_len,
+                           double *out) {
+    if (nm <= 0 || N <= 0) return hipSuccess;
+    const int bx = (ext_len + 255) / 256;
+    hipLaunchKernelGGL(k_pad_traj, dim3(bx, nm, N), dim3(256), 0, s, n, N, pad_l, ext_len, traj, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_ub_row(hipStream_t s, int n, double sigma_b, double len_b, double *row) {
     double amp = sigma_b * pow(2.0 / M_PI, 0.25) / sqrt(len_b);

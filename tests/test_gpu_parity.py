@@ -111,6 +111,21 @@ def test_hessvec_mixed_precision_bound(case):
     assert 1e-10 < err < 1e-4, err
 
 
+@pytest.mark.parametrize("case", ["C1", "n1001"])
+def test_hessvec_mixed_dense_bf16_bound(case):
+    # Dense U_B with the reduced-precision flag: both U_B products take BF16
+    # operands (unit roundoff 2^-9 each) with FP32 accumulation, the TL/AD runs
+    # FP32.  Each product carries about 2^-9 relative rounding from each operand,
+    # so the stated bound on the whole A X is 1e-2; it must also exceed the FP32
+    # path's error (the BF16 products really ran).
+    cfg, g, o = problem(case, "dense")
+    n = cfg["n"]
+    X = np.random.default_rng(4).standard_normal((cfg["ell"], n))
+    Y = to_np_cols(g.hessvec(np.zeros(cfg["ell"], dtype=np.int32), torch.from_numpy(X).cuda(), mixed=True), n)
+    err = colrel(Y, o.A(X.T, [0] * cfg["ell"]))
+    assert 1e-5 < err < 1e-2, err
+
+
 def test_hessvec_edge_cases():
     cfg, g, o = problem("C1")
     n = cfg["n"]
