@@ -46,7 +46,37 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-baseline sample time")
     ap.add_argument("--hv-reps", type=int, default=20)
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch (256 problems) measurement")
+    ap.add_argument("--batch-problems", type=int, default=256)
+    ap.add_argument("--batch-plain", type=int, default=64, help="problems timed through the per-problem path")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration; untimed)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tlad_C3_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2605_23571_amd", "csrc", "l96_tlad.hip")
+
+
+def kernel_sha():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(active_per_launch):
+    """HBM bytes per launch of the fused PCG kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading),
+    or None when the summary is missing or was taken on another kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("traffic-json: "):
+            t = json.loads(line[len("traffic-json: "):])
+            if t.get("kernel_sha") != kernel_sha():
+                return None
+            return round(t["bytes_per_active_column"] * active_per_launch)
+    return None
 
 
 def pcg_kernel_bytes_per_col(cfg):
@@ -114,6 +144,67 @@ def run_form(cfg, z, ub_mode, steps, warmup, hv_reps):
     return res
 
 
+def run_uneven_batch(count, reps, plain_count):
+    """Uneven batching: `count` independent problems (n in {40,...,2048}, window
+    10/20/40, 8-64 members, k = min(32, members)), every member solved to
+    rtol 1e-6 with its problem's Gamma-Nystrom LMP.  Chosen: one batch (per-class
+    sketch launches, Nystrom cores and persistent solve launches in one captured
+    graph, autotuned geometry); the first call tunes and captures, the timed
+    calls replay.  Plain: the same problems one after another through
+    eda_sketch_evd + eda_pcg_solve (first plain_count problems)."""
+    import torch
+    from paper_2605_23571_amd import eda
+
+    cfgs = W.uneven_problems(count)
+    t0 = time.perf_counter()
+    probs = [eda.Problem(c, W.problem_normals(c)) for c in cfgs]
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    bt = eda.Batch(probs)
+    t0 = time.perf_counter()
+    bt.solve(k_cap=32, rtol=1e-6, maxit=2000)
+    first_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    fb = [0, 0]
+    for _ in range(reps):
+        f = bt.solve(k_cap=32, rtol=1e-6, maxit=2000)
+        fb = [fb[0] + f[0], fb[1] + f[1]]
+    dt = (time.perf_counter() - t0) / reps
+    cols = sum(c["members"] + 1 for c in cfgs)
+    conv, iters = True, []
+    for p in range(count):
+        r = bt.result(p, with_dz=False)
+        conv &= bool((r["status"] == eda.EDA_MEMBER_CONVERGED).all())
+        iters.append(r["iters"])
+    tun = bt.tuning()
+    bt.close()
+    # plain: host-driven per-problem path on the first plain_count problems
+    pc = min(plain_count, count)
+    pcols = sum(c["members"] + 1 for c in cfgs[:pc])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c, g in zip(cfgs[:pc], probs[:pc]):
+        try:
+            g.sketch_evd("rhs_diff", ell=c["k"], k=c["k"])
+            lmp = True
+        except eda.EdaError as e:  # the same rule as the batch: no LMP where the shifted sketch fails
+            if e.code != eda.EDA_ERR_NOT_SPD:
+                raise
+            lmp = False
+        g.pcg(np.arange(c["members"] + 1), rtol=1e-6, maxit=2000, use_lmp=lmp)
+    torch.cuda.synchronize()
+    plain_dt = time.perf_counter() - t0
+    for g in probs:
+        g.close()
+    it = np.concatenate(iters)
+    return {"problems": count, "member_solves": cols, "value": round(cols / dt, 1), "unit": "solves/s",
+            "s_per_batch": round(dt, 4), "first_call_s": round(first_s, 3), "setup_s": round(setup_s, 2),
+            "all_converged": conv, "host_redone_per_call": fb[0] / reps, "without_lmp_per_call": fb[1] / reps, "iters_median": float(np.median(it)), "iters_max": int(it.max()),
+            "classes": tun,
+            "plain": {"problems": pc, "member_solves": pcols, "value": round(pcols / plain_dt, 1),
+                      "unit": "solves/s"}}
+
+
 def cpu_baseline(cfg, z, target_s):
     """The CPU oracle (unchanged) on a bounded sample of the same workload: the
     Gamma-Nystrom sketch once, then LMP-PCG for members 0, 1, ... until about
@@ -149,6 +240,12 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     cfg = W.config(a.workload)
     z = W.problem_normals(cfg)
+    if a.copy_mib > 0:
+        src = torch.ones(a.copy_mib << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(f"[bench] {a.workload} chosen form (banded U_B)", file=sys.stderr, flush=True)
     chosen = run_form(cfg, z, "banded", a.steps, a.warmup, a.hv_reps)
     plain = None
@@ -177,10 +274,12 @@ def main():
                                f"Gamma-Nystrom ell=k={cfg['k']}, LMP-PCG to rtol {cfg['rtol']}",
                    "form": "chosen (banded circulant U_B, FP64)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(chosen["active_cols"] / max(1, chosen["tlad_launches"])),
                      "kernel": "k_tlad<double, 9, TLAD_PCG> (fused PCG iteration: U_B, TL, AD, U_B, updates)",
                      "bytes_per_column": bpc, "avg_launch_ms": round(avg_ms, 4),
-                     "launches": chosen["tlad_launches"]},
+                     "launches": chosen["tlad_launches"], "active_column_iterations": chosen["active_cols"],
+                     "kernel_sha": kernel_sha()},
         "pcg_iterations": {"median": chosen["iters_median"], "min": chosen["iters_min"], "max": chosen["iters_max"],
                            "all_converged": chosen["converged"]},
         "hessvec_per_s": {k: round(v, 1) for k, v in chosen["hessvec_per_s"].items()},
@@ -190,6 +289,9 @@ def main():
         line["plain"] = {"value": round(plain["solves_per_s"], 3), "ms_per_step": round(plain["ms_per_step"], 3),
                          "hessvec_per_s": {k: round(v, 1) for k, v in plain["hessvec_per_s"].items()},
                          "iters_median": plain["iters_median"], "all_converged": plain["converged"]}
+    if not a.no_batch:
+        print(f"[bench] uneven batch of {a.batch_problems} problems", file=sys.stderr, flush=True)
+        line["uneven_batch"] = run_uneven_batch(a.batch_problems, max(1, a.steps), a.batch_plain)
     if not a.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(cfg, z, a.cpu_seconds)

@@ -218,6 +218,71 @@ int eda_profile_read(eda_ctx *ctx, int64_t *launches, double *total_ms);
 /* Free the context's host structures (the workspace stays the caller's). */
 int eda_destroy(eda_ctx *ctx);
 
+/* ---- batches of independent problems ----
+ * Many EDA problems of uneven n, window length and ensemble size solved
+ * together: for every problem the RHS-difference sketch (Gamma of the
+ * structure-of-the-EDA subsection, ell = min(k_cap, L, max_ell) columns), the
+ * single-pass Nystrom approximation (the q-pass Nystrom algorithm with q = 1),
+ * the spectral LMP with theta = (lambda_k(I+A) + 1)/2 and LMP-PCG of all members
+ * 0..L from dz = 0 (the system_with_CVT equation), i.e. per problem exactly
+ * what eda_sketch_evd(RHS_DIFF, ell, ell, 1, NYSTROM, MID) followed by
+ * eda_pcg_solve(0..L) computes, up to rounding order.
+ * Problems with equal n form a class.  A class runs one multi-problem sketch
+ * launch and one persistent solve launch whose workgroups take member columns
+ * from a work queue and iterate each to its final status without host
+ * round trips; the classes run as parallel branches of one captured graph that
+ * later calls with the same parameters replay.  The first call also tunes, per
+ * class, the launch geometry (waves per workgroup, time-block length) by timing
+ * the class's sketch launch.
+ * Every context must use the banded U_B (EDA_UB_BANDED), be set up and not be
+ * used concurrently by other calls while the batch exists; a context appears
+ * at most once.  The batch reuses each context's workspace for its sketch and
+ * PCG state and writes each problem's solutions to that problem's PCG state
+ * (read them with eda_batch_result). */
+typedef struct eda_batch eda_batch;
+
+/* Device workspace the batch needs for np problems (argument blocks, task
+ * lists and queue counters; 256-byte aligned). */
+int eda_batch_workspace_bytes(eda_ctx *const *ctxs, int32_t np, size_t *bytes);
+
+/* Create a batch over ctxs[0..np).  d_ws: >= eda_batch_workspace_bytes, owned
+ * by the caller, 256-byte aligned.  stream: the caller's stream; work already
+ * enqueued on it (the problems' set-up) is ordered before the batch's work, and
+ * the batch runs on a stream of its own.  Errors: EDA_ERR_INVALID_ARG (null or
+ * repeated context, misaligned workspace), EDA_ERR_UNSUPPORTED (dense U_B),
+ * EDA_ERR_WORKSPACE, EDA_ERR_HIP. */
+int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_bytes, void *stream,
+                     eda_batch **out);
+
+/* Sketch, Nystrom and LMP-PCG of every member of every problem (see above);
+ * returns after the work is done.  rtol, maxit: the PCG stopping rule of
+ * eda_pcg_solve.  use_lmp = 0 skips the sketch and runs plain CG.  The graph
+ * uses unshifted CholQR2 and Cholesky; a problem where one of them fails is
+ * solved by plain CG in the graph and then redone by eda_sketch_evd (shifted
+ * CholQR and the Nystrom shift of the Nystrom-variants appendix) and
+ * eda_pcg_solve; if that sketch fails too (EDA_ERR_NOT_SPD: Phi numerically
+ * rank-deficient, e.g. ell close to n), the plain CG solution is kept.
+ * h_fallbacks (optional, 2 entries) receives the number of problems redone and,
+ * of those, the number left without LMP.  Returns EDA_OK or a negative error. */
+int eda_batch_solve(eda_batch *batch, int32_t k_cap, double rtol, int32_t maxit, int32_t use_lmp,
+                    int32_t *h_fallbacks);
+
+/* Results of problem p of the last eda_batch_solve: d_DZ (optional, n x
+ * (L+1), ldz >= n) receives dz of members 0..L; h_iters, h_relres, h_status
+ * (L+1 entries each) as in eda_pcg_solve.  Returns EDA_OK or
+ * EDA_WARN_NOT_CONVERGED. */
+int eda_batch_result(eda_batch *batch, int32_t p, double *d_DZ, int64_t ldz, int32_t *h_iters, double *h_relres,
+                     int32_t *h_status);
+
+/* Tuning outcome of class cls (classes in increasing n), valid after the first
+ * eda_batch_solve: h_out[8] = {n, problems, waves per workgroup, points per
+ * lane, time-block length, persistent grid, member columns, tuned sketch launch
+ * time in microseconds}.  Returns the number of classes. */
+int eda_batch_tuning(eda_batch *batch, int32_t cls, int32_t *h_out);
+
+/* Free the batch's host structures and its graph and stream. */
+int eda_batch_destroy(eda_batch *batch);
+
 /* Static description of a status code. */
 const char *eda_strerror(int code);
 

@@ -2,6 +2,7 @@
 // products, randomized eigendecomposition, spectral LMP and batched PCG.
 // Host code only sequences kernels on the context's stream; every arithmetic
 // step of the path runs in this library's HIP kernels.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -739,6 +740,500 @@ const char *eda_strerror(int code) {
         case EDA_WARN_NOT_CONVERGED: return "some members did not converge";
         default: return "unknown status";
     }
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches of independent problems of uneven n, window length and ensemble
+// size: the Gamma sketches of every problem, their Nystrom cores and the
+// LMP-PCG solves of every member, replayed as one captured graph.  Problems
+// with the same n form a class; each class has one multi-problem sketch launch
+// and one persistent solve launch (k_solve, a work queue over the class's
+// member columns), and the classes run as parallel branches of the graph.
+// ---------------------------------------------------------------------------
+struct eda_batch {
+    std::vector<Ctx *> probs;
+    std::vector<eda_ctx *> handles;
+    hipStream_t user = nullptr;    // the caller's stream (ordering only)
+    hipStream_t stream = nullptr;  // the batch's own capture stream
+    hipEvent_t entry = nullptr;
+    char *ws = nullptr;
+    TladArgs *d_solve = nullptr, *d_hv = nullptr;
+    SolveTask *d_stasks = nullptr, *d_htasks = nullptr;
+    int *d_counters = nullptr;
+    struct Class {
+        int n = 0;
+        std::vector<int> members;  // problem indices
+        int s_off = 0, s_cnt = 0, h_off = 0, h_cnt = 0;
+        TladGeom g{};
+        size_t lds_solve = 0, lds_hv = 0;
+        int grid = 0;
+        double tune_us = 0.0;
+        hipStream_t side = nullptr;
+        hipEvent_t done = nullptr;
+    };
+    std::vector<Class> classes;
+    hipEvent_t fork = nullptr;
+    std::vector<int> ell;
+    bool tuned = false;
+    int k_cap = -1, maxit = -1, use_lmp = -1;
+    double rtol = -1.0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+struct BatchPlan {
+    size_t off_solve, off_hv, off_st, off_ht, off_cnt, total;
+};
+
+BatchPlan batch_plan(eda_ctx *const *ctxs, int np) {
+    Layout lay;
+    BatchPlan P{};
+    size_t st = 0, ht = 0;
+    for (int i = 0; i < np; i++) {
+        const Ctx &c = ctxs[i]->c;
+        st += (size_t)c.L + 1;
+        ht += (size_t)(c.max_ell < c.L ? c.max_ell : c.L);
+    }
+    P.off_solve = lay.take(sizeof(TladArgs) * np);
+    P.off_hv = lay.take(sizeof(TladArgs) * np);
+    P.off_st = lay.take(sizeof(SolveTask) * (st ? st : 1));
+    P.off_ht = lay.take(sizeof(SolveTask) * (ht ? ht : 1));
+    P.off_cnt = lay.take(sizeof(int) * np);
+    P.total = lay.total;
+    return P;
+}
+
+// The Nystrom core of eda_sketch_evd (q = 1, no shift) with no host
+// synchronisation: CholQR2 of Y, W = Phi^T Y, C = chol(W), T = R_Y C^-1, SVD,
+// S = Q U, signs, theta "mid" and the LMP coefficients.  The three Cholesky
+// outcomes land in sk_info[0..2]; the caller checks them after the run.
+int nystrom_nosync(Ctx &c, int l, int k) {
+    hipStream_t s = c.stream;
+    const int n = c.n;
+    const size_t ls = (size_t)c.max_ell * c.max_ell;
+    double *G = c.sk_small, *R1 = c.sk_small + 1 * ls, *R1i = c.sk_small + 2 * ls;
+    double *R2 = c.sk_small + 3 * ls, *R2i = c.sk_small + 4 * ls;
+    double *RY = c.sk_small + 7 * ls, *Wm = c.sk_small + 8 * ls, *Cm = c.sk_small + 9 * ls;
+    double *Ci = c.sk_small + 1 * ls, *Tm = c.sk_small + 2 * ls, *Um = c.sk_small + 3 * ls;
+    double *sig = c.sk_small + 4 * ls;
+    double *dscal = reinterpret_cast<double *>(c.sk_info + 16);
+    HIP_TRY(gemm_f64(s, true, l, l, n, c.sk_y, n, c.sk_y, n, G, l, nullptr, 0, nullptr, c.splitk, c.splitk_elems));
+    HIP_TRY(launch_chol_inv(s, l, G, 0.0, R1, R1i, c.sk_info + 0));
+    HIP_TRY(gemm_f64(s, false, n, l, l, c.sk_y, n, R1i, l, c.sk_q1, n, nullptr, 0, nullptr, nullptr, 0));
+    HIP_TRY(gemm_f64(s, true, l, l, n, c.sk_q1, n, c.sk_q1, n, G, l, nullptr, 0, nullptr, c.splitk, c.splitk_elems));
+    HIP_TRY(launch_chol_inv(s, l, G, 0.0, R2, R2i, c.sk_info + 1));
+    HIP_TRY(gemm_f64(s, false, n, l, l, c.sk_q1, n, R2i, l, c.sk_q, n, nullptr, 0, nullptr, nullptr, 0));
+    HIP_TRY(launch_small_gemm(s, l, false, false, R2, R1, RY));
+    HIP_TRY(gemm_f64(s, true, l, l, n, c.sk_phi, n, c.sk_y, n, Wm, l, nullptr, 0, nullptr, c.splitk, c.splitk_elems));
+    HIP_TRY(launch_sym(s, l, Wm));
+    HIP_TRY(launch_chol_inv(s, l, Wm, 0.0, Cm, Ci, c.sk_info + 2));
+    HIP_TRY(launch_small_gemm(s, l, false, false, RY, Ci, Tm));
+    HIP_TRY(launch_jacobi_svd_u(s, l, Tm, Um, sig));
+    HIP_TRY(gemm_f64(s, false, n, k, l, c.sk_q, n, Um, l, c.sk_s, n, nullptr, 0, nullptr, nullptr, 0));
+    HIP_TRY(launch_fix_signs(s, n, k, c.sk_s, n));
+    HIP_TRY(launch_lmp_coef(s, k, sig, 0.0, 1, EDA_THETA_MID, c.sk_eig, c.sk_coef, c.sk_coefu, dscal + 1));
+    return EDA_OK;
+}
+
+// Device argument blocks of problem i: solve (PCG of members 0..L) and sketch
+// (ell columns of Phi on the control trajectory).
+void batch_args(eda_batch &b, int i, TladArgs &sa, TladArgs &ha) {
+    Ctx &c = *b.probs[i];
+    sa = tlad_args(c, c.L + 1, c.pc_members, nullptr);
+    sa.obs = c.hv_obs;
+    sa.pcg.members = c.pc_members;
+    sa.pcg.b = c.b;
+    sa.pcg.x = c.pc_x;
+    sa.pcg.r = c.pc_r;
+    sa.pcg.z = b.use_lmp ? c.pc_z : c.pc_r;
+    sa.pcg.p = c.pc_p;
+    sa.pcg.scal = c.pc_scal;
+    sa.pcg.status = c.pc_status;
+    sa.pcg.iters = c.pc_iters;
+    sa.pcg.hist = nullptr;
+    sa.pcg.hist_cap = c.hist_cap;
+    sa.pcg.rtol = b.rtol;
+    sa.pcg.maxit = b.maxit;
+    sa.pcg.lmp_s = c.sk_s;
+    sa.pcg.lmp_c = c.sk_coef;
+    sa.pcg.lmp_k = b.use_lmp ? b.ell[i] : 0;
+    sa.pcg.lmp_info = b.use_lmp ? c.sk_info : nullptr;
+    ha = tlad_args(c, b.ell[i], c.zero_members, nullptr);
+    ha.V = c.sk_phi;
+    ha.ldv = c.n;
+    ha.obs = c.hv_obs;
+    ha.lam = c.sk_y;
+    ha.ldl = c.n;
+    ha.add_identity = 0;
+}
+
+int batch_class_lds(eda_batch &b, eda_batch::Class &k, const TladGeom &g, size_t &lds_solve, size_t &lds_hv) {
+    lds_solve = lds_hv = 0;
+    for (int i : k.members) {
+        TladArgs sa, ha;
+        batch_args(b, i, sa, ha);
+        size_t a1 = tlad_lds_bytes(sa, g, TLAD_PCG), a2 = tlad_lds_bytes(ha, g, TLAD_HV);
+        if (a1 > lds_solve) lds_solve = a1;
+        if (a2 > lds_hv) lds_hv = a2;
+    }
+    return (lds_solve + 4096 <= 160 * 1024 && lds_hv <= 160 * 1024) ? EDA_OK : EDA_ERR_UNSUPPORTED;
+}
+
+// Autotuner: per class, time the multi-problem sketch launch for each
+// candidate geometry (waves per workgroup around the default, time-block
+// length at its maximum and at half) and keep the fastest; the persistent
+// solve grid is what the CUs hold of that geometry.
+int batch_tune(eda_batch &b) {
+    hipStream_t s = b.stream;
+    for (size_t i = 0; i < b.probs.size(); i++)
+        HIP_TRY(launch_gamma(s, b.probs[i]->n, b.ell[i], b.probs[i]->b, b.probs[i]->sk_phi));
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int rc = EDA_OK;
+    for (auto &k : b.classes) {
+        const TladGeom g0 = tlad_geometry(k.n, 0);
+        double best = 1e300;
+        for (int w : {g0.waves / 2, g0.waves, g0.waves * 2}) {
+            if (w < 1 || !tlad_waves_ok(k.n, w)) continue;
+            const TladGeom gw = tlad_geometry(k.n, w);
+            for (int tb : {gw.tb, gw.tb / 2}) {
+                if (tb < 1) continue;
+                const TladGeom g = tlad_geometry(k.n, w, tb);
+                size_t ls, lh;
+                if (batch_class_lds(b, k, g, ls, lh) != EDA_OK) continue;
+                if (launch_hv_multi(s, b.d_hv, b.d_htasks + k.h_off, k.h_cnt, g, lh) != hipSuccess) continue;
+                if (hipEventRecord(e0, s) != hipSuccess) { rc = EDA_ERR_HIP; break; }
+                for (int r = 0; r < 3; r++)
+                    if (launch_hv_multi(s, b.d_hv, b.d_htasks + k.h_off, k.h_cnt, g, lh) != hipSuccess) rc = EDA_ERR_HIP;
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) rc = EDA_ERR_HIP;
+                if (rc != EDA_OK) break;
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best) {
+                    best = ms;
+                    k.g = g;
+                    k.lds_solve = ls;
+                    k.lds_hv = lh;
+                }
+            }
+            if (rc != EDA_OK) break;
+        }
+        if (rc != EDA_OK) break;
+        if (best >= 1e300) {
+            rc = EDA_ERR_UNSUPPORTED;
+            break;
+        }
+        k.tune_us = 1e3 * best / 3.0;
+        const int per_cu = solve_blocks_per_cu(k.g, k.lds_solve);
+        int grid = (per_cu > 0 ? per_cu : 1) * cus;
+        k.grid = grid < k.s_cnt ? grid : k.s_cnt;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == EDA_OK) b.tuned = true;
+    return rc;
+}
+
+// Enqueue the whole batched solve on b.stream (captured by the caller).
+int batch_enqueue(eda_batch &b) {
+    hipStream_t s = b.stream;
+    for (size_t i = 0; i < b.probs.size(); i++)
+        HIP_TRY(launch_gamma(s, b.probs[i]->n, b.ell[i], b.probs[i]->b, b.probs[i]->sk_phi));
+    // sketch products, one branch per class
+    HIP_TRY(hipEventRecord(b.fork, s));
+    for (auto &k : b.classes) {
+        HIP_TRY(hipStreamWaitEvent(k.side, b.fork, 0));
+        HIP_TRY(launch_hv_multi(k.side, b.d_hv, b.d_htasks + k.h_off, k.h_cnt, k.g, k.lds_hv));
+        HIP_TRY(hipEventRecord(k.done, k.side));
+        HIP_TRY(hipStreamWaitEvent(s, k.done, 0));
+    }
+    // Nystrom cores
+    for (size_t i = 0; i < b.probs.size(); i++) {
+        Ctx &c = *b.probs[i];
+        c.stream = s;
+        if (b.use_lmp) EDA_TRY(nystrom_nosync(c, b.ell[i], b.ell[i]));
+    }
+    // persistent solves, one branch per class
+    HIP_TRY(launch_fill_int(s, (int)b.classes.size(), 0, b.d_counters));
+    HIP_TRY(hipEventRecord(b.fork, s));
+    for (size_t ci = 0; ci < b.classes.size(); ci++) {
+        auto &k = b.classes[ci];
+        HIP_TRY(hipStreamWaitEvent(k.side, b.fork, 0));
+        HIP_TRY(launch_solve(k.side, b.d_solve, b.d_stasks + k.s_off, k.s_cnt, b.d_counters + ci, k.g, k.lds_solve,
+                             k.grid));
+        HIP_TRY(hipEventRecord(k.done, k.side));
+        HIP_TRY(hipStreamWaitEvent(s, k.done, 0));
+    }
+    return EDA_OK;
+}
+
+void batch_free_graph(eda_batch &b) {
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int eda_batch_workspace_bytes(eda_ctx *const *ctxs, int32_t np, size_t *bytes) {
+    if (!ctxs || np < 1 || !bytes) return EDA_ERR_INVALID_ARG;
+    for (int i = 0; i < np; i++)
+        if (!ctxs[i]) return EDA_ERR_INVALID_ARG;
+    *bytes = batch_plan(ctxs, np).total;
+    return EDA_OK;
+}
+
+int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_bytes, void *stream, eda_batch **out) {
+    if (!ctxs || np < 1 || !d_ws || !out) return EDA_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0) return EDA_ERR_INVALID_ARG;
+    for (int i = 0; i < np; i++) {
+        if (!ctxs[i]) return EDA_ERR_INVALID_ARG;
+        if (ctxs[i]->c.cfg.ub_mode != EDA_UB_BANDED) return EDA_ERR_UNSUPPORTED;
+        for (int j = 0; j < i; j++)
+            if (ctxs[j] == ctxs[i]) return EDA_ERR_INVALID_ARG;
+    }
+    const BatchPlan P = batch_plan(ctxs, np);
+    if (ws_bytes < P.total) return EDA_ERR_WORKSPACE;
+    eda_batch *b = new (std::nothrow) eda_batch();
+    if (!b) return EDA_ERR_INVALID_ARG;
+    auto fail = [&](int code) {
+        for (auto &k : b->classes) {
+            if (k.side) (void)hipStreamDestroy(k.side);
+            if (k.done) (void)hipEventDestroy(k.done);
+        }
+        if (b->fork) (void)hipEventDestroy(b->fork);
+        if (b->entry) (void)hipEventDestroy(b->entry);
+        if (b->stream) (void)hipStreamDestroy(b->stream);
+        delete b;
+        return code;
+    };
+    b->user = reinterpret_cast<hipStream_t>(stream);
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) return fail(EDA_ERR_HIP);
+    if (hipEventCreateWithFlags(&b->entry, hipEventDisableTiming) != hipSuccess) return fail(EDA_ERR_HIP);
+    // everything already enqueued on the caller's stream (the problems' set-up) comes first
+    if (hipEventRecord(b->entry, b->user) != hipSuccess || hipStreamWaitEvent(b->stream, b->entry, 0) != hipSuccess)
+        return fail(EDA_ERR_HIP);
+    b->ws = static_cast<char *>(d_ws);
+    b->d_solve = reinterpret_cast<TladArgs *>(b->ws + P.off_solve);
+    b->d_hv = reinterpret_cast<TladArgs *>(b->ws + P.off_hv);
+    b->d_stasks = reinterpret_cast<SolveTask *>(b->ws + P.off_st);
+    b->d_htasks = reinterpret_cast<SolveTask *>(b->ws + P.off_ht);
+    b->d_counters = reinterpret_cast<int *>(b->ws + P.off_cnt);
+    for (int i = 0; i < np; i++) {
+        b->probs.push_back(&ctxs[i]->c);
+        b->handles.push_back(ctxs[i]);
+    }
+    // classes by n, in increasing n
+    std::vector<int> ns;
+    for (int i = 0; i < np; i++) {
+        bool seen = false;
+        for (int v : ns) seen |= v == b->probs[i]->n;
+        if (!seen) ns.push_back(b->probs[i]->n);
+    }
+    std::sort(ns.begin(), ns.end());
+    for (int v : ns) {
+        eda_batch::Class k;
+        k.n = v;
+        for (int i = 0; i < np; i++)
+            if (b->probs[i]->n == v) k.members.push_back(i);
+        k.g = tlad_geometry(v, 0);
+        b->classes.push_back(k);
+    }
+    for (auto &k : b->classes) {
+        if (hipStreamCreateWithFlags(&k.side, hipStreamNonBlocking) != hipSuccess) return fail(EDA_ERR_HIP);
+        if (hipEventCreateWithFlags(&k.done, hipEventDisableTiming) != hipSuccess) return fail(EDA_ERR_HIP);
+    }
+    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) return fail(EDA_ERR_HIP);
+    // member lists 0..L of every problem
+    std::vector<int32_t> m;
+    for (int i = 0; i < np; i++) {
+        Ctx &c = *b->probs[i];
+        m.resize(c.L + 1);
+        for (int j = 0; j <= c.L; j++) m[j] = j;
+        if (hipMemcpyAsync(c.pc_members, m.data(), sizeof(int32_t) * m.size(), hipMemcpyHostToDevice, b->stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(b->stream) != hipSuccess)
+            return fail(EDA_ERR_HIP);
+    }
+    *out = b;
+    return EDA_OK;
+}
+
+int eda_batch_solve(eda_batch *b, int32_t k_cap, double rtol, int32_t maxit, int32_t use_lmp,
+                    int32_t *h_fallbacks) {
+    if (!b || k_cap < 1 || !(rtol >= 0) || maxit < 0) return EDA_ERR_INVALID_ARG;
+    const int np = (int)b->probs.size();
+    HIP_TRY(hipEventRecord(b->entry, b->user));
+    HIP_TRY(hipStreamWaitEvent(b->stream, b->entry, 0));
+    const bool same = b->exec && k_cap == b->k_cap && rtol == b->rtol && maxit == b->maxit &&
+                      (use_lmp != 0) == (b->use_lmp != 0);
+    if (!same) {
+        batch_free_graph(*b);
+        b->k_cap = k_cap;
+        b->rtol = rtol;
+        b->maxit = maxit;
+        b->use_lmp = use_lmp != 0;
+        b->ell.assign(np, 0);
+        for (int i = 0; i < np; i++) {
+            const Ctx &c = *b->probs[i];
+            int l = k_cap < c.L ? k_cap : c.L;
+            if (l > c.max_ell) l = c.max_ell;
+            b->ell[i] = l;
+        }
+        // argument blocks and task lists, grouped by class
+        std::vector<TladArgs> sa(np), ha(np);
+        for (int i = 0; i < np; i++) batch_args(*b, i, sa[i], ha[i]);
+        std::vector<SolveTask> st, ht;
+        for (auto &k : b->classes) {
+            k.s_off = (int)st.size();
+            k.h_off = (int)ht.size();
+            for (int i : k.members) {
+                for (int j = 0; j <= b->probs[i]->L; j++) st.push_back(SolveTask{i, j});
+                for (int j = 0; j < b->ell[i]; j++) ht.push_back(SolveTask{i, j});
+            }
+            k.s_cnt = (int)st.size() - k.s_off;
+            k.h_cnt = (int)ht.size() - k.h_off;
+        }
+        hipStream_t s = b->stream;
+        HIP_TRY(hipMemcpyAsync(b->d_solve, sa.data(), sizeof(TladArgs) * np, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(b->d_hv, ha.data(), sizeof(TladArgs) * np, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(b->d_stasks, st.data(), sizeof(SolveTask) * st.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(b->d_htasks, ht.data(), sizeof(SolveTask) * ht.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (!b->tuned) EDA_TRY(batch_tune(*b));
+        for (auto &k : b->classes) {
+            size_t ls, lh;
+            EDA_TRY(batch_class_lds(*b, k, k.g, ls, lh));
+            k.lds_solve = ls;
+            k.lds_hv = lh;
+            const int per_cu = solve_blocks_per_cu(k.g, ls);
+            int cus = 0;
+            HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
+            const int grid = (per_cu > 0 ? per_cu : 1) * cus;
+            k.grid = grid < k.s_cnt ? grid : k.s_cnt;
+        }
+        // capture
+        std::vector<hipStream_t> saved(np);
+        for (int i = 0; i < np; i++) saved[i] = b->probs[i]->stream;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        const int rc = batch_enqueue(*b);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(s, &g);
+        for (int i = 0; i < np; i++) b->probs[i]->stream = saved[i];
+        if (rc != EDA_OK || ec != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc != EDA_OK ? rc : EDA_ERR_HIP;
+        }
+        b->graph = g;
+        if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            batch_free_graph(*b);
+            return EDA_ERR_HIP;
+        }
+    }
+    HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    // Cholesky outcomes of the in-graph sketches.  A problem whose sketch failed
+    // was solved by plain CG in the graph; it is redone by the host-driven path
+    // (shifted CholQR and shifted Nystrom, then LMP-PCG), and keeps the plain CG
+    // result only if that sketch fails as well.
+    int fallbacks = 0, unprec = 0, warn = EDA_OK;
+    if (b->use_lmp) {
+        for (int i = 0; i < np; i++) {
+            Ctx &c = *b->probs[i];
+            int32_t info[3] = {0, 0, 0};
+            HIP_TRY(hipMemcpy(info, c.sk_info, sizeof(info), hipMemcpyDeviceToHost));
+            if (info[0] == 0 && info[1] == 0 && info[2] == 0) {
+                c.have_lmp = true;
+                c.k = b->ell[i];
+                continue;
+            }
+            fallbacks++;
+            hipStream_t keep = c.stream;
+            c.stream = b->stream;
+            eda_ctx *h = b->handles[i];
+            int r = eda_sketch_evd(h, EDA_SKETCH_RHS_DIFF, nullptr, 0, b->ell[i], b->ell[i], 1, EDA_METHOD_NYSTROM,
+                                   EDA_THETA_MID, 0, nullptr, nullptr);
+            if (r == EDA_ERR_NOT_SPD) {
+                unprec++;
+                r = EDA_OK;
+            } else if (r >= 0) {
+                // solutions land in the problem's PCG state (pc_x); hv_v is scratch
+                std::vector<int32_t> mem(c.L + 1), it(c.L + 1), stt(c.L + 1);
+                std::vector<double> rr(c.L + 1);
+                for (int j = 0; j <= c.L; j++) mem[j] = j;
+                r = eda_pcg_solve(h, mem.data(), c.L + 1, b->rtol, b->maxit, 1, c.hv_v, c.n, it.data(), rr.data(),
+                                  stt.data(), nullptr);
+            }
+            c.stream = keep;
+            if (r < 0) return r;
+        }
+    }
+    if (h_fallbacks) {
+        h_fallbacks[0] = fallbacks;
+        h_fallbacks[1] = unprec;
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return warn;
+}
+
+int eda_batch_result(eda_batch *b, int32_t p, double *d_DZ, int64_t ldz, int32_t *h_iters, double *h_relres,
+                     int32_t *h_status) {
+    if (!b || p < 0 || p >= (int)b->probs.size() || !h_iters || !h_relres || !h_status) return EDA_ERR_INVALID_ARG;
+    Ctx &c = *b->probs[p];
+    if (d_DZ && ldz < c.n) return EDA_ERR_INVALID_ARG;
+    const int m = c.L + 1;
+    hipStream_t s = b->stream;
+    if (d_DZ) HIP_TRY(launch_copy_cols(s, c.n, m, c.pc_x, c.n, d_DZ, ldz));
+    std::vector<double> scal(4 * (size_t)m);
+    HIP_TRY(hipMemcpyAsync(h_iters, c.pc_iters, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h_status, c.pc_status, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(scal.data(), c.pc_scal, sizeof(double) * scal.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int warn = EDA_OK;
+    for (int j = 0; j < m; j++) {
+        h_relres[j] = scal[4 * j + 2];
+        if (h_status[j] != EDA_MEMBER_CONVERGED) warn = EDA_WARN_NOT_CONVERGED;
+    }
+    return warn;
+}
+
+int eda_batch_tuning(eda_batch *b, int32_t cls, int32_t *h_out) {
+    if (!b || !h_out) return EDA_ERR_INVALID_ARG;
+    if (cls < 0 || cls >= (int)b->classes.size()) return EDA_ERR_INVALID_ARG;
+    const auto &k = b->classes[cls];
+    h_out[0] = k.n;
+    h_out[1] = (int32_t)k.members.size();
+    h_out[2] = k.g.waves;
+    h_out[3] = k.g.q;
+    h_out[4] = k.g.tb;
+    h_out[5] = k.grid;
+    h_out[6] = k.s_cnt;
+    h_out[7] = (int32_t)(k.tune_us + 0.5);
+    return (int32_t)b->classes.size();
+}
+
+int eda_batch_destroy(eda_batch *b) {
+    if (!b) return EDA_ERR_INVALID_ARG;
+    batch_free_graph(*b);
+    for (auto &k : b->classes) {
+        if (k.side) (void)hipStreamDestroy(k.side);
+        if (k.done) (void)hipEventDestroy(k.done);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->entry) (void)hipEventDestroy(b->entry);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return EDA_OK;
 }
 
 }  // extern "C"

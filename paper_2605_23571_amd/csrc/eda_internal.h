@@ -95,6 +95,15 @@ struct PcgCols {
     double rtol;
     int it;     // iteration number of this launch (1-based)
     int first;  // 1: p = z, rho = r^T z (first iteration)
+    int maxit;  // persistent solve: iteration limit
+    // persistent solve: LMP z = r + S diag(coef) S^T r (lmp_k = 0: z = r)
+    const double *lmp_s, *lmp_c;
+    int lmp_k;
+    const int32_t *lmp_info;  // persistent solve: 3 Cholesky outcomes of the sketch; any nonzero: no LMP
+};
+// One column of a batched persistent solve: problem index, PCG column.
+struct SolveTask {
+    int prob, col;
 };
 
 // Tangent-linear / adjoint kernel modes.
@@ -133,7 +142,23 @@ struct TladArgs {
 struct TladGeom {
     int waves, S, q, tb, hl_tl, hl_ad;
 };
-TladGeom tlad_geometry(int n, int waves_hint);
+TladGeom tlad_geometry(int n, int waves_hint, int tb_hint = 0);
+// Waves per workgroup the geometry accepts for n (1, 2, 4, 8 with Q <= 9).
+bool tlad_waves_ok(int n, int waves);
+// Bytes of dynamic LDS one column of this problem needs in the given mode.
+size_t tlad_lds_bytes(const TladArgs &a, const TladGeom &g, int mode);
+// Persistent batched PCG: every workgroup takes tasks from *counter (zeroed
+// before the launch) until ntasks are handed out; each task is a whole LMP-PCG
+// solve of one column (init, iterations, in-kernel LMP, final status).  probs
+// holds one TladArgs per problem (device memory); all share n and geometry g.
+hipError_t launch_solve(hipStream_t s, const TladArgs *d_probs, const SolveTask *d_tasks, int ntasks,
+                        int *d_counter, const TladGeom &g, size_t lds, int grid);
+// Hessian products (banded U_B, HV mode) for a list of (problem, column) tasks
+// of problems sharing n: one workgroup per task.
+hipError_t launch_hv_multi(hipStream_t s, const TladArgs *d_probs, const SolveTask *d_tasks, int ntasks,
+                           const TladGeom &g, size_t lds);
+// Workgroups of k_solve one CU holds for this geometry and LDS size.
+int solve_blocks_per_cu(const TladGeom &g, size_t lds);
 // Pads of the periodic row extension that every wave window of the TL/AD
 // kernel fits in without wrapping: window points j in [-pad_l, n + pad_r).
 void tlad_pads(int n, int *pad_l, int *pad_r);
@@ -171,6 +196,8 @@ hipError_t launch_innov(hipStream_t s, int n, int N, int L, int p, int nv, int o
                         double *force, double *costc);
 // Periodic extension of trajectory rows: out[m][s][j] = traj[m][s][(j - pad_l) mod n],
 // j < ext_len, for states s < N of each of nm members (input rows N + 1 per member).
+// p[0 .. count) = value (a kernel, so that it can sit in a captured graph).
+hipError_t launch_fill_int(hipStream_t s, int count, int value, int *p);
 hipError_t launch_pad_traj(hipStream_t s, int n, int N, int nm, const double *traj, int pad_l, int ext_len,
                            double *out);
 hipError_t launch_gamma(hipStream_t s, int n, int ell, const double *b, double *gam);

@@ -222,18 +222,15 @@ __device__ __forceinline__ double block_sum(double v, double *red, int waves) {
     return s;
 }
 
+// One column of one problem, all modes (the workgroup's whole job in k_tlad,
+// one step of the task loop in k_solve).  PCG mode runs iteration `it` (first:
+// p = z).  Every early exit is taken by the whole workgroup.
 template <typename T, int Q, int MODE>
-__global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
+__device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g, const int c, const int it,
+                                            const int first, unsigned char *smraw) {
     constexpr bool FUSED = (MODE == TLAD_HV || MODE == TLAD_PCG);
-    extern __shared__ __align__(16) unsigned char smraw[];
-    const int c = blockIdx.x;
     const int n = a.n, N = a.N, p = a.nt * a.nv;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x, nthr = blockDim.x;
-    if (MODE == TLAD_PCG) {
-        if (a.pcg.status[c] != COL_RUNNING) return;
-    } else if (a.active && a.active[c] != COL_RUNNING) {
-        return;
-    }
     // LDS: [ring: 2n T][qi: waves*64*Q int][xw: waves*64*Q double][u: n double][taps: W double][red: 16 double]
     T *ring = reinterpret_cast<T *>(smraw);  // two buffers, indexed rsel * n + position
     int *qi = reinterpret_cast<int *>(ring + 2 * n) + wave * 64 * Q;
@@ -270,7 +267,7 @@ __global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
             for (int i = tid; i < n; i += nthr) rz += r[i] * z[i];
             rz = block_sum(rz, red, g.waves);
             double beta = 0.0;
-            if (!a.pcg.first) {
+            if (!first) {
                 if (!(rz > 0.0) || !isfinite(rz)) {
                     if (tid == 0) a.pcg.status[c] = EDA_MEMBER_BREAKDOWN;
                     return;
@@ -279,7 +276,7 @@ __global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
             }
             rho = rz;
             for (int i = tid; i < n; i += nthr) {
-                double v = a.pcg.first ? z[i] : z[i] + beta * pp[i];
+                double v = first ? z[i] : z[i] + beta * pp[i];
                 pp[i] = v;
                 u[i] = v;
             }
@@ -488,7 +485,6 @@ __global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
         }
     }
     pq = block_sum(pq, red, g.waves);
-    const int it = a.pcg.it;
     if (!(pq > 0.0) || !isfinite(pq)) {
         if (tid == 0) {
             a.pcg.status[c] = EDA_MEMBER_BREAKDOWN;
@@ -524,6 +520,132 @@ __global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
         if (!isfinite(rn)) a.pcg.status[c] = EDA_MEMBER_BREAKDOWN;
         else if (rn <= a.pcg.rtol * bnorm) a.pcg.status[c] = EDA_MEMBER_CONVERGED;
     }
+}
+
+template <typename T, int Q, int MODE>
+__global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
+    extern __shared__ __align__(16) unsigned char smraw[];
+    const int c = blockIdx.x;
+    if (MODE == TLAD_PCG) {
+        if (a.pcg.status[c] != COL_RUNNING) return;
+    } else if (a.active && a.active[c] != COL_RUNNING) {
+        return;
+    }
+    tlad_column<T, Q, MODE>(a, g, c, a.pcg.it, a.pcg.first, smraw);
+}
+
+// z = P r = r + S diag(coef) S^T r for one column (in-kernel LMP of the
+// persistent solve): t = coef .* (S^T r) with the k dot products split over the
+// waves (fixed lane order and shuffle tree), then z row by row.  r and z are
+// the column's global vectors, tsh k doubles of LDS.
+__device__ __forceinline__ void lmp_column(const PcgCols &pc, int n, const double *r, double *z, double *tsh,
+                                           int waves) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x, nthr = blockDim.x;
+    const int k = pc.lmp_k;
+    for (int j = wave; j < k; j += waves) {
+        const double *sj = pc.lmp_s + (long long)j * n;
+        double sum = 0.0;
+        for (int i = lane; i < n; i += 64) sum += sj[i] * r[i];
+        for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
+        if (lane == 0) tsh[j] = pc.lmp_c[j] * sum;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += nthr) {
+        double v = r[i];
+        for (int j = 0; j < k; j++) v += pc.lmp_s[i + (long long)j * n] * tsh[j];
+        z[i] = v;
+    }
+    __syncthreads();
+}
+
+// Persistent LMP-PCG over a task list: the same iteration as eda_pcg_solve's
+// fused path (tlad_column in PCG mode), with the LMP applied in-kernel, so a
+// column runs from x = 0 to its final status without leaving the workgroup.
+// Every workgroup exits once the counter passes ntasks; a task ends after at
+// most maxit iterations.
+template <int Q>
+__global__ __launch_bounds__(512) void k_solve(const TladArgs *__restrict__ probs,
+                                               const SolveTask *__restrict__ tasks, int ntasks, int *counter,
+                                               TladGeom g) {
+    extern __shared__ __align__(16) unsigned char smraw[];
+    __shared__ int s_task;
+    __shared__ double s_red[16];
+    __shared__ double s_t[128];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    for (;;) {
+        if (tid == 0) s_task = atomicAdd(counter, 1);
+        __syncthreads();
+        const int t = s_task;
+        __syncthreads();
+        if (t >= ntasks) break;
+        const TladArgs &a = probs[tasks[t].prob];
+        const PcgCols &pc = a.pcg;
+        const int c = tasks[t].col, n = a.n;
+        const long long cn = (long long)c * n;
+        double *x = pc.x + cn, *r = pc.r + cn, *z = pc.z + cn;
+        const double *b = pc.b + (long long)pc.members[c] * n;
+        // x = 0, r = b, ||b||; history row
+        double bb = 0.0;
+        for (int i = tid; i < n; i += nthr) {
+            const double v = b[i];
+            x[i] = 0.0;
+            r[i] = v;
+            bb += v * v;
+        }
+        bb = block_sum(bb, s_red, nthr >> 6);
+        if (pc.hist)
+            for (int i = tid; i < pc.hist_cap; i += nthr)
+                pc.hist[(long long)c * pc.hist_cap + i] = i == 0 ? 0.0 : __builtin_nan("");
+        if (tid == 0) {
+            pc.scal[4 * c + 1] = sqrt(bb);
+            pc.scal[4 * c + 2] = bb > 0 ? 1.0 : 0.0;
+            pc.status[c] = bb > 0 ? COL_RUNNING : EDA_MEMBER_CONVERGED;
+            pc.iters[c] = 0;
+        }
+        __syncthreads();
+        if (!(bb > 0)) continue;
+        // a sketch whose Cholesky failed gives no LMP: plain CG for its members
+        const bool lmp = pc.lmp_k > 0 && !(pc.lmp_info && (pc.lmp_info[0] | pc.lmp_info[1] | pc.lmp_info[2]));
+        if (lmp) {
+            lmp_column(pc, n, r, z, s_t, nthr >> 6);
+        } else {
+            for (int i = tid; i < n; i += nthr) z[i] = r[i];
+            __syncthreads();
+        }
+        int st = COL_RUNNING;
+        for (int it = 1; it <= pc.maxit; it++) {
+            tlad_column<double, Q, TLAD_PCG>(a, g, c, it, it == 1, smraw);
+            __syncthreads();
+            st = pc.status[c];
+            __syncthreads();
+            if (st != COL_RUNNING) break;
+            if (lmp) {
+                lmp_column(pc, n, r, z, s_t, nthr >> 6);
+            } else {
+                for (int i = tid; i < n; i += nthr) z[i] = r[i];
+                __syncthreads();
+            }
+        }
+        if (st == COL_RUNNING) {
+            // iteration limit: the breakdown test on r^T z that the next
+            // iteration would make, then not-converged
+            double rz = 0.0;
+            for (int i = tid; i < n; i += nthr) rz += r[i] * z[i];
+            rz = block_sum(rz, s_red, nthr >> 6);
+            if (tid == 0) pc.status[c] = (pc.maxit > 0 && !(rz > 0.0 && isfinite(rz))) ? EDA_MEMBER_BREAKDOWN
+                                                                                       : EDA_MEMBER_NOT_CONVERGED;
+        }
+        __syncthreads();
+    }
+}
+
+// Hessian products of (problem, column) tasks, one workgroup per task.
+template <int Q>
+__global__ __launch_bounds__(512) void k_hv_multi(const TladArgs *__restrict__ probs,
+                                                  const SolveTask *__restrict__ tasks, TladGeom g) {
+    extern __shared__ __align__(16) unsigned char smraw[];
+    const SolveTask t = tasks[blockIdx.x];
+    tlad_column<double, Q, TLAD_HV>(probs[t.prob], g, t.col, 0, 0, smraw);
 }
 
 template <typename T, int Q>
@@ -564,13 +686,96 @@ hipError_t launch_t(hipStream_t s, const TladArgs &a, const TladGeom &g, int mod
     }
 }
 
+template <int Q>
+hipError_t launch_solve_q(hipStream_t s, const TladArgs *d_probs, const SolveTask *d_tasks, int ntasks,
+                          int *d_counter, const TladGeom &g, size_t lds, int grid) {
+    hipLaunchKernelGGL(k_solve<Q>, dim3(grid), dim3(64 * g.waves), lds, s, d_probs, d_tasks, ntasks, d_counter, g);
+    return hipGetLastError();
+}
+
+template <int Q>
+hipError_t launch_hv_multi_q(hipStream_t s, const TladArgs *d_probs, const SolveTask *d_tasks, int ntasks,
+                             const TladGeom &g, size_t lds) {
+    hipLaunchKernelGGL(k_hv_multi<Q>, dim3(ntasks), dim3(64 * g.waves), lds, s, d_probs, d_tasks, g);
+    return hipGetLastError();
+}
+
+// static LDS of k_solve (task id, reduction slots, LMP coefficients)
+constexpr size_t SOLVE_STATIC_LDS = sizeof(int) + 16 * sizeof(double) + 128 * sizeof(double) + 64;
+
 }  // namespace
+
+size_t tlad_lds_bytes(const TladArgs &a, const TladGeom &g, int mode) {
+    switch (g.q) {
+        case 2: return lds_bytes<double, 2>(a, g, mode);
+        case 3: return lds_bytes<double, 3>(a, g, mode);
+        case 4: return lds_bytes<double, 4>(a, g, mode);
+        case 5: return lds_bytes<double, 5>(a, g, mode);
+        case 6: return lds_bytes<double, 6>(a, g, mode);
+        case 7: return lds_bytes<double, 7>(a, g, mode);
+        case 8: return lds_bytes<double, 8>(a, g, mode);
+        case 9: return lds_bytes<double, 9>(a, g, mode);
+        default: return (size_t)-1;
+    }
+}
+
+hipError_t launch_solve(hipStream_t s, const TladArgs *d_probs, const SolveTask *d_tasks, int ntasks, int *d_counter,
+                        const TladGeom &g, size_t lds, int grid) {
+    if (ntasks <= 0) return hipSuccess;
+    if (grid <= 0 || lds + SOLVE_STATIC_LDS > 160 * 1024) return hipErrorInvalidValue;
+    switch (g.q) {
+        case 2: return launch_solve_q<2>(s, d_probs, d_tasks, ntasks, d_counter, g, lds, grid);
+        case 3: return launch_solve_q<3>(s, d_probs, d_tasks, ntasks, d_counter, g, lds, grid);
+        case 4: return launch_solve_q<4>(s, d_probs, d_tasks, ntasks, d_counter, g, lds, grid);
+        case 5: return launch_solve_q<5>(s, d_probs, d_tasks, ntasks, d_counter, g, lds, grid);
+        case 6: return launch_solve_q<6>(s, d_probs, d_tasks, ntasks, d_counter, g, lds, grid);
+        case 7: return launch_solve_q<7>(s, d_probs, d_tasks, ntasks, d_counter, g, lds, grid);
+        case 8: return launch_solve_q<8>(s, d_probs, d_tasks, ntasks, d_counter, g, lds, grid);
+        case 9: return launch_solve_q<9>(s, d_probs, d_tasks, ntasks, d_counter, g, lds, grid);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_hv_multi(hipStream_t s, const TladArgs *d_probs, const SolveTask *d_tasks, int ntasks,
+                           const TladGeom &g, size_t lds) {
+    if (ntasks <= 0) return hipSuccess;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    switch (g.q) {
+        case 2: return launch_hv_multi_q<2>(s, d_probs, d_tasks, ntasks, g, lds);
+        case 3: return launch_hv_multi_q<3>(s, d_probs, d_tasks, ntasks, g, lds);
+        case 4: return launch_hv_multi_q<4>(s, d_probs, d_tasks, ntasks, g, lds);
+        case 5: return launch_hv_multi_q<5>(s, d_probs, d_tasks, ntasks, g, lds);
+        case 6: return launch_hv_multi_q<6>(s, d_probs, d_tasks, ntasks, g, lds);
+        case 7: return launch_hv_multi_q<7>(s, d_probs, d_tasks, ntasks, g, lds);
+        case 8: return launch_hv_multi_q<8>(s, d_probs, d_tasks, ntasks, g, lds);
+        case 9: return launch_hv_multi_q<9>(s, d_probs, d_tasks, ntasks, g, lds);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int solve_blocks_per_cu(const TladGeom &g, size_t lds) {
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    const int threads = 64 * g.waves;
+    switch (g.q) {
+        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<2>, threads, lds); break;
+        case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<3>, threads, lds); break;
+        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<4>, threads, lds); break;
+        case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<5>, threads, lds); break;
+        case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<6>, threads, lds); break;
+        case 7: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<7>, threads, lds); break;
+        case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<8>, threads, lds); break;
+        case 9: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<9>, threads, lds); break;
+        default: break;
+    }
+    return e == hipSuccess ? nb : 0;
+}
 
 // Geometry: waves per workgroup, owned segment per wave, points per lane and
 // the time-block length, with halos hl_tl = 8 TB (TL cone: 8 left, 4 right per
 // step) and hl_ad = 4 TB + 8 (AD cone: 4 left, 8 right per step, plus the
 // recomputed stage states' fixed reach), requiring S + 12 TB + 16 <= 64 Q.
-TladGeom tlad_geometry(int n, int waves_hint) {
+TladGeom tlad_geometry(int n, int waves_hint, int tb_hint) {
     TladGeom g{};
     int W = waves_hint > 0 ? waves_hint : (n >= 2048 ? 8 : n >= 512 ? 4 : n >= 128 ? 2 : 1);
     g.waves = W;
@@ -579,19 +784,37 @@ TladGeom tlad_geometry(int n, int waves_hint) {
     while (64 * Q < g.S + 12 * 2 + 16) Q++;
     g.q = Q;
     g.tb = (64 * Q - g.S - 16) / 12;
+    if (tb_hint > 0 && tb_hint < g.tb) g.tb = tb_hint;
     g.hl_tl = 8 * g.tb;
     g.hl_ad = 4 * g.tb + 8;
     return g;
 }
 
+bool tlad_waves_ok(int n, int waves) {
+    if (waves != 1 && waves != 2 && waves != 4 && waves != 8) return false;
+    const TladGeom g = tlad_geometry(n, waves);
+    return g.q <= 9 && g.tb >= 1;
+}
+
+// Pads covering the windows of every geometry the launchers accept: any
+// accepted wave count and any time-block length up to its maximum.
 void tlad_pads(int n, int *pad_l, int *pad_r) {
-    const TladGeom g = tlad_geometry(n, 0);
-    const int hmax = g.hl_tl > g.hl_ad ? g.hl_tl : g.hl_ad;
-    const int hmin = g.hl_tl < g.hl_ad ? g.hl_tl : g.hl_ad;
-    // window of wave w: [w S - hl, w S - hl + 64 Q)
-    const int right = (g.waves - 1) * g.S - hmin + 64 * g.q - n;
-    *pad_l = hmax;
-    *pad_r = right > 0 ? right : 0;
+    int pl = 0, pr = 0;
+    for (int W = 1; W <= 8; W *= 2) {
+        if (!tlad_waves_ok(n, W)) continue;
+        const TladGeom g0 = tlad_geometry(n, W);
+        for (int tb = 1; tb <= g0.tb; tb++) {
+            const TladGeom g = tlad_geometry(n, W, tb);
+            const int hmax = g.hl_tl > g.hl_ad ? g.hl_tl : g.hl_ad;
+            const int hmin = g.hl_tl < g.hl_ad ? g.hl_tl : g.hl_ad;
+            // window of wave w: [w S - hl, w S - hl + 64 Q)
+            const int right = (g.waves - 1) * g.S - hmin + 64 * g.q - n;
+            if (hmax > pl) pl = hmax;
+            if (right > pr) pr = right;
+        }
+    }
+    *pad_l = pl;
+    *pad_r = pr;
 }
 
 hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32) {

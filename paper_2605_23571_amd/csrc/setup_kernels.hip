@@ -149,7 +149,18 @@ __global__ void k_pad_traj(int n, int N, int pad_l, int ext_len, const double *_
     }
 }
 
+__global__ void k_fill_int(int count, int value, int *__restrict__ p) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = value;
+}
+
 }  // namespace
+
+hipError_t launch_fill_int(hipStream_t s, int count, int value, int *p) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_int, dim3((count + 255) / 256), dim3(256), 0, s, count, value, p);
+    return hipGetLastError();
+}
 
 hipError_t launch_pad_traj(hipStream_t s, int n, int N, int nm, const double *traj, int pad_l, int ext_len,
                            double *out) {

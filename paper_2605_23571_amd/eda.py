@@ -80,6 +80,12 @@ def lib():
             "eda_profile_read": [vp, ctypes.POINTER(i64), ctypes.POINTER(dbl)],
             "eda_destroy": [vp],
             "eda_strerror": [ctypes.c_int],
+            "eda_batch_workspace_bytes": [vp, i32, ctypes.POINTER(sz)],
+            "eda_batch_create": [vp, i32, vp, sz, vp, ctypes.POINTER(vp)],
+            "eda_batch_solve": [vp, i32, dbl, i32, i32, vp],
+            "eda_batch_result": [vp, i32, vp, i64, vp, vp, vp],
+            "eda_batch_tuning": [vp, i32, vp],
+            "eda_batch_destroy": [vp],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -220,6 +226,93 @@ def eda_profile_read(ctx):
 
 def eda_destroy(ctx):
     _check("eda_destroy", lib().eda_destroy(ctx))
+
+
+def eda_batch_workspace_bytes(ctxs) -> int:
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.value for c in ctxs])
+    out = ctypes.c_size_t()
+    _check("eda_batch_workspace_bytes", lib().eda_batch_workspace_bytes(arr, len(ctxs), ctypes.byref(out)))
+    return out.value
+
+
+def eda_batch_create(ctxs, ws):
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.value for c in ctxs])
+    b = ctypes.c_void_p()
+    _check("eda_batch_create", lib().eda_batch_create(arr, len(ctxs), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                                      _stream(), ctypes.byref(b)))
+    return b
+
+
+def eda_batch_solve(batch, k_cap: int, rtol: float, maxit: int, use_lmp: bool = True) -> tuple[int, int]:
+    """Returns (problems redone on the host path, of those left without LMP)."""
+    fb = (ctypes.c_int32 * 2)()
+    _check("eda_batch_solve", lib().eda_batch_solve(batch, int(k_cap), float(rtol), int(maxit), int(bool(use_lmp)),
+                                                    fb))
+    return int(fb[0]), int(fb[1])
+
+
+def eda_batch_result(batch, p: int, n: int, m: int, DZ=None):
+    iters = np.zeros(m, dtype=np.int32)
+    relres = np.zeros(m)
+    status = np.zeros(m, dtype=np.int32)
+    if DZ is not None:
+        pdz, ldz = _dev_f64(DZ, n)
+    else:
+        pdz, ldz = ctypes.c_void_p(), n
+    code = lib().eda_batch_result(batch, int(p), pdz, ldz, iters.ctypes.data_as(ctypes.c_void_p),
+                                  relres.ctypes.data_as(ctypes.c_void_p), status.ctypes.data_as(ctypes.c_void_p))
+    _check("eda_batch_result", code, ok=(EDA_OK, EDA_WARN_NOT_CONVERGED))
+    return dict(iters=iters, relres=relres, status=status, dz=DZ)
+
+
+def eda_batch_tuning(batch) -> list[dict]:
+    out = (ctypes.c_int32 * 8)()
+    ncls = lib().eda_batch_tuning(batch, 0, out)
+    _check("eda_batch_tuning", min(ncls, 0))
+    res = []
+    for c in range(ncls):
+        lib().eda_batch_tuning(batch, c, out)
+        res.append(dict(zip(["n", "problems", "waves", "q", "tb", "grid", "columns", "tune_us"], list(out))))
+    return res
+
+
+def eda_batch_destroy(batch):
+    _check("eda_batch_destroy", lib().eda_batch_destroy(batch))
+
+
+class Batch:
+    """Many Problems solved together (sketch, Nystrom, LMP-PCG of every member)."""
+
+    def __init__(self, problems: list):
+        torch = _torch()
+        self.problems = list(problems)
+        ctxs = [p.ctx for p in self.problems]
+        self.ws = torch.empty(eda_batch_workspace_bytes(ctxs), dtype=torch.uint8, device="cuda")
+        self.b = eda_batch_create(ctxs, self.ws)
+
+    def solve(self, k_cap: int, rtol: float, maxit: int, use_lmp: bool = True) -> tuple[int, int]:
+        return eda_batch_solve(self.b, k_cap, rtol, maxit, use_lmp)
+
+    def result(self, p: int, with_dz: bool = True):
+        torch = _torch()
+        pr = self.problems[p]
+        m = pr.cfg["members"] + 1
+        DZ = torch.empty((m, pr.n), dtype=torch.float64, device="cuda") if with_dz else None
+        return eda_batch_result(self.b, p, pr.n, m, DZ)
+
+    def tuning(self) -> list[dict]:
+        return eda_batch_tuning(self.b)
+
+    def close(self):
+        if self.b:
+            eda_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Problem:

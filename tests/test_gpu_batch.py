@@ -1,0 +1,165 @@
+"""GPU: batches of uneven problems (eda_batch_*) against the per-problem path
+and the CPU oracle.  The batch computes, per problem, what eda_sketch_evd
+(RHS differences, Nystrom, theta mid) + eda_pcg_solve compute, so results are
+compared with (a) the oracle's exact solution of (I + A_j) dz = b_j and (b) the
+single-problem GPU path (same operator, same preconditioner definition; the
+in-kernel LMP sums in another order, so iteration counts may differ by rounding)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2605_23571_amd import eda  # noqa: E402
+
+
+def small_uneven():
+    # ragged ring sizes over four classes, three window lengths, uneven ensembles
+    base = dict(spinup=100)
+    shapes = [(40, 10, 6, 2.0), (203, 20, 9, 3.0), (40, 20, 5, 2.0), (128, 10, 12, 4.0), (203, 12, 7, 3.0),
+              (515, 10, 8, 8.0)]
+    out = []
+    for pid, (n, N, L, lb) in enumerate(shapes):
+        k = min(6, L)
+        out.append(W.config("C2", n=n, nsteps=N, members=L, ell=k, k=k, len_b=lb, problem_id=100 + pid,
+                            obs_dt=5 if N % 5 == 0 else 4, obs_dx=1 + pid % 3, obs_x0=pid % 2, **base))
+    return out
+
+
+_state = {}
+
+
+def batch_state():
+    if "b" not in _state:
+        cfgs = small_uneven()
+        zs = [W.problem_normals(c) for c in cfgs]
+        print(f"[batch] {len(cfgs)} problems n={[c['n'] for c in cfgs]}", flush=True)
+        probs = [eda.Problem(c, z) for c, z in zip(cfgs, zs)]
+        bt = eda.Batch(probs)
+        _state.update(cfgs=cfgs, zs=zs, probs=probs, b=bt)
+    return _state
+
+
+def test_batch_solutions_match_exact():
+    st = batch_state()
+    bt, cfgs, zs = st["b"], st["cfgs"], st["zs"]
+    fb = bt.solve(k_cap=6, rtol=1e-10, maxit=3000)
+    assert fb == (0, 0)
+    for p, (cfg, z) in enumerate(zip(cfgs, zs)):
+        res = bt.result(p)
+        assert (res["status"] == eda.EDA_MEMBER_CONVERGED).all(), (p, res["status"])
+        assert (res["relres"] <= 1e-10).all()
+        o = O.Problem(cfg, z)
+        dz = res["dz"].cpu().numpy()
+        for m in range(cfg["members"] + 1):
+            ex = O.exact_solution(o, m)
+            err = np.linalg.norm(dz[m] - ex) / np.linalg.norm(ex)
+            # rtol 1e-10 on the residual: solution error <= cond(I + A) 1e-10
+            assert err < 1e-6, (p, m, err)
+
+
+def test_batch_matches_single_problem_path():
+    st = batch_state()
+    bt, cfgs, zs = st["b"], st["cfgs"], st["zs"]
+    bt.solve(k_cap=6, rtol=1e-6, maxit=3000)
+    for p, (cfg, z) in enumerate(zip(cfgs, zs)):
+        res = bt.result(p)
+        g = eda.Problem(cfg, z)
+        k = min(6, cfg["members"])
+        g.sketch_evd("rhs_diff", ell=k, k=k)
+        ref = g.pcg(np.arange(cfg["members"] + 1), rtol=1e-6, maxit=3000, use_lmp=True)
+        g.close()
+        assert (ref["status"] == res["status"]).all()
+        # same method, summation order differs in the LMP: iteration counts
+        # agree to within rounding-driven drift
+        tol = np.maximum(2, (0.05 * ref["iters"]).astype(int))
+        assert (np.abs(res["iters"] - ref["iters"]) <= tol).all(), (p, res["iters"], ref["iters"])
+        a, r = res["dz"].cpu().numpy(), ref["dz"].cpu().numpy()
+        # both satisfy ||r|| <= 1e-6 ||b||; their difference is bounded by the
+        # two solution errors
+        assert np.linalg.norm(a - r) / np.linalg.norm(r) < 1e-3
+
+
+def test_batch_graph_replay_is_deterministic():
+    st = batch_state()
+    bt, cfgs = st["b"], st["cfgs"]
+    bt.solve(k_cap=6, rtol=1e-8, maxit=3000)
+    first = [bt.result(p)["dz"].cpu().numpy() for p in range(len(cfgs))]
+    it1 = [bt.result(p, with_dz=False)["iters"] for p in range(len(cfgs))]
+    for _ in range(2):
+        bt.solve(k_cap=6, rtol=1e-8, maxit=3000)  # same parameters: graph replay
+        for p in range(len(cfgs)):
+            r = bt.result(p)
+            assert np.array_equal(r["dz"].cpu().numpy(), first[p])
+            assert np.array_equal(r["iters"], it1[p])
+
+
+def test_batch_tuning_and_plain_cg():
+    st = batch_state()
+    bt, cfgs = st["b"], st["cfgs"]
+    bt.solve(k_cap=6, rtol=1e-8, maxit=5000, use_lmp=False)
+    for p in range(len(cfgs)):
+        assert (bt.result(p, with_dz=False)["status"] == eda.EDA_MEMBER_CONVERGED).all()
+    tun = bt.tuning()
+    assert [t["n"] for t in tun] == sorted({c["n"] for c in cfgs})
+    for t in tun:
+        assert t["waves"] in (1, 2, 4, 8) and 2 <= t["q"] <= 9 and t["tb"] >= 1
+        assert 1 <= t["grid"] <= t["columns"]
+        assert t["columns"] == sum(c["members"] + 1 for c in cfgs if c["n"] == t["n"])
+
+
+def test_batch_maxit_not_converged():
+    st = batch_state()
+    bt, cfgs = st["b"], st["cfgs"]
+    bt.solve(k_cap=6, rtol=1e-14, maxit=3)
+    for p in range(len(cfgs)):
+        r = bt.result(p, with_dz=False)
+        assert (r["iters"] <= 3).all()
+        assert set(r["status"].tolist()) <= {eda.EDA_MEMBER_NOT_CONVERGED, eda.EDA_MEMBER_CONVERGED,
+                                             eda.EDA_MEMBER_BREAKDOWN}
+        assert (r["status"] == eda.EDA_MEMBER_NOT_CONVERGED).any()
+
+
+def test_batch_rejects_dense_and_repeats():
+    cfg = W.config("C1", spinup=50)
+    z = W.problem_normals(cfg)
+    gd = eda.Problem(cfg, z, ub_mode="dense")
+    with pytest.raises(eda.EdaError) as e:
+        eda.Batch([gd])
+    assert e.value.code == eda.EDA_ERR_UNSUPPORTED
+    gb = eda.Problem(cfg, z)
+    with pytest.raises(eda.EdaError) as e:
+        eda.Batch([gb, gb])
+    assert e.value.code == eda.EDA_ERR_INVALID_ARG
+    gd.close()
+    gb.close()
+
+
+def test_batch_near_full_rank_sketch_still_solves():
+    # ell = 32 on a 40-point ring with length scale 2: Gamma and A Gamma are
+    # numerically rank-deficient, the unshifted Cholesky in the graph can fail.
+    # Whatever path a problem takes (graph LMP, host shifted sketch, or plain
+    # CG when the shifted Cholesky fails too), its members must reach the exact
+    # solution.
+    cfgs = [W.config("C2", n=40, nsteps=N, members=40, ell=32, k=32, len_b=2.0, problem_id=200 + i, spinup=100)
+            for i, N in enumerate((10, 20))]
+    zs = [W.problem_normals(c) for c in cfgs]
+    probs = [eda.Problem(c, z) for c, z in zip(cfgs, zs)]
+    bt = eda.Batch(probs)
+    redone, unprec = bt.solve(k_cap=32, rtol=1e-10, maxit=3000)
+    print(f"[batch] redone {redone}, without LMP {unprec}", flush=True)
+    assert 0 <= unprec <= redone <= len(cfgs)
+    for p, (cfg, z) in enumerate(zip(cfgs, zs)):
+        res = bt.result(p)
+        assert (res["status"] == eda.EDA_MEMBER_CONVERGED).all(), (p, res["status"])
+        o = O.Problem(cfg, z)
+        dz = res["dz"].cpu().numpy()
+        for m in (0, 7, cfg["members"]):
+            ex = O.exact_solution(o, m)
+            assert np.linalg.norm(dz[m] - ex) / np.linalg.norm(ex) < 1e-6
+    bt.close()
+    for g in probs:
+        g.close()
