@@ -8,8 +8,9 @@ Nystrom core), the spectral LMP, and batched LMP-PCG of all L + 1 members to
 (spin-up, trajectories, right-hand sides) is done before the timed region and
 reported separately.
 
-Forms: "chosen" = banded circulant U_B products; "plain" = dense U_B as FP64
-MFMA GEMMs.  Both are FP64 throughout.  Hessian-vector products per second
+Forms: "chosen" = banded circulant U_B inside the fused TL/AD kernels, with the
+sketch's Hessian products in FP32 (trajectory, CholQR2, eigensolve, LMP and
+PCG in FP64); "plain" = dense U_B as FP64 MFMA GEMMs, FP64 throughout.  Hessian-vector products per second
 (member mode: every column on its own trajectory; sketch mode: all on the
 control trajectory) are reported too.
 
@@ -89,7 +90,7 @@ def pcg_kernel_bytes_per_col(cfg):
     return 8 * (2 * N * n + 2 * nt * nv + 9 * n)
 
 
-def run_form(cfg, z, ub_mode, steps, warmup, hv_reps):
+def run_form(cfg, z, ub_mode, steps, warmup, hv_reps, mixed=False, keep=False):
     import torch
     from paper_2605_23571_amd import eda
 
@@ -101,7 +102,7 @@ def run_form(cfg, z, ub_mode, steps, warmup, hv_reps):
     members = np.arange(L + 1)
 
     def step():
-        g.sketch_evd("rhs_diff", ell=ell, k=cfg["k"])
+        g.sketch_evd("rhs_diff", ell=ell, k=cfg["k"], mixed=mixed)
         return g.pcg(members, rtol=cfg["rtol"], maxit=cfg["maxit"], use_lmp=True)
 
     for _ in range(warmup):
@@ -140,8 +141,41 @@ def run_form(cfg, z, ub_mode, steps, warmup, hv_reps):
                iters_median=float(np.median(it)), iters_max=int(it.max()), iters_min=int(it.min()),
                tlad_launches=launches, tlad_ms=tlad_ms, hessvec_per_s=hv,
                active_cols=iters_total)
-    g.close()
+    res["last_dz"] = outs[-1]["dz"]
+    res["problem"] = g if keep else None
+    if not keep:
+        g.close()
     return res
+
+
+def precision_report(cfg, g, dz_chosen, oracle_lmp):
+    """Errors of the reduced-precision sketch (FP32 TL/AD products) at full size:
+    against the same sketch with FP64 products on the GPU, and against the CPU
+    oracle's FP64 sketch when it is available (eigenvalues D_k, the LMP operator
+    on 16 seeded probes, solutions of the oracle's members at the same rtol)."""
+    import torch
+    rep = {}
+    V = np.random.default_rng(11).standard_normal((cfg["n"], 16))
+    Vt = torch.from_numpy(np.ascontiguousarray(V.T)).cuda()
+    eig_mx, th_mx = g.sketch_evd("rhs_diff", ell=cfg["ell"], k=cfg["k"], mixed=True)
+    P_mx = g.lmp_apply(Vt).cpu().numpy().T
+    eig_64, th_64 = g.sketch_evd("rhs_diff", ell=cfg["ell"], k=cfg["k"])
+    P_64 = g.lmp_apply(Vt).cpu().numpy().T
+    rep["vs_gpu_fp64"] = {"eig_max_rel": float(np.max(np.abs(eig_mx - eig_64) / eig_64)),
+                          "theta_rel": float(abs(th_mx - th_64) / th_64),
+                          "lmp_rel": float(np.linalg.norm(P_mx - P_64) / np.linalg.norm(V))}
+    if oracle_lmp is not None:
+        from oracle import oracle as O
+        S, D, th, dz_o = oracle_lmp
+        P_o = O.lmp_apply(S, D, th, V)
+        d = [float(np.linalg.norm(dz_chosen[m] - dz_o[m]) / np.linalg.norm(dz_o[m])) for m in range(len(dz_o))]
+        rep["vs_oracle"] = {"eig_max_rel": float(np.max(np.abs(eig_mx - D) / D)),
+                            "theta_rel": float(abs(th_mx - th) / th),
+                            "lmp_rel": float(np.linalg.norm(P_mx - P_o) / np.linalg.norm(V)),
+                            "dz_rel_diff_members": d,
+                            "note": "dz: GPU (reduced-precision sketch) and oracle solutions, both stopped at "
+                                    f"||r|| <= {cfg['rtol']} ||b||"}
+    return rep
 
 
 def run_uneven_batch(count, reps, plain_count):
@@ -162,12 +196,12 @@ def run_uneven_batch(count, reps, plain_count):
     setup_s = time.perf_counter() - t0
     bt = eda.Batch(probs)
     t0 = time.perf_counter()
-    bt.solve(k_cap=32, rtol=1e-6, maxit=2000)
+    bt.solve(k_cap=32, rtol=1e-6, maxit=5000)
     first_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     fb = [0, 0]
     for _ in range(reps):
-        f = bt.solve(k_cap=32, rtol=1e-6, maxit=2000)
+        f = bt.solve(k_cap=32, rtol=1e-6, maxit=5000)
         fb = [fb[0] + f[0], fb[1] + f[1]]
     dt = (time.perf_counter() - t0) / reps
     cols = sum(c["members"] + 1 for c in cfgs)
@@ -177,6 +211,7 @@ def run_uneven_batch(count, reps, plain_count):
         conv &= bool((r["status"] == eda.EDA_MEMBER_CONVERGED).all())
         iters.append(r["iters"])
     tun = bt.tuning()
+    phases = {k: round(v, 2) for k, v in bt.timing().items()}
     bt.close()
     # plain: host-driven per-problem path on the first plain_count problems
     pc = min(plain_count, count)
@@ -191,7 +226,7 @@ def run_uneven_batch(count, reps, plain_count):
             if e.code != eda.EDA_ERR_NOT_SPD:
                 raise
             lmp = False
-        g.pcg(np.arange(c["members"] + 1), rtol=1e-6, maxit=2000, use_lmp=lmp)
+        g.pcg(np.arange(c["members"] + 1), rtol=1e-6, maxit=5000, use_lmp=lmp)
     torch.cuda.synchronize()
     plain_dt = time.perf_counter() - t0
     for g in probs:
@@ -200,7 +235,7 @@ def run_uneven_batch(count, reps, plain_count):
     return {"problems": count, "member_solves": cols, "value": round(cols / dt, 1), "unit": "solves/s",
             "s_per_batch": round(dt, 4), "first_call_s": round(first_s, 3), "setup_s": round(setup_s, 2),
             "all_converged": conv, "host_redone_per_call": fb[0] / reps, "without_lmp_per_call": fb[1] / reps, "iters_median": float(np.median(it)), "iters_max": int(it.max()),
-            "classes": tun,
+            "last_call_phases_ms": phases, "classes": tun,
             "plain": {"problems": pc, "member_solves": pcols, "value": round(pcols / plain_dt, 1),
                       "unit": "solves/s"}}
 
@@ -217,17 +252,19 @@ def cpu_baseline(cfg, z, target_s):
     th = O.theta(D)
     t_sketch = time.perf_counter() - t0
     pre = lambda v: O.lmp_apply(S, D, th, v[:, None])[:, 0]
-    m, t_pcg = 0, 0.0
+    m, t_pcg, dz = 0, 0.0, []
     while m <= L and (m == 0 or t_pcg + t_sketch < target_s):
         t1 = time.perf_counter()
-        O.pcg(lambda v: P.hess(v[:, None], [m])[:, 0], P.b[:, m], pre, cfg["rtol"], cfg["maxit"])
+        x = O.pcg(lambda v: P.hess(v[:, None], [m])[:, 0], P.b[:, m], pre, cfg["rtol"], cfg["maxit"])[0]
         t_pcg += time.perf_counter() - t1
+        dz.append(x)
         m += 1
     cost = t_sketch * m / (L + 1) + t_pcg
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return dict(value=m / cost, unit="solves/s", cores=cores, kind="oracle",
                 sample=f"Gamma-Nystrom sketch (ell={cfg['ell']}) once, amortised over {L + 1} members, + "
-                       f"LMP-PCG to rtol {cfg['rtol']} for members 0..{m - 1}; {t_sketch + t_pcg:.1f} s of CPU work")
+                       f"LMP-PCG to rtol {cfg['rtol']} for members 0..{m - 1}; {t_sketch + t_pcg:.1f} s of CPU work"), \
+        (S, D, th, dz)
 
 
 def main():
@@ -247,7 +284,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     print(f"[bench] {a.workload} chosen form (banded U_B)", file=sys.stderr, flush=True)
-    chosen = run_form(cfg, z, "banded", a.steps, a.warmup, a.hv_reps)
+    chosen = run_form(cfg, z, "banded", a.steps, a.warmup, a.hv_reps, mixed=True, keep=True)
     plain = None
     if not a.no_plain:
         print(f"[bench] {a.workload} plain form (dense U_B GEMMs)", file=sys.stderr, flush=True)
@@ -272,7 +309,8 @@ def main():
         "config": {"workload": f"{a.workload}: Lorenz-96 n={cfg['n']}, window {cfg['nsteps']} steps, "
                                f"p={nt * nv} obs ({nt} times x {nv} vars), {cfg['members']} members + control, "
                                f"Gamma-Nystrom ell=k={cfg['k']}, LMP-PCG to rtol {cfg['rtol']}",
-                   "form": "chosen (banded circulant U_B, FP64)"},
+                   "form": "chosen (banded circulant U_B in the fused kernels; sketch products FP32 TL/AD, "
+                           "everything else FP64)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(chosen["active_cols"] / max(1, chosen["tlad_launches"])),
@@ -292,9 +330,13 @@ def main():
     if not a.no_batch:
         print(f"[bench] uneven batch of {a.batch_problems} problems", file=sys.stderr, flush=True)
         line["uneven_batch"] = run_uneven_batch(a.batch_problems, max(1, a.steps), a.batch_plain)
+    oracle_lmp = None
     if not a.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(cfg, z, a.cpu_seconds)
+        line["cpu_baseline"], oracle_lmp = cpu_baseline(cfg, z, a.cpu_seconds)
+    g = chosen["problem"]
+    line["reduced_precision_sketch"] = precision_report(cfg, g, chosen["last_dz"].cpu().numpy(), oracle_lmp)
+    g.close()
     print(json.dumps(line), flush=True)
 
 

@@ -59,7 +59,10 @@ extern "C" {
                            /* U_B's first row that exceed 2^-60 |r(0)|                        */
 
 #define EDA_HV_ADD_IDENTITY  1u  /* eda_hessvec returns (I + A) X instead of A X           */
-#define EDA_HV_MIXED         2u  /* FP32 tangent-linear/adjoint runs (sketch products only) */
+#define EDA_HV_MIXED         2u  /* reduced precision (sketch products): FP32 TL/AD runs; the  */
+                                 /* dense U_B products on the matrix cores with FP32 operands */
+                                 /* and FP32 accumulation                                      */
+#define EDA_HV_BF16          4u  /* as EDA_HV_MIXED, the dense U_B products with BF16 operands */
 
 #define EDA_SKETCH_RHS_DIFF  0   /* Phi = Gamma = [b_1 - b_0, ..., b_ell - b_0] (Gamma eq.) */
 #define EDA_SKETCH_USER      1   /* Phi = d_phi (e.g. a Gaussian Psi drawn by the caller)   */
@@ -137,8 +140,11 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
  * linearisation trajectory.  A_m x = U_B^T G_m^T R^-1 G_m U_B x: a U_B product,
  * a TL run over the window writing the observed increments, an AD run forced
  * by them, and a U_B^T product.  nb <= max_cols; X and Y must not overlap.
- * EDA_HV_MIXED runs the TL/AD in FP32 (relative error of order 1e-6 against
- * FP64; meant for sketch products only). */
+ * EDA_HV_MIXED runs the TL/AD in FP32 and, with the dense U_B, the U_B products
+ * with FP32 operands (relative error of order 1e-6 against FP64); EDA_HV_BF16
+ * takes BF16 operands for the dense U_B products (relative error of order 1e-3).
+ * Both are meant for sketch products only; with the banded U_B the U_B products
+ * stay FP64. */
 int eda_hessvec(eda_ctx *ctx, const int32_t *d_col_member, int32_t nb,
                 const double *d_X, int64_t ldx, double *d_Y, int64_t ldy, uint32_t flags);
 
@@ -151,7 +157,9 @@ int eda_hessvec(eda_ctx *ctx, const int32_t *d_col_member, int32_t nb,
  * the shift nu = 2^-52 ||Y||_F on breakdown, T = R_Y C^-1, SVD T = U Sigma V^T,
  * S = Q_Y U, D = Sigma^2, truncation to k); EDA_METHOD_REVD runs
  * Q = orth(A Phi), T = Q^T A Q, T = V D V^T, S = Q V (q ignored).
- * theta_rule: EDA_THETA_*.  flags: 0 or EDA_HV_MIXED for the sketch products.
+ * theta_rule: EDA_THETA_*.  flags: 0, EDA_HV_MIXED or EDA_HV_BF16 for the
+ * sketch products (with BF16 operands the Cholesky of an ill-conditioned
+ * sketch can fail: EDA_ERR_NOT_SPD).
  * The context keeps S_k, D_k and theta for eda_lmp_apply / eda_pcg_solve.
  * h_eig (k doubles, may be NULL): D_k, descending; h_theta (may be NULL).
  * 1 <= k <= ell <= max_ell, q >= 1.  Synchronises the stream.
@@ -215,6 +223,14 @@ int eda_field(const eda_ctx *ctx, int32_t field, size_t *byte_offset, int64_t *c
 int eda_profile(eda_ctx *ctx, int32_t enable);
 int eda_profile_read(eda_ctx *ctx, int64_t *launches, double *total_ms);
 
+/* Launch geometry of this context's TL/AD kernels (eda_hessvec, the sketch
+ * products and eda_pcg_solve): waves per workgroup (1, 2, 4 or 8; 0 = the
+ * default for n) and time-block length (1 .. the maximum the window allows;
+ * 0 = that maximum).  Results do not depend on it (the products are computed
+ * point by point in the same order), only speed; the batch autotuner chooses
+ * among these.  Errors: EDA_ERR_UNSUPPORTED for a geometry n does not admit. */
+int eda_set_geometry(eda_ctx *ctx, int32_t waves, int32_t tb);
+
 /* Free the context's host structures (the workspace stays the caller's). */
 int eda_destroy(eda_ctx *ctx);
 
@@ -256,14 +272,14 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
 
 /* Sketch, Nystrom and LMP-PCG of every member of every problem (see above);
  * returns after the work is done.  rtol, maxit: the PCG stopping rule of
- * eda_pcg_solve.  use_lmp = 0 skips the sketch and runs plain CG.  The graph
- * uses unshifted CholQR2 and Cholesky; a problem where one of them fails is
- * solved by plain CG in the graph and then redone by eda_sketch_evd (shifted
- * CholQR and the Nystrom shift of the Nystrom-variants appendix) and
- * eda_pcg_solve; if that sketch fails too (EDA_ERR_NOT_SPD: Phi numerically
- * rank-deficient, e.g. ell close to n), the plain CG solution is kept.
- * h_fallbacks (optional, 2 entries) receives the number of problems redone and,
- * of those, the number left without LMP.  Returns EDA_OK or a negative error. */
+ * eda_pcg_solve.  use_lmp = 0 skips the sketch and runs plain CG.  The sketch
+ * graph uses unshifted CholQR2 and Cholesky; a problem where one of them fails
+ * gets its LMP from eda_sketch_evd instead (shifted CholQR and the Nystrom shift
+ * of the Nystrom-variants appendix) before the solve graph runs; if that sketch
+ * fails too (EDA_ERR_NOT_SPD: Phi numerically rank-deficient, e.g. ell close to
+ * n), its members are solved by plain CG.  h_fallbacks (optional, 2 entries)
+ * receives the number of problems whose sketch was redone and, of those, the
+ * number solved without LMP.  Returns EDA_OK or a negative error. */
 int eda_batch_solve(eda_batch *batch, int32_t k_cap, double rtol, int32_t maxit, int32_t use_lmp,
                     int32_t *h_fallbacks);
 
@@ -280,7 +296,12 @@ int eda_batch_result(eda_batch *batch, int32_t p, double *d_DZ, int64_t ldz, int
  * time in microseconds}.  Returns the number of classes. */
 int eda_batch_tuning(eda_batch *batch, int32_t cls, int32_t *h_out);
 
-/* Free the batch's host structures and its graph and stream. */
+/* Wall times of the last eda_batch_solve in milliseconds: h_ms[0] the
+ * sketch graph, h_ms[1] the host-driven sketches of problems whose graph
+ * sketch failed, h_ms[2] the solve graph. */
+int eda_batch_timing(eda_batch *batch, double *h_ms);
+
+/* Free the batch's host structures and its graphs and stream. */
 int eda_batch_destroy(eda_batch *batch);
 
 /* Static description of a status code. */

@@ -3,6 +3,7 @@
 // Host code only sequences kernels on the context's stream; every arithmetic
 // step of the path runs in this library's HIP kernels.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -47,7 +48,7 @@ bool valid_cfg(const eda_config *c) {
 struct Plan {
     int n, N, L, nt, nv, p, maxc, maxl;
     int pad_l, ext_len;
-    size_t off_trajx, off_ub16;
+    size_t off_trajx, off_ub16, off_ub32;
     size_t off_ubrow, off_ub, off_truth, off_spin, off_xb, off_traj, off_y, off_d, off_force, off_b, off_costc;
     size_t off_hv_v, off_hv_obs, off_hv_lam, off_zero;
     size_t off_phi, off_sy, off_sq, off_sq1, off_ss, off_small, off_eig, off_coef, off_coefu, off_info, off_splitk,
@@ -74,6 +75,7 @@ Plan make_plan(const eda_config *c) {
     P.off_ubrow = lay.take(n * d);
     P.off_ub = c->ub_mode == EDA_UB_DENSE ? lay.take(n * n * d) : (size_t)-1;
     P.off_ub16 = c->ub_mode == EDA_UB_DENSE ? lay.take(n * n * sizeof(uint16_t)) : (size_t)-1;
+    P.off_ub32 = c->ub_mode == EDA_UB_DENSE ? lay.take(n * n * sizeof(float)) : (size_t)-1;
     P.off_truth = lay.take((P.N + 1) * n * d);
     P.off_spin = lay.take(n * d);
     P.off_xb = lay.take(n * L1 * d);
@@ -143,12 +145,15 @@ void band_taps(int n, double len_b, int &lo, int &hi) {
     }
 }
 
-// Y = U_B X (+ Add), columns optionally masked.  lowp: the dense product runs
-// with BF16 operands and FP32 accumulation (reduced-precision sketch).
+// Y = U_B X (+ Add), columns optionally masked.  lowp (reduced-precision
+// sketch): the dense product runs on the matrix cores with FP32 accumulation
+// and FP32 operands (1) or BF16 operands (2).
 int ub_apply(Ctx &c, int nb, const double *X, long long ldx, double *Y, long long ldy, const double *Add,
-             long long ldadd, const int32_t *active, bool lowp = false) {
-    if (c.cfg.ub_mode == EDA_UB_DENSE && lowp) {
+             long long ldadd, const int32_t *active, int lowp = 0) {
+    if (c.cfg.ub_mode == EDA_UB_DENSE && lowp == 2) {
         HIP_TRY(gemm_bf16(c.stream, c.n, nb, c.n, c.ub16, c.n, X, ldx, Y, ldy, Add, ldadd));
+    } else if (c.cfg.ub_mode == EDA_UB_DENSE && lowp == 1) {
+        HIP_TRY(gemm_f32in(c.stream, c.n, nb, c.n, c.ub32, c.n, X, ldx, Y, ldy, Add, ldadd));
     } else if (c.cfg.ub_mode == EDA_UB_DENSE) {
         HIP_TRY(gemm_f64(c.stream, false, c.n, nb, c.n, c.ub, c.n, X, ldx, Y, ldy, Add, ldadd, nullptr, nullptr, 0));
     } else {
@@ -202,7 +207,7 @@ int run_tlad(Ctx &c, const TladArgs &a, int mode, bool fp32) {
         c.ev_used += 2;
         HIP_TRY(hipEventRecord(e0, c.stream));
     }
-    HIP_TRY(launch_tlad(c.stream, a, mode, fp32));
+    HIP_TRY(launch_tlad(c.stream, a, mode, fp32, c.geo_waves, c.geo_tb));
     if (rec) {
         HIP_TRY(hipEventRecord(e1, c.stream));
         c.prof_launches++;
@@ -216,7 +221,8 @@ int hessvec(Ctx &c, const int32_t *cols, int nb, const double *X, long long ldx,
             uint32_t flags, const int32_t *active) {
     if (nb <= 0) return EDA_OK;
     const bool add = (flags & EDA_HV_ADD_IDENTITY) != 0;
-    const bool fp32 = (flags & EDA_HV_MIXED) != 0;
+    const bool fp32 = (flags & (EDA_HV_MIXED | EDA_HV_BF16)) != 0;
+    const int lowp = (flags & EDA_HV_BF16) ? 2 : fp32 ? 1 : 0;
     if (c.cfg.ub_mode == EDA_UB_BANDED) {
         TladArgs a = tlad_args(c, nb, cols, active);
         a.V = X;
@@ -227,7 +233,7 @@ int hessvec(Ctx &c, const int32_t *cols, int nb, const double *X, long long ldx,
         a.add_identity = add ? 1 : 0;
         return run_tlad(c, a, TLAD_HV, fp32);
     }
-    EDA_TRY(ub_apply(c, nb, X, ldx, c.hv_v, c.n, nullptr, 0, active, fp32));
+    EDA_TRY(ub_apply(c, nb, X, ldx, c.hv_v, c.n, nullptr, 0, active, lowp));
     TladArgs a = tlad_args(c, nb, cols, active);
     a.V = c.hv_v;
     a.ldv = c.n;
@@ -235,7 +241,7 @@ int hessvec(Ctx &c, const int32_t *cols, int nb, const double *X, long long ldx,
     a.lam = c.hv_lam;
     a.ldl = c.n;
     EDA_TRY(run_tlad(c, a, TLAD_RAW, fp32));
-    EDA_TRY(ub_apply(c, nb, c.hv_lam, c.n, Y, ldy, add ? X : nullptr, ldx, active, fp32));
+    EDA_TRY(ub_apply(c, nb, c.hv_lam, c.n, Y, ldy, add ? X : nullptr, ldx, active, lowp));
     return EDA_OK;
 }
 
@@ -332,6 +338,7 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
     c.ubrow = at<double>(w, P.off_ubrow);
     c.ub = P.off_ub == (size_t)-1 ? nullptr : at<double>(w, P.off_ub);
     c.ub16 = P.off_ub16 == (size_t)-1 ? nullptr : at<uint16_t>(w, P.off_ub16);
+    c.ub32 = P.off_ub32 == (size_t)-1 ? nullptr : at<float>(w, P.off_ub32);
     c.truth = at<double>(w, P.off_truth);
     double *spin = at<double>(w, P.off_spin);
     c.xb = at<double>(w, P.off_xb);
@@ -389,6 +396,7 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
     if (launch_ub_row(s, n, cfg->sigma_b, cfg->len_b, c.ubrow) != hipSuccess) return fail(EDA_ERR_HIP);
     if (c.ub && launch_ub_fill(s, n, c.ubrow, c.ub) != hipSuccess) return fail(EDA_ERR_HIP);
     if (c.ub16 && launch_to_bf16(s, (long long)n * n, c.ub, c.ub16) != hipSuccess) return fail(EDA_ERR_HIP);
+    if (c.ub32 && launch_to_f32(s, (long long)n * n, c.ub, c.ub32) != hipSuccess) return fail(EDA_ERR_HIP);
     // truth: spin-up then the window
     if (launch_spin_init(s, n, F, cfg->spin_pert_std, z, spin) != hipSuccess) return fail(EDA_ERR_HIP);
     if (cfg->spinup > 0 && launch_nl(s, n, 1, cfg->spinup, F, hh, dt, c6, spin, nullptr, spin) != hipSuccess)
@@ -436,7 +444,7 @@ int eda_hessvec(eda_ctx *h, const int32_t *d_col_member, int32_t nb, const doubl
     if (nb < 0 || nb > c.max_cols || ldx < c.n || ldy < c.n) return EDA_ERR_INVALID_ARG;
     if (nb == 0) return EDA_OK;
     if (!d_col_member || !d_X || !d_Y) return EDA_ERR_INVALID_ARG;
-    if (flags & ~(EDA_HV_ADD_IDENTITY | EDA_HV_MIXED)) return EDA_ERR_INVALID_ARG;
+    if (flags & ~(EDA_HV_ADD_IDENTITY | EDA_HV_MIXED | EDA_HV_BF16)) return EDA_ERR_INVALID_ARG;
     return hessvec(c, d_col_member, nb, d_X, ldx, d_Y, ldy, flags, nullptr);
 }
 
@@ -447,7 +455,7 @@ int eda_sketch_evd(eda_ctx *h, int32_t kind, const double *d_phi, int64_t ldphi,
     if (ell < 1 || ell > c.max_ell || k < 1 || k > ell || q < 1) return EDA_ERR_INVALID_ARG;
     if (method != EDA_METHOD_NYSTROM && method != EDA_METHOD_REVD) return EDA_ERR_INVALID_ARG;
     if (theta_rule < EDA_THETA_MID || theta_rule > EDA_THETA_ONE) return EDA_ERR_INVALID_ARG;
-    if (flags & ~EDA_HV_MIXED) return EDA_ERR_INVALID_ARG;
+    if (flags & ~(EDA_HV_MIXED | EDA_HV_BF16)) return EDA_ERR_INVALID_ARG;
     if (kind == EDA_SKETCH_RHS_DIFF) {
         if (ell > c.L) return EDA_ERR_INVALID_ARG;
     } else if (kind == EDA_SKETCH_USER || kind == EDA_SKETCH_B_PSI || kind == EDA_SKETCH_UBT_PSI) {
@@ -474,7 +482,7 @@ int eda_sketch_evd(eda_ctx *h, int32_t kind, const double *d_phi, int64_t ldphi,
     double *sig = c.sk_small + 4 * ls;
     double *dscal = reinterpret_cast<double *>(c.sk_info + 16);
     double nu = 0.0;
-    const uint32_t hvf = flags & EDA_HV_MIXED;
+    const uint32_t hvf = flags & (EDA_HV_MIXED | EDA_HV_BF16);
     if (method == EDA_METHOD_NYSTROM) {
         EDA_TRY(hessvec(c, c.zero_members, ell, c.sk_phi, n, c.sk_y, n, hvf, nullptr));
         EDA_TRY(cholqr2(c, ell, c.sk_y, c.sk_q, RY));
@@ -721,6 +729,17 @@ int eda_profile_read(eda_ctx *h, int64_t *launches, double *total_ms) {
     return EDA_OK;
 }
 
+int eda_set_geometry(eda_ctx *h, int32_t waves, int32_t tb) {
+    if (!h || waves < 0 || tb < 0) return EDA_ERR_INVALID_ARG;
+    Ctx &c = h->c;
+    if (waves != 0 && !tlad_waves_ok(c.n, waves)) return EDA_ERR_UNSUPPORTED;
+    const TladGeom g = tlad_geometry(c.n, waves);
+    if (tb > g.tb) return EDA_ERR_UNSUPPORTED;
+    c.geo_waves = waves;
+    c.geo_tb = tb;
+    return EDA_OK;
+}
+
 int eda_destroy(eda_ctx *h) {
     if (!h) return EDA_ERR_INVALID_ARG;
     for (hipEvent_t e : h->c.ev) (void)hipEventDestroy(e);
@@ -762,6 +781,11 @@ struct eda_batch {
     TladArgs *d_solve = nullptr, *d_hv = nullptr;
     SolveTask *d_stasks = nullptr, *d_htasks = nullptr;
     int *d_counters = nullptr;
+    const int32_t **d_infoptr = nullptr;  // each problem's sketch outcome slots
+    int32_t *d_flags = nullptr;           // gathered outcomes, one per problem
+    int32_t *d_titer = nullptr;           // iterations of each solve task in the last call
+    std::vector<SolveTask> stasks;        // solve tasks, grouped by class, in queue order
+    double last_ms[3] = {0.0, 0.0, 0.0};  // sketch graph, host fallback, solve graph
     struct Class {
         int n = 0;
         std::vector<int> members;  // problem indices
@@ -775,18 +799,21 @@ struct eda_batch {
     };
     std::vector<Class> classes;
     hipEvent_t fork = nullptr;
+    // branches for the per-problem Nystrom cores (independent, one CU each)
+    std::vector<hipStream_t> lanes;
+    std::vector<hipEvent_t> lane_done;
     std::vector<int> ell;
     bool tuned = false;
     int k_cap = -1, maxit = -1, use_lmp = -1;
     double rtol = -1.0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr, graph_sk = nullptr;
+    hipGraphExec_t exec = nullptr, exec_sk = nullptr;
 };
 
 namespace {
 
 struct BatchPlan {
-    size_t off_solve, off_hv, off_st, off_ht, off_cnt, total;
+    size_t off_solve, off_hv, off_st, off_ht, off_cnt, off_iptr, off_flags, off_titer, total;
 };
 
 BatchPlan batch_plan(eda_ctx *const *ctxs, int np) {
@@ -803,6 +830,9 @@ BatchPlan batch_plan(eda_ctx *const *ctxs, int np) {
     P.off_st = lay.take(sizeof(SolveTask) * (st ? st : 1));
     P.off_ht = lay.take(sizeof(SolveTask) * (ht ? ht : 1));
     P.off_cnt = lay.take(sizeof(int) * np);
+    P.off_iptr = lay.take(sizeof(int32_t *) * np);
+    P.off_flags = lay.take(sizeof(int32_t) * np);
+    P.off_titer = lay.take(sizeof(int32_t) * (st ? st : 1));
     P.total = lay.total;
     return P;
 }
@@ -941,8 +971,9 @@ int batch_tune(eda_batch &b) {
     return rc;
 }
 
-// Enqueue the whole batched solve on b.stream (captured by the caller).
-int batch_enqueue(eda_batch &b) {
+// Enqueue the batch's sketches (Gamma, products, Nystrom cores) and the
+// gathering of their Cholesky outcomes on b.stream (captured by the caller).
+int batch_enqueue_sketch(eda_batch &b) {
     hipStream_t s = b.stream;
     for (size_t i = 0; i < b.probs.size(); i++)
         HIP_TRY(launch_gamma(s, b.probs[i]->n, b.ell[i], b.probs[i]->b, b.probs[i]->sk_phi));
@@ -954,13 +985,26 @@ int batch_enqueue(eda_batch &b) {
         HIP_TRY(hipEventRecord(k.done, k.side));
         HIP_TRY(hipStreamWaitEvent(s, k.done, 0));
     }
-    // Nystrom cores
+    // Nystrom cores, problems spread over parallel branches
+    const size_t nl = b.lanes.size();
+    HIP_TRY(hipEventRecord(b.fork, s));
+    for (size_t l = 0; l < nl; l++) HIP_TRY(hipStreamWaitEvent(b.lanes[l], b.fork, 0));
     for (size_t i = 0; i < b.probs.size(); i++) {
         Ctx &c = *b.probs[i];
-        c.stream = s;
-        if (b.use_lmp) EDA_TRY(nystrom_nosync(c, b.ell[i], b.ell[i]));
+        c.stream = b.lanes[i % nl];
+        EDA_TRY(nystrom_nosync(c, b.ell[i], b.ell[i]));
     }
-    // persistent solves, one branch per class
+    for (size_t l = 0; l < nl; l++) {
+        HIP_TRY(hipEventRecord(b.lane_done[l], b.lanes[l]));
+        HIP_TRY(hipStreamWaitEvent(s, b.lane_done[l], 0));
+    }
+    HIP_TRY(launch_gather_info(s, (int)b.probs.size(), b.d_infoptr, b.d_flags));
+    return EDA_OK;
+}
+
+// Enqueue the persistent solves, one branch per class.
+int batch_enqueue_solve(eda_batch &b) {
+    hipStream_t s = b.stream;
     HIP_TRY(launch_fill_int(s, (int)b.classes.size(), 0, b.d_counters));
     HIP_TRY(hipEventRecord(b.fork, s));
     for (size_t ci = 0; ci < b.classes.size(); ci++) {
@@ -977,8 +1021,38 @@ int batch_enqueue(eda_batch &b) {
 void batch_free_graph(eda_batch &b) {
     if (b.exec) (void)hipGraphExecDestroy(b.exec);
     if (b.graph) (void)hipGraphDestroy(b.graph);
-    b.exec = nullptr;
-    b.graph = nullptr;
+    if (b.exec_sk) (void)hipGraphExecDestroy(b.exec_sk);
+    if (b.graph_sk) (void)hipGraphDestroy(b.graph_sk);
+    b.exec = b.exec_sk = nullptr;
+    b.graph = b.graph_sk = nullptr;
+}
+
+// Capture what `enqueue` puts on b.stream into an instantiated graph.
+int batch_capture(eda_batch &b, int (*enqueue)(eda_batch &), hipGraph_t &graph, hipGraphExec_t &exec) {
+    const int np = (int)b.probs.size();
+    std::vector<hipStream_t> saved(np);
+    for (int i = 0; i < np; i++) saved[i] = b.probs[i]->stream;
+    HIP_TRY(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue(b);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b.stream, &g);
+    for (int i = 0; i < np; i++) b.probs[i]->stream = saved[i];
+    if (rc != EDA_OK || ec != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc != EDA_OK ? rc : EDA_ERR_HIP;
+    }
+    graph = g;
+    if (hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        graph = nullptr;
+        exec = nullptr;
+        return EDA_ERR_HIP;
+    }
+    return EDA_OK;
+}
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
 }  // namespace
@@ -1011,6 +1085,8 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
             if (k.side) (void)hipStreamDestroy(k.side);
             if (k.done) (void)hipEventDestroy(k.done);
         }
+        for (auto st : b->lanes) (void)hipStreamDestroy(st);
+        for (auto ev : b->lane_done) (void)hipEventDestroy(ev);
         if (b->fork) (void)hipEventDestroy(b->fork);
         if (b->entry) (void)hipEventDestroy(b->entry);
         if (b->stream) (void)hipStreamDestroy(b->stream);
@@ -1029,6 +1105,9 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
     b->d_stasks = reinterpret_cast<SolveTask *>(b->ws + P.off_st);
     b->d_htasks = reinterpret_cast<SolveTask *>(b->ws + P.off_ht);
     b->d_counters = reinterpret_cast<int *>(b->ws + P.off_cnt);
+    b->d_infoptr = reinterpret_cast<const int32_t **>(b->ws + P.off_iptr);
+    b->d_flags = reinterpret_cast<int32_t *>(b->ws + P.off_flags);
+    b->d_titer = reinterpret_cast<int32_t *>(b->ws + P.off_titer);
     for (int i = 0; i < np; i++) {
         b->probs.push_back(&ctxs[i]->c);
         b->handles.push_back(ctxs[i]);
@@ -1054,6 +1133,15 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
         if (hipEventCreateWithFlags(&k.done, hipEventDisableTiming) != hipSuccess) return fail(EDA_ERR_HIP);
     }
     if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) return fail(EDA_ERR_HIP);
+    const int nlanes = np < 16 ? np : 16;
+    for (int l = 0; l < nlanes; l++) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return fail(EDA_ERR_HIP);
+        b->lanes.push_back(st);
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return fail(EDA_ERR_HIP);
+        b->lane_done.push_back(ev);
+    }
     // member lists 0..L of every problem
     std::vector<int32_t> m;
     for (int i = 0; i < np; i++) {
@@ -1103,12 +1191,22 @@ int eda_batch_solve(eda_batch *b, int32_t k_cap, double rtol, int32_t maxit, int
             }
             k.s_cnt = (int)st.size() - k.s_off;
             k.h_cnt = (int)ht.size() - k.h_off;
+            // queue order: longest expected task first (window length, then
+            // ensemble size); later calls reorder by measured cost
+            std::stable_sort(st.begin() + k.s_off, st.end(), [&](const SolveTask &x, const SolveTask &y) {
+                const Ctx &a = *b->probs[x.prob], &c = *b->probs[y.prob];
+                return a.N != c.N ? a.N > c.N : a.L > c.L;
+            });
         }
         hipStream_t s = b->stream;
         HIP_TRY(hipMemcpyAsync(b->d_solve, sa.data(), sizeof(TladArgs) * np, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(b->d_hv, ha.data(), sizeof(TladArgs) * np, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(b->d_stasks, st.data(), sizeof(SolveTask) * st.size(), hipMemcpyHostToDevice, s));
+        b->stasks = st;
         HIP_TRY(hipMemcpyAsync(b->d_htasks, ht.data(), sizeof(SolveTask) * ht.size(), hipMemcpyHostToDevice, s));
+        std::vector<const int32_t *> ip(np);
+        for (int i = 0; i < np; i++) ip[i] = b->probs[i]->sk_info;
+        HIP_TRY(hipMemcpyAsync(b->d_infoptr, ip.data(), sizeof(int32_t *) * np, hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (!b->tuned) EDA_TRY(batch_tune(*b));
         for (auto &k : b->classes) {
@@ -1122,62 +1220,71 @@ int eda_batch_solve(eda_batch *b, int32_t k_cap, double rtol, int32_t maxit, int
             const int grid = (per_cu > 0 ? per_cu : 1) * cus;
             k.grid = grid < k.s_cnt ? grid : k.s_cnt;
         }
-        // capture
-        std::vector<hipStream_t> saved(np);
-        for (int i = 0; i < np; i++) saved[i] = b->probs[i]->stream;
-        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        const int rc = batch_enqueue(*b);
-        hipGraph_t g = nullptr;
-        const hipError_t ec = hipStreamEndCapture(s, &g);
-        for (int i = 0; i < np; i++) b->probs[i]->stream = saved[i];
-        if (rc != EDA_OK || ec != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return rc != EDA_OK ? rc : EDA_ERR_HIP;
-        }
-        b->graph = g;
-        if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
-            batch_free_graph(*b);
-            return EDA_ERR_HIP;
-        }
+        if (b->use_lmp) EDA_TRY(batch_capture(*b, batch_enqueue_sketch, b->graph_sk, b->exec_sk));
+        EDA_TRY(batch_capture(*b, batch_enqueue_solve, b->graph, b->exec));
     }
-    HIP_TRY(hipGraphLaunch(b->exec, b->stream));
-    HIP_TRY(hipStreamSynchronize(b->stream));
-    // Cholesky outcomes of the in-graph sketches.  A problem whose sketch failed
-    // was solved by plain CG in the graph; it is redone by the host-driven path
-    // (shifted CholQR and shifted Nystrom, then LMP-PCG), and keeps the plain CG
-    // result only if that sketch fails as well.
-    int fallbacks = 0, unprec = 0, warn = EDA_OK;
+    // 1) sketches in one graph; 2) where an unshifted Cholesky failed, the
+    // host-driven sketch (shifted CholQR, Nystrom shift) redoes that problem's
+    // LMP, and a problem whose shifted sketch fails as well is marked for plain
+    // CG; 3) all solves in one graph.
+    int fallbacks = 0, unprec = 0;
+    double t0 = now_ms(), t1 = t0;
     if (b->use_lmp) {
+        HIP_TRY(hipGraphLaunch(b->exec_sk, b->stream));
+        std::vector<int32_t> flags(np);
+        HIP_TRY(hipMemcpyAsync(flags.data(), b->d_flags, sizeof(int32_t) * np, hipMemcpyDeviceToHost, b->stream));
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        t1 = now_ms();
         for (int i = 0; i < np; i++) {
             Ctx &c = *b->probs[i];
-            int32_t info[3] = {0, 0, 0};
-            HIP_TRY(hipMemcpy(info, c.sk_info, sizeof(info), hipMemcpyDeviceToHost));
-            if (info[0] == 0 && info[1] == 0 && info[2] == 0) {
-                c.have_lmp = true;
-                c.k = b->ell[i];
-                continue;
-            }
+            c.have_lmp = true;
+            c.k = b->ell[i];
+            if (flags[i] == 0) continue;
             fallbacks++;
             hipStream_t keep = c.stream;
             c.stream = b->stream;
-            eda_ctx *h = b->handles[i];
-            int r = eda_sketch_evd(h, EDA_SKETCH_RHS_DIFF, nullptr, 0, b->ell[i], b->ell[i], 1, EDA_METHOD_NYSTROM,
-                                   EDA_THETA_MID, 0, nullptr, nullptr);
+            int r = eda_sketch_evd(b->handles[i], EDA_SKETCH_RHS_DIFF, nullptr, 0, b->ell[i], b->ell[i], 1,
+                                   EDA_METHOD_NYSTROM, EDA_THETA_MID, 0, nullptr, nullptr);
             if (r == EDA_ERR_NOT_SPD) {
                 unprec++;
-                r = EDA_OK;
+                c.have_lmp = false;
+                r = launch_fill_int(c.stream, 1, 1, c.sk_info) == hipSuccess ? EDA_OK : EDA_ERR_HIP;
             } else if (r >= 0) {
-                // solutions land in the problem's PCG state (pc_x); hv_v is scratch
-                std::vector<int32_t> mem(c.L + 1), it(c.L + 1), stt(c.L + 1);
-                std::vector<double> rr(c.L + 1);
-                for (int j = 0; j <= c.L; j++) mem[j] = j;
-                r = eda_pcg_solve(h, mem.data(), c.L + 1, b->rtol, b->maxit, 1, c.hv_v, c.n, it.data(), rr.data(),
-                                  stt.data(), nullptr);
+                r = launch_fill_int(c.stream, 3, 0, c.sk_info) == hipSuccess ? EDA_OK : EDA_ERR_HIP;
             }
             c.stream = keep;
             if (r < 0) return r;
         }
     }
+    const double t2 = now_ms();
+    HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    const double t3 = now_ms();
+    // schedule of the next call: within each class, tasks by decreasing measured
+    // cost (iterations x window length), so the longest columns start first
+    {
+        const int nt = (int)b->stasks.size();
+        std::vector<int32_t> its(nt);
+        HIP_TRY(launch_task_iters(b->stream, nt, b->d_solve, b->d_stasks, b->d_titer));
+        HIP_TRY(hipMemcpyAsync(its.data(), b->d_titer, sizeof(int32_t) * nt, hipMemcpyDeviceToHost, b->stream));
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        std::vector<std::pair<long long, SolveTask>> order(nt);
+        for (int t = 0; t < nt; t++)
+            order[t] = {(long long)its[t] * b->probs[b->stasks[t].prob]->N, b->stasks[t]};
+        for (auto &k : b->classes)
+            std::stable_sort(order.begin() + k.s_off, order.begin() + k.s_off + k.s_cnt,
+                             [](const std::pair<long long, SolveTask> &x, const std::pair<long long, SolveTask> &y) {
+                                 return x.first > y.first;
+                             });
+        for (int t = 0; t < nt; t++) b->stasks[t] = order[t].second;
+        HIP_TRY(hipMemcpyAsync(b->d_stasks, b->stasks.data(), sizeof(SolveTask) * nt, hipMemcpyHostToDevice,
+                               b->stream));
+        HIP_TRY(hipStreamSynchronize(b->stream));
+    }
+    b->last_ms[0] = t1 - t0;
+    b->last_ms[1] = t2 - t1;
+    b->last_ms[2] = t3 - t2;
+    int warn = EDA_OK;
     if (h_fallbacks) {
         h_fallbacks[0] = fallbacks;
         h_fallbacks[1] = unprec;
@@ -1222,6 +1329,12 @@ int eda_batch_tuning(eda_batch *b, int32_t cls, int32_t *h_out) {
     return (int32_t)b->classes.size();
 }
 
+int eda_batch_timing(eda_batch *b, double *h_ms) {
+    if (!b || !h_ms) return EDA_ERR_INVALID_ARG;
+    for (int i = 0; i < 3; i++) h_ms[i] = b->last_ms[i];
+    return EDA_OK;
+}
+
 int eda_batch_destroy(eda_batch *b) {
     if (!b) return EDA_ERR_INVALID_ARG;
     batch_free_graph(*b);
@@ -1229,6 +1342,8 @@ int eda_batch_destroy(eda_batch *b) {
         if (k.side) (void)hipStreamDestroy(k.side);
         if (k.done) (void)hipEventDestroy(k.done);
     }
+    for (auto st : b->lanes) (void)hipStreamDestroy(st);
+    for (auto ev : b->lane_done) (void)hipEventDestroy(ev);
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->entry) (void)hipEventDestroy(b->entry);
     if (b->stream) (void)hipStreamDestroy(b->stream);

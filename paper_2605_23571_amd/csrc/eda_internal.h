@@ -36,6 +36,7 @@ struct Ctx {
     // problem data
     double *ubrow = nullptr, *ub = nullptr, *truth = nullptr, *xb = nullptr, *traj = nullptr;
     uint16_t *ub16 = nullptr;  // dense U_B in BF16 (reduced-precision sketch products)
+    float *ub32 = nullptr;     // dense U_B in FP32 (reduced-precision sketch products)
     double *trajx = nullptr;  // trajectory rows s < N, periodically padded for the TL/AD windows
     int ext_len = 0, pad_l = 0;
     double *y = nullptr, *d = nullptr, *b = nullptr, *costc = nullptr, *forcing = nullptr;
@@ -66,6 +67,7 @@ struct Ctx {
     // profiling of the TL/AD kernel inside eda_pcg_solve
     bool prof = false;
     bool in_pcg = false;
+    int geo_waves = 0, geo_tb = 0;  // TL/AD launch geometry override (0: default)
     std::vector<hipEvent_t> ev;
     int64_t prof_launches = 0;
     size_t ev_used = 0;
@@ -157,12 +159,16 @@ hipError_t launch_solve(hipStream_t s, const TladArgs *d_probs, const SolveTask 
 // of problems sharing n: one workgroup per task.
 hipError_t launch_hv_multi(hipStream_t s, const TladArgs *d_probs, const SolveTask *d_tasks, int ntasks,
                            const TladGeom &g, size_t lds);
+// out[t] = iteration count of task t (probs[tasks[t].prob].pcg.iters[col]).
+hipError_t launch_task_iters(hipStream_t s, int ntasks, const TladArgs *d_probs, const SolveTask *d_tasks,
+                             int32_t *d_out);
 // Workgroups of k_solve one CU holds for this geometry and LDS size.
 int solve_blocks_per_cu(const TladGeom &g, size_t lds);
 // Pads of the periodic row extension that every wave window of the TL/AD
 // kernel fits in without wrapping: window points j in [-pad_l, n + pad_r).
 void tlad_pads(int n, int *pad_l, int *pad_r);
-hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32);
+// waves, tb: geometry override (0: the default for n).
+hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32, int waves = 0, int tb = 0);
 
 // U_B first row (closed form) and dense fill.
 hipError_t launch_ub_row(hipStream_t s, int n, double sigma_b, double len_b, double *row);
@@ -184,6 +190,10 @@ size_t gemm_splitk_elems(int M, int N, int K);
 // column-major), B, C, Add in FP64 (B rounded to BF16 as it is staged).
 hipError_t gemm_bf16(hipStream_t s, int M, int N, int K, const unsigned short *A, long long lda, const double *B,
                      long long ldb, double *C, long long ldc, const double *Add, long long ldadd);
+// The same with FP32 operands (A in FP32, B rounded to FP32 when staged).
+hipError_t gemm_f32in(hipStream_t s, int M, int N, int K, const float *A, long long lda, const double *B,
+                      long long ldb, double *C, long long ldc, const double *Add, long long ldadd);
+hipError_t launch_to_f32(hipStream_t s, long long count, const double *x, float *y);
 // y = bf16(x), round to nearest even.
 hipError_t launch_to_bf16(hipStream_t s, long long count, const double *x, unsigned short *y);
 
@@ -196,6 +206,8 @@ hipError_t launch_innov(hipStream_t s, int n, int N, int L, int p, int nv, int o
                         double *force, double *costc);
 // Periodic extension of trajectory rows: out[m][s][j] = traj[m][s][(j - pad_l) mod n],
 // j < ext_len, for states s < N of each of nm members (input rows N + 1 per member).
+// out[i] = info[i][0] | info[i][1] | info[i][2] (the sketch outcomes of a batch).
+hipError_t launch_gather_info(hipStream_t s, int np, const int32_t *const *info, int32_t *out);
 // p[0 .. count) = value (a kernel, so that it can sit in a captured graph).
 hipError_t launch_fill_int(hipStream_t s, int count, int value, int *p);
 hipError_t launch_pad_traj(hipStream_t s, int n, int N, int nm, const double *traj, int pad_l, int ext_len,

@@ -1,5 +1,6 @@
-// BF16-input, FP32-accumulate GEMM on the matrix cores
-// (v_mfma_f32_16x16x16_bf16), column-major:  C = A B (+ Add).
+// Reduced-precision GEMMs on the matrix cores, column-major C = A B (+ Add),
+// FP32 accumulation: BF16 operands (v_mfma_f32_16x16x16_bf16) and FP32
+// operands (v_mfma_f32_16x16x4_f32).
 // Used for the dense U_B products of the reduced-precision sketch: A is U_B
 // held in BF16 (converted once at set-up), B is an FP64 block converted to BF16
 // (round to nearest even) as it is staged, C and Add are FP64.  Each product
@@ -121,7 +122,103 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const un
             }
 }
 
+// The same product with FP32 operands (v_mfma_f32_16x16x4_f32): A in FP32, B
+// rounded to FP32 as it is staged; relative rounding 2^-24 per operand.
+__global__ __launch_bounds__(256) void k_gemm_f32in(int M, int N, int K, const float *__restrict__ A, long long lda,
+                                                    const double *__restrict__ B, long long ldb,
+                                                    double *__restrict__ C, long long ldc,
+                                                    const double *__restrict__ Add, long long ldadd) {
+    __shared__ float As[BK][BM + 4];
+    __shared__ float Bs[BK][BN + 4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
+    float4v acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++) acc[a][b] = float4v{0.f, 0.f, 0.f, 0.f};
+    float ra[8], rb[8];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int idx = tid + 256 * e;
+            const int r = idx % BM, kk = idx / BM;
+            const int gi = i0 + r, gk = k0 + kk;
+            ra[e] = (gi < M && gk < K) ? A[gi + (long long)gk * lda] : 0.f;
+            const int kb = idx % BK, cc = idx / BK;
+            const int gj = j0 + cc, gkb = k0 + kb;
+            rb[e] = (gj < N && gkb < K) ? (float)B[gkb + (long long)gj * ldb] : 0.f;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int idx = tid + 256 * e;
+            As[idx / BM][idx % BM] = ra[e];
+            Bs[idx % BK][idx / BK] = rb[e];
+        }
+    };
+    load(0);
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        store();
+        __syncthreads();
+        if (k0 + BK < K) load(k0 + BK);
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ks++) {
+            const int kk = ks * 4 + (lane >> 4);  // lane l supplies k = 4 ks + l / 16
+            float av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; a++) av[a] = As[kk][wr * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+            for (int b = 0; b < 2; b++) bv[b] = Bs[kk][wc * 32 + b * 16 + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < 2; a++)
+#pragma unroll
+                for (int b = 0; b < 2; b++)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[b], av[a], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int row = i0 + wr * 32 + a * 16 + (lane & 15);
+                const int col = j0 + wc * 32 + b * 16 + 4 * (lane >> 4) + v;
+                if (row < M && col < N) {
+                    double val = (double)acc[a][b][v];
+                    if (Add) val += Add[row + (long long)col * ldadd];
+                    C[row + (long long)col * ldc] = val;
+                }
+            }
+}
+
+__global__ void k_to_f32(long long count, const double *__restrict__ x, float *__restrict__ y) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (long long)gridDim.x * blockDim.x)
+        y[i] = (float)x[i];
+}
+
 }  // namespace
+
+hipError_t launch_to_f32(hipStream_t s, long long count, const double *x, float *y) {
+    if (count <= 0) return hipSuccess;
+    long long blocks = (count + 255) / 256;
+    if (blocks > 65535) blocks = 65535;
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)blocks), dim3(256), 0, s, count, x, y);
+    return hipGetLastError();
+}
+
+hipError_t gemm_f32in(hipStream_t s, int M, int N, int K, const float *A, long long lda, const double *B,
+                      long long ldb, double *C, long long ldc, const double *Add, long long ldadd) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN);
+    hipLaunchKernelGGL(k_gemm_f32in, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, Add, ldadd);
+    return hipGetLastError();
+}
 
 hipError_t launch_to_bf16(hipStream_t s, long long count, const double *x, unsigned short *y) {
     if (count <= 0) return hipSuccess;

@@ -535,24 +535,44 @@ __global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
 }
 
 // z = P r = r + S diag(coef) S^T r for one column (in-kernel LMP of the
-// persistent solve): t = coef .* (S^T r) with the k dot products split over the
-// waves (fixed lane order and shuffle tree), then z row by row.  r and z are
-// the column's global vectors, tsh k doubles of LDS.
-__device__ __forceinline__ void lmp_column(const PcgCols &pc, int n, const double *r, double *z, double *tsh,
-                                           int waves) {
+// persistent solve).  r is first staged in LDS (rs, n doubles).  t = coef .*
+// (S^T r): the k dot products are split over the waves, each lane keeps eight
+// independent partial sums so that sixteen loads are in flight, then a fixed
+// shuffle tree.  z = r + S t: rows over the threads, eight columns of S per
+// round.  r and z are the column's global vectors, tsh k doubles of LDS.
+__device__ __forceinline__ void lmp_column(const PcgCols &pc, int n, const double *r, double *z, double *rs,
+                                           double *tsh, int waves) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x, nthr = blockDim.x;
     const int k = pc.lmp_k;
+    for (int i = tid; i < n; i += nthr) rs[i] = r[i];
+    __syncthreads();
     for (int j = wave; j < k; j += waves) {
         const double *sj = pc.lmp_s + (long long)j * n;
-        double sum = 0.0;
-        for (int i = lane; i < n; i += 64) sum += sj[i] * r[i];
+        double acc[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) acc[u] = 0.0;
+        int i = lane;
+        for (; i + 7 * 64 < n; i += 8 * 64) {
+#pragma unroll
+            for (int u = 0; u < 8; u++) acc[u] += sj[i + u * 64] * rs[i + u * 64];
+        }
+        for (; i < n; i += 64) acc[0] += sj[i] * rs[i];
+        double sum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
         for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
         if (lane == 0) tsh[j] = pc.lmp_c[j] * sum;
     }
     __syncthreads();
     for (int i = tid; i < n; i += nthr) {
-        double v = r[i];
-        for (int j = 0; j < k; j++) v += pc.lmp_s[i + (long long)j * n] * tsh[j];
+        double v = rs[i];
+        int j = 0;
+        for (; j + 8 <= k; j += 8) {
+            double sv[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) sv[u] = pc.lmp_s[i + (long long)(j + u) * n];
+#pragma unroll
+            for (int u = 0; u < 8; u++) v += sv[u] * tsh[j + u];
+        }
+        for (; j < k; j++) v += pc.lmp_s[i + (long long)j * n] * tsh[j];
         z[i] = v;
     }
     __syncthreads();
@@ -607,7 +627,7 @@ __global__ __launch_bounds__(512) void k_solve(const TladArgs *__restrict__ prob
         // a sketch whose Cholesky failed gives no LMP: plain CG for its members
         const bool lmp = pc.lmp_k > 0 && !(pc.lmp_info && (pc.lmp_info[0] | pc.lmp_info[1] | pc.lmp_info[2]));
         if (lmp) {
-            lmp_column(pc, n, r, z, s_t, nthr >> 6);
+            lmp_column(pc, n, r, z, reinterpret_cast<double *>(smraw), s_t, nthr >> 6);
         } else {
             for (int i = tid; i < n; i += nthr) z[i] = r[i];
             __syncthreads();
@@ -620,7 +640,7 @@ __global__ __launch_bounds__(512) void k_solve(const TladArgs *__restrict__ prob
             __syncthreads();
             if (st != COL_RUNNING) break;
             if (lmp) {
-                lmp_column(pc, n, r, z, s_t, nthr >> 6);
+                lmp_column(pc, n, r, z, reinterpret_cast<double *>(smraw), s_t, nthr >> 6);
             } else {
                 for (int i = tid; i < n; i += nthr) z[i] = r[i];
                 __syncthreads();
@@ -637,6 +657,13 @@ __global__ __launch_bounds__(512) void k_solve(const TladArgs *__restrict__ prob
         }
         __syncthreads();
     }
+}
+
+// out[t] = iterations task t took in the last persistent solve.
+__global__ void k_task_iters(int ntasks, const TladArgs *__restrict__ probs, const SolveTask *__restrict__ tasks,
+                             int32_t *__restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < ntasks) out[t] = probs[tasks[t].prob].pcg.iters[tasks[t].col];
 }
 
 // Hessian products of (problem, column) tasks, one workgroup per task.
@@ -753,6 +780,13 @@ hipError_t launch_hv_multi(hipStream_t s, const TladArgs *d_probs, const SolveTa
     }
 }
 
+hipError_t launch_task_iters(hipStream_t s, int ntasks, const TladArgs *d_probs, const SolveTask *d_tasks,
+                             int32_t *d_out) {
+    if (ntasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_task_iters, dim3((ntasks + 255) / 256), dim3(256), 0, s, ntasks, d_probs, d_tasks, d_out);
+    return hipGetLastError();
+}
+
 int solve_blocks_per_cu(const TladGeom &g, size_t lds) {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
@@ -817,9 +851,10 @@ void tlad_pads(int n, int *pad_l, int *pad_r) {
     *pad_r = pr;
 }
 
-hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32) {
+hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32, int waves, int tb) {
     if (a.nb <= 0) return hipSuccess;
-    TladGeom g = tlad_geometry(a.n, 0);
+    if (waves != 0 && !tlad_waves_ok(a.n, waves)) return hipErrorInvalidValue;
+    TladGeom g = tlad_geometry(a.n, waves, tb);
     if (g.q > 9 || g.tb < 1) return hipErrorInvalidValue;
     if (mode == TLAD_PCG && fp32) return hipErrorInvalidValue;  // PCG recurrences stay FP64
     return fp32 ? launch_t<float>(s, a, g, mode) : launch_t<double>(s, a, g, mode);

@@ -154,7 +154,18 @@ __global__ void k_fill_int(int count, int value, int *__restrict__ p) {
     if (i < count) p[i] = value;
 }
 
+__global__ void k_gather_info(int np, const int32_t *const *__restrict__ info, int32_t *__restrict__ out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < np) out[i] = info[i][0] | info[i][1] | info[i][2];
+}
+
 }  // namespace
+
+hipError_t launch_gather_info(hipStream_t s, int np, const int32_t *const *info, int32_t *out) {
+    if (np <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_info, dim3((np + 255) / 256), dim3(256), 0, s, np, info, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_int(hipStream_t s, int count, int value, int *p) {
     if (count <= 0) return hipSuccess;

@@ -29,7 +29,7 @@ EDA_ERR_UNSUPPORTED = -6
 EDA_WARN_NOT_CONVERGED = 1
 EDA_MEMBER_CONVERGED, EDA_MEMBER_NOT_CONVERGED, EDA_MEMBER_BREAKDOWN = 0, 1, 2
 EDA_UB_DENSE, EDA_UB_BANDED = 0, 1
-EDA_HV_ADD_IDENTITY, EDA_HV_MIXED = 1, 2
+EDA_HV_ADD_IDENTITY, EDA_HV_MIXED, EDA_HV_BF16 = 1, 2, 4
 EDA_SKETCH_RHS_DIFF, EDA_SKETCH_USER, EDA_SKETCH_B_PSI, EDA_SKETCH_UBT_PSI = 0, 1, 2, 3
 EDA_METHOD_NYSTROM, EDA_METHOD_REVD = 0, 1
 EDA_THETA_MID, EDA_THETA_LAMK, EDA_THETA_ONE = 0, 1, 2
@@ -79,12 +79,14 @@ def lib():
             "eda_profile": [vp, i32],
             "eda_profile_read": [vp, ctypes.POINTER(i64), ctypes.POINTER(dbl)],
             "eda_destroy": [vp],
+            "eda_set_geometry": [vp, i32, i32],
             "eda_strerror": [ctypes.c_int],
             "eda_batch_workspace_bytes": [vp, i32, ctypes.POINTER(sz)],
             "eda_batch_create": [vp, i32, vp, sz, vp, ctypes.POINTER(vp)],
             "eda_batch_solve": [vp, i32, dbl, i32, i32, vp],
             "eda_batch_result": [vp, i32, vp, i64, vp, vp, vp],
             "eda_batch_tuning": [vp, i32, vp],
+            "eda_batch_timing": [vp, vp],
             "eda_batch_destroy": [vp],
         }
         for name, args in sigs.items():
@@ -224,6 +226,10 @@ def eda_profile_read(ctx):
     return n.value, ms.value
 
 
+def eda_set_geometry(ctx, waves: int, tb: int):
+    _check("eda_set_geometry", lib().eda_set_geometry(ctx, int(waves), int(tb)))
+
+
 def eda_destroy(ctx):
     _check("eda_destroy", lib().eda_destroy(ctx))
 
@@ -276,8 +282,21 @@ def eda_batch_tuning(batch) -> list[dict]:
     return res
 
 
+def eda_batch_timing(batch) -> dict:
+    out = (ctypes.c_double * 3)()
+    _check("eda_batch_timing", lib().eda_batch_timing(batch, out))
+    return dict(sketch_graph_ms=out[0], host_sketch_ms=out[1], solve_graph_ms=out[2])
+
+
 def eda_batch_destroy(batch):
     _check("eda_batch_destroy", lib().eda_batch_destroy(batch))
+
+
+def _lowp_flag(mixed) -> int:
+    """False: FP64; True or "fp32": EDA_HV_MIXED; "bf16": EDA_HV_BF16."""
+    if mixed == "bf16":
+        return EDA_HV_BF16
+    return EDA_HV_MIXED if mixed else 0
 
 
 class Batch:
@@ -302,6 +321,9 @@ class Batch:
 
     def tuning(self) -> list[dict]:
         return eda_batch_tuning(self.b)
+
+    def timing(self) -> dict:
+        return eda_batch_timing(self.b)
 
     def close(self):
         if self.b:
@@ -339,7 +361,7 @@ class Problem:
         torch = _torch()
         cols = torch.as_tensor(np.asarray(members, dtype=np.int32)).cuda()
         Y = torch.empty_like(X)
-        flags = (EDA_HV_ADD_IDENTITY if add_identity else 0) | (EDA_HV_MIXED if mixed else 0)
+        flags = (EDA_HV_ADD_IDENTITY if add_identity else 0) | _lowp_flag(mixed)
         return eda_hessvec(self.ctx, self.n, cols, X, Y, flags)
 
     def sketch_evd(self, kind: str = "rhs_diff", ell: int | None = None, k: int | None = None, q: int = 1,
@@ -350,7 +372,7 @@ class Problem:
         k = k or self.cfg["k"]
         return eda_sketch_evd(self.ctx, self.n, kinds[kind], phi, ell, k, q,
                               EDA_METHOD_NYSTROM if method == "nystrom" else EDA_METHOD_REVD, THETA_RULES[theta],
-                              EDA_HV_MIXED if mixed else 0)
+                              _lowp_flag(mixed))
 
     def lmp_apply(self, X, which: str = "P"):
         torch = _torch()

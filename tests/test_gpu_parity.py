@@ -113,17 +113,64 @@ def test_hessvec_mixed_precision_bound(case):
 
 @pytest.mark.parametrize("case", ["C1", "n1001"])
 def test_hessvec_mixed_dense_bf16_bound(case):
-    # Dense U_B with the reduced-precision flag: both U_B products take BF16
-    # operands (unit roundoff 2^-9 each) with FP32 accumulation, the TL/AD runs
-    # FP32.  Each product carries about 2^-9 relative rounding from each operand,
-    # so the stated bound on the whole A X is 1e-2; it must also exceed the FP32
-    # path's error (the BF16 products really ran).
+    # Dense U_B with EDA_HV_BF16: both U_B products take BF16 operands (unit
+    # roundoff 2^-9 each) with FP32 accumulation, the TL/AD runs FP32.  Each
+    # product carries about 2^-9 relative rounding from each operand, so the
+    # stated bound on the whole A X is 1e-2; it must also exceed the FP32 path's
+    # error (the BF16 products really ran).
     cfg, g, o = problem(case, "dense")
     n = cfg["n"]
     X = np.random.default_rng(4).standard_normal((cfg["ell"], n))
-    Y = to_np_cols(g.hessvec(np.zeros(cfg["ell"], dtype=np.int32), torch.from_numpy(X).cuda(), mixed=True), n)
+    Y = to_np_cols(g.hessvec(np.zeros(cfg["ell"], dtype=np.int32), torch.from_numpy(X).cuda(), mixed="bf16"), n)
     err = colrel(Y, o.A(X.T, [0] * cfg["ell"]))
     assert 1e-5 < err < 1e-2, err
+
+
+@pytest.mark.parametrize("case", ["C1", "n1001"])
+def test_hessvec_mixed_dense_fp32_bound(case):
+    # Dense U_B with EDA_HV_MIXED: U_B products with FP32 operands and FP32
+    # accumulation, FP32 TL/AD: single-precision rounding amplified by the
+    # window, stated bound 1e-4 (as the banded FP32 path), and above 1e-10.
+    cfg, g, o = problem(case, "dense")
+    n = cfg["n"]
+    X = np.random.default_rng(5).standard_normal((cfg["ell"], n))
+    Y = to_np_cols(g.hessvec(np.zeros(cfg["ell"], dtype=np.int32), torch.from_numpy(X).cuda(), mixed=True), n)
+    err = colrel(Y, o.A(X.T, [0] * cfg["ell"]))
+    assert 1e-10 < err < 1e-4, err
+
+
+@pytest.mark.parametrize("case", ["n203", "n1001", "n2049"])
+@pytest.mark.parametrize("mode", ["banded", "dense"])
+def test_hessvec_every_geometry(case, mode):
+    # Every launch geometry the autotuner may pick (waves per workgroup, time-
+    # block length) computes each point with the same formula; only the
+    # compiler's FMA contraction may differ between the template instances
+    # (points per lane), so the products agree to FP64 rounding (1e-13) with
+    # the oracle and each other, member and sketch mode.
+    cfg, g, o = problem(case, mode)
+    n, L = cfg["n"], cfg["members"]
+    Xn = np.random.default_rng(9).standard_normal((L + 1, n))
+    X = torch.from_numpy(Xn).cuda()
+    cols = np.arange(L + 1, dtype=np.int32)
+    exact = o.A(Xn.T, list(range(L + 1))).T + Xn
+    exact0 = o.A(Xn.T, [0] * (L + 1)).T
+    tried, worst = 0, 0.0
+    for w in (1, 2, 4, 8):
+        for tb in (1, 2, 0):
+            try:
+                eda.eda_set_geometry(g.ctx, w, tb)
+            except eda.EdaError as e:
+                assert e.code == eda.EDA_ERR_UNSUPPORTED
+                continue
+            tried += 1
+            y = g.hessvec(cols, X, add_identity=True).cpu().numpy()
+            y0 = g.hessvec(np.zeros(L + 1, dtype=np.int32), X).cpu().numpy()
+            e = max(colrel(y.T, exact.T), colrel(y0.T, exact0.T))
+            worst = max(worst, e)
+            assert e < 1e-12, (w, tb, e)
+    eda.eda_set_geometry(g.ctx, 0, 0)
+    print(f"[geometry] {case} {mode}: {tried} geometries, worst {worst:.2e}", flush=True)
+    assert tried >= 3
 
 
 def test_hessvec_edge_cases():
