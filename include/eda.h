@@ -223,6 +223,60 @@ int eda_field(const eda_ctx *ctx, int32_t field, size_t *byte_offset, int64_t *c
 int eda_profile(eda_ctx *ctx, int32_t enable);
 int eda_profile_read(eda_ctx *ctx, int64_t *launches, double *total_ms);
 
+/* ---- learned sketch ----
+ * A small MLP maps the control member's right-hand side to k sketch directions
+ * (there is no such component in the paper; it learns what its Nystrom finds):
+ *   x = b_0 / ||b_0|| sqrt(n),  h1 = gelu(W1 x + b1),  h2 = gelu(W2 h1 + b2),
+ *   o = W3 h2 + b3,  Z[:, j] = o[j n : (j + 1) n]  (Z: n x k),
+ * gelu(t) = t Phi(t) (erf form).  Training pairs: inputs x and Ritz pairs
+ * (S, D) of the control A computed by the q-pass Nystrom algorithm, S
+ * orthonormal n x k; loss = ||Z Z^T - S diag(D) S^T||_F^2 / ||D||^2 averaged
+ * over the batch.  Parameters: one flat FP32 array, column-major
+ * W1 (h x n), b1 (h), W2 (h x h), b2 (h), W3 (k n x h), b3 (k n).
+ * Batches are column-major: X n x B (FP32), S n x k x B, D k x B. */
+typedef struct {
+    int32_t n;       /* state size (input length), 4..4096 */
+    int32_t hidden;  /* width of both hidden layers         */
+    int32_t k;       /* directions produced, 1..32          */
+} eda_mlp_dims;
+
+int eda_mlp_param_count(const eda_mlp_dims *dims, int64_t *count);
+/* Device workspace of eda_mlp_forward / eda_mlp_loss_grad for `batch` samples. */
+int eda_mlp_workspace_bytes(const eda_mlp_dims *dims, int32_t batch, size_t *bytes);
+/* He initialisation: weights = d_normals * sqrt(2 / fan_in), biases 0
+ * (d_normals: one standard normal per parameter). */
+int eda_mlp_init(const eda_mlp_dims *dims, const float *d_normals, float *d_params, void *stream);
+/* FP32 forward pass: d_O (k n x batch) = outputs o of the batch d_X (n x batch). */
+int eda_mlp_forward(const eda_mlp_dims *dims, int32_t batch, const float *d_params, const float *d_X, float *d_O,
+                    void *d_ws, size_t ws_bytes, void *stream);
+/* FP32 forward pass, loss (mean over the batch, to *h_loss) and, if d_grad is
+ * not NULL, the gradient of that mean with respect to every parameter (same
+ * layout as the parameters).  Synchronises the stream. */
+int eda_mlp_loss_grad(const eda_mlp_dims *dims, int32_t batch, const float *d_params, const float *d_X,
+                      const float *d_S, const float *d_D, float *d_grad, void *d_ws, size_t ws_bytes, void *stream,
+                      double *h_loss);
+/* Adam (Kingma and Ba), step counted from 1: m = b1 m + (1-b1) g,
+ * v = b2 v + (1-b2) g^2, theta -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps). */
+int eda_mlp_adam(int64_t count, float *d_params, const float *d_grad, float *d_m, float *d_v, int32_t step, float lr,
+                 float beta1, float beta2, float eps, void *stream);
+/* The network input of this problem, x = b_0 / ||b_0|| sqrt(n) in FP32 (n
+ * floats at d_x), enqueued on the context's stream. */
+int eda_mlp_input(eda_ctx *ctx, float *d_x);
+/* BF16 copy of the parameters (round to nearest even) for inference. */
+int eda_mlp_to_bf16(int64_t count, const float *d_params, uint16_t *d_params16, void *stream);
+/* BF16 inference on this problem's control right-hand side: d_Z (n x k, FP64)
+ * = Z; BF16 weights and inputs, FP32 accumulation, FP64 epilogues.  dims->n
+ * must equal the problem's n. */
+int eda_mlp_infer(eda_ctx *ctx, const eda_mlp_dims *dims, const uint16_t *d_params16, double *d_Z);
+/* The learned sketch: Phi = CholQR2(Z) with Z from eda_mlp_infer, then the
+ * single-pass Nystrom approximation with that Phi (ell = dims->k), truncation
+ * to k and theta, as eda_sketch_evd(EDA_SKETCH_USER, ...).  If that breaks down
+ * (a Cholesky fails or an eigenvalue is not finite) the right-hand-side
+ * difference sketch of the same size is used instead; *h_used (may be NULL)
+ * receives 1 for the learned sketch, 0 for the fallback. */
+int eda_sketch_learned(eda_ctx *ctx, const eda_mlp_dims *dims, const uint16_t *d_params16, int32_t k,
+                       int32_t theta_rule, double *h_eig, double *h_theta, int32_t *h_used);
+
 /* Launch geometry of this context's TL/AD kernels (eda_hessvec, the sketch
  * products and eda_pcg_solve): waves per workgroup (1, 2, 4 or 8; 0 = the
  * default for n) and time-block length (1 .. the maximum the window allows;

@@ -1352,3 +1352,135 @@ int eda_batch_destroy(eda_batch *b) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Learned sketch: MLP training and inference kernels behind the C ABI
+// ---------------------------------------------------------------------------
+namespace {
+
+bool mlp_dims_ok(const eda_mlp_dims *d) {
+    return d && d->n >= 4 && d->n <= 4096 && d->hidden >= 1 && d->hidden <= 4096 && d->k >= 1 && d->k <= 32;
+}
+
+}  // namespace
+
+extern "C" {
+
+int eda_mlp_param_count(const eda_mlp_dims *d, int64_t *count) {
+    if (!mlp_dims_ok(d) || !count) return EDA_ERR_INVALID_ARG;
+    *count = mlp_layout(d->n, d->hidden, d->k).total;
+    return EDA_OK;
+}
+
+int eda_mlp_workspace_bytes(const eda_mlp_dims *d, int32_t batch, size_t *bytes) {
+    if (!mlp_dims_ok(d) || batch < 1 || !bytes) return EDA_ERR_INVALID_ARG;
+    *bytes = sizeof(float) * mlp_ws_floats(d->n, d->hidden, d->k, batch) + sizeof(double) * (size_t)batch + 256;
+    return EDA_OK;
+}
+
+int eda_mlp_init(const eda_mlp_dims *d, const float *d_normals, float *d_params, void *stream) {
+    if (!mlp_dims_ok(d) || !d_normals || !d_params) return EDA_ERR_INVALID_ARG;
+    HIP_TRY(mlp_init(reinterpret_cast<hipStream_t>(stream), d->n, d->hidden, d->k, d_normals, d_params));
+    return EDA_OK;
+}
+
+int eda_mlp_forward(const eda_mlp_dims *d, int32_t batch, const float *d_params, const float *d_X, float *d_O,
+                    void *d_ws, size_t ws_bytes, void *stream) {
+    if (!mlp_dims_ok(d) || batch < 1 || !d_params || !d_X || !d_O || !d_ws) return EDA_ERR_INVALID_ARG;
+    size_t need = 0;
+    EDA_TRY(eda_mlp_workspace_bytes(d, batch, &need));
+    if (ws_bytes < need) return EDA_ERR_WORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    float *ws = static_cast<float *>(d_ws);
+    HIP_TRY(mlp_forward(s, d->n, d->hidden, d->k, batch, d_params, d_X, ws));
+    const size_t kn = (size_t)d->k * d->n, h = d->hidden;
+    HIP_TRY(hipMemcpyAsync(d_O, ws + 4 * h * batch, sizeof(float) * kn * batch, hipMemcpyDeviceToDevice, s));
+    return EDA_OK;
+}
+
+int eda_mlp_loss_grad(const eda_mlp_dims *d, int32_t batch, const float *d_params, const float *d_X,
+                      const float *d_S, const float *d_D, float *d_grad, void *d_ws, size_t ws_bytes, void *stream,
+                      double *h_loss) {
+    if (!mlp_dims_ok(d) || batch < 1 || !d_params || !d_X || !d_S || !d_D || !d_ws || !h_loss)
+        return EDA_ERR_INVALID_ARG;
+    size_t need = 0;
+    EDA_TRY(eda_mlp_workspace_bytes(d, batch, &need));
+    if (ws_bytes < need) return EDA_ERR_WORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    float *ws = static_cast<float *>(d_ws);
+    double *lps = reinterpret_cast<double *>(
+        (reinterpret_cast<uintptr_t>(ws + mlp_ws_floats(d->n, d->hidden, d->k, batch)) + 255) & ~uintptr_t(255));
+    HIP_TRY(mlp_loss_grad(s, d->n, d->hidden, d->k, batch, d_params, d_X, d_S, d_D, d_grad, ws, lps));
+    std::vector<double> l(batch);
+    HIP_TRY(hipMemcpyAsync(l.data(), lps, sizeof(double) * batch, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double sum = 0.0;
+    for (int b = 0; b < batch; b++) sum += l[b];
+    *h_loss = sum / batch;
+    return EDA_OK;
+}
+
+int eda_mlp_adam(int64_t count, float *d_params, const float *d_grad, float *d_m, float *d_v, int32_t step, float lr,
+                 float beta1, float beta2, float eps, void *stream) {
+    if (count < 1 || !d_params || !d_grad || !d_m || !d_v || step < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) ||
+        !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        return EDA_ERR_INVALID_ARG;
+    HIP_TRY(mlp_adam(reinterpret_cast<hipStream_t>(stream), count, d_params, d_grad, d_m, d_v, step, lr, beta1, beta2,
+                     eps));
+    return EDA_OK;
+}
+
+int eda_mlp_to_bf16(int64_t count, const float *d_params, uint16_t *d_params16, void *stream) {
+    if (count < 1 || !d_params || !d_params16) return EDA_ERR_INVALID_ARG;
+    HIP_TRY(mlp_to_bf16(reinterpret_cast<hipStream_t>(stream), count, d_params, d_params16));
+    return EDA_OK;
+}
+
+int eda_mlp_input(eda_ctx *h, float *d_x) {
+    if (!h || !d_x) return EDA_ERR_INVALID_ARG;
+    Ctx &c = h->c;
+    HIP_TRY(mlp_normalise(c.stream, c.n, 1, c.b, c.n, d_x));
+    return EDA_OK;
+}
+
+int eda_mlp_infer(eda_ctx *h, const eda_mlp_dims *d, const uint16_t *d_params16, double *d_Z) {
+    if (!h || !mlp_dims_ok(d) || !d_params16 || !d_Z) return EDA_ERR_INVALID_ARG;
+    Ctx &c = h->c;
+    if (d->n != c.n) return EDA_ERR_INVALID_ARG;
+    if ((size_t)c.n + 2 * (size_t)d->hidden > (size_t)c.n * c.max_cols) return EDA_ERR_UNSUPPORTED;
+    HIP_TRY(mlp_infer_bf16(c.stream, c.n, d->hidden, d->k, d_params16, c.b, d_Z, c.hv_v));
+    return EDA_OK;
+}
+
+int eda_sketch_learned(eda_ctx *h, const eda_mlp_dims *d, const uint16_t *d_params16, int32_t k, int32_t theta_rule,
+                       double *h_eig, double *h_theta, int32_t *h_used) {
+    if (!h || !mlp_dims_ok(d) || !d_params16) return EDA_ERR_INVALID_ARG;
+    Ctx &c = h->c;
+    const int l = d->k;
+    if (d->n != c.n || l > c.max_ell || k < 1 || k > l) return EDA_ERR_INVALID_ARG;
+    if (theta_rule < EDA_THETA_MID || theta_rule > EDA_THETA_ONE) return EDA_ERR_INVALID_ARG;
+    // Phi = CholQR2(MLP(b_0)), directions in sk_phi; the Nystrom of the user-sketch path
+    EDA_TRY(eda_mlp_infer(h, d, d_params16, c.sk_phi));
+    const size_t ls = (size_t)c.max_ell * c.max_ell;
+    int r = cholqr2(c, l, c.sk_phi, c.sk_q, c.sk_small + 7 * ls);
+    if (r == EDA_OK) {
+        HIP_TRY(launch_copy_cols(c.stream, c.n, l, c.sk_q, c.n, c.sk_phi, c.n));
+        r = eda_sketch_evd(h, EDA_SKETCH_USER, c.sk_phi, c.n, l, k, 1, EDA_METHOD_NYSTROM, theta_rule, 0, h_eig,
+                           h_theta);
+    }
+    bool ok = r == EDA_OK;
+    if (ok && h_eig)
+        for (int i = 0; i < k; i++) ok &= std::isfinite(h_eig[i]);
+    if (ok) {
+        if (h_used) *h_used = 1;
+        return EDA_OK;
+    }
+    if (r < 0 && r != EDA_ERR_NOT_SPD) return r;
+    // fallback: the right-hand-side-difference sketch of the same size
+    if (l > c.L) return EDA_ERR_NOT_SPD;
+    if (h_used) *h_used = 0;
+    return eda_sketch_evd(h, EDA_SKETCH_RHS_DIFF, nullptr, 0, l, k, 1, EDA_METHOD_NYSTROM, theta_rule, 0, h_eig,
+                          h_theta);
+}
+
+}  // extern "C"

@@ -194,6 +194,24 @@ hipError_t gemm_bf16(hipStream_t s, int M, int N, int K, const unsigned short *A
 hipError_t gemm_f32in(hipStream_t s, int M, int N, int K, const float *A, long long lda, const double *B,
                       long long ldb, double *C, long long ldc, const double *Add, long long ldadd);
 hipError_t launch_to_f32(hipStream_t s, long long count, const double *x, float *y);
+// ---- learned sketch (MLP) ----
+struct MlpLayout {
+    long long W1, b1, W2, b2, W3, b3, total;  // offsets in the flat parameter array
+};
+MlpLayout mlp_layout(int n, int h, int k);
+size_t mlp_ws_floats(int n, int h, int k, int B);
+hipError_t sgemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, float alpha, const float *A, long long lda,
+                 const float *B, long long ldb, float beta, float *C, long long ldc, float *part);
+hipError_t mlp_normalise(hipStream_t s, int n, int count, const double *b, long long ldb, float *x);
+hipError_t mlp_init(hipStream_t s, int n, int h, int k, const float *z, float *th);
+hipError_t mlp_forward(hipStream_t s, int n, int h, int k, int B, const float *th, const float *X, float *ws);
+hipError_t mlp_loss_grad(hipStream_t s, int n, int h, int k, int B, const float *th, const float *X,
+                         const float *S, const float *D, float *grad, float *ws, double *loss_per_sample);
+hipError_t mlp_adam(hipStream_t s, long long count, float *th, const float *g, float *m, float *v, int step, float lr,
+                    float b1, float b2, float eps);
+hipError_t mlp_to_bf16(hipStream_t s, long long count, const float *th, unsigned short *th16);
+hipError_t mlp_infer_bf16(hipStream_t s, int n, int h, int k, const unsigned short *th16, const double *b, double *Z,
+                          double *tmp);
 // y = bf16(x), round to nearest even.
 hipError_t launch_to_bf16(hipStream_t s, long long count, const double *x, unsigned short *y);
 

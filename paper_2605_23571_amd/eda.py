@@ -80,6 +80,17 @@ def lib():
             "eda_profile_read": [vp, ctypes.POINTER(i64), ctypes.POINTER(dbl)],
             "eda_destroy": [vp],
             "eda_set_geometry": [vp, i32, i32],
+            "eda_mlp_param_count": [vp, ctypes.POINTER(i64)],
+            "eda_mlp_workspace_bytes": [vp, i32, ctypes.POINTER(sz)],
+            "eda_mlp_init": [vp, vp, vp, vp],
+            "eda_mlp_forward": [vp, i32, vp, vp, vp, vp, sz, vp],
+            "eda_mlp_loss_grad": [vp, i32, vp, vp, vp, vp, vp, vp, sz, vp, ctypes.POINTER(dbl)],
+            "eda_mlp_adam": [i64, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                             ctypes.c_float, vp],
+            "eda_mlp_to_bf16": [i64, vp, vp, vp],
+            "eda_mlp_input": [vp, vp],
+            "eda_mlp_infer": [vp, vp, vp, vp],
+            "eda_sketch_learned": [vp, vp, vp, i32, i32, vp, vp, vp],
             "eda_strerror": [ctypes.c_int],
             "eda_batch_workspace_bytes": [vp, i32, ctypes.POINTER(sz)],
             "eda_batch_create": [vp, i32, vp, sz, vp, ctypes.POINTER(vp)],
@@ -290,6 +301,97 @@ def eda_batch_timing(batch) -> dict:
 
 def eda_batch_destroy(batch):
     _check("eda_batch_destroy", lib().eda_batch_destroy(batch))
+
+
+class eda_mlp_dims(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("hidden", ctypes.c_int32), ("k", ctypes.c_int32)]
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class MLP:
+    """The learned-sketch network's parameters on the GPU and its training
+    calls (FP32 forward/backward, Adam) and BF16 inference."""
+
+    def __init__(self, n: int, hidden: int = 256, k: int = 32, batch: int = 64):
+        torch = _torch()
+        self.dims = eda_mlp_dims(n, hidden, k)
+        cnt = ctypes.c_int64()
+        _check("eda_mlp_param_count", lib().eda_mlp_param_count(ctypes.byref(self.dims), ctypes.byref(cnt)))
+        self.count = cnt.value
+        self.batch = batch
+        wsb = ctypes.c_size_t()
+        _check("eda_mlp_workspace_bytes", lib().eda_mlp_workspace_bytes(ctypes.byref(self.dims), batch,
+                                                                        ctypes.byref(wsb)))
+        self.ws = torch.empty(wsb.value, dtype=torch.uint8, device="cuda")
+        self.params = torch.zeros(self.count, dtype=torch.float32, device="cuda")
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.step = 0
+
+    def init(self, normals):
+        torch = _torch()
+        z = torch.as_tensor(np.ascontiguousarray(normals, dtype=np.float32)).cuda()
+        _check("eda_mlp_init", lib().eda_mlp_init(ctypes.byref(self.dims), _ptr(z), _ptr(self.params), _stream()))
+
+    def forward(self, X):
+        torch = _torch()
+        B = X.shape[0]
+        assert B <= self.batch and X.dtype == torch.float32 and X.is_contiguous()
+        O = torch.empty((B, self.dims.k * self.dims.n), dtype=torch.float32, device="cuda")
+        _check("eda_mlp_forward", lib().eda_mlp_forward(ctypes.byref(self.dims), B, _ptr(self.params), _ptr(X),
+                                                        _ptr(O), _ptr(self.ws), self.ws.numel(), _stream()))
+        return O
+
+    def loss_grad(self, X, S, D, want_grad: bool = True) -> float:
+        """X: [B, n] FP32; S: [B, k, n] (column j of sample b = S[b, j]); D: [B, k]."""
+        B = X.shape[0]
+        assert B <= self.batch
+        loss = ctypes.c_double()
+        _check("eda_mlp_loss_grad", lib().eda_mlp_loss_grad(ctypes.byref(self.dims), B, _ptr(self.params), _ptr(X),
+                                                            _ptr(S), _ptr(D),
+                                                            _ptr(self.grad) if want_grad else None, _ptr(self.ws),
+                                                            self.ws.numel(), _stream(), ctypes.byref(loss)))
+        return loss.value
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self.step += 1
+        _check("eda_mlp_adam", lib().eda_mlp_adam(self.count, _ptr(self.params), _ptr(self.grad), _ptr(self.m),
+                                                  _ptr(self.v), self.step, lr, beta1, beta2, eps, _stream()))
+
+    def bf16(self):
+        torch = _torch()
+        p16 = torch.empty(self.count, dtype=torch.int16, device="cuda")
+        _check("eda_mlp_to_bf16", lib().eda_mlp_to_bf16(self.count, _ptr(self.params), _ptr(p16), _stream()))
+        return p16
+
+
+def mlp_input(problem) -> "torch.Tensor":
+    torch = _torch()
+    x = torch.empty(problem.n, dtype=torch.float32, device="cuda")
+    _check("eda_mlp_input", lib().eda_mlp_input(problem.ctx, _ptr(x)))
+    return x
+
+
+def mlp_infer(problem, dims: eda_mlp_dims, params16):
+    torch = _torch()
+    Z = torch.empty((dims.k, dims.n), dtype=torch.float64, device="cuda")
+    _check("eda_mlp_infer", lib().eda_mlp_infer(problem.ctx, ctypes.byref(dims), _ptr(params16), _ptr(Z)))
+    return Z
+
+
+def sketch_learned(problem, dims: eda_mlp_dims, params16, k: int, theta: str = "mid"):
+    """Returns (eigenvalues, theta, used_learned)."""
+    eig = np.zeros(k)
+    th = ctypes.c_double()
+    used = ctypes.c_int32()
+    _check("eda_sketch_learned", lib().eda_sketch_learned(problem.ctx, ctypes.byref(dims), _ptr(params16), k,
+                                                          THETA_RULES[theta], eig.ctypes.data_as(ctypes.c_void_p),
+                                                          ctypes.byref(th), ctypes.byref(used)))
+    return eig, th.value, bool(used.value)
 
 
 def _lowp_flag(mixed) -> int:

@@ -1,0 +1,126 @@
+"""Train the learned-sketch network on Ritz pairs the method computes (GPU).
+
+Data: problems of the n = 1024 preset (window 40 steps, every variable
+observed every 5 steps, B length scale 8) with problem ids from the training
+and validation ranges.  Input: the control right-hand side, normalised
+(eda_mlp_input).  Target: the control A's leading Ritz pairs from the q-pass
+Nystrom algorithm (q = 2, a seeded Gaussian sketch of 64 columns, truncated to
+k = 32) computed by eda_sketch_evd.  Only the control member is needed, so the
+data problems carry one perturbed member.
+
+Training: FP32 forward/backward and Adam in the library's kernels (eda_mlp_*),
+batch 64, learning rate 1e-3, He initialisation; the epoch with the lowest
+validation loss is kept and written as BF16 parameters (little-endian uint16,
+the flat parameter layout of include/eda.h) with a JSON description.
+
+  python -m paper_2605_23571_amd.train_sketch --train 20000 --val 500 --epochs 30 --out DIR
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+import workloads as W  # noqa: E402
+from paper_2605_23571_amd import eda  # noqa: E402
+
+N, HIDDEN, K, ELL_TARGET, Q_TARGET = 1024, 256, 32, 64, 2
+WEIGHTS = os.path.join(HERE, "weights", f"sketch_mlp_n{N}_h{HIDDEN}_k{K}")
+
+
+def make_samples(ids, log_every=1000):
+    """(X [m, n], S [m, k, n], D [m, k]) on the GPU for the given problem ids."""
+    import torch
+    m = len(ids)
+    X = torch.empty((m, N), dtype=torch.float32, device="cuda")
+    S = torch.empty((m, K, N), dtype=torch.float32, device="cuda")
+    D = torch.empty((m, K), dtype=torch.float32, device="cuda")
+    t0 = time.time()
+    for i, pid in enumerate(ids):
+        cfg = W.learned_problem(int(pid), members=1)
+        g = eda.Problem(cfg, W.problem_normals(cfg), max_ell=ELL_TARGET)
+        psi = torch.from_numpy(W.gaussian_matrix(cfg, N, ELL_TARGET)).cuda()
+        eig, _ = g.sketch_evd("user", ell=ELL_TARGET, k=K, q=Q_TARGET, phi=psi)
+        X[i] = eda.mlp_input(g)
+        S[i] = g.field("S")[: N * K].view(K, N).float()
+        D[i] = torch.from_numpy(eig).float().cuda()
+        g.close()
+        if (i + 1) % log_every == 0:
+            print(f"[train] samples {i + 1}/{m} ({time.time() - t0:.0f} s)", flush=True)
+    return X, S, D
+
+
+def mean_loss(net, X, S, D):
+    tot, cnt = 0.0, 0
+    for a in range(0, X.shape[0], net.batch):
+        b = min(X.shape[0], a + net.batch)
+        tot += net.loss_grad(X[a:b], S[a:b], D[a:b], want_grad=False) * (b - a)
+        cnt += b - a
+    return tot / cnt
+
+
+def main():
+    import torch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=20000)
+    ap.add_argument("--val", type=int, default=500)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--out", default=WEIGHTS)
+    a = ap.parse_args()
+    tr0, _ = W.LEARNED_SPLITS["train"]
+    va0, _ = W.LEARNED_SPLITS["val"]
+    Xt, St, Dt = make_samples(range(tr0, tr0 + a.train))
+    Xv, Sv, Dv = make_samples(range(va0, va0 + a.val))
+    net = eda.MLP(N, HIDDEN, K, batch=a.batch)
+    net.init(W.mlp_init_normals(net.count))
+    best, best_ep, hist = mean_loss(net, Xv, Sv, Dv), 0, []
+    best_params = net.params.clone()
+    print(f"[train] initial validation loss {best:.4f}", flush=True)
+    t0 = time.time()
+    for ep in range(1, a.epochs + 1):
+        order = torch.from_numpy(W.data_order(a.train, ep)).cuda()
+        tl = 0.0
+        for s in range(0, a.train - a.batch + 1, a.batch):
+            idx = order[s:s + a.batch]
+            tl += net.loss_grad(Xt[idx].contiguous(), St[idx].contiguous(), Dt[idx].contiguous())
+            net.adam(a.lr)
+        tl /= a.train // a.batch
+        vl = mean_loss(net, Xv, Sv, Dv)
+        hist.append((ep, tl, vl))
+        if vl < best:
+            best, best_ep = vl, ep
+            best_params.copy_(net.params)
+        print(f"[train] epoch {ep}: train {tl:.4f} val {vl:.4f} ({time.time() - t0:.0f} s)", flush=True)
+    net.params.copy_(best_params)
+    p16 = net.bf16().cpu().numpy().view(np.uint16)
+    os.makedirs(os.path.dirname(a.out), exist_ok=True)
+    p16.astype("<u2").tofile(a.out + ".bf16")
+    meta = {"n": N, "hidden": HIDDEN, "k": K, "params": int(net.count), "format": "bf16 little-endian, flat layout",
+            "train_ids": [tr0, tr0 + a.train - 1], "val_ids": [va0, va0 + a.val - 1],
+            "target": f"Nystrom q={Q_TARGET}, Gaussian sketch ell={ELL_TARGET}, k={K}", "epochs": a.epochs,
+            "batch": a.batch, "lr": a.lr, "best_epoch": best_ep, "best_val_loss": best,
+            "history": [{"epoch": e, "train": t, "val": v} for e, t, v in hist]}
+    with open(a.out + ".json", "w") as f:
+        json.dump(meta, f, indent=1)
+    print(f"[train] kept epoch {best_ep} (validation loss {best:.4f}); wrote {a.out}.bf16", flush=True)
+
+
+def load_bf16(path: str = WEIGHTS):
+    """(dims, params16 on the GPU) of a saved network, or None if absent."""
+    import torch
+    if not os.path.exists(path + ".bf16"):
+        return None
+    meta = json.load(open(path + ".json"))
+    p = np.fromfile(path + ".bf16", dtype="<u2").view(np.int16)
+    return eda.eda_mlp_dims(meta["n"], meta["hidden"], meta["k"]), torch.from_numpy(p.copy()).cuda()
+
+
+if __name__ == "__main__":
+    main()

@@ -100,3 +100,23 @@ def uneven_problems(count: int = 256, seed: int = 0) -> list[dict]:
                    len_b=2.0 if n == 40 else 8.0, seed=seed)
         out.append(c)
     return out
+
+
+def mlp_init_normals(count: int, seed: int = 0) -> np.ndarray:
+    """Standard normals for the learned-sketch network's initialisation
+    (stream 6), one per parameter."""
+    return _rng(seed, 0, 6).standard_normal(count).astype(np.float32)
+
+
+def data_order(count: int, epoch: int, seed: int = 0) -> np.ndarray:
+    """A permutation of the training samples for one epoch (stream 7)."""
+    return _rng(seed, epoch, 7).permutation(count)
+
+
+LEARNED_SPLITS = {"train": (1, 20000), "val": (20001, 20500), "test": (30001, 30256)}
+
+
+def learned_problem(problem_id: int, members: int = 64, seed: int = 0) -> dict:
+    """A problem of the n = 1024 preset for the learned sketch (train, validation
+    and test ids as in LEARNED_SPLITS)."""
+    return config("C2", members=members, ell=min(32, members), k=min(32, members), problem_id=problem_id, seed=seed)
