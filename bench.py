@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch (256 problems) measurement")
     ap.add_argument("--batch-problems", type=int, default=256)
     ap.add_argument("--batch-plain", type=int, default=64, help="problems timed through the per-problem path")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-sketch comparison")
+    ap.add_argument("--learned-problems", type=int, default=16)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration; untimed)")
     return ap.parse_args()
@@ -240,6 +242,46 @@ def run_uneven_batch(count, reps, plain_count):
                       "unit": "solves/s"}}
 
 
+def run_learned(count):
+    """Learned sketch vs the RHS-difference sketch on `count` test problems of
+    the n = 1024 preset (64 members): sketch + LMP-PCG of every member to rtol
+    1e-6 with each, timed; the committed BF16 network runs the inference."""
+    import torch
+    from paper_2605_23571_amd import eda
+    from paper_2605_23571_amd import train_sketch as T
+    net = T.load_bf16()
+    if net is None:
+        return None
+    dims, p16 = net
+    t0, _ = W.LEARNED_SPLITS["test"]
+    res = {"gamma": {"t": 0.0, "iters": []}, "learned": {"t": 0.0, "iters": []}}
+    used, solves = 0, 0
+    for pid in range(t0, t0 + count):
+        cfg = W.learned_problem(pid)
+        g = eda.Problem(cfg, W.problem_normals(cfg))
+        members = np.arange(cfg["members"] + 1)
+        for name in ("gamma", "learned"):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if name == "gamma":
+                g.sketch_evd("rhs_diff", ell=32, k=32)
+            else:
+                used += int(eda.sketch_learned(g, dims, p16, 32)[2])
+            out = g.pcg(members, rtol=1e-6, maxit=5000)
+            torch.cuda.synchronize()
+            res[name]["t"] += time.perf_counter() - t1
+            res[name]["iters"].append(out["iters"])
+        solves += members.size
+        g.close()
+    rep = {"problems": count, "learned_used": used, "member_solves": solves}
+    for name, r in res.items():
+        it = np.concatenate(r["iters"])
+        rep[name] = {"solves_per_s": round(solves / r["t"], 1), "iters_median": float(np.median(it)),
+                     "iters_mean": round(float(np.mean(it)), 1)}
+    rep["iteration_ratio_gamma_over_learned"] = round(rep["gamma"]["iters_mean"] / rep["learned"]["iters_mean"], 3)
+    return rep
+
+
 def cpu_baseline(cfg, z, target_s):
     """The CPU oracle (unchanged) on a bounded sample of the same workload: the
     Gamma-Nystrom sketch once, then LMP-PCG for members 0, 1, ... until about
@@ -330,6 +372,11 @@ def main():
     if not a.no_batch:
         print(f"[bench] uneven batch of {a.batch_problems} problems", file=sys.stderr, flush=True)
         line["uneven_batch"] = run_uneven_batch(a.batch_problems, max(1, a.steps), a.batch_plain)
+    if not a.no_learned:
+        print("[bench] learned sketch vs RHS differences (n = 1024 test problems)", file=sys.stderr, flush=True)
+        lr = run_learned(a.learned_problems)
+        if lr is not None:
+            line["learned_sketch"] = lr
     oracle_lmp = None
     if not a.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
