@@ -602,8 +602,35 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
     a.rtol = rtol;
     HIP_TRY(launch_pcg_init(s, a));
     if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n));
-    std::vector<int32_t> st(nm);
-    const int check_every = 8;
+    // Convergence checks are pipelined: every check_every iterations the status
+    // array is copied to a pinned host slot behind an event; the host reads a
+    // checkpoint once its event has completed, and waits only when more than
+    // max_ahead checkpoints are outstanding, so the GPU always has queued work.
+    // Iterations queued after every column stopped return at once.
+    const int check_every = 8, max_ahead = 2;
+    if (!c.h_ck) {
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&c.h_ck),
+                              sizeof(int32_t) * Ctx::CK_SLOTS * (size_t)c.max_cols, hipHostMallocDefault));
+        for (int i = 0; i < Ctx::CK_SLOTS; i++) HIP_TRY(hipEventCreateWithFlags(&c.ck_ev[i], hipEventDisableTiming));
+    }
+    int ck_issued = 0, ck_done = 0;
+    bool none_running = false;
+    auto consume = [&](bool block) -> int {  // read the oldest outstanding checkpoint
+        const int slot = ck_done % Ctx::CK_SLOTS;
+        if (block) {
+            HIP_TRY(hipEventSynchronize(c.ck_ev[slot]));
+        } else {
+            hipError_t q = hipEventQuery(c.ck_ev[slot]);
+            if (q == hipErrorNotReady) return 0;
+            if (q != hipSuccess) return EDA_ERR_HIP;
+        }
+        const int32_t *st = c.h_ck + (size_t)slot * c.max_cols;
+        bool running = false;
+        for (int i = 0; i < nm; i++) running |= (st[i] == COL_RUNNING);
+        none_running |= !running;
+        ck_done++;
+        return 1;
+    };
     const bool fused = c.cfg.ub_mode == EDA_UB_BANDED;
     bool stopped_early = false;
     if (!fused) HIP_TRY(launch_pcg_start(s, a));
@@ -642,15 +669,26 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                 HIP_TRY(launch_pcg_beta(s, a));
             }
             if (it % check_every == 0 || it == maxit) {
-                EDA_TRY(sync_read(c, st.data(), c.pc_status, sizeof(int32_t) * nm));
-                bool running = false;
-                for (int i = 0; i < nm; i++) running |= (st[i] == COL_RUNNING);
-                if (!running) {
+                if (ck_issued - ck_done >= Ctx::CK_SLOTS) EDA_TRY(consume(true));
+                const int slot = ck_issued % Ctx::CK_SLOTS;
+                HIP_TRY(hipMemcpyAsync(c.h_ck + (size_t)slot * c.max_cols, c.pc_status, sizeof(int32_t) * nm,
+                                       hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipEventRecord(c.ck_ev[slot], s));
+                ck_issued++;
+                int r;
+                while (ck_done < ck_issued && (r = consume(false)) == 1) {
+                }
+                if (ck_done < ck_issued) EDA_TRY(r);
+                while (ck_issued - ck_done > max_ahead) EDA_TRY(consume(true));
+                if (none_running) {
                     stopped_early = true;
                     break;
                 }
             }
         }
+        // the remaining checkpoints decide whether every column stopped
+        while (ck_done < ck_issued) EDA_TRY(consume(true));
+        stopped_early = none_running;
     }
     // the fused form tests r^T z for breakdown at the start of the next
     // iteration; after the last one that test runs here (as the textbook loop does)
@@ -743,6 +781,12 @@ int eda_set_geometry(eda_ctx *h, int32_t waves, int32_t tb) {
 int eda_destroy(eda_ctx *h) {
     if (!h) return EDA_ERR_INVALID_ARG;
     for (hipEvent_t e : h->c.ev) (void)hipEventDestroy(e);
+    if (h->c.h_ck) {
+        (void)hipStreamSynchronize(h->c.stream);
+        (void)hipHostFree(h->c.h_ck);
+        for (hipEvent_t e : h->c.ck_ev)
+            if (e) (void)hipEventDestroy(e);
+    }
     delete h;
     return EDA_OK;
 }

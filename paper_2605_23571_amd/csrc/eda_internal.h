@@ -57,7 +57,10 @@ struct Ctx {
     int32_t *pc_status = nullptr, *pc_iters = nullptr, *pc_members = nullptr;
     double *pc_hist = nullptr;
     int hist_cap = 0;
-    int32_t *h_pinned_status = nullptr;
+    // pipelined PCG convergence checks: pinned host slots and their events
+    static constexpr int CK_SLOTS = 4;
+    int32_t *h_ck = nullptr;  // CK_SLOTS x max_cols statuses (pinned host memory)
+    hipEvent_t ck_ev[CK_SLOTS] = {};
 
     // LMP state
     bool have_lmp = false;

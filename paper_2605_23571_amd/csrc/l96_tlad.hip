@@ -30,6 +30,8 @@
 // inside the workgroup (the column is in LDS), and TLAD_PCG performs a whole
 // PCG iteration for its member: p = z + beta p, q = (I + A) p, alpha, x and r
 // updates, the convergence test -- one launch in place of eight.
+#include <utility>
+
 #include "eda_internal.h"
 
 namespace eda {
@@ -99,19 +101,37 @@ __device__ __forceinline__ int wpos(int base, int q, int n) {
     return p >= n ? p - n : p;
 }
 
+// Copy i of a window: the instruction's immediate offset (applied to both the
+// global and the LDS address) carries 256 (i % 16) bytes; every 16 copies the
+// two bases advance by 4096 bytes, kept out of the 13-bit offset field.
+template <int I>
+__device__ __forceinline__ void lds_copy(const char *g, char *l) {
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)g,
+                                     (void __attribute__((address_space(3))) *)l, 4, 256 * (I % 16), 0);
+}
+template <int BASE, int... I>
+__device__ __forceinline__ void lds_copy_run(const char *g, char *l, std::integer_sequence<int, I...>) {
+    (lds_copy<BASE + I>(g, l), ...);
+}
+
 // Start the asynchronous copy of this wave's trajectory window -- 64 Q
 // consecutive doubles of a padded state row, from xe on -- into the wave's LDS
 // slice: 2Q direct global-to-LDS dword copies, lane l of copy i moving dword
 // 64 i + l, so slice[j] = xe[j].  No registers are held while it is in flight.
 template <int Q>
 __device__ __forceinline__ void prefetch_window(const double *xe, double *slice) {
+    static_assert(2 * Q <= 32, "window copies: two runs of at most 16");
     const int lane = threadIdx.x & 63;
     const char *g = reinterpret_cast<const char *>(xe) + 4 * lane;
     char *l = reinterpret_cast<char *>(slice);
-#pragma unroll
-    for (int i = 0; i < 2 * Q; i++)
-        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(g + 256 * i),
-                                         (void __attribute__((address_space(3))) *)(l + 256 * i), 4, 0, 0);
+    constexpr int R0 = 2 * Q < 16 ? 2 * Q : 16;
+    lds_copy_run<0>(g, l, std::make_integer_sequence<int, R0>{});
+    if constexpr (2 * Q > 16) {
+        const char *g2 = g + 4096;
+        char *l2 = l + 4096;
+        asm volatile("" : "+v"(g2));  // opaque: the 4096 stays in the base, not the offset field
+        lds_copy_run<16>(g2, l2, std::make_integer_sequence<int, 2 * Q - 16>{});
+    }
 }
 
 // This lane's Q window points from the wave's slice, once the copy has landed
