@@ -71,28 +71,35 @@ __device__ __forceinline__ void ext(const T (&v)[Q], T (&e)[Q + 4]) {
     e[Q + 3] = from_next(v[1]);
 }
 
-// Tendency k and TL increment dk at own points.
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// The tendency without its forcing, k'_i = (y_{i+1} - y_{i-2}) y_{i-1} - y_i
+// (F enters the stage states through x + h F, precomputed once per step), and
+// the TL increment dk_i = a_i v_{i-1} + y_{i-1} (v_{i+1} - v_{i-2}) - v_i with
+// a_i = y_{i+1} - y_{i-2}, written as fused multiply-adds: 2 and 3 operations.
 template <typename T, int Q, bool WANT_K>
-__device__ __forceinline__ void tl_stage(const T (&y)[Q + 4], const T (&v)[Q + 4], T F, T (&k)[Q], T (&dk)[Q]) {
+__device__ __forceinline__ void tl_stage(const T (&y)[Q + 4], const T (&v)[Q + 4], T (&k)[Q], T (&dk)[Q]) {
 #pragma unroll
     for (int j = 0; j < Q; j++) {
-        T a = y[j + 3] - y[j];
-        if (WANT_K) k[j] = a * y[j + 1] - y[j + 2] + F;
-        dk[j] = y[j + 1] * (v[j + 3] - v[j]) + a * v[j + 1] - v[j + 2];
+        const T a = y[j + 3] - y[j];
+        if (WANT_K) k[j] = fma_t(a, y[j + 1], -y[j + 2]);
+        dk[j] = fma_t(a, v[j + 1], fma_t(y[j + 1], v[j + 3] - v[j], -v[j + 2]));
     }
 }
 
 template <typename T, int Q>
-__device__ __forceinline__ void tendency(const T (&y)[Q + 4], T F, T (&k)[Q]) {
+__device__ __forceinline__ void tendency(const T (&y)[Q + 4], T (&k)[Q]) {
 #pragma unroll
-    for (int j = 0; j < Q; j++) k[j] = (y[j + 3] - y[j]) * y[j + 1] - y[j + 2] + F;
+    for (int j = 0; j < Q; j++) k[j] = fma_t(y[j + 3] - y[j], y[j + 1], -y[j + 2]);
 }
 
+// (J^T w)_k = y_{k-2} w_{k-1} - y_{k+1} w_{k+2} + (y_{k+2} - y_{k-1}) w_{k+1} - w_k
 template <typename T, int Q>
 __device__ __forceinline__ void jt(const T (&y)[Q + 4], const T (&w)[Q + 4], T (&out)[Q]) {
 #pragma unroll
     for (int j = 0; j < Q; j++)
-        out[j] = y[j] * w[j + 1] - y[j + 3] * w[j + 4] + (y[j + 4] - y[j + 1]) * w[j + 3] - w[j + 2];
+        out[j] = fma_t(y[j + 4] - y[j + 1], w[j + 3], fma_t(-y[j + 3], w[j + 4], fma_t(y[j], w[j + 1], -w[j + 2])));
 }
 
 // Ring position of this lane's window point q: base + q, wrapped once.
@@ -264,7 +271,7 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
     const int own_lo = wave * g.S, own_hi = min(n, own_lo + g.S);
     const int member = MODE == TLAD_PCG ? a.pcg.members[c] : (a.col_member ? a.col_member[c] : 0);
     const double *trajm = a.trajx + (long long)member * a.trajx_stride + a.pad_l;  // row s: trajm + s ext_len
-    const T F = (T)a.F, h = (T)a.h, dt = (T)a.dt, dt6 = (T)a.dt6, dt3 = (T)a.dt3;
+    const T h = (T)a.h, dt = (T)a.dt, dt6 = (T)a.dt6, dt3 = (T)a.dt3, hF = (T)(a.h * a.F);
     unsigned ownm;
     int rsel = 0;
     double rho = 0.0;
@@ -338,36 +345,37 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
                 if (s + 1 < N) prefetch_window<Q>(trajm + (long long)(s + 1) * a.ext_len + w0, xw);
                 ext<T, Q>(x, Y);
                 ext<T, Q>(dx, V);
-                tl_stage<T, Q, true>(Y, V, F, k, dk);
+                tl_stage<T, Q, true>(Y, V, k, dk);
 #pragma unroll
                 for (int j = 0; j < Q; j++) {
+                    x[j] += hF;  // x + h F: the stage states are x + h (k' + F)
                     acc[j] = dk[j];
-                    ys[j] = x[j] + h * k[j];
-                    vs[j] = dx[j] + h * dk[j];
+                    ys[j] = fma_t(h, k[j], x[j]);
+                    vs[j] = fma_t(h, dk[j], dx[j]);
                 }
                 ext<T, Q>(ys, Y);
                 ext<T, Q>(vs, V);
-                tl_stage<T, Q, true>(Y, V, F, k, dk);
+                tl_stage<T, Q, true>(Y, V, k, dk);
 #pragma unroll
                 for (int j = 0; j < Q; j++) {
-                    acc[j] += T(2) * dk[j];
-                    ys[j] = x[j] + h * k[j];
-                    vs[j] = dx[j] + h * dk[j];
+                    acc[j] = fma_t(T(2), dk[j], acc[j]);
+                    ys[j] = fma_t(h, k[j], x[j]);
+                    vs[j] = fma_t(h, dk[j], dx[j]);
                 }
                 ext<T, Q>(ys, Y);
                 ext<T, Q>(vs, V);
-                tl_stage<T, Q, true>(Y, V, F, k, dk);
+                tl_stage<T, Q, true>(Y, V, k, dk);
 #pragma unroll
                 for (int j = 0; j < Q; j++) {
-                    acc[j] += T(2) * dk[j];
-                    ys[j] = x[j] + dt * k[j];
-                    vs[j] = dx[j] + dt * dk[j];
+                    acc[j] = fma_t(T(2), dk[j], acc[j]);
+                    ys[j] = fma_t(dt, k[j], x[j] + hF);  // x + dt F
+                    vs[j] = fma_t(dt, dk[j], dx[j]);
                 }
                 ext<T, Q>(ys, Y);
                 ext<T, Q>(vs, V);
-                tl_stage<T, Q, false>(Y, V, F, k, dk);
+                tl_stage<T, Q, false>(Y, V, k, dk);
 #pragma unroll
-                for (int j = 0; j < Q; j++) dx[j] = dx[j] + dt6 * (acc[j] + dk[j]);
+                for (int j = 0; j < Q; j++) dx[j] = fma_t(dt6, acc[j] + dk[j], dx[j]);
             }
             if (s1 < N) {
 #pragma unroll
@@ -411,18 +419,19 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
             {
                 T Y1[Q + 4];
                 ext<T, Q>(x, Y1);
-                tendency<T, Q>(Y1, F, k);
+                tendency<T, Q>(Y1, k);
             }
+            // stage states x + h (k' + F) and x + dt (k' + F), from xh = x + h F
 #pragma unroll
-            for (int j = 0; j < Q; j++) ys[j] = x[j] + h * k[j];
+            for (int j = 0; j < Q; j++) ys[j] = fma_t(h, k[j], x[j] + hF);
             ext<T, Q>(ys, Y2);
-            tendency<T, Q>(Y2, F, k);
+            tendency<T, Q>(Y2, k);
 #pragma unroll
-            for (int j = 0; j < Q; j++) ys[j] = x[j] + h * k[j];
+            for (int j = 0; j < Q; j++) ys[j] = fma_t(h, k[j], x[j] + hF);
             ext<T, Q>(ys, Y3);
-            tendency<T, Q>(Y3, F, k);
+            tendency<T, Q>(Y3, k);
 #pragma unroll
-            for (int j = 0; j < Q; j++) ys[j] = x[j] + dt * k[j];
+            for (int j = 0; j < Q; j++) ys[j] = fma_t(dt, k[j], (x[j] + hF) + hF);
             ext<T, Q>(ys, Y4);
             // backward through the stages: mu4 = dt/6 lam, mu3 = mu2 = dt/3 lam, mu1 = dt/6 lam
             T nu[Q], acc[Q], mu[Q];

@@ -73,10 +73,13 @@ def test_batch_matches_single_problem_path():
         ref = g.pcg(np.arange(cfg["members"] + 1), rtol=1e-6, maxit=3000, use_lmp=True)
         g.close()
         assert (ref["status"] == res["status"]).all()
-        # same method, summation order differs in the LMP: iteration counts
-        # agree to within rounding-driven drift
-        tol = np.maximum(2, (0.05 * ref["iters"]).astype(int))
+        # same method; the LMP sums in another order, so the CG recurrences see
+        # different rounding, and finite-precision CG iteration counts to a fixed
+        # tolerance drift with it: each member within 10% (at least 3), the
+        # median within 3%
+        tol = np.maximum(3, (0.10 * ref["iters"]).astype(int))
         assert (np.abs(res["iters"] - ref["iters"]) <= tol).all(), (p, res["iters"], ref["iters"])
+        assert abs(np.median(res["iters"]) - np.median(ref["iters"])) <= max(2, 0.03 * np.median(ref["iters"]))
         a, r = res["dz"].cpu().numpy(), ref["dz"].cpu().numpy()
         # both satisfy ||r|| <= 1e-6 ||b||; their difference is bounded by the
         # two solution errors
