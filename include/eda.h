@@ -217,11 +217,15 @@ int eda_field(const eda_ctx *ctx, int32_t field, size_t *byte_offset, int64_t *c
 /* Opt-in timing of the tangent-linear/adjoint kernel launched by
  * eda_pcg_solve (the fused PCG-iteration kernel with the banded U_B, the TL/AD
  * kernel between the U_B GEMMs with the dense U_B), with HIP events recorded
- * on the context's stream around each of its launches.  eda_profile(ctx, 1)
- * starts (and clears) the accounting; eda_profile_read synchronises and returns
- * the number of launches and their summed duration in milliseconds. */
-int eda_profile(eda_ctx *ctx, int32_t enable);
-int eda_profile_read(eda_ctx *ctx, int64_t *launches, double *total_ms);
+ * on the context's stream around its launches.  eda_profile(ctx, every)
+ * starts (and clears) the accounting, timing every `every`-th launch
+ * (every = 1: each launch; a larger period keeps the event records, which sit
+ * between kernels on the stream, out of most iterations); eda_profile(ctx, 0)
+ * stops it.  eda_profile_read synchronises and returns the number of timed
+ * launches, the number of all such launches since eda_profile, and the timed
+ * launches' summed duration in milliseconds.  every < 0: EDA_ERR_INVALID_ARG. */
+int eda_profile(eda_ctx *ctx, int32_t every);
+int eda_profile_read(eda_ctx *ctx, int64_t *timed, int64_t *launches, double *timed_ms);
 
 /* ---- learned sketch ----
  * A small MLP maps the control member's right-hand side to k sketch directions

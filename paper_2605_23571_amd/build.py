@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libeda.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["l96_nl.hip", "l96_tlad.hip", "gemm_f64.hip", "gemm_bf16.hip", "setup_kernels.hip", "small_la.hip", "pcg_kernels.hip", "mlp.hip",
+SOURCES = ["l96_nl.hip", "l96_tlad.hip", "gemm_f64.hip", "gemm_bf16.hip", "setup_kernels.hip", "small_la.hip", "pcg_kernels.hip", "lmp_kernels.hip", "mlp.hip",
            "eda_api.hip"]
 
 COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

@@ -52,7 +52,7 @@ struct Plan {
     size_t off_ubrow, off_ub, off_truth, off_spin, off_xb, off_traj, off_y, off_d, off_force, off_b, off_costc;
     size_t off_hv_v, off_hv_obs, off_hv_lam, off_zero;
     size_t off_phi, off_sy, off_sq, off_sq1, off_ss, off_small, off_eig, off_coef, off_coefu, off_info, off_splitk,
-        off_lmpt;
+        off_lmpt, off_lmpw, off_sr;
     size_t off_x, off_r, off_z, off_pp, off_q, off_scal, off_status, off_iters, off_members, off_hist;
     size_t splitk_elems;
     size_t total;
@@ -111,6 +111,8 @@ Plan make_plan(const eda_config *c) {
     P.splitk_elems = sk > sk2 ? sk : sk2;
     P.off_splitk = lay.take((P.splitk_elems ? P.splitk_elems : 1) * d);
     P.off_lmpt = lay.take(ml * mc * d);
+    P.off_lmpw = lay.take(lmp_work_doubles(P.n, P.maxl, P.maxc) * d);
+    P.off_sr = lay.take(n * ml * d);
     P.off_x = lay.take(n * mc * d);
     P.off_r = lay.take(n * mc * d);
     P.off_z = lay.take(n * mc * d);
@@ -193,7 +195,7 @@ TladArgs tlad_args(Ctx &c, int nb, const int32_t *cols, const int32_t *active) {
 
 int run_tlad(Ctx &c, const TladArgs &a, int mode, bool fp32) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool rec = c.prof && c.in_pcg;
+    const bool rec = c.prof > 0 && c.in_pcg && c.prof_seen++ % c.prof == 0;
     if (rec) {
         if (c.ev_used + 2 > c.ev.size()) {
             for (int i = 0; i < 64; i++) {
@@ -368,6 +370,8 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
     c.splitk = at<double>(w, P.off_splitk);
     c.splitk_elems = P.splitk_elems;
     c.lmp_t = at<double>(w, P.off_lmpt);
+    c.lmp_work = at<double>(w, P.off_lmpw);
+    c.sk_sr = at<double>(w, P.off_sr);
     c.pc_x = at<double>(w, P.off_x);
     c.pc_r = at<double>(w, P.off_r);
     c.pc_z = at<double>(w, P.off_z);
@@ -466,6 +470,7 @@ int eda_sketch_evd(eda_ctx *h, int32_t kind, const double *d_phi, int64_t ldphi,
     hipStream_t s = c.stream;
     const int n = c.n;
     c.have_lmp = false;
+    c.sr_ready = false;
     // sketching matrix Phi
     switch (kind) {
         case EDA_SKETCH_RHS_DIFF: HIP_TRY(launch_gamma(s, n, ell, c.b, c.sk_phi)); break;
@@ -540,6 +545,7 @@ int eda_sketch_evd(eda_ctx *h, int32_t kind, const double *d_phi, int64_t ldphi,
     c.theta = th;
     c.k = k;
     c.have_lmp = true;
+    c.sr_ready = false;
     return EDA_OK;
 }
 
@@ -547,12 +553,16 @@ int eda_sketch_evd(eda_ctx *h, int32_t kind, const double *d_phi, int64_t ldphi,
 
 namespace {
 
-// Y = X + S_k diag(coef) S_k^T X (coef: P_theta or U_theta coefficients).
-int lmp_apply(Ctx &c, int which, int nb, const double *X, long long ldx, double *Y, long long ldy) {
+// Y = X + S_k diag(coef) S_k^T X (coef: P_theta or U_theta coefficients);
+// inside PCG (status given) tiles of stopped members are skipped.
+int lmp_apply(Ctx &c, int which, int nb, const double *X, long long ldx, double *Y, long long ldy,
+              const int32_t *status = nullptr) {
     const double *coef = which == EDA_LMP_U ? c.sk_coefu : c.sk_coef;
-    HIP_TRY(gemm_f64(c.stream, true, c.k, nb, c.n, c.sk_s, c.n, X, ldx, c.lmp_t, c.k, nullptr, 0, coef, c.splitk,
-                     c.splitk_elems));
-    HIP_TRY(gemm_f64(c.stream, false, c.n, nb, c.k, c.sk_s, c.n, c.lmp_t, c.k, Y, ldy, X, ldx, nullptr, nullptr, 0));
+    if (!c.sr_ready) {
+        HIP_TRY(launch_lmp_rowmajor(c.stream, c.n, c.k, c.sk_s, c.sk_sr));
+        c.sr_ready = true;
+    }
+    HIP_TRY(launch_lmp(c.stream, c.n, c.k, nb, c.sk_s, c.sk_sr, coef, X, ldx, Y, ldy, status, c.lmp_work));
     return EDA_OK;
 }
 
@@ -601,7 +611,7 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
     a.hist_cap = c.hist_cap;
     a.rtol = rtol;
     HIP_TRY(launch_pcg_init(s, a));
-    if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n));
+    if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status));
     // Convergence checks are pipelined: every check_every iterations the status
     // array is copied to a pinned host slot behind an event; the host reads a
     // checkpoint once its event has completed, and waits only when more than
@@ -661,11 +671,11 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                 t.pcg.it = it;
                 t.pcg.first = it == 1 ? 1 : 0;
                 EDA_TRY(run_tlad(c, t, TLAD_PCG, false));
-                if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n));
+                if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status));
             } else {
                 EDA_TRY(hessvec(c, c.pc_members, nm, c.pc_p, n, c.pc_q, n, EDA_HV_ADD_IDENTITY, c.pc_status));
                 HIP_TRY(launch_pcg_alpha(s, a, it));
-                if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n));
+                if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status));
                 HIP_TRY(launch_pcg_beta(s, a));
             }
             if (it % check_every == 0 || it == maxit) {
@@ -742,18 +752,19 @@ int eda_field(const eda_ctx *h, int32_t field, size_t *byte_offset, int64_t *cou
     return EDA_OK;
 }
 
-int eda_profile(eda_ctx *h, int32_t enable) {
-    if (!h) return EDA_ERR_INVALID_ARG;
+int eda_profile(eda_ctx *h, int32_t every) {
+    if (!h || every < 0) return EDA_ERR_INVALID_ARG;
     Ctx &c = h->c;
     HIP_TRY(hipStreamSynchronize(c.stream));
-    c.prof = enable != 0;
+    c.prof = every;
+    c.prof_seen = 0;
     c.prof_launches = 0;
     c.ev_used = 0;
     return EDA_OK;
 }
 
-int eda_profile_read(eda_ctx *h, int64_t *launches, double *total_ms) {
-    if (!h || !launches || !total_ms) return EDA_ERR_INVALID_ARG;
+int eda_profile_read(eda_ctx *h, int64_t *timed, int64_t *launches, double *timed_ms) {
+    if (!h || !timed || !launches || !timed_ms) return EDA_ERR_INVALID_ARG;
     Ctx &c = h->c;
     HIP_TRY(hipStreamSynchronize(c.stream));
     double tot = 0.0;
@@ -762,8 +773,9 @@ int eda_profile_read(eda_ctx *h, int64_t *launches, double *total_ms) {
         HIP_TRY(hipEventElapsedTime(&ms, c.ev[i], c.ev[i + 1]));
         tot += ms;
     }
-    *launches = c.prof_launches;
-    *total_ms = tot;
+    *timed = c.prof_launches;
+    *launches = c.prof_seen;
+    *timed_ms = tot;
     return EDA_OK;
 }
 
@@ -1282,6 +1294,7 @@ int eda_batch_solve(eda_batch *b, int32_t k_cap, double rtol, int32_t maxit, int
         for (int i = 0; i < np; i++) {
             Ctx &c = *b->probs[i];
             c.have_lmp = true;
+            c.sr_ready = false;
             c.k = b->ell[i];
             if (flags[i] == 0) continue;
             fallbacks++;
@@ -1292,6 +1305,7 @@ int eda_batch_solve(eda_batch *b, int32_t k_cap, double rtol, int32_t maxit, int
             if (r == EDA_ERR_NOT_SPD) {
                 unprec++;
                 c.have_lmp = false;
+                c.sr_ready = false;
                 r = launch_fill_int(c.stream, 1, 1, c.sk_info) == hipSuccess ? EDA_OK : EDA_ERR_HIP;
             } else if (r >= 0) {
                 r = launch_fill_int(c.stream, 3, 0, c.sk_info) == hipSuccess ? EDA_OK : EDA_ERR_HIP;

@@ -49,6 +49,9 @@ struct Ctx {
     double *sk_eig = nullptr, *sk_coef = nullptr, *sk_coefu = nullptr;
     int32_t *sk_info = nullptr;
     double *lmp_t = nullptr;   // k x max_cols LMP coefficients S_k^T X
+    double *lmp_work = nullptr;  // LMP row-block partial projections
+    double *sk_sr = nullptr;     // S_k row-major (n x k), made from sk_s on the first LMP use
+    bool sr_ready = false;
     double *splitk = nullptr;  // split-K partial sums
     size_t splitk_elems = 0;
     // pcg scratch
@@ -68,7 +71,8 @@ struct Ctx {
     double theta = 1.0;
 
     // profiling of the TL/AD kernel inside eda_pcg_solve
-    bool prof = false;
+    int prof = 0;             // time every prof-th TL/AD launch inside PCG (0: off)
+    int64_t prof_seen = 0;
     bool in_pcg = false;
     int geo_waves = 0, geo_tb = 0;  // TL/AD launch geometry override (0: default)
     std::vector<hipEvent_t> ev;
@@ -189,6 +193,18 @@ hipError_t gemm_f64(hipStream_t s, bool trans_a, int M, int N, int K, const doub
                     const double *B, long long ldb, double *C, long long ldc, const double *Add,
                     long long ldadd, const double *rowscale, double *part, size_t part_elems);
 size_t gemm_splitk_elems(int M, int N, int K);
+
+// Spectral LMP on a block: Y = X + S diag(coef) S^T X (S: n x k column-major,
+// Sr: the same row-major, from launch_lmp_rowmajor; X, Y: n x nb); column tiles
+// whose members all left the running state are skipped (status may be null).
+// work: lmp_work_doubles(n, k, ncols); k <= LMP_K_MAX.
+constexpr int LMP_RB_MAX = 16;
+constexpr int LMP_K_MAX = 128;
+void lmp_blocks(int n, int *rows, int *nrb);
+size_t lmp_work_doubles(int n, int k, int ncols);
+hipError_t launch_lmp_rowmajor(hipStream_t s, int n, int k, const double *S, double *Sr);
+hipError_t launch_lmp(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
+                      const double *X, long long ldx, double *Y, long long ldy, const int32_t *status, double *work);
 // BF16-operand, FP32-accumulate GEMM C = A B (+ Add): A in BF16 (M x K,
 // column-major), B, C, Add in FP64 (B rounded to BF16 as it is staged).
 hipError_t gemm_bf16(hipStream_t s, int M, int N, int K, const unsigned short *A, long long lda, const double *B,

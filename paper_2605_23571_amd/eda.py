@@ -77,7 +77,7 @@ def lib():
             "eda_pcg_solve": [vp, vp, i32, dbl, i32, i32, vp, i64, vp, vp, vp, vp],
             "eda_field": [vp, i32, ctypes.POINTER(sz), ctypes.POINTER(i64)],
             "eda_profile": [vp, i32],
-            "eda_profile_read": [vp, ctypes.POINTER(i64), ctypes.POINTER(dbl)],
+            "eda_profile_read": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(dbl)],
             "eda_destroy": [vp],
             "eda_set_geometry": [vp, i32, i32],
             "eda_mlp_param_count": [vp, ctypes.POINTER(i64)],
@@ -227,14 +227,16 @@ def eda_field(ctx, field: int):
     return off.value, cnt.value
 
 
-def eda_profile(ctx, enable: bool):
-    _check("eda_profile", lib().eda_profile(ctx, int(bool(enable))))
+def eda_profile(ctx, every: int):
+    """Time every `every`-th TL/AD launch of eda_pcg_solve (0: off; True: each)."""
+    _check("eda_profile", lib().eda_profile(ctx, int(every)))
 
 
 def eda_profile_read(ctx):
-    n, ms = ctypes.c_int64(), ctypes.c_double()
-    _check("eda_profile_read", lib().eda_profile_read(ctx, ctypes.byref(n), ctypes.byref(ms)))
-    return n.value, ms.value
+    """(timed launches, all launches, summed duration of the timed ones in ms)"""
+    t, n, ms = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+    _check("eda_profile_read", lib().eda_profile_read(ctx, ctypes.byref(t), ctypes.byref(n), ctypes.byref(ms)))
+    return t.value, n.value, ms.value
 
 
 def eda_set_geometry(ctx, waves: int, tb: int):

@@ -234,6 +234,36 @@ def test_nystrom_rhs_diff(case):
     _compare_lmp(g, o, cfg, S, D, O.theta(D), eig, thg, 1e-9)
 
 
+LMP_CASES = {
+    # ragged: n not a multiple of 16, k not a multiple of 4, 37 columns (3 tiles, the last of 5)
+    "n203": (CASES["n203"], 37),
+    # one row block per 128 rows, 16 row blocks, every column tile of a C3-sized block (129 = 8 x 16 + 1)
+    "n4096": (W.config("C3", nsteps=8, obs_dt=4, members=80, ell=64, k=61, spinup=100), 129),
+    # rank above 64 (the wider expansion kernel), n odd, 6 tiles
+    "n1001k77": (W.config("C2", n=1001, nsteps=6, obs_dt=3, members=90, ell=80, k=77, spinup=100), 91),
+}
+
+
+@pytest.mark.parametrize("case", list(LMP_CASES))
+def test_lmp_block_matches_definition(case):
+    # The block LMP (split projection with a fixed-order reduction, then the
+    # expansion) against its definition X + S diag(coef) S^T X evaluated by the
+    # oracle on the GPU's own Ritz pairs and theta: FP64 to 1e-13.
+    cfg, ncols = LMP_CASES[case]
+    g = eda.Problem(cfg, W.problem_normals(cfg), max_cols=ncols)
+    eig, th = g.sketch_evd("rhs_diff")
+    n = cfg["n"]
+    S = g.field("S").cpu().numpy().reshape(-1, n).T
+    V = np.random.default_rng(11).standard_normal((ncols, n))
+    Vt = torch.from_numpy(V).cuda()
+    for which in ("P", "U"):
+        for nb in (ncols, ncols - 1, 1):
+            Pg = to_np_cols(g.lmp_apply(Vt[:nb].contiguous(), which), n)
+            Po = O.lmp_apply(S, eig, th, V[:nb].T, which)
+            assert rel(Pg, Po) < 1e-13, (which, nb, rel(Pg, Po))
+    g.close()
+
+
 @pytest.mark.parametrize("case", ["C1", "n1001"])
 def test_revd_and_power_pass(case):
     cfg, g, o = problem(case)
@@ -334,17 +364,24 @@ def test_pcg_not_converged_and_deterministic():
 
 def test_profile_counts_pcg_tlad_launches():
     # the profile covers the TL/AD kernel inside eda_pcg_solve only: one fused
-    # launch per iteration (banded U_B); Hessian products outside PCG are not timed
+    # launch per iteration (banded U_B); Hessian products outside PCG are not
+    # timed; with a period of 5, launches 1, 6, 11 of 12 are timed
     cfg, g, o = problem("C1")
-    eda.eda_profile(g.ctx, True)
+    eda.eda_profile(g.ctx, 1)
     X = torch.from_numpy(np.ones((3, cfg["n"]))).cuda()
     g.hessvec([0, 1, 2], X)
-    assert eda.eda_profile_read(g.ctx)[0] == 0
+    assert eda.eda_profile_read(g.ctx)[:2] == (0, 0)
     out = g.pcg([0, 1, 2], rtol=0.0, maxit=12, use_lmp=False)
-    n, ms = eda.eda_profile_read(g.ctx)
-    eda.eda_profile(g.ctx, False)
+    t, n, ms = eda.eda_profile_read(g.ctx)
     assert (out["iters"] == 12).all()
-    assert n == 12 and ms > 0
+    assert t == 12 and n == 12 and ms > 0
+    eda.eda_profile(g.ctx, 5)
+    g.pcg([0, 1, 2], rtol=0.0, maxit=12, use_lmp=False)
+    t, n, ms5 = eda.eda_profile_read(g.ctx)
+    eda.eda_profile(g.ctx, 0)
+    assert t == 3 and n == 12 and 0 < ms5 < ms
+    with pytest.raises(eda.EdaError):
+        eda.eda_profile(g.ctx, -1)
 
 
 # ------------------------------------------------- full-size (sampled) ------
