@@ -289,6 +289,21 @@ int eda_sketch_learned(eda_ctx *ctx, const eda_mlp_dims *dims, const uint16_t *d
  * among these.  Errors: EDA_ERR_UNSUPPORTED for a geometry n does not admit. */
 int eda_set_geometry(eda_ctx *ctx, int32_t waves, int32_t tb);
 
+/* Pieces per member column in the iterations of eda_pcg_solve with the banded
+ * U_B and the LMP.  The Hessian part of such an iteration runs on P pieces of
+ * every running column, one workgroup each: a piece integrates its share of
+ * the n states plus a halo of 12 N + 2 w states on each side (w the half-width
+ * of the banded U_B), the reach of the TL/AD runs over the window and of U_B
+ * on both ends, so its own outputs are exact; the pieces' partial sums of
+ * p^T (I + A) p are added in piece order.  pieces = 0 (the default): P is the
+ * largest of 1, 2, 4, 8 with P x (members still running at the last
+ * convergence check) <= the device's compute units; 1, 2, 4 or 8: that P in
+ * every iteration.  Solutions agree with P = 1 to rounding.  Errors:
+ * EDA_ERR_UNSUPPORTED if the context is not banded, or P > 1 pieces do not fit
+ * n (ring of ceil(n / P) + 2 halo states longer than n, or a window wider than
+ * the kernel supports); EDA_ERR_INVALID_ARG for other values. */
+int eda_set_split(eda_ctx *ctx, int32_t pieces);
+
 /* Free the context's host structures (the workspace stays the caller's). */
 int eda_destroy(eda_ctx *ctx);
 

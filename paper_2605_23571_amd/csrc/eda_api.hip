@@ -54,9 +54,25 @@ struct Plan {
     size_t off_phi, off_sy, off_sq, off_sq1, off_ss, off_small, off_eig, off_coef, off_coefu, off_info, off_splitk,
         off_lmpt, off_lmpw, off_sr;
     size_t off_x, off_r, off_z, off_pp, off_q, off_scal, off_status, off_iters, off_members, off_hist;
+    size_t off_p2, off_pqp, off_fin;  // split PCG iterations (banded U_B)
     size_t splitk_elems;
     size_t total;
 };
+
+// Banded U_B taps: offsets o with r(|o|) > 2^-60 r(0), i.e. o^2 < 60 ln 2 len^2,
+// clipped to one full period of the ring.
+void band_taps(int n, double len_b, int &lo, int &hi) {
+    const double lim = 60.0 * std::log(2.0) * len_b * len_b;
+    int w = 0;
+    while (w + 1 <= n / 2 && (double)(w + 1) * (w + 1) < lim) w++;
+    if (2 * w + 1 >= n) {
+        lo = -((n - 1) / 2);
+        hi = n / 2;
+    } else {
+        lo = -w;
+        hi = w;
+    }
+}
 
 Plan make_plan(const eda_config *c) {
     Plan P{};
@@ -80,9 +96,15 @@ Plan make_plan(const eda_config *c) {
     P.off_spin = lay.take(n * d);
     P.off_xb = lay.take(n * L1 * d);
     P.off_traj = lay.take(L1 * (P.N + 1) * n * d);
+    const bool banded = c->ub_mode == EDA_UB_BANDED;
+    int band_lo, band_hi;
+    band_taps(P.n, c->len_b, band_lo, band_hi);
     {
         int pl, pr;
-        tlad_pads(P.n, &pl, &pr);
+        if (banded)
+            tlad_pads_split(P.n, P.N, band_hi, &pl, &pr);
+        else
+            tlad_pads(P.n, &pl, &pr);
         P.pad_l = pl;
         P.ext_len = ((P.n + pl + pr + 31) / 32) * 32;
     }
@@ -93,7 +115,7 @@ Plan make_plan(const eda_config *c) {
     P.off_b = lay.take(n * L1 * d);
     P.off_costc = lay.take(L1 * d);
     P.off_hv_v = lay.take(n * mc * d);
-    P.off_hv_obs = lay.take(p * mc * d);
+    P.off_hv_obs = lay.take(p * mc * (banded ? SPLIT_PMAX : 1) * d);  // split: one block per piece
     P.off_hv_lam = lay.take(n * mc * d);
     P.off_zero = lay.take(mc * sizeof(int32_t));
     P.off_phi = lay.take(n * ml * d);
@@ -123,6 +145,9 @@ Plan make_plan(const eda_config *c) {
     P.off_iters = lay.take(mc * sizeof(int32_t));
     P.off_members = lay.take(mc * sizeof(int32_t));
     P.off_hist = lay.take(mc * (size_t)HIST_CAP * d);
+    P.off_p2 = lay.take((banded ? n * mc : 1) * d);
+    P.off_pqp = lay.take(mc * SPLIT_PMAX * d);
+    P.off_fin = lay.take(lmp_fin_doubles(P.maxc) * d);
     P.total = lay.total;
     return P;
 }
@@ -130,21 +155,6 @@ Plan make_plan(const eda_config *c) {
 template <typename T>
 T *at(char *ws, size_t off) {
     return reinterpret_cast<T *>(ws + off);
-}
-
-// Banded U_B taps: offsets o with r(|o|) > 2^-60 r(0), i.e. o^2 < 60 ln 2 len^2,
-// clipped to one full period of the ring.
-void band_taps(int n, double len_b, int &lo, int &hi) {
-    const double lim = 60.0 * std::log(2.0) * len_b * len_b;
-    int w = 0;
-    while (w + 1 <= n / 2 && (double)(w + 1) * (w + 1) < lim) w++;
-    if (2 * w + 1 >= n) {
-        lo = -((n - 1) / 2);
-        hi = n / 2;
-    } else {
-        lo = -w;
-        hi = w;
-    }
 }
 
 // Y = U_B X (+ Add), columns optionally masked.  lowp (reduced-precision
@@ -383,7 +393,18 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
     c.pc_members = at<int32_t>(w, P.off_members);
     c.pc_hist = at<double>(w, P.off_hist);
     c.hist_cap = HIST_CAP;
+    c.pc_p2 = at<double>(w, P.off_p2);
+    c.pc_pqp = at<double>(w, P.off_pqp);
+    c.lmp_fin = at<double>(w, P.off_fin);
     band_taps(c.n, cfg->len_b, c.band_lo, c.band_hi);
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&c.num_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            delete h;
+            return EDA_ERR_HIP;
+        }
+    }
 
     auto fail = [&](int code) {
         delete h;
@@ -566,6 +587,39 @@ int lmp_apply(Ctx &c, int which, int nb, const double *X, long long ldx, double 
     return EDA_OK;
 }
 
+// One fused PCG iteration (banded U_B) of every running column: p = z + beta p
+// (p updated in place), (I + A) p, alpha, x, r, the convergence test.
+int fused_iteration(Ctx &c, int nm, const PcgArgs &a, double *p, double rtol, int it) {
+    TladArgs t = tlad_args(c, nm, c.pc_members, nullptr);
+    t.obs = c.hv_obs;
+    t.pcg.members = c.pc_members;
+    t.pcg.b = c.b;
+    t.pcg.x = c.pc_x;
+    t.pcg.r = c.pc_r;
+    t.pcg.z = a.z;
+    t.pcg.p = p;
+    t.pcg.scal = c.pc_scal;
+    t.pcg.status = c.pc_status;
+    t.pcg.iters = c.pc_iters;
+    t.pcg.hist = a.hist;
+    t.pcg.hist_cap = c.hist_cap;
+    t.pcg.rtol = rtol;
+    t.pcg.it = it;
+    t.pcg.first = it == 1 ? 1 : 0;
+    return run_tlad(c, t, TLAD_PCG, false);
+}
+
+// The update half of a split PCG iteration with z = P_theta r of the new r.
+int lmp_update(Ctx &c, int nb, const LmpFin &f) {
+    if (!c.sr_ready) {
+        HIP_TRY(launch_lmp_rowmajor(c.stream, c.n, c.k, c.sk_s, c.sk_sr));
+        c.sr_ready = true;
+    }
+    HIP_TRY(launch_lmp_fin(c.stream, c.n, c.k, nb, c.sk_s, c.sk_sr, c.sk_coef, c.pc_r, c.pc_z, c.pc_status,
+                           c.lmp_work, f));
+    return EDA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -624,6 +678,7 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
         for (int i = 0; i < Ctx::CK_SLOTS; i++) HIP_TRY(hipEventCreateWithFlags(&c.ck_ev[i], hipEventDisableTiming));
     }
     int ck_issued = 0, ck_done = 0;
+    std::vector<int> ck_running;  // running columns at each checkpoint read
     bool none_running = false;
     auto consume = [&](bool block) -> int {  // read the oldest outstanding checkpoint
         const int slot = ck_done % Ctx::CK_SLOTS;
@@ -635,13 +690,20 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
             if (q != hipSuccess) return EDA_ERR_HIP;
         }
         const int32_t *st = c.h_ck + (size_t)slot * c.max_cols;
-        bool running = false;
-        for (int i = 0; i < nm; i++) running |= (st[i] == COL_RUNNING);
-        none_running |= !running;
+        int running = 0;
+        for (int i = 0; i < nm; i++) running += (st[i] == COL_RUNNING);
+        ck_running.push_back(running);
+        none_running |= running == 0;
         ck_done++;
         return 1;
     };
     const bool fused = c.cfg.ub_mode == EDA_UB_BANDED;
+    // with the LMP, the banded form runs split iterations: the Hessian part on
+    // P pieces per column (P * running columns <= compute units), then the
+    // update fused with the LMP of the new residual
+    const bool split = fused && use_lmp;
+    double *pbuf[2] = {c.pc_p, c.pc_p2};
+    int cur = 0;  // pbuf[cur] holds the current p
     bool stopped_early = false;
     if (!fused) HIP_TRY(launch_pcg_start(s, a));
     struct InPcg {  // profile scope, also left on an error return
@@ -652,25 +714,71 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
     {
         InPcg scope(c);
         for (int it = 1; it <= maxit; it++) {
-            if (fused) {
+            if (split) {
+                int P = c.split_force;
+                if (P == 0) {
+                    // running columns as of the checkpoint 16 .. 23 iterations back (waited
+                    // for if need be, so that the pieces, and the rounding, of every
+                    // iteration do not depend on timing)
+                    int active = nm;
+                    const int j = it / check_every - 3;
+                    if (j >= 0 && j < ck_issued) {
+                        while (ck_done <= j) EDA_TRY(consume(true));
+                        active = ck_running[j];
+                    }
+                    P = 1;
+                    for (int cand = 2; cand <= SPLIT_PMAX; cand *= 2)
+                        if ((long long)cand * active <= c.num_cus && tlad_split_ring(n, c.N, c.band_hi, cand) > 0)
+                            P = cand;
+                }
+                if (P == 1) {
+                    // whole columns: the fused iteration (its update hidden under the
+                    // TL/AD work), then the LMP of the new residual
+                    EDA_TRY(fused_iteration(c, nm, a, pbuf[cur], rtol, it));
+                    EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status));
+                } else {
+                    TladArgs t = tlad_args(c, nm, c.pc_members, nullptr);
+                    t.obs = c.hv_obs;
+                    t.pieces = P;
+                    t.ring = tlad_split_ring(n, c.N, c.band_hi, P);
+                    t.halo = tlad_split_halo(c.N, c.band_hi);
+                    t.pcg.members = c.pc_members;
+                    t.pcg.b = c.b;
+                    t.pcg.x = c.pc_x;
+                    t.pcg.r = c.pc_r;
+                    t.pcg.z = c.pc_z;
+                    t.pcg.p = pbuf[cur];
+                    t.pcg.p_out = pbuf[cur ^ 1];
+                    t.pcg.q = c.pc_q;
+                    t.pcg.pq_part = c.pc_pqp;
+                    t.pcg.scal = c.pc_scal;
+                    t.pcg.status = c.pc_status;
+                    t.pcg.iters = c.pc_iters;
+                    t.pcg.it = it;
+                    t.pcg.first = it == 1 ? 1 : 0;
+                    EDA_TRY(run_tlad(c, t, TLAD_SPLIT, false));
+                    LmpFin f{};
+                    f.q = c.pc_q;
+                    f.p = pbuf[cur ^ 1];
+                    f.pq_part = c.pc_pqp;
+                    f.b = c.b;
+                    f.members = c.pc_members;
+                    f.x = c.pc_x;
+                    f.scal = c.pc_scal;
+                    f.hist = a.hist;
+                    f.iters = c.pc_iters;
+                    f.pieces = P;
+                    f.it = it;
+                    f.hist_cap = c.hist_cap;
+                    f.rtol = rtol;
+                    f.rr_part = c.lmp_fin;
+                    f.xbr_part = c.lmp_fin + lmp_fin_doubles(c.max_cols) / 2;
+                    EDA_TRY(lmp_update(c, nm, f));
+                    cur ^= 1;
+                }
+            } else if (fused) {
                 // one launch: p = z + beta p, q = (I + A) p, alpha, x, r, convergence
-                TladArgs t = tlad_args(c, nm, c.pc_members, nullptr);
-                t.obs = c.hv_obs;
-                t.pcg.members = c.pc_members;
-                t.pcg.b = c.b;
-                t.pcg.x = c.pc_x;
-                t.pcg.r = c.pc_r;
-                t.pcg.z = a.z;
-                t.pcg.p = c.pc_p;
-                t.pcg.scal = c.pc_scal;
-                t.pcg.status = c.pc_status;
-                t.pcg.iters = c.pc_iters;
-                t.pcg.hist = a.hist;
-                t.pcg.hist_cap = c.hist_cap;
-                t.pcg.rtol = rtol;
-                t.pcg.it = it;
-                t.pcg.first = it == 1 ? 1 : 0;
-                EDA_TRY(run_tlad(c, t, TLAD_PCG, false));
+                EDA_TRY(fused_iteration(c, nm, a, c.pc_p, rtol, it));
                 if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status));
             } else {
                 EDA_TRY(hessvec(c, c.pc_members, nm, c.pc_p, n, c.pc_q, n, EDA_HV_ADD_IDENTITY, c.pc_status));
@@ -787,6 +895,16 @@ int eda_set_geometry(eda_ctx *h, int32_t waves, int32_t tb) {
     if (tb > g.tb) return EDA_ERR_UNSUPPORTED;
     c.geo_waves = waves;
     c.geo_tb = tb;
+    return EDA_OK;
+}
+
+int eda_set_split(eda_ctx *h, int32_t pieces) {
+    if (!h) return EDA_ERR_INVALID_ARG;
+    Ctx &c = h->c;
+    if (pieces != 0 && pieces != 1 && pieces != 2 && pieces != 4 && pieces != 8) return EDA_ERR_INVALID_ARG;
+    if (c.cfg.ub_mode != EDA_UB_BANDED) return EDA_ERR_UNSUPPORTED;
+    if (pieces > 1 && tlad_split_ring(c.n, c.N, c.band_hi, pieces) == 0) return EDA_ERR_UNSUPPORTED;
+    c.split_force = pieces;
     return EDA_OK;
 }
 

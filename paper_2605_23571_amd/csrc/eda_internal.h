@@ -60,6 +60,11 @@ struct Ctx {
     int32_t *pc_status = nullptr, *pc_iters = nullptr, *pc_members = nullptr;
     double *pc_hist = nullptr;
     int hist_cap = 0;
+    // split PCG iterations: second p buffer, the pieces' p^T (I + A) p, the
+    // update's per-row-block ||r||^2 and x^T (b + r); compute units of the device
+    double *pc_p2 = nullptr, *pc_pqp = nullptr, *lmp_fin = nullptr;
+    int num_cus = 0;
+    int split_force = 0;  // pieces per column forced by eda_set_split (0: automatic)
     // pipelined PCG convergence checks: pinned host slots and their events
     static constexpr int CK_SLOTS = 4;
     int32_t *h_ck = nullptr;  // CK_SLOTS x max_cols statuses (pinned host memory)
@@ -109,6 +114,10 @@ struct PcgCols {
     const double *lmp_s, *lmp_c;
     int lmp_k;
     const int32_t *lmp_info;  // persistent solve: 3 Cholesky outcomes of the sketch; any nonzero: no LMP
+    // split iteration (TLAD_SPLIT): p is read from p and written to p_out (the
+    // pieces of a column read each other's halos), (I + A) p goes to q and the
+    // pieces' partial sums of p^T (I + A) p to pq_part[c * pieces + piece]
+    double *p_out, *q, *pq_part;
 };
 // One column of a batched persistent solve: problem index, PCG column.
 struct SolveTask {
@@ -121,7 +130,16 @@ enum TladMode : int {
     TLAD_ADJ = 1,   // forcing (global) -> AD -> lambda_0 (global)
     TLAD_HV = 2,    // X -> U_B X -> TL -> AD -> U_B lambda_0 (+ X) -> Y, banded U_B in-kernel
     TLAD_PCG = 3,   // one fused PCG iteration per member column (banded U_B), see k_tlad
+    TLAD_SPLIT = 4, // the Hessian part of a PCG iteration on pieces of each member column, see tlad_column
 };
+
+// A member column split into P pieces: piece i owns the states
+// [i n / P, (i + 1) n / P) and integrates a ring of ceil(n / P) + 2 H points
+// around them, H = 12 N + 2 band_hi (the TL/AD dependency cone over the window
+// plus U_B on both sides), so its owned outputs are exact.
+constexpr int SPLIT_PMAX = 8;
+int tlad_split_halo(int N, int band_hi);
+int tlad_split_ring(int n, int N, int band_hi, int pieces);  // 0: not possible (ring longer than n)
 
 // Arguments of the TL/AD kernel.  Columns with active[c] != COL_RUNNING are
 // skipped when active is non-null (TLAD_PCG uses pcg.status instead).
@@ -144,6 +162,7 @@ struct TladArgs {
     const double *ubrow;  // HV/PCG: U_B first row and tap range
     int band_lo, band_hi;
     int add_identity;     // HV: Y = U_B lambda_0 + X
+    int pieces, ring, halo;  // TLAD_SPLIT: pieces per column, ring length, halo
     PcgCols pcg;
 };
 // Launch geometry of the TL/AD kernel: waves per workgroup, ring segment owned
@@ -174,6 +193,8 @@ int solve_blocks_per_cu(const TladGeom &g, size_t lds);
 // Pads of the periodic row extension that every wave window of the TL/AD
 // kernel fits in without wrapping: window points j in [-pad_l, n + pad_r).
 void tlad_pads(int n, int *pad_l, int *pad_r);
+// The same, also covering the rings of every split (pieces 2 .. SPLIT_PMAX).
+void tlad_pads_split(int n, int N, int band_hi, int *pad_l, int *pad_r);
 // waves, tb: geometry override (0: the default for n).
 hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32, int waves = 0, int tb = 0);
 
@@ -205,6 +226,23 @@ size_t lmp_work_doubles(int n, int k, int ncols);
 hipError_t launch_lmp_rowmajor(hipStream_t s, int n, int k, const double *S, double *Sr);
 hipError_t launch_lmp(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
                       const double *X, long long ldx, double *Y, long long ldy, const int32_t *status, double *work);
+// The update half of a split PCG iteration, fused with the LMP of the new
+// residual: for every running column, alpha = rho / p^T (I + A) p (rho from
+// scal[4c + 3], the pieces' partial sums pq_part), x += alpha p, r -= alpha q,
+// z = P r, ||r||, the history entry and the status -- what the fused PCG
+// kernel does after its Hessian product.  r, z, x: n x nb (ld n).
+struct LmpFin {
+    const double *q, *p, *pq_part, *b;
+    const int32_t *members;
+    double *x, *scal, *hist;
+    int32_t *iters;
+    int pieces, it, hist_cap;
+    double rtol;
+    double *rr_part, *xbr_part;  // LMP_RB_MAX x ldw each
+};
+size_t lmp_fin_doubles(int ncols);
+hipError_t launch_lmp_fin(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
+                          double *r, double *z, int32_t *status, double *work, const LmpFin &f);
 // BF16-operand, FP32-accumulate GEMM C = A B (+ Add): A in BF16 (M x K,
 // column-major), B, C, Add in FP64 (B rounded to BF16 as it is staged).
 hipError_t gemm_bf16(hipStream_t s, int M, int N, int K, const unsigned short *A, long long lda, const double *B,

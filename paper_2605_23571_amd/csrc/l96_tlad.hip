@@ -30,6 +30,7 @@
 // inside the workgroup (the column is in LDS), and TLAD_PCG performs a whole
 // PCG iteration for its member: p = z + beta p, q = (I + A) p, alpha, x and r
 // updates, the convergence test -- one launch in place of eight.
+#include <type_traits>
 #include <utility>
 
 #include "eda_internal.h"
@@ -163,20 +164,22 @@ __device__ __forceinline__ void store_obs(double *o, const int *qi, const T (&dx
     }
 }
 
-// Window of this lane: ring position of its first point (base; the others
+// Window of this lane on a ring of R points whose position j is the state
+// index off + j (mod n): ring position of its first point (base; the others
 // follow contiguously, wrapped), the mask of points inside the wave's owned
 // segment, and, in LDS (qi[q * 64 + lane]), the observation index of observed
 // points (-1 otherwise; owned points only if owned_obs_only).
 template <int Q>
 __device__ __forceinline__ int window(const TladArgs &a, int w0, int own_lo, int own_hi, bool owned_obs_only,
-                                      unsigned &ownm, int *qi) {
+                                      unsigned &ownm, int *qi, int R, int off) {
     const int n = a.n, lane = threadIdx.x & 63;
-    int b = (w0 + lane * Q) % n;
-    if (b < 0) b += n;
+    int b = (w0 + lane * Q) % R;
+    if (b < 0) b += R;
     ownm = 0;
 #pragma unroll
     for (int q = 0; q < Q; q++) {
-        const int p = wpos(b, q, n);
+        int p = wpos(b, q, R) + off;  // state index
+        p = p < 0 ? p + n : (p >= n ? p - n : p);
         const int jw = w0 + lane * Q + q;  // unwrapped position
         const bool own = jw >= own_lo && jw < own_hi;
         if (own) ownm |= 1u << q;
@@ -251,26 +254,45 @@ __device__ __forceinline__ double block_sum(double v, double *red, int waves) {
 
 // One column of one problem, all modes (the workgroup's whole job in k_tlad,
 // one step of the task loop in k_solve).  PCG mode runs iteration `it` (first:
-// p = z).  Every early exit is taken by the whole workgroup.
+// p = z).  SPLIT mode runs the Hessian part of that iteration on piece `piece`
+// of the column: the ring is the piece's owned states [lo, hi) with a.halo
+// states on each side (ring position j = state lo - halo + j mod n); positions
+// whose dependency cone reaches the ring's seam are wrong, the owned ones
+// exact.  Every early exit is taken by the whole workgroup.
 template <typename T, int Q, int MODE>
 __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g, const int c, const int it,
-                                            const int first, unsigned char *smraw) {
-    constexpr bool FUSED = (MODE == TLAD_HV || MODE == TLAD_PCG);
+                                            const int first, unsigned char *smraw, const int piece = 0) {
+    constexpr bool SPLIT = MODE == TLAD_SPLIT;
+    constexpr bool FUSED = (MODE == TLAD_HV || MODE == TLAD_PCG || SPLIT);
     const int n = a.n, N = a.N, p = a.nt * a.nv;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x, nthr = blockDim.x;
-    // LDS: [ring: 2n T][qi: waves*64*Q int][xw: waves*64*Q double][u: n double][taps: W double][red: 16 double]
-    T *ring = reinterpret_cast<T *>(smraw);  // two buffers, indexed rsel * n + position
-    int *qi = reinterpret_cast<int *>(ring + 2 * n) + wave * 64 * Q;
-    double *xw_all = reinterpret_cast<double *>(reinterpret_cast<int *>(ring + 2 * n) + g.waves * 64 * Q);
+    // ring length, state index of ring position 0, owned ring positions
+    const int R = SPLIT ? a.ring : n;
+    int off = 0, core_lo = 0, core_hi = n;
+    if (SPLIT) {
+        const int lo = (int)((long long)piece * n / a.pieces), hi = (int)((long long)(piece + 1) * n / a.pieces);
+        off = lo - a.halo;
+        core_lo = a.halo;
+        core_hi = a.halo + hi - lo;
+    }
+    auto state = [&](int j) {  // state index of ring position j
+        int v = off + j;
+        return v < 0 ? v + n : (v >= n ? v - n : v);
+    };
+    // LDS: [ring: 2R T][qi: waves*64*Q int][xw: waves*64*Q double][u: R double][taps: W double][red: 16 double]
+    T *ring = reinterpret_cast<T *>(smraw);  // two buffers, indexed rsel * R + position
+    int *qi = reinterpret_cast<int *>(ring + 2 * R) + wave * 64 * Q;
+    double *xw_all = reinterpret_cast<double *>(reinterpret_cast<int *>(ring + 2 * R) + g.waves * 64 * Q);
     double *xw = xw_all + wave * 64 * Q;  // this wave's trajectory window slice
     double *u = xw_all + g.waves * 64 * Q;
-    double *taps = u + n;
+    double *taps = u + R;
     const int W = a.band_hi - a.band_lo + 1;
     double *red = taps + W;
     double *lamd = reinterpret_cast<double *>(ring);  // ring reused as a double array for lambda_0
-    const int own_lo = wave * g.S, own_hi = min(n, own_lo + g.S);
-    const int member = MODE == TLAD_PCG ? a.pcg.members[c] : (a.col_member ? a.col_member[c] : 0);
-    const double *trajm = a.trajx + (long long)member * a.trajx_stride + a.pad_l;  // row s: trajm + s ext_len
+    const int own_lo = wave * g.S, own_hi = min(R, own_lo + g.S);
+    const int member = (MODE == TLAD_PCG || SPLIT) ? a.pcg.members[c] : (a.col_member ? a.col_member[c] : 0);
+    // row s of the member's padded trajectory, from ring position 0: trajm + s ext_len
+    const double *trajm = a.trajx + (long long)member * a.trajx_stride + a.pad_l + off;
     const T h = (T)a.h, dt = (T)a.dt, dt6 = (T)a.dt6, dt3 = (T)a.dt3, hF = (T)(a.h * a.F);
     unsigned ownm;
     int rsel = 0;
@@ -296,16 +318,28 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
             double beta = 0.0;
             if (!first) {
                 if (!(rz > 0.0) || !isfinite(rz)) {
-                    if (tid == 0) a.pcg.status[c] = EDA_MEMBER_BREAKDOWN;
+                    if (tid == 0 && piece == 0) a.pcg.status[c] = EDA_MEMBER_BREAKDOWN;
                     return;
                 }
                 beta = rz / a.pcg.scal[4 * c];
             }
             rho = rz;
-            for (int i = tid; i < n; i += nthr) {
-                double v = first ? z[i] : z[i] + beta * pp[i];
-                pp[i] = v;
-                u[i] = v;
+            if (!SPLIT) {
+                for (int i = tid; i < n; i += nthr) {
+                    double v = first ? z[i] : z[i] + beta * pp[i];
+                    pp[i] = v;
+                    u[i] = v;
+                }
+            } else {
+                // p over the ring from the previous p; the new p written for the owned states only
+                double *pout = a.pcg.p_out + cn;
+                for (int j = tid; j < R; j += nthr) {
+                    const int gi = state(j);
+                    const double v = first ? z[gi] : z[gi] + beta * pp[gi];
+                    u[j] = v;
+                    if (j >= core_lo && j < core_hi) pout[gi] = v;
+                }
+                if (piece == 0 && tid == 0) a.pcg.scal[4 * c + 3] = rz;  // rho of this iteration, for the update
             }
         }
         __syncthreads();
@@ -315,11 +349,11 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
         // ---------------- TL forward run ----------------
         const int w0 = own_lo - g.hl_tl;
         prefetch_window<Q>(trajm + w0, xw);
-        int base = window<Q>(a, w0, own_lo, own_hi, true, ownm, qi);
+        int base = window<Q>(a, w0, own_lo, own_hi, true, ownm, qi, R, off);
         T dx[Q];
         if (FUSED) {
             double v0[Q];
-            band_lane<Q>(u, taps, W, a.band_hi, n, base, v0);
+            band_lane<Q>(u, taps, W, a.band_hi, R, base, v0);
 #pragma unroll
             for (int q = 0; q < Q; q++) dx[q] = (T)v0[q];
         } else {
@@ -327,12 +361,12 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
 #pragma unroll
             for (int q = 0; q < Q; q++) dx[q] = (T)vcol[wpos(base, q, n)];
         }
-        double *obs = a.obs + (long long)c * p;
+        double *obs = a.obs + ((long long)c * (SPLIT ? a.pieces : 1) + piece) * p;
         for (int s0 = 0; s0 < N; s0 += g.tb) {
             if (s0 > 0) {
                 __syncthreads();
 #pragma unroll
-                for (int q = 0; q < Q; q++) dx[q] = ring[rsel * n + wpos(base, q, n)];
+                for (int q = 0; q < Q; q++) dx[q] = ring[rsel * R + wpos(base, q, R)];
             }
             const int s1 = min(N, s0 + g.tb);
             for (int s = s0; s < s1; s++) {
@@ -380,7 +414,7 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
             if (s1 < N) {
 #pragma unroll
                 for (int q = 0; q < Q; q++)
-                    if (ownm & (1u << q)) ring[(rsel ^ 1) * n + wpos(base, q, n)] = dx[q];
+                    if (ownm & (1u << q)) ring[(rsel ^ 1) * R + wpos(base, q, R)] = dx[q];
                 rsel ^= 1;
             }
         }
@@ -392,8 +426,9 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
     // ---------------- AD backward run ----------------
     const int w0 = own_lo - g.hl_ad;
     prefetch_window<Q>(trajm + (long long)(N - 1) * a.ext_len + w0, xw);
-    const int base = window<Q>(a, w0, own_lo, own_hi, false, ownm, qi);
-    const double *force = (MODE == TLAD_ADJ) ? a.force + (long long)c * p : a.obs + (long long)c * p;
+    const int base = window<Q>(a, w0, own_lo, own_hi, false, ownm, qi, R, off);
+    const double *force = (MODE == TLAD_ADJ) ? a.force + (long long)c * p
+                                              : a.obs + ((long long)c * (SPLIT ? a.pieces : 1) + piece) * p;
     T lam[Q];
 #pragma unroll
     for (int q = 0; q < Q; q++) lam[q] = T(0);
@@ -401,7 +436,7 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
         if (s_hi < N) {
             __syncthreads();
 #pragma unroll
-            for (int q = 0; q < Q; q++) lam[q] = ring[rsel * n + wpos(base, q, n)];
+            for (int q = 0; q < Q; q++) lam[q] = ring[rsel * R + wpos(base, q, R)];
         }
         const int s_lo = max(0, s_hi - g.tb);
         for (int s = s_hi; s > s_lo; s--) {
@@ -470,7 +505,7 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
         if (s_lo > 0) {
 #pragma unroll
             for (int q = 0; q < Q; q++)
-                if (ownm & (1u << q)) ring[(rsel ^ 1) * n + wpos(base, q, n)] = lam[q];
+                if (ownm & (1u << q)) ring[(rsel ^ 1) * R + wpos(base, q, R)] = lam[q];
             rsel ^= 1;
         }
     }
@@ -487,10 +522,10 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
     __syncthreads();  // every wave is done reading the ring
 #pragma unroll
     for (int q = 0; q < Q; q++)
-        if (ownm & (1u << q)) lamd[wpos(base, q, n)] = (double)lam[q];
+        if (ownm & (1u << q)) lamd[wpos(base, q, R)] = (double)lam[q];
     __syncthreads();
     double y[Q];
-    band_lane<Q>(lamd, taps, W, a.band_hi, n, base, y);
+    band_lane<Q>(lamd, taps, W, a.band_hi, R, base, y);
     if (MODE == TLAD_HV) {
         double *out = a.lam + (long long)c * a.ldl;
 #pragma unroll
@@ -500,6 +535,24 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
                 out[ps] = a.add_identity ? y[q] + u[ps] : y[q];
             }
         }
+        return;
+    }
+
+    if (SPLIT) {
+        // (I + A) p at the owned states and this piece's part of p^T (I + A) p
+        double pq = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+            const int j = wpos(base, q, R);
+            if ((ownm & (1u << q)) && j >= core_lo && j < core_hi) {
+                const double pv = u[j];
+                y[q] += pv;
+                pq += pv * y[q];
+                a.pcg.q[cn + state(j)] = y[q];
+            }
+        }
+        pq = block_sum(pq, red, g.waves);
+        if (tid == 0) a.pcg.pq_part[(long long)c * a.pieces + piece] = pq;
         return;
     }
 
@@ -554,13 +607,14 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
 template <typename T, int Q, int MODE>
 __global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
     extern __shared__ __align__(16) unsigned char smraw[];
-    const int c = blockIdx.x;
-    if (MODE == TLAD_PCG) {
+    const int c = MODE == TLAD_SPLIT ? blockIdx.x / a.pieces : blockIdx.x;
+    const int piece = MODE == TLAD_SPLIT ? blockIdx.x % a.pieces : 0;
+    if (MODE == TLAD_PCG || MODE == TLAD_SPLIT) {
         if (a.pcg.status[c] != COL_RUNNING) return;
     } else if (a.active && a.active[c] != COL_RUNNING) {
         return;
     }
-    tlad_column<T, Q, MODE>(a, g, c, a.pcg.it, a.pcg.first, smraw);
+    tlad_column<T, Q, MODE>(a, g, c, a.pcg.it, a.pcg.first, smraw, piece);
 }
 
 // z = P r = r + S diag(coef) S^T r for one column (in-kernel LMP of the
@@ -706,9 +760,10 @@ __global__ __launch_bounds__(512) void k_hv_multi(const TladArgs *__restrict__ p
 
 template <typename T, int Q>
 size_t lds_bytes(const TladArgs &a, const TladGeom &g, int mode) {
-    size_t b = sizeof(T) * 2 * (size_t)a.n + (sizeof(int) + sizeof(double)) * (size_t)g.waves * 64 * Q;
-    if (mode == TLAD_HV || mode == TLAD_PCG)
-        b += sizeof(double) * ((size_t)a.n + (size_t)(a.band_hi - a.band_lo + 1) + 16);
+    const size_t R = mode == TLAD_SPLIT ? (size_t)a.ring : (size_t)a.n;
+    size_t b = sizeof(T) * 2 * R + (sizeof(int) + sizeof(double)) * (size_t)g.waves * 64 * Q;
+    if (mode == TLAD_HV || mode == TLAD_PCG || mode == TLAD_SPLIT)
+        b += sizeof(double) * (R + (size_t)(a.band_hi - a.band_lo + 1) + 16);
     return b;
 }
 
@@ -722,6 +777,13 @@ hipError_t launch_q(hipStream_t s, const TladArgs &a, const TladGeom &g, int mod
         case TLAD_ADJ: hipLaunchKernelGGL((k_tlad<T, Q, TLAD_ADJ>), dim3(a.nb), block, lds, s, a, g); break;
         case TLAD_HV: hipLaunchKernelGGL((k_tlad<T, Q, TLAD_HV>), dim3(a.nb), block, lds, s, a, g); break;
         case TLAD_PCG: hipLaunchKernelGGL((k_tlad<T, Q, TLAD_PCG>), dim3(a.nb), block, lds, s, a, g); break;
+        case TLAD_SPLIT:
+            if constexpr (std::is_same<T, double>::value) {
+                hipLaunchKernelGGL((k_tlad<T, Q, TLAD_SPLIT>), dim3(a.nb * a.pieces), block, lds, s, a, g);
+                break;
+            } else {
+                return hipErrorInvalidValue;
+            }
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -859,22 +921,57 @@ bool tlad_waves_ok(int n, int waves) {
     return g.q <= 9 && g.tb >= 1;
 }
 
-// Pads covering the windows of every geometry the launchers accept: any
-// accepted wave count and any time-block length up to its maximum.
-void tlad_pads(int n, int *pad_l, int *pad_r) {
+int tlad_split_halo(int N, int band_hi) { return 12 * N + 2 * band_hi; }
+
+int tlad_split_ring(int n, int N, int band_hi, int pieces) {
+    if (pieces < 2) return n;
+    const int R = (n + pieces - 1) / pieces + 2 * tlad_split_halo(N, band_hi);
+    if (R > n) return 0;
+    const TladGeom g = tlad_geometry(R, 0);
+    return (g.q <= 9 && g.tb >= 1) ? R : 0;
+}
+
+// Reach of the windows on a ring of R points over every geometry the
+// launchers accept (any accepted wave count, any time-block length up to its
+// maximum): windows start up to *left points before ring position 0 and end up
+// to *right points after position R.
+static void ring_reach(int R, int *left, int *right) {
     int pl = 0, pr = 0;
     for (int W = 1; W <= 8; W *= 2) {
-        if (!tlad_waves_ok(n, W)) continue;
-        const TladGeom g0 = tlad_geometry(n, W);
+        if (!tlad_waves_ok(R, W)) continue;
+        const TladGeom g0 = tlad_geometry(R, W);
         for (int tb = 1; tb <= g0.tb; tb++) {
-            const TladGeom g = tlad_geometry(n, W, tb);
+            const TladGeom g = tlad_geometry(R, W, tb);
             const int hmax = g.hl_tl > g.hl_ad ? g.hl_tl : g.hl_ad;
             const int hmin = g.hl_tl < g.hl_ad ? g.hl_tl : g.hl_ad;
             // window of wave w: [w S - hl, w S - hl + 64 Q)
-            const int right = (g.waves - 1) * g.S - hmin + 64 * g.q - n;
+            const int right = (g.waves - 1) * g.S - hmin + 64 * g.q - R;
             if (hmax > pl) pl = hmax;
             if (right > pr) pr = right;
         }
+    }
+    *left = pl;
+    *right = pr;
+}
+
+void tlad_pads(int n, int *pad_l, int *pad_r) { ring_reach(n, pad_l, pad_r); }
+
+// Split rings: ring position 0 is state lo - H, so windows reach H + left
+// below state 0 (first piece) and up to the last ring's end plus its reach
+// above state n (last piece).
+void tlad_pads_split(int n, int N, int band_hi, int *pad_l, int *pad_r) {
+    int pl, pr;
+    tlad_pads(n, &pl, &pr);
+    const int H = tlad_split_halo(N, band_hi);
+    for (int P = 2; P <= SPLIT_PMAX; P *= 2) {
+        const int R = tlad_split_ring(n, N, band_hi, P);
+        if (R == 0) continue;
+        int l, r;
+        ring_reach(R, &l, &r);
+        const int lo_last = (int)((long long)(P - 1) * n / P);
+        const int left = H + l, right = (lo_last - H) + R + r - n;
+        if (left > pl) pl = left;
+        if (right > pr) pr = right;
     }
     *pad_l = pl;
     *pad_r = pr;
@@ -882,8 +979,14 @@ void tlad_pads(int n, int *pad_l, int *pad_r) {
 
 hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32, int waves, int tb) {
     if (a.nb <= 0) return hipSuccess;
-    if (waves != 0 && !tlad_waves_ok(a.n, waves)) return hipErrorInvalidValue;
-    TladGeom g = tlad_geometry(a.n, waves, tb);
+    if (mode == TLAD_SPLIT) {
+        if (fp32 || a.pieces < 1 || a.ring < 1 || a.ring > a.n) return hipErrorInvalidValue;
+        if (a.pieces == 1 ? (a.ring != a.n || a.halo != 0) : a.ring != tlad_split_ring(a.n, a.N, a.band_hi, a.pieces))
+            return hipErrorInvalidValue;
+    }
+    const int R = mode == TLAD_SPLIT ? a.ring : a.n;
+    if (waves != 0 && !tlad_waves_ok(R, waves)) return hipErrorInvalidValue;
+    TladGeom g = tlad_geometry(R, waves, tb);
     if (g.q > 9 || g.tb < 1) return hipErrorInvalidValue;
     if (mode == TLAD_PCG && fp32) return hipErrorInvalidValue;  // PCG recurrences stay FP64
     return fp32 ? launch_t<float>(s, a, g, mode) : launch_t<double>(s, a, g, mode);

@@ -7,7 +7,7 @@
 // Two launches on the FP64 matrix cores (v_mfma_f64_16x16x4f64):
 //  * k_lmp_proj   -- workgroup (row block, tile of 16 columns): the partial
 //    projection S_b^T X_b of its rows onto every direction;
-//  * k_lmp_expand -- workgroup (128 rows, 16 columns): W = diag(coef) S^T X for
+//  * k_lmp_expand -- workgroup (256 rows, 16 columns): W = diag(coef) S^T X for
 //    its columns (the row blocks summed in block order, into LDS), then
 //    Y = X + S W.
 // Sums are taken in a fixed order, so results do not depend on scheduling; the
@@ -39,6 +39,18 @@ __device__ __forceinline__ bool tile_running(const int32_t *status, int c0, int 
     return any;
 }
 
+// p^T (I + A) p of column col: the pieces' partial sums in piece order, all
+// loaded before the sum
+__device__ __forceinline__ double pieces_sum(const LmpFin &f, int col) {
+    double v[SPLIT_PMAX];
+#pragma unroll
+    for (int i = 0; i < SPLIT_PMAX; i++) v[i] = i < f.pieces ? f.pq_part[(long long)col * f.pieces + i] : 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < SPLIT_PMAX; i++) s += v[i];
+    return s;
+}
+
 // Sr[i k + j] = S[j n + i]
 __global__ void k_lmp_rowmajor(int n, int k, const double *__restrict__ S, double *__restrict__ Sr) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -47,69 +59,143 @@ __global__ void k_lmp_rowmajor(int n, int k, const double *__restrict__ S, doubl
     Sr[e] = S[(long long)j * n + i];
 }
 
-// Partial projections part[rb][j][col] = sum_{i in block rb} S[i][j] X[i][col].
-// Wave w takes 4 slabs of 16 rows; step t of a slab runs on the rows
-// i = i0 + 4 g + t (A[m][g] = Sr[i][j0 + m], B[g][m] = X[i][c0 + m]).  All of a
-// wave's loads -- the tile's status included -- are issued before the first
-// MFMA, so the kernel waits on one round trip to memory.  The four waves'
-// accumulators are summed in wave order through LDS.
-__global__ __launch_bounds__(256) void k_lmp_proj(int n, int k, int nb, int rows, const double *__restrict__ Sr,
-                                                  const double *__restrict__ X, long long ldx,
-                                                  const int32_t *__restrict__ status, double *__restrict__ part,
-                                                  int ldw) {
-    __shared__ double red[4][4][4][64];  // [wave][j tile in group][v][lane]
+// Partial projections part[rb][j][col] = sum_{i in block rb} S[i][j] X[i][col]
+// for a block of 256 rows and a tile of 16 columns, in two phases.
+//  1. Coalesced pass: thread t takes column c0 + t / 32 and rows
+//     r0 + t % 32 + 32 u (u < 8); it stages X there in LDS (xs[column][row]).
+//     FIN (X = r of a split PCG iteration): it first updates the column's
+//     entries, r -= alpha q and x += alpha p (alpha from the pieces' partial
+//     sums; running columns only), stages the new r, and sums ||r||^2 and
+//     x^T (b + r) over its rows; a 32-lane shuffle tree gives the column's sums
+//     for the row block (f.rr_part, f.xbr_part).
+//  2. Eight waves, each on 32 rows (two slabs of 16): step t of a slab runs on
+//     the rows i = i0 + 4 g + t, A[m][g] = Sr[i][j0 + m] (16 consecutive
+//     directions per quarter-wave), B[g][m] = xs[m][i]; the waves' accumulators
+//     are summed in wave order through LDS.
+// The first group's Sr operands are loaded before phase 1, so both phases wait
+// on one round trip to memory.
+template <bool FIN>
+__global__ __launch_bounds__(512) void k_lmp_proj(int n, int k, int nb, int rows, const double *__restrict__ Sr,
+                                                  double *X, long long ldx, const int32_t *__restrict__ status,
+                                                  double *__restrict__ part, int ldw, LmpFin f) {
+    constexpr int RB = 256, XP = RB + 1;  // odd row stride: the 16 columns of one read fall in distinct banks
+    __shared__ double xs[CT][XP];
+    __shared__ double red[8][4][4][64];  // [wave][j tile in group][v][lane]
     const int rb = blockIdx.x, c0 = blockIdx.y * CT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, m = lane & 15;
-    const int r0 = rb * rows, r1 = min(n, r0 + rows);
-    const int wrows = rows / 4;  // a multiple of 64
-    const int w0 = r0 + wave * wrows, w1 = min(r1, w0 + wrows);
-    const int col = c0 + m;
-    const bool colok = col < nb;
-    const double *xc = X + (long long)(colok ? col : 0) * ldx;
+    const int r0 = rb * rows, r1 = min(n, r0 + rows);  // rows == RB
+    const int w0 = r0 + wave * 32, w1 = min(r1, w0 + 32);
     const int njt = (k + 15) / 16;
-    bool run = true;
 
+    // Sr operands of the first direction group
+    double a[2][4][4];  // [slab][j tile][t]
+    auto load_a = [&](int jg) {
+#pragma unroll
+        for (int sl = 0; sl < 2; sl++) {
+            const int ib = w0 + 16 * sl + 4 * g;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int j = (jg + q) * 16 + m;
+                const bool jok = j < k;
+#pragma unroll
+                for (int t = 0; t < 4; t++)
+                    a[sl][q][t] = (jok && ib + t < w1) ? Sr[(long long)(ib + t) * k + j] : 0.0;
+            }
+        }
+    };
+    load_a(0);
+
+    // phase 1
+    {
+        const int cq = tid >> 5, rl = tid & 31, col = c0 + cq;
+        const bool colok = col < nb;
+        const int cc = colok ? col : 0;
+        double *xc = X + (long long)cc * ldx;
+        double xv[8], qv[8], pv[8], zv[8], bv[8];
+        double pq = 0.0, rho = 0.0;
+        int st = 0;
+        const double *bc = nullptr;
+        if (FIN) {
+            pq = pieces_sum(f, cc);
+            rho = f.scal[4 * cc + 3];
+            st = status[cc];
+            if (f.hist) bc = f.b + (long long)f.members[cc] * n;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int i = r0 + rl + 32 * u;
+            const bool ok = colok && i < r1;
+            xv[u] = ok ? xc[i] : 0.0;
+            if (FIN) {
+                const long long e = (long long)cc * n + i;
+                qv[u] = ok ? f.q[e] : 0.0;
+                pv[u] = ok ? f.p[e] : 0.0;
+                zv[u] = ok ? f.x[e] : 0.0;
+                bv[u] = (ok && bc) ? bc[i] : 0.0;
+            }
+        }
+        if (FIN) {
+            const bool upd = colok && st == COL_RUNNING && pq > 0.0 && isfinite(pq);
+            const double alpha = upd ? rho / pq : 0.0;
+            double rr = 0.0, xbr = 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int i = r0 + rl + 32 * u;
+                if (upd && i < r1) {
+                    const double rn = xv[u] - alpha * qv[u];
+                    const double xn = zv[u] + alpha * pv[u];
+                    xc[i] = rn;
+                    f.x[(long long)cc * n + i] = xn;
+                    rr += rn * rn;
+                    if (bc) xbr += xn * (bv[u] + rn);
+                    xv[u] = rn;
+                }
+            }
+            // the 32 lanes of this column: fixed tree
+#pragma unroll
+            for (int o = 16; o > 0; o >>= 1) {
+                rr += __shfl_down(rr, o, 32);
+                xbr += __shfl_down(xbr, o, 32);
+            }
+            if (rl == 0 && colok) {
+                f.rr_part[(long long)rb * ldw + col] = rr;
+                f.xbr_part[(long long)rb * ldw + col] = xbr;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) xs[cq][rl + 32 * u] = xv[u];
+    }
+    const bool run = tile_running(status, c0, nb);
+    __syncthreads();
+
+    // phase 2
     for (int jg = 0; jg < njt; jg += 4) {
+        if (jg > 0) load_a(jg);
         double4v acc[4];
 #pragma unroll
         for (int q = 0; q < 4; q++) acc[q] = double4v{0.0, 0.0, 0.0, 0.0};
-        for (int i0 = w0; i0 < w1; i0 += 64) {
-            double b[4][4], a[4][4][4];  // [slab][t], [slab][j tile][t]
 #pragma unroll
-            for (int sl = 0; sl < 4; sl++) {
-                const int ib = i0 + 16 * sl + 4 * g;
+        for (int sl = 0; sl < 2; sl++)
 #pragma unroll
-                for (int t = 0; t < 4; t++) b[sl][t] = (colok && ib + t < w1) ? xc[ib + t] : 0.0;
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const int j = (jg + q) * 16 + m;
-                    const bool jok = j < k;
-#pragma unroll
-                    for (int t = 0; t < 4; t++)
-                        a[sl][q][t] = (jok && ib + t < w1) ? Sr[(long long)(ib + t) * k + j] : 0.0;
-                }
-            }
-            if (jg == 0 && i0 == w0) run = tile_running(status, c0, nb);
-#pragma unroll
-            for (int sl = 0; sl < 4; sl++)
+            for (int t = 0; t < 4; t++) {
+                const double b = xs[m][wave * 32 + 16 * sl + 4 * g + t];  // zero beyond r1
 #pragma unroll
                 for (int q = 0; q < 4; q++)
-#pragma unroll
-                    for (int t = 0; t < 4; t++)
-                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sl][q][t], b[sl][t], acc[q], 0, 0, 0);
-        }
+                    acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sl][q][t], b, acc[q], 0, 0, 0);
+            }
         // D[j][col] of tile q: lane l, element v -> j = (jg + q) 16 + l / 16 + 4 v, col = c0 + l % 16
 #pragma unroll
         for (int q = 0; q < 4; q++)
 #pragma unroll
             for (int v = 0; v < 4; v++) red[wave][q][v][lane] = acc[q][v];
         __syncthreads();
-        if (w0 >= w1 && jg == 0) run = tile_running(status, c0, nb);  // waves without rows
-        for (int e = tid; e < 4 * 4 * 64; e += 256) {
+        for (int e = tid; e < 4 * 4 * 64; e += 512) {
             const int q = e >> 8, v = (e >> 6) & 3, l = e & 63;
             const int j = (jg + q) * 16 + (l >> 4) + 4 * v;
             if (run && j < k) {
-                const double s = ((red[0][q][v][l] + red[1][q][v][l]) + red[2][q][v][l]) + red[3][q][v][l];
+                double s = 0.0;
+#pragma unroll
+                for (int w = 0; w < 8; w++) s += red[w][q][v][l];
                 part[((long long)rb * k + j) * ldw + c0 + (l & 15)] = s;
             }
         }
@@ -117,27 +203,29 @@ __global__ __launch_bounds__(256) void k_lmp_proj(int n, int k, int nb, int rows
     }
 }
 
-// Y = X + S W on 128 rows x 16 columns.  Each thread loads, in one batch, its
-// share of the row-block partials of W (4 entries), this lane's S operands
+// Y = X + S W on 256 rows x 16 columns (eight waves).  Each thread loads, in
+// one batch, its share of the row-block partials of W, this lane's S operands
 // and X entries; the workgroup then forms W[j][c] = coef[j] sum_b part[b][j][c]
 // (block order) in LDS, and wave w computes rows 32 w .. 32 w + 31 as two MFMA
 // blocks on (W^T, S^T): A[m][g] = W[j][c0 + m], B[g][m] = S[i + m][j],
 // j = j0 + g, so accumulator lanes run along rows (element v: row i + m,
-// column c0 + g + 4 v).
-template <int KM>
-__global__ __launch_bounds__(256) void k_lmp_expand(int n, int k, int nb, int nrb, const double *__restrict__ S,
+// column c0 + g + 4 v).  FIN: the first workgroup of the tile then ends the
+// iteration of its columns as the fused PCG kernel does (its inputs loaded at
+// the start).
+template <int KM, bool FIN>
+__global__ __launch_bounds__(512) void k_lmp_expand(int n, int k, int nb, int nrb, const double *__restrict__ S,
                                                     const double *__restrict__ coef, const double *X, long long ldx,
-                                                    double *Y, long long ldy, const int32_t *__restrict__ status,
-                                                    const double *__restrict__ part, int ldw) {
+                                                    double *Y, long long ldy, int32_t *status,
+                                                    const double *__restrict__ part, int ldw, LmpFin f) {
+    constexpr int PE = KM * CT / 512;  // W entries per thread
     __shared__ double ws[KM][CT];
     const int c0 = blockIdx.y * CT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, m = lane & 15;
-    const int ib = blockIdx.x * 128 + wave * 32;
-    // partials of KM CT / 256 W entries per thread (k <= KM)
-    double pv[KM * CT / 256][LMP_RB_MAX];
+    const int ib = blockIdx.x * 256 + wave * 32;
+    double pv[PE][LMP_RB_MAX];
 #pragma unroll
-    for (int u = 0; u < KM * CT / 256; u++) {
-        const int e = tid + 256 * u;
+    for (int u = 0; u < PE; u++) {
+        const int e = tid + 512 * u;
         const bool ok = e < k * CT;
         const double *pe = part + (long long)(ok ? e / CT : 0) * ldw + c0 + e % CT;
 #pragma unroll
@@ -151,6 +239,24 @@ __global__ __launch_bounds__(256) void k_lmp_expand(int n, int k, int nb, int nr
             const int i = ib + 16 * rt + m, col = c0 + g + 4 * v;
             xv[rt][v] = (i < n && col < nb) ? X[(long long)col * ldx + i] : 0.0;
         }
+    // FIN: the iteration-end inputs of column c0 + tid (first workgroup of the tile)
+    const bool fin_lane = FIN && blockIdx.x == 0 && tid < CT && c0 + tid < nb;
+    const int fcol = fin_lane ? c0 + tid : 0;
+    double rv[LMP_RB_MAX], xr[LMP_RB_MAX], fpq = 0.0, fbn = 0.0, frho = 0.0;
+    int fst = 0;
+    if (FIN) {
+#pragma unroll
+        for (int b = 0; b < LMP_RB_MAX; b++) {
+            rv[b] = (fin_lane && b < nrb) ? f.rr_part[(long long)b * ldw + fcol] : 0.0;
+            xr[b] = (fin_lane && b < nrb && f.hist) ? f.xbr_part[(long long)b * ldw + fcol] : 0.0;
+        }
+        if (fin_lane) {
+            fpq = pieces_sum(f, fcol);
+            fbn = f.scal[4 * fcol + 1];
+            frho = f.scal[4 * fcol + 3];
+            fst = status[fcol];
+        }
+    }
     double4v acc[2] = {double4v{0.0, 0.0, 0.0, 0.0}, double4v{0.0, 0.0, 0.0, 0.0}};
     const bool run = tile_running(status, c0, nb);
     for (int j0 = 0; j0 < k; j0 += 64) {
@@ -166,8 +272,8 @@ __global__ __launch_bounds__(256) void k_lmp_expand(int n, int k, int nb, int nr
         }
         if (j0 == 0) {
 #pragma unroll
-            for (int u = 0; u < KM * CT / 256; u++) {
-                const int e = tid + 256 * u;
+            for (int u = 0; u < PE; u++) {
+                const int e = tid + 512 * u;
                 if (e < k * CT) {
                     double s = 0.0;
 #pragma unroll
@@ -185,31 +291,47 @@ __global__ __launch_bounds__(256) void k_lmp_expand(int n, int k, int nb, int nr
             for (int rt = 0; rt < 2; rt++) acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[rt][u], acc[rt], 0, 0, 0);
         }
     }
-    if (!run) return;
+    if (run) {
 #pragma unroll
-    for (int rt = 0; rt < 2; rt++) {
-        const int i = ib + 16 * rt + m;
-        if (i >= n) continue;
+        for (int rt = 0; rt < 2; rt++) {
+            const int i = ib + 16 * rt + m;
+            if (i >= n) continue;
 #pragma unroll
-        for (int v = 0; v < 4; v++) {
-            const int col = c0 + g + 4 * v;
-            if (col < nb) Y[(long long)col * ldy + i] = xv[rt][v] + acc[rt][v];
+            for (int v = 0; v < 4; v++) {
+                const int col = c0 + g + 4 * v;
+                if (col < nb) Y[(long long)col * ldy + i] = xv[rt][v] + acc[rt][v];
+            }
+        }
+    }
+    if (FIN && fin_lane && fst == COL_RUNNING) {
+        // the iteration's end for column fcol, as in the fused PCG kernel
+        if (!(fpq > 0.0) || !isfinite(fpq)) {
+            status[fcol] = EDA_MEMBER_BREAKDOWN;
+            f.iters[fcol] = f.it - 1;
+        } else {
+            double rr = 0.0, xbr = 0.0;
+#pragma unroll
+            for (int b = 0; b < LMP_RB_MAX; b++) {  // row blocks in order; absent ones add 0
+                rr += rv[b];
+                xbr += xr[b];
+            }
+            const double rn = sqrt(rr);
+            f.scal[4 * fcol] = frho;
+            f.scal[4 * fcol + 2] = rn / fbn;
+            f.iters[fcol] = f.it;
+            if (f.hist && f.it < f.hist_cap) f.hist[(long long)fcol * f.hist_cap + f.it] = -0.5 * xbr;
+            if (!isfinite(rn)) status[fcol] = EDA_MEMBER_BREAKDOWN;
+            else if (rn <= f.rtol * fbn) status[fcol] = EDA_MEMBER_CONVERGED;
         }
     }
 }
 
 }  // namespace
 
-// Row blocks of the projection: at most LMP_RB_MAX, each a multiple of
-// 256 rows (64 for each of the four waves).
+// Row blocks of the projection: 256 rows each (n <= 4096: at most LMP_RB_MAX).
 void lmp_blocks(int n, int *rows, int *nrb) {
-    const int unit = 256;
-    const int units = (n + unit - 1) / unit;
-    int b = units < LMP_RB_MAX ? units : LMP_RB_MAX;
-    if (b < 1) b = 1;
-    const int per = (units + b - 1) / b;
-    *rows = per * unit;
-    *nrb = (n + *rows - 1) / *rows;
+    *rows = 256;
+    *nrb = (n + 255) / 256;
 }
 
 size_t lmp_work_doubles(int n, int k, int ncols) {
@@ -226,24 +348,45 @@ hipError_t launch_lmp_rowmajor(hipStream_t s, int n, int k, const double *S, dou
     return hipGetLastError();
 }
 
-hipError_t launch_lmp(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
-                      const double *X, long long ldx, double *Y, long long ldy, const int32_t *status,
-                      double *work) {
+size_t lmp_fin_doubles(int ncols) { return 2 * (size_t)LMP_RB_MAX * ((size_t)(ncols + CT - 1) / CT * CT); }
+
+namespace {
+template <bool FIN>
+hipError_t lmp_launch(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
+                      double *X, long long ldx, double *Y, long long ldy, int32_t *status, double *work,
+                      const LmpFin &f) {
     if (n <= 0 || nb <= 0) return hipSuccess;
     if (k <= 0 || k > LMP_K_MAX) return hipErrorInvalidValue;
     int rows, nrb;
     lmp_blocks(n, &rows, &nrb);
+    if (nrb > LMP_RB_MAX) return hipErrorInvalidValue;
     const int tiles = (nb + CT - 1) / CT, ldw = tiles * CT;
-    hipLaunchKernelGGL(k_lmp_proj, dim3(nrb, tiles), dim3(256), 0, s, n, k, nb, rows, Sr, X, ldx, status, work, ldw);
+    hipLaunchKernelGGL(k_lmp_proj<FIN>, dim3(nrb, tiles), dim3(512), 0, s, n, k, nb, rows, Sr, X, ldx, status, work,
+                       ldw, f);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (k <= 64)
-        hipLaunchKernelGGL(k_lmp_expand<64>, dim3((n + 127) / 128, tiles), dim3(256), 0, s, n, k, nb, nrb, S, coef, X,
-                           ldx, Y, ldy, status, work, ldw);
+        hipLaunchKernelGGL((k_lmp_expand<64, FIN>), dim3((n + 255) / 256, tiles), dim3(512), 0, s, n, k, nb, nrb, S,
+                           coef, X, ldx, Y, ldy, status, work, ldw, f);
     else
-        hipLaunchKernelGGL(k_lmp_expand<LMP_K_MAX>, dim3((n + 127) / 128, tiles), dim3(256), 0, s, n, k, nb, nrb, S,
-                           coef, X, ldx, Y, ldy, status, work, ldw);
+        hipLaunchKernelGGL((k_lmp_expand<LMP_K_MAX, FIN>), dim3((n + 255) / 256, tiles), dim3(512), 0, s, n, k, nb,
+                           nrb, S, coef, X, ldx, Y, ldy, status, work, ldw, f);
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_lmp(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
+                      const double *X, long long ldx, double *Y, long long ldy, const int32_t *status,
+                      double *work) {
+    // the plain form only reads X and status
+    return lmp_launch<false>(s, n, k, nb, S, Sr, coef, const_cast<double *>(X), ldx, Y, ldy,
+                             const_cast<int32_t *>(status), work, LmpFin{});
+}
+
+hipError_t launch_lmp_fin(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
+                          double *r, double *z, int32_t *status, double *work, const LmpFin &f) {
+    if (!status || f.pieces < 1) return hipErrorInvalidValue;
+    return lmp_launch<true>(s, n, k, nb, S, Sr, coef, r, n, z, n, status, work, f);
 }
 
 }  // namespace eda

@@ -80,6 +80,7 @@ def lib():
             "eda_profile_read": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(dbl)],
             "eda_destroy": [vp],
             "eda_set_geometry": [vp, i32, i32],
+            "eda_set_split": [vp, i32],
             "eda_mlp_param_count": [vp, ctypes.POINTER(i64)],
             "eda_mlp_workspace_bytes": [vp, i32, ctypes.POINTER(sz)],
             "eda_mlp_init": [vp, vp, vp, vp],
@@ -241,6 +242,11 @@ def eda_profile_read(ctx):
 
 def eda_set_geometry(ctx, waves: int, tb: int):
     _check("eda_set_geometry", lib().eda_set_geometry(ctx, int(waves), int(tb)))
+
+
+def eda_set_split(ctx, pieces: int):
+    """Pieces per member column in split PCG iterations (0: automatic)."""
+    _check("eda_set_split", lib().eda_set_split(ctx, int(pieces)))
 
 
 def eda_destroy(ctx):

@@ -31,9 +31,11 @@ def test_workspace_and_normals(name):
     b_band = eda.eda_workspace_bytes(c)
     b_dense = eda.eda_workspace_bytes(eda.make_config(cfg, ub_mode="dense"))
     n = cfg["n"]
-    assert b_dense - b_band >= 8 * n * n  # dense U_B stored only in dense mode
     traj = (cfg["members"] + 1) * (cfg["nsteps"] + 1) * n * 8
-    assert b_band > traj
+    assert b_dense >= 14 * n * n + traj  # U_B stored dense in FP64, FP32 and BF16
+    # the banded form holds a block of observed increments per piece of a split column
+    nt, nv = W.obs_counts(cfg)
+    assert b_band > traj + 8 * nt * nv * (cfg["members"] + 1) * 8
 
 
 @pytest.mark.parametrize("bad", [dict(n=3), dict(n=5000), dict(len_b=1.0), dict(obs_x0=40), dict(sigma_o=0.0),

@@ -362,6 +362,56 @@ def test_pcg_not_converged_and_deterministic():
     assert torch.equal(a["dz"][0], a["dz"][2])  # same member twice: same bits
 
 
+@pytest.mark.parametrize("case", ["n1001", "n2049"])
+def test_split_iterations_match_whole_columns(case):
+    # Split iterations (the Hessian part on P pieces per column, each with
+    # halos of 12 N + 2 w states) against whole columns (P = 1).  The pieces'
+    # outputs are the whole column's bits; only the order of the pieces'
+    # partial sums of p^T (I + A) p differs, so after 4 iterations the iterates
+    # agree to rounding; solved to rtol 1e-10 every P reaches the exact solution.
+    cfg, g, o = problem(case)
+    g.sketch_evd("rhs_diff")
+    members = np.arange(cfg["members"] + 1)
+    ref = None
+    for P in (1, 2, 4, 8):
+        eda.eda_set_split(g.ctx, P)
+        dz = g.pcg(members, rtol=0.0, maxit=4)["dz"].cpu().numpy()
+        if ref is None:
+            ref = dz
+        else:
+            assert rel(dz, ref) < 1e-12, (P, rel(dz, ref))
+    for P in (1, 8):
+        eda.eda_set_split(g.ctx, P)
+        out = g.pcg(members, rtol=1e-10, maxit=500, history=True)
+        assert np.all(out["status"] == eda.EDA_MEMBER_CONVERGED)
+        assert np.all(out["relres"] <= 1e-10)
+        for m in (0, cfg["members"]):
+            xe = O.exact_solution(o, m)
+            assert rel(out["dz"][m].cpu().numpy(), xe) < 1e-8, (P, m)
+            h = out["hist"][m][: out["iters"][m] + 1]
+            assert np.all(np.diff(h) <= 1e-10 * abs(h[-1]))  # the cost decreases
+    eda.eda_set_split(g.ctx, 0)
+    a = g.pcg(members, rtol=1e-8, maxit=500)
+    b = g.pcg(members, rtol=1e-8, maxit=500)
+    assert torch.equal(a["dz"], b["dz"])  # the automatic pieces do not depend on timing
+
+
+def test_split_errors():
+    cfg, g, o = problem("C1")  # n = 40: no ring shorter than n
+    with pytest.raises(eda.EdaError) as e:
+        eda.eda_set_split(g.ctx, 2)
+    assert e.value.code == eda.EDA_ERR_UNSUPPORTED
+    with pytest.raises(eda.EdaError) as e:
+        eda.eda_set_split(g.ctx, 3)
+    assert e.value.code == eda.EDA_ERR_INVALID_ARG
+    eda.eda_set_split(g.ctx, 1)
+    eda.eda_set_split(g.ctx, 0)
+    cfg, gd, o = problem("n1001", mode="dense")
+    with pytest.raises(eda.EdaError) as e:
+        eda.eda_set_split(gd.ctx, 2)
+    assert e.value.code == eda.EDA_ERR_UNSUPPORTED
+
+
 def test_profile_counts_pcg_tlad_launches():
     # the profile covers the TL/AD kernel inside eda_pcg_solve only: one fused
     # launch per iteration (banded U_B); Hessian products outside PCG are not
