@@ -88,11 +88,12 @@ def measured_traffic(active_per_launch):
 
 def pcg_kernel_bytes_per_col(cfg):
     """Algorithmic HBM bytes of one member column in one launch of the Hessian
-    part of a split PCG iteration: the trajectory read by the TL run and again
-    by the AD run (N states of n each), the observed increments written and
-    read back (p each), and the vectors: r, z read for r^T z; z and the old p
-    read for p; the new p and (I + A) p written.  The halos of a split column
-    are recomputation, not algorithmic traffic."""
+    part of a PCG iteration (whole column or split): the trajectory read by the
+    TL run and again by the AD run (N states of n each), the observed
+    increments written and read back (p each), and the vectors: r, z read for
+    r^T z; z and the old p read for p; the new p and (I + A) p written.  The
+    whole-column kernel also updates x and r (3 n more, not counted); the halos
+    of a split column are recomputation, not algorithmic traffic."""
     n, N = cfg["n"], cfg["nsteps"]
     nt, nv = W.obs_counts(cfg)
     return 8 * (2 * N * n + 2 * nt * nv + 6 * n)
@@ -365,8 +366,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(act_per_launch),
-                     "kernel": "k_tlad<double, Q, TLAD_SPLIT> (Hessian part of a PCG iteration on 1-8 pieces per member "
-                               "column: U_B, TL, AD, U_B, (I + A) p)",
+                     "kernel": "k_tlad<double, Q, 3|4> (Hessian part of a PCG iteration: U_B, TL, AD, U_B, (I + A) p; "
+                               "3 = whole columns with the update fused, 4 = 2-8 pieces per column)",
                      "bytes_per_column": bpc, "avg_launch_ms": round(avg_ms, 4),
                      "launches": chosen["tlad_launches"], "timed_launches": chosen["tlad_timed"], "active_column_iterations": chosen["active_cols"],
                      "kernel_sha": kernel_sha()},

@@ -203,7 +203,7 @@ TladArgs tlad_args(Ctx &c, int nb, const int32_t *cols, const int32_t *active) {
     return a;
 }
 
-int run_tlad(Ctx &c, const TladArgs &a, int mode, bool fp32) {
+int run_tlad(Ctx &c, const TladArgs &a, int mode, bool fp32, const SplitCols *sc = nullptr) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool rec = c.prof > 0 && c.in_pcg && c.prof_seen++ % c.prof == 0;
     if (rec) {
@@ -219,7 +219,7 @@ int run_tlad(Ctx &c, const TladArgs &a, int mode, bool fp32) {
         c.ev_used += 2;
         HIP_TRY(hipEventRecord(e0, c.stream));
     }
-    HIP_TRY(launch_tlad(c.stream, a, mode, fp32, c.geo_waves, c.geo_tb));
+    HIP_TRY(launch_tlad(c.stream, a, mode, fp32, c.geo_waves, c.geo_tb, sc));
     if (rec) {
         HIP_TRY(hipEventRecord(e1, c.stream));
         c.prof_launches++;
@@ -677,8 +677,13 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                               sizeof(int32_t) * Ctx::CK_SLOTS * (size_t)c.max_cols, hipHostMallocDefault));
         for (int i = 0; i < Ctx::CK_SLOTS; i++) HIP_TRY(hipEventCreateWithFlags(&c.ck_ev[i], hipEventDisableTiming));
     }
+    const bool fused = c.cfg.ub_mode == EDA_UB_BANDED;
+    // with the LMP, the banded form runs split iterations: the Hessian part on
+    // P pieces per column (P * running columns <= compute units), then the
+    // update fused with the LMP of the new residual
+    const bool split = fused && use_lmp;
     int ck_issued = 0, ck_done = 0;
-    std::vector<int> ck_running;  // running columns at each checkpoint read
+    std::vector<std::vector<int16_t>> ck_running;  // running columns at each checkpoint read
     bool none_running = false;
     auto consume = [&](bool block) -> int {  // read the oldest outstanding checkpoint
         const int slot = ck_done % Ctx::CK_SLOTS;
@@ -690,18 +695,19 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
             if (q != hipSuccess) return EDA_ERR_HIP;
         }
         const int32_t *st = c.h_ck + (size_t)slot * c.max_cols;
-        int running = 0;
-        for (int i = 0; i < nm; i++) running += (st[i] == COL_RUNNING);
-        ck_running.push_back(running);
-        none_running |= running == 0;
+        std::vector<int16_t> running;
+        if (split && nm <= SPLIT_LIST_MAX) {
+            for (int i = 0; i < nm; i++)
+                if (st[i] == COL_RUNNING) running.push_back((int16_t)i);
+        } else {
+            for (int i = 0; i < nm; i++)
+                if (st[i] == COL_RUNNING) running.push_back(0);  // only the count is used
+        }
+        none_running |= running.empty();
+        ck_running.push_back(std::move(running));
         ck_done++;
         return 1;
     };
-    const bool fused = c.cfg.ub_mode == EDA_UB_BANDED;
-    // with the LMP, the banded form runs split iterations: the Hessian part on
-    // P pieces per column (P * running columns <= compute units), then the
-    // update fused with the LMP of the new residual
-    const bool split = fused && use_lmp;
     double *pbuf[2] = {c.pc_p, c.pc_p2};
     int cur = 0;  // pbuf[cur] holds the current p
     bool stopped_early = false;
@@ -715,17 +721,24 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
         InPcg scope(c);
         for (int it = 1; it <= maxit; it++) {
             if (split) {
-                int P = c.split_force;
+                // running columns as of the checkpoint 16 .. 23 iterations back (waited
+                // for if need be, so that the pieces, and the rounding, of every
+                // iteration do not depend on timing): a superset of the running ones
+                SplitCols sc{};
+                int active = nm;
+                const int j = it / check_every - 3;
+                const std::vector<int16_t> *known = nullptr;
+                if (j >= 0 && j < ck_issued) {
+                    while (ck_done <= j) EDA_TRY(consume(true));
+                    known = &ck_running[j];
+                    active = (int)known->size();
+                }
+                if (nm <= SPLIT_LIST_MAX) {
+                    sc.count = known ? (int)known->size() : nm;
+                    for (int i = 0; i < sc.count; i++) sc.col[i] = known ? (*known)[i] : (int16_t)i;
+                }
+                int P = active == 0 ? 1 : c.split_force;
                 if (P == 0) {
-                    // running columns as of the checkpoint 16 .. 23 iterations back (waited
-                    // for if need be, so that the pieces, and the rounding, of every
-                    // iteration do not depend on timing)
-                    int active = nm;
-                    const int j = it / check_every - 3;
-                    if (j >= 0 && j < ck_issued) {
-                        while (ck_done <= j) EDA_TRY(consume(true));
-                        active = ck_running[j];
-                    }
                     P = 1;
                     for (int cand = 2; cand <= SPLIT_PMAX; cand *= 2)
                         if ((long long)cand * active <= c.num_cus && tlad_split_ring(n, c.N, c.band_hi, cand) > 0)
@@ -756,7 +769,7 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                     t.pcg.iters = c.pc_iters;
                     t.pcg.it = it;
                     t.pcg.first = it == 1 ? 1 : 0;
-                    EDA_TRY(run_tlad(c, t, TLAD_SPLIT, false));
+                    EDA_TRY(run_tlad(c, t, TLAD_SPLIT, false, &sc));
                     LmpFin f{};
                     f.q = c.pc_q;
                     f.p = pbuf[cur ^ 1];

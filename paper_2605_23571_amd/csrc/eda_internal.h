@@ -138,6 +138,15 @@ enum TladMode : int {
 // around them, H = 12 N + 2 band_hi (the TL/AD dependency cone over the window
 // plus U_B on both sides), so its owned outputs are exact.
 constexpr int SPLIT_PMAX = 8;
+// Columns of a split launch: workgroup b works on piece b / count of column
+// col[b % count], so the running columns' workgroups are contiguous and the
+// XCDs (dealt workgroups in turn) get equal shares.  count = 0: every column
+// of the launch (col[i] = i).
+constexpr int SPLIT_LIST_MAX = 256;
+struct SplitCols {
+    int32_t count;
+    int16_t col[SPLIT_LIST_MAX];
+};
 int tlad_split_halo(int N, int band_hi);
 int tlad_split_ring(int n, int N, int band_hi, int pieces);  // 0: not possible (ring longer than n)
 
@@ -196,7 +205,9 @@ void tlad_pads(int n, int *pad_l, int *pad_r);
 // The same, also covering the rings of every split (pieces 2 .. SPLIT_PMAX).
 void tlad_pads_split(int n, int N, int band_hi, int *pad_l, int *pad_r);
 // waves, tb: geometry override (0: the default for n).
-hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32, int waves = 0, int tb = 0);
+// sc: TLAD_SPLIT only (null: every column).
+hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32, int waves = 0, int tb = 0,
+                       const SplitCols *sc = nullptr);
 
 // U_B first row (closed form) and dense fill.
 hipError_t launch_ub_row(hipStream_t s, int n, double sigma_b, double len_b, double *row);

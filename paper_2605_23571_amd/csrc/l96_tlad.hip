@@ -607,14 +607,25 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
 template <typename T, int Q, int MODE>
 __global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
     extern __shared__ __align__(16) unsigned char smraw[];
-    const int c = MODE == TLAD_SPLIT ? blockIdx.x / a.pieces : blockIdx.x;
-    const int piece = MODE == TLAD_SPLIT ? blockIdx.x % a.pieces : 0;
-    if (MODE == TLAD_PCG || MODE == TLAD_SPLIT) {
+    const int c = blockIdx.x;
+    if (MODE == TLAD_PCG) {
         if (a.pcg.status[c] != COL_RUNNING) return;
     } else if (a.active && a.active[c] != COL_RUNNING) {
         return;
     }
-    tlad_column<T, Q, MODE>(a, g, c, a.pcg.it, a.pcg.first, smraw, piece);
+    tlad_column<T, Q, MODE>(a, g, c, a.pcg.it, a.pcg.first, smraw);
+}
+
+// Split iterations: workgroup b takes piece b / m of column col[b % m]
+// (m = sc.count, or every column), pieces in piece-major order.
+template <int Q>
+__global__ __launch_bounds__(512) void k_tlad_split(TladArgs a, TladGeom g, SplitCols sc) {
+    extern __shared__ __align__(16) unsigned char smraw[];
+    const int m = sc.count > 0 ? sc.count : a.nb;
+    const int c = sc.count > 0 ? sc.col[blockIdx.x % m] : (int)(blockIdx.x % m);
+    const int piece = blockIdx.x / m;
+    if (a.pcg.status[c] != COL_RUNNING) return;
+    tlad_column<double, Q, TLAD_SPLIT>(a, g, c, a.pcg.it, a.pcg.first, smraw, piece);
 }
 
 // z = P r = r + S diag(coef) S^T r for one column (in-kernel LMP of the
@@ -768,7 +779,7 @@ size_t lds_bytes(const TladArgs &a, const TladGeom &g, int mode) {
 }
 
 template <typename T, int Q>
-hipError_t launch_q(hipStream_t s, const TladArgs &a, const TladGeom &g, int mode) {
+hipError_t launch_q(hipStream_t s, const TladArgs &a, const TladGeom &g, int mode, const SplitCols *sc) {
     const size_t lds = lds_bytes<T, Q>(a, g, mode);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     const dim3 block(64 * g.waves);
@@ -777,29 +788,30 @@ hipError_t launch_q(hipStream_t s, const TladArgs &a, const TladGeom &g, int mod
         case TLAD_ADJ: hipLaunchKernelGGL((k_tlad<T, Q, TLAD_ADJ>), dim3(a.nb), block, lds, s, a, g); break;
         case TLAD_HV: hipLaunchKernelGGL((k_tlad<T, Q, TLAD_HV>), dim3(a.nb), block, lds, s, a, g); break;
         case TLAD_PCG: hipLaunchKernelGGL((k_tlad<T, Q, TLAD_PCG>), dim3(a.nb), block, lds, s, a, g); break;
-        case TLAD_SPLIT:
-            if constexpr (std::is_same<T, double>::value) {
-                hipLaunchKernelGGL((k_tlad<T, Q, TLAD_SPLIT>), dim3(a.nb * a.pieces), block, lds, s, a, g);
-                break;
-            } else {
-                return hipErrorInvalidValue;
-            }
+        case TLAD_SPLIT: {
+            if (!std::is_same<T, double>::value) return hipErrorInvalidValue;
+            SplitCols all{};
+            const SplitCols &cs = sc ? *sc : all;
+            const int m = cs.count > 0 ? cs.count : a.nb;
+            hipLaunchKernelGGL(k_tlad_split<Q>, dim3(m * a.pieces), block, lds, s, a, g, cs);
+            break;
+        }
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_t(hipStream_t s, const TladArgs &a, const TladGeom &g, int mode) {
+hipError_t launch_t(hipStream_t s, const TladArgs &a, const TladGeom &g, int mode, const SplitCols *sc) {
     switch (g.q) {
-        case 2: return launch_q<T, 2>(s, a, g, mode);
-        case 3: return launch_q<T, 3>(s, a, g, mode);
-        case 4: return launch_q<T, 4>(s, a, g, mode);
-        case 5: return launch_q<T, 5>(s, a, g, mode);
-        case 6: return launch_q<T, 6>(s, a, g, mode);
-        case 7: return launch_q<T, 7>(s, a, g, mode);
-        case 8: return launch_q<T, 8>(s, a, g, mode);
-        case 9: return launch_q<T, 9>(s, a, g, mode);
+        case 2: return launch_q<T, 2>(s, a, g, mode, sc);
+        case 3: return launch_q<T, 3>(s, a, g, mode, sc);
+        case 4: return launch_q<T, 4>(s, a, g, mode, sc);
+        case 5: return launch_q<T, 5>(s, a, g, mode, sc);
+        case 6: return launch_q<T, 6>(s, a, g, mode, sc);
+        case 7: return launch_q<T, 7>(s, a, g, mode, sc);
+        case 8: return launch_q<T, 8>(s, a, g, mode, sc);
+        case 9: return launch_q<T, 9>(s, a, g, mode, sc);
         default: return hipErrorInvalidValue;
     }
 }
@@ -977,7 +989,8 @@ void tlad_pads_split(int n, int N, int band_hi, int *pad_l, int *pad_r) {
     *pad_r = pr;
 }
 
-hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32, int waves, int tb) {
+hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32, int waves, int tb,
+                       const SplitCols *sc) {
     if (a.nb <= 0) return hipSuccess;
     if (mode == TLAD_SPLIT) {
         if (fp32 || a.pieces < 1 || a.ring < 1 || a.ring > a.n) return hipErrorInvalidValue;
@@ -989,7 +1002,12 @@ hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32, in
     TladGeom g = tlad_geometry(R, waves, tb);
     if (g.q > 9 || g.tb < 1) return hipErrorInvalidValue;
     if (mode == TLAD_PCG && fp32) return hipErrorInvalidValue;  // PCG recurrences stay FP64
-    return fp32 ? launch_t<float>(s, a, g, mode) : launch_t<double>(s, a, g, mode);
+    if (sc) {
+        if (sc->count < 0 || sc->count > SPLIT_LIST_MAX || sc->count > a.nb) return hipErrorInvalidValue;
+        for (int i = 0; i < sc->count; i++)
+            if (sc->col[i] < 0 || sc->col[i] >= a.nb) return hipErrorInvalidValue;
+    }
+    return fp32 ? launch_t<float>(s, a, g, mode, sc) : launch_t<double>(s, a, g, mode, sc);
 }
 
 }  // namespace eda
