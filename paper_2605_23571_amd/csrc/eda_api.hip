@@ -995,6 +995,9 @@ struct eda_batch {
     double rtol = -1.0;
     hipGraph_t graph = nullptr, graph_sk = nullptr;
     hipGraphExec_t exec = nullptr, exec_sk = nullptr;
+    // pinned decision slots of the lockstep sketch fallback
+    int32_t *h_fbi = nullptr;
+    double *h_fbd = nullptr;
 };
 
 namespace {
@@ -1244,6 +1247,181 @@ double now_ms() {
 
 }  // namespace
 
+namespace {
+
+// Lockstep shifted sketch.  For the problems whose unshifted sketch in the
+// graph failed, what eda_sketch_evd computes (RHS differences, one pass,
+// Nystrom, theta mid, FP64 products): CholQR2 of Y = A Gamma (CholQR3 with the
+// trace shift when the first Cholesky fails), W = Gamma^T Y and its Cholesky,
+// on failure the Nystrom shift Y + nu Gamma and the same again, then T, the
+// SVD, S and the LMP coefficients -- per problem the same kernels, arguments
+// and decisions, on the Y the graph already holds.  The problems are spread
+// over the batch's lanes and each decision waits once for all of them.
+// ok[t] = 0: the Cholesky failed after the shifts (EDA_ERR_NOT_SPD there).
+int batch_fallback(eda_batch &b, const std::vector<int> &ids, std::vector<char> &ok) {
+    const int m = (int)ids.size();
+    ok.assign(m, 1);
+    if (m == 0) return EDA_OK;
+    const int np = (int)b.probs.size();
+    int lmax = 1;
+    for (int i : ids) lmax = b.ell[i] > lmax ? b.ell[i] : lmax;
+    const size_t ds = (size_t)lmax + 2;  // doubles per problem: diag(G) or ||Y||^2, then theta
+    if (!b.h_fbi) {
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&b.h_fbi), sizeof(int32_t) * 8 * (size_t)np,
+                              hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&b.h_fbd), sizeof(double) * 130 * (size_t)np,
+                              hipHostMallocDefault));
+    }
+    const int nl = (int)b.lanes.size();
+    auto lane = [&](int t) { return b.lanes[t % nl]; };
+    auto wait_all = [&]() -> int {
+        for (auto st : b.lanes) HIP_TRY(hipStreamSynchronize(st));
+        return EDA_OK;
+    };
+    std::vector<double> nu(m, 0.0);
+    std::vector<int> passes(m, 2);
+    auto small = [&](int t, int slot) {
+        const Ctx &c = *b.probs[ids[t]];
+        return c.sk_small + (size_t)slot * c.max_ell * c.max_ell;
+    };
+    int32_t *hi = b.h_fbi;
+    double *hd = b.h_fbd;
+    // CholQR of each selected problem's Y into (Q, R_Y), as cholqr() does
+    auto cholqr = [&](const std::vector<int> &sel) -> int {
+        for (int t : sel) {
+            Ctx &c = *b.probs[ids[t]];
+            const int l = b.ell[ids[t]];
+            hipStream_t st = lane(t);
+            HIP_TRY(gemm_f64(st, true, l, l, c.n, c.sk_y, c.n, c.sk_y, c.n, small(t, 0), l, nullptr, 0, nullptr,
+                             c.splitk, c.splitk_elems));
+            HIP_TRY(launch_chol_inv(st, l, small(t, 0), 0.0, small(t, 1), small(t, 2), c.sk_info + 4));
+            HIP_TRY(hipMemcpyAsync(hi + 8 * t, c.sk_info + 4, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        }
+        EDA_TRY(wait_all());
+        std::vector<int> shifted;
+        for (int t : sel) {
+            passes[t] = 2;
+            if (hi[8 * t] == 0) continue;
+            shifted.push_back(t);
+            passes[t] = 3;
+            const int l = b.ell[ids[t]];
+            HIP_TRY(hipMemcpy2DAsync(hd + ds * t, sizeof(double), small(t, 0), sizeof(double) * (l + 1),
+                                     sizeof(double), l, hipMemcpyDeviceToHost, lane(t)));
+        }
+        if (!shifted.empty()) {
+            EDA_TRY(wait_all());
+            for (int t : shifted) {
+                Ctx &c = *b.probs[ids[t]];
+                const int l = b.ell[ids[t]];
+                double tr = 0.0;
+                for (int i = 0; i < l; i++) tr += hd[ds * t + i];
+                const double shift = 11.0 * ((double)c.n * l + (double)l * (l + 1)) * 2.220446049250313e-16 * tr;
+                HIP_TRY(launch_chol_inv(lane(t), l, small(t, 0), shift, small(t, 1), small(t, 2), c.sk_info + 4));
+                HIP_TRY(hipMemcpyAsync(hi + 8 * t, c.sk_info + 4, sizeof(int32_t), hipMemcpyDeviceToHost, lane(t)));
+            }
+            EDA_TRY(wait_all());
+            for (int t : shifted)
+                if (hi[8 * t] != 0) ok[t] = 0;
+        }
+        for (int t : sel) {
+            if (!ok[t]) continue;
+            Ctx &c = *b.probs[ids[t]];
+            const int l = b.ell[ids[t]];
+            hipStream_t st = lane(t);
+            HIP_TRY(gemm_f64(st, false, c.n, l, l, c.sk_y, c.n, small(t, 2), l, c.sk_q1, c.n, nullptr, 0, nullptr,
+                             nullptr, 0));
+            HIP_TRY(launch_copy_cols(st, l, l, small(t, 1), l, small(t, 5), l));
+            const double *Qin = c.sk_q1;
+            for (int pass = 2; pass <= passes[t]; pass++) {
+                double *Qout = (pass == passes[t]) ? c.sk_q : (Qin == c.sk_q1 ? c.sk_s : c.sk_q1);
+                HIP_TRY(gemm_f64(st, true, l, l, c.n, Qin, c.n, Qin, c.n, small(t, 0), l, nullptr, 0, nullptr,
+                                 c.splitk, c.splitk_elems));
+                HIP_TRY(launch_chol_inv(st, l, small(t, 0), 0.0, small(t, 3), small(t, 4), c.sk_info + 4 + pass));
+                HIP_TRY(gemm_f64(st, false, c.n, l, l, Qin, c.n, small(t, 4), l, Qout, c.n, nullptr, 0, nullptr,
+                                 nullptr, 0));
+                HIP_TRY(launch_small_gemm(st, l, false, false, small(t, 3), small(t, 5), small(t, 6)));
+                HIP_TRY(launch_copy_cols(st, l, l, small(t, 6), l, small(t, 5), l));
+                Qin = Qout;
+            }
+            HIP_TRY(launch_copy_cols(st, l, l, small(t, 5), l, small(t, 7), l));
+            HIP_TRY(hipMemcpyAsync(hi + 8 * t + 2, c.sk_info + 6, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        }
+        EDA_TRY(wait_all());
+        for (int t : sel)
+            if (ok[t] && (hi[8 * t + 2] != 0 || (passes[t] == 3 && hi[8 * t + 3] != 0))) ok[t] = 0;
+        return EDA_OK;
+    };
+    // W = Gamma^T Y, symmetrised; W = C^T C
+    auto cholw = [&](const std::vector<int> &sel) -> int {
+        for (int t : sel) {
+            if (!ok[t]) continue;
+            Ctx &c = *b.probs[ids[t]];
+            const int l = b.ell[ids[t]];
+            hipStream_t st = lane(t);
+            HIP_TRY(gemm_f64(st, true, l, l, c.n, c.sk_phi, c.n, c.sk_y, c.n, small(t, 8), l, nullptr, 0, nullptr,
+                             c.splitk, c.splitk_elems));
+            HIP_TRY(launch_sym(st, l, small(t, 8)));
+            HIP_TRY(launch_chol_inv(st, l, small(t, 8), 0.0, small(t, 9), small(t, 1), c.sk_info + 8));
+            HIP_TRY(hipMemcpyAsync(hi + 8 * t + 4, c.sk_info + 8, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        }
+        return wait_all();
+    };
+    std::vector<int> all(m);
+    for (int t = 0; t < m; t++) all[t] = t;
+    EDA_TRY(cholqr(all));
+    EDA_TRY(cholw(all));
+    std::vector<int> shiftw;
+    for (int t = 0; t < m; t++)
+        if (ok[t] && hi[8 * t + 4] != 0) shiftw.push_back(t);
+    if (!shiftw.empty()) {
+        // the Nystrom shift: Y <- Y + nu Gamma, nu = eps ||Y||_F
+        for (int t : shiftw) {
+            Ctx &c = *b.probs[ids[t]];
+            const int l = b.ell[ids[t]];
+            double *dscal = reinterpret_cast<double *>(c.sk_info + 16);
+            HIP_TRY(gemm_f64(lane(t), true, 1, 1, c.n * l, c.sk_y, c.n * l, c.sk_y, c.n * l, dscal, 1, nullptr, 0,
+                             nullptr, c.splitk, c.splitk_elems));
+            HIP_TRY(hipMemcpyAsync(hd + ds * t, dscal, sizeof(double), hipMemcpyDeviceToHost, lane(t)));
+        }
+        EDA_TRY(wait_all());
+        for (int t : shiftw) {
+            Ctx &c = *b.probs[ids[t]];
+            nu[t] = 2.220446049250313e-16 * std::sqrt(hd[ds * t]);
+            HIP_TRY(launch_axpy_cols(lane(t), c.n, b.ell[ids[t]], nu[t], c.sk_phi, c.n, c.sk_y, c.n));
+        }
+        EDA_TRY(cholqr(shiftw));
+        EDA_TRY(cholw(shiftw));
+        for (int t : shiftw)
+            if (ok[t] && hi[8 * t + 4] != 0) ok[t] = 0;
+    }
+    // T = R_Y C^-1, SVD T = U Sigma V^T, S = Q_Y U, D = Sigma^2 - nu
+    for (int t = 0; t < m; t++) {
+        if (!ok[t]) continue;
+        Ctx &c = *b.probs[ids[t]];
+        const int l = b.ell[ids[t]];
+        hipStream_t st = lane(t);
+        double *dscal = reinterpret_cast<double *>(c.sk_info + 16);
+        HIP_TRY(launch_small_gemm(st, l, false, false, small(t, 7), small(t, 1), small(t, 2)));
+        HIP_TRY(launch_jacobi_svd_u(st, l, small(t, 2), small(t, 3), small(t, 4)));
+        HIP_TRY(gemm_f64(st, false, c.n, l, l, c.sk_q, c.n, small(t, 3), l, c.sk_s, c.n, nullptr, 0, nullptr, nullptr,
+                         0));
+        HIP_TRY(launch_fix_signs(st, c.n, l, c.sk_s, c.n));
+        HIP_TRY(launch_lmp_coef(st, l, small(t, 4), nu[t], 1, EDA_THETA_MID, c.sk_eig, c.sk_coef, c.sk_coefu,
+                                dscal + 1));
+        HIP_TRY(hipMemcpyAsync(hd + ds * t + lmax, dscal + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    EDA_TRY(wait_all());
+    for (int t = 0; t < m; t++) {
+        if (!ok[t]) continue;
+        Ctx &c = *b.probs[ids[t]];
+        c.theta = hd[ds * t + lmax];
+        c.k = b.ell[ids[t]];
+    }
+    return EDA_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int eda_batch_workspace_bytes(eda_ctx *const *ctxs, int32_t np, size_t *bytes) {
@@ -1422,27 +1600,26 @@ int eda_batch_solve(eda_batch *b, int32_t k_cap, double rtol, int32_t maxit, int
         HIP_TRY(hipMemcpyAsync(flags.data(), b->d_flags, sizeof(int32_t) * np, hipMemcpyDeviceToHost, b->stream));
         HIP_TRY(hipStreamSynchronize(b->stream));
         t1 = now_ms();
+        std::vector<int> ids;
         for (int i = 0; i < np; i++) {
             Ctx &c = *b->probs[i];
             c.have_lmp = true;
             c.sr_ready = false;
             c.k = b->ell[i];
-            if (flags[i] == 0) continue;
-            fallbacks++;
-            hipStream_t keep = c.stream;
-            c.stream = b->stream;
-            int r = eda_sketch_evd(b->handles[i], EDA_SKETCH_RHS_DIFF, nullptr, 0, b->ell[i], b->ell[i], 1,
-                                   EDA_METHOD_NYSTROM, EDA_THETA_MID, 0, nullptr, nullptr);
-            if (r == EDA_ERR_NOT_SPD) {
+            if (flags[i] != 0) ids.push_back(i);
+        }
+        std::vector<char> ok;
+        EDA_TRY(batch_fallback(*b, ids, ok));
+        fallbacks = (int)ids.size();
+        for (size_t t = 0; t < ids.size(); t++) {
+            Ctx &c = *b->probs[ids[t]];
+            if (!ok[t]) {
                 unprec++;
                 c.have_lmp = false;
-                c.sr_ready = false;
-                r = launch_fill_int(c.stream, 1, 1, c.sk_info) == hipSuccess ? EDA_OK : EDA_ERR_HIP;
-            } else if (r >= 0) {
-                r = launch_fill_int(c.stream, 3, 0, c.sk_info) == hipSuccess ? EDA_OK : EDA_ERR_HIP;
+                HIP_TRY(launch_fill_int(b->stream, 1, 1, c.sk_info));
+            } else {
+                HIP_TRY(launch_fill_int(b->stream, 3, 0, c.sk_info));
             }
-            c.stream = keep;
-            if (r < 0) return r;
         }
     }
     const double t2 = now_ms();
@@ -1535,6 +1712,8 @@ int eda_batch_destroy(eda_batch *b) {
     for (auto ev : b->lane_done) (void)hipEventDestroy(ev);
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->entry) (void)hipEventDestroy(b->entry);
+    if (b->h_fbi) (void)hipHostFree(b->h_fbi);
+    if (b->h_fbd) (void)hipHostFree(b->h_fbd);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return EDA_OK;

@@ -166,3 +166,48 @@ def test_batch_near_full_rank_sketch_still_solves():
     bt.close()
     for g in probs:
         g.close()
+
+
+def test_batch_fallback_equals_single_problem_sketch():
+    # Problems whose unshifted sketch fails in the graph are redone in lockstep
+    # (shifted CholQR, Nystrom shift): per problem the kernels, arguments and
+    # decisions of eda_sketch_evd, so the eigenvalues and the Ritz basis are
+    # those of the single-problem sketch bit for bit (or both end NOT_SPD).
+    shapes = ((40, 10, 2.0), (40, 20, 2.0), (128, 10, 2.0), (64, 12, 2.0), (96, 8, 3.0))
+    cfgs = [W.config("C2", n=n, nsteps=N, members=40, ell=32, k=32, len_b=lb, problem_id=300 + i, spinup=100)
+            for i, (n, N, lb) in enumerate(shapes)]
+    zs = [W.problem_normals(c) for c in cfgs]
+    probs = [eda.Problem(c, z) for c, z in zip(cfgs, zs)]
+    bt = eda.Batch(probs)
+    redone, unprec = bt.solve(k_cap=32, rtol=1e-8, maxit=3000)
+    print(f"[batch] redone {redone}, without LMP {unprec}", flush=True)
+    assert redone >= 1
+    nsp = 0
+    for p, (cfg, z) in enumerate(zip(cfgs, zs)):
+        g = eda.Problem(cfg, z)
+        try:
+            eig_s, _ = g.sketch_evd("rhs_diff", ell=32, k=32)
+            S_s = g.field("S").cpu().numpy()
+            single_ok = True
+        except eda.EdaError as e:
+            assert e.code == eda.EDA_ERR_NOT_SPD
+            single_ok = False
+        g.close()
+        try:
+            eig_b = probs[p].field("eig").cpu().numpy()
+            S_b = probs[p].field("S").cpu().numpy()
+            batch_ok = True
+        except eda.EdaError as e:
+            assert e.code == eda.EDA_ERR_ORDER  # the batch solved this problem without LMP
+            batch_ok = False
+        assert batch_ok == single_ok, p
+        nsp += not batch_ok
+        if batch_ok:
+            assert np.array_equal(eig_b, eig_s), p
+            assert np.array_equal(S_b, S_s), p
+        res = bt.result(p)
+        assert (res["status"] == eda.EDA_MEMBER_CONVERGED).all(), (p, res["status"])
+    assert nsp == unprec
+    bt.close()
+    for g in probs:
+        g.close()
