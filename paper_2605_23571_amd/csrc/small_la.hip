@@ -11,6 +11,7 @@ namespace {
 
 constexpr int ST = 256;   // threads of the small kernels
 constexpr int SJ = 1024;  // threads of the Jacobi kernels (one wave per column pair)
+constexpr int SC = 1024;  // threads of the Cholesky kernel (element-parallel updates)
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -18,14 +19,19 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // W = C^T C with C upper triangular (W + shift I), then Cinv = C^-1.
-// info = 0 on success, j + 1 if pivot j is not positive.
-__global__ __launch_bounds__(ST) void k_chol_inv(int l, const double *__restrict__ W, double shift,
+// info = 0 on success, j + 1 if pivot j is not positive.  Right-looking: step j
+// takes the pivot, scales row j and updates the trailing upper triangle, all
+// threads in parallel (three barriers a step).  The inverse solves C X = I
+// from the last row up, X[i] /= C_ii then X[r] -= C_ri X[i] for r < i, in a
+// second LDS buffer when l <= 64; for larger l column j of X is built from the
+// finished columns, X_ij = -X_jj sum_{k=i}^{j-1} X_ik C_kj, in place.
+__global__ __launch_bounds__(SC) void k_chol_inv(int l, const double *__restrict__ W, double shift,
                                                  double *__restrict__ C, double *__restrict__ Cinv,
                                                  int32_t *__restrict__ info) {
-    extern __shared__ double S[];  // l x l, col-major; upper triangle becomes C
+    extern __shared__ double S[];  // l x l, col-major; upper triangle becomes C; then X (l <= 64)
     __shared__ int fail;
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < l * l; idx += ST) {
+    for (int idx = tid; idx < l * l; idx += SC) {
         int i = idx % l, j = idx / l;
         S[idx] = W[idx] + (i == j ? shift : 0.0);
     }
@@ -33,37 +39,63 @@ __global__ __launch_bounds__(ST) void k_chol_inv(int l, const double *__restrict
     __syncthreads();
     for (int j = 0; j < l; j++) {
         if (tid == 0) {
-            double dsum = S[j + j * l];
-            for (int k = 0; k < j; k++) dsum -= S[k + j * l] * S[k + j * l];
-            if (!(dsum > 0.0) || !isfinite(dsum)) fail = j + 1;
-            else S[j + j * l] = sqrt(dsum);
+            const double d = S[j + j * l];
+            if (!(d > 0.0) || !isfinite(d)) fail = j + 1;
+            else S[j + j * l] = sqrt(d);
         }
         __syncthreads();
         if (fail) break;
         const double piv = S[j + j * l];
-        for (int i = j + 1 + tid; i < l; i += ST) {
-            double v = S[j + i * l];
-            for (int k = 0; k < j; k++) v -= S[k + j * l] * S[k + i * l];
-            S[j + i * l] = v / piv;
+        for (int c = j + 1 + tid; c < l; c += SC) S[j + c * l] /= piv;
+        __syncthreads();
+        const int m = l - 1 - j;  // trailing block rows/columns j+1 .. l-1
+        for (int idx = tid; idx < m * m; idx += SC) {
+            const int r = j + 1 + idx % m, c = j + 1 + idx / m;
+            if (r <= c) S[r + c * l] -= S[j + r * l] * S[j + c * l];
         }
         __syncthreads();
     }
     if (tid == 0) *info = fail;
     if (fail) return;
-    for (int idx = tid; idx < l * l; idx += ST) {
+    for (int idx = tid; idx < l * l; idx += SC) {
         int i = idx % l, j = idx / l;
         C[idx] = (i <= j) ? S[idx] : 0.0;
     }
-    // column j of C^-1 by back substitution (upper triangular)
-    for (int j = tid; j < l; j += ST) {
-        double *x = Cinv + (long long)j * l;
-        for (int i = l - 1; i > j; i--) x[i] = 0.0;
-        x[j] = 1.0 / S[j + j * l];
-        for (int i = j - 1; i >= 0; i--) {
-            double v = 0.0;
-            for (int k = i + 1; k <= j; k++) v += S[i + k * l] * x[k];
-            x[i] = -v / S[i + i * l];
+    if (l <= 64) {
+        double *X = S + l * l;
+        for (int idx = tid; idx < l * l; idx += SC) X[idx] = (idx % l == idx / l) ? 1.0 : 0.0;
+        __syncthreads();
+        for (int i = l - 1; i >= 0; i--) {
+            const double cii = S[i + i * l];
+            for (int c = i + tid; c < l; c += SC) X[i + c * l] /= cii;
+            __syncthreads();
+            const int w = l - i;  // columns i .. l-1 of rows 0 .. i-1
+            for (int idx = tid; idx < i * w; idx += SC) {
+                const int r = idx % i, c = i + idx / i;
+                X[r + c * l] -= S[r + i * l] * X[i + c * l];
+            }
+            __syncthreads();
         }
+        for (int idx = tid; idx < l * l; idx += SC) {
+            int i = idx % l, j = idx / l;
+            Cinv[idx] = (i <= j) ? X[idx] : 0.0;
+        }
+        return;
+    }
+    for (int j = 0; j < l; j++) {
+        const double xjj = 1.0 / S[j + j * l];
+        double v = 0.0;
+        const int i = tid;
+        if (i < j)
+            for (int k = i; k < j; k++) v += S[i + k * l] * S[k + j * l];
+        __syncthreads();
+        if (i < j) S[i + j * l] = -xjj * v;
+        if (i == j) S[j + j * l] = xjj;
+        __syncthreads();
+    }
+    for (int idx = tid; idx < l * l; idx += SC) {
+        int i = idx % l, j = idx / l;
+        Cinv[idx] = (i <= j) ? S[idx] : 0.0;
     }
 }
 
@@ -117,7 +149,10 @@ __global__ __launch_bounds__(SJ) void k_jacobi_svd(int l, const double *__restri
     for (int idx = tid; idx < l * l; idx += SJ) A[idx] = T[idx];
     __syncthreads();
     const int m = (l + 1) & ~1;
-    const double tol = 1e-15;
+    // a pair is rotated while |t_p^T t_q| > l eps ||t_p|| ||t_q||: below that the
+    // product is at the rounding level of the wave sum, and rotating on noise
+    // would keep the sweeps from ending
+    const double tol = (double)l * 2.220446049250313e-16;
     for (int sweep = 0; sweep < 60; sweep++) {
         if (tid == 0) rotated = 0;
         __syncthreads();
@@ -197,7 +232,7 @@ __global__ __launch_bounds__(ST) void k_jacobi_eig(int l, const double *__restri
                 double c = 1.0, s = 0.0;
                 if (q < l) {
                     double apq = A[p + q * l], app = A[p + p * l], aqq = A[q + q * l];
-                    if (apq != 0.0 && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
+                    if (apq != 0.0 && fabs(apq) > (double)l * 2.220446049250313e-16 * sqrt(fabs(app * aqq))) {
                         double tau = (aqq - app) / (2.0 * apq);
                         double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                         c = 1.0 / sqrt(1.0 + t * t);
@@ -328,7 +363,8 @@ __global__ void k_copy_cols(int n, int nb, const double *__restrict__ X, long lo
 
 hipError_t launch_chol_inv(hipStream_t s, int l, const double *W, double shift, double *C, double *Cinv,
                            int32_t *info) {
-    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(ST), sizeof(double) * l * l, s, l, W, shift, C, Cinv, info);
+    const size_t lds = sizeof(double) * l * l * (l <= 64 ? 2 : 1);
+    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(SC), lds, s, l, W, shift, C, Cinv, info);
     return hipGetLastError();
 }
 
