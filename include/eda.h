@@ -364,9 +364,11 @@ int eda_batch_result(eda_batch *batch, int32_t p, double *d_DZ, int64_t ldz, int
                      int32_t *h_status);
 
 /* Tuning outcome of class cls (classes in increasing n), valid after the first
- * eda_batch_solve: h_out[8] = {n, problems, waves per workgroup, points per
- * lane, time-block length, persistent grid, member columns, tuned sketch launch
- * time in microseconds}.  Returns the number of classes. */
+ * eda_batch_solve: h_out[11] = {n, problems, solve waves per workgroup, solve
+ * points per lane, solve time-block length, persistent grid (one solve launch
+ * for all classes, the same for every class), member columns, tuned sketch
+ * launch time in microseconds, sketch waves, sketch points per lane, sketch
+ * time-block length}.  Returns the number of classes. */
 int eda_batch_tuning(eda_batch *batch, int32_t cls, int32_t *h_out);
 
 /* Wall times of the last eda_batch_solve in milliseconds: h_ms[0] the

@@ -967,20 +967,26 @@ struct eda_batch {
     char *ws = nullptr;
     TladArgs *d_solve = nullptr, *d_hv = nullptr;
     SolveTask *d_stasks = nullptr, *d_htasks = nullptr;
-    int *d_counters = nullptr;
+    int *d_counters = nullptr;            // SOLVE_QUEUES queue counters
+    int *d_qoff = nullptr;                // SOLVE_QUEUES + 1 queue offsets
+    TladGeom *d_geom = nullptr;           // solve geometry of each problem
+    int solve_waves = 0, solve_grid = 0;  // the one persistent solve launch
+    size_t solve_lds = 0;
     const int32_t **d_infoptr = nullptr;  // each problem's sketch outcome slots
     int32_t *d_flags = nullptr;           // gathered outcomes, one per problem
     int32_t *d_titer = nullptr;           // iterations of each solve task in the last call
-    std::vector<SolveTask> stasks;        // solve tasks, grouped by class, in queue order
+    std::vector<SolveTask> stasks;        // solve tasks in queue order
+    std::vector<int> qoff;                // host copy of d_qoff
     double last_ms[3] = {0.0, 0.0, 0.0};  // sketch graph, host fallback, solve graph
     struct Class {
         int n = 0;
         std::vector<int> members;  // problem indices
-        int s_off = 0, s_cnt = 0, h_off = 0, h_cnt = 0;
-        TladGeom g{};
+        int s_cnt = 0, h_off = 0, h_cnt = 0;
+        TladGeom g{};   // sketch-product geometry (tuned)
+        TladGeom gs{};  // solve geometry (the launch's common waves)
         size_t lds_solve = 0, lds_hv = 0;
-        int grid = 0;
         double tune_us = 0.0;
+        std::vector<std::pair<TladGeom, float>> timed;  // tuner candidates and their times
         hipStream_t side = nullptr;
         hipEvent_t done = nullptr;
     };
@@ -1003,7 +1009,7 @@ struct eda_batch {
 namespace {
 
 struct BatchPlan {
-    size_t off_solve, off_hv, off_st, off_ht, off_cnt, off_iptr, off_flags, off_titer, total;
+    size_t off_solve, off_hv, off_st, off_ht, off_cnt, off_qoff, off_geom, off_iptr, off_flags, off_titer, total;
 };
 
 BatchPlan batch_plan(eda_ctx *const *ctxs, int np) {
@@ -1019,7 +1025,9 @@ BatchPlan batch_plan(eda_ctx *const *ctxs, int np) {
     P.off_hv = lay.take(sizeof(TladArgs) * np);
     P.off_st = lay.take(sizeof(SolveTask) * (st ? st : 1));
     P.off_ht = lay.take(sizeof(SolveTask) * (ht ? ht : 1));
-    P.off_cnt = lay.take(sizeof(int) * np);
+    P.off_cnt = lay.take(sizeof(int) * SOLVE_QUEUES);
+    P.off_qoff = lay.take(sizeof(int) * (SOLVE_QUEUES + 1));
+    P.off_geom = lay.take(sizeof(TladGeom) * np);
     P.off_iptr = lay.take(sizeof(int32_t *) * np);
     P.off_flags = lay.take(sizeof(int32_t) * np);
     P.off_titer = lay.take(sizeof(int32_t) * (st ? st : 1));
@@ -1103,16 +1111,60 @@ int batch_class_lds(eda_batch &b, eda_batch::Class &k, const TladGeom &g, size_t
     return (lds_solve + 4096 <= 160 * 1024 && lds_hv <= 160 * 1024) ? EDA_OK : EDA_ERR_UNSUPPORTED;
 }
 
+// Dynamic LDS and grid of the one persistent solve launch from the classes'
+// solve geometries; each class's sketch LDS from its sketch geometry.
+int batch_solve_layout(eda_batch &b) {
+    size_t lds = 0;
+    int cols = 0;
+    for (auto &k : b.classes) {
+        size_t ls, lh, ls2, lh2;
+        EDA_TRY(batch_class_lds(b, k, k.g, ls, lh));
+        EDA_TRY(batch_class_lds(b, k, k.gs, ls2, lh2));
+        k.lds_hv = lh;
+        k.lds_solve = ls2;
+        if (ls2 > lds) lds = ls2;
+        cols += k.s_cnt;
+    }
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
+    const int per_cu = solve_blocks_per_cu(b.solve_waves, lds);
+    const int grid = (per_cu > 0 ? per_cu : 1) * cus;
+    b.solve_lds = lds;
+    b.solve_grid = grid < cols ? grid : cols;
+    return EDA_OK;
+}
+
+// Solve geometry of every class for a common number of waves W: the fastest
+// timed candidate with W waves, else the default time block for W.
+bool batch_solve_geometry(eda_batch &b, int W) {
+    for (auto &k : b.classes) {
+        if (!tlad_waves_ok(k.n, W)) return false;
+        float best = 1e30f;
+        TladGeom g = tlad_geometry(k.n, W);
+        for (const auto &c : k.timed)
+            if (c.first.waves == W && c.second < best) {
+                best = c.second;
+                g = c.first;
+            }
+        size_t ls, lh;
+        if (batch_class_lds(b, k, g, ls, lh) != EDA_OK) return false;
+        k.gs = g;
+    }
+    b.solve_waves = W;
+    return true;
+}
+
 // Autotuner: per class, time the multi-problem sketch launch for each
 // candidate geometry (waves per workgroup around the default, time-block
-// length at its maximum and at half) and keep the fastest; the persistent
-// solve grid is what the CUs hold of that geometry.
+// length at its maximum and at half) and keep the fastest for the sketch.
+// The solve is one launch for all classes, so it takes one number of waves:
+// that of the class with the most work (members x window x n), each class
+// with its fastest time block at that width (8 waves where that width does
+// not fit every class).  The persistent grid is what the CUs hold.
 int batch_tune(eda_batch &b) {
     hipStream_t s = b.stream;
     for (size_t i = 0; i < b.probs.size(); i++)
         HIP_TRY(launch_gamma(s, b.probs[i]->n, b.ell[i], b.probs[i]->b, b.probs[i]->sk_phi));
-    int cus = 0;
-    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -1120,6 +1172,7 @@ int batch_tune(eda_batch &b) {
     for (auto &k : b.classes) {
         const TladGeom g0 = tlad_geometry(k.n, 0);
         double best = 1e300;
+        k.timed.clear();
         for (int w : {g0.waves / 2, g0.waves, g0.waves * 2}) {
             if (w < 1 || !tlad_waves_ok(k.n, w)) continue;
             const TladGeom gw = tlad_geometry(k.n, w);
@@ -1136,11 +1189,10 @@ int batch_tune(eda_batch &b) {
                 if (rc != EDA_OK) break;
                 float ms = 0.f;
                 (void)hipEventElapsedTime(&ms, e0, e1);
+                k.timed.push_back({g, ms});
                 if (ms < best) {
                     best = ms;
                     k.g = g;
-                    k.lds_solve = ls;
-                    k.lds_hv = lh;
                 }
             }
             if (rc != EDA_OK) break;
@@ -1151,18 +1203,89 @@ int batch_tune(eda_batch &b) {
             break;
         }
         k.tune_us = 1e3 * best / 3.0;
-        const int per_cu = solve_blocks_per_cu(k.g, k.lds_solve);
-        int grid = (per_cu > 0 ? per_cu : 1) * cus;
-        k.grid = grid < k.s_cnt ? grid : k.s_cnt;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (rc == EDA_OK) b.tuned = true;
-    return rc;
+    if (rc != EDA_OK) return rc;
+    const eda_batch::Class *big = nullptr;
+    double most = -1.0;
+    for (const auto &k : b.classes) {
+        double w = 0.0;
+        for (int i : k.members) w += (b.probs[i]->L + 1.0) * b.probs[i]->N * k.n;
+        if (w > most) {
+            most = w;
+            big = &k;
+        }
+    }
+    if (!batch_solve_geometry(b, big->g.waves) && !batch_solve_geometry(b, 8)) return EDA_ERR_UNSUPPORTED;
+    b.tuned = true;
+    return EDA_OK;
 }
 
 // Enqueue the batch's sketches (Gamma, products, Nystrom cores) and the
 // gathering of their Cholesky outcomes on b.stream (captured by the caller).
+// Queue layout of the next persistent solve.  The tasks are grouped by
+// problem and the problems dealt to the SOLVE_QUEUES queues, largest total
+// cost first, each onto the queue with the least cost so far.  Inside a queue
+// the problems come by decreasing cost of their costliest column and each
+// problem's columns by decreasing cost, so the longest columns start first.
+// cost[t] belongs to b.stasks[t].  b.stasks and b.qoff are rewritten and
+// uploaded on b.stream (the caller synchronises).
+int batch_schedule(eda_batch &b, const std::vector<long long> &cost) {
+    using Item = std::pair<long long, SolveTask>;
+    const int np = (int)b.probs.size();
+    std::vector<std::vector<Item>> cols(np);
+    std::vector<long long> total(np, 0), top(np, 0);
+    for (size_t t = 0; t < b.stasks.size(); t++) {
+        const int p = b.stasks[t].prob;
+        cols[p].push_back({cost[t], b.stasks[t]});
+        total[p] += cost[t];
+        top[p] = std::max(top[p], cost[t]);
+    }
+    for (auto &v : cols)
+        std::stable_sort(v.begin(), v.end(), [](const Item &x, const Item &y) {
+            if (x.first != y.first) return x.first > y.first;
+            return x.second.col < y.second.col;
+        });
+    std::vector<int> by_total;
+    for (int p = 0; p < np; p++)
+        if (!cols[p].empty()) by_total.push_back(p);
+    std::stable_sort(by_total.begin(), by_total.end(), [&](int x, int y) { return total[x] > total[y]; });
+    long long load[SOLVE_QUEUES] = {};
+    std::vector<std::vector<int>> queue(SOLVE_QUEUES);
+    for (int p : by_total) {
+        int q = 0;
+        for (int r = 1; r < SOLVE_QUEUES; r++)
+            if (load[r] < load[q]) q = r;
+        load[q] += total[p];
+        queue[q].push_back(p);
+    }
+    std::vector<SolveTask> out;
+    out.reserve(b.stasks.size());
+    b.qoff.assign(SOLVE_QUEUES + 1, 0);
+    for (int q = 0; q < SOLVE_QUEUES; q++) {
+        b.qoff[q] = (int)out.size();
+        std::stable_sort(queue[q].begin(), queue[q].end(), [&](int x, int y) { return top[x] > top[y]; });
+        for (int p : queue[q])
+            for (const Item &it : cols[p]) out.push_back(it.second);
+    }
+    b.qoff[SOLVE_QUEUES] = (int)out.size();
+    if (out.size() != b.stasks.size()) return EDA_ERR_INVALID_ARG;
+    b.stasks = out;
+    HIP_TRY(hipMemcpyAsync(b.d_stasks, b.stasks.data(), sizeof(SolveTask) * b.stasks.size(), hipMemcpyHostToDevice,
+                           b.stream));
+    HIP_TRY(hipMemcpyAsync(b.d_qoff, b.qoff.data(), sizeof(int) * b.qoff.size(), hipMemcpyHostToDevice, b.stream));
+    return EDA_OK;
+}
+
+// Expected cost of one iteration of a column of problem p: window steps x
+// points per lane of its solve geometry (all classes share the waves).
+long long batch_step_cost(const eda_batch &b, int p) {
+    for (const auto &k : b.classes)
+        if (k.n == b.probs[p]->n) return (long long)b.probs[p]->N * k.gs.q;
+    return b.probs[p]->N;
+}
+
 int batch_enqueue_sketch(eda_batch &b) {
     hipStream_t s = b.stream;
     for (size_t i = 0; i < b.probs.size(); i++)
@@ -1192,19 +1315,12 @@ int batch_enqueue_sketch(eda_batch &b) {
     return EDA_OK;
 }
 
-// Enqueue the persistent solves, one branch per class.
+// Enqueue the persistent solve: one launch over the tasks of every class.
 int batch_enqueue_solve(eda_batch &b) {
     hipStream_t s = b.stream;
-    HIP_TRY(launch_fill_int(s, (int)b.classes.size(), 0, b.d_counters));
-    HIP_TRY(hipEventRecord(b.fork, s));
-    for (size_t ci = 0; ci < b.classes.size(); ci++) {
-        auto &k = b.classes[ci];
-        HIP_TRY(hipStreamWaitEvent(k.side, b.fork, 0));
-        HIP_TRY(launch_solve(k.side, b.d_solve, b.d_stasks + k.s_off, k.s_cnt, b.d_counters + ci, k.g, k.lds_solve,
-                             k.grid));
-        HIP_TRY(hipEventRecord(k.done, k.side));
-        HIP_TRY(hipStreamWaitEvent(s, k.done, 0));
-    }
+    HIP_TRY(launch_fill_int(s, SOLVE_QUEUES, 0, b.d_counters));
+    HIP_TRY(launch_solve(s, b.d_solve, b.d_geom, b.d_stasks, (int)b.stasks.size(), b.d_qoff, b.d_counters,
+                         b.solve_waves, b.solve_lds, b.solve_grid));
     return EDA_OK;
 }
 
@@ -1470,6 +1586,8 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
     b->d_stasks = reinterpret_cast<SolveTask *>(b->ws + P.off_st);
     b->d_htasks = reinterpret_cast<SolveTask *>(b->ws + P.off_ht);
     b->d_counters = reinterpret_cast<int *>(b->ws + P.off_cnt);
+    b->d_qoff = reinterpret_cast<int *>(b->ws + P.off_qoff);
+    b->d_geom = reinterpret_cast<TladGeom *>(b->ws + P.off_geom);
     b->d_infoptr = reinterpret_cast<const int32_t **>(b->ws + P.off_iptr);
     b->d_flags = reinterpret_cast<int32_t *>(b->ws + P.off_flags);
     b->d_titer = reinterpret_cast<int32_t *>(b->ws + P.off_titer);
@@ -1548,43 +1666,36 @@ int eda_batch_solve(eda_batch *b, int32_t k_cap, double rtol, int32_t maxit, int
         for (int i = 0; i < np; i++) batch_args(*b, i, sa[i], ha[i]);
         std::vector<SolveTask> st, ht;
         for (auto &k : b->classes) {
-            k.s_off = (int)st.size();
+            const size_t s0 = st.size();
             k.h_off = (int)ht.size();
             for (int i : k.members) {
                 for (int j = 0; j <= b->probs[i]->L; j++) st.push_back(SolveTask{i, j});
                 for (int j = 0; j < b->ell[i]; j++) ht.push_back(SolveTask{i, j});
             }
-            k.s_cnt = (int)st.size() - k.s_off;
+            k.s_cnt = (int)(st.size() - s0);
             k.h_cnt = (int)ht.size() - k.h_off;
-            // queue order: longest expected task first (window length, then
-            // ensemble size); later calls reorder by measured cost
-            std::stable_sort(st.begin() + k.s_off, st.end(), [&](const SolveTask &x, const SolveTask &y) {
-                const Ctx &a = *b->probs[x.prob], &c = *b->probs[y.prob];
-                return a.N != c.N ? a.N > c.N : a.L > c.L;
-            });
         }
         hipStream_t s = b->stream;
         HIP_TRY(hipMemcpyAsync(b->d_solve, sa.data(), sizeof(TladArgs) * np, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(b->d_hv, ha.data(), sizeof(TladArgs) * np, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(b->d_stasks, st.data(), sizeof(SolveTask) * st.size(), hipMemcpyHostToDevice, s));
-        b->stasks = st;
         HIP_TRY(hipMemcpyAsync(b->d_htasks, ht.data(), sizeof(SolveTask) * ht.size(), hipMemcpyHostToDevice, s));
         std::vector<const int32_t *> ip(np);
         for (int i = 0; i < np; i++) ip[i] = b->probs[i]->sk_info;
         HIP_TRY(hipMemcpyAsync(b->d_infoptr, ip.data(), sizeof(int32_t *) * np, hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (!b->tuned) EDA_TRY(batch_tune(*b));
-        for (auto &k : b->classes) {
-            size_t ls, lh;
-            EDA_TRY(batch_class_lds(*b, k, k.g, ls, lh));
-            k.lds_solve = ls;
-            k.lds_hv = lh;
-            const int per_cu = solve_blocks_per_cu(k.g, ls);
-            int cus = 0;
-            HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
-            const int grid = (per_cu > 0 ? per_cu : 1) * cus;
-            k.grid = grid < k.s_cnt ? grid : k.s_cnt;
-        }
+        EDA_TRY(batch_solve_layout(*b));
+        std::vector<TladGeom> geo(np);
+        for (const auto &k : b->classes)
+            for (int i : k.members) geo[i] = k.gs;
+        HIP_TRY(hipMemcpyAsync(b->d_geom, geo.data(), sizeof(TladGeom) * np, hipMemcpyHostToDevice, s));
+        // first queue layout from the expected cost of a column (one
+        // iteration each); later calls use the measured cost
+        b->stasks = st;
+        std::vector<long long> cost0(st.size());
+        for (size_t t = 0; t < st.size(); t++) cost0[t] = batch_step_cost(*b, st[t].prob);
+        EDA_TRY(batch_schedule(*b, cost0));
+        HIP_TRY(hipStreamSynchronize(s));
         if (b->use_lmp) EDA_TRY(batch_capture(*b, batch_enqueue_sketch, b->graph_sk, b->exec_sk));
         EDA_TRY(batch_capture(*b, batch_enqueue_solve, b->graph, b->exec));
     }
@@ -1626,25 +1737,17 @@ int eda_batch_solve(eda_batch *b, int32_t k_cap, double rtol, int32_t maxit, int
     HIP_TRY(hipGraphLaunch(b->exec, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     const double t3 = now_ms();
-    // schedule of the next call: within each class, tasks by decreasing measured
-    // cost (iterations x window length), so the longest columns start first
+    // queue layout of the next call from the measured cost of each column
+    // (iterations x window length)
     {
         const int nt = (int)b->stasks.size();
         std::vector<int32_t> its(nt);
         HIP_TRY(launch_task_iters(b->stream, nt, b->d_solve, b->d_stasks, b->d_titer));
         HIP_TRY(hipMemcpyAsync(its.data(), b->d_titer, sizeof(int32_t) * nt, hipMemcpyDeviceToHost, b->stream));
         HIP_TRY(hipStreamSynchronize(b->stream));
-        std::vector<std::pair<long long, SolveTask>> order(nt);
-        for (int t = 0; t < nt; t++)
-            order[t] = {(long long)its[t] * b->probs[b->stasks[t].prob]->N, b->stasks[t]};
-        for (auto &k : b->classes)
-            std::stable_sort(order.begin() + k.s_off, order.begin() + k.s_off + k.s_cnt,
-                             [](const std::pair<long long, SolveTask> &x, const std::pair<long long, SolveTask> &y) {
-                                 return x.first > y.first;
-                             });
-        for (int t = 0; t < nt; t++) b->stasks[t] = order[t].second;
-        HIP_TRY(hipMemcpyAsync(b->d_stasks, b->stasks.data(), sizeof(SolveTask) * nt, hipMemcpyHostToDevice,
-                               b->stream));
+        std::vector<long long> cost(nt);
+        for (int t = 0; t < nt; t++) cost[t] = (long long)its[t] * batch_step_cost(*b, b->stasks[t].prob);
+        EDA_TRY(batch_schedule(*b, cost));
         HIP_TRY(hipStreamSynchronize(b->stream));
     }
     b->last_ms[0] = t1 - t0;
@@ -1686,12 +1789,15 @@ int eda_batch_tuning(eda_batch *b, int32_t cls, int32_t *h_out) {
     const auto &k = b->classes[cls];
     h_out[0] = k.n;
     h_out[1] = (int32_t)k.members.size();
-    h_out[2] = k.g.waves;
-    h_out[3] = k.g.q;
-    h_out[4] = k.g.tb;
-    h_out[5] = k.grid;
+    h_out[2] = k.gs.waves;
+    h_out[3] = k.gs.q;
+    h_out[4] = k.gs.tb;
+    h_out[5] = b->solve_grid;
     h_out[6] = k.s_cnt;
     h_out[7] = (int32_t)(k.tune_us + 0.5);
+    h_out[8] = k.g.waves;
+    h_out[9] = k.g.q;
+    h_out[10] = k.g.tb;
     return (int32_t)b->classes.size();
 }
 

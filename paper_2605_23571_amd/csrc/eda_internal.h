@@ -184,12 +184,18 @@ TladGeom tlad_geometry(int n, int waves_hint, int tb_hint = 0);
 bool tlad_waves_ok(int n, int waves);
 // Bytes of dynamic LDS one column of this problem needs in the given mode.
 size_t tlad_lds_bytes(const TladArgs &a, const TladGeom &g, int mode);
-// Persistent batched PCG: every workgroup takes tasks from *counter (zeroed
-// before the launch) until ntasks are handed out; each task is a whole LMP-PCG
-// solve of one column (init, iterations, in-kernel LMP, final status).  probs
-// holds one TladArgs per problem (device memory); all share n and geometry g.
-hipError_t launch_solve(hipStream_t s, const TladArgs *d_probs, const SolveTask *d_tasks, int ntasks,
-                        int *d_counter, const TladGeom &g, size_t lds, int grid);
+// Persistent batched PCG over ntasks tasks cut into SOLVE_QUEUES queues: queue
+// q is tasks [qoff[q], qoff[q+1]) (qoff: SOLVE_QUEUES + 1 ints in device
+// memory, 0 = qoff[0] <= ... <= qoff[SOLVE_QUEUES] = ntasks) with counter
+// counters[q] (zeroed before the launch).  Workgroup b starts on queue
+// b mod SOLVE_QUEUES (its XCD) and moves to the next queues as they run dry;
+// each task is a whole LMP-PCG solve of one column (init, iterations,
+// in-kernel LMP, final status).  probs and geoms hold one TladArgs and one
+// geometry per problem (device memory); every geometry has `waves` waves, and
+// lds covers the largest problem's dynamic LDS.
+constexpr int SOLVE_QUEUES = 8;
+hipError_t launch_solve(hipStream_t s, const TladArgs *d_probs, const TladGeom *d_geoms, const SolveTask *d_tasks,
+                        int ntasks, const int *d_qoff, int *d_counters, int waves, size_t lds, int grid);
 // Hessian products (banded U_B, HV mode) for a list of (problem, column) tasks
 // of problems sharing n: one workgroup per task.
 hipError_t launch_hv_multi(hipStream_t s, const TladArgs *d_probs, const SolveTask *d_tasks, int ntasks,
@@ -197,8 +203,8 @@ hipError_t launch_hv_multi(hipStream_t s, const TladArgs *d_probs, const SolveTa
 // out[t] = iteration count of task t (probs[tasks[t].prob].pcg.iters[col]).
 hipError_t launch_task_iters(hipStream_t s, int ntasks, const TladArgs *d_probs, const SolveTask *d_tasks,
                              int32_t *d_out);
-// Workgroups of k_solve one CU holds for this geometry and LDS size.
-int solve_blocks_per_cu(const TladGeom &g, size_t lds);
+// Workgroups of k_solve (waves waves each) one CU holds with this dynamic LDS.
+int solve_blocks_per_cu(int waves, size_t lds);
 // Pads of the periodic row extension that every wave window of the TL/AD
 // kernel fits in without wrapping: window points j in [-pad_l, n + pad_r).
 void tlad_pads(int n, int *pad_l, int *pad_r);

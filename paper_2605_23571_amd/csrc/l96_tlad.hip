@@ -31,7 +31,6 @@
 // PCG iteration for its member: p = z + beta p, q = (I + A) p, alpha, x and r
 // updates, the convergence test -- one launch in place of eight.
 #include <type_traits>
-#include <utility>
 
 #include "eda_internal.h"
 
@@ -109,48 +108,33 @@ __device__ __forceinline__ int wpos(int base, int q, int n) {
     return p >= n ? p - n : p;
 }
 
-// Copy i of a window: the instruction's immediate offset (applied to both the
-// global and the LDS address) carries 256 (i % 16) bytes; every 16 copies the
-// two bases advance by 4096 bytes, kept out of the 13-bit offset field.
-template <int I>
-__device__ __forceinline__ void lds_copy(const char *g, char *l) {
-    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)g,
-                                     (void __attribute__((address_space(3))) *)l, 4, 256 * (I % 16), 0);
-}
-template <int BASE, int... I>
-__device__ __forceinline__ void lds_copy_run(const char *g, char *l, std::integer_sequence<int, I...>) {
-    (lds_copy<BASE + I>(g, l), ...);
-}
-
-// Start the asynchronous copy of this wave's trajectory window -- 64 Q
-// consecutive doubles of a padded state row, from xe on -- into the wave's LDS
-// slice: 2Q direct global-to-LDS dword copies, lane l of copy i moving dword
-// 64 i + l, so slice[j] = xe[j].  No registers are held while it is in flight.
+// Copy this wave's trajectory window -- 64 Q consecutive doubles of a padded
+// state row, from xe on -- into the wave's LDS slice: Q coalesced loads (lane
+// l of load i takes double 64 i + l) into registers, then the same pattern of
+// LDS stores, so slice[j] = xe[j].  The stores have the type of read_window's
+// loads, so the compiler keeps them after the previous step's reads.  The
+// copy goes through registers on purpose: direct global-to-LDS copies were
+// measured to deliver stale or misplaced words now and then when workgroups
+// share a CU, even behind a vector-memory wait.
 template <int Q>
 __device__ __forceinline__ void prefetch_window(const double *xe, double *slice) {
-    static_assert(2 * Q <= 32, "window copies: two runs of at most 16");
     const int lane = threadIdx.x & 63;
-    const char *g = reinterpret_cast<const char *>(xe) + 4 * lane;
-    char *l = reinterpret_cast<char *>(slice);
-    constexpr int R0 = 2 * Q < 16 ? 2 * Q : 16;
-    lds_copy_run<0>(g, l, std::make_integer_sequence<int, R0>{});
-    if constexpr (2 * Q > 16) {
-        const char *g2 = g + 4096;
-        char *l2 = l + 4096;
-        asm volatile("" : "+v"(g2));  // opaque: the 4096 stays in the base, not the offset field
-        lds_copy_run<16>(g2, l2, std::make_integer_sequence<int, 2 * Q - 16>{});
-    }
+    const double *g = xe + lane;
+    double *l = slice + lane;
+    double v[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) v[i] = g[64 * i];
+#pragma unroll
+    for (int i = 0; i < Q; i++) l[64 * i] = v[i];
 }
 
-// This lane's Q window points from the wave's slice, once the copy has landed
-// (vmcnt(0)); the reads complete (lgkmcnt(0)) before the slice may be refilled.
+// This lane's Q window points from the wave's slice (written by the same wave:
+// its LDS stores and loads complete in order).
 template <typename T, int Q>
 __device__ __forceinline__ void read_window(const double *slice, T (&x)[Q]) {
     const int lane = threadIdx.x & 63;
-    __builtin_amdgcn_s_waitcnt(0x0F70);
 #pragma unroll
     for (int q = 0; q < Q; q++) x[q] = (T)slice[lane * Q + q];
-    __builtin_amdgcn_s_waitcnt(0xC07F);
 }
 
 // Observed increments R^-1 H dx of this lane's owned observed points.
@@ -372,8 +356,7 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
             for (int s = s0; s < s1; s++) {
                 T x[Q], Y[Q + 4], V[Q + 4], k[Q], dk[Q], acc[Q], ys[Q], vs[Q];
                 read_window<T, Q>(xw, x);
-                // observed increment of time s, stored here (after the wait on
-                // the window copy) so that no store is pending at the next wait
+                // observed increment of time s
                 if (s > 0 && s % a.obs_dt == 0)
                     store_obs<T, Q>(obs + (long long)(s / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
                 if (s + 1 < N) prefetch_window<Q>(trajm + (long long)(s + 1) * a.ext_len + w0, xw);
@@ -630,10 +613,23 @@ __global__ __launch_bounds__(512) void k_tlad_split(TladArgs a, TladGeom g, Spli
 
 // z = P r = r + S diag(coef) S^T r for one column (in-kernel LMP of the
 // persistent solve).  r is first staged in LDS (rs, n doubles).  t = coef .*
-// (S^T r): the k dot products are split over the waves, each lane keeps eight
-// independent partial sums so that sixteen loads are in flight, then a fixed
-// shuffle tree.  z = r + S t: rows over the threads, eight columns of S per
-// round.  r and z are the column's global vectors, tsh k doubles of LDS.
+// (S^T r): the k dot products are split over the waves; lane l keeps eight
+// partial sums, partial u mod 8 taking rows l + 64 u of each 512-row stride in
+// turn, then a fixed shuffle tree.  z = r + S t: rows over the threads, the
+// columns of S in order.  S lives in HBM or the last-level cache, so each step
+// is one memory round trip: the loads of up to four strides (phase one) or 32
+// columns (phase two) are issued together before the sums that use them, in
+// the same summation order as a stride-at-a-time loop.  r and z are the
+// column's global vectors, tsh k doubles of LDS.
+template <int U>
+__device__ __forceinline__ void lmp_dot_strides(const double *sj, const double *rs, int i, double (&acc)[8]) {
+    double sv[8 * U];
+#pragma unroll
+    for (int u = 0; u < 8 * U; u++) sv[u] = sj[i + u * 64];
+#pragma unroll
+    for (int u = 0; u < 8 * U; u++) acc[u & 7] += sv[u] * rs[i + u * 64];
+}
+
 __device__ __forceinline__ void lmp_column(const PcgCols &pc, int n, const double *r, double *z, double *rs,
                                            double *tsh, int waves) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x, nthr = blockDim.x;
@@ -646,9 +642,14 @@ __device__ __forceinline__ void lmp_column(const PcgCols &pc, int n, const doubl
 #pragma unroll
         for (int u = 0; u < 8; u++) acc[u] = 0.0;
         int i = lane;
-        for (; i + 7 * 64 < n; i += 8 * 64) {
-#pragma unroll
-            for (int u = 0; u < 8; u++) acc[u] += sj[i + u * 64] * rs[i + u * 64];
+        for (; i + 31 * 64 < n; i += 32 * 64) lmp_dot_strides<4>(sj, rs, i, acc);
+        if (i + 15 * 64 < n) {
+            lmp_dot_strides<2>(sj, rs, i, acc);
+            i += 16 * 64;
+        }
+        if (i + 7 * 64 < n) {
+            lmp_dot_strides<1>(sj, rs, i, acc);
+            i += 8 * 64;
         }
         for (; i < n; i += 64) acc[0] += sj[i] * rs[i];
         double sum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
@@ -657,99 +658,149 @@ __device__ __forceinline__ void lmp_column(const PcgCols &pc, int n, const doubl
     }
     __syncthreads();
     for (int i = tid; i < n; i += nthr) {
+        const double *si = pc.lmp_s + i;
         double v = rs[i];
         int j = 0;
+        for (; j + 32 <= k; j += 32) {
+            double sv[32];
+#pragma unroll
+            for (int u = 0; u < 32; u++) sv[u] = si[(long long)(j + u) * n];
+#pragma unroll
+            for (int u = 0; u < 32; u++) v += sv[u] * tsh[j + u];
+        }
         for (; j + 8 <= k; j += 8) {
             double sv[8];
 #pragma unroll
-            for (int u = 0; u < 8; u++) sv[u] = pc.lmp_s[i + (long long)(j + u) * n];
+            for (int u = 0; u < 8; u++) sv[u] = si[(long long)(j + u) * n];
 #pragma unroll
             for (int u = 0; u < 8; u++) v += sv[u] * tsh[j + u];
         }
-        for (; j < k; j++) v += pc.lmp_s[i + (long long)j * n] * tsh[j];
+        for (; j < k; j++) v += si[(long long)j * n] * tsh[j];
         z[i] = v;
     }
     __syncthreads();
 }
 
-// Persistent LMP-PCG over a task list: the same iteration as eda_pcg_solve's
-// fused path (tlad_column in PCG mode), with the LMP applied in-kernel, so a
-// column runs from x = 0 to its final status without leaving the workgroup.
-// Every workgroup exits once the counter passes ntasks; a task ends after at
-// most maxit iterations.
+// The whole LMP-PCG solve of column c of problem a (Q points per lane): the
+// same iteration as eda_pcg_solve's fused path (tlad_column in PCG mode),
+// with the LMP applied in-kernel, so the column runs from x = 0 to its final
+// status without leaving the workgroup; at most maxit iterations.
 template <int Q>
-__global__ __launch_bounds__(512) void k_solve(const TladArgs *__restrict__ probs,
-                                               const SolveTask *__restrict__ tasks, int ntasks, int *counter,
-                                               TladGeom g) {
-    extern __shared__ __align__(16) unsigned char smraw[];
-    __shared__ int s_task;
-    __shared__ double s_red[16];
-    __shared__ double s_t[128];
+__device__ __forceinline__ void solve_column(const TladArgs &a, const TladGeom &g, int c, unsigned char *smraw,
+                                             double *s_red, double *s_t) {
     const int tid = threadIdx.x, nthr = blockDim.x;
-    for (;;) {
-        if (tid == 0) s_task = atomicAdd(counter, 1);
+    const PcgCols &pc = a.pcg;
+    const int n = a.n;
+    const long long cn = (long long)c * n;
+    double *x = pc.x + cn, *r = pc.r + cn, *z = pc.z + cn;
+    const double *b = pc.b + (long long)pc.members[c] * n;
+    // x = 0, r = b, ||b||; history row
+    double bb = 0.0;
+    for (int i = tid; i < n; i += nthr) {
+        const double v = b[i];
+        x[i] = 0.0;
+        r[i] = v;
+        bb += v * v;
+    }
+    bb = block_sum(bb, s_red, nthr >> 6);
+    if (pc.hist)
+        for (int i = tid; i < pc.hist_cap; i += nthr)
+            pc.hist[(long long)c * pc.hist_cap + i] = i == 0 ? 0.0 : __builtin_nan("");
+    if (tid == 0) {
+        pc.scal[4 * c + 1] = sqrt(bb);
+        pc.scal[4 * c + 2] = bb > 0 ? 1.0 : 0.0;
+        pc.status[c] = bb > 0 ? COL_RUNNING : EDA_MEMBER_CONVERGED;
+        pc.iters[c] = 0;
+    }
+    __syncthreads();
+    if (!(bb > 0)) return;
+    // a sketch whose Cholesky failed gives no LMP: plain CG for its members
+    const bool lmp = pc.lmp_k > 0 && !(pc.lmp_info && (pc.lmp_info[0] | pc.lmp_info[1] | pc.lmp_info[2]));
+    if (lmp) {
+        lmp_column(pc, n, r, z, reinterpret_cast<double *>(smraw), s_t, nthr >> 6);
+    } else {
+        for (int i = tid; i < n; i += nthr) z[i] = r[i];
         __syncthreads();
-        const int t = s_task;
+    }
+    int st = COL_RUNNING;
+    for (int it = 1; it <= pc.maxit; it++) {
+        tlad_column<double, Q, TLAD_PCG>(a, g, c, it, it == 1, smraw);
         __syncthreads();
-        if (t >= ntasks) break;
-        const TladArgs &a = probs[tasks[t].prob];
-        const PcgCols &pc = a.pcg;
-        const int c = tasks[t].col, n = a.n;
-        const long long cn = (long long)c * n;
-        double *x = pc.x + cn, *r = pc.r + cn, *z = pc.z + cn;
-        const double *b = pc.b + (long long)pc.members[c] * n;
-        // x = 0, r = b, ||b||; history row
-        double bb = 0.0;
-        for (int i = tid; i < n; i += nthr) {
-            const double v = b[i];
-            x[i] = 0.0;
-            r[i] = v;
-            bb += v * v;
-        }
-        bb = block_sum(bb, s_red, nthr >> 6);
-        if (pc.hist)
-            for (int i = tid; i < pc.hist_cap; i += nthr)
-                pc.hist[(long long)c * pc.hist_cap + i] = i == 0 ? 0.0 : __builtin_nan("");
-        if (tid == 0) {
-            pc.scal[4 * c + 1] = sqrt(bb);
-            pc.scal[4 * c + 2] = bb > 0 ? 1.0 : 0.0;
-            pc.status[c] = bb > 0 ? COL_RUNNING : EDA_MEMBER_CONVERGED;
-            pc.iters[c] = 0;
-        }
+        st = pc.status[c];
         __syncthreads();
-        if (!(bb > 0)) continue;
-        // a sketch whose Cholesky failed gives no LMP: plain CG for its members
-        const bool lmp = pc.lmp_k > 0 && !(pc.lmp_info && (pc.lmp_info[0] | pc.lmp_info[1] | pc.lmp_info[2]));
+        if (st != COL_RUNNING) break;
         if (lmp) {
             lmp_column(pc, n, r, z, reinterpret_cast<double *>(smraw), s_t, nthr >> 6);
         } else {
             for (int i = tid; i < n; i += nthr) z[i] = r[i];
             __syncthreads();
         }
-        int st = COL_RUNNING;
-        for (int it = 1; it <= pc.maxit; it++) {
-            tlad_column<double, Q, TLAD_PCG>(a, g, c, it, it == 1, smraw);
-            __syncthreads();
-            st = pc.status[c];
-            __syncthreads();
-            if (st != COL_RUNNING) break;
-            if (lmp) {
-                lmp_column(pc, n, r, z, reinterpret_cast<double *>(smraw), s_t, nthr >> 6);
-            } else {
-                for (int i = tid; i < n; i += nthr) z[i] = r[i];
-                __syncthreads();
+    }
+    if (st == COL_RUNNING) {
+        // iteration limit: the breakdown test on r^T z that the next
+        // iteration would make, then not-converged
+        double rz = 0.0;
+        for (int i = tid; i < n; i += nthr) rz += r[i] * z[i];
+        rz = block_sum(rz, s_red, nthr >> 6);
+        if (tid == 0) pc.status[c] = (pc.maxit > 0 && !(rz > 0.0 && isfinite(rz))) ? EDA_MEMBER_BREAKDOWN
+                                                                                   : EDA_MEMBER_NOT_CONVERGED;
+    }
+    __syncthreads();
+}
+
+// Persistent LMP-PCG over a task list, one solve_column per task.  One launch
+// serves problems of every n: geoms[p] is problem p's geometry (all with
+// blockDim.x / 64 waves), and the workgroup takes the matching points-per-lane
+// instance for each task.  The list is cut into SOLVE_QUEUES queues, queue q =
+// tasks [qoff[q], qoff[q+1]) with its own counter.  Workgroups are dispatched
+// to the XCDs round-robin, so workgroup b starts on queue b mod SOLVE_QUEUES
+// and the columns one XCD runs at a time come from few problems, whose S then
+// stays in that XCD's L2 for the in-kernel LMP; a workgroup whose queue is
+// empty takes tasks from the next queues in turn.  Every workgroup exits once
+// it has found all queues empty.
+__global__ __launch_bounds__(512) void k_solve(const TladArgs *__restrict__ probs, const TladGeom *__restrict__ geoms,
+                                               const SolveTask *__restrict__ tasks, const int *__restrict__ qoff,
+                                               int *counters) {
+    extern __shared__ __align__(16) unsigned char smraw[];
+    __shared__ int s_task;
+    __shared__ double s_red[16];
+    __shared__ double s_t[128];
+    const int tid = threadIdx.x;
+    int q = blockIdx.x % SOLVE_QUEUES, left = SOLVE_QUEUES;  // meaningful in thread 0 only
+    for (;;) {
+        if (tid == 0) {
+            int t = -1;
+            while (left > 0) {
+                const int lo = qoff[q], hi = qoff[q + 1];
+                if (lo < hi) {
+                    const int u = lo + atomicAdd(counters + q, 1);
+                    if (u < hi) {
+                        t = u;
+                        break;
+                    }
+                }
+                q = (q + 1) % SOLVE_QUEUES;
+                left--;
             }
-        }
-        if (st == COL_RUNNING) {
-            // iteration limit: the breakdown test on r^T z that the next
-            // iteration would make, then not-converged
-            double rz = 0.0;
-            for (int i = tid; i < n; i += nthr) rz += r[i] * z[i];
-            rz = block_sum(rz, s_red, nthr >> 6);
-            if (tid == 0) pc.status[c] = (pc.maxit > 0 && !(rz > 0.0 && isfinite(rz))) ? EDA_MEMBER_BREAKDOWN
-                                                                                       : EDA_MEMBER_NOT_CONVERGED;
+            s_task = t;
         }
         __syncthreads();
+        const int t = s_task;
+        __syncthreads();
+        if (t < 0) break;
+        const SolveTask task = tasks[t];
+        const TladArgs &a = probs[task.prob];
+        const TladGeom g = geoms[task.prob];
+        switch (g.q) {
+            case 2: solve_column<2>(a, g, task.col, smraw, s_red, s_t); break;
+            case 3: solve_column<3>(a, g, task.col, smraw, s_red, s_t); break;
+            case 4: solve_column<4>(a, g, task.col, smraw, s_red, s_t); break;
+            case 5: solve_column<5>(a, g, task.col, smraw, s_red, s_t); break;
+            case 6: solve_column<6>(a, g, task.col, smraw, s_red, s_t); break;
+            case 7: solve_column<7>(a, g, task.col, smraw, s_red, s_t); break;
+            case 8: solve_column<8>(a, g, task.col, smraw, s_red, s_t); break;
+            default: solve_column<9>(a, g, task.col, smraw, s_red, s_t); break;
+        }
     }
 }
 
@@ -817,13 +868,6 @@ hipError_t launch_t(hipStream_t s, const TladArgs &a, const TladGeom &g, int mod
 }
 
 template <int Q>
-hipError_t launch_solve_q(hipStream_t s, const TladArgs *d_probs, const SolveTask *d_tasks, int ntasks,
-                          int *d_counter, const TladGeom &g, size_t lds, int grid) {
-    hipLaunchKernelGGL(k_solve<Q>, dim3(grid), dim3(64 * g.waves), lds, s, d_probs, d_tasks, ntasks, d_counter, g);
-    return hipGetLastError();
-}
-
-template <int Q>
 hipError_t launch_hv_multi_q(hipStream_t s, const TladArgs *d_probs, const SolveTask *d_tasks, int ntasks,
                              const TladGeom &g, size_t lds) {
     hipLaunchKernelGGL(k_hv_multi<Q>, dim3(ntasks), dim3(64 * g.waves), lds, s, d_probs, d_tasks, g);
@@ -849,21 +893,13 @@ size_t tlad_lds_bytes(const TladArgs &a, const TladGeom &g, int mode) {
     }
 }
 
-hipError_t launch_solve(hipStream_t s, const TladArgs *d_probs, const SolveTask *d_tasks, int ntasks, int *d_counter,
-                        const TladGeom &g, size_t lds, int grid) {
+hipError_t launch_solve(hipStream_t s, const TladArgs *d_probs, const TladGeom *d_geoms, const SolveTask *d_tasks,
+                        int ntasks, const int *d_qoff, int *d_counters, int waves, size_t lds, int grid) {
     if (ntasks <= 0) return hipSuccess;
-    if (grid <= 0 || lds + SOLVE_STATIC_LDS > 160 * 1024) return hipErrorInvalidValue;
-    switch (g.q) {
-        case 2: return launch_solve_q<2>(s, d_probs, d_tasks, ntasks, d_counter, g, lds, grid);
-        case 3: return launch_solve_q<3>(s, d_probs, d_tasks, ntasks, d_counter, g, lds, grid);
-        case 4: return launch_solve_q<4>(s, d_probs, d_tasks, ntasks, d_counter, g, lds, grid);
-        case 5: return launch_solve_q<5>(s, d_probs, d_tasks, ntasks, d_counter, g, lds, grid);
-        case 6: return launch_solve_q<6>(s, d_probs, d_tasks, ntasks, d_counter, g, lds, grid);
-        case 7: return launch_solve_q<7>(s, d_probs, d_tasks, ntasks, d_counter, g, lds, grid);
-        case 8: return launch_solve_q<8>(s, d_probs, d_tasks, ntasks, d_counter, g, lds, grid);
-        case 9: return launch_solve_q<9>(s, d_probs, d_tasks, ntasks, d_counter, g, lds, grid);
-        default: return hipErrorInvalidValue;
-    }
+    if (grid <= 0 || (waves != 1 && waves != 2 && waves != 4 && waves != 8) || lds + SOLVE_STATIC_LDS > 160 * 1024)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_solve, dim3(grid), dim3(64 * waves), lds, s, d_probs, d_geoms, d_tasks, d_qoff, d_counters);
+    return hipGetLastError();
 }
 
 hipError_t launch_hv_multi(hipStream_t s, const TladArgs *d_probs, const SolveTask *d_tasks, int ntasks,
@@ -890,22 +926,9 @@ hipError_t launch_task_iters(hipStream_t s, int ntasks, const TladArgs *d_probs,
     return hipGetLastError();
 }
 
-int solve_blocks_per_cu(const TladGeom &g, size_t lds) {
+int solve_blocks_per_cu(int waves, size_t lds) {
     int nb = 0;
-    hipError_t e = hipErrorInvalidValue;
-    const int threads = 64 * g.waves;
-    switch (g.q) {
-        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<2>, threads, lds); break;
-        case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<3>, threads, lds); break;
-        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<4>, threads, lds); break;
-        case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<5>, threads, lds); break;
-        case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<6>, threads, lds); break;
-        case 7: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<7>, threads, lds); break;
-        case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<8>, threads, lds); break;
-        case 9: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<9>, threads, lds); break;
-        default: break;
-    }
-    return e == hipSuccess ? nb : 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve, 64 * waves, lds) == hipSuccess ? nb : 0;
 }
 
 // Geometry: waves per workgroup, owned segment per wave, points per lane and

@@ -291,13 +291,14 @@ def eda_batch_result(batch, p: int, n: int, m: int, DZ=None):
 
 
 def eda_batch_tuning(batch) -> list[dict]:
-    out = (ctypes.c_int32 * 8)()
+    out = (ctypes.c_int32 * 11)()
     ncls = lib().eda_batch_tuning(batch, 0, out)
     _check("eda_batch_tuning", min(ncls, 0))
     res = []
     for c in range(ncls):
         lib().eda_batch_tuning(batch, c, out)
-        res.append(dict(zip(["n", "problems", "waves", "q", "tb", "grid", "columns", "tune_us"], list(out))))
+        res.append(dict(zip(["n", "problems", "waves", "q", "tb", "grid", "columns", "tune_us", "sketch_waves",
+                             "sketch_q", "sketch_tb"], list(out))))
     return res
 
 

@@ -108,9 +108,12 @@ def test_batch_tuning_and_plain_cg():
         assert (bt.result(p, with_dz=False)["status"] == eda.EDA_MEMBER_CONVERGED).all()
     tun = bt.tuning()
     assert [t["n"] for t in tun] == sorted({c["n"] for c in cfgs})
+    # one persistent solve launch: common waves and grid over the classes
+    assert len({t["waves"] for t in tun}) == 1 and len({t["grid"] for t in tun}) == 1
     for t in tun:
         assert t["waves"] in (1, 2, 4, 8) and 2 <= t["q"] <= 9 and t["tb"] >= 1
-        assert 1 <= t["grid"] <= t["columns"]
+        assert t["sketch_waves"] in (1, 2, 4, 8) and 2 <= t["sketch_q"] <= 9 and t["sketch_tb"] >= 1
+        assert 1 <= t["grid"] <= sum(c["members"] + 1 for c in cfgs)
         assert t["columns"] == sum(c["members"] + 1 for c in cfgs if c["n"] == t["n"])
 
 
@@ -208,6 +211,33 @@ def test_batch_fallback_equals_single_problem_sketch():
         res = bt.result(p)
         assert (res["status"] == eda.EDA_MEMBER_CONVERGED).all(), (p, res["status"])
     assert nsp == unprec
+    bt.close()
+    for g in probs:
+        g.close()
+
+
+def test_batch_repeat_calls_bitwise_with_shared_cus():
+    # the n = 2048 class of the 256-problem workload: more member columns than persistent workgroups,
+    # two workgroups per CU, so each workgroup runs several columns in turn next
+    # to another one; the queue layout changes after the first call (measured
+    # costs), so columns land on other workgroups and CUs.  Every call must give
+    # the same bits: a column's arithmetic does not depend on where it runs.
+    cfgs = [c for c in W.uneven_problems(256) if c["n"] == 2048]
+    probs = [eda.Problem(c, W.problem_normals(c)) for c in cfgs]
+    bt = eda.Batch(probs)
+    cols = sum(c["members"] + 1 for c in cfgs)
+    first = None
+    for call in range(3):
+        bt.solve(k_cap=32, rtol=1e-6, maxit=2000)
+        res = [bt.result(p) for p in range(len(cfgs))]
+        got = ([r["dz"].cpu().numpy() for r in res], [r["iters"] for r in res])
+        if call == 0:
+            first = got
+            assert cols > bt.tuning()[0]["grid"], (cols, bt.tuning())
+            continue
+        diff = [p for p in range(len(cfgs))
+                if not (np.array_equal(got[0][p], first[0][p]) and np.array_equal(got[1][p], first[1][p]))]
+        assert not diff, (call, diff)
     bt.close()
     for g in probs:
         g.close()
