@@ -108,24 +108,34 @@ __device__ __forceinline__ int wpos(int base, int q, int n) {
     return p >= n ? p - n : p;
 }
 
-// Copy this wave's trajectory window -- 64 Q consecutive doubles of a padded
-// state row, from xe on -- into the wave's LDS slice: Q coalesced loads (lane
-// l of load i takes double 64 i + l) into registers, then the same pattern of
-// LDS stores, so slice[j] = xe[j].  The stores have the type of read_window's
-// loads, so the compiler keeps them after the previous step's reads.  The
-// copy goes through registers on purpose: direct global-to-LDS copies were
-// measured to deliver stale or misplaced words now and then when workgroups
-// share a CU, even behind a vector-memory wait.
+// Copy of this wave's trajectory window -- 64 Q consecutive doubles of a
+// padded state row, from xe on -- into the wave's LDS slice, through
+// registers: lane l loads doubles 64 i + l (i in [I0, I1), coalesced) and
+// stores them at the same slice positions, so slice[j] = xe[j].  The stores
+// have the type of read_window's loads, so the compiler keeps them after the
+// reads of the previous step.  The loads of the next step's window are issued
+// early and stored late (load_part / store_part) where registers allow, else
+// the whole copy is done at once (prefetch_window).  The copy goes through
+// registers on purpose: direct global-to-LDS copies were measured to deliver
+// stale or misplaced words now and then when workgroups share a CU, even
+// behind a vector-memory wait.
+template <int I0, int I1, int Q>
+__device__ __forceinline__ void load_part(const double *xe, double (&v)[Q]) {
+    const double *g = xe + (threadIdx.x & 63);
+#pragma unroll
+    for (int i = I0; i < I1; i++) v[i] = g[64 * i];
+}
+template <int I0, int I1, int Q>
+__device__ __forceinline__ void store_part(double *slice, const double (&v)[Q]) {
+    double *l = slice + (threadIdx.x & 63);
+#pragma unroll
+    for (int i = I0; i < I1; i++) l[64 * i] = v[i];
+}
 template <int Q>
 __device__ __forceinline__ void prefetch_window(const double *xe, double *slice) {
-    const int lane = threadIdx.x & 63;
-    const double *g = xe + lane;
-    double *l = slice + lane;
     double v[Q];
-#pragma unroll
-    for (int i = 0; i < Q; i++) v[i] = g[64 * i];
-#pragma unroll
-    for (int i = 0; i < Q; i++) l[64 * i] = v[i];
+    load_part<0, Q, Q>(xe, v);
+    store_part<0, Q, Q>(slice, v);
 }
 
 // This lane's Q window points from the wave's slice (written by the same wave:
@@ -243,7 +253,7 @@ __device__ __forceinline__ double block_sum(double v, double *red, int waves) {
 // states on each side (ring position j = state lo - halo + j mod n); positions
 // whose dependency cone reaches the ring's seam are wrong, the owned ones
 // exact.  Every early exit is taken by the whole workgroup.
-template <typename T, int Q, int MODE>
+template <typename T, int Q, int MODE, bool EARLY = true>
 __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g, const int c, const int it,
                                             const int first, unsigned char *smraw, const int piece = 0) {
     constexpr bool SPLIT = MODE == TLAD_SPLIT;
@@ -359,7 +369,15 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
                 // observed increment of time s
                 if (s > 0 && s % a.obs_dt == 0)
                     store_obs<T, Q>(obs + (long long)(s / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
-                if (s + 1 < N) prefetch_window<Q>(trajm + (long long)(s + 1) * a.ext_len + w0, xw);
+                // next step's window: all of it early (Q <= 7), half early and
+                // half after the second stage (Q > 7), or at once (!EARLY)
+                const double *xn = trajm + (long long)(s + 1) * a.ext_len + w0;
+                double nxt[Q];
+                if (s + 1 < N) {
+                    if constexpr (!EARLY) prefetch_window<Q>(xn, xw);
+                    else if constexpr (Q <= 7) load_part<0, Q, Q>(xn, nxt);
+                    else load_part<0, Q / 2, Q>(xn, nxt);
+                }
                 ext<T, Q>(x, Y);
                 ext<T, Q>(dx, V);
                 tl_stage<T, Q, true>(Y, V, k, dk);
@@ -373,6 +391,11 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
                 ext<T, Q>(ys, Y);
                 ext<T, Q>(vs, V);
                 tl_stage<T, Q, true>(Y, V, k, dk);
+                if constexpr (EARLY && Q > 7)
+                    if (s + 1 < N) {
+                        store_part<0, Q / 2, Q>(xw, nxt);
+                        load_part<Q / 2, Q, Q>(xn, nxt);
+                    }
 #pragma unroll
                 for (int j = 0; j < Q; j++) {
                     acc[j] = fma_t(T(2), dk[j], acc[j]);
@@ -393,6 +416,8 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
                 tl_stage<T, Q, false>(Y, V, k, dk);
 #pragma unroll
                 for (int j = 0; j < Q; j++) dx[j] = fma_t(dt6, acc[j] + dk[j], dx[j]);
+                if constexpr (EARLY)
+                    if (s + 1 < N) store_part<(Q <= 7 ? 0 : Q / 2), Q, Q>(xw, nxt);
             }
             if (s1 < N) {
 #pragma unroll
@@ -433,7 +458,14 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
             }
             T x[Q], Y2[Q + 4], Y3[Q + 4], Y4[Q + 4], M[Q + 4], k[Q], ys[Q];
             read_window<T, Q>(xw, x);  // X[s - 1]
-            if (s >= 2) prefetch_window<Q>(trajm + (long long)(s - 2) * a.ext_len + w0, xw);
+            // next step's window (X[s - 2]), split as in the TL run
+            const double *xn = trajm + (long long)(s - 2) * a.ext_len + w0;
+            double nxt[Q];
+            if (s >= 2) {
+                if constexpr (!EARLY) prefetch_window<Q>(xn, xw);
+                else if constexpr (Q <= 7) load_part<0, Q, Q>(xn, nxt);
+                else load_part<0, Q / 2, Q>(xn, nxt);
+            }
             {
                 T Y1[Q + 4];
                 ext<T, Q>(x, Y1);
@@ -457,6 +489,11 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
             for (int j = 0; j < Q; j++) mu[j] = dt6 * lam[j];
             ext<T, Q>(mu, M);
             jt<T, Q>(Y4, M, nu);
+            if constexpr (EARLY && Q > 7)
+                if (s >= 2) {
+                    store_part<0, Q / 2, Q>(xw, nxt);
+                    load_part<Q / 2, Q, Q>(xn, nxt);
+                }
 #pragma unroll
             for (int j = 0; j < Q; j++) {
                 acc[j] = lam[j] + nu[j];
@@ -484,6 +521,8 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
             }
 #pragma unroll
             for (int j = 0; j < Q; j++) lam[j] = acc[j] + nu[j];
+            if constexpr (EARLY)
+                if (s >= 2) store_part<(Q <= 7 ? 0 : Q / 2), Q, Q>(xw, nxt);
         }
         if (s_lo > 0) {
 #pragma unroll
@@ -724,7 +763,7 @@ __device__ __forceinline__ void solve_column(const TladArgs &a, const TladGeom &
     }
     int st = COL_RUNNING;
     for (int it = 1; it <= pc.maxit; it++) {
-        tlad_column<double, Q, TLAD_PCG>(a, g, c, it, it == 1, smraw);
+        tlad_column<double, Q, TLAD_PCG, false>(a, g, c, it, it == 1, smraw);
         __syncthreads();
         st = pc.status[c];
         __syncthreads();
