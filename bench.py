@@ -195,9 +195,9 @@ def run_uneven_batch(count, reps, plain_count):
     """Uneven batching: `count` independent problems (n in {40,...,2048}, window
     10/20/40, 8-64 members, k = min(32, members)), every member solved to
     rtol 1e-6 with its problem's Gamma-Nystrom LMP.  Chosen: one batch (per-class
-    sketch launches, Nystrom cores and persistent solve launches in one captured
-    graph, autotuned geometry); the first call tunes and captures, the timed
-    calls replay.  Plain: the same problems one after another through
+    sketch launches and the Nystrom cores in one captured graph, one persistent
+    solve launch for every class in another, autotuned geometry); the first call
+    tunes and captures, the timed calls replay.  Plain: the same problems one after another through
     eda_sketch_evd + eda_pcg_solve (first plain_count problems)."""
     import torch
     from paper_2605_23571_amd import eda
