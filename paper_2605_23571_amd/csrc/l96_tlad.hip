@@ -371,12 +371,15 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
                     store_obs<T, Q>(obs + (long long)(s / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
                 // next step's window: all of it early (Q <= 7), half early and
                 // half after the second stage (Q > 7), or at once (!EARLY)
-                const double *xn = trajm + (long long)(s + 1) * a.ext_len + w0;
+                // (the last step reloads its own row: no branch inside the step)
+                const double *xn = trajm + (long long)min(s + 1, N - 1) * a.ext_len + w0;
                 double nxt[Q];
-                if (s + 1 < N) {
-                    if constexpr (!EARLY) prefetch_window<Q>(xn, xw);
-                    else if constexpr (Q <= 7) load_part<0, Q, Q>(xn, nxt);
-                    else load_part<0, Q / 2, Q>(xn, nxt);
+                if constexpr (!EARLY) {
+                    if (s + 1 < N) prefetch_window<Q>(xn, xw);
+                } else if constexpr (Q <= 7) {
+                    load_part<0, Q, Q>(xn, nxt);
+                } else {
+                    load_part<0, Q / 2, Q>(xn, nxt);
                 }
                 ext<T, Q>(x, Y);
                 ext<T, Q>(dx, V);
@@ -391,11 +394,10 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
                 ext<T, Q>(ys, Y);
                 ext<T, Q>(vs, V);
                 tl_stage<T, Q, true>(Y, V, k, dk);
-                if constexpr (EARLY && Q > 7)
-                    if (s + 1 < N) {
-                        store_part<0, Q / 2, Q>(xw, nxt);
-                        load_part<Q / 2, Q, Q>(xn, nxt);
-                    }
+                if constexpr (EARLY && Q > 7) {
+                    store_part<0, Q / 2, Q>(xw, nxt);
+                    load_part<Q / 2, Q, Q>(xn, nxt);
+                }
 #pragma unroll
                 for (int j = 0; j < Q; j++) {
                     acc[j] = fma_t(T(2), dk[j], acc[j]);
@@ -416,8 +418,7 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
                 tl_stage<T, Q, false>(Y, V, k, dk);
 #pragma unroll
                 for (int j = 0; j < Q; j++) dx[j] = fma_t(dt6, acc[j] + dk[j], dx[j]);
-                if constexpr (EARLY)
-                    if (s + 1 < N) store_part<(Q <= 7 ? 0 : Q / 2), Q, Q>(xw, nxt);
+                if constexpr (EARLY) store_part<(Q <= 7 ? 0 : Q / 2), Q, Q>(xw, nxt);
             }
             if (s1 < N) {
 #pragma unroll
@@ -459,12 +460,14 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
             T x[Q], Y2[Q + 4], Y3[Q + 4], Y4[Q + 4], M[Q + 4], k[Q], ys[Q];
             read_window<T, Q>(xw, x);  // X[s - 1]
             // next step's window (X[s - 2]), split as in the TL run
-            const double *xn = trajm + (long long)(s - 2) * a.ext_len + w0;
+            const double *xn = trajm + (long long)max(s - 2, 0) * a.ext_len + w0;
             double nxt[Q];
-            if (s >= 2) {
-                if constexpr (!EARLY) prefetch_window<Q>(xn, xw);
-                else if constexpr (Q <= 7) load_part<0, Q, Q>(xn, nxt);
-                else load_part<0, Q / 2, Q>(xn, nxt);
+            if constexpr (!EARLY) {
+                if (s >= 2) prefetch_window<Q>(xn, xw);
+            } else if constexpr (Q <= 7) {
+                load_part<0, Q, Q>(xn, nxt);
+            } else {
+                load_part<0, Q / 2, Q>(xn, nxt);
             }
             {
                 T Y1[Q + 4];
@@ -489,11 +492,10 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
             for (int j = 0; j < Q; j++) mu[j] = dt6 * lam[j];
             ext<T, Q>(mu, M);
             jt<T, Q>(Y4, M, nu);
-            if constexpr (EARLY && Q > 7)
-                if (s >= 2) {
-                    store_part<0, Q / 2, Q>(xw, nxt);
-                    load_part<Q / 2, Q, Q>(xn, nxt);
-                }
+            if constexpr (EARLY && Q > 7) {
+                store_part<0, Q / 2, Q>(xw, nxt);
+                load_part<Q / 2, Q, Q>(xn, nxt);
+            }
 #pragma unroll
             for (int j = 0; j < Q; j++) {
                 acc[j] = lam[j] + nu[j];
@@ -521,8 +523,7 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
             }
 #pragma unroll
             for (int j = 0; j < Q; j++) lam[j] = acc[j] + nu[j];
-            if constexpr (EARLY)
-                if (s >= 2) store_part<(Q <= 7 ? 0 : Q / 2), Q, Q>(xw, nxt);
+            if constexpr (EARLY) store_part<(Q <= 7 ? 0 : Q / 2), Q, Q>(xw, nxt);
         }
         if (s_lo > 0) {
 #pragma unroll
