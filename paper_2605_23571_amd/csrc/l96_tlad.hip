@@ -764,7 +764,7 @@ __device__ __forceinline__ void solve_column(const TladArgs &a, const TladGeom &
     }
     int st = COL_RUNNING;
     for (int it = 1; it <= pc.maxit; it++) {
-        tlad_column<double, Q, TLAD_PCG, false>(a, g, c, it, it == 1, smraw);
+        tlad_column<double, Q, TLAD_PCG, (Q <= 7)>(a, g, c, it, it == 1, smraw);
         __syncthreads();
         st = pc.status[c];
         __syncthreads();
