@@ -157,59 +157,30 @@ __global__ __launch_bounds__(SJ) void k_jacobi_svd(int l, const double *__restri
         if (tid == 0) rotated = 0;
         __syncthreads();
         for (int r = 0; r < m - 1; r++) {
-            // two pairs of the round per wave at a time: their six sums go down
-            // one interleaved shuffle tree (each sum in the same order as a tree
-            // of its own), so the latency of the tree is paid once
-            constexpr int NW = SJ / 64;
-            for (int k0 = wave; k0 < m / 2; k0 += 2 * NW) {
-                int p[2] = {0, 0}, q[2] = {0, 0};
-                bool on[2];
-                double al[2] = {0, 0}, be[2] = {0, 0}, ga[2] = {0, 0};
-#pragma unroll
-                for (int j = 0; j < 2; j++) {
-                    const int k = k0 + j * NW;
-                    on[j] = k < m / 2;
-                    if (on[j]) {
-                        rr_pair(m, r, k, p[j], q[j]);
-                        on[j] = q[j] < l;
-                    }
-                    if (on[j]) {
-                        const double *ap = A + p[j] * l, *aq = A + q[j] * l;
-                        for (int i = lane; i < l; i += 64) {
-                            al[j] += ap[i] * ap[i];
-                            be[j] += aq[i] * aq[i];
-                            ga[j] += ap[i] * aq[i];
-                        }
-                    }
+            for (int k = wave; k < m / 2; k += SJ / 64) {
+                int p, q;
+                rr_pair(m, r, k, p, q);
+                if (q >= l) continue;
+                double *ap = A + p * l, *aq = A + q * l;
+                double al = 0, be = 0, ga = 0;
+                for (int i = lane; i < l; i += 64) {
+                    al += ap[i] * ap[i];
+                    be += aq[i] * aq[i];
+                    ga += ap[i] * aq[i];
                 }
-                for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-                    for (int j = 0; j < 2; j++) {
-                        al[j] += __shfl_down(al[j], off, 64);
-                        be[j] += __shfl_down(be[j], off, 64);
-                        ga[j] += __shfl_down(ga[j], off, 64);
+                al = wave_sum(al);
+                be = wave_sum(be);
+                ga = wave_sum(ga);
+                if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+                    double zeta = (be - al) / (2.0 * ga);
+                    double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+                    for (int i = lane; i < l; i += 64) {
+                        double x = ap[i], y = aq[i];
+                        ap[i] = c * x - sn * y;
+                        aq[i] = sn * x + c * y;
                     }
-                }
-#pragma unroll
-                for (int j = 0; j < 2; j++) {
-                    al[j] = __shfl(al[j], 0, 64);
-                    be[j] = __shfl(be[j], 0, 64);
-                    ga[j] = __shfl(ga[j], 0, 64);
-                }
-#pragma unroll
-                for (int j = 0; j < 2; j++) {
-                    if (on[j] && ga[j] != 0.0 && fabs(ga[j]) > tol * sqrt(al[j] * be[j])) {
-                        const double zeta = (be[j] - al[j]) / (2.0 * ga[j]);
-                        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-                        double *ap = A + p[j] * l, *aq = A + q[j] * l;
-                        for (int i = lane; i < l; i += 64) {
-                            double x = ap[i], y = aq[i];
-                            ap[i] = c * x - sn * y;
-                            aq[i] = sn * x + c * y;
-                        }
-                        if (lane == 0) rotated = 1;
-                    }
+                    if (lane == 0) rotated = 1;
                 }
             }
             __syncthreads();
