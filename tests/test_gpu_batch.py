@@ -238,6 +238,18 @@ def test_batch_repeat_calls_bitwise_with_shared_cus():
         diff = [p for p in range(len(cfgs))
                 if not (np.array_equal(got[0][p], first[0][p]) and np.array_equal(got[1][p], first[1][p]))]
         assert not diff, (call, diff)
+    # full-size parity in the benchmark's launch configuration: the oracle's
+    # true residual of sampled members of the problem with the longest solve
+    # and of a 40-step problem
+    worst = int(np.argmax([first[1][p].max() for p in range(len(cfgs))]))
+    long_window = next(p for p, c in enumerate(cfgs) if c["nsteps"] == 40)
+    for p in sorted({worst, long_window}):
+        o = O.Problem(cfgs[p], W.problem_normals(cfgs[p]))
+        L = cfgs[p]["members"]
+        for m in (0, int(np.argmax(first[1][p])), L):
+            dz = first[0][p][m]
+            r = o.b[:, m] - o.hess(dz[:, None], [m])[:, 0]
+            assert np.linalg.norm(r) <= 2e-6 * np.linalg.norm(o.b[:, m]), (p, m)
     bt.close()
     for g in probs:
         g.close()
