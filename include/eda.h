@@ -296,9 +296,9 @@ int eda_set_geometry(eda_ctx *ctx, int32_t waves, int32_t tb);
  * of the banded U_B), the reach of the TL/AD runs over the window and of U_B
  * on both ends, so its own outputs are exact; the pieces' partial sums of
  * p^T (I + A) p are added in piece order.  pieces = 0 (the default): P is the
- * largest of 1, 2, 4, 8 with P x (members still running at the last
- * convergence check) <= the device's compute units; 1, 2, 4 or 8: that P in
- * every iteration.  Solutions agree with P = 1 to rounding.  Errors:
+ * largest of 1, 2, 3, 4, 8 with P x (members still running at the last
+ * convergence check) <= the device's compute units; 1 to 8: that P in every
+ * iteration.  Solutions agree with P = 1 to rounding.  Errors:
  * EDA_ERR_UNSUPPORTED if the context is not banded, or P > 1 pieces do not fit
  * n (ring of ceil(n / P) + 2 halo states longer than n, or a window wider than
  * the kernel supports); EDA_ERR_INVALID_ARG for other values. */

@@ -739,8 +739,11 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                 }
                 int P = active == 0 ? 1 : c.split_force;
                 if (P == 0) {
+                    // the largest of 1, 2, 3, 4, 8 that fits: 5 to 7 pieces
+                    // were measured no faster than 4 (their rings take a
+                    // geometry with fewer waves or a shorter time block)
                     P = 1;
-                    for (int cand = 2; cand <= SPLIT_PMAX; cand *= 2)
+                    for (int cand : {2, 3, 4, 8})
                         if ((long long)cand * active <= c.num_cus && tlad_split_ring(n, c.N, c.band_hi, cand) > 0)
                             P = cand;
                 }
@@ -914,7 +917,7 @@ int eda_set_geometry(eda_ctx *h, int32_t waves, int32_t tb) {
 int eda_set_split(eda_ctx *h, int32_t pieces) {
     if (!h) return EDA_ERR_INVALID_ARG;
     Ctx &c = h->c;
-    if (pieces != 0 && pieces != 1 && pieces != 2 && pieces != 4 && pieces != 8) return EDA_ERR_INVALID_ARG;
+    if (pieces < 0 || pieces > SPLIT_PMAX) return EDA_ERR_INVALID_ARG;
     if (c.cfg.ub_mode != EDA_UB_BANDED) return EDA_ERR_UNSUPPORTED;
     if (pieces > 1 && tlad_split_ring(c.n, c.N, c.band_hi, pieces) == 0) return EDA_ERR_UNSUPPORTED;
     c.split_force = pieces;

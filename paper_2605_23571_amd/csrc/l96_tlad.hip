@@ -1038,7 +1038,7 @@ void tlad_pads_split(int n, int N, int band_hi, int *pad_l, int *pad_r) {
     int pl, pr;
     tlad_pads(n, &pl, &pr);
     const int H = tlad_split_halo(N, band_hi);
-    for (int P = 2; P <= SPLIT_PMAX; P *= 2) {
+    for (int P = 2; P <= SPLIT_PMAX; P++) {
         const int R = tlad_split_ring(n, N, band_hi, P);
         if (R == 0) continue;
         int l, r;

@@ -373,8 +373,12 @@ def test_split_iterations_match_whole_columns(case):
     g.sketch_evd("rhs_diff")
     members = np.arange(cfg["members"] + 1)
     ref = None
-    for P in (1, 2, 4, 8):
-        eda.eda_set_split(g.ctx, P)
+    for P in (1, 2, 3, 4, 5, 8):
+        try:
+            eda.eda_set_split(g.ctx, P)
+        except eda.EdaError as e:  # a ring of ceil(n / P) + 2 halos longer than n
+            assert e.code == eda.EDA_ERR_UNSUPPORTED and P > 2, (P, e.code)
+            continue
         dz = g.pcg(members, rtol=0.0, maxit=4)["dz"].cpu().numpy()
         if ref is None:
             ref = dz
@@ -403,7 +407,11 @@ def test_split_errors():
     assert e.value.code == eda.EDA_ERR_UNSUPPORTED
     with pytest.raises(eda.EdaError) as e:
         eda.eda_set_split(g.ctx, 3)
-    assert e.value.code == eda.EDA_ERR_INVALID_ARG
+    assert e.value.code == eda.EDA_ERR_UNSUPPORTED
+    for bad in (-1, 9):
+        with pytest.raises(eda.EdaError) as e:
+            eda.eda_set_split(g.ctx, bad)
+        assert e.value.code == eda.EDA_ERR_INVALID_ARG
     eda.eda_set_split(g.ctx, 1)
     eda.eda_set_split(g.ctx, 0)
     cfg, gd, o = problem("n1001", mode="dense")
