@@ -973,6 +973,8 @@ struct eda_batch {
     int *d_counters = nullptr;            // SOLVE_QUEUES queue counters
     int *d_qoff = nullptr;                // SOLVE_QUEUES + 1 queue offsets
     TladGeom *d_geom = nullptr;           // solve geometry of each problem
+    JacobiJob *d_jobs = nullptr;          // SVD operands of every problem (sketch graph)
+    JacobiJob *d_fbjobs = nullptr;        // SVD operands of the fallback problems
     int solve_waves = 0, solve_grid = 0;  // the one persistent solve launch
     size_t solve_lds = 0;
     const int32_t **d_infoptr = nullptr;  // each problem's sketch outcome slots
@@ -1012,7 +1014,8 @@ struct eda_batch {
 namespace {
 
 struct BatchPlan {
-    size_t off_solve, off_hv, off_st, off_ht, off_cnt, off_qoff, off_geom, off_iptr, off_flags, off_titer, total;
+    size_t off_solve, off_hv, off_st, off_ht, off_cnt, off_qoff, off_geom, off_jobs, off_fbjobs, off_iptr, off_flags,
+        off_titer, total;
 };
 
 BatchPlan batch_plan(eda_ctx *const *ctxs, int np) {
@@ -1031,6 +1034,8 @@ BatchPlan batch_plan(eda_ctx *const *ctxs, int np) {
     P.off_cnt = lay.take(sizeof(int) * SOLVE_QUEUES);
     P.off_qoff = lay.take(sizeof(int) * (SOLVE_QUEUES + 1));
     P.off_geom = lay.take(sizeof(TladGeom) * np);
+    P.off_jobs = lay.take(sizeof(JacobiJob) * np);
+    P.off_fbjobs = lay.take(sizeof(JacobiJob) * np);
     P.off_iptr = lay.take(sizeof(int32_t *) * np);
     P.off_flags = lay.take(sizeof(int32_t) * np);
     P.off_titer = lay.take(sizeof(int32_t) * (st ? st : 1));
@@ -1039,19 +1044,24 @@ BatchPlan batch_plan(eda_ctx *const *ctxs, int np) {
 }
 
 // The Nystrom core of eda_sketch_evd (q = 1, no shift) with no host
-// synchronisation: CholQR2 of Y, W = Phi^T Y, C = chol(W), T = R_Y C^-1, SVD,
-// S = Q U, signs, theta "mid" and the LMP coefficients.  The three Cholesky
-// outcomes land in sk_info[0..2]; the caller checks them after the run.
-int nystrom_nosync(Ctx &c, int l, int k) {
+// synchronisation, in two halves around the SVD of T (which the batch runs for
+// all problems in one launch, jacobi_job gives its operands): CholQR2 of Y,
+// W = Phi^T Y, C = chol(W), T = R_Y C^-1; then S = Q U, signs, theta "mid" and
+// the LMP coefficients.  The three Cholesky outcomes land in sk_info[0..2]; the
+// caller checks them after the run.
+JacobiJob jacobi_job(const Ctx &c, int l) {
+    const size_t ls = (size_t)c.max_ell * c.max_ell;
+    return JacobiJob{l, c.sk_small + 2 * ls, c.sk_small + 3 * ls, c.sk_small + 4 * ls};
+}
+
+int nystrom_pre_svd(Ctx &c, int l) {
     hipStream_t s = c.stream;
     const int n = c.n;
     const size_t ls = (size_t)c.max_ell * c.max_ell;
     double *G = c.sk_small, *R1 = c.sk_small + 1 * ls, *R1i = c.sk_small + 2 * ls;
     double *R2 = c.sk_small + 3 * ls, *R2i = c.sk_small + 4 * ls;
     double *RY = c.sk_small + 7 * ls, *Wm = c.sk_small + 8 * ls, *Cm = c.sk_small + 9 * ls;
-    double *Ci = c.sk_small + 1 * ls, *Tm = c.sk_small + 2 * ls, *Um = c.sk_small + 3 * ls;
-    double *sig = c.sk_small + 4 * ls;
-    double *dscal = reinterpret_cast<double *>(c.sk_info + 16);
+    double *Ci = c.sk_small + 1 * ls, *Tm = c.sk_small + 2 * ls;
     HIP_TRY(gemm_f64(s, true, l, l, n, c.sk_y, n, c.sk_y, n, G, l, nullptr, 0, nullptr, c.splitk, c.splitk_elems));
     HIP_TRY(launch_chol_inv(s, l, G, 0.0, R1, R1i, c.sk_info + 0));
     HIP_TRY(gemm_f64(s, false, n, l, l, c.sk_y, n, R1i, l, c.sk_q1, n, nullptr, 0, nullptr, nullptr, 0));
@@ -1063,10 +1073,17 @@ int nystrom_nosync(Ctx &c, int l, int k) {
     HIP_TRY(launch_sym(s, l, Wm));
     HIP_TRY(launch_chol_inv(s, l, Wm, 0.0, Cm, Ci, c.sk_info + 2));
     HIP_TRY(launch_small_gemm(s, l, false, false, RY, Ci, Tm));
-    HIP_TRY(launch_jacobi_svd_u(s, l, Tm, Um, sig));
-    HIP_TRY(gemm_f64(s, false, n, k, l, c.sk_q, n, Um, l, c.sk_s, n, nullptr, 0, nullptr, nullptr, 0));
+    return EDA_OK;
+}
+
+int nystrom_post_svd(Ctx &c, int l, int k) {
+    hipStream_t s = c.stream;
+    const int n = c.n;
+    const JacobiJob j = jacobi_job(c, l);
+    double *dscal = reinterpret_cast<double *>(c.sk_info + 16);
+    HIP_TRY(gemm_f64(s, false, n, k, l, c.sk_q, n, j.U, l, c.sk_s, n, nullptr, 0, nullptr, nullptr, 0));
     HIP_TRY(launch_fix_signs(s, n, k, c.sk_s, n));
-    HIP_TRY(launch_lmp_coef(s, k, sig, 0.0, 1, EDA_THETA_MID, c.sk_eig, c.sk_coef, c.sk_coefu, dscal + 1));
+    HIP_TRY(launch_lmp_coef(s, k, j.sig, 0.0, 1, EDA_THETA_MID, c.sk_eig, c.sk_coef, c.sk_coefu, dscal + 1));
     return EDA_OK;
 }
 
@@ -1301,18 +1318,27 @@ int batch_enqueue_sketch(eda_batch &b) {
         HIP_TRY(hipEventRecord(k.done, k.side));
         HIP_TRY(hipStreamWaitEvent(s, k.done, 0));
     }
-    // Nystrom cores, problems spread over parallel branches
+    // Nystrom cores, problems spread over parallel branches, with the SVDs of
+    // T of every problem in one launch (one workgroup each) in the middle
     const size_t nl = b.lanes.size();
-    HIP_TRY(hipEventRecord(b.fork, s));
-    for (size_t l = 0; l < nl; l++) HIP_TRY(hipStreamWaitEvent(b.lanes[l], b.fork, 0));
-    for (size_t i = 0; i < b.probs.size(); i++) {
-        Ctx &c = *b.probs[i];
-        c.stream = b.lanes[i % nl];
-        EDA_TRY(nystrom_nosync(c, b.ell[i], b.ell[i]));
-    }
-    for (size_t l = 0; l < nl; l++) {
-        HIP_TRY(hipEventRecord(b.lane_done[l], b.lanes[l]));
-        HIP_TRY(hipStreamWaitEvent(s, b.lane_done[l], 0));
+    int lmax = 1;
+    for (int l : b.ell) lmax = l > lmax ? l : lmax;
+    for (int half = 0; half < 2; half++) {
+        HIP_TRY(hipEventRecord(b.fork, s));
+        for (size_t l = 0; l < nl; l++) HIP_TRY(hipStreamWaitEvent(b.lanes[l], b.fork, 0));
+        for (size_t i = 0; i < b.probs.size(); i++) {
+            Ctx &c = *b.probs[i];
+            c.stream = b.lanes[i % nl];
+            if (half == 0)
+                EDA_TRY(nystrom_pre_svd(c, b.ell[i]));
+            else
+                EDA_TRY(nystrom_post_svd(c, b.ell[i], b.ell[i]));
+        }
+        for (size_t l = 0; l < nl; l++) {
+            HIP_TRY(hipEventRecord(b.lane_done[l], b.lanes[l]));
+            HIP_TRY(hipStreamWaitEvent(s, b.lane_done[l], 0));
+        }
+        if (half == 0) HIP_TRY(launch_jacobi_svd_batch(s, (int)b.probs.size(), b.d_jobs, lmax));
     }
     HIP_TRY(launch_gather_info(s, (int)b.probs.size(), b.d_infoptr, b.d_flags));
     return EDA_OK;
@@ -1513,15 +1539,29 @@ int batch_fallback(eda_batch &b, const std::vector<int> &ids, std::vector<char> 
         for (int t : shiftw)
             if (ok[t] && hi[8 * t + 4] != 0) ok[t] = 0;
     }
-    // T = R_Y C^-1, SVD T = U Sigma V^T, S = Q_Y U, D = Sigma^2 - nu
+    // T = R_Y C^-1; the SVDs T = U Sigma V^T of all of them in one launch
+    // (one workgroup each); S = Q_Y U, D = Sigma^2 - nu
+    std::vector<JacobiJob> jobs;
+    for (int t = 0; t < m; t++) {
+        if (!ok[t]) continue;
+        const int l = b.ell[ids[t]];
+        HIP_TRY(launch_small_gemm(lane(t), l, false, false, small(t, 7), small(t, 1), small(t, 2)));
+        jobs.push_back(JacobiJob{l, small(t, 2), small(t, 3), small(t, 4)});
+    }
+    if (!jobs.empty()) {
+        HIP_TRY(hipMemcpyAsync(b.d_fbjobs, jobs.data(), sizeof(JacobiJob) * jobs.size(), hipMemcpyHostToDevice,
+                               b.lanes[0]));
+        EDA_TRY(wait_all());
+        HIP_TRY(launch_jacobi_svd_batch(b.lanes[0], (int)jobs.size(), b.d_fbjobs, lmax));
+        HIP_TRY(hipEventRecord(b.lane_done[0], b.lanes[0]));
+        for (size_t l = 1; l < b.lanes.size(); l++) HIP_TRY(hipStreamWaitEvent(b.lanes[l], b.lane_done[0], 0));
+    }
     for (int t = 0; t < m; t++) {
         if (!ok[t]) continue;
         Ctx &c = *b.probs[ids[t]];
         const int l = b.ell[ids[t]];
         hipStream_t st = lane(t);
         double *dscal = reinterpret_cast<double *>(c.sk_info + 16);
-        HIP_TRY(launch_small_gemm(st, l, false, false, small(t, 7), small(t, 1), small(t, 2)));
-        HIP_TRY(launch_jacobi_svd_u(st, l, small(t, 2), small(t, 3), small(t, 4)));
         HIP_TRY(gemm_f64(st, false, c.n, l, l, c.sk_q, c.n, small(t, 3), l, c.sk_s, c.n, nullptr, 0, nullptr, nullptr,
                          0));
         HIP_TRY(launch_fix_signs(st, c.n, l, c.sk_s, c.n));
@@ -1591,6 +1631,8 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
     b->d_counters = reinterpret_cast<int *>(b->ws + P.off_cnt);
     b->d_qoff = reinterpret_cast<int *>(b->ws + P.off_qoff);
     b->d_geom = reinterpret_cast<TladGeom *>(b->ws + P.off_geom);
+    b->d_jobs = reinterpret_cast<JacobiJob *>(b->ws + P.off_jobs);
+    b->d_fbjobs = reinterpret_cast<JacobiJob *>(b->ws + P.off_fbjobs);
     b->d_infoptr = reinterpret_cast<const int32_t **>(b->ws + P.off_iptr);
     b->d_flags = reinterpret_cast<int32_t *>(b->ws + P.off_flags);
     b->d_titer = reinterpret_cast<int32_t *>(b->ws + P.off_titer);
@@ -1692,6 +1734,9 @@ int eda_batch_solve(eda_batch *b, int32_t k_cap, double rtol, int32_t maxit, int
         for (const auto &k : b->classes)
             for (int i : k.members) geo[i] = k.gs;
         HIP_TRY(hipMemcpyAsync(b->d_geom, geo.data(), sizeof(TladGeom) * np, hipMemcpyHostToDevice, s));
+        std::vector<JacobiJob> jobs(np);
+        for (int i = 0; i < np; i++) jobs[i] = jacobi_job(*b->probs[i], b->ell[i]);
+        HIP_TRY(hipMemcpyAsync(b->d_jobs, jobs.data(), sizeof(JacobiJob) * np, hipMemcpyHostToDevice, s));
         // first queue layout from the expected cost of a column (one
         // iteration each); later calls use the measured cost
         b->stasks = st;

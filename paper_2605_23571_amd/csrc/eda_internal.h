@@ -313,6 +313,14 @@ hipError_t launch_sym(hipStream_t s, int l, double *W);
 hipError_t launch_small_gemm(hipStream_t s, int l, bool ta, bool tb, const double *A, const double *B,
                              double *C);
 hipError_t launch_jacobi_svd_u(hipStream_t s, int l, double *T, double *U, double *sig);
+// One Jacobi SVD of a batch: T (l x l) -> U, sig as launch_jacobi_svd_u.
+struct JacobiJob {
+    int l;
+    const double *T;
+    double *U, *sig;
+};
+// One workgroup per job (device array); every job's l <= lmax <= 128.
+hipError_t launch_jacobi_svd_batch(hipStream_t s, int njobs, const JacobiJob *d_jobs, int lmax);
 hipError_t launch_jacobi_eig(hipStream_t s, int l, double *T, double *Vwork, double *V, double *lam);
 hipError_t launch_fix_signs(hipStream_t s, int n, int k, double *S, long long lds);
 hipError_t launch_lmp_coef(hipStream_t s, int k, const double *sig, double nu, int square,

@@ -140,11 +140,9 @@ __device__ __forceinline__ void rr_pair(int m, int r, int k, int &p, int &q) {
 // One-sided (Hestenes) Jacobi SVD of T (l x l): columns are rotated until
 // mutually orthogonal; then sigma_j = ||t_j||, U[:, rank(j)] = t_j / sigma_j
 // with ranks sorting sigma descending (ties: lower index first).
-__global__ __launch_bounds__(SJ) void k_jacobi_svd(int l, const double *__restrict__ T, double *__restrict__ U,
-                                                   double *__restrict__ sig) {
-    extern __shared__ double A[];  // l x l col-major
-    __shared__ int rotated;
-    __shared__ double nrm[128];
+// A: l x l doubles of LDS; rotated, nrm: LDS flags and norms (128).
+__device__ __forceinline__ void jacobi_svd(int l, const double *__restrict__ T, double *__restrict__ U,
+                                           double *__restrict__ sig, double *A, int &rotated, double *nrm) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int idx = tid; idx < l * l; idx += SJ) A[idx] = T[idx];
     __syncthreads();
@@ -206,6 +204,24 @@ __global__ __launch_bounds__(SJ) void k_jacobi_svd(int l, const double *__restri
         double inv = sj > 0 ? 1.0 / sj : 0.0;
         for (int i = 0; i < l; i++) U[i + (long long)rank * l] = A[i + j * l] * inv;
     }
+}
+
+__global__ __launch_bounds__(SJ) void k_jacobi_svd(int l, const double *__restrict__ T, double *__restrict__ U,
+                                                   double *__restrict__ sig) {
+    extern __shared__ double A[];  // l x l col-major
+    __shared__ int rotated;
+    __shared__ double nrm[128];
+    jacobi_svd(l, T, U, sig, A, rotated, nrm);
+}
+
+// Many independent SVDs in one launch, one workgroup each (the same
+// arithmetic as k_jacobi_svd, so the same bits).
+__global__ __launch_bounds__(SJ) void k_jacobi_svd_batch(const JacobiJob *__restrict__ jobs) {
+    extern __shared__ double A[];
+    __shared__ int rotated;
+    __shared__ double nrm[128];
+    const JacobiJob j = jobs[blockIdx.x];
+    jacobi_svd(j.l, j.T, j.U, j.sig, A, rotated, nrm);
 }
 
 // Two-sided cyclic Jacobi EVD of symmetric T (l x l), parallel ordering:
@@ -381,6 +397,13 @@ hipError_t launch_small_gemm(hipStream_t s, int l, bool ta, bool tb, const doubl
 hipError_t launch_jacobi_svd_u(hipStream_t s, int l, double *T, double *U, double *sig) {
     if (l > 128) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_jacobi_svd, dim3(1), dim3(SJ), sizeof(double) * l * l, s, l, T, U, sig);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_svd_batch(hipStream_t s, int njobs, const JacobiJob *d_jobs, int lmax) {
+    if (njobs <= 0) return hipSuccess;
+    if (lmax < 1 || lmax > 128) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_jacobi_svd_batch, dim3(njobs), dim3(SJ), sizeof(double) * lmax * lmax, s, d_jobs);
     return hipGetLastError();
 }
 
