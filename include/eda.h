@@ -316,13 +316,17 @@ int eda_destroy(eda_ctx *ctx);
  * 0..L from dz = 0 (the system_with_CVT equation), i.e. per problem exactly
  * what eda_sketch_evd(RHS_DIFF, ell, ell, 1, NYSTROM, MID) followed by
  * eda_pcg_solve(0..L) computes, up to rounding order.
- * Problems with equal n form a class.  A class runs one multi-problem sketch
- * launch and one persistent solve launch whose workgroups take member columns
- * from a work queue and iterate each to its final status without host
- * round trips; the classes run as parallel branches of one captured graph that
- * later calls with the same parameters replay.  The first call also tunes, per
- * class, the launch geometry (waves per workgroup, time-block length) by timing
- * the class's sketch launch.
+ * Problems with equal n form a class.  Each class runs one multi-problem
+ * sketch launch (the classes as parallel branches), and the Nystrom cores of
+ * all problems follow, in one captured graph; problems whose unshifted
+ * Cholesky fails are then redone with the shifts of eda_sketch_evd.  One
+ * persistent launch, in a second captured graph, solves the members of every
+ * problem: its workgroups take member columns from work queues (one per XCD,
+ * whole problems each) and iterate each to its final status without host
+ * round trips.  Later calls with the same parameters replay both graphs.  The
+ * first call also tunes, per class, the sketch geometry (waves per workgroup,
+ * time-block length) by timing the class's sketch launch, and the solve
+ * geometry for one common number of waves.
  * Every context must use the banded U_B (EDA_UB_BANDED), be set up and not be
  * used concurrently by other calls while the batch exists; a context appears
  * at most once.  The batch reuses each context's workspace for its sketch and
