@@ -975,6 +975,7 @@ struct eda_batch {
     TladGeom *d_geom = nullptr;           // solve geometry of each problem
     JacobiJob *d_jobs = nullptr;          // SVD operands of every problem (sketch graph)
     JacobiJob *d_fbjobs = nullptr;        // SVD operands of the fallback problems
+    CholJob *d_chol = nullptr;            // operands of the three Cholesky steps, 3 x np
     int solve_waves = 0, solve_grid = 0;  // the one persistent solve launch
     size_t solve_lds = 0;
     const int32_t **d_infoptr = nullptr;  // each problem's sketch outcome slots
@@ -1014,8 +1015,8 @@ struct eda_batch {
 namespace {
 
 struct BatchPlan {
-    size_t off_solve, off_hv, off_st, off_ht, off_cnt, off_qoff, off_geom, off_jobs, off_fbjobs, off_iptr, off_flags,
-        off_titer, total;
+    size_t off_solve, off_hv, off_st, off_ht, off_cnt, off_qoff, off_geom, off_jobs, off_fbjobs, off_chol, off_iptr,
+        off_flags, off_titer, total;
 };
 
 BatchPlan batch_plan(eda_ctx *const *ctxs, int np) {
@@ -1036,6 +1037,7 @@ BatchPlan batch_plan(eda_ctx *const *ctxs, int np) {
     P.off_geom = lay.take(sizeof(TladGeom) * np);
     P.off_jobs = lay.take(sizeof(JacobiJob) * np);
     P.off_fbjobs = lay.take(sizeof(JacobiJob) * np);
+    P.off_chol = lay.take(sizeof(CholJob) * 3 * np);
     P.off_iptr = lay.take(sizeof(int32_t *) * np);
     P.off_flags = lay.take(sizeof(int32_t) * np);
     P.off_titer = lay.take(sizeof(int32_t) * (st ? st : 1));
@@ -1044,35 +1046,61 @@ BatchPlan batch_plan(eda_ctx *const *ctxs, int np) {
 }
 
 // The Nystrom core of eda_sketch_evd (q = 1, no shift) with no host
-// synchronisation, in two halves around the SVD of T (which the batch runs for
-// all problems in one launch, jacobi_job gives its operands): CholQR2 of Y,
-// W = Phi^T Y, C = chol(W), T = R_Y C^-1; then S = Q U, signs, theta "mid" and
-// the LMP coefficients.  The three Cholesky outcomes land in sk_info[0..2]; the
-// caller checks them after the run.
+// synchronisation, in phases around the three Cholesky factorisations and the
+// SVD of T, which the batch runs for all problems at once (one launch each,
+// one workgroup per problem; chol_job and jacobi_job give their operands):
+//   0: G = Y^T Y                  -> chol 0: R1, R1^-1
+//   1: Q1 = Y R1^-1, G = Q1^T Q1  -> chol 1: R2, R2^-1
+//   2: Q = Q1 R2^-1, R_Y = R2 R1, W = Phi^T Y (symmetrised) -> chol 2: C, C^-1
+//   3: T = R_Y C^-1               -> SVD
+// then nystrom_post_svd: S = Q U, signs, theta "mid", the LMP coefficients.
+// The three Cholesky outcomes land in sk_info[0..2]; the caller checks them
+// after the run.  Slots of sk_small (l_max^2 doubles each): 0 G, 1 R1 then
+// C^-1, 2 R1^-1 then T, 3 R2 then U, 4 R2^-1 then sigma, 7 R_Y, 8 W, 9 C.
 JacobiJob jacobi_job(const Ctx &c, int l) {
     const size_t ls = (size_t)c.max_ell * c.max_ell;
     return JacobiJob{l, c.sk_small + 2 * ls, c.sk_small + 3 * ls, c.sk_small + 4 * ls};
 }
 
-int nystrom_pre_svd(Ctx &c, int l) {
+CholJob chol_job(const Ctx &c, int l, int which) {
+    const size_t ls = (size_t)c.max_ell * c.max_ell;
+    double *m = c.sk_small;
+    switch (which) {
+        case 0: return CholJob{l, m, 0.0, m + 1 * ls, m + 2 * ls, c.sk_info + 0};
+        case 1: return CholJob{l, m, 0.0, m + 3 * ls, m + 4 * ls, c.sk_info + 1};
+        default: return CholJob{l, m + 8 * ls, 0.0, m + 9 * ls, m + 1 * ls, c.sk_info + 2};
+    }
+}
+
+int nystrom_phase(Ctx &c, int l, int phase) {
     hipStream_t s = c.stream;
     const int n = c.n;
     const size_t ls = (size_t)c.max_ell * c.max_ell;
     double *G = c.sk_small, *R1 = c.sk_small + 1 * ls, *R1i = c.sk_small + 2 * ls;
     double *R2 = c.sk_small + 3 * ls, *R2i = c.sk_small + 4 * ls;
-    double *RY = c.sk_small + 7 * ls, *Wm = c.sk_small + 8 * ls, *Cm = c.sk_small + 9 * ls;
+    double *RY = c.sk_small + 7 * ls, *Wm = c.sk_small + 8 * ls;
     double *Ci = c.sk_small + 1 * ls, *Tm = c.sk_small + 2 * ls;
-    HIP_TRY(gemm_f64(s, true, l, l, n, c.sk_y, n, c.sk_y, n, G, l, nullptr, 0, nullptr, c.splitk, c.splitk_elems));
-    HIP_TRY(launch_chol_inv(s, l, G, 0.0, R1, R1i, c.sk_info + 0));
-    HIP_TRY(gemm_f64(s, false, n, l, l, c.sk_y, n, R1i, l, c.sk_q1, n, nullptr, 0, nullptr, nullptr, 0));
-    HIP_TRY(gemm_f64(s, true, l, l, n, c.sk_q1, n, c.sk_q1, n, G, l, nullptr, 0, nullptr, c.splitk, c.splitk_elems));
-    HIP_TRY(launch_chol_inv(s, l, G, 0.0, R2, R2i, c.sk_info + 1));
-    HIP_TRY(gemm_f64(s, false, n, l, l, c.sk_q1, n, R2i, l, c.sk_q, n, nullptr, 0, nullptr, nullptr, 0));
-    HIP_TRY(launch_small_gemm(s, l, false, false, R2, R1, RY));
-    HIP_TRY(gemm_f64(s, true, l, l, n, c.sk_phi, n, c.sk_y, n, Wm, l, nullptr, 0, nullptr, c.splitk, c.splitk_elems));
-    HIP_TRY(launch_sym(s, l, Wm));
-    HIP_TRY(launch_chol_inv(s, l, Wm, 0.0, Cm, Ci, c.sk_info + 2));
-    HIP_TRY(launch_small_gemm(s, l, false, false, RY, Ci, Tm));
+    switch (phase) {
+        case 0:
+            HIP_TRY(gemm_f64(s, true, l, l, n, c.sk_y, n, c.sk_y, n, G, l, nullptr, 0, nullptr, c.splitk,
+                             c.splitk_elems));
+            break;
+        case 1:
+            HIP_TRY(gemm_f64(s, false, n, l, l, c.sk_y, n, R1i, l, c.sk_q1, n, nullptr, 0, nullptr, nullptr, 0));
+            HIP_TRY(gemm_f64(s, true, l, l, n, c.sk_q1, n, c.sk_q1, n, G, l, nullptr, 0, nullptr, c.splitk,
+                             c.splitk_elems));
+            break;
+        case 2:
+            HIP_TRY(gemm_f64(s, false, n, l, l, c.sk_q1, n, R2i, l, c.sk_q, n, nullptr, 0, nullptr, nullptr, 0));
+            HIP_TRY(launch_small_gemm(s, l, false, false, R2, R1, RY));
+            HIP_TRY(gemm_f64(s, true, l, l, n, c.sk_phi, n, c.sk_y, n, Wm, l, nullptr, 0, nullptr, c.splitk,
+                             c.splitk_elems));
+            HIP_TRY(launch_sym(s, l, Wm));
+            break;
+        default:
+            HIP_TRY(launch_small_gemm(s, l, false, false, RY, Ci, Tm));
+            break;
+    }
     return EDA_OK;
 }
 
@@ -1318,19 +1346,21 @@ int batch_enqueue_sketch(eda_batch &b) {
         HIP_TRY(hipEventRecord(k.done, k.side));
         HIP_TRY(hipStreamWaitEvent(s, k.done, 0));
     }
-    // Nystrom cores, problems spread over parallel branches, with the SVDs of
-    // T of every problem in one launch (one workgroup each) in the middle
+    // Nystrom cores: the per-problem GEMMs of each phase spread over parallel
+    // branches, then the phase's Cholesky factorisations (or SVDs) of every
+    // problem in one launch (one workgroup each)
     const size_t nl = b.lanes.size();
+    const int np = (int)b.probs.size();
     int lmax = 1;
     for (int l : b.ell) lmax = l > lmax ? l : lmax;
-    for (int half = 0; half < 2; half++) {
+    for (int phase = 0; phase < 5; phase++) {
         HIP_TRY(hipEventRecord(b.fork, s));
         for (size_t l = 0; l < nl; l++) HIP_TRY(hipStreamWaitEvent(b.lanes[l], b.fork, 0));
-        for (size_t i = 0; i < b.probs.size(); i++) {
+        for (int i = 0; i < np; i++) {
             Ctx &c = *b.probs[i];
             c.stream = b.lanes[i % nl];
-            if (half == 0)
-                EDA_TRY(nystrom_pre_svd(c, b.ell[i]));
+            if (phase < 4)
+                EDA_TRY(nystrom_phase(c, b.ell[i], phase));
             else
                 EDA_TRY(nystrom_post_svd(c, b.ell[i], b.ell[i]));
         }
@@ -1338,7 +1368,8 @@ int batch_enqueue_sketch(eda_batch &b) {
             HIP_TRY(hipEventRecord(b.lane_done[l], b.lanes[l]));
             HIP_TRY(hipStreamWaitEvent(s, b.lane_done[l], 0));
         }
-        if (half == 0) HIP_TRY(launch_jacobi_svd_batch(s, (int)b.probs.size(), b.d_jobs, lmax));
+        if (phase < 3) HIP_TRY(launch_chol_inv_batch(s, np, b.d_chol + (size_t)phase * np, lmax));
+        if (phase == 3) HIP_TRY(launch_jacobi_svd_batch(s, np, b.d_jobs, lmax));
     }
     HIP_TRY(launch_gather_info(s, (int)b.probs.size(), b.d_infoptr, b.d_flags));
     return EDA_OK;
@@ -1633,6 +1664,7 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
     b->d_geom = reinterpret_cast<TladGeom *>(b->ws + P.off_geom);
     b->d_jobs = reinterpret_cast<JacobiJob *>(b->ws + P.off_jobs);
     b->d_fbjobs = reinterpret_cast<JacobiJob *>(b->ws + P.off_fbjobs);
+    b->d_chol = reinterpret_cast<CholJob *>(b->ws + P.off_chol);
     b->d_infoptr = reinterpret_cast<const int32_t **>(b->ws + P.off_iptr);
     b->d_flags = reinterpret_cast<int32_t *>(b->ws + P.off_flags);
     b->d_titer = reinterpret_cast<int32_t *>(b->ws + P.off_titer);
@@ -1735,8 +1767,13 @@ int eda_batch_solve(eda_batch *b, int32_t k_cap, double rtol, int32_t maxit, int
             for (int i : k.members) geo[i] = k.gs;
         HIP_TRY(hipMemcpyAsync(b->d_geom, geo.data(), sizeof(TladGeom) * np, hipMemcpyHostToDevice, s));
         std::vector<JacobiJob> jobs(np);
-        for (int i = 0; i < np; i++) jobs[i] = jacobi_job(*b->probs[i], b->ell[i]);
+        std::vector<CholJob> cjobs(3 * (size_t)np);
+        for (int i = 0; i < np; i++) {
+            jobs[i] = jacobi_job(*b->probs[i], b->ell[i]);
+            for (int w = 0; w < 3; w++) cjobs[(size_t)w * np + i] = chol_job(*b->probs[i], b->ell[i], w);
+        }
         HIP_TRY(hipMemcpyAsync(b->d_jobs, jobs.data(), sizeof(JacobiJob) * np, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(b->d_chol, cjobs.data(), sizeof(CholJob) * cjobs.size(), hipMemcpyHostToDevice, s));
         // first queue layout from the expected cost of a column (one
         // iteration each); later calls use the measured cost
         b->stasks = st;

@@ -321,6 +321,16 @@ struct JacobiJob {
 };
 // One workgroup per job (device array); every job's l <= lmax <= 128.
 hipError_t launch_jacobi_svd_batch(hipStream_t s, int njobs, const JacobiJob *d_jobs, int lmax);
+// One factorisation of a batch: as launch_chol_inv(l, W, shift, C, Cinv, info).
+struct CholJob {
+    int l;
+    const double *W;
+    double shift;
+    double *C, *Cinv;
+    int32_t *info;
+};
+// One workgroup per job (device array); every job's l <= lmax <= 128.
+hipError_t launch_chol_inv_batch(hipStream_t s, int njobs, const CholJob *d_jobs, int lmax);
 hipError_t launch_jacobi_eig(hipStream_t s, int l, double *T, double *Vwork, double *V, double *lam);
 hipError_t launch_fix_signs(hipStream_t s, int n, int k, double *S, long long lds);
 hipError_t launch_lmp_coef(hipStream_t s, int k, const double *sig, double nu, int square,

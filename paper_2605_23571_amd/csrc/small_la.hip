@@ -25,11 +25,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 // from the last row up, X[i] /= C_ii then X[r] -= C_ri X[i] for r < i, in a
 // second LDS buffer when l <= 64; for larger l column j of X is built from the
 // finished columns, X_ij = -X_jj sum_{k=i}^{j-1} X_ik C_kj, in place.
-__global__ __launch_bounds__(SC) void k_chol_inv(int l, const double *__restrict__ W, double shift,
-                                                 double *__restrict__ C, double *__restrict__ Cinv,
-                                                 int32_t *__restrict__ info) {
-    extern __shared__ double S[];  // l x l, col-major; upper triangle becomes C; then X (l <= 64)
-    __shared__ int fail;
+// S: LDS, l x l doubles (2 l x l when l <= 64); fail: an LDS flag.
+__device__ __forceinline__ void chol_inv(int l, const double *__restrict__ W, double shift, double *__restrict__ C,
+                                         double *__restrict__ Cinv, int32_t *__restrict__ info, double *S,
+                                         int &fail) {
     const int tid = threadIdx.x;
     for (int idx = tid; idx < l * l; idx += SC) {
         int i = idx % l, j = idx / l;
@@ -97,6 +96,23 @@ __global__ __launch_bounds__(SC) void k_chol_inv(int l, const double *__restrict
         int i = idx % l, j = idx / l;
         Cinv[idx] = (i <= j) ? S[idx] : 0.0;
     }
+}
+
+__global__ __launch_bounds__(SC) void k_chol_inv(int l, const double *__restrict__ W, double shift,
+                                                 double *__restrict__ C, double *__restrict__ Cinv,
+                                                 int32_t *__restrict__ info) {
+    extern __shared__ double S[];  // l x l, col-major; upper triangle becomes C; then X (l <= 64)
+    __shared__ int fail;
+    chol_inv(l, W, shift, C, Cinv, info, S, fail);
+}
+
+// Many independent factorisations in one launch, one workgroup each (the same
+// arithmetic as k_chol_inv, so the same bits).
+__global__ __launch_bounds__(SC) void k_chol_inv_batch(const CholJob *__restrict__ jobs) {
+    extern __shared__ double S[];
+    __shared__ int fail;
+    const CholJob j = jobs[blockIdx.x];
+    chol_inv(j.l, j.W, j.shift, j.C, j.Cinv, j.info, S, fail);
 }
 
 __global__ void k_sym(int l, double *W) {
@@ -381,6 +397,16 @@ hipError_t launch_chol_inv(hipStream_t s, int l, const double *W, double shift, 
                            int32_t *info) {
     const size_t lds = sizeof(double) * l * l * (l <= 64 ? 2 : 1);
     hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(SC), lds, s, l, W, shift, C, Cinv, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_chol_inv_batch(hipStream_t s, int njobs, const CholJob *d_jobs, int lmax) {
+    if (njobs <= 0) return hipSuccess;
+    if (lmax < 1 || lmax > 128) return hipErrorInvalidValue;
+    // every job fits: a job needs 2 l^2 doubles up to l = 64 and l^2 above
+    const int need = lmax <= 64 ? 2 * lmax * lmax : (lmax * lmax > 2 * 64 * 64 ? lmax * lmax : 2 * 64 * 64);
+    const size_t lds = sizeof(double) * need;
+    hipLaunchKernelGGL(k_chol_inv_batch, dim3(njobs), dim3(SC), lds, s, d_jobs);
     return hipGetLastError();
 }
 
