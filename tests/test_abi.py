@@ -58,3 +58,16 @@ def test_null_handles_rejected():
     assert L.eda_hessvec(None, None, 1, None, 40, None, 40, 0) == eda.EDA_ERR_INVALID_ARG
     assert L.eda_destroy(None) == eda.EDA_ERR_INVALID_ARG
     assert L.eda_profile(None, 1) == eda.EDA_ERR_INVALID_ARG
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU per run: the bench exits with a message before it touches a device
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
