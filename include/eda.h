@@ -144,7 +144,9 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
  * with FP32 operands (relative error of order 1e-6 against FP64); EDA_HV_BF16
  * takes BF16 operands for the dense U_B products (relative error of order 1e-3).
  * Both are meant for sketch products only; with the banded U_B the U_B products
- * stay FP64. */
+ * stay FP64.  With the banded U_B in FP64, when few columns are given the
+ * columns run on pieces (eda_set_split); the results are the same bit for bit.
+ */
 int eda_hessvec(eda_ctx *ctx, const int32_t *d_col_member, int32_t nb,
                 const double *d_X, int64_t ldx, double *d_Y, int64_t ldy, uint32_t flags);
 
@@ -289,16 +291,18 @@ int eda_sketch_learned(eda_ctx *ctx, const eda_mlp_dims *dims, const uint16_t *d
  * among these.  Errors: EDA_ERR_UNSUPPORTED for a geometry n does not admit. */
 int eda_set_geometry(eda_ctx *ctx, int32_t waves, int32_t tb);
 
-/* Pieces per member column in the iterations of eda_pcg_solve with the banded
- * U_B and the LMP.  The Hessian part of such an iteration runs on P pieces of
- * every running column, one workgroup each: a piece integrates its share of
+/* Pieces per column in the iterations of eda_pcg_solve with the banded U_B and
+ * the LMP, and in FP64 eda_hessvec calls with the banded U_B.  The Hessian part
+ * of such an iteration, or such a product, runs on P pieces of every running
+ * column, one workgroup each: a piece integrates its share of
  * the n states plus a halo of 12 N + 2 w states on each side (w the half-width
  * of the banded U_B), the reach of the TL/AD runs over the window and of U_B
  * on both ends, so its own outputs are exact; the pieces' partial sums of
  * p^T (I + A) p are added in piece order.  pieces = 0 (the default): P is the
  * largest of 1, 2, 3, 4, 8 with P x (members still running at the last
- * convergence check) <= the device's compute units; 1 to 8: that P in every
- * iteration.  Solutions agree with P = 1 to rounding.  Errors:
+ * convergence check, or columns of the product) <= the device's compute units;
+ * 1 to 8: that P in every iteration and product.  Solutions agree with P = 1 to
+ * rounding; Hessian products are bit-identical.  Errors:
  * EDA_ERR_UNSUPPORTED if the context is not banded, or P > 1 pieces do not fit
  * n (ring of ceil(n / P) + 2 halo states longer than n, or a window wider than
  * the kernel supports); EDA_ERR_INVALID_ARG for other values. */

@@ -227,8 +227,20 @@ int run_tlad(Ctx &c, const TladArgs &a, int mode, bool fp32, const SplitCols *sc
     return EDA_OK;
 }
 
+// Pieces per column of a split launch over `columns` columns: the forced
+// count, else the largest of 1, 2, 3, 4, 8 with pieces x columns <= CUs whose
+// ring fits n (5 to 7 pieces were measured no faster than 4).
+int split_pieces(const Ctx &c, int columns) {
+    if (c.split_force != 0) return c.split_force;
+    int P = 1;
+    for (int cand : {2, 3, 4, 8})
+        if ((long long)cand * columns <= c.num_cus && tlad_split_ring(c.n, c.N, c.band_hi, cand) > 0) P = cand;
+    return P;
+}
+
 // Batched Hessian product.  Banded U_B: one fused launch (U_B, TL, AD, U_B,
-// identity) per call; dense U_B: FP64 MFMA GEMM, TL/AD, GEMM.
+// identity) per call, on pieces of each column when fewer columns than CUs
+// run (FP64 only); dense U_B: FP64 MFMA GEMM, TL/AD, GEMM.
 int hessvec(Ctx &c, const int32_t *cols, int nb, const double *X, long long ldx, double *Y, long long ldy,
             uint32_t flags, const int32_t *active) {
     if (nb <= 0) return EDA_OK;
@@ -243,6 +255,13 @@ int hessvec(Ctx &c, const int32_t *cols, int nb, const double *X, long long ldx,
         a.lam = Y;
         a.ldl = ldy;
         a.add_identity = add ? 1 : 0;
+        const int P = fp32 ? 1 : split_pieces(c, nb);
+        if (P > 1) {
+            a.pieces = P;
+            a.ring = tlad_split_ring(c.n, c.N, c.band_hi, P);
+            a.halo = tlad_split_halo(c.N, c.band_hi);
+            return run_tlad(c, a, TLAD_SPLIT_HV, false);
+        }
         return run_tlad(c, a, TLAD_HV, fp32);
     }
     EDA_TRY(ub_apply(c, nb, X, ldx, c.hv_v, c.n, nullptr, 0, active, lowp));
@@ -737,16 +756,7 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                     sc.count = known ? (int)known->size() : nm;
                     for (int i = 0; i < sc.count; i++) sc.col[i] = known ? (*known)[i] : (int16_t)i;
                 }
-                int P = active == 0 ? 1 : c.split_force;
-                if (P == 0) {
-                    // the largest of 1, 2, 3, 4, 8 that fits: 5 to 7 pieces
-                    // were measured no faster than 4 (their rings take a
-                    // geometry with fewer waves or a shorter time block)
-                    P = 1;
-                    for (int cand : {2, 3, 4, 8})
-                        if ((long long)cand * active <= c.num_cus && tlad_split_ring(n, c.N, c.band_hi, cand) > 0)
-                            P = cand;
-                }
+                const int P = active == 0 ? 1 : split_pieces(c, active);
                 if (P == 1) {
                     // whole columns: the fused iteration (its update hidden under the
                     // TL/AD work), then the LMP of the new residual

@@ -131,6 +131,7 @@ enum TladMode : int {
     TLAD_HV = 2,    // X -> U_B X -> TL -> AD -> U_B lambda_0 (+ X) -> Y, banded U_B in-kernel
     TLAD_PCG = 3,   // one fused PCG iteration per member column (banded U_B), see k_tlad
     TLAD_SPLIT = 4, // the Hessian part of a PCG iteration on pieces of each member column, see tlad_column
+    TLAD_SPLIT_HV = 5, // TLAD_HV on pieces of each column (ring, halos and pieces as TLAD_SPLIT)
 };
 
 // A member column split into P pieces: piece i owns the states

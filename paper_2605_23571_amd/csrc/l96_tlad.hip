@@ -256,7 +256,8 @@ __device__ __forceinline__ double block_sum(double v, double *red, int waves) {
 template <typename T, int Q, int MODE, bool EARLY = true>
 __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g, const int c, const int it,
                                             const int first, unsigned char *smraw, const int piece = 0) {
-    constexpr bool SPLIT = MODE == TLAD_SPLIT;
+    constexpr bool SPLIT_HV = MODE == TLAD_SPLIT_HV;
+    constexpr bool SPLIT = MODE == TLAD_SPLIT || SPLIT_HV;  // ring of one piece
     constexpr bool FUSED = (MODE == TLAD_HV || MODE == TLAD_PCG || SPLIT);
     const int n = a.n, N = a.N, p = a.nt * a.nv;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x, nthr = blockDim.x;
@@ -284,7 +285,8 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
     double *red = taps + W;
     double *lamd = reinterpret_cast<double *>(ring);  // ring reused as a double array for lambda_0
     const int own_lo = wave * g.S, own_hi = min(R, own_lo + g.S);
-    const int member = (MODE == TLAD_PCG || SPLIT) ? a.pcg.members[c] : (a.col_member ? a.col_member[c] : 0);
+    const int member = (MODE == TLAD_PCG || MODE == TLAD_SPLIT) ? a.pcg.members[c]
+                                                               : (a.col_member ? a.col_member[c] : 0);
     // row s of the member's padded trajectory, from ring position 0: trajm + s ext_len
     const double *trajm = a.trajx + (long long)member * a.trajx_stride + a.pad_l + off;
     const T h = (T)a.h, dt = (T)a.dt, dt6 = (T)a.dt6, dt3 = (T)a.dt3, hF = (T)(a.h * a.F);
@@ -302,6 +304,9 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
         if (MODE == TLAD_HV) {
             const double *x = a.V + (long long)c * a.ldv;
             for (int i = tid; i < n; i += nthr) u[i] = x[i];
+        } else if (SPLIT_HV) {
+            const double *x = a.V + (long long)c * a.ldv;
+            for (int j = tid; j < R; j += nthr) u[j] = x[state(j)];
         } else {
             // p = z + beta p with beta = rho'/rho, rho' = r^T z; first iteration p = z
             const double *r = a.pcg.r + cn, *z = a.pcg.z + cn;
@@ -561,6 +566,17 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
         return;
     }
 
+    if (SPLIT_HV) {
+        // Y (+ X) at the owned states of this piece
+        double *out = a.lam + (long long)c * a.ldl;
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+            const int j = wpos(base, q, R);
+            if ((ownm & (1u << q)) && j >= core_lo && j < core_hi) out[state(j)] = a.add_identity ? y[q] + u[j] : y[q];
+        }
+        return;
+    }
+
     if (SPLIT) {
         // (I + A) p at the owned states and this piece's part of p^T (I + A) p
         double pq = 0.0;
@@ -649,6 +665,16 @@ __global__ __launch_bounds__(512) void k_tlad_split(TladArgs a, TladGeom g, Spli
     const int piece = blockIdx.x / m;
     if (a.pcg.status[c] != COL_RUNNING) return;
     tlad_column<double, Q, TLAD_SPLIT>(a, g, c, a.pcg.it, a.pcg.first, smraw, piece);
+}
+
+// Split Hessian products: workgroup b takes piece b / nb of column b % nb.
+template <int Q>
+__global__ __launch_bounds__(512) void k_tlad_split_hv(TladArgs a, TladGeom g) {
+    extern __shared__ __align__(16) unsigned char smraw[];
+    const int c = (int)(blockIdx.x % a.nb);
+    const int piece = (int)(blockIdx.x / a.nb);
+    if (a.active && a.active[c] != COL_RUNNING) return;
+    tlad_column<double, Q, TLAD_SPLIT_HV>(a, g, c, 0, 0, smraw, piece);
 }
 
 // z = P r = r + S diag(coef) S^T r for one column (in-kernel LMP of the
@@ -862,9 +888,9 @@ __global__ __launch_bounds__(512) void k_hv_multi(const TladArgs *__restrict__ p
 
 template <typename T, int Q>
 size_t lds_bytes(const TladArgs &a, const TladGeom &g, int mode) {
-    const size_t R = mode == TLAD_SPLIT ? (size_t)a.ring : (size_t)a.n;
+    const size_t R = (mode == TLAD_SPLIT || mode == TLAD_SPLIT_HV) ? (size_t)a.ring : (size_t)a.n;
     size_t b = sizeof(T) * 2 * R + (sizeof(int) + sizeof(double)) * (size_t)g.waves * 64 * Q;
-    if (mode == TLAD_HV || mode == TLAD_PCG || mode == TLAD_SPLIT)
+    if (mode == TLAD_HV || mode == TLAD_PCG || mode == TLAD_SPLIT || mode == TLAD_SPLIT_HV)
         b += sizeof(double) * (R + (size_t)(a.band_hi - a.band_lo + 1) + 16);
     return b;
 }
@@ -887,6 +913,10 @@ hipError_t launch_q(hipStream_t s, const TladArgs &a, const TladGeom &g, int mod
             hipLaunchKernelGGL(k_tlad_split<Q>, dim3(m * a.pieces), block, lds, s, a, g, cs);
             break;
         }
+        case TLAD_SPLIT_HV:
+            if (!std::is_same<T, double>::value) return hipErrorInvalidValue;
+            hipLaunchKernelGGL(k_tlad_split_hv<Q>, dim3(a.nb * a.pieces), block, lds, s, a, g);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1055,12 +1085,12 @@ void tlad_pads_split(int n, int N, int band_hi, int *pad_l, int *pad_r) {
 hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32, int waves, int tb,
                        const SplitCols *sc) {
     if (a.nb <= 0) return hipSuccess;
-    if (mode == TLAD_SPLIT) {
+    if (mode == TLAD_SPLIT || mode == TLAD_SPLIT_HV) {
         if (fp32 || a.pieces < 1 || a.ring < 1 || a.ring > a.n) return hipErrorInvalidValue;
         if (a.pieces == 1 ? (a.ring != a.n || a.halo != 0) : a.ring != tlad_split_ring(a.n, a.N, a.band_hi, a.pieces))
             return hipErrorInvalidValue;
     }
-    const int R = mode == TLAD_SPLIT ? a.ring : a.n;
+    const int R = (mode == TLAD_SPLIT || mode == TLAD_SPLIT_HV) ? a.ring : a.n;
     if (waves != 0 && !tlad_waves_ok(R, waves)) return hipErrorInvalidValue;
     TladGeom g = tlad_geometry(R, waves, tb);
     if (g.q > 9 || g.tb < 1) return hipErrorInvalidValue;

@@ -400,6 +400,39 @@ def test_split_iterations_match_whole_columns(case):
     assert torch.equal(a["dz"], b["dz"])  # the automatic pieces do not depend on timing
 
 
+@pytest.mark.parametrize("case", ["n1001", "n2049"])
+def test_split_hessvec_matches_whole_columns(case):
+    # Hessian products on P pieces per column (ring of the piece's states with
+    # halos of 12 N + 2 w): every owned output is the whole column's, bit for
+    # bit, in member mode and in sketch mode, with and without the identity;
+    # and the oracle agrees.
+    cfg, g, o = problem(case)
+    n, L = cfg["n"], cfg["members"]
+    rng = np.random.default_rng(7)
+    X = torch.from_numpy(rng.standard_normal((L + 1, n))).cuda()
+    cols = np.arange(L + 1)
+    zero = np.zeros(L + 1, dtype=np.int64)
+    for cc in (cols, zero):
+        for add in (False, True):
+            eda.eda_set_split(g.ctx, 1)
+            ref = g.hessvec(cc, X, add_identity=add).clone()
+            done = 0
+            for P in (0, 2, 3, 4, 8):
+                try:
+                    eda.eda_set_split(g.ctx, P)
+                except eda.EdaError as e:
+                    assert e.code == eda.EDA_ERR_UNSUPPORTED and P > 2
+                    continue
+                Y = g.hessvec(cc, X, add_identity=add)
+                assert torch.equal(Y, ref), (case, P, add)
+                done += 1
+            assert done >= 3
+    eda.eda_set_split(g.ctx, 0)
+    Yc = to_np_cols(g.hessvec(cols, X, add_identity=True), n)
+    Xc = X.cpu().numpy().T
+    assert colrel(Yc, o.hess(Xc, cols)) < 1e-12
+
+
 def test_split_errors():
     cfg, g, o = problem("C1")  # n = 40: no ring shorter than n
     with pytest.raises(eda.EdaError) as e:
