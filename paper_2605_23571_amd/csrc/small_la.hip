@@ -10,12 +10,33 @@ namespace eda {
 namespace {
 
 constexpr int ST = 256;   // threads of the small kernels
-constexpr int SJ = 1024;  // threads of the Jacobi kernels (one wave per column pair)
+constexpr int SJ = 1024;  // threads of the Jacobi SVD kernels (one 16-lane row per column pair)
 constexpr int SC = 1024;  // threads of the Cholesky kernel (element-parallel updates)
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     return __shfl(v, 0, 64);
+}
+
+// v of lane (lane ^ M) within the 16-lane row, M fixed by the DPP control
+// (0x140: M = 15, 0x141: M = 7, 0xB1: M = 1, 0x4E: M = 2), as two 32-bit moves
+template <int CTRL>
+__device__ __forceinline__ double row_xor(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 16 lanes of a row: an xor butterfly over the masks 15, 7, 1, 2,
+// which span the row's lane indices.  Each step adds the same two values on
+// both lanes of a pair (in either order), so every lane ends with the same bits.
+__device__ __forceinline__ double row_sum(double v) {
+    v += row_xor<0x140>(v);
+    v += row_xor<0x141>(v);
+    v += row_xor<0xB1>(v);
+    v += row_xor<0x4E>(v);
+    return v;
 }
 
 // W = C^T C with C upper triangular (W + shift I), then Cinv = C^-1.
@@ -171,30 +192,32 @@ __device__ __forceinline__ void jacobi_svd(int l, const double *__restrict__ T, 
         if (tid == 0) rotated = 0;
         __syncthreads();
         for (int r = 0; r < m - 1; r++) {
-            for (int k = wave; k < m / 2; k += SJ / 64) {
+            // one 16-lane row per pair (rows of a wave run four pairs at once);
+            // a row takes or skips a pair as a whole
+            for (int k = tid >> 4; k < m / 2; k += SJ / 16) {
                 int p, q;
                 rr_pair(m, r, k, p, q);
                 if (q >= l) continue;
                 double *ap = A + p * l, *aq = A + q * l;
                 double al = 0, be = 0, ga = 0;
-                for (int i = lane; i < l; i += 64) {
+                for (int i = tid & 15; i < l; i += 16) {
                     al += ap[i] * ap[i];
                     be += aq[i] * aq[i];
                     ga += ap[i] * aq[i];
                 }
-                al = wave_sum(al);
-                be = wave_sum(be);
-                ga = wave_sum(ga);
+                al = row_sum(al);
+                be = row_sum(be);
+                ga = row_sum(ga);
                 if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
                     double zeta = (be - al) / (2.0 * ga);
                     double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                     double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-                    for (int i = lane; i < l; i += 64) {
+                    for (int i = tid & 15; i < l; i += 16) {
                         double x = ap[i], y = aq[i];
                         ap[i] = c * x - sn * y;
                         aq[i] = sn * x + c * y;
                     }
-                    if (lane == 0) rotated = 1;
+                    if ((tid & 15) == 0) rotated = 1;
                 }
             }
             __syncthreads();

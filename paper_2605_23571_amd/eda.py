@@ -158,11 +158,17 @@ def _stream():
 
 
 def _dev_f64(t, rows: int):
-    """(pointer, ld) of a [cols, rows] contiguous float64 CUDA tensor."""
+    """(pointer, ld) of a [cols, rows] float64 CUDA tensor whose rows are contiguous; ld = the
+    stride between columns (>= rows), so a column slice of a wider buffer passes as is."""
     torch = _torch()
-    if not (t.is_cuda and t.dtype == torch.float64 and t.dim() == 2 and t.shape[1] == rows and t.is_contiguous()):
-        raise ValueError(f"expected a contiguous float64 CUDA tensor of shape [cols, {rows}]")
-    return ctypes.c_void_p(t.data_ptr()), rows
+    ok = t.is_cuda and t.dtype == torch.float64 and t.dim() == 2 and t.shape[1] == rows
+    if ok and t.shape[0] > 1 and rows > 0:
+        ok = t.stride(1) == 1 and t.stride(0) >= rows
+    elif ok:
+        ok = t.is_contiguous()
+    if not ok:
+        raise ValueError(f"expected a float64 CUDA tensor of shape [cols, {rows}] with contiguous rows")
+    return ctypes.c_void_p(t.data_ptr()), (t.stride(0) if t.shape[0] > 1 and rows > 0 else rows)
 
 
 def eda_setup(c: eda_config, normals, ws):

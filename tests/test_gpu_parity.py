@@ -431,6 +431,23 @@ def test_split_hessvec_matches_whole_columns(case):
     Yc = to_np_cols(g.hessvec(cols, X, add_identity=True), n)
     Xc = X.cpu().numpy().T
     assert colrel(Yc, o.hess(Xc, cols)) < 1e-12
+    # five columns (8 pieces each by default) read from and written to column
+    # slices of wider buffers (ldx = n + 37, ldy = n + 53): the same values as
+    # whole columns, and the padding rows stay as they were
+    sel = torch.tensor([3, 0, L, 1, 2], dtype=torch.int32, device="cuda")
+    Xw = torch.from_numpy(rng.standard_normal((5, n + 37))).cuda()
+    for P in (1, 0):
+        eda.eda_set_split(g.ctx, P)
+        Yw = torch.full((5, n + 53), 7.25, dtype=torch.float64, device="cuda")
+        eda.eda_hessvec(g.ctx, n, sel, Xw[:, :n], Yw[:, :n], eda.EDA_HV_ADD_IDENTITY)
+        assert torch.all(Yw[:, n:] == 7.25)
+        if P == 1:
+            ref = Yw[:, :n].clone()
+        else:
+            assert torch.equal(Yw[:, :n], ref), case
+    eda.eda_set_split(g.ctx, 0)
+    Xs = Xw[:, :n].cpu().numpy().T
+    assert colrel(to_np_cols(ref.contiguous(), n), o.hess(Xs, sel.cpu().numpy())) < 1e-12
 
 
 def test_split_errors():
