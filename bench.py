@@ -12,14 +12,15 @@ Forms: "chosen" = banded circulant U_B inside the fused TL/AD kernels, with the
 sketch's Hessian products in FP32 (trajectory, CholQR2, eigensolve, LMP and
 PCG in FP64); "plain" = dense U_B as FP64 MFMA GEMMs, FP64 throughout.  Hessian-vector products per second
 (member mode: every column on its own trajectory; sketch mode: all on the
-control trajectory) are reported too.
+control trajectory) are reported too, and so is the time of one sketch call per
+variant (Nystrom q = 1, 2, reduced precision, REVD).
 
-The roofline entry is for the dominant kernel, the fused PCG-iteration kernel
-(banded U_B, TL run, AD run, banded U_B, vector updates, one workgroup per
-member column): algorithmic bytes per active column (pcg_kernel_bytes_per_col)
-x active member-iterations over the timed region, divided by that kernel's
-summed duration from HIP events recorded around each of its launches on the
-launching stream.
+The roofline entry is for the dominant kernel, the Hessian part of a PCG
+iteration (banded U_B, TL run, AD run, banded U_B, vector updates; one
+workgroup per member column, or per piece of it): algorithmic bytes per active
+column (pcg_kernel_bytes_per_col) x active member-iterations per launch,
+divided by the kernel's average launch duration from HIP events recorded on the
+launching stream around every 16th launch of the timed steps.
 """
 import argparse
 import json
@@ -189,6 +190,27 @@ def precision_report(cfg, g, dz_chosen, oracle_lmp):
                             "note": "dz: GPU (reduced-precision sketch) and oracle solutions, both stopped at "
                                     f"||r|| <= {cfg['rtol']} ||b||"}
     return rep
+
+
+def sketch_times(cfg, g, reps=3):
+    """Wall time of one eda_sketch_evd call at full size (RHS-difference sketch,
+    ell and k of the workload), per variant, in ms: Nystrom with q = 1 and 2
+    passes in FP64, the chosen reduced-precision q = 2 Nystrom, and REVD (two
+    A-products and the Jacobi EVD).  Each call ends with its eigenvalues on the
+    host, so the wall clock brackets the whole device work."""
+    import torch
+    out = {}
+    variants = (("nystrom_q1_fp64", dict(q=1)), ("nystrom_q2_fp64", dict(q=2)),
+                ("nystrom_q2_mixed", dict(q=2, mixed=True)), ("revd_fp64", dict(method="revd")))
+    for name, kw in variants:
+        g.sketch_evd("rhs_diff", ell=cfg["ell"], k=cfg["k"], **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.sketch_evd("rhs_diff", ell=cfg["ell"], k=cfg["k"], **kw)
+        torch.cuda.synchronize()
+        out[name] = round(1e3 * (time.perf_counter() - t0) / reps, 3)
+    return out
 
 
 def run_uneven_batch(count, reps, plain_count):
@@ -397,6 +419,7 @@ def main():
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"], oracle_lmp = cpu_baseline(cfg, z, a.cpu_seconds)
     g = chosen["problem"]
+    line["sketch_ms"] = sketch_times(cfg, g)
     line["reduced_precision_sketch"] = precision_report(cfg, g, chosen["last_dz"].cpu().numpy(), oracle_lmp)
     g.close()
     print(json.dumps(line), flush=True)

@@ -264,30 +264,41 @@ __global__ __launch_bounds__(SJ) void k_jacobi_svd_batch(const JacobiJob *__rest
 }
 
 // Two-sided cyclic Jacobi EVD of symmetric T (l x l), parallel ordering:
-// T V = V diag(lam), lam descending (ties: lower index first).
-__global__ __launch_bounds__(ST) void k_jacobi_eig(int l, const double *__restrict__ T, double *__restrict__ V,
+// T V = V diag(lam), lam descending (ties: lower index first).  A round
+// rotates the m / 2 disjoint pairs (p_k, q_k) of the round-robin ordering at
+// once, A <- J^T A J and V <- V J.  The pairs partition the indices, so A
+// splits into 2 x 2 blocks (rows {p_a, q_a}, columns {p_b, q_b}) and each
+// block of J^T A J needs only its own entries: (B J_b) first, then J_a^T, the
+// same operations per entry as a column pass followed by a row pass.  One
+// barrier after the angles, one after the rotations.  V stays in LDS when
+// l <= 64 (VL), else in the global scratch Vg.
+template <bool VL>
+__global__ __launch_bounds__(SJ) void k_jacobi_eig(int l, const double *__restrict__ T, double *__restrict__ Vg,
                                                    double *__restrict__ Vout, double *__restrict__ lam) {
-    extern __shared__ double A[];  // l x l in LDS; V (l x l) is global scratch
+    extern __shared__ double A[];  // l x l (then V, l x l, when VL)
+    double *V = VL ? A + l * l : Vg;
     __shared__ double cs[64], sn[64];
+    __shared__ int pp[64], qq[64];
     __shared__ int rotated;
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < l * l; idx += ST) {
+    for (int idx = tid; idx < l * l; idx += SJ) {
         A[idx] = T[idx];
         V[idx] = (idx % l == idx / l) ? 1.0 : 0.0;
     }
     __syncthreads();
     const int m = (l + 1) & ~1, half = m / 2;
+    const double tol = (double)l * 2.220446049250313e-16;
     for (int sweep = 0; sweep < 60; sweep++) {
         if (tid == 0) rotated = 0;
         __syncthreads();
         for (int r = 0; r < m - 1; r++) {
-            for (int k = tid; k < half; k += ST) {
+            for (int k = tid; k < half; k += SJ) {
                 int p, q;
                 rr_pair(m, r, k, p, q);
                 double c = 1.0, s = 0.0;
                 if (q < l) {
                     double apq = A[p + q * l], app = A[p + p * l], aqq = A[q + q * l];
-                    if (apq != 0.0 && fabs(apq) > (double)l * 2.220446049250313e-16 * sqrt(fabs(app * aqq))) {
+                    if (apq != 0.0 && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
                         double tau = (aqq - app) / (2.0 * apq);
                         double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                         c = 1.0 / sqrt(1.0 + t * t);
@@ -295,41 +306,64 @@ __global__ __launch_bounds__(ST) void k_jacobi_eig(int l, const double *__restri
                         rotated = 1;
                     }
                 }
+                pp[k] = p;
+                qq[k] = q;
                 cs[k] = c;
                 sn[k] = s;
             }
             __syncthreads();
-            // columns: A <- A J, V <- V J
-            for (int idx = tid; idx < half * l; idx += ST) {
-                int k = idx / l, i = idx % l, p, q;
-                rr_pair(m, r, k, p, q);
-                if (q >= l || sn[k] == 0.0) continue;
-                double c = cs[k], s = sn[k];
-                double x = A[i + p * l], y = A[i + q * l];
-                A[i + p * l] = c * x - s * y;
-                A[i + q * l] = s * x + c * y;
-                x = V[i + p * l];
-                y = V[i + q * l];
-                V[i + p * l] = c * x - s * y;
-                V[i + q * l] = s * x + c * y;
+            // A <- J^T A J, one 2 x 2 block per (a, b); a q index of l (odd l)
+            // is the empty slot of the ordering and has no entries
+            for (int e = tid; e < half * half; e += SJ) {
+                const int a = e / half, b = e - a * half;
+                const double sa = sn[a], sb = sn[b];
+                if (sa == 0.0 && sb == 0.0) continue;
+                const double ca = cs[a], cb = cs[b];
+                const int pa = pp[a], qa = qq[a], pb = pp[b], qb = qq[b];
+                const bool qav = qa < l, qbv = qb < l;
+                // block entries x_rc: row r in {p_a, q_a}, column c in {p_b, q_b}
+                double xpp = A[pa + pb * l];
+                double xpq = qbv ? A[pa + qb * l] : 0.0;
+                double xqp = qav ? A[qa + pb * l] : 0.0;
+                double xqq = (qav && qbv) ? A[qa + qb * l] : 0.0;
+                if (sb != 0.0) {  // columns: col p = c col p - s col q, col q = s col p + c col q
+                    const double yp = cb * xpp - sb * xpq, yq = sb * xpp + cb * xpq;
+                    const double zp = cb * xqp - sb * xqq, zq = sb * xqp + cb * xqq;
+                    xpp = yp;
+                    xpq = yq;
+                    xqp = zp;
+                    xqq = zq;
+                }
+                if (sa != 0.0) {  // rows: row p = c row p - s row q, row q = s row p + c row q
+                    const double yp = ca * xpp - sa * xqp, yq = sa * xpp + ca * xqp;
+                    const double zp = ca * xpq - sa * xqq, zq = sa * xpq + ca * xqq;
+                    xpp = yp;
+                    xqp = yq;
+                    xpq = zp;
+                    xqq = zq;
+                }
+                A[pa + pb * l] = xpp;
+                if (qbv) A[pa + qb * l] = xpq;
+                if (qav) A[qa + pb * l] = xqp;
+                if (qav && qbv) A[qa + qb * l] = xqq;
             }
-            __syncthreads();
-            // rows: A <- J^T A
-            for (int idx = tid; idx < half * l; idx += ST) {
-                int k = idx / l, j = idx % l, p, q;
-                rr_pair(m, r, k, p, q);
-                if (q >= l || sn[k] == 0.0) continue;
-                double c = cs[k], s = sn[k];
-                double x = A[p + j * l], y = A[q + j * l];
-                A[p + j * l] = c * x - s * y;
-                A[q + j * l] = s * x + c * y;
+            // V <- V J
+            for (int e = tid; e < half * l; e += SJ) {
+                const int b = e / l, i = e - b * l;
+                const double sb = sn[b];
+                if (sb == 0.0) continue;
+                const double cb = cs[b];
+                const int pb = pp[b], qb = qq[b];
+                const double x = V[i + pb * l], y = V[i + qb * l];
+                V[i + pb * l] = cb * x - sb * y;
+                V[i + qb * l] = sb * x + cb * y;
             }
             __syncthreads();
         }
         if (!rotated) break;
         __syncthreads();
     }
-    for (int j = tid; j < l; j += ST) {
+    for (int j = tid; j < l; j += SJ) {
         double dj = A[j + j * l];
         int rank = 0;
         for (int i = 0; i < l; i++) {
@@ -458,7 +492,11 @@ hipError_t launch_jacobi_svd_batch(hipStream_t s, int njobs, const JacobiJob *d_
 
 hipError_t launch_jacobi_eig(hipStream_t s, int l, double *T, double *Vwork, double *V, double *lam) {
     if (l > 128) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_jacobi_eig, dim3(1), dim3(ST), sizeof(double) * l * l, s, l, T, Vwork, V, lam);
+    if (l < 1) return hipErrorInvalidValue;
+    if (l <= 64)
+        hipLaunchKernelGGL(k_jacobi_eig<true>, dim3(1), dim3(SJ), sizeof(double) * 2 * l * l, s, l, T, Vwork, V, lam);
+    else
+        hipLaunchKernelGGL(k_jacobi_eig<false>, dim3(1), dim3(SJ), sizeof(double) * l * l, s, l, T, Vwork, V, lam);
     return hipGetLastError();
 }
 

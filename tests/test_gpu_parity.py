@@ -275,6 +275,31 @@ def test_revd_and_power_pass(case):
     _compare_lmp(g, o, cfg, S, D, O.theta(D, "lamk"), eig, thg, 1e-9)
 
 
+REVD_CORES = {
+    # odd ell: the round-robin ordering of the EVD has an empty slot
+    "ell5": CASES["n203"],
+    # ell = 64: A and V of the EVD both in LDS
+    "ell64": LMP_CASES["n4096"][0],
+    # ell = 80: V in the global scratch
+    "ell80": LMP_CASES["n1001k77"][0],
+}
+
+
+@pytest.mark.parametrize("case", list(REVD_CORES))
+def test_revd_core_sizes(case):
+    # REVD (second A-product pass, Jacobi EVD of Q^T A Q) against the oracle's
+    # REVD at core sizes that take each path of the EVD kernel.
+    cfg = REVD_CORES[case]
+    z = W.problem_normals(cfg)
+    print(f"[revd] {case} n={cfg['n']} ell={cfg['ell']} k={cfg['k']}", flush=True)
+    g = eda.Problem(cfg, z)
+    o = O.Problem(cfg, z)
+    eig, thg = g.sketch_evd("rhs_diff", method="revd")
+    S, D = _oracle_sketch(o, "rhs_diff", cfg["ell"], cfg["k"], method="revd")
+    _compare_lmp(g, o, cfg, S, D, O.theta(D), eig, thg, 1e-9)
+    g.close()
+
+
 @pytest.mark.parametrize("kind", ["user", "b_psi", "ubt_psi"])
 def test_sketch_kinds(kind):
     cfg, g, o = problem("C1")
