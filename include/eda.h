@@ -144,9 +144,8 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
  * with FP32 operands (relative error of order 1e-6 against FP64); EDA_HV_BF16
  * takes BF16 operands for the dense U_B products (relative error of order 1e-3).
  * Both are meant for sketch products only; with the banded U_B the U_B products
- * stay FP64.  With the banded U_B in FP64, when few columns are given the
- * columns run on pieces (eda_set_split); the results are the same bit for bit.
- */
+ * stay FP64.  With the banded U_B, when few columns are given the columns run
+ * on pieces (eda_set_split); the results are the same bit for bit. */
 int eda_hessvec(eda_ctx *ctx, const int32_t *d_col_member, int32_t nb,
                 const double *d_X, int64_t ldx, double *d_Y, int64_t ldy, uint32_t flags);
 
@@ -292,7 +291,7 @@ int eda_sketch_learned(eda_ctx *ctx, const eda_mlp_dims *dims, const uint16_t *d
 int eda_set_geometry(eda_ctx *ctx, int32_t waves, int32_t tb);
 
 /* Pieces per column in the iterations of eda_pcg_solve with the banded U_B and
- * the LMP, and in FP64 eda_hessvec calls with the banded U_B.  The Hessian part
+ * the LMP, and in eda_hessvec calls with the banded U_B.  The Hessian part
  * of such an iteration, or such a product, runs on P pieces of every running
  * column, one workgroup each: a piece integrates its share of
  * the n states plus a halo of 12 N + 2 w states on each side (w the half-width

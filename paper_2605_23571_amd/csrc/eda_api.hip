@@ -240,7 +240,7 @@ int split_pieces(const Ctx &c, int columns) {
 
 // Batched Hessian product.  Banded U_B: one fused launch (U_B, TL, AD, U_B,
 // identity) per call, on pieces of each column when fewer columns than CUs
-// run (FP64 only); dense U_B: FP64 MFMA GEMM, TL/AD, GEMM.
+// run; dense U_B: FP64 MFMA GEMM, TL/AD, GEMM.
 int hessvec(Ctx &c, const int32_t *cols, int nb, const double *X, long long ldx, double *Y, long long ldy,
             uint32_t flags, const int32_t *active) {
     if (nb <= 0) return EDA_OK;
@@ -255,12 +255,12 @@ int hessvec(Ctx &c, const int32_t *cols, int nb, const double *X, long long ldx,
         a.lam = Y;
         a.ldl = ldy;
         a.add_identity = add ? 1 : 0;
-        const int P = fp32 ? 1 : split_pieces(c, nb);
+        const int P = split_pieces(c, nb);
         if (P > 1) {
             a.pieces = P;
             a.ring = tlad_split_ring(c.n, c.N, c.band_hi, P);
             a.halo = tlad_split_halo(c.N, c.band_hi);
-            return run_tlad(c, a, TLAD_SPLIT_HV, false);
+            return run_tlad(c, a, TLAD_SPLIT_HV, fp32);
         }
         return run_tlad(c, a, TLAD_HV, fp32);
     }

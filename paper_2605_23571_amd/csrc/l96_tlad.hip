@@ -667,14 +667,15 @@ __global__ __launch_bounds__(512) void k_tlad_split(TladArgs a, TladGeom g, Spli
     tlad_column<double, Q, TLAD_SPLIT>(a, g, c, a.pcg.it, a.pcg.first, smraw, piece);
 }
 
-// Split Hessian products: workgroup b takes piece b / nb of column b % nb.
-template <int Q>
+// Split Hessian products: workgroup b takes piece b / nb of column b % nb
+// (TL/AD in T; the U_B products and the trajectory stay FP64).
+template <typename T, int Q>
 __global__ __launch_bounds__(512) void k_tlad_split_hv(TladArgs a, TladGeom g) {
     extern __shared__ __align__(16) unsigned char smraw[];
     const int c = (int)(blockIdx.x % a.nb);
     const int piece = (int)(blockIdx.x / a.nb);
     if (a.active && a.active[c] != COL_RUNNING) return;
-    tlad_column<double, Q, TLAD_SPLIT_HV>(a, g, c, 0, 0, smraw, piece);
+    tlad_column<T, Q, TLAD_SPLIT_HV>(a, g, c, 0, 0, smraw, piece);
 }
 
 // z = P r = r + S diag(coef) S^T r for one column (in-kernel LMP of the
@@ -914,8 +915,7 @@ hipError_t launch_q(hipStream_t s, const TladArgs &a, const TladGeom &g, int mod
             break;
         }
         case TLAD_SPLIT_HV:
-            if (!std::is_same<T, double>::value) return hipErrorInvalidValue;
-            hipLaunchKernelGGL(k_tlad_split_hv<Q>, dim3(a.nb * a.pieces), block, lds, s, a, g);
+            hipLaunchKernelGGL((k_tlad_split_hv<T, Q>), dim3(a.nb * a.pieces), block, lds, s, a, g);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -1086,7 +1086,7 @@ hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32, in
                        const SplitCols *sc) {
     if (a.nb <= 0) return hipSuccess;
     if (mode == TLAD_SPLIT || mode == TLAD_SPLIT_HV) {
-        if (fp32 || a.pieces < 1 || a.ring < 1 || a.ring > a.n) return hipErrorInvalidValue;
+        if ((fp32 && mode == TLAD_SPLIT) || a.pieces < 1 || a.ring < 1 || a.ring > a.n) return hipErrorInvalidValue;
         if (a.pieces == 1 ? (a.ring != a.n || a.halo != 0) : a.ring != tlad_split_ring(a.n, a.N, a.band_hi, a.pieces))
             return hipErrorInvalidValue;
     }

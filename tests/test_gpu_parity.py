@@ -429,8 +429,8 @@ def test_split_iterations_match_whole_columns(case):
 def test_split_hessvec_matches_whole_columns(case):
     # Hessian products on P pieces per column (ring of the piece's states with
     # halos of 12 N + 2 w): every owned output is the whole column's, bit for
-    # bit, in member mode and in sketch mode, with and without the identity;
-    # and the oracle agrees.
+    # bit, in member mode and in sketch mode, with and without the identity,
+    # with FP64 and with FP32 TL/AD runs; and the oracle agrees.
     cfg, g, o = problem(case)
     n, L = cfg["n"], cfg["members"]
     rng = np.random.default_rng(7)
@@ -438,9 +438,9 @@ def test_split_hessvec_matches_whole_columns(case):
     cols = np.arange(L + 1)
     zero = np.zeros(L + 1, dtype=np.int64)
     for cc in (cols, zero):
-        for add in (False, True):
+        for add, mixed in ((False, False), (True, False), (True, True)):
             eda.eda_set_split(g.ctx, 1)
-            ref = g.hessvec(cc, X, add_identity=add).clone()
+            ref = g.hessvec(cc, X, add_identity=add, mixed=mixed).clone()
             done = 0
             for P in (0, 2, 3, 4, 8):
                 try:
@@ -448,8 +448,8 @@ def test_split_hessvec_matches_whole_columns(case):
                 except eda.EdaError as e:
                     assert e.code == eda.EDA_ERR_UNSUPPORTED and P > 2
                     continue
-                Y = g.hessvec(cc, X, add_identity=add)
-                assert torch.equal(Y, ref), (case, P, add)
+                Y = g.hessvec(cc, X, add_identity=add, mixed=mixed)
+                assert torch.equal(Y, ref), (case, P, add, mixed)
                 done += 1
             assert done >= 3
     eda.eda_set_split(g.ctx, 0)
