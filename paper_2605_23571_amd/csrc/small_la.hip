@@ -313,9 +313,11 @@ __global__ __launch_bounds__(SJ) void k_jacobi_eig(int l, const double *__restri
             }
             __syncthreads();
             // A <- J^T A J, one 2 x 2 block per (a, b); a q index of l (odd l)
-            // is the empty slot of the ordering and has no entries
+            // is the empty slot of the ordering and has no entries.  The row
+            // pair a varies fastest, so the lanes of a wave read down columns
+            // (distinct LDS banks) rather than along rows (one bank).
             for (int e = tid; e < half * half; e += SJ) {
-                const int a = e / half, b = e - a * half;
+                const int b = e / half, a = e - b * half;
                 const double sa = sn[a], sb = sn[b];
                 if (sa == 0.0 && sb == 0.0) continue;
                 const double ca = cs[a], cb = cs[b];
