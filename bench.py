@@ -13,7 +13,7 @@ sketch's Hessian products in FP32 (trajectory, CholQR2, eigensolve, LMP and
 PCG in FP64); "plain" = dense U_B as FP64 MFMA GEMMs, FP64 throughout.  Hessian-vector products per second
 (member mode: every column on its own trajectory; sketch mode: all on the
 control trajectory) are reported too, and so is the time of one sketch call per
-variant (Nystrom q = 1, 2, reduced precision, REVD).
+variant (Nystrom q = 1, 2, reduced precision, REVD), and PCG without the LMP.
 
 The roofline entry is for the dominant kernel, the Hessian part of a PCG
 iteration (banded U_B, TL run, AD run, banded U_B, vector updates; one
@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (dense U_B) form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-no-lmp", action="store_true", help="skip the unpreconditioned PCG leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-baseline sample time")
     ap.add_argument("--hv-reps", type=int, default=20)
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch (256 problems) measurement")
@@ -156,13 +157,35 @@ def run_form(cfg, z, ub_mode, steps, warmup, hv_reps, mixed=False, keep=False, q
                tlad_timed=timed, tlad_launches=launches, tlad_ms=tlad_ms, hessvec_per_s=hv,
                active_cols=iters_total)
     res["last_dz"] = outs[-1]["dz"]
+    res["last_iters"] = np.asarray(outs[-1]["iters"])
     res["problem"] = g if keep else None
     if not keep:
         g.close()
     return res
 
 
-def precision_report(cfg, g, dz_chosen, oracle_lmp):
+def no_lmp_report(cfg, g, iters_lmp):
+    """PCG of every member without a preconditioner (the comparison the paper
+    makes for the LMP) on the same problem and rtol: member solves per second
+    over one timed call after an untimed one, and the iteration counts beside
+    those of the LMP-PCG."""
+    import torch
+    members = np.arange(cfg["members"] + 1)
+    g.pcg(members, rtol=cfg["rtol"], maxit=cfg["maxit"], use_lmp=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = g.pcg(members, rtol=cfg["rtol"], maxit=cfg["maxit"], use_lmp=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    it = np.asarray(out["iters"])
+    from paper_2605_23571_amd import eda
+    return {"value": round(members.size / dt, 3), "unit": "solves/s", "maxit": cfg["maxit"],
+            "all_converged": bool(np.all(out["status"] == eda.EDA_MEMBER_CONVERGED)),
+            "iters_median": float(np.median(it)), "iters_max": int(it.max()),
+            "lmp_iters_median": float(np.median(iters_lmp)), "lmp_iters_max": int(np.max(iters_lmp))}
+
+
+def precision_report(cfg, g, dz_chosen, oracle_lmp, iters_chosen=None):
     """Errors of the reduced-precision sketch (FP32 TL/AD products) at full size:
     against the same sketch with FP64 products on the GPU, and against the CPU
     oracle's FP64 sketch when it is available (eigenvalues D_k, the LMP operator
@@ -178,6 +201,16 @@ def precision_report(cfg, g, dz_chosen, oracle_lmp):
     rep["vs_gpu_fp64"] = {"eig_max_rel": float(np.max(np.abs(eig_mx - eig_64) / eig_64)),
                           "theta_rel": float(abs(th_mx - th_64) / th_64),
                           "lmp_rel": float(np.linalg.norm(P_mx - P_64) / np.linalg.norm(V))}
+    if iters_chosen is not None:
+        # every member solved again with the FP64 sketch's LMP: iteration change
+        # and solution difference (both runs stop at the same rtol)
+        out = g.pcg(np.arange(cfg["members"] + 1), rtol=cfg["rtol"], maxit=cfg["maxit"], use_lmp=True)
+        d_it = np.asarray(iters_chosen) - np.asarray(out["iters"])
+        dz64 = out["dz"].cpu().numpy()
+        dzr = np.linalg.norm(dz_chosen - dz64, axis=1) / np.linalg.norm(dz64, axis=1)
+        rep["vs_gpu_fp64"].update({"iters_delta_median": float(np.median(d_it)),
+                                   "iters_delta_max_abs": int(np.max(np.abs(d_it))),
+                                   "dz_rel_diff_median": float(np.median(dzr)), "dz_rel_diff_max": float(dzr.max())})
     if oracle_lmp is not None:
         from oracle import oracle as O
         S, D, th, dz_o = oracle_lmp
@@ -420,7 +453,11 @@ def main():
         line["cpu_baseline"], oracle_lmp = cpu_baseline(cfg, z, a.cpu_seconds)
     g = chosen["problem"]
     line["sketch_ms"] = sketch_times(cfg, g)
-    line["reduced_precision_sketch"] = precision_report(cfg, g, chosen["last_dz"].cpu().numpy(), oracle_lmp)
+    line["reduced_precision_sketch"] = precision_report(cfg, g, chosen["last_dz"].cpu().numpy(), oracle_lmp,
+                                                        chosen["last_iters"])
+    if not a.no_no_lmp:
+        print("[bench] PCG without the LMP", file=sys.stderr, flush=True)
+        line["no_lmp"] = no_lmp_report(cfg, g, chosen["last_iters"])
     g.close()
     print(json.dumps(line), flush=True)
 
