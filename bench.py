@@ -164,6 +164,25 @@ def run_form(cfg, z, ub_mode, steps, warmup, hv_reps, mixed=False, keep=False, q
     return res
 
 
+def copy_bandwidth(mib=1024, reps=5):
+    """Attainable HBM bandwidth on this device: a plain device-to-device copy of
+    `mib` MiB (read + write bytes) timed with events on torch's stream, GB/s."""
+    import torch
+    src = torch.ones(mib << 17, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * (mib << 20) / (ms * 1e-3) / 1e9
+
+
 def no_lmp_report(cfg, g, iters_lmp):
     """PCG of every member without a preconditioner (the comparison the paper
     makes for the LMP) on the same problem and rtol: member solves per second
@@ -404,6 +423,7 @@ def main():
     act_per_launch = chosen["active_cols"] / max(1, chosen["tlad_launches"])
     achieved = bpc * act_per_launch / (avg_ms * 1e-3) / 1e9
     nt, nv = W.obs_counts(cfg)
+    attainable = copy_bandwidth()
     line = {
         "metric": "ensemble PCG solves/s at rel-res 1e-6, plain vs chosen; Hess-vec prods/s",
         "value": round(chosen["solves_per_s"], 3),
@@ -429,7 +449,8 @@ def main():
                                "3 = whole columns with the update fused, 4 = 2-8 pieces per column)",
                      "bytes_per_column": bpc, "avg_launch_ms": round(avg_ms, 4),
                      "launches": chosen["tlad_launches"], "timed_launches": chosen["tlad_timed"], "active_column_iterations": chosen["active_cols"],
-                     "kernel_sha": kernel_sha()},
+                     "kernel_sha": kernel_sha(),
+                     "attainable_GBs": round(attainable, 1), "frac_attainable": round(achieved / attainable, 4)},
         "pcg_iterations": {"median": chosen["iters_median"], "min": chosen["iters_min"], "max": chosen["iters_max"],
                            "all_converged": chosen["converged"]},
         "hessvec_per_s": {k: round(v, 1) for k, v in chosen["hessvec_per_s"].items()},
