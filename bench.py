@@ -13,7 +13,8 @@ sketch's Hessian products in FP32 (trajectory, CholQR2, eigensolve, LMP and
 PCG in FP64); "plain" = dense U_B as FP64 MFMA GEMMs, FP64 throughout.  Hessian-vector products per second
 (member mode: every column on its own trajectory; sketch mode: all on the
 control trajectory) are reported too, and so is the time of one sketch call per
-variant (Nystrom q = 1, 2, reduced precision, REVD), and PCG without the LMP.
+variant (Nystrom q = 1, 2, reduced precision, REVD), of one LMP application per
+column count, and PCG without the LMP.
 
 The roofline entry is for the dominant kernel, the Hessian part of a PCG
 iteration (banded U_B, TL run, AD run, banded U_B, vector updates; one
@@ -162,6 +163,25 @@ def run_form(cfg, z, ub_mode, steps, warmup, hv_reps, mixed=False, keep=False, q
     if not keep:
         g.close()
     return res
+
+
+def lmp_times(cfg, g, reps=200):
+    """Wall time of one eda_lmp_apply (P_theta on nb columns: projection and
+    expansion launches) in us, for 1, 16 and L + 1 columns, on the context's
+    current sketch; the spread against nb shows whether it is latency-bound."""
+    import torch
+    out = {}
+    for nb in (1, 16, cfg["members"] + 1):
+        X = torch.randn((nb, cfg["n"]), dtype=torch.float64, device="cuda")
+        for _ in range(5):
+            g.lmp_apply(X)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.lmp_apply(X)
+        torch.cuda.synchronize()
+        out[str(nb)] = round(1e6 * (time.perf_counter() - t0) / reps, 2)
+    return out
 
 
 def copy_bandwidth(mib=1024, reps=5):
@@ -488,6 +508,7 @@ def main():
         line["cpu_baseline"], oracle_lmp = cpu_baseline(cfg, z, a.cpu_seconds)
     g = chosen["problem"]
     line["sketch_ms"] = sketch_times(cfg, g)
+    line["lmp_apply_us"] = lmp_times(cfg, g)
     line["reduced_precision_sketch"] = precision_report(cfg, g, chosen["last_dz"].cpu().numpy(), oracle_lmp,
                                                         chosen["last_iters"])
     if not a.no_no_lmp:
