@@ -56,7 +56,12 @@ extern "C" {
 /* ---- options ---- */
 #define EDA_UB_DENSE   0   /* U_B products as dense FP64 MFMA GEMMs (n x n matrix stored)   */
 #define EDA_UB_BANDED  1   /* U_B products as a cyclic banded convolution over the taps of  */
-                           /* U_B's first row that exceed 2^-60 |r(0)|                        */
+                           /* U_B's first row that exceed 2^-60 |r(0)| (for the diffusion B: */
+                           /* those of the unbounded line's kernel)                           */
+
+#define EDA_B_GAUSS      0  /* B = sigma_b^2 C, C the cyclic Gaussian correlation (len_b)       */
+#define EDA_B_DIFFUSION  1  /* B = sigma_b^2 C_B, C_B the diffusion-based correlation with Daley */
+                            /* length-scale len_b and diff_steps implicit diffusion steps        */
 
 #define EDA_HV_ADD_IDENTITY  1u  /* eda_hessvec returns (I + A) X instead of A X           */
 #define EDA_HV_MIXED         2u  /* reduced precision (sketch products): FP32 TL/AD runs; the  */
@@ -83,10 +88,20 @@ extern "C" {
  * Lorenz-96 (numerical-experiments section): n >= 4 cyclic variables, forcing F,
  * RK4 step dt, window of nsteps steps.  Observations (direct, R = sigma_o^2 I)
  * at steps s = obs_dt, 2 obs_dt, ..., <= nsteps (time 0 is not observed) of the
- * variables i = obs_x0 + q obs_dx < n.  B = sigma_b^2 C, C the cyclic Gaussian
- * correlation exp(-d^2 / (2 len_b^2)); U_B is its symmetric root in closed form,
- * the cyclic Gaussian r(d) = sigma_b (2/pi)^(1/4) len_b^(-1/2) exp(-d^2/len_b^2)
- * (U_B U_B = B to 5e-9 relative for len_b >= 2, which is required).
+ * variables i = obs_x0 + q obs_dx < n.
+ * Background-error covariance B (b_kind), U_B symmetric with B = U_B U_B:
+ *  - EDA_B_GAUSS: B = sigma_b^2 C, C the cyclic Gaussian correlation
+ *    exp(-d^2 / (2 len_b^2)); U_B is its symmetric root in closed form, the
+ *    cyclic Gaussian r(d) = sigma_b (2/pi)^(1/4) len_b^(-1/2) exp(-d^2/len_b^2)
+ *    (U_B U_B = B to 5e-9 relative for len_b >= 2, which is required);
+ *  - EDA_B_DIFFUSION: the diffusion-based correlation of the experiments
+ *    section (the paper names it, with a Daley length-scale D and a number M of
+ *    diffusion steps, without defining it; this is the reading taken):
+ *    C_B = g^2 (I - kappa Lap)^-M on the ring, Lap the second difference,
+ *    kappa = D^2 / (2M - 3) (the Daley length-scale of the spectrum
+ *    (1 + kappa k^2)^-M), g normalising diag(C_B) to one; U_B =
+ *    sigma_b g (I - kappa Lap)^(-M/2), built by M/2 implicit diffusion steps
+ *    applied to a unit impulse.  len_b = D > 0, diff_steps = M even, 2..64.
  * Truth: spin-up of `spinup` RK4 steps from F * 1 with spin_pert_std * z added
  * to variable 0.  members = L perturbed members (identical-twin set-up of the
  * experiments).  max_cols bounds the number of columns of one eda_hessvec call
@@ -105,7 +120,9 @@ typedef struct {
     int32_t members;
     int32_t max_ell;
     int32_t max_cols;
-    int32_t ub_mode;     /* EDA_UB_DENSE or EDA_UB_BANDED */
+    int32_t ub_mode;     /* EDA_UB_DENSE or EDA_UB_BANDED  */
+    int32_t b_kind;      /* EDA_B_GAUSS or EDA_B_DIFFUSION */
+    int32_t diff_steps;  /* M (EDA_B_DIFFUSION only)       */
 } eda_config;
 
 typedef struct eda_ctx eda_ctx;

@@ -18,6 +18,10 @@ Readings taken where the paper is silent:
     d the cyclic grid distance; U_B is its symmetric square root in closed form
     (a Gaussian of length len/sqrt(2), see ub_row), and B is taken as U_B U_B,
     equal to sigma_b^2 C to within 5e-9 relative for len >= 2;
+  * or (b_kind "diffusion", the paper's own kind of B, named but not defined
+    there) the diffusion-based correlation g^2 (I - kappa Lap)^-M with
+    kappa = D^2 / (2M - 3) and U_B = sigma_b g (I - kappa Lap)^(-M/2), see
+    diffusion_ub_row;
   * control background x^b = x^t_0 + U_B xi_0; members x^b_j = x^b + U_B xi_j,
     y_j = y + sigma_o eta_j (ensemble-formulation section and experiment set-up);
   * the truth is spun up from F*1 with N(0, spin_pert_std^2) added to variable 0;
@@ -170,14 +174,6 @@ def GT_apply(cfg, traj_all: np.ndarray, members, W: np.ndarray) -> np.ndarray:
 # --------------------------------------------------------------------------
 # Background-error covariance (incremental 4D-Var section; experiment set-up)
 # --------------------------------------------------------------------------
-def correlation_row(n: int, len_b: float) -> np.ndarray:
-    """First row of the cyclic Gaussian correlation: c(d) = exp(-d^2/(2 len^2)),
-    d = min(i, n - i)."""
-    i = np.arange(n)
-    d = np.minimum(i, n - i).astype(np.float64)
-    return np.exp(-d * d / (2.0 * len_b * len_b))
-
-
 def ub_row(n: int, sigma_b: float, len_b: float) -> np.ndarray:
     """First row r of U_B (U_B[i, j] = r[(i - j) mod n]).
 
@@ -194,10 +190,54 @@ def ub_row(n: int, sigma_b: float, len_b: float) -> np.ndarray:
     return a * np.exp(-d * d / (len_b * len_b))
 
 
-def build_ub(n: int, sigma_b: float, len_b: float) -> np.ndarray:
-    r = ub_row(n, sigma_b, len_b)
+def diffusion_kappa(daley: float, steps: int) -> float:
+    """Diffusion coefficient of an M-step implicit diffusion correlation on a
+    line with Daley length-scale D: the spectrum (1 + kappa k^2)^-M has
+    -1/c''(0) = kappa (2M - 3), so kappa = D^2 / (2M - 3)."""
+    return daley * daley / (2.0 * steps - 3.0)
+
+
+def diffusion_ub_row(n: int, sigma_b: float, daley: float, steps: int) -> np.ndarray:
+    """First row of U_B for the diffusion-based correlation of the experiments
+    (B = sigma_b^2 C_B, C_B depending on a Daley length-scale D and a number M
+    of diffusion steps, with U_B = U_B^T; the paper names the operator without
+    defining it).  Reading: C_B = g^2 (I - kappa Lap)^-M on the ring of n
+    points, Lap the second difference, kappa = D^2 / (2M - 3), g normalising
+    the diagonal of C_B to one; U_B = sigma_b g (I - kappa Lap)^(-M/2), M even.
+
+    Written from the spectrum: (I - kappa Lap) has eigenvalue
+    s_m = 1 + 4 kappa sin^2(pi m / n) on the Fourier mode m, so
+        g^2 = n / sum_m s_m^-M,
+        r(d) = (1/n) sum_m sigma_b g s_m^(-M/2) cos(2 pi m d / n)."""
+    if steps < 2 or steps % 2:
+        raise ValueError("the number of diffusion steps must be even and >= 2")
+    kap = diffusion_kappa(daley, steps)
+    m = np.arange(n)
+    s = 1.0 + 4.0 * kap * np.sin(np.pi * m / n) ** 2
+    g = np.sqrt(n / np.sum(s ** (-float(steps))))
+    lam = sigma_b * g * s ** (-0.5 * steps)
+    half = np.cos(2.0 * np.pi * np.outer(np.arange(n // 2 + 1), m) / n) @ lam / n
+    return half[np.minimum(m, n - m)]             # r(d) = r(n - d) exactly
+
+
+def ub_row_for(cfg) -> np.ndarray:
+    """U_B's first row for a workload: the cyclic Gaussian (default) or the
+    diffusion-based operator (cfg["b_kind"] == "diffusion", Daley length-scale
+    len_b, cfg["diff_steps"] steps)."""
+    if cfg.get("b_kind", "gauss") == "diffusion":
+        return diffusion_ub_row(cfg["n"], cfg["sigma_b"], cfg["len_b"], cfg["diff_steps"])
+    return ub_row(cfg["n"], cfg["sigma_b"], cfg["len_b"])
+
+
+def circulant(r: np.ndarray) -> np.ndarray:
+    """The symmetric circulant matrix with first row r (M[i, j] = r[(i - j) mod n])."""
+    n = r.size
     i = np.arange(n)
     return r[(i[:, None] - i[None, :]) % n]
+
+
+def build_ub(n: int, sigma_b: float, len_b: float) -> np.ndarray:
+    return circulant(ub_row(n, sigma_b, len_b))
 
 
 # --------------------------------------------------------------------------
@@ -228,7 +268,7 @@ class Problem:
         Y[:, 1:] = y[:, None] + cfg["sigma_o"] * eta[:, 1:]
         self.y = Y
         # U_B and backgrounds
-        self.ub = build_ub(n, cfg["sigma_b"], cfg["len_b"])
+        self.ub = circulant(ub_row_for(cfg))
         UX = self.ub @ xi
         xb = self.xt0 + UX[:, 0]
         XB = np.empty((n, L + 1))
@@ -291,39 +331,59 @@ def fix_signs(S: np.ndarray) -> np.ndarray:
     return S * s
 
 
-def nystrom(Aop, Phi: np.ndarray, k: int, q: int = 1):
-    """The q-pass Nystrom approximation (the paper's Algorithm 1) of a symmetric
-    positive semidefinite A given through Aop(X) = A X.
-
-    Returns (S_k, D_k, info): S_k n x k with orthonormal columns, D_k the k
-    largest approximate eigenvalues (descending), info = {"shift": nu}.
-    Breakdown of the Cholesky factorisation is handled by the shift of the
-    appendix on Nystrom variants: Y <- Y + nu Phi with nu = eps ||Y||_F, and
-    nu subtracted from the squared singular values.
-    """
-    Y = Aop(Phi)                                  # sketch Y = A Phi
-    Q, R = qr_pos(Y)                              # economic QR
-    for _ in range(2, q + 1):                     # power passes
+def _range_sketch(Aop, Phi: np.ndarray, passes: int):
+    """Sketch of A's range with `passes` products: Y = A Phi, and each further
+    pass replaces Phi by the orthonormal basis of the previous Y (subspace
+    iteration).  Returns the Phi of the last product, that Y, and Y = Q R with
+    positive diag(R)."""
+    Y = Aop(Phi)
+    Q, R = qr_pos(Y)
+    for _ in range(passes - 1):
         Phi = Q
         Y = Aop(Phi)
         Q, R = qr_pos(Y)
+    return Phi, Y, Q, R
+
+
+def _nystrom_factors(Phi: np.ndarray, Y: np.ndarray, Q: np.ndarray, R: np.ndarray):
+    """Ritz pairs of A_N = Y (Phi^T Y)^-1 Y^T (the nystrom_approx equation).
+
+    With Phi^T Y = L L^T (Cholesky; raises LinAlgError when the core is not
+    numerically positive definite) and Y = Q R,  A_N = (Q F)(Q F)^T with
+    F = R L^-T, so the SVD F = U diag(sig) V^T gives A_N = (Q U) diag(sig^2)
+    (Q U)^T.  Returns (S = Q U with the sign convention, sig^2 descending,
+    the 2-norm condition number of the core)."""
+    core = Phi.T @ Y
+    core = 0.5 * (core + core.T)
+    Lc = np.linalg.cholesky(core)
+    F = np.linalg.solve(Lc, R.T).T               # R L^-T
+    U, sig, _ = np.linalg.svd(F)
+    return fix_signs(Q @ U), sig * sig, float(np.linalg.cond(core))
+
+
+def nystrom(Aop, Phi: np.ndarray, k: int, q: int = 1, eps: float = float(np.finfo(np.float64).eps)):
+    """Randomized Nystrom approximation of a symmetric positive semidefinite A
+    given through Aop(X) = A X, with q products (the paper's Algorithm 1).
+
+    Returns (S_k, D_k, info): S_k n x k with orthonormal columns, D_k the k
+    largest approximate eigenvalues (descending); info["shift"] is the shift
+    nu used (0 when none was needed) and info["cond_core"] the condition
+    number of the Cholesky core Phi^T A Phi.  When the core is not positive
+    definite in floating point, the shifted approximation of the Nystrom
+    appendix is taken instead: Y + nu Phi with nu = eps ||Y||_F (eps the unit
+    roundoff of the products), whose eigenvalues are then lowered by nu.
+    """
+    Phi, Y, Q, R = _range_sketch(Aop, Phi, q)
     nu = 0.0
-    W = Phi.T @ Y                                 # W = Phi^T Y
-    W = 0.5 * (W + W.T)
     try:
-        C = np.linalg.cholesky(W).T               # W = C^T C, C upper triangular
+        S, D, cond = _nystrom_factors(Phi, Y, Q, R)
     except np.linalg.LinAlgError:
-        nu = np.finfo(np.float64).eps * np.linalg.norm(Y)
-        Y = Y + nu * Phi
-        Q, R = qr_pos(Y)
-        W = Phi.T @ Y
-        W = 0.5 * (W + W.T)
-        C = np.linalg.cholesky(W).T
-    T = np.linalg.solve(C.T, R.T).T               # T = R_Y C^-1
-    U, sig, _ = np.linalg.svd(T)                  # economic SVD, descending
-    S = fix_signs(Q @ U)                          # S = Q_Y U_T
-    D = np.maximum(sig * sig - nu, 0.0)           # D = Sigma_T^2
-    return S[:, :k], D[:k], {"shift": nu}
+        nu = eps * np.linalg.norm(Y)
+        Ys = Y + nu * Phi
+        Qs, Rs = qr_pos(Ys)
+        S, D, cond = _nystrom_factors(Phi, Ys, Qs, Rs)
+        D = np.maximum(D - nu, 0.0)
+    return S[:, :k], D[:k], {"shift": nu, "cond_core": cond}
 
 
 def revd(Aop, Phi: np.ndarray, k: int):

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "eda_internal.h"
 
@@ -37,7 +38,15 @@ bool valid_cfg(const eda_config *c) {
     if (c->n < 4 || c->n > 4096) return false;
     if (c->nsteps < 1 || c->obs_dt < 1 || c->obs_dx < 1 || c->obs_x0 < 0 || c->obs_x0 >= c->n) return false;
     if (c->nsteps / c->obs_dt < 1) return false;
-    if (!(c->sigma_o > 0) || !(c->sigma_b > 0) || !(c->len_b >= 2.0) || !(c->dt > 0)) return false;
+    if (!(c->sigma_o > 0) || !(c->sigma_b > 0) || !(c->dt > 0)) return false;
+    if (c->b_kind == EDA_B_GAUSS) {
+        if (!(c->len_b >= 2.0)) return false;
+    } else if (c->b_kind == EDA_B_DIFFUSION) {
+        if (!(c->len_b > 0) || !(c->len_b <= 1e3) || c->diff_steps < 2 || c->diff_steps > 64 || (c->diff_steps & 1))
+            return false;
+    } else {
+        return false;
+    }
     if (c->members < 1 || c->spinup < 0) return false;
     if (c->max_ell < 1 || c->max_ell > 128) return false;
     if (c->max_cols < 0) return false;
@@ -59,12 +68,52 @@ struct Plan {
     size_t total;
 };
 
-// Banded U_B taps: offsets o with r(|o|) > 2^-60 r(0), i.e. o^2 < 60 ln 2 len^2,
-// clipped to one full period of the ring.
-void band_taps(int n, double len_b, int &lo, int &hi) {
-    const double lim = 60.0 * std::log(2.0) * len_b * len_b;
+// Banded U_B taps: offsets o with |r(o)| > 2^-60 r(0), clipped to one full
+// period of the ring.  Gaussian B: o^2 < 60 ln 2 len^2.  Diffusion B: the
+// offsets where the unbounded line's kernel of (I - kappa Lap)^(-M/2) exceeds
+// 2^-60 of its centre (the ring's kernel adds the other periods' tails, which
+// are below that wherever the band stops short of a period).  That kernel is
+// evaluated here on a window wide enough that its edge is below 2^-80 of the
+// centre, only to size the band; the taps themselves are the device's row.
+int diffusion_half_width(int n, double daley, int steps) {
+    const double kappa = daley * daley / (2.0 * steps - 3.0);
+    const double rho = 2.0 * kappa / ((1.0 + 2.0 * kappa) + std::sqrt(1.0 + 4.0 * kappa));
+    const int m = steps / 2;
+    for (int K = 64;; K *= 2) {
+        if (K >= n) return n;  // the band would reach a whole period: it is clipped to one
+        const int len = 2 * K + 1;
+        std::vector<double> g(len), r(len), t(len);
+        for (int i = 0; i < len; i++) g[i] = std::pow(rho, std::abs(i - K));
+        r = g;
+        for (int step = 1; step < m; step++) {
+            for (int i = 0; i < len; i++) {
+                double acc = 0.0;
+                for (int j = 0; j < len; j++) {
+                    const int o = i - j + K;
+                    if (o >= 0 && o < len) acc += r[j] * g[o];
+                }
+                t[i] = acc;
+            }
+            r.swap(t);
+        }
+        if (r[len - 1] < std::ldexp(r[K], -80)) {
+            int w = 0;
+            for (int o = 1; o <= K; o++)
+                if (r[K + o] > std::ldexp(r[K], -60)) w = o;
+            return w;
+        }
+    }
+}
+
+void band_taps(const eda_config *c, int &lo, int &hi) {
+    const int n = c->n;
     int w = 0;
-    while (w + 1 <= n / 2 && (double)(w + 1) * (w + 1) < lim) w++;
+    if (c->b_kind == EDA_B_DIFFUSION) {
+        w = diffusion_half_width(n, c->len_b, c->diff_steps);
+    } else {
+        const double lim = 60.0 * std::log(2.0) * c->len_b * c->len_b;
+        while (w + 1 <= n / 2 && (double)(w + 1) * (w + 1) < lim) w++;
+    }
     if (2 * w + 1 >= n) {
         lo = -((n - 1) / 2);
         hi = n / 2;
@@ -98,7 +147,7 @@ Plan make_plan(const eda_config *c) {
     P.off_traj = lay.take(L1 * (P.N + 1) * n * d);
     const bool banded = c->ub_mode == EDA_UB_BANDED;
     int band_lo, band_hi;
-    band_taps(P.n, c->len_b, band_lo, band_hi);
+    band_taps(c, band_lo, band_hi);
     {
         int pl, pr;
         if (banded)
@@ -415,7 +464,7 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
     c.pc_p2 = at<double>(w, P.off_p2);
     c.pc_pqp = at<double>(w, P.off_pqp);
     c.lmp_fin = at<double>(w, P.off_fin);
-    band_taps(c.n, cfg->len_b, c.band_lo, c.band_hi);
+    band_taps(cfg, c.band_lo, c.band_hi);
     {
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -437,7 +486,10 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
     const double *eta = d_normals + 1 + (size_t)(L + 1) * n;
     if (hipMemsetAsync(c.zero_members, 0, sizeof(int32_t) * c.max_cols, s) != hipSuccess) return fail(EDA_ERR_HIP);
     // U_B
-    if (launch_ub_row(s, n, cfg->sigma_b, cfg->len_b, c.ubrow) != hipSuccess) return fail(EDA_ERR_HIP);
+    if ((cfg->b_kind == EDA_B_DIFFUSION
+             ? launch_ub_row_diffusion(s, n, cfg->sigma_b, cfg->len_b, cfg->diff_steps, c.ubrow)
+             : launch_ub_row(s, n, cfg->sigma_b, cfg->len_b, c.ubrow)) != hipSuccess)
+        return fail(EDA_ERR_HIP);
     if (c.ub && launch_ub_fill(s, n, c.ubrow, c.ub) != hipSuccess) return fail(EDA_ERR_HIP);
     if (c.ub16 && launch_to_bf16(s, (long long)n * n, c.ub, c.ub16) != hipSuccess) return fail(EDA_ERR_HIP);
     if (c.ub32 && launch_to_f32(s, (long long)n * n, c.ub, c.ub32) != hipSuccess) return fail(EDA_ERR_HIP);

@@ -218,6 +218,7 @@ hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32, in
 
 // U_B first row (closed form) and dense fill.
 hipError_t launch_ub_row(hipStream_t s, int n, double sigma_b, double len_b, double *row);
+hipError_t launch_ub_row_diffusion(hipStream_t s, int n, double sigma_b, double daley, int steps, double *row);
 hipError_t launch_ub_fill(hipStream_t s, int n, const double *row, double *ub);
 // Y = U_B X (+ Add) with U_B circulant banded: taps o in [lo, hi], r(|o|).
 hipError_t launch_band_conv(hipStream_t s, int n, int nb, int lo, int hi, const double *row,

@@ -17,6 +17,63 @@ __global__ void k_ub_row(int n, double amp, double len2, double *row) {
     row[i] = amp * exp(-d * d / len2);
 }
 
+// First row of U_B = sigma_b g (I - kappa Lap)^(-m) (m = M/2) on the ring of
+// n points (the diffusion-based B), in real space: one implicit diffusion
+// step is the cyclic convolution with the ring's Green's function of
+// (I - kappa Lap),
+//   G(d) = (rho^d + rho^(n-d)) / (kappa (1/rho - rho) (1 - rho^n)),
+//   rho the root in (0, 1) of kappa rho^2 - (1 + 2 kappa) rho + kappa = 0
+// (the unbounded line's kernel rho^|d| / (kappa (1/rho - rho)), summed over the
+// ring's periods), so the row is G convolved with itself m times.  Every
+// term is positive, so the sums carry no cancellation.  g normalises the
+// diagonal of C_B = (U_B / sigma_b)^2 to one: the diagonal of the M-step
+// operator is sum_d r0(d)^2 for the symmetric row r0 of the m-step one.  One
+// workgroup; a and b are two n-double LDS arrays.
+__global__ __launch_bounds__(1024) void k_ub_row_diffusion(int n, double kappa, int m, double sigma_b,
+                                                           double *row) {
+    extern __shared__ double lds_d[];
+    double *a = lds_d, *b = lds_d + n;
+    __shared__ double red[16];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const double rho = 2.0 * kappa / ((1.0 + 2.0 * kappa) + sqrt(1.0 + 4.0 * kappa));
+    const double rn = pow(rho, (double)n);
+    const double amp = 1.0 / (kappa * (1.0 / rho - rho) * (1.0 - rn));
+    for (int d = tid; d < n; d += nthr) {
+        const double g = amp * (pow(rho, (double)d) + pow(rho, (double)(n - d)));
+        a[d] = g;
+        b[d] = g;
+    }
+    __syncthreads();
+    // b <- a (*) b, m - 1 times (a keeps G)
+    for (int step = 1; step < m; step++) {
+        double out[4];
+        int cnt = 0;
+        for (int d = tid; d < n; d += nthr) {
+            double acc = 0.0;
+            for (int e = 0; e < n; e++) {
+                int j = d - e;
+                j = j < 0 ? j + n : j;
+                acc += b[e] * a[j];
+            }
+            out[cnt++] = acc;
+        }
+        __syncthreads();
+        cnt = 0;
+        for (int d = tid; d < n; d += nthr) b[d] = out[cnt++];
+        __syncthreads();
+    }
+    // g^2 = 1 / sum_d b(d)^2, by a fixed-order reduction
+    double ss = 0.0;
+    for (int d = tid; d < n; d += nthr) ss += b[d] * b[d];
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_down(ss, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = ss;
+    __syncthreads();
+    double tot = 0.0;
+    for (int w = 0; w < (nthr >> 6); w++) tot += red[w];
+    const double scale = sigma_b / sqrt(tot);
+    for (int d = tid; d < n; d += nthr) row[d] = scale * b[d];
+}
+
 __global__ void k_ub_fill(int n, const double *__restrict__ row, double *__restrict__ ub) {
     long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long long)n * n) return;
@@ -184,6 +241,14 @@ hipError_t launch_pad_traj(hipStream_t s, int n, int N, int nm, const double *tr
 hipError_t launch_ub_row(hipStream_t s, int n, double sigma_b, double len_b, double *row) {
     double amp = sigma_b * pow(2.0 / M_PI, 0.25) / sqrt(len_b);
     hipLaunchKernelGGL(k_ub_row, dim3((n + 255) / 256), dim3(256), 0, s, n, amp, len_b * len_b, row);
+    return hipGetLastError();
+}
+
+hipError_t launch_ub_row_diffusion(hipStream_t s, int n, double sigma_b, double daley, int steps, double *row) {
+    if (n < 4 || n > 4096 || steps < 2 || (steps & 1) || !(daley > 0)) return hipErrorInvalidValue;
+    const double kappa = daley * daley / (2.0 * steps - 3.0);
+    hipLaunchKernelGGL(k_ub_row_diffusion, dim3(1), dim3(1024), 2 * n * sizeof(double), s, n, kappa, steps / 2,
+                       sigma_b, row);
     return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ EDA_ERR_UNSUPPORTED = -6
 EDA_WARN_NOT_CONVERGED = 1
 EDA_MEMBER_CONVERGED, EDA_MEMBER_NOT_CONVERGED, EDA_MEMBER_BREAKDOWN = 0, 1, 2
 EDA_UB_DENSE, EDA_UB_BANDED = 0, 1
+EDA_B_GAUSS, EDA_B_DIFFUSION = 0, 1
 EDA_HV_ADD_IDENTITY, EDA_HV_MIXED, EDA_HV_BF16 = 1, 2, 4
 EDA_SKETCH_RHS_DIFF, EDA_SKETCH_USER, EDA_SKETCH_B_PSI, EDA_SKETCH_UBT_PSI = 0, 1, 2, 3
 EDA_METHOD_NYSTROM, EDA_METHOD_REVD = 0, 1
@@ -50,7 +51,7 @@ class eda_config(ctypes.Structure):
                 ("obs_dt", ctypes.c_int32), ("obs_dx", ctypes.c_int32), ("obs_x0", ctypes.c_int32),
                 ("sigma_o", ctypes.c_double), ("sigma_b", ctypes.c_double), ("len_b", ctypes.c_double),
                 ("members", ctypes.c_int32), ("max_ell", ctypes.c_int32), ("max_cols", ctypes.c_int32),
-                ("ub_mode", ctypes.c_int32)]
+                ("ub_mode", ctypes.c_int32), ("b_kind", ctypes.c_int32), ("diff_steps", ctypes.c_int32)]
 
 
 _lib = None
@@ -130,7 +131,9 @@ def make_config(cfg: dict, ub_mode: str = "banded", max_ell: int | None = None, 
     return eda_config(cfg["n"], cfg["nsteps"], cfg["F"], cfg["dt"], cfg["spinup"], cfg["spin_pert_std"],
                       cfg["obs_dt"], cfg["obs_dx"], cfg["obs_x0"], cfg["sigma_o"], cfg["sigma_b"], cfg["len_b"],
                       cfg["members"], int(max_ell if max_ell is not None else cfg.get("ell", 1)), int(max_cols),
-                      EDA_UB_DENSE if ub_mode == "dense" else EDA_UB_BANDED)
+                      EDA_UB_DENSE if ub_mode == "dense" else EDA_UB_BANDED,
+                      EDA_B_DIFFUSION if cfg.get("b_kind", "gauss") == "diffusion" else EDA_B_GAUSS,
+                      int(cfg.get("diff_steps", 0)))
 
 
 def eda_workspace_bytes(c: eda_config) -> int:

@@ -23,7 +23,7 @@ def test_exports_only_abi_symbols():
     assert exported == set(eda.header_symbols())
 
 
-@pytest.mark.parametrize("name", ["C1", "C2", "C3"])
+@pytest.mark.parametrize("name", ["C1", "C2", "C3", "paper"])
 def test_workspace_and_normals(name):
     cfg = W.config(name)
     c = eda.make_config(cfg)
@@ -39,12 +39,30 @@ def test_workspace_and_normals(name):
 
 
 @pytest.mark.parametrize("bad", [dict(n=3), dict(n=5000), dict(len_b=1.0), dict(obs_x0=40), dict(sigma_o=0.0),
-                                 dict(members=0), dict(nsteps=2, obs_dt=5)])
+                                 dict(members=0), dict(nsteps=2, obs_dt=5),
+                                 dict(b_kind="diffusion", diff_steps=9), dict(b_kind="diffusion", diff_steps=0),
+                                 dict(b_kind="diffusion", diff_steps=66), dict(b_kind="diffusion", len_b=0.0)])
 def test_invalid_config_rejected(bad):
     cfg = W.config("C1", **bad)
     c = eda.make_config(cfg)
     out = ctypes.c_size_t()
     assert eda.lib().eda_workspace_bytes(ctypes.byref(c), ctypes.byref(out)) == eda.EDA_ERR_INVALID_ARG
+
+
+def test_invalid_b_kind_rejected():
+    c = eda.make_config(W.config("C1"))
+    c.b_kind = 2
+    out = ctypes.c_size_t()
+    assert eda.lib().eda_workspace_bytes(ctypes.byref(c), ctypes.byref(out)) == eda.EDA_ERR_INVALID_ARG
+
+
+def test_diffusion_band_is_wider_than_a_short_gaussian():
+    # the banded U_B's halo enters the split rings' padding: the diffusion
+    # kernel (exponential tails) needs more taps than a Gaussian of the same
+    # Daley length, so its workspace is at least as large
+    g = eda.eda_workspace_bytes(eda.make_config(W.config("paper", b_kind="gauss")))
+    d = eda.eda_workspace_bytes(eda.make_config(W.config("paper")))
+    assert d > g
 
 
 def test_strerror_static():

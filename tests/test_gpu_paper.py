@@ -1,0 +1,165 @@
+"""The paper's own experimental set-up on the GPU against the CPU oracle.
+
+Numerical-experiments section: Lorenz-96 with n = 1500, a window of ten RK4
+steps, direct observations of 50 variables at three times (p = 150),
+sigma_o = 0.05, sigma_b = 0.8, the diffusion-based B (Daley length-scale D = 6,
+M = 10 diffusion steps; the reading of that operator is in the header), an
+ensemble of L = 20 perturbed members and sketches of ell = 20 columns with
+k = 20 or 15 retained pairs.  The five sketching matrices of that section are
+checked against the oracle: Psi (q = 1), A Psi (q = 2 on Psi), B Psi, U_B^T Psi
+and Gamma; so are the three theta rules and the oversampled k = 15 in LMP-PCG
+(sensitivity analysis), through the cost history J of the control member.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2605_23571_amd import eda  # noqa: E402
+
+CFG = W.config("paper")
+_cache = {}
+
+
+def problem(mode="banded"):
+    if mode not in _cache:
+        z = W.problem_normals(CFG)
+        print(f"[paper] set-up {mode} n={CFG['n']} p=150 L={CFG['members']}", flush=True)
+        if "oracle" not in _cache:
+            _cache["oracle"] = O.Problem(CFG, z)
+        _cache[mode] = eda.Problem(CFG, z, ub_mode=mode)
+    return _cache[mode], _cache["oracle"]
+
+
+def colrel(A, B):
+    return float(np.max(np.abs(A - B).max(axis=0) / np.abs(B).max(axis=0)))
+
+
+def to_np_cols(t, n):
+    return t.detach().cpu().numpy().reshape(-1, n).T
+
+
+def eig_bars(D, cond_core, c=16.0):
+    # the Cholesky core's cond * eps moves d_i by ~ 2 cond eps sqrt(d_1 / d_i)
+    eps = np.finfo(float).eps
+    return np.maximum(1e-13, c * 2 * cond_core * eps * np.sqrt(D[0] / D))
+
+
+@pytest.mark.parametrize("mode", ["banded", "dense"])
+def test_paper_setup_and_hessian(mode):
+    g, o = problem(mode)
+    n, L, N = CFG["n"], CFG["members"], CFG["nsteps"]
+    # U_B: the device builds the row in real space (implicit diffusion steps on
+    # an impulse), the oracle from the spectrum
+    r = O.ub_row_for(CFG)
+    rg = g.field("ubrow").cpu().numpy()
+    e_row = np.abs(rg - r).max() / r[0]
+    print(f"[paper] {mode} U_B row: max |difference| / r(0) = {e_row:.2e}", flush=True)
+    assert e_row < 1e-13
+    assert np.array_equal(g.field("truth").cpu().numpy().reshape(N + 1, n), o.xt_traj)
+    traj = g.field("traj").cpu().numpy().reshape(L + 1, N + 1, n)
+    assert np.abs(traj - o.traj).max() <= 1e-13 * np.abs(o.traj).max()
+    assert colrel(to_np_cols(g.field("b"), n), o.b) < 1e-12
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((L + 1, n))
+    cols = np.arange(L + 1)[::-1].copy()
+    Y = to_np_cols(g.hessvec(cols, torch.from_numpy(X).cuda(), add_identity=True), n)
+    e_hv = colrel(Y, o.hess(X.T, cols))
+    Xs = rng.standard_normal((CFG["ell"], n))
+    Ys = to_np_cols(g.hessvec(np.zeros(CFG["ell"], dtype=np.int32), torch.from_numpy(Xs).cuda()), n)
+    e_sk = colrel(Ys, o.A(Xs.T, [0] * CFG["ell"]))
+    print(f"[paper] {mode} Hessian products: member mode {e_hv:.2e}, sketch mode {e_sk:.2e}", flush=True)
+    assert e_hv < 1e-12 and e_sk < 1e-12
+
+
+def _sketch_pair(g, o, kind, k):
+    """(GPU eigenvalues, GPU theta, oracle S, D, info) for one of the five
+    sketching matrices of the experiments (seeded Psi, stream 5)."""
+    n, ell = CFG["n"], CFG["ell"]
+    psi = W.gaussian_matrix(CFG, n, ell)        # ell x n: row c is column c
+    Aop = lambda V: o.A(V, [0] * V.shape[1])
+    pt = torch.from_numpy(psi).cuda()
+    if kind == "gamma":
+        eig, th = g.sketch_evd("rhs_diff", ell=ell, k=k)
+        S, D, info = O.nystrom(Aop, o.gamma(ell), k)
+    elif kind == "psi":
+        eig, th = g.sketch_evd("user", ell=ell, k=k, phi=pt)
+        S, D, info = O.nystrom(Aop, psi.T, k)
+    elif kind == "a_psi":
+        eig, th = g.sketch_evd("user", ell=ell, k=k, q=2, phi=pt)
+        S, D, info = O.nystrom(Aop, psi.T, k, q=2)
+    elif kind == "b_psi":
+        eig, th = g.sketch_evd("b_psi", ell=ell, k=k, phi=pt)
+        S, D, info = O.nystrom(Aop, o.ub.T @ o.ub @ psi.T, k)
+    else:
+        eig, th = g.sketch_evd("ubt_psi", ell=ell, k=k, phi=pt)
+        S, D, info = O.nystrom(Aop, o.ub.T @ psi.T, k)
+    return eig, th, S, D, info
+
+
+@pytest.mark.parametrize("kind", ["psi", "a_psi", "b_psi", "ubt_psi", "gamma"])
+def test_paper_sketching_matrices(kind):
+    # Algorithm 1 with each sketching matrix of the experiments; A Psi is the
+    # two-pass form (q = 2) on a Gaussian Psi.  Eigenvalues to per-eigenvalue
+    # bars, the LMP operator on probes, theta (mid rule).
+    g, o = problem()
+    k = CFG["k"]
+    eig, th, S, D, info = _sketch_pair(g, o, kind, k)
+    bars = eig_bars(D, info["cond_core"])
+    err = np.abs(eig - D) / D
+    print(f"[paper] sketch {kind}: cond(core) {info['cond_core']:.1e}, max err/bar {np.max(err / bars):.3f}, "
+          f"err[0] {err[0]:.1e}, err[-1] {err[-1]:.1e}, d_1 {D[0]:.4e}, d_k {D[-1]:.4e}", flush=True)
+    assert np.all(err <= bars), (err, bars)
+    th_o = O.theta(D)
+    assert abs(th - th_o) <= bars[-1] * th_o
+    n = CFG["n"]
+    V = np.random.default_rng(5).standard_normal((16, n))
+    Pg = to_np_cols(g.lmp_apply(torch.from_numpy(V).cuda()), n)
+    Po = O.lmp_apply(S, D, th_o, V.T)
+    assert colrel(Pg, Po) < max(1e-12, float(bars.max()))
+
+
+@pytest.mark.parametrize("k", [20, 15])
+@pytest.mark.parametrize("theta", ["mid", "lamk", "one"])
+def test_paper_theta_rules_and_oversampling(theta, k):
+    # Sensitivity analysis: the Gamma sketch with ell = 20 and k = 20 or 15
+    # (oversampling by 5), each theta rule; LMP-PCG of the control for 30
+    # iterations, whose cost history J_i - c must follow the oracle's PCG with
+    # the oracle's own LMP while J still decreases by more than 1e-12 |J|
+    # (beyond that two correct implementations wander at rounding level).
+    g, o = problem()
+    eig, th = g.sketch_evd("rhs_diff", ell=CFG["ell"], k=k, theta=theta)
+    S, D, info = O.nystrom(lambda V: o.A(V, [0] * V.shape[1]), o.gamma(CFG["ell"]), k)
+    th_o = O.theta(D, theta)
+    assert abs(th - th_o) <= eig_bars(D, info["cond_core"])[-1] * th_o
+    out = g.pcg([0], rtol=0.0, maxit=30, use_lmp=True, history=True)
+    _, _, _, _, hist = O.pcg(lambda v: o.hess(v[:, None], [0])[:, 0], o.b[:, 0],
+                             lambda v: O.lmp_apply(S, D, th_o, v[:, None])[:, 0], 0.0, 30)
+    hg = out["hist"][0][:len(hist)]
+    meaningful = np.concatenate([[True], np.abs(np.diff(hist)) > 1e-12 * np.abs(hist[-1])])
+    cut = np.argmin(meaningful) if not meaningful.all() else len(hist)
+    d = np.abs(hg[:cut] - hist[:cut]).max() / abs(hist[cut - 1])
+    print(f"[paper] theta={theta} k={k}: J history agrees over {cut} iterations to {d:.1e}; "
+          f"J_1 {hist[1]:.6e}, J_30 {hist[-1]:.6e}", flush=True)
+    assert cut >= 5 and d < 1e-8
+
+
+def test_paper_members_converge_with_the_control_lmp():
+    # Ensemble-members results: the control's Gamma LMP (k = 15, theta mid)
+    # preconditions every member; each member solved to rtol 1e-10 matches the
+    # oracle's exact solution (dense Cholesky) on sampled members.
+    g, o = problem()
+    g.sketch_evd("rhs_diff", ell=CFG["ell"], k=15)
+    L = CFG["members"]
+    out = g.pcg(np.arange(L + 1), rtol=1e-10, maxit=3000, use_lmp=True)
+    assert np.all(out["status"] == eda.EDA_MEMBER_CONVERGED)
+    for m in (0, 7, L):
+        xe = O.exact_solution(o, m)
+        dz = out["dz"][m].cpu().numpy()
+        e = np.abs(dz - xe).max() / np.abs(xe).max()
+        print(f"[paper] member {m}: {out['iters'][m]} iterations, element-wise error {e:.2e}", flush=True)
+        assert e < 1e-6

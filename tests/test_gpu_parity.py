@@ -47,7 +47,38 @@ def rel(a, b):
 
 
 def colrel(A, B):
-    return np.max(np.linalg.norm(A - B, axis=0) / np.linalg.norm(B, axis=0))
+    """Largest element-wise difference of a column, relative to that column's
+    largest magnitude, maximised over the columns (element-wise bar)."""
+    A, B = np.atleast_2d(A), np.atleast_2d(B)
+    return np.max(np.abs(A - B).max(axis=0) / np.abs(B).max(axis=0))
+
+
+def elrel(a, b):
+    """max_i |a_i - b_i| / max_i |b_i| for vectors."""
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+_exact = {}
+
+
+def exact(name, o, m):
+    """The oracle's exact solution of (I + A_m) dz = b_m (dense assembly and
+    Cholesky solve), cached per workload and member."""
+    key = (name, m)
+    if key not in _exact:
+        _exact[key] = O.exact_solution(o, m)
+    return _exact[key]
+
+
+def eig_bars(D, cond_core, c=16.0):
+    """Per-eigenvalue relative bars for Nystrom eigenvalues computed by two
+    correct FP64 implementations: the Cholesky factor of the core
+    Phi^T A Phi carries relative error ~ cond * eps, which moves singular value
+    i of T = R C^-1 by ~ cond * eps * sigma_1, i.e. eigenvalue d_i = sigma_i^2
+    by ~ 2 cond eps sqrt(d_1 / d_i) relative; c is the safety factor, and the
+    floor 1e-13 covers well-conditioned cores."""
+    eps = np.finfo(float).eps
+    return np.maximum(1e-13, c * 2 * cond_core * eps * np.sqrt(D[0] / D))
 
 
 def to_np_cols(t, n):
@@ -195,43 +226,53 @@ def test_hessvec_edge_cases():
 
 # ----------------------------------------------------------------- sketch --
 def _oracle_sketch(o, kind, ell, k, q=1, method="nystrom", phi=None):
+    """Oracle Ritz pairs and per-eigenvalue bars for the GPU's (see eig_bars;
+    REVD: the Rayleigh quotients of two bases of range(A Phi) that agree to
+    cond(Y) eps, which moves d_i by ~ cond(Y) eps d_1 absolute)."""
     Aop = lambda V: o.A(V, [0] * V.shape[1])
     if kind == "rhs_diff":
         phi = o.gamma(ell)
     if method == "nystrom":
-        S, D, _ = O.nystrom(Aop, phi, k, q)
+        S, D, info = O.nystrom(Aop, phi, k, q)
+        bars = eig_bars(D, info["cond_core"])
     else:
         S, D = O.revd(Aop, phi, k)
-    return S, D
+        condY = np.linalg.cond(Aop(phi))
+        bars = np.maximum(1e-13, 16.0 * np.finfo(float).eps * condY * D[0] / D)
+    return S, D, bars
 
 
-def _compare_lmp(g, o, cfg, S, D, th, eig, theta_gpu, tol):
-    np.testing.assert_allclose(eig, D, rtol=tol, atol=tol * D[0])
-    assert abs(theta_gpu - th) <= tol * th
+def _compare_lmp(g, o, cfg, S, D, th, eig, theta_gpu, bars, label=""):
+    err = np.abs(eig - D) / D
+    print(f"[eig] {label} max err/bar {np.max(err / bars):.3f}; err[0] {err[0]:.2e} (bar {bars[0]:.1e}), "
+          f"err[-1] {err[-1]:.2e} (bar {bars[-1]:.1e})", flush=True)
+    assert np.all(err <= bars), (err, bars)
+    tol = float(np.max(bars))
+    assert abs(theta_gpu - th) <= bars[-1] * th
     n = cfg["n"]
     V = np.random.default_rng(9).standard_normal((min(16, g.max_cols), n))
     Vt = torch.from_numpy(V).cuda()
     for which in ("P", "U"):
         Pg = to_np_cols(g.lmp_apply(Vt, which), n)
         Po = O.lmp_apply(S, D, th, V.T, which)
-        assert rel(Pg, Po) < tol, (which, rel(Pg, Po))
+        assert colrel(Pg, Po) < max(tol, 1e-12), (which, colrel(Pg, Po))
     Sg = g.field("S").cpu().numpy().reshape(-1, n).T
     # eigenvectors compared where the eigenvalue gap is large enough for them to be determined
     gaps = np.abs(np.diff(np.concatenate([[np.inf], D, [0.0]])))
     for i in range(len(D)):
         if min(gaps[i], gaps[i + 1]) > 1e-3 * D[0]:
-            assert np.linalg.norm(Sg[:, i] - S[:, i]) < 1e3 * tol, i
+            assert np.linalg.norm(Sg[:, i] - S[:, i]) < 1e3 * max(tol, 1e-12), i
 
 
 @pytest.mark.parametrize("case", list(CASES))
 def test_nystrom_rhs_diff(case):
     # Algorithm 1 with Phi = Gamma.  CholQR2 (GPU) and Householder QR (oracle)
-    # agree to cond(Y) eps; with cond(Y) <~ 1e4 here the eigenvalues and the
-    # preconditioner agree to 1e-9 relative.
+    # agree to cond(Y) eps, and the Cholesky of the core to cond(core) eps:
+    # each eigenvalue is held to its own bar (eig_bars).
     cfg, g, o = problem(case)
     eig, thg = g.sketch_evd("rhs_diff")
-    S, D = _oracle_sketch(o, "rhs_diff", cfg["ell"], cfg["k"])
-    _compare_lmp(g, o, cfg, S, D, O.theta(D), eig, thg, 1e-9)
+    S, D, bars = _oracle_sketch(o, "rhs_diff", cfg["ell"], cfg["k"])
+    _compare_lmp(g, o, cfg, S, D, O.theta(D), eig, thg, bars, f"nystrom {case}")
 
 
 LMP_CASES = {
@@ -260,7 +301,7 @@ def test_lmp_block_matches_definition(case):
         for nb in (ncols, ncols - 1, 1):
             Pg = to_np_cols(g.lmp_apply(Vt[:nb].contiguous(), which), n)
             Po = O.lmp_apply(S, eig, th, V[:nb].T, which)
-            assert rel(Pg, Po) < 1e-13, (which, nb, rel(Pg, Po))
+            assert colrel(Pg, Po) < 1e-13, (which, nb, colrel(Pg, Po))
     g.close()
 
 
@@ -268,11 +309,11 @@ def test_lmp_block_matches_definition(case):
 def test_revd_and_power_pass(case):
     cfg, g, o = problem(case)
     eig, thg = g.sketch_evd("rhs_diff", method="revd")
-    S, D = _oracle_sketch(o, "rhs_diff", cfg["ell"], cfg["k"], method="revd")
-    _compare_lmp(g, o, cfg, S, D, O.theta(D), eig, thg, 1e-9)
+    S, D, bars = _oracle_sketch(o, "rhs_diff", cfg["ell"], cfg["k"], method="revd")
+    _compare_lmp(g, o, cfg, S, D, O.theta(D), eig, thg, bars, f"revd {case}")
     eig, thg = g.sketch_evd("rhs_diff", q=2, theta="lamk")
-    S, D = _oracle_sketch(o, "rhs_diff", cfg["ell"], cfg["k"], q=2)
-    _compare_lmp(g, o, cfg, S, D, O.theta(D, "lamk"), eig, thg, 1e-9)
+    S, D, bars = _oracle_sketch(o, "rhs_diff", cfg["ell"], cfg["k"], q=2)
+    _compare_lmp(g, o, cfg, S, D, O.theta(D, "lamk"), eig, thg, bars, f"q2 {case}")
 
 
 REVD_CORES = {
@@ -295,8 +336,8 @@ def test_revd_core_sizes(case):
     g = eda.Problem(cfg, z)
     o = O.Problem(cfg, z)
     eig, thg = g.sketch_evd("rhs_diff", method="revd")
-    S, D = _oracle_sketch(o, "rhs_diff", cfg["ell"], cfg["k"], method="revd")
-    _compare_lmp(g, o, cfg, S, D, O.theta(D), eig, thg, 1e-9)
+    S, D, bars = _oracle_sketch(o, "rhs_diff", cfg["ell"], cfg["k"], method="revd")
+    _compare_lmp(g, o, cfg, S, D, O.theta(D), eig, thg, bars, f"revd core {case}")
     g.close()
 
 
@@ -307,8 +348,8 @@ def test_sketch_kinds(kind):
     psi = W.gaussian_matrix(cfg, n, ell)          # ell x n (row c = column c)
     phi = {"user": psi.T, "b_psi": o.ub @ o.ub @ psi.T, "ubt_psi": o.ub.T @ psi.T}[kind]
     eig, thg = g.sketch_evd(kind, phi=torch.from_numpy(psi).cuda(), theta="one")
-    S, D = _oracle_sketch(o, "user", ell, cfg["k"], phi=phi)
-    _compare_lmp(g, o, cfg, S, D, O.theta(D, "one"), eig, thg, 1e-9)
+    S, D, bars = _oracle_sketch(o, "user", ell, cfg["k"], phi=phi)
+    _compare_lmp(g, o, cfg, S, D, O.theta(D, "one"), eig, thg, bars, f"kind {kind}")
 
 
 def test_sketch_errors():
@@ -335,7 +376,7 @@ def test_pcg_c1_fixed_iterations():
     # final solutions against the exact solution.
     cfg, g, o = problem("C1")
     g.sketch_evd("rhs_diff")
-    S, D = _oracle_sketch(o, "rhs_diff", cfg["ell"], cfg["k"])
+    S, D, _ = _oracle_sketch(o, "rhs_diff", cfg["ell"], cfg["k"])
     th = O.theta(D)
     L = cfg["members"]
     out = g.pcg(np.arange(L + 1), rtol=0.0, maxit=50, use_lmp=True, history=True)
@@ -358,7 +399,7 @@ def test_pcg_converges_like_oracle(case, use_lmp):
     L = cfg["members"]
     if use_lmp:
         g.sketch_evd("rhs_diff")
-        S, D = _oracle_sketch(o, "rhs_diff", cfg["ell"], cfg["k"])
+        S, D, _ = _oracle_sketch(o, "rhs_diff", cfg["ell"], cfg["k"])
         th = O.theta(D)
         Pop = lambda v: O.lmp_apply(S, D, th, v[:, None])[:, 0]
     else:
@@ -518,31 +559,47 @@ def test_profile_counts_pcg_tlad_launches():
 
 
 # ------------------------------------------------- full-size (sampled) ------
-@pytest.mark.parametrize("name,mode", [("C2", "banded"), ("C2", "dense"), ("C3", "banded")])
+_full = {}
+
+
+def full_oracle(name):
+    if name not in _full:
+        cfg = W.config(name)
+        _full[name] = O.Problem(cfg, W.problem_normals(cfg))
+    return _full[name]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name,mode", [("C2", "banded"), ("C2", "dense"), ("C3", "banded"), ("C3", "dense")])
 def test_full_size_sampled(name, mode):
-    # The benchmark configurations at full size: set-up fields, sampled Hessian
-    # columns, the Gamma-Nystrom eigenvalues, and the batched LMP-PCG to 1e-6
-    # checked by the oracle's true residual on sampled members.
+    # The benchmark configurations at full size, in both U_B forms (the dense
+    # form is the bench's plain FP64 form: U_B products as 4096 x 4096 FP64
+    # MFMA GEMMs at C3): set-up fields, sampled Hessian columns, the
+    # Gamma-Nystrom eigenvalues, and the batched LMP-PCG of every member to
+    # rtol 1e-6, whose sampled members are checked by the oracle's true
+    # residual.
     cfg = W.config(name)
     z = W.problem_normals(cfg)
     print(f"[full] {name} {mode}", flush=True)
     g = eda.Problem(cfg, z, ub_mode=mode)
-    o = _cache.get((name, "oracle"))
-    if o is None:
-        o = O.Problem(cfg, z)
-        _cache[(name, "oracle")] = o
+    o = full_oracle(name)
     n, L, N = cfg["n"], cfg["members"], cfg["nsteps"]
     assert np.array_equal(g.field("truth").cpu().numpy().reshape(N + 1, n), o.xt_traj)
     assert colrel(to_np_cols(g.field("b"), n), o.b) < 1e-12
     cols = np.array([0, 1, L // 2, L])
     X = np.random.default_rng(1).standard_normal((cols.size, n))
     Y = to_np_cols(g.hessvec(cols, torch.from_numpy(X).cuda(), add_identity=True), n)
-    assert colrel(Y, o.hess(X.T, cols)) < 1e-12
+    e = colrel(Y, o.hess(X.T, cols))
+    print(f"[full] {name} {mode} hessvec element-wise error {e:.2e}", flush=True)
+    assert e < 1e-12
     eig, th = g.sketch_evd("rhs_diff")
-    _, D = _oracle_sketch(o, "rhs_diff", cfg["ell"], cfg["k"])
-    np.testing.assert_allclose(eig, D, rtol=1e-8)
+    _, D, bars = _oracle_sketch(o, "rhs_diff", cfg["ell"], cfg["k"])
+    err = np.abs(eig - D) / D
+    print(f"[full] {name} {mode} eigenvalues: max err/bar {np.max(err / bars):.3f}, err[0] {err[0]:.1e}, "
+          f"err[-1] {err[-1]:.1e}", flush=True)
+    assert np.all(err <= bars)
     out = g.pcg(np.arange(L + 1), rtol=1e-6, maxit=2000, use_lmp=True)
-    print(f"[full] {name} iterations min/median/max {out['iters'].min()}/{np.median(out['iters'])}/"
+    print(f"[full] {name} {mode} iterations min/median/max {out['iters'].min()}/{np.median(out['iters'])}/"
           f"{out['iters'].max()}", flush=True)
     assert np.all(out["status"] == eda.EDA_MEMBER_CONVERGED)
     dz = out["dz"].cpu().numpy()
@@ -552,17 +609,35 @@ def test_full_size_sampled(name, mode):
     g.close()
 
 
-def test_c2_solution_accuracy_at_tight_tolerance():
-    # Solution parity (reading of the tolerance pair): at rtol 1e-10 the GPU
-    # solution is within 1e-6 relative of the exact solution of (I + A) dz = b
-    # assembled and solved densely by the oracle.
-    cfg = W.config("C2")
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name,members", [("C2", (0, 64)), ("C3", (0, 1, 64, 128))])
+def test_solution_bar_of_the_chosen_form(name, members):
+    # The solution bar (reading of the tolerance pair): with the bench's chosen
+    # form -- banded U_B, the Gamma-Nystrom sketch with two passes and FP32
+    # TL/AD sketch products (C3), or the FP64 single-pass sketch (C2) --
+    # members solved to rtol 1e-10 are within 1e-6 relative of the exact
+    # solution of (I + A_m) dz = b_m, assembled densely and solved by Cholesky
+    # in the oracle, element by element (largest difference over largest
+    # magnitude) and in the 2-norm.  At the throughput tolerance 1e-6 the error
+    # is printed, not gated (it is bounded only by cond(I + A) 1e-6).
+    cfg = W.config(name)
     z = W.problem_normals(cfg)
     g = eda.Problem(cfg, z)
-    o = _cache.get(("C2", "oracle")) or O.Problem(cfg, z)
-    g.sketch_evd("rhs_diff")
-    out = g.pcg([0, 64], rtol=1e-10, maxit=2000, use_lmp=True)
-    for i, m in enumerate((0, 64)):
-        xe = O.exact_solution(o, m)
-        assert rel(out["dz"][i].cpu().numpy(), xe) < 1e-6
+    o = full_oracle(name)
+    if name == "C3":
+        g.sketch_evd("rhs_diff", q=2, mixed=True)
+    else:
+        g.sketch_evd("rhs_diff")
+    tight = g.pcg(members, rtol=1e-10, maxit=4000, use_lmp=True)
+    loose = g.pcg(members, rtol=1e-6, maxit=4000, use_lmp=True)
+    assert np.all(tight["status"] == eda.EDA_MEMBER_CONVERGED)
+    for i, m in enumerate(members):
+        xe = exact(name, o, m)
+        dz = tight["dz"][i].cpu().numpy()
+        e_el, e_2 = elrel(dz, xe), rel(dz, xe)
+        d6 = loose["dz"][i].cpu().numpy()
+        print(f"[bar] {name} member {m}: rtol 1e-10 ({tight['iters'][i]} it) element-wise {e_el:.2e}, "
+              f"2-norm {e_2:.2e}; rtol 1e-6 ({loose['iters'][i]} it) element-wise {elrel(d6, xe):.2e}, "
+              f"2-norm {rel(d6, xe):.2e}", flush=True)
+        assert e_el <= 1e-6 and e_2 <= 1e-6
     g.close()

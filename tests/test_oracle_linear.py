@@ -44,6 +44,84 @@ def test_ub_is_symmetric_sqrt_of_b(n, len_b):
             np.testing.assert_allclose(U, root, rtol=0, atol=1e-6 * np.abs(root).max())
 
 
+@pytest.mark.parametrize("n,D,M", [(1500, 6.0, 10), (300, 6.0, 2), (256, 12.0, 4), (64, 3.0, 10)])
+def test_diffusion_ub_real_space_and_normalisation(n, D, M):
+    # The diffusion-based U_B (reading of the experiments' C_B) is written from
+    # its spectrum.  In real space, M/2 implicit diffusion steps, i.e. M/2
+    # applications of the tridiagonal (1 + 2 kappa) I - kappa (shift + shift^T),
+    # must turn U_B into a multiple of the identity; B = U_B U_B must have unit
+    # correlations on its diagonal (times sigma_b^2); U_B is symmetric,
+    # circulant and positive definite.
+    sb = 0.8
+    U = O.circulant(O.diffusion_ub_row(n, sb, D, M))
+    assert np.array_equal(U, U.T)
+    assert np.array_equal(U[1:, 1:], U[:-1, :-1])
+    assert np.linalg.eigvalsh(U).min() > 0
+    B = U @ U
+    np.testing.assert_allclose(np.diag(B), sb ** 2, rtol=1e-13)
+    kap = O.diffusion_kappa(D, M)
+    T = (1 + 2 * kap) * np.eye(n) - kap * (np.roll(np.eye(n), 1, axis=0) + np.roll(np.eye(n), -1, axis=0))
+    X = U.copy()
+    for _ in range(M // 2):
+        X = T @ X
+    # rounding in U_B is amplified by ||T||^(M/2) <= (1 + 4 kappa)^(M/2)
+    tol = 64 * np.finfo(float).eps * (1 + 4 * kap) ** (M // 2)
+    assert X[0, 0] > 0
+    assert np.abs(X - X[0, 0] * np.eye(n)).max() <= tol * X[0, 0]
+
+
+def test_diffusion_daley_length_and_heat_kernel_limit():
+    # kappa = D^2 / (2M - 3) makes D the Daley length-scale, -1/c''(0) = D^2, of
+    # the correlation c; on the grid the second difference at 0 gives it to
+    # O(1/D^2).  As M grows at fixed D the spectrum (1 + 4 kappa sin^2(t/2))^-M
+    # tends to exp(-D^2 (1 - cos t)), whose lattice kernel is the discrete heat
+    # kernel: c(d) -> I_d(D^2) / I_0(D^2) (modified Bessel functions), with an
+    # O(1/M) difference.
+    from scipy.special import ive
+    for n, D, M in ((1500, 6.0, 10), (1000, 20.0, 10)):
+        U = O.circulant(O.diffusion_ub_row(n, 1.0, D, M))
+        c = (U @ U)[0]
+        d_est = np.sqrt(1.0 / (2.0 * (1.0 - c[1] / c[0])))
+        assert abs(d_est - D) < 0.01 * D, (D, d_est)
+    n, D = 800, 8.0
+    i = np.arange(n)
+    heat = ive(np.minimum(i, n - i), D * D) / ive(0, D * D)
+    errs = []
+    for M in (400, 2000):
+        U = O.circulant(O.diffusion_ub_row(n, 1.0, D, M))
+        errs.append(np.abs((U @ U)[0] - heat).max())
+    assert errs[1] < 2e-4 and errs[1] < errs[0] / 4, errs
+
+
+def test_diffusion_problem_hessian():
+    # The paper's set-up with the diffusion B at reduced size: the Hessian is
+    # symmetric, I + A >= I, and rank(A) <= p.
+    cfg = W.config("paper", n=120, obs_dx=6, members=2, spinup=200)
+    P = O.Problem(cfg, W.problem_normals(cfg))
+    assert P.p == 60
+    A = P.A(np.eye(120), [0] * 120)
+    assert np.abs(A - A.T).max() <= 1e-12 * np.abs(A).max()
+    lam = np.linalg.eigvalsh(0.5 * (A + A.T))
+    assert lam.min() > -1e-10 * lam.max()
+    assert np.sum(lam > 1e-9 * lam.max()) <= P.p
+
+
+def test_fix_signs_convention():
+    # Eigenvector sign reading: the entry of largest magnitude of each column is
+    # made positive, the lowest index winning a tie in magnitude.
+    S = np.array([[0.1, 0.5, -0.5, 0.0],
+                  [-0.9, -0.5, 0.5, 0.0],
+                  [0.2, 0.3, 0.1, -1.0]])
+    F = O.fix_signs(S)
+    want = np.array([[-0.1, 0.5, 0.5, 0.0],
+                     [0.9, -0.5, -0.5, 0.0],
+                     [-0.2, 0.3, -0.1, 1.0]])
+    assert np.array_equal(F, want)
+    # idempotent, and a column and its negative map to the same column
+    assert np.array_equal(O.fix_signs(F), F)
+    assert np.array_equal(O.fix_signs(-S), F)
+
+
 # ------------------------------------------------------------ Hessian ------
 def test_hessian_symmetric_and_above_identity(c1):
     n = c1.cfg["n"]

@@ -27,12 +27,15 @@ import numpy as np
 #   n, nsteps (window N), F, dt, spinup (truth spin-up steps), spin_pert_std,
 #   obs_dt (observation every obs_dt steps, time 0 excluded), obs_dx, obs_x0
 #   (observed variables i = obs_x0 + q*obs_dx), sigma_o (R = sigma_o^2 I),
-#   sigma_b, len_b (B = sigma_b^2 * cyclic Gaussian correlation of length len_b),
+#   sigma_b, len_b, b_kind, diff_steps (B = sigma_b^2 C: b_kind "gauss", the
+#   cyclic Gaussian correlation of length len_b; or "diffusion", the
+#   diffusion-based correlation with Daley length-scale len_b and diff_steps
+#   diffusion steps),
 #   members (L perturbed members; member 0 is the control),
 #   ell, k (sketch columns / retained rank), q (Nystrom passes), theta ('mid'),
 #   rtol, maxit (PCG).
 _BASE = dict(F=8.0, dt=0.025, spinup=1000, spin_pert_std=0.1, obs_x0=0,
-             sigma_o=0.5, sigma_b=1.0, q=1, theta="mid", seed=0, problem_id=0)
+             sigma_o=0.5, sigma_b=1.0, b_kind="gauss", diff_steps=0, q=1, theta="mid", seed=0, problem_id=0)
 
 CONFIGS = {
     # Plain FP64, n = 40; every 2nd variable every 5 steps; PCG exactly 50 iterations.
@@ -44,6 +47,14 @@ CONFIGS = {
     # n = 4096, every 2nd variable every 4 steps, 128 members, k = 64.
     "C3": dict(_BASE, n=4096, nsteps=40, obs_dt=4, obs_dx=2, len_b=8.0, members=128,
                ell=64, k=64, rtol=1e-6, maxit=2000),
+    # The paper's own set-up (numerical-experiments section): n = 1500, a
+    # 10-step window, direct observations of 50 variables (every 30th) at 3
+    # times (steps 3, 6, 9: p = 150), sigma_o = 0.05, sigma_b = 0.8, the
+    # diffusion-based B with D = 6 and M = 10, L = ell = 20 members, k = 20
+    # (k = 15 with oversampling in the sensitivity study).
+    "paper": dict(_BASE, n=1500, nsteps=10, obs_dt=3, obs_dx=30, sigma_o=0.05, sigma_b=0.8,
+                  b_kind="diffusion", len_b=6.0, diff_steps=10, members=20, ell=20, k=20,
+                  rtol=1e-6, maxit=2000),
 }
 
 
@@ -77,6 +88,21 @@ def _rng(seed: int, problem_id: int, stream: int) -> np.random.Generator:
 def problem_normals(cfg: dict) -> np.ndarray:
     """Standard normals for one EDA problem (layout in the module docstring)."""
     return _rng(cfg["seed"], cfg["problem_id"], 0).standard_normal(n_normals(cfg))
+
+
+def ensemble_normals(cfg: dict, draw: int) -> np.ndarray:
+    """Normals of one problem whose control part (truth perturbation, xi_0,
+    eta_0) is that of problem_normals(cfg) and whose member perturbations
+    (xi_j, eta_j, j >= 1) are draw `draw` of a separate stream (9): the same
+    control problem with another ensemble, as in repeated experiments with
+    different ensemble instances."""
+    z = problem_normals(cfg)
+    nt, nv = obs_counts(cfg)
+    n, L, p = cfg["n"], cfg["members"], nt * nv
+    fresh = _rng(cfg["seed"], cfg["problem_id"] * 4096 + draw, 9).standard_normal(L * (n + p))
+    z[1 + n:1 + (L + 1) * n] = fresh[:L * n]
+    z[1 + (L + 1) * n + p:] = fresh[L * n:]
+    return z
 
 
 def gaussian_matrix(cfg: dict, rows: int, cols: int, stream: int = 5) -> np.ndarray:
