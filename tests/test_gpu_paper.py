@@ -123,29 +123,49 @@ def test_paper_sketching_matrices(kind):
     assert colrel(Pg, Po) < max(1e-12, float(bars.max()))
 
 
+def _oracle_hist(o, S, D, th, iters):
+    _, _, _, _, hist = O.pcg(lambda v: o.hess(v[:, None], [0])[:, 0], o.b[:, 0],
+                             lambda v: O.lmp_apply(S, D, th, v[:, None])[:, 0], 0.0, iters)
+    return np.asarray(hist)
+
+
 @pytest.mark.parametrize("k", [20, 15])
 @pytest.mark.parametrize("theta", ["mid", "lamk", "one"])
 def test_paper_theta_rules_and_oversampling(theta, k):
     # Sensitivity analysis: the Gamma sketch with ell = 20 and k = 20 or 15
     # (oversampling by 5), each theta rule; LMP-PCG of the control for 30
     # iterations, whose cost history J_i - c must follow the oracle's PCG with
-    # the oracle's own LMP while J still decreases by more than 1e-12 |J|
-    # (beyond that two correct implementations wander at rounding level).
+    # the oracle's own LMP.  How far two correct computations may drift apart
+    # is measured on the oracle alone: the same Nystrom approximation from
+    # Gamma with its columns permuted (the approximation is invariant to that,
+    # its rounding is not) gives a second history; the GPU history is held to
+    # 1e-8 |J| over the iterations where those two still agree to 1e-11 |J|,
+    # and to the measured spread of that pair beyond.
     g, o = problem()
-    eig, th = g.sketch_evd("rhs_diff", ell=CFG["ell"], k=k, theta=theta)
-    S, D, info = O.nystrom(lambda V: o.A(V, [0] * V.shape[1]), o.gamma(CFG["ell"]), k)
+    ell = CFG["ell"]
+    eig, th = g.sketch_evd("rhs_diff", ell=ell, k=k, theta=theta)
+    Aop = lambda V: o.A(V, [0] * V.shape[1])
+    S, D, info = O.nystrom(Aop, o.gamma(ell), k)
     th_o = O.theta(D, theta)
     assert abs(th - th_o) <= eig_bars(D, info["cond_core"])[-1] * th_o
-    out = g.pcg([0], rtol=0.0, maxit=30, use_lmp=True, history=True)
-    _, _, _, _, hist = O.pcg(lambda v: o.hess(v[:, None], [0])[:, 0], o.b[:, 0],
-                             lambda v: O.lmp_apply(S, D, th_o, v[:, None])[:, 0], 0.0, 30)
-    hg = out["hist"][0][:len(hist)]
-    meaningful = np.concatenate([[True], np.abs(np.diff(hist)) > 1e-12 * np.abs(hist[-1])])
-    cut = np.argmin(meaningful) if not meaningful.all() else len(hist)
-    d = np.abs(hg[:cut] - hist[:cut]).max() / abs(hist[cut - 1])
-    print(f"[paper] theta={theta} k={k}: J history agrees over {cut} iterations to {d:.1e}; "
+    iters = 30
+    out = g.pcg([0], rtol=0.0, maxit=iters, use_lmp=True, history=True)
+    hist = _oracle_hist(o, S, D, th_o, iters)
+    perm = np.random.default_rng(1).permutation(ell)
+    S2, D2, _ = O.nystrom(Aop, o.gamma(ell)[:, perm], k)
+    hist2 = _oracle_hist(o, S2, D2, O.theta(D2, theta), iters)
+    scale = abs(hist[-1])
+    spread = np.maximum.accumulate(np.abs(hist2 - hist)) / scale
+    cut = int(np.argmax(spread > 1e-11)) if np.any(spread > 1e-11) else len(hist)
+    hg = np.asarray(out["hist"][0][:len(hist)])
+    d = np.abs(hg - hist) / scale
+    beyond = float(d[cut:].max()) if cut < len(hist) else 0.0
+    print(f"[paper] theta={theta} k={k}: oracle pair agrees to 1e-11 over {cut} iterations; GPU there "
+          f"{d[:cut].max():.1e}, beyond {beyond:.1e} (oracle pair {spread[-1]:.1e}); "
           f"J_1 {hist[1]:.6e}, J_30 {hist[-1]:.6e}", flush=True)
-    assert cut >= 5 and d < 1e-8
+    assert cut >= 10 and d[:cut].max() < 1e-8
+    assert np.all(np.diff(hg[:cut]) <= 1e-12 * scale), "cost history must decrease"
+    assert beyond <= max(1e-8, 100 * spread[-1])
 
 
 def test_paper_members_converge_with_the_control_lmp():
