@@ -193,6 +193,24 @@ int eda_sketch_evd(eda_ctx *ctx, int32_t kind, const double *d_phi, int64_t ldph
 int eda_lmp_apply(eda_ctx *ctx, int32_t which, int32_t nb, const double *d_X, int64_t ldx,
                   double *d_Y, int64_t ldy);
 
+/* Allocation-free variant of eda_lmp_apply, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same operation, arguments, kernels and bits as
+ * eda_lmp_apply; the row-block partial projections S_b^T X_b, which
+ * eda_lmp_apply keeps in the context's workspace, go to a fixed device buffer
+ * of EDA_LMP_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs
+ * on (one per device, kept until the process ends; no call allocates or frees
+ * anything).  The partials of a call need ceil(n / 256) * k * (16 ceil(nb / 16))
+ * doubles; larger requests return EDA_ERR_UNSUPPORTED before anything is
+ * enqueued.  Every call on one GPU shares that GPU's buffer: calls that overlap
+ * in time on one GPU (other streams, other threads, other contexts) race and
+ * must be serialised by the caller.  Each call writes every partial it reads
+ * before reading it, so nothing needs to start at zero.  EDA_ERR_ORDER before a
+ * sketch; other errors as eda_lmp_apply. */
+#define EDA_LMP_NOALLOC_SCRATCH_BYTES 4194304
+int eda_lmp_apply_noalloc(eda_ctx *ctx, int32_t which, int32_t nb, const double *d_X, int64_t ldx,
+                          double *d_Y, int64_t ldy);
+
 /* Batched PCG (solving-linear-systems section) for members h_members[0..nm-1]
  * (host array, each in 0..L, nm <= max_cols), from dz = 0, preconditioned by
  * the context's P_theta when use_lmp != 0 (EDA_ERR_ORDER if none was built) or

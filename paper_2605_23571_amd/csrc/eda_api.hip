@@ -468,7 +468,8 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
     {
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&c.num_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            hipDeviceGetAttribute(&c.num_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            lmp_noalloc_scratch(&c.lmp_noalloc) != hipSuccess) {
             delete h;
             return EDA_ERR_HIP;
         }
@@ -704,6 +705,26 @@ int eda_lmp_apply(eda_ctx *h, int32_t which, int32_t nb, const double *d_X, int6
     if (nb == 0) return EDA_OK;
     if (!d_X || !d_Y) return EDA_ERR_INVALID_ARG;
     return lmp_apply(c, which, nb, d_X, ldx, d_Y, ldy);
+}
+
+int eda_lmp_apply_noalloc(eda_ctx *h, int32_t which, int32_t nb, const double *d_X, int64_t ldx, double *d_Y,
+                          int64_t ldy) {
+    if (!h) return EDA_ERR_INVALID_ARG;
+    Ctx &c = h->c;
+    if (which != EDA_LMP_P && which != EDA_LMP_U) return EDA_ERR_INVALID_ARG;
+    if (nb < 0 || nb > c.max_cols || ldx < c.n || ldy < c.n) return EDA_ERR_INVALID_ARG;
+    if (!c.have_lmp) return EDA_ERR_ORDER;
+    if (nb == 0) return EDA_OK;
+    if (!d_X || !d_Y) return EDA_ERR_INVALID_ARG;
+    if (!c.lmp_noalloc) return EDA_ERR_HIP;
+    if (lmp_work_doubles(c.n, c.k, nb) > LMP_NOALLOC_DOUBLES) return EDA_ERR_UNSUPPORTED;
+    const double *coef = which == EDA_LMP_U ? c.sk_coefu : c.sk_coef;
+    if (!c.sr_ready) {
+        HIP_TRY(launch_lmp_rowmajor(c.stream, c.n, c.k, c.sk_s, c.sk_sr));
+        c.sr_ready = true;
+    }
+    HIP_TRY(launch_lmp(c.stream, c.n, c.k, nb, c.sk_s, c.sk_sr, coef, d_X, ldx, d_Y, ldy, nullptr, c.lmp_noalloc));
+    return EDA_OK;
 }
 
 int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol, int32_t maxit, int32_t use_lmp,

@@ -50,6 +50,7 @@ struct Ctx {
     int32_t *sk_info = nullptr;
     double *lmp_t = nullptr;   // k x max_cols LMP coefficients S_k^T X
     double *lmp_work = nullptr;  // LMP row-block partial projections
+    double *lmp_noalloc = nullptr;  // the same, fixed buffer of eda_lmp_apply_noalloc (this device)
     double *sk_sr = nullptr;     // S_k row-major (n x k), made from sk_s on the first LMP use
     bool sr_ready = false;
     double *splitk = nullptr;  // split-K partial sums
@@ -242,6 +243,10 @@ constexpr int LMP_RB_MAX = 16;
 constexpr int LMP_K_MAX = 128;
 void lmp_blocks(int n, int *rows, int *nrb);
 size_t lmp_work_doubles(int n, int k, int ncols);
+// Size of the fixed partial-projection buffer of eda_lmp_apply_noalloc and its
+// device address on the current device (looked up once per device).
+constexpr size_t LMP_NOALLOC_DOUBLES = (size_t)EDA_LMP_NOALLOC_SCRATCH_BYTES / sizeof(double);
+hipError_t lmp_noalloc_scratch(double **out);
 hipError_t launch_lmp_rowmajor(hipStream_t s, int n, int k, const double *S, double *Sr);
 hipError_t launch_lmp(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
                       const double *X, long long ldx, double *Y, long long ldy, const int32_t *status, double *work);

@@ -23,7 +23,16 @@
 // takes S column-major (row index contiguous) and W from LDS.  Both kernels are
 // bound by memory latency rather than bandwidth, so each issues all of its
 // global loads before it waits.
+#include <mutex>
+
 #include "eda_internal.h"
+
+// Fixed device buffer of the allocation-free LMP entry point: the row-block
+// partial projections of one call, LMP_NOALLOC_DOUBLES doubles (4 MiB).  Each
+// GPU the library runs on holds its own copy until the process ends.  In host
+// code this name is not a device address: its address on a device comes from
+// hipGetSymbolAddress (lmp_noalloc_scratch), and only that address is used.
+static __device__ __align__(256) double scratch[eda::LMP_NOALLOC_DOUBLES];
 
 namespace eda {
 namespace {
@@ -381,6 +390,27 @@ hipError_t launch_lmp(hipStream_t s, int n, int k, int nb, const double *S, cons
     // the plain form only reads X and status
     return lmp_launch<false>(s, n, k, nb, S, Sr, coef, const_cast<double *>(X), ldx, Y, ldy,
                              const_cast<int32_t *>(status), work, LmpFin{});
+}
+
+// Device address of `scratch` on the current device, looked up once per device
+// (with that device current) and kept; later calls return the kept address.
+hipError_t lmp_noalloc_scratch(double **out) {
+    constexpr int MAX_DEV = 64;
+    static std::mutex mu;
+    static double *addr[MAX_DEV] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<double *>(p);
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_lmp_fin(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,

@@ -35,6 +35,7 @@ EDA_SKETCH_RHS_DIFF, EDA_SKETCH_USER, EDA_SKETCH_B_PSI, EDA_SKETCH_UBT_PSI = 0, 
 EDA_METHOD_NYSTROM, EDA_METHOD_REVD = 0, 1
 EDA_THETA_MID, EDA_THETA_LAMK, EDA_THETA_ONE = 0, 1, 2
 EDA_LMP_P, EDA_LMP_U = 0, 1
+EDA_LMP_NOALLOC_SCRATCH_BYTES = 4194304
 FIELDS = dict(truth=0, xb=1, traj=2, y=3, d=4, b=5, costc=6, ubrow=7, S=8, eig=9)
 THETA_RULES = {"mid": EDA_THETA_MID, "lamk": EDA_THETA_LAMK, "one": EDA_THETA_ONE}
 
@@ -75,6 +76,7 @@ def lib():
             "eda_hessvec": [vp, vp, i32, vp, i64, vp, i64, u32],
             "eda_sketch_evd": [vp, i32, vp, i64, i32, i32, i32, i32, i32, u32, vp, vp],
             "eda_lmp_apply": [vp, i32, i32, vp, i64, vp, i64],
+            "eda_lmp_apply_noalloc": [vp, i32, i32, vp, i64, vp, i64],
             "eda_pcg_solve": [vp, vp, i32, dbl, i32, i32, vp, i64, vp, vp, vp, vp],
             "eda_field": [vp, i32, ctypes.POINTER(sz), ctypes.POINTER(i64)],
             "eda_profile": [vp, i32],
@@ -212,6 +214,13 @@ def eda_lmp_apply(ctx, n: int, which: int, X, Y):
     px, ldx = _dev_f64(X, n)
     py, ldy = _dev_f64(Y, n)
     _check("eda_lmp_apply", lib().eda_lmp_apply(ctx, which, X.shape[0], px, ldx, py, ldy))
+    return Y
+
+
+def eda_lmp_apply_noalloc(ctx, n: int, which: int, X, Y):
+    px, ldx = _dev_f64(X, n)
+    py, ldy = _dev_f64(Y, n)
+    _check("eda_lmp_apply_noalloc", lib().eda_lmp_apply_noalloc(ctx, which, X.shape[0], px, ldx, py, ldy))
     return Y
 
 
