@@ -105,10 +105,13 @@ def ensemble_normals(cfg: dict, draw: int) -> np.ndarray:
     return z
 
 
-def gaussian_matrix(cfg: dict, rows: int, cols: int, stream: int = 5) -> np.ndarray:
+def gaussian_matrix(cfg: dict, rows: int, cols: int, stream: int = 5, draw: int | None = None) -> np.ndarray:
     """A seeded standard-Gaussian matrix stored column-major as an array of
-    shape (cols, rows): row c of the array is column c of the matrix."""
-    return _rng(cfg["seed"], cfg["problem_id"], stream).standard_normal((cols, rows))
+    shape (cols, rows): row c of the array is column c of the matrix.  With
+    `draw`, draw number `draw` of a family of independent such matrices (keyed
+    as ensemble_normals keys its draws)."""
+    pid = cfg["problem_id"] if draw is None else cfg["problem_id"] * 4096 + draw
+    return _rng(cfg["seed"], pid, stream).standard_normal((cols, rows))
 
 
 def uneven_problems(count: int = 256, seed: int = 0) -> list[dict]:
