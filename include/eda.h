@@ -46,6 +46,8 @@ extern "C" {
 #define EDA_ERR_NOT_SPD        -4  /* Cholesky of Phi^T A Phi failed even after the shift      */
 #define EDA_ERR_ORDER          -5  /* LMP requested before eda_sketch_evd built one            */
 #define EDA_ERR_UNSUPPORTED    -6  /* option not supported by this build (sizes, modes)        */
+#define EDA_ERR_SYNC           -7  /* a wait between the exchange form's wave pieces gave up,  */
+                                   /* or the device placed workgroups unlike that form expects  */
 #define EDA_WARN_NOT_CONVERGED  1  /* eda_pcg_solve: some member hit maxit or broke down      */
 
 /* ---- per-member PCG outcome (h_status of eda_pcg_solve) ---- */
@@ -80,6 +82,10 @@ extern "C" {
 #define EDA_THETA_MID   0        /* theta = (lambda_k(I+A) + 1) / 2                          */
 #define EDA_THETA_LAMK  1        /* theta = lambda_k(I+A)                                    */
 #define EDA_THETA_ONE   2        /* theta = 1                                                */
+
+#define EDA_XCH_OFF   0          /* eda_set_exchange: never (default)                          */
+#define EDA_XCH_ON    1          /* eda_set_exchange: wave pieces with halo exchange whenever  */
+                                 /* a launch shape exists for the running columns             */
 
 #define EDA_LMP_P  0             /* apply P_theta                                            */
 #define EDA_LMP_U  1             /* apply the symmetric factor U_theta                       */
@@ -341,6 +347,25 @@ int eda_set_geometry(eda_ctx *ctx, int32_t waves, int32_t tb);
  * n (ring of ceil(n / P) + 2 halo states longer than n, or a window wider than
  * the kernel supports); EDA_ERR_INVALID_ARG for other values. */
 int eda_set_split(eda_ctx *ctx, int32_t pieces);
+
+/* Wave pieces with halo exchange in the split iterations of eda_pcg_solve
+ * (banded U_B with the LMP, n >= 512, pieces = 0 in eda_set_split).  Every
+ * wave of a launch owns one segment of one running column; the segments of a
+ * column exchange the edges of their TL and AD states through device memory
+ * at every time-block boundary, so a column is spread over many compute units
+ * with no recomputed halo (the integrations of the tangent linear and adjoint
+ * models over the assimilation window, cost model of the Nystrom
+ * subsection).  The launch takes one workgroup per compute unit, all
+ * co-resident; waits are bounded.  mode: EDA_XCH_OFF (default; on MI355X
+ * the ring pieces are faster at the sizes measured) or EDA_XCH_ON (used
+ * whenever a launch shape exists for the running columns).  spin_limit:
+ * polls of one wait before it gives up; < 0 restores the default (about a
+ * second); 0 makes every wait give up at once (to exercise the error path).
+ * A wait that gives up stops its member with EDA_MEMBER_BREAKDOWN and makes
+ * eda_pcg_solve return EDA_ERR_SYNC; so does a workgroup placed on an XCD other
+ * than the one the layout assumes.  Solutions agree with the other forms to
+ * rounding.  Errors: EDA_ERR_INVALID_ARG for other modes. */
+int eda_set_exchange(eda_ctx *ctx, int32_t mode, int64_t spin_limit);
 
 /* Free the context's host structures (the workspace stays the caller's). */
 int eda_destroy(eda_ctx *ctx);

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -64,6 +65,7 @@ struct Plan {
         off_lmpt, off_lmpw, off_sr;
     size_t off_x, off_r, off_z, off_pp, off_q, off_scal, off_status, off_iters, off_members, off_hist;
     size_t off_p2, off_pqp, off_fin;  // split PCG iterations (banded U_B)
+    size_t off_xflags, off_xedges, off_xerr, off_xnseg, off_rzp;  // wave pieces with halo exchange
     size_t splitk_elems;
     size_t total;
 };
@@ -150,10 +152,14 @@ Plan make_plan(const eda_config *c) {
     band_taps(c, band_lo, band_hi);
     {
         int pl, pr;
-        if (banded)
+        if (banded) {
             tlad_pads_split(P.n, P.N, band_hi, &pl, &pr);
-        else
+            // the exchange form's windows: up to 8 XCH_TB_MAX before a segment, 64 x 8 after its start
+            if (pl < 8 * XCH_TB_MAX) pl = 8 * XCH_TB_MAX;
+            if (pr < 64 * 8) pr = 64 * 8;
+        } else {
             tlad_pads(P.n, &pl, &pr);
+        }
         P.pad_l = pl;
         P.ext_len = ((P.n + pl + pr + 31) / 32) * 32;
     }
@@ -195,8 +201,17 @@ Plan make_plan(const eda_config *c) {
     P.off_members = lay.take(mc * sizeof(int32_t));
     P.off_hist = lay.take(mc * (size_t)HIST_CAP * d);
     P.off_p2 = lay.take((banded ? n * mc : 1) * d);
-    P.off_pqp = lay.take(mc * SPLIT_PMAX * d);
+    P.off_pqp = lay.take(mc * (XCH_SEG_MAX > SPLIT_PMAX ? XCH_SEG_MAX : SPLIT_PMAX) * d);
     P.off_fin = lay.take(lmp_fin_doubles(P.maxc) * d);
+    {
+        const bool xch = banded && P.n >= XCH_N_MIN;
+        const size_t slots = xch ? 8 * (size_t)XCH_GRID_MAX : 1;
+        P.off_xflags = lay.take((slots + (xch ? XCH_GRID_MAX : 0)) * sizeof(unsigned long long));
+        P.off_xedges = lay.take((xch ? slots * 4 * XCH_E_MAX : 1) * d);
+        P.off_xerr = lay.take(sizeof(int32_t));
+        P.off_xnseg = lay.take(mc * sizeof(int32_t));
+        P.off_rzp = lay.take((size_t)LMP_RB_MAX * ((mc + 15) / 16 * 16) * d);
+    }
     P.total = lay.total;
     return P;
 }
@@ -250,6 +265,33 @@ TladArgs tlad_args(Ctx &c, int nb, const int32_t *cols, const int32_t *active) {
     a.band_lo = c.band_lo;
     a.band_hi = c.band_hi;
     return a;
+}
+
+// Enqueues launch() with HIP events around it when the PCG-loop profiling
+// samples this launch.
+template <typename F>
+int profiled(Ctx &c, F launch) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool rec = c.prof > 0 && c.in_pcg && c.prof_seen++ % c.prof == 0;
+    if (rec) {
+        if (c.ev_used + 2 > c.ev.size()) {
+            for (int i = 0; i < 64; i++) {
+                hipEvent_t e;
+                HIP_TRY(hipEventCreate(&e));
+                c.ev.push_back(e);
+            }
+        }
+        e0 = c.ev[c.ev_used];
+        e1 = c.ev[c.ev_used + 1];
+        c.ev_used += 2;
+        HIP_TRY(hipEventRecord(e0, c.stream));
+    }
+    HIP_TRY(launch());
+    if (rec) {
+        HIP_TRY(hipEventRecord(e1, c.stream));
+        c.prof_launches++;
+    }
+    return EDA_OK;
 }
 
 int run_tlad(Ctx &c, const TladArgs &a, int mode, bool fp32, const SplitCols *sc = nullptr) {
@@ -464,6 +506,14 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
     c.pc_p2 = at<double>(w, P.off_p2);
     c.pc_pqp = at<double>(w, P.off_pqp);
     c.lmp_fin = at<double>(w, P.off_fin);
+    c.pad_r = P.ext_len - P.n - P.pad_l;
+    if (cfg->ub_mode == EDA_UB_BANDED && P.n >= XCH_N_MIN) {
+        c.xch_flags = at<unsigned long long>(w, P.off_xflags);
+        c.xch_edges = at<double>(w, P.off_xedges);
+    }
+    c.xch_err = at<int32_t>(w, P.off_xerr);
+    c.xch_nseg = at<int32_t>(w, P.off_xnseg);
+    c.rz_part = at<double>(w, P.off_rzp);
     band_taps(cfg, c.band_lo, c.band_hi);
     {
         int dev = 0;
@@ -486,6 +536,11 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
     const double *xi = d_normals + 1;
     const double *eta = d_normals + 1 + (size_t)(L + 1) * n;
     if (hipMemsetAsync(c.zero_members, 0, sizeof(int32_t) * c.max_cols, s) != hipSuccess) return fail(EDA_ERR_HIP);
+    // exchange flags start below every launch's phases; segment counts start empty
+    if ((c.xch_flags && hipMemsetAsync(c.xch_flags, 0, sizeof(unsigned long long) * 9 * XCH_GRID_MAX, s) != hipSuccess) ||
+        hipMemsetAsync(c.xch_nseg, 0, sizeof(int32_t) * c.max_cols, s) != hipSuccess ||
+        hipMemsetAsync(c.xch_err, 0, sizeof(int32_t), s) != hipSuccess)
+        return fail(EDA_ERR_HIP);
     // U_B
     if ((cfg->b_kind == EDA_B_DIFFUSION
              ? launch_ub_row_diffusion(s, n, cfg->sigma_b, cfg->len_b, cfg->diff_steps, c.ubrow)
@@ -649,13 +704,13 @@ namespace {
 // Y = X + S_k diag(coef) S_k^T X (coef: P_theta or U_theta coefficients);
 // inside PCG (status given) tiles of stopped members are skipped.
 int lmp_apply(Ctx &c, int which, int nb, const double *X, long long ldx, double *Y, long long ldy,
-              const int32_t *status = nullptr) {
+              const int32_t *status = nullptr, double *rz = nullptr) {
     const double *coef = which == EDA_LMP_U ? c.sk_coefu : c.sk_coef;
     if (!c.sr_ready) {
         HIP_TRY(launch_lmp_rowmajor(c.stream, c.n, c.k, c.sk_s, c.sk_sr));
         c.sr_ready = true;
     }
-    HIP_TRY(launch_lmp(c.stream, c.n, c.k, nb, c.sk_s, c.sk_sr, coef, X, ldx, Y, ldy, status, c.lmp_work));
+    HIP_TRY(launch_lmp(c.stream, c.n, c.k, nb, c.sk_s, c.sk_sr, coef, X, ldx, Y, ldy, status, c.lmp_work, rz));
     return EDA_OK;
 }
 
@@ -688,7 +743,7 @@ int lmp_update(Ctx &c, int nb, const LmpFin &f) {
         c.sr_ready = true;
     }
     HIP_TRY(launch_lmp_fin(c.stream, c.n, c.k, nb, c.sk_s, c.sk_sr, c.sk_coef, c.pc_r, c.pc_z, c.pc_status,
-                           c.lmp_work, f));
+                           c.lmp_work, f, c.rz_part));
     return EDA_OK;
 }
 
@@ -757,7 +812,17 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
     a.hist_cap = c.hist_cap;
     a.rtol = rtol;
     HIP_TRY(launch_pcg_init(s, a));
-    if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status));
+    const bool fused = c.cfg.ub_mode == EDA_UB_BANDED;
+    // with the LMP, the banded form runs split iterations: the Hessian part on
+    // pieces of every running column (wave pieces with halo exchange, or P ring
+    // pieces per column with P * running columns <= compute units), then the
+    // update fused with the LMP of the new residual (which also leaves the
+    // row-block partials of r^T z for the exchange form)
+    const bool split = fused && use_lmp;
+    if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status, split ? c.rz_part : nullptr));
+    if (split) HIP_TRY(hipMemsetAsync(c.xch_err, 0, sizeof(int32_t), s));
+    const int xch_grid = (c.num_cus < XCH_GRID_MAX ? c.num_cus : XCH_GRID_MAX) & ~7;
+    bool xch_used = false;
     // Convergence checks are pipelined: every check_every iterations the status
     // array is copied to a pinned host slot behind an event; the host reads a
     // checkpoint once its event has completed, and waits only when more than
@@ -769,11 +834,6 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                               sizeof(int32_t) * Ctx::CK_SLOTS * (size_t)c.max_cols, hipHostMallocDefault));
         for (int i = 0; i < Ctx::CK_SLOTS; i++) HIP_TRY(hipEventCreateWithFlags(&c.ck_ev[i], hipEventDisableTiming));
     }
-    const bool fused = c.cfg.ub_mode == EDA_UB_BANDED;
-    // with the LMP, the banded form runs split iterations: the Hessian part on
-    // P pieces per column (P * running columns <= compute units), then the
-    // update fused with the LMP of the new residual
-    const bool split = fused && use_lmp;
     int ck_issued = 0, ck_done = 0;
     std::vector<std::vector<int16_t>> ck_running;  // running columns at each checkpoint read
     bool none_running = false;
@@ -829,12 +889,71 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                     sc.count = known ? (int)known->size() : nm;
                     for (int i = 0; i < sc.count; i++) sc.col[i] = known ? (*known)[i] : (int16_t)i;
                 }
+                XchPlan xp{};
+                if (c.xch_mode == EDA_XCH_ON && c.split_force == 0 && c.xch_flags && active > 0)
+                    xp = xch_plan(n, c.N, c.band_hi, sc.count > 0 ? sc.count : nm, xch_grid, c.pad_l, c.pad_r);
                 const int P = active == 0 ? 1 : split_pieces(c, active);
-                if (P == 1) {
+                if (xp.ok) {
+                    // wave pieces with halo exchange
+                    TladArgs t = tlad_args(c, nm, c.pc_members, nullptr);
+                    t.obs = c.hv_obs;
+                    t.pcg.members = c.pc_members;
+                    t.pcg.b = c.b;
+                    t.pcg.x = c.pc_x;
+                    t.pcg.r = c.pc_r;
+                    t.pcg.z = c.pc_z;
+                    t.pcg.p = pbuf[cur];
+                    t.pcg.p_out = pbuf[cur ^ 1];
+                    t.pcg.q = c.pc_q;
+                    t.pcg.pq_part = c.pc_pqp;
+                    t.pcg.scal = c.pc_scal;
+                    t.pcg.status = c.pc_status;
+                    t.pcg.iters = c.pc_iters;
+                    t.pcg.it = it;
+                    t.pcg.first = it == 1 ? 1 : 0;
+                    XchArgs xa{};
+                    xa.flags = c.xch_flags;
+                    xa.claim = c.xch_flags + 8 * XCH_GRID_MAX;
+                    xa.edges = c.xch_edges;
+                    xa.E = xp.E;
+                    xa.tb = xp.tb;
+                    xa.grid = xp.grid;
+                    xa.max_seg = xp.max_seg;
+                    xa.epoch = (++c.xch_epoch) << 16;
+                    xa.spin_max = c.xch_spin < 0 ? XCH_SPIN_DEFAULT : c.xch_spin;
+                    xa.err = c.xch_err;
+                    xa.rz_part = c.rz_part;
+                    xa.rz_ld = (nm + 15) / 16 * 16;
+                    int rows_, nrb_;
+                    lmp_blocks(n, &rows_, &nrb_);
+                    xa.nrb = nrb_;
+                    xa.nseg = c.xch_nseg;
+                    EDA_TRY(profiled(c, [&] { return launch_tlad_x(s, t, xa, xp, sc); }));
+                    LmpFin f{};
+                    f.q = c.pc_q;
+                    f.p = pbuf[cur ^ 1];
+                    f.pq_part = c.pc_pqp;
+                    f.b = c.b;
+                    f.members = c.pc_members;
+                    f.x = c.pc_x;
+                    f.scal = c.pc_scal;
+                    f.hist = a.hist;
+                    f.iters = c.pc_iters;
+                    f.pieces = 0;
+                    f.nseg = c.xch_nseg;
+                    f.it = it;
+                    f.hist_cap = c.hist_cap;
+                    f.rtol = rtol;
+                    f.rr_part = c.lmp_fin;
+                    f.xbr_part = c.lmp_fin + lmp_fin_doubles(c.max_cols) / 2;
+                    EDA_TRY(lmp_update(c, nm, f));
+                    cur ^= 1;
+                    xch_used = true;
+                } else if (P == 1) {
                     // whole columns: the fused iteration (its update hidden under the
                     // TL/AD work), then the LMP of the new residual
                     EDA_TRY(fused_iteration(c, nm, a, pbuf[cur], rtol, it));
-                    EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status));
+                    EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status, c.rz_part));
                 } else {
                     TladArgs t = tlad_args(c, nm, c.pc_members, nullptr);
                     t.obs = c.hv_obs;
@@ -921,6 +1040,11 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
         h_relres[i] = scal[4 * i + 2];
         if (h_status[i] != EDA_MEMBER_CONVERGED) warn = EDA_WARN_NOT_CONVERGED;
     }
+    if (xch_used) {
+        int32_t err = 0;
+        EDA_TRY(sync_read(c, &err, c.xch_err, sizeof(int32_t)));
+        if (err != 0) warn = EDA_ERR_SYNC;
+    }
     if (h_cost_hist) {
         std::vector<double> hist((size_t)nm * c.hist_cap);
         EDA_TRY(sync_read(c, hist.data(), c.pc_hist, sizeof(double) * hist.size()));
@@ -997,6 +1121,13 @@ int eda_set_geometry(eda_ctx *h, int32_t waves, int32_t tb) {
     return EDA_OK;
 }
 
+int eda_set_exchange(eda_ctx *h, int32_t mode, int64_t spin_limit) {
+    if (!h || (mode != EDA_XCH_ON && mode != EDA_XCH_OFF)) return EDA_ERR_INVALID_ARG;
+    h->c.xch_mode = mode;
+    h->c.xch_spin = spin_limit < 0 ? -1 : (long long)spin_limit;
+    return EDA_OK;
+}
+
 int eda_set_split(eda_ctx *h, int32_t pieces) {
     if (!h) return EDA_ERR_INVALID_ARG;
     Ctx &c = h->c;
@@ -1029,6 +1160,7 @@ const char *eda_strerror(int code) {
         case EDA_ERR_NOT_SPD: return "Cholesky of the sketched matrix failed after the shift";
         case EDA_ERR_ORDER: return "no preconditioner: call eda_sketch_evd first";
         case EDA_ERR_UNSUPPORTED: return "unsupported size or option";
+        case EDA_ERR_SYNC: return "a wait between exchanging wave pieces gave up, or workgroups ran on unexpected XCDs";
         case EDA_WARN_NOT_CONVERGED: return "some members did not converge";
         default: return "unknown status";
     }

@@ -65,6 +65,17 @@ struct Ctx {
     // update's per-row-block ||r||^2 and x^T (b + r); compute units of the device
     double *pc_p2 = nullptr, *pc_pqp = nullptr, *lmp_fin = nullptr;
     int num_cus = 0;
+    int pad_r = 0;  // right pad of the padded trajectory rows
+    // wave pieces with halo exchange: flags and edges (banded, n >= XCH_N_MIN),
+    // error word, segments per column, r^T z row-block partials, launch epoch,
+    // mode and wait limit (eda_set_exchange)
+    unsigned long long *xch_flags = nullptr;  // 8 XCH_GRID_MAX slot flags, then XCH_GRID_MAX claims
+    double *xch_edges = nullptr;
+    int32_t *xch_err = nullptr, *xch_nseg = nullptr;
+    double *rz_part = nullptr;
+    unsigned long long xch_epoch = 0;
+    int xch_mode = EDA_XCH_OFF;
+    long long xch_spin = -1;
     int split_force = 0;  // pieces per column forced by eda_set_split (0: automatic)
     // pipelined PCG convergence checks: pinned host slots and their events
     static constexpr int CK_SLOTS = 4;
@@ -152,6 +163,85 @@ struct SplitCols {
 int tlad_split_halo(int N, int band_hi);
 int tlad_split_ring(int n, int N, int band_hi, int pieces);  // 0: not possible (ring longer than n)
 
+// ---- wave pieces with halo exchange (the Hessian part of a PCG iteration) ----
+// Every wave of the launch owns one segment of one running column and runs the
+// TL/AD windows of its segment alone; at every time-block boundary (and once
+// between the TL and AD runs, and once before the outgoing U_B product) it
+// publishes the edges of its owned values to device memory and takes its
+// neighbours' edges as its window halos.  The running columns are dealt to the
+// XCDs in turn (list index i to XCD i mod 8), and an XCD's wave slots
+// (workgroups b = x mod 8, eight waves each) are shared among its columns,
+// consecutive slots holding one column's consecutive segments, so that
+// neighbours exchange through one XCD's L2.
+constexpr int XCH_SEG_MAX = 64;     // segments per column at most
+constexpr int XCH_GRID_MAX = 1024;  // workgroups of one launch at most
+constexpr int XCH_E_MAX = 160;      // edge width at most (doubles per side)
+constexpr int XCH_TB_MAX = 16;      // time-block length at most
+constexpr size_t XCH_LDS_MIN = 96 * 1024;  // one workgroup per CU: all of a launch's waves co-resident
+constexpr int XCH_N_MIN = 512;      // smaller rings keep the whole-column and ring-piece forms
+constexpr long long XCH_SPIN_DEFAULT = 1ll << 21;  // polls of one wait (about a second)
+struct XchPlan {
+    int ok, q, tb, E, max_seg, grid;
+};
+// The launch shape for m running columns on `grid` workgroups (0 = none fits):
+// the most segments per column whose lengths still cover the edge width, the
+// fewest points per lane whose window holds the longest segment and its halos,
+// and the longest time block that window allows; the windows must lie inside
+// the padded trajectory rows (pad_l, pad_r).
+XchPlan xch_plan(int n, int N, int band_hi, int m, int grid, int pad_l, int pad_r);
+struct XchArgs {
+    unsigned long long *flags;  // one per wave slot (8 per workgroup), monotone over launches
+    unsigned long long *claim;  // one per workgroup index: the epoch of the launch that took it
+    double *edges;              // per slot: 2 parities x 2 sides x E
+    int E, tb, grid, max_seg;
+    unsigned long long epoch;   // flag base of this launch; phase k publishes epoch + k + 1
+    long long spin_max;         // polls of a wait before it gives up
+    int32_t *err;               // set to 1 when a wait gave up, 2 when a workgroup ran on another XCD
+    const double *rz_part;      // r^T z per (row block, column): nrb x rz_ld
+    int rz_ld, nrb;
+    int32_t *nseg;              // segments of each column (written by its first segment)
+};
+// One wave slot: the index of its column in the launch's list (-1: idle), its
+// segment, the column's segment count and the neighbouring slots.
+struct XSlot {
+    int li, seg, nseg, left, right;
+};
+__host__ __device__ inline XSlot xch_slot(int slot, int m, int grid, int max_seg) {
+    XSlot r{-1, 0, 0, 0, 0};
+    const int b = slot >> 3, w = slot & 7, x = b & 7;
+    const int slots = ((grid - x + 7) >> 3) * 8;
+    const int cols = m > x ? (m - x + 7) >> 3 : 0;
+    if (cols == 0) return r;
+    int base = slots / cols, extra = slots - base * cols;
+    if (base >= max_seg) {
+        base = max_seg;
+        extra = 0;
+    }
+    if (base < 1) return r;
+    const int ls = (b >> 3) * 8 + w;
+    int lc, seg, nseg, start;
+    if (ls < extra * (base + 1)) {
+        lc = ls / (base + 1);
+        seg = ls - lc * (base + 1);
+        nseg = base + 1;
+        start = lc * (base + 1);
+    } else {
+        const int l2 = ls - extra * (base + 1);
+        lc = extra + l2 / base;
+        seg = l2 % base;
+        nseg = base;
+        start = extra * (base + 1) + (lc - extra) * base;
+    }
+    if (lc >= cols) return r;
+    const int lft = start + (seg + nseg - 1) % nseg, rgt = start + (seg + 1) % nseg;
+    r.li = x + 8 * lc;
+    r.seg = seg;
+    r.nseg = nseg;
+    r.left = ((x + 8 * (lft >> 3)) << 3) | (lft & 7);
+    r.right = ((x + 8 * (rgt >> 3)) << 3) | (rgt & 7);
+    return r;
+}
+
 // Arguments of the TL/AD kernel.  Columns with active[c] != COL_RUNNING are
 // skipped when active is non-null (TLAD_PCG uses pcg.status instead).
 struct TladArgs {
@@ -216,6 +306,11 @@ void tlad_pads_split(int n, int N, int band_hi, int *pad_l, int *pad_r);
 // sc: TLAD_SPLIT only (null: every column).
 hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32, int waves = 0, int tb = 0,
                        const SplitCols *sc = nullptr);
+// The Hessian part of a PCG iteration (as TLAD_SPLIT) on wave pieces with halo
+// exchange; pq_part holds XCH_SEG_MAX entries per column.  Slots are numbered
+// by virtual workgroup index (the dispatch index with its low three bits
+// replaced by the XCD the workgroup runs on), so neighbours share an XCD.
+hipError_t launch_tlad_x(hipStream_t s, const TladArgs &a, const XchArgs &x, const XchPlan &pl, const SplitCols &sc);
 
 // U_B first row (closed form) and dense fill.
 hipError_t launch_ub_row(hipStream_t s, int n, double sigma_b, double len_b, double *row);
@@ -248,8 +343,11 @@ size_t lmp_work_doubles(int n, int k, int ncols);
 constexpr size_t LMP_NOALLOC_DOUBLES = (size_t)EDA_LMP_NOALLOC_SCRATCH_BYTES / sizeof(double);
 hipError_t lmp_noalloc_scratch(double **out);
 hipError_t launch_lmp_rowmajor(hipStream_t s, int n, int k, const double *S, double *Sr);
+// rz (optional): r^T z per (row block, column) with X = r and Y = z, rz[rb *
+// ldw + col], ldw = 16 ceil(nb / 16), summed over the block's rows in a fixed order.
 hipError_t launch_lmp(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
-                      const double *X, long long ldx, double *Y, long long ldy, const int32_t *status, double *work);
+                      const double *X, long long ldx, double *Y, long long ldy, const int32_t *status, double *work,
+                      double *rz = nullptr);
 // The update half of a split PCG iteration, fused with the LMP of the new
 // residual: for every running column, alpha = rho / p^T (I + A) p (rho from
 // scal[4c + 3], the pieces' partial sums pq_part), x += alpha p, r -= alpha q,
@@ -260,13 +358,14 @@ struct LmpFin {
     const int32_t *members;
     double *x, *scal, *hist;
     int32_t *iters;
-    int pieces, it, hist_cap;
+    int pieces, it, hist_cap;  // pieces = 0: wave pieces, nseg[c] per column (stride XCH_SEG_MAX)
     double rtol;
     double *rr_part, *xbr_part;  // LMP_RB_MAX x ldw each
+    const int32_t *nseg;
 };
 size_t lmp_fin_doubles(int ncols);
 hipError_t launch_lmp_fin(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
-                          double *r, double *z, int32_t *status, double *work, const LmpFin &f);
+                          double *r, double *z, int32_t *status, double *work, const LmpFin &f, double *rz = nullptr);
 // BF16-operand, FP32-accumulate GEMM C = A B (+ Add): A in BF16 (M x K,
 // column-major), B, C, Add in FP64 (B rounded to BF16 as it is staged).
 hipError_t gemm_bf16(hipStream_t s, int M, int N, int K, const unsigned short *A, long long lda, const double *B,

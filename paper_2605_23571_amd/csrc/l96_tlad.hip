@@ -234,6 +234,146 @@ __device__ __forceinline__ void band_lane(const double *u, const double *taps, i
     }
 }
 
+// Step constants in the arithmetic type of the run: h = dt / 2, dt, dt / 6,
+// dt / 3 and h F.
+template <typename T>
+struct StepK {
+    T h, dt, dt6, dt3, hF;
+};
+
+// One TL step of this lane's window: dx <- M_s dx about the trajectory state in
+// the wave's window slice xw (X[s]); xn is the next step's window in the
+// padded trajectory, copied into xw around the step (all early for Q <= 7, half
+// and half for Q > 7, at once for !EARLY when `more`).
+template <typename T, int Q, bool EARLY>
+__device__ __forceinline__ void tl_step(const StepK<T> &K, double *xw, const double *xn, bool more, T (&dx)[Q]) {
+    const T h = K.h, dt = K.dt, dt6 = K.dt6, hF = K.hF;
+    T x[Q], Y[Q + 4], V[Q + 4], k[Q], dk[Q], acc[Q], ys[Q], vs[Q];
+    read_window<T, Q>(xw, x);
+    // next step's window: all of it early (Q <= 7), half early and
+    // half after the second stage (Q > 7), or at once (!EARLY)
+    // (the last step reloads its own row: no branch inside the step)
+    double nxt[Q];
+    if constexpr (!EARLY) {
+        if (more) prefetch_window<Q>(xn, xw);
+    } else if constexpr (Q <= 7) {
+        load_part<0, Q, Q>(xn, nxt);
+    } else {
+        load_part<0, Q / 2, Q>(xn, nxt);
+    }
+    ext<T, Q>(x, Y);
+    ext<T, Q>(dx, V);
+    tl_stage<T, Q, true>(Y, V, k, dk);
+#pragma unroll
+    for (int j = 0; j < Q; j++) {
+        x[j] += hF;  // x + h F: the stage states are x + h (k' + F)
+        acc[j] = dk[j];
+        ys[j] = fma_t(h, k[j], x[j]);
+        vs[j] = fma_t(h, dk[j], dx[j]);
+    }
+    ext<T, Q>(ys, Y);
+    ext<T, Q>(vs, V);
+    tl_stage<T, Q, true>(Y, V, k, dk);
+    if constexpr (EARLY && Q > 7) {
+        store_part<0, Q / 2, Q>(xw, nxt);
+        load_part<Q / 2, Q, Q>(xn, nxt);
+    }
+#pragma unroll
+    for (int j = 0; j < Q; j++) {
+        acc[j] = fma_t(T(2), dk[j], acc[j]);
+        ys[j] = fma_t(h, k[j], x[j]);
+        vs[j] = fma_t(h, dk[j], dx[j]);
+    }
+    ext<T, Q>(ys, Y);
+    ext<T, Q>(vs, V);
+    tl_stage<T, Q, true>(Y, V, k, dk);
+#pragma unroll
+    for (int j = 0; j < Q; j++) {
+        acc[j] = fma_t(T(2), dk[j], acc[j]);
+        ys[j] = fma_t(dt, k[j], x[j] + hF);  // x + dt F
+        vs[j] = fma_t(dt, dk[j], dx[j]);
+    }
+    ext<T, Q>(ys, Y);
+    ext<T, Q>(vs, V);
+    tl_stage<T, Q, false>(Y, V, k, dk);
+#pragma unroll
+    for (int j = 0; j < Q; j++) dx[j] = fma_t(dt6, acc[j] + dk[j], dx[j]);
+    if constexpr (EARLY) store_part<(Q <= 7 ? 0 : Q / 2), Q, Q>(xw, nxt);
+}
+
+// One AD step of this lane's window: lam <- M_{s-1}^T lam about the state in
+// xw (X[s - 1]); xn is the next window (X[s - 2]), copied into xw as in tl_step.
+template <typename T, int Q, bool EARLY>
+__device__ __forceinline__ void ad_step(const StepK<T> &K, double *xw, const double *xn, bool more, T (&lam)[Q]) {
+    const T h = K.h, dt = K.dt, dt6 = K.dt6, dt3 = K.dt3, hF = K.hF;
+    T x[Q], Y2[Q + 4], Y3[Q + 4], Y4[Q + 4], M[Q + 4], k[Q], ys[Q];
+    read_window<T, Q>(xw, x);  // X[s - 1]
+    // next step's window (X[s - 2]), split as in the TL run
+    double nxt[Q];
+    if constexpr (!EARLY) {
+        if (more) prefetch_window<Q>(xn, xw);
+    } else if constexpr (Q <= 7) {
+        load_part<0, Q, Q>(xn, nxt);
+    } else {
+        load_part<0, Q / 2, Q>(xn, nxt);
+    }
+    {
+        T Y1[Q + 4];
+        ext<T, Q>(x, Y1);
+        tendency<T, Q>(Y1, k);
+    }
+    // stage states x + h (k' + F) and x + dt (k' + F), from xh = x + h F
+#pragma unroll
+    for (int j = 0; j < Q; j++) ys[j] = fma_t(h, k[j], x[j] + hF);
+    ext<T, Q>(ys, Y2);
+    tendency<T, Q>(Y2, k);
+#pragma unroll
+    for (int j = 0; j < Q; j++) ys[j] = fma_t(h, k[j], x[j] + hF);
+    ext<T, Q>(ys, Y3);
+    tendency<T, Q>(Y3, k);
+#pragma unroll
+    for (int j = 0; j < Q; j++) ys[j] = fma_t(dt, k[j], (x[j] + hF) + hF);
+    ext<T, Q>(ys, Y4);
+    // backward through the stages: mu4 = dt/6 lam, mu3 = mu2 = dt/3 lam, mu1 = dt/6 lam
+    T nu[Q], acc[Q], mu[Q];
+#pragma unroll
+    for (int j = 0; j < Q; j++) mu[j] = dt6 * lam[j];
+    ext<T, Q>(mu, M);
+    jt<T, Q>(Y4, M, nu);
+    if constexpr (EARLY && Q > 7) {
+        store_part<0, Q / 2, Q>(xw, nxt);
+        load_part<Q / 2, Q, Q>(xn, nxt);
+    }
+#pragma unroll
+    for (int j = 0; j < Q; j++) {
+        acc[j] = lam[j] + nu[j];
+        mu[j] = dt3 * lam[j] + dt * nu[j];
+    }
+    ext<T, Q>(mu, M);
+    jt<T, Q>(Y3, M, nu);
+#pragma unroll
+    for (int j = 0; j < Q; j++) {
+        acc[j] += nu[j];
+        mu[j] = dt3 * lam[j] + h * nu[j];
+    }
+    ext<T, Q>(mu, M);
+    jt<T, Q>(Y2, M, nu);
+#pragma unroll
+    for (int j = 0; j < Q; j++) {
+        acc[j] += nu[j];
+        mu[j] = dt6 * lam[j] + h * nu[j];
+    }
+    ext<T, Q>(mu, M);
+    {
+        T Y1[Q + 4];
+        ext<T, Q>(x, Y1);
+        jt<T, Q>(Y1, M, nu);
+    }
+#pragma unroll
+    for (int j = 0; j < Q; j++) lam[j] = acc[j] + nu[j];
+    if constexpr (EARLY) store_part<(Q <= 7 ? 0 : Q / 2), Q, Q>(xw, nxt);
+}
+
 // Deterministic workgroup sum (fixed shuffle tree per wave, then waves in order).
 __device__ __forceinline__ double block_sum(double v, double *red, int waves) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -289,7 +429,7 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
                                                                : (a.col_member ? a.col_member[c] : 0);
     // row s of the member's padded trajectory, from ring position 0: trajm + s ext_len
     const double *trajm = a.trajx + (long long)member * a.trajx_stride + a.pad_l + off;
-    const T h = (T)a.h, dt = (T)a.dt, dt6 = (T)a.dt6, dt3 = (T)a.dt3, hF = (T)(a.h * a.F);
+    const StepK<T> K{(T)a.h, (T)a.dt, (T)a.dt6, (T)a.dt3, (T)(a.h * a.F)};
     unsigned ownm;
     int rsel = 0;
     double rho = 0.0;
@@ -369,61 +509,10 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
             }
             const int s1 = min(N, s0 + g.tb);
             for (int s = s0; s < s1; s++) {
-                T x[Q], Y[Q + 4], V[Q + 4], k[Q], dk[Q], acc[Q], ys[Q], vs[Q];
-                read_window<T, Q>(xw, x);
                 // observed increment of time s
                 if (s > 0 && s % a.obs_dt == 0)
                     store_obs<T, Q>(obs + (long long)(s / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
-                // next step's window: all of it early (Q <= 7), half early and
-                // half after the second stage (Q > 7), or at once (!EARLY)
-                // (the last step reloads its own row: no branch inside the step)
-                const double *xn = trajm + (long long)min(s + 1, N - 1) * a.ext_len + w0;
-                double nxt[Q];
-                if constexpr (!EARLY) {
-                    if (s + 1 < N) prefetch_window<Q>(xn, xw);
-                } else if constexpr (Q <= 7) {
-                    load_part<0, Q, Q>(xn, nxt);
-                } else {
-                    load_part<0, Q / 2, Q>(xn, nxt);
-                }
-                ext<T, Q>(x, Y);
-                ext<T, Q>(dx, V);
-                tl_stage<T, Q, true>(Y, V, k, dk);
-#pragma unroll
-                for (int j = 0; j < Q; j++) {
-                    x[j] += hF;  // x + h F: the stage states are x + h (k' + F)
-                    acc[j] = dk[j];
-                    ys[j] = fma_t(h, k[j], x[j]);
-                    vs[j] = fma_t(h, dk[j], dx[j]);
-                }
-                ext<T, Q>(ys, Y);
-                ext<T, Q>(vs, V);
-                tl_stage<T, Q, true>(Y, V, k, dk);
-                if constexpr (EARLY && Q > 7) {
-                    store_part<0, Q / 2, Q>(xw, nxt);
-                    load_part<Q / 2, Q, Q>(xn, nxt);
-                }
-#pragma unroll
-                for (int j = 0; j < Q; j++) {
-                    acc[j] = fma_t(T(2), dk[j], acc[j]);
-                    ys[j] = fma_t(h, k[j], x[j]);
-                    vs[j] = fma_t(h, dk[j], dx[j]);
-                }
-                ext<T, Q>(ys, Y);
-                ext<T, Q>(vs, V);
-                tl_stage<T, Q, true>(Y, V, k, dk);
-#pragma unroll
-                for (int j = 0; j < Q; j++) {
-                    acc[j] = fma_t(T(2), dk[j], acc[j]);
-                    ys[j] = fma_t(dt, k[j], x[j] + hF);  // x + dt F
-                    vs[j] = fma_t(dt, dk[j], dx[j]);
-                }
-                ext<T, Q>(ys, Y);
-                ext<T, Q>(vs, V);
-                tl_stage<T, Q, false>(Y, V, k, dk);
-#pragma unroll
-                for (int j = 0; j < Q; j++) dx[j] = fma_t(dt6, acc[j] + dk[j], dx[j]);
-                if constexpr (EARLY) store_part<(Q <= 7 ? 0 : Q / 2), Q, Q>(xw, nxt);
+                tl_step<T, Q, EARLY>(K, xw, trajm + (long long)min(s + 1, N - 1) * a.ext_len + w0, s + 1 < N, dx);
             }
             if (s1 < N) {
 #pragma unroll
@@ -456,79 +545,13 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
         for (int s = s_hi; s > s_lo; s--) {
             if (s % a.obs_dt == 0) {
                 const double *f = force + (long long)(s / a.obs_dt - 1) * a.nv;
-#pragma unroll
+            #pragma unroll
                 for (int q = 0; q < Q; q++) {
                     const int oi = qi[q * 64 + lane];
                     if (oi >= 0) lam[q] += (T)f[oi];
                 }
             }
-            T x[Q], Y2[Q + 4], Y3[Q + 4], Y4[Q + 4], M[Q + 4], k[Q], ys[Q];
-            read_window<T, Q>(xw, x);  // X[s - 1]
-            // next step's window (X[s - 2]), split as in the TL run
-            const double *xn = trajm + (long long)max(s - 2, 0) * a.ext_len + w0;
-            double nxt[Q];
-            if constexpr (!EARLY) {
-                if (s >= 2) prefetch_window<Q>(xn, xw);
-            } else if constexpr (Q <= 7) {
-                load_part<0, Q, Q>(xn, nxt);
-            } else {
-                load_part<0, Q / 2, Q>(xn, nxt);
-            }
-            {
-                T Y1[Q + 4];
-                ext<T, Q>(x, Y1);
-                tendency<T, Q>(Y1, k);
-            }
-            // stage states x + h (k' + F) and x + dt (k' + F), from xh = x + h F
-#pragma unroll
-            for (int j = 0; j < Q; j++) ys[j] = fma_t(h, k[j], x[j] + hF);
-            ext<T, Q>(ys, Y2);
-            tendency<T, Q>(Y2, k);
-#pragma unroll
-            for (int j = 0; j < Q; j++) ys[j] = fma_t(h, k[j], x[j] + hF);
-            ext<T, Q>(ys, Y3);
-            tendency<T, Q>(Y3, k);
-#pragma unroll
-            for (int j = 0; j < Q; j++) ys[j] = fma_t(dt, k[j], (x[j] + hF) + hF);
-            ext<T, Q>(ys, Y4);
-            // backward through the stages: mu4 = dt/6 lam, mu3 = mu2 = dt/3 lam, mu1 = dt/6 lam
-            T nu[Q], acc[Q], mu[Q];
-#pragma unroll
-            for (int j = 0; j < Q; j++) mu[j] = dt6 * lam[j];
-            ext<T, Q>(mu, M);
-            jt<T, Q>(Y4, M, nu);
-            if constexpr (EARLY && Q > 7) {
-                store_part<0, Q / 2, Q>(xw, nxt);
-                load_part<Q / 2, Q, Q>(xn, nxt);
-            }
-#pragma unroll
-            for (int j = 0; j < Q; j++) {
-                acc[j] = lam[j] + nu[j];
-                mu[j] = dt3 * lam[j] + dt * nu[j];
-            }
-            ext<T, Q>(mu, M);
-            jt<T, Q>(Y3, M, nu);
-#pragma unroll
-            for (int j = 0; j < Q; j++) {
-                acc[j] += nu[j];
-                mu[j] = dt3 * lam[j] + h * nu[j];
-            }
-            ext<T, Q>(mu, M);
-            jt<T, Q>(Y2, M, nu);
-#pragma unroll
-            for (int j = 0; j < Q; j++) {
-                acc[j] += nu[j];
-                mu[j] = dt6 * lam[j] + h * nu[j];
-            }
-            ext<T, Q>(mu, M);
-            {
-                T Y1[Q + 4];
-                ext<T, Q>(x, Y1);
-                jt<T, Q>(Y1, M, nu);
-            }
-#pragma unroll
-            for (int j = 0; j < Q; j++) lam[j] = acc[j] + nu[j];
-            if constexpr (EARLY) store_part<(Q <= 7 ? 0 : Q / 2), Q, Q>(xw, nxt);
+            ad_step<T, Q, EARLY>(K, xw, trajm + (long long)max(s - 2, 0) * a.ext_len + w0, s >= 2, lam);
         }
         if (s_lo > 0) {
 #pragma unroll
@@ -887,6 +910,301 @@ __global__ __launch_bounds__(512) void k_hv_multi(const TladArgs *__restrict__ p
     tlad_column<double, Q, TLAD_HV>(probs[t.prob], g, t.col, 0, 0, smraw);
 }
 
+
+// ---------------- wave pieces with halo exchange ----------------
+// Every wave owns segment [lo, hi) of one column and runs its TL/AD windows
+// alone (no workgroup barrier after the start).  At each exchange it publishes
+// the first and last E of its owned values, stores them behind a completed
+// vector-memory wait, raises its flag to the phase number, waits for both
+// neighbours' flags and reads their edges into its window halos.  The reads
+// bypass the CU's L1 (device-scope loads): the same addresses carry new values
+// every other phase.  Edges are double-buffered by phase parity: a wave
+// rewrites a parity only after it has read the neighbours' next phase, which
+// they publish after reading this one.
+
+// XCC_ID hardware register (id 20, bits 3:0): the XCD a wave runs on.
+__device__ __forceinline__ int xcc_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11)); }
+
+__device__ __forceinline__ double load_dev(const double *p) {
+    return __longlong_as_double((long long)__hip_atomic_load(reinterpret_cast<const unsigned long long *>(p),
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Banded circulant product from a slice: out[q] = sum_m taps[m] us[l Q + q + m]
+// for this lane l (us: 64 Q + W - 1 values); a circular register buffer of Q
+// values keeps one LDS read per tap, the taps in ascending order.
+template <int Q>
+__device__ __forceinline__ void band_slice(const double *us, const double *taps, int W, double (&out)[Q]) {
+    const double *u = us + (threadIdx.x & 63) * Q;
+    double B[Q];
+#pragma unroll
+    for (int j = 0; j < Q; j++) B[j] = u[j];
+#pragma unroll
+    for (int q = 0; q < Q; q++) out[q] = 0.0;
+    int m0 = 0;
+    for (; m0 + Q <= W; m0 += Q) {
+#pragma unroll
+        for (int mm = 0; mm < Q; mm++) {
+            const double t = taps[m0 + mm];
+#pragma unroll
+            for (int q = 0; q < Q; q++) out[q] += t * B[(mm + q) % Q];
+            B[mm] = u[m0 + mm + Q];
+        }
+    }
+#pragma unroll
+    for (int mm = 0; mm < Q - 1; mm++) {
+        if (m0 + mm < W) {
+            const double t = taps[m0 + mm];
+#pragma unroll
+            for (int q = 0; q < Q; q++) out[q] += t * (mm + q < Q ? B[mm + q] : u[m0 + mm + q]);
+        }
+    }
+}
+
+// Waits (bounded) until both flags reach `want`.
+__device__ __forceinline__ bool xch_wait(const unsigned long long *fa, const unsigned long long *fb,
+                                         unsigned long long want, long long spin_max) {
+    for (long long it = 0; it < spin_max; it++) {
+        const unsigned long long va = __hip_atomic_load(fa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long vb = __hip_atomic_load(fb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (va >= want && vb >= want) return true;
+    }
+    return false;
+}
+
+// Raises this slot's flag to phase `ph` after the wave's earlier stores
+// completed, then waits for the neighbours' flags to reach it.  A wait that
+// gives up sets the error word and the wave's `failed`, after which the wave
+// no longer waits (its results are void; the host reports the error).
+__device__ __forceinline__ void xch_sync(const XchArgs &xa, int slot, const XSlot &sl, int ph, bool &failed) {
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    const unsigned long long want = xa.epoch + (unsigned long long)ph + 1ull;
+    if ((threadIdx.x & 63) == 0) __hip_atomic_store(xa.flags + slot, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (failed) return;
+    if (!xch_wait(xa.flags + sl.left, xa.flags + sl.right, want, xa.spin_max)) {
+        failed = true;
+        if ((threadIdx.x & 63) == 0) __hip_atomic_store(xa.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Edge exchange of window values v (window position j = l Q + q, owned index
+// j - hl in [0, seg)): publish, sync, and fill the halo positions from the
+// neighbours' edges (left: its last E values; right: its first E, zeros beyond).
+template <int Q>
+__device__ __forceinline__ void xch_edges(const XchArgs &xa, int slot, const XSlot &sl, int seg, int hl, int ph,
+                                          bool &failed, double (&v)[Q]) {
+    const int lane = threadIdx.x & 63, E = xa.E;
+    const long long par = ph & 1;
+    double *mine = xa.edges + ((long long)slot * 2 + par) * 2 * E;
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        const int o = lane * Q + q - hl;
+        if (o >= 0 && o < E) mine[o] = v[q];
+        if (o >= seg - E && o < seg) mine[E + o - (seg - E)] = v[q];
+    }
+    xch_sync(xa, slot, sl, ph, failed);
+    const double *le = xa.edges + ((long long)sl.left * 2 + par) * 2 * E + E;
+    const double *re = xa.edges + ((long long)sl.right * 2 + par) * 2 * E;
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        const int o = lane * Q + q - hl;
+        if (o < 0) v[q] = load_dev(le + E + o);
+        else if (o >= seg) v[q] = o - seg < E ? load_dev(re + (o - seg)) : 0.0;
+    }
+}
+
+// The Hessian part of PCG iteration a.pcg.it on the wave's segment (what
+// TLAD_SPLIT computes on a ring piece): r^T z from the row-block partials, p =
+// z + beta p (new p written for the owned states), V = U_B p over the TL
+// window, TL, AD, U_B lambda_0 + p at the owned states into q and the
+// segment's part of p^T (I + A) p.
+template <int Q>
+__global__ __launch_bounds__(512) void k_tlad_x(TladArgs a, XchArgs xa, SplitCols sc) {
+    extern __shared__ __align__(16) unsigned char smraw[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n = a.n, N = a.N, tb = xa.tb;
+    const int W = a.band_hi - a.band_lo + 1;
+    const int UL = 64 * Q + W - 1;
+    // LDS (xch_lds_doubles): taps (W, rounded up to even), then per wave: the
+    // trajectory window (64 Q), the U_B slice (UL + Q, rounded up to even: the
+    // product's register buffer reads up to Q - 1 values past the slice) and
+    // the observation indices (64 Q ints)
+    double *taps = reinterpret_cast<double *>(smraw);
+    const int per_wave = 64 * Q + ((UL + Q + 1) & ~1) + 32 * Q;  // in doubles
+    double *xw = taps + ((W + 1) & ~1) + (long long)wave * per_wave;
+    double *u = xw + 64 * Q;
+    int *qi = reinterpret_cast<int *>(u + ((UL + Q + 1) & ~1));
+    for (int m = threadIdx.x; m < W; m += blockDim.x) {
+        const int o = a.band_hi - m;
+        taps[m] = a.ubrow[o < 0 ? -o : o];
+    }
+    // Workgroups are dealt to the XCDs in turn from a starting XCD that varies
+    // between launches: the workgroup takes the virtual index whose low three
+    // bits are its XCD (a permutation of the launch's indices under that
+    // dealing) and claims it for this launch; a second claim of one index means
+    // another placement, reported (its neighbours' waits then give up).
+    __shared__ int s_vb;
+    if (threadIdx.x == 0) {
+        const int vb = (int)(blockIdx.x & ~7u) | (xcc_id() & 7);
+        const unsigned long long prev =
+            __hip_atomic_exchange(xa.claim + vb, xa.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == xa.epoch) __hip_atomic_store(xa.err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_vb = vb;
+    }
+    __syncthreads();  // the last workgroup barrier: the waves are independent from here on
+
+    const int slot = s_vb * 8 + wave;
+    const int m = sc.count > 0 ? sc.count : a.nb;
+    const XSlot sl = xch_slot(slot, m, xa.grid, xa.max_seg);
+    if (sl.li < 0) return;
+    const int c = sc.count > 0 ? sc.col[sl.li] : sl.li;
+    if (a.pcg.status[c] != COL_RUNNING) return;
+    const int lo = (int)((long long)sl.seg * n / sl.nseg), hi = (int)((long long)(sl.seg + 1) * n / sl.nseg);
+    const int seg = hi - lo;
+    const long long cn = (long long)c * n;
+    const int first = a.pcg.first;
+
+    // r^T z: the row blocks' partial sums in block order
+    double rz = 0.0;
+    {
+        double v[LMP_RB_MAX];
+#pragma unroll
+        for (int b = 0; b < LMP_RB_MAX; b++) v[b] = b < xa.nrb ? xa.rz_part[(long long)b * xa.rz_ld + c] : 0.0;
+#pragma unroll
+        for (int b = 0; b < LMP_RB_MAX; b++) rz += v[b];
+    }
+    double beta = 0.0;
+    if (!first) {
+        if (!(rz > 0.0) || !isfinite(rz)) {
+            if (lane == 0 && sl.seg == 0) a.pcg.status[c] = EDA_MEMBER_BREAKDOWN;
+            return;
+        }
+        beta = rz / a.pcg.scal[4 * c];
+    }
+    if (lane == 0 && sl.seg == 0) {
+        a.pcg.scal[4 * c + 3] = rz;  // rho of this iteration, for the update
+        xa.nseg[c] = sl.nseg;
+    }
+
+    // p over the U_B slice of the TL window (slice j: state w0 - band_hi + j)
+    const int hl_tl = 8 * tb, hl_ad = 4 * tb + 8;
+    const int w0 = lo - hl_tl;
+    const double *z = a.pcg.z + cn, *pold = a.pcg.p + cn;
+    double *pout = a.pcg.p_out + cn;
+    for (int j = lane; j < UL; j += 64) {
+        int st = (w0 - a.band_hi + j) % n;
+        st = st < 0 ? st + n : st;
+        const double v = first ? z[st] : z[st] + beta * pold[st];
+        u[j] = v;
+        const int o = j - a.band_hi - hl_tl;
+        if (o >= 0 && o < seg) pout[st] = v;
+    }
+    __asm__ volatile("" ::: "memory");
+    const double *trajm = a.trajx + (long long)a.pcg.members[c] * a.trajx_stride + a.pad_l;
+    const StepK<double> K{a.h, a.dt, a.dt6, a.dt3, a.h * a.F};
+    unsigned ownm;
+    int ph = 0;
+    bool failed = false;
+
+    // ---------------- TL forward run ----------------
+    prefetch_window<Q>(trajm + w0, xw);
+    window<Q>(a, w0, lo, hi, true, ownm, qi, n, 0);
+    double dx[Q];
+    band_slice<Q>(u, taps, W, dx);
+    double *obs = a.obs + (long long)c * a.nt * a.nv;
+    for (int s0 = 0; s0 < N; s0 += tb) {
+        if (s0 > 0) xch_edges<Q>(xa, slot, sl, seg, hl_tl, ph++, failed, dx);
+        const int s1 = min(N, s0 + tb);
+        for (int s = s0; s < s1; s++) {
+            if (s > 0 && s % a.obs_dt == 0)
+                store_obs<double, Q>(obs + (long long)(s / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
+            tl_step<double, Q, true>(K, xw, trajm + (long long)min(s + 1, N - 1) * a.ext_len + w0, s + 1 < N, dx);
+        }
+    }
+    if (N % a.obs_dt == 0) store_obs<double, Q>(obs + (long long)(N / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
+    // the neighbours' observed increments are complete
+    xch_sync(xa, slot, sl, ph++, failed);
+
+    // ---------------- AD backward run ----------------
+    const int w0a = lo - hl_ad;
+    prefetch_window<Q>(trajm + (long long)(N - 1) * a.ext_len + w0a, xw);
+    window<Q>(a, w0a, lo, hi, false, ownm, qi, n, 0);
+    {
+        // forcing only where it can reach the owned outputs (the AD cone and the
+        // stage states' reach): the immediate neighbours' owned points
+        const int jmax = hl_ad + seg + 8 * tb + 8;
+#pragma unroll
+        for (int q = 0; q < Q; q++)
+            if (lane * Q + q >= jmax) qi[q * 64 + lane] = -1;
+    }
+    double lam[Q];
+#pragma unroll
+    for (int q = 0; q < Q; q++) lam[q] = 0.0;
+    for (int s_hi = N; s_hi >= 1; s_hi -= tb) {
+        if (s_hi < N) xch_edges<Q>(xa, slot, sl, seg, hl_ad, ph++, failed, lam);
+        const int s_lo = max(0, s_hi - tb);
+        for (int s = s_hi; s > s_lo; s--) {
+            if (s % a.obs_dt == 0) {
+                const double *f = obs + (long long)(s / a.obs_dt - 1) * a.nv;
+#pragma unroll
+                for (int q = 0; q < Q; q++) {
+                    const int oi = qi[q * 64 + lane];
+                    if (oi >= 0) lam[q] += load_dev(f + oi);
+                }
+            }
+            ad_step<double, Q, true>(K, xw, trajm + (long long)max(s - 2, 0) * a.ext_len + w0a, s >= 2, lam);
+        }
+    }
+
+    // ---------------- U_B on the way out: slice j = state w0a - band_hi + j ----------------
+    {
+        const int E = xa.E;
+        const long long par = ph & 1;
+        double *mine = xa.edges + ((long long)slot * 2 + par) * 2 * E;
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+            const int o = lane * Q + q - hl_ad;
+            if (o >= 0 && o < E) mine[o] = lam[q];
+            if (o >= seg - E && o < seg) mine[E + o - (seg - E)] = lam[q];
+            if (o >= 0 && o < seg) u[lane * Q + q + a.band_hi] = lam[q];
+        }
+        xch_sync(xa, slot, sl, ph++, failed);
+        const double *le = xa.edges + ((long long)sl.left * 2 + par) * 2 * E + E;
+        const double *re = xa.edges + ((long long)sl.right * 2 + par) * 2 * E;
+        for (int t = lane; t < a.band_hi; t += 64) {
+            u[hl_ad + t] = load_dev(le + E - a.band_hi + t);
+            u[hl_ad + a.band_hi + seg + t] = load_dev(re + t);
+        }
+    }
+    __asm__ volatile("" ::: "memory");
+    double y[Q];
+    band_slice<Q>(u, taps, W, y);
+    double pq = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        const int o = lane * Q + q - hl_ad;
+        if (o >= 0 && o < seg) {
+            int st = lo + o;
+            st = st >= n ? st - n : st;
+            const double pv = first ? z[st] : z[st] + beta * pold[st];
+            const double yq = y[q] + pv;
+            pq += pv * yq;
+            a.pcg.q[cn + st] = yq;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) pq += __shfl_down(pq, off, 64);
+    if (lane == 0) {
+        a.pcg.pq_part[(long long)c * XCH_SEG_MAX + sl.seg] = pq;
+        if (failed) a.pcg.status[c] = EDA_MEMBER_BREAKDOWN;  // void results: the member stops
+    }
+}
+
+template <int Q>
+hipError_t launch_x_q(hipStream_t s, const TladArgs &a, const XchArgs &x, const SplitCols &sc, size_t lds) {
+    hipLaunchKernelGGL(k_tlad_x<Q>, dim3(x.grid), dim3(512), lds, s, a, x, sc);
+    return hipGetLastError();
+}
+
 template <typename T, int Q>
 size_t lds_bytes(const TladArgs &a, const TladGeom &g, int mode) {
     const size_t R = (mode == TLAD_SPLIT || mode == TLAD_SPLIT_HV) ? (size_t)a.ring : (size_t)a.n;
@@ -1080,6 +1398,89 @@ void tlad_pads_split(int n, int N, int band_hi, int *pad_l, int *pad_r) {
     }
     *pad_l = pl;
     *pad_r = pr;
+}
+
+// Dynamic LDS of k_tlad_x (see its layout), at least XCH_LDS_MIN so that one
+// workgroup takes a CU.
+static size_t xch_lds_bytes(int Q, int W) {
+    const size_t UL = 64 * (size_t)Q + W - 1;
+    const size_t per_wave = 64 * (size_t)Q + ((UL + Q + 1) & ~(size_t)1) + 32 * (size_t)Q;
+    const size_t b = sizeof(double) * ((((size_t)W + 1) & ~(size_t)1) + 8 * per_wave);
+    return b > XCH_LDS_MIN ? b : XCH_LDS_MIN;
+}
+
+XchPlan xch_plan(int n, int N, int band_hi, int m, int grid, int pad_l, int pad_r) {
+    XchPlan P{};
+    grid = (grid > XCH_GRID_MAX ? XCH_GRID_MAX : grid) & ~7;
+    if (m < 1 || grid < 8 || N < 1) return P;
+    for (int cap = XCH_SEG_MAX; cap >= 2; cap--) {
+        int nmin = 1 << 30, nmax = 0;
+        for (int x = 0; x < 8; x++) {
+            const int slots = ((grid - x + 7) / 8) * 8;
+            const int cols = m > x ? (m - x + 7) / 8 : 0;
+            if (cols == 0) continue;
+            int base = slots / cols, extra = slots - base * cols;
+            if (base >= cap) {
+                base = cap;
+                extra = 0;
+            }
+            if (base < nmin) nmin = base;
+            const int hi = extra > 0 ? base + 1 : base;
+            if (hi > nmax) nmax = hi;
+        }
+        if (nmin < 2) return P;  // more columns than the slots can take in pairs
+        const int seg_max = (n + nmin - 1) / nmin, seg_min = n / nmax;
+        if (64 * 8 < seg_max + 12 + 16) return P;  // longer segments only with fewer segments per column
+        // points per lane: a wider window allows longer time blocks (fewer
+        // exchanges) at more work per step; estimated cycles of one launch:
+        // N steps of about 66 Q + 136 VALU instructions (TL + AD, two waves
+        // per SIMD at 4 cycles each) and about 2800 cycles per exchange
+        long long best = -1;
+        for (int Q = 2; Q <= 8; Q++) {
+            if (64 * Q < seg_max + 12 + 16) continue;
+            int tb = (64 * Q - seg_max - 16) / 12;
+            if (tb > XCH_TB_MAX) tb = XCH_TB_MAX;
+            if (tb > N) tb = N;
+            while (tb > 1 && 8 * tb + 8 > seg_min) tb--;
+            const int E = 8 * tb + 8 > band_hi ? 8 * tb + 8 : band_hi;
+            if (E > XCH_E_MAX || seg_min < E) continue;
+            // windows inside the padded rows: TL from lo - 8 tb, AD from lo - 4 tb - 8, 64 Q long
+            const int hl_ad = 4 * tb + 8;
+            const int reach_r = 64 * Q - (8 * tb < hl_ad ? 8 * tb : hl_ad) - seg_min;
+            if (8 * tb > pad_l || hl_ad > pad_l || reach_r > pad_r) continue;
+            const long long est = (long long)N * (66 * Q + 136) * 8 + (2LL * ((N + tb - 1) / tb) + 2) * 2800;
+            if (best < 0 || est < best) {
+                best = est;
+                P.ok = 1;
+                P.q = Q;
+                P.tb = tb;
+                P.E = E;
+                P.max_seg = cap;
+                P.grid = grid;
+            }
+        }
+        if (P.ok) return P;  // else segments too short for the edges: fewer of them
+    }
+    return P;
+}
+
+hipError_t launch_tlad_x(hipStream_t s, const TladArgs &a, const XchArgs &x, const XchPlan &pl, const SplitCols &sc) {
+    const int W = a.band_hi - a.band_lo + 1;
+    if (!pl.ok || x.grid != pl.grid || x.tb != pl.tb || x.E != pl.E || x.max_seg != pl.max_seg ||
+        W != 2 * a.band_hi + 1 || a.band_hi > x.E || sc.count < 0 || sc.count > SPLIT_LIST_MAX)
+        return hipErrorInvalidValue;
+    const size_t lds = xch_lds_bytes(pl.q, W);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    switch (pl.q) {
+        case 2: return launch_x_q<2>(s, a, x, sc, lds);
+        case 3: return launch_x_q<3>(s, a, x, sc, lds);
+        case 4: return launch_x_q<4>(s, a, x, sc, lds);
+        case 5: return launch_x_q<5>(s, a, x, sc, lds);
+        case 6: return launch_x_q<6>(s, a, x, sc, lds);
+        case 7: return launch_x_q<7>(s, a, x, sc, lds);
+        case 8: return launch_x_q<8>(s, a, x, sc, lds);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32, int waves, int tb,

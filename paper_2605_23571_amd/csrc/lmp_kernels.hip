@@ -49,14 +49,27 @@ __device__ __forceinline__ bool tile_running(const int32_t *status, int c0, int 
 }
 
 // p^T (I + A) p of column col: the pieces' partial sums in piece order, all
-// loaded before the sum
+// loaded before the sum (wave pieces: nseg[col] segments, eight loads at a time)
 __device__ __forceinline__ double pieces_sum(const LmpFin &f, int col) {
-    double v[SPLIT_PMAX];
+    if (f.pieces > 0) {
+        double v[SPLIT_PMAX];
 #pragma unroll
-    for (int i = 0; i < SPLIT_PMAX; i++) v[i] = i < f.pieces ? f.pq_part[(long long)col * f.pieces + i] : 0.0;
+        for (int i = 0; i < SPLIT_PMAX; i++) v[i] = i < f.pieces ? f.pq_part[(long long)col * f.pieces + i] : 0.0;
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < SPLIT_PMAX; i++) s += v[i];
+        return s;
+    }
+    const int ns = min(max(f.nseg[col], 0), XCH_SEG_MAX);
+    const double *pp = f.pq_part + (long long)col * XCH_SEG_MAX;
     double s = 0.0;
+    for (int i0 = 0; i0 < ns; i0 += 8) {
+        double v[8];
 #pragma unroll
-    for (int i = 0; i < SPLIT_PMAX; i++) s += v[i];
+        for (int i = 0; i < 8; i++) v[i] = i0 + i < ns ? pp[i0 + i] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; i++) s += v[i];
+    }
     return s;
 }
 
@@ -225,9 +238,11 @@ template <int KM, bool FIN>
 __global__ __launch_bounds__(512) void k_lmp_expand(int n, int k, int nb, int nrb, const double *__restrict__ S,
                                                     const double *__restrict__ coef, const double *X, long long ldx,
                                                     double *Y, long long ldy, int32_t *status,
-                                                    const double *__restrict__ part, int ldw, LmpFin f) {
+                                                    const double *__restrict__ part, int ldw, LmpFin f,
+                                                    double *__restrict__ rz) {
     constexpr int PE = KM * CT / 512;  // W entries per thread
     __shared__ double ws[KM][CT];
+    __shared__ double rzs[8][CT];
     const int c0 = blockIdx.y * CT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, m = lane & 15;
     const int ib = blockIdx.x * 256 + wave * 32;
@@ -312,6 +327,28 @@ __global__ __launch_bounds__(512) void k_lmp_expand(int n, int k, int nb, int nr
             }
         }
     }
+    if (rz && run) {
+        // r^T z of the block's 256 rows per column: this lane's two rows, the
+        // 16 lanes of its row group (xor tree), then the waves in order
+        double t[4];
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            t[v] = xv[0][v] * (xv[0][v] + acc[0][v]) + xv[1][v] * (xv[1][v] + acc[1][v]);
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) t[v] += __shfl_xor(t[v], o, 16);
+        }
+        if (m == 0) {
+#pragma unroll
+            for (int v = 0; v < 4; v++) rzs[wave][g + 4 * v] = t[v];
+        }
+        __syncthreads();
+        if (tid < CT && c0 + tid < nb) {
+            double sum = 0.0;
+#pragma unroll
+            for (int w = 0; w < 8; w++) sum += rzs[w][tid];
+            rz[(long long)blockIdx.x * ldw + c0 + tid] = sum;
+        }
+    }
     if (FIN && fin_lane && fst == COL_RUNNING) {
         // the iteration's end for column fcol, as in the fused PCG kernel
         if (!(fpq > 0.0) || !isfinite(fpq)) {
@@ -363,7 +400,7 @@ namespace {
 template <bool FIN>
 hipError_t lmp_launch(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
                       double *X, long long ldx, double *Y, long long ldy, int32_t *status, double *work,
-                      const LmpFin &f) {
+                      const LmpFin &f, double *rz) {
     if (n <= 0 || nb <= 0) return hipSuccess;
     if (k <= 0 || k > LMP_K_MAX) return hipErrorInvalidValue;
     int rows, nrb;
@@ -376,20 +413,20 @@ hipError_t lmp_launch(hipStream_t s, int n, int k, int nb, const double *S, cons
     if (e != hipSuccess) return e;
     if (k <= 64)
         hipLaunchKernelGGL((k_lmp_expand<64, FIN>), dim3((n + 255) / 256, tiles), dim3(512), 0, s, n, k, nb, nrb, S,
-                           coef, X, ldx, Y, ldy, status, work, ldw, f);
+                           coef, X, ldx, Y, ldy, status, work, ldw, f, rz);
     else
         hipLaunchKernelGGL((k_lmp_expand<LMP_K_MAX, FIN>), dim3((n + 255) / 256, tiles), dim3(512), 0, s, n, k, nb,
-                           nrb, S, coef, X, ldx, Y, ldy, status, work, ldw, f);
+                           nrb, S, coef, X, ldx, Y, ldy, status, work, ldw, f, rz);
     return hipGetLastError();
 }
 }  // namespace
 
 hipError_t launch_lmp(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
                       const double *X, long long ldx, double *Y, long long ldy, const int32_t *status,
-                      double *work) {
+                      double *work, double *rz) {
     // the plain form only reads X and status
     return lmp_launch<false>(s, n, k, nb, S, Sr, coef, const_cast<double *>(X), ldx, Y, ldy,
-                             const_cast<int32_t *>(status), work, LmpFin{});
+                             const_cast<int32_t *>(status), work, LmpFin{}, rz);
 }
 
 // Device address of `scratch` on the current device, looked up once per device
@@ -414,9 +451,9 @@ hipError_t lmp_noalloc_scratch(double **out) {
 }
 
 hipError_t launch_lmp_fin(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
-                          double *r, double *z, int32_t *status, double *work, const LmpFin &f) {
-    if (!status || f.pieces < 1) return hipErrorInvalidValue;
-    return lmp_launch<true>(s, n, k, nb, S, Sr, coef, r, n, z, n, status, work, f);
+                          double *r, double *z, int32_t *status, double *work, const LmpFin &f, double *rz) {
+    if (!status || f.pieces < 0 || (f.pieces == 0 && !f.nseg)) return hipErrorInvalidValue;
+    return lmp_launch<true>(s, n, k, nb, S, Sr, coef, r, n, z, n, status, work, f, rz);
 }
 
 }  // namespace eda

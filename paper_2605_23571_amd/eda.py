@@ -26,6 +26,7 @@ EDA_ERR_HIP = -3
 EDA_ERR_NOT_SPD = -4
 EDA_ERR_ORDER = -5
 EDA_ERR_UNSUPPORTED = -6
+EDA_ERR_SYNC = -7
 EDA_WARN_NOT_CONVERGED = 1
 EDA_MEMBER_CONVERGED, EDA_MEMBER_NOT_CONVERGED, EDA_MEMBER_BREAKDOWN = 0, 1, 2
 EDA_UB_DENSE, EDA_UB_BANDED = 0, 1
@@ -35,6 +36,7 @@ EDA_SKETCH_RHS_DIFF, EDA_SKETCH_USER, EDA_SKETCH_B_PSI, EDA_SKETCH_UBT_PSI = 0, 
 EDA_METHOD_NYSTROM, EDA_METHOD_REVD = 0, 1
 EDA_THETA_MID, EDA_THETA_LAMK, EDA_THETA_ONE = 0, 1, 2
 EDA_LMP_P, EDA_LMP_U = 0, 1
+EDA_XCH_OFF, EDA_XCH_ON = 0, 1
 EDA_LMP_NOALLOC_SCRATCH_BYTES = 4194304
 FIELDS = dict(truth=0, xb=1, traj=2, y=3, d=4, b=5, costc=6, ubrow=7, S=8, eig=9)
 THETA_RULES = {"mid": EDA_THETA_MID, "lamk": EDA_THETA_LAMK, "one": EDA_THETA_ONE}
@@ -84,6 +86,7 @@ def lib():
             "eda_destroy": [vp],
             "eda_set_geometry": [vp, i32, i32],
             "eda_set_split": [vp, i32],
+            "eda_set_exchange": [vp, i32, i64],
             "eda_mlp_param_count": [vp, ctypes.POINTER(i64)],
             "eda_mlp_workspace_bytes": [vp, i32, ctypes.POINTER(sz)],
             "eda_mlp_init": [vp, vp, vp, vp],
@@ -260,6 +263,10 @@ def eda_profile_read(ctx):
 
 def eda_set_geometry(ctx, waves: int, tb: int):
     _check("eda_set_geometry", lib().eda_set_geometry(ctx, int(waves), int(tb)))
+
+
+def eda_set_exchange(ctx, mode: int, spin_limit: int = -1):
+    _check("eda_set_exchange", lib().eda_set_exchange(ctx, int(mode), int(spin_limit)))
 
 
 def eda_set_split(ctx, pieces: int):

@@ -467,6 +467,82 @@ def test_split_iterations_match_whole_columns(case):
 
 
 @pytest.mark.parametrize("case", ["n1001", "n2049"])
+def test_exchange_iterations_match_whole_columns(case):
+    # Wave pieces with halo exchange (eda_set_exchange ON, n >= 512) against
+    # whole columns: only the summation order of r^T z and p^T (I + A) p
+    # differs, so after 4 iterations the iterates agree to rounding; solved to
+    # rtol 1e-10 they reach the exact solution; repeated solves are bit-identical.
+    cfg, g, o = problem(case)
+    g.sketch_evd("rhs_diff")
+    members = np.arange(cfg["members"] + 1)
+    eda.eda_set_split(g.ctx, 1)
+    ref = g.pcg(members, rtol=0.0, maxit=4)["dz"].cpu().numpy()
+    eda.eda_set_split(g.ctx, 0)
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_ON)
+    dz = g.pcg(members, rtol=0.0, maxit=4)["dz"].cpu().numpy()
+    e4 = rel(dz, ref)
+    out = g.pcg(members, rtol=1e-10, maxit=500, history=True)
+    assert np.all(out["status"] == eda.EDA_MEMBER_CONVERGED), out["status"]
+    errs = []
+    for m in (0, cfg["members"]):
+        xe = O.exact_solution(o, m)
+        errs.append(elrel(out["dz"][m].cpu().numpy(), xe))
+        h = out["hist"][m][: out["iters"][m] + 1]
+        assert np.all(np.diff(h) <= 1e-10 * abs(h[-1]))  # the cost decreases
+    again = g.pcg(members, rtol=1e-10, maxit=500)
+    print(f"[xch] {case}: 4 iterations vs whole columns {e4:.1e}; rtol 1e-10 in {out['iters'].tolist()} "
+          f"iterations, element-wise error vs exact {max(errs):.1e}", flush=True)
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OFF)
+    assert e4 < 1e-12 and max(errs) < 1e-8
+    assert torch.equal(out["dz"], again["dz"])
+
+
+def test_exchange_after_a_multi_stream_batch():
+    # A batch solve (work on many streams) leaves the dealing of workgroups to
+    # XCDs starting elsewhere; the exchange form then still pairs neighbours on
+    # one XCD (virtual workgroup indices) and solves correctly.
+    cfgs = [W.config("C2", n=1024, nsteps=10, members=12, ell=8, k=8, problem_id=41, spinup=200),
+            W.config("C2", n=512, nsteps=20, members=9, ell=6, k=6, problem_id=42, spinup=200)]
+    probs = [eda.Problem(c, W.problem_normals(c)) for c in cfgs]
+    bt = eda.Batch(probs)
+    bt.solve(k_cap=8, rtol=1e-8, maxit=500)
+    bt.close()
+    for c, g in zip(cfgs, probs):
+        g.sketch_evd("rhs_diff")
+        members = np.arange(c["members"] + 1)
+        eda.eda_set_exchange(g.ctx, eda.EDA_XCH_ON)
+        out = g.pcg(members, rtol=1e-10, maxit=500)
+        assert np.all(out["status"] == eda.EDA_MEMBER_CONVERGED)
+        eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OFF)
+        ref = g.pcg(members, rtol=1e-10, maxit=500)
+        e = rel(out["dz"].cpu().numpy(), ref["dz"].cpu().numpy())
+        print(f"[xch] after a batch, n={c['n']}: exchange vs ring pieces {e:.1e}", flush=True)
+        assert e < 1e-8
+        g.close()
+
+
+def test_exchange_wait_limit_reports_sync_error():
+    # Every wait of the exchange form gives up at once (limit 0, set from the
+    # host): the members stop with a breakdown and the solve reports
+    # EDA_ERR_SYNC; every kernel still runs to its end.  With the default limit
+    # the same context solves normally again.
+    cfg, g, o = problem("n1001")
+    g.sketch_evd("rhs_diff")
+    members = np.arange(cfg["members"] + 1)
+    eda.eda_set_split(g.ctx, 0)
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_ON, 0)
+    with pytest.raises(eda.EdaError) as ei:
+        g.pcg(members, rtol=1e-10, maxit=50)
+    assert ei.value.code == eda.EDA_ERR_SYNC
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_ON, -1)
+    out = g.pcg(members, rtol=1e-10, maxit=500)
+    assert np.all(out["status"] == eda.EDA_MEMBER_CONVERGED)
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OFF)
+    off = g.pcg(members, rtol=1e-10, maxit=500)
+    assert rel(off["dz"].cpu().numpy(), out["dz"].cpu().numpy()) < 1e-8
+
+
+@pytest.mark.parametrize("case", ["n1001", "n2049"])
 def test_split_hessvec_matches_whole_columns(case):
     # Hessian products on P pieces per column (ring of the piece's states with
     # halos of 12 N + 2 w): every owned output is the whole column's, bit for
