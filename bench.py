@@ -387,45 +387,112 @@ def run_learned(count):
     return rep
 
 
-def _cpu_sample(O, P, cfg, target_s):
-    """Gamma-Nystrom sketch once, then LMP-PCG for members 0, 1, ... until about
-    target_s seconds; returns (solves/s with the sketch amortised over all L + 1
-    members, members solved, seconds of work, (S, D, theta, solutions))."""
-    L = cfg["members"]
+# ---------------------------------------------------------------- CPU oracle --
+# The oracle is timed as it stands on the host cores: one member's PCG per
+# worker process (numpy's BLAS at one thread each), members solved concurrently,
+# the sketch once per problem on one core and amortised over its members.
+_CPU = {}
+
+
+def _cpu_member(m):
+    from oracle import oracle as O
+    P, cfg, S, D, th = _CPU["P"], _CPU["cfg"], _CPU["S"], _CPU["D"], _CPU["th"]
+    pre = (lambda v: O.lmp_apply(S, D, th, v[:, None])[:, 0]) if S is not None else None
     t0 = time.perf_counter()
-    S, D, _ = O.nystrom(lambda V: P.A(V, [0] * V.shape[1]), P.gamma(cfg["ell"]), cfg["k"], CHOSEN_Q)
-    th = O.theta(D)
-    t_sketch = time.perf_counter() - t0
-    pre = lambda v: O.lmp_apply(S, D, th, v[:, None])[:, 0]
-    m, t_pcg, dz = 0, 0.0, []
-    while m <= L and (m == 0 or t_pcg + t_sketch < target_s):
+    x = O.pcg(lambda v: P.hess(v[:, None], [m])[:, 0], P.b[:, m], pre, cfg["rtol"], cfg["maxit"])[0]
+    return m, x, time.perf_counter() - t0
+
+
+def _cpu_workers():
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        return max(1, os.cpu_count() or 1)
+
+
+def _cpu_problem(O, cfg, z, q, members, workers):
+    """Sketch (one core) + LMP-PCG of `members` on `workers` processes; returns
+    (sketch seconds, wall seconds of the member solves, solutions, (S, D, theta))."""
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
+    P = O.Problem(cfg, z)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        try:
+            S, D, _ = O.nystrom(lambda V: P.A(V, [0] * V.shape[1]), P.gamma(cfg["ell"]), cfg["k"], q)
+            th = O.theta(D)
+        except np.linalg.LinAlgError:  # the shifted sketch fails too: plain CG, as the library does
+            S = D = th = None
+        t_sketch = time.perf_counter() - t0
+        _CPU.update(P=P, cfg=cfg, S=S, D=D, th=th)
         t1 = time.perf_counter()
-        x = O.pcg(lambda v: P.hess(v[:, None], [m])[:, 0], P.b[:, m], pre, cfg["rtol"], cfg["maxit"])[0]
-        t_pcg += time.perf_counter() - t1
-        dz.append(x)
-        m += 1
-    cost = t_sketch * m / (L + 1) + t_pcg
-    return m / cost, m, t_sketch + t_pcg, (S, D, th, dz)
+        if workers == 1:
+            res = [_cpu_member(m) for m in members]
+        else:
+            with mp.get_context("fork").Pool(workers) as pool:
+                res = pool.map(_cpu_member, members, chunksize=1)
+        wall = time.perf_counter() - t1
+    return t_sketch, wall, {m: x for m, x, _ in res}, (S, D, th)
 
 
 def cpu_baseline(cfg, z, target_s):
-    """The CPU oracle (unchanged) on a bounded sample of the same workload, run
-    twice on one oracle problem: with numpy's BLAS limited to one thread, and
-    with the BLAS pools as they are.  value is the faster of the two and cores
-    its thread count; both figures are reported."""
-    from threadpoolctl import threadpool_info, threadpool_limits
+    """The CPU oracle (unchanged) on bounded samples on the host's cores:
+    C3 (the metric's workload: the sketch once, amortised over the 129 members,
+    then as many members as there are cores, solved concurrently), C1 and C2
+    whole, and a 16-problem sample of the uneven batch (each problem's sketch
+    and its first members, extrapolated to whole problems by member count).
+    value: C3 solves/s on all cores; the one-core figure beside it."""
+    import platform
     from oracle import oracle as O
-    P = O.Problem(cfg, z)
-    with threadpool_limits(limits=1):
-        v1, m1, w1, _ = _cpu_sample(O, P, cfg, target_s / 2)
-    vN, mN, wN, lmp = _cpu_sample(O, P, cfg, target_s / 2)
-    nthr = max([int(p.get("num_threads", 1)) for p in threadpool_info()] or [1])
-    best_one = v1 >= vN
-    return dict(value=v1 if best_one else vN, unit="solves/s", cores=1 if best_one else nthr, kind="oracle",
-                value_1_thread=v1, value_all_threads=vN, all_threads=nthr,
-                sample=f"Gamma-Nystrom sketch (ell={cfg['ell']}, q={CHOSEN_Q}) once, amortised over "
-                       f"{cfg['members'] + 1} members, + LMP-PCG to rtol {cfg['rtol']} for the first members: "
-                       f"{m1} members in {w1:.1f} s at 1 thread, {mN} in {wN:.1f} s at {nthr} BLAS threads"), lmp
+    workers = _cpu_workers()
+    cpu = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), cpu)
+    except OSError:
+        pass
+    L = cfg["members"]
+
+    def note(msg):
+        print(f"[bench] CPU oracle: {msg}", file=sys.stderr, flush=True)
+
+    # C3 sample: one member on one core, then `workers` members at once
+    note(f"C3 one member on one core ({workers} cores)")
+    t_sk, w1, _, _ = _cpu_problem(O, cfg, z, CHOSEN_Q, [0], 1)
+    v1 = 1.0 / (t_sk / (L + 1) + w1)
+    mem = list(range(min(L + 1, workers)))
+    note(f"C3 {len(mem)} members at once")
+    t_sk, wN, dz, lmp = _cpu_problem(O, cfg, z, CHOSEN_Q, mem, workers)
+    vN = len(mem) / (t_sk * len(mem) / (L + 1) + wN)
+    per = {}
+    for name in ("C1", "C2"):
+        note(name)
+        c = W.config(name)
+        zz = W.problem_normals(c)
+        ts, wall, _, _ = _cpu_problem(O, c, zz, 1, list(range(c["members"] + 1)), workers)
+        per[name] = {"solves_per_s": round((c["members"] + 1) / (ts + wall), 3), "sketch_s": round(ts, 3),
+                     "pcg_wall_s": round(wall, 3)}
+    # uneven batch: 16 problems, their sketches and first members
+    probs = W.uneven_problems(256)[:16]
+    tot_s, solves, full_members = 0.0, 0, 0
+    per_problem = max(1, workers // 4)
+    note(f"{len(probs)} problems of the uneven batch")
+    for c in probs:
+        zz = W.problem_normals(c)
+        mem_c = list(range(min(c["members"] + 1, per_problem)))
+        ts, wall, _, _ = _cpu_problem(O, c, zz, 1, mem_c, min(workers, len(mem_c)))
+        # whole problem on all cores: the sketch plus its members in rounds of `workers`
+        rounds = -(-(c["members"] + 1) // workers)
+        tot_s += ts + wall * rounds
+        solves += c["members"] + 1
+    per["C4_sample"] = {"problems": len(probs), "solves_per_s_extrapolated": round(solves / tot_s, 3),
+                        "note": f"each problem's sketch and first {per_problem} members timed; whole problems "
+                                "extrapolated as rounds of one member per core"}
+    return dict(value=vN, unit="solves/s", cores=workers, kind="oracle", value_1_core=v1, value_all_cores=vN,
+                cpu=cpu, per_config=per,
+                sample=f"C3: Gamma-Nystrom sketch (ell={cfg['ell']}, q={CHOSEN_Q}) once on one core, amortised over "
+                       f"{L + 1} members; LMP-PCG to rtol {cfg['rtol']} of {len(mem)} members at once, one per "
+                       f"process ({workers} processes, one BLAS thread each)"), (lmp[0], lmp[1], lmp[2], [dz[m] for m in sorted(dz)])
 
 
 def main():
@@ -434,10 +501,16 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU: --gpus must be 1 (a single GPU holds one EDA "
                                    "problem's full member batch; multi-GPU member sharding is not built)"}))
         sys.exit(2)
-    import torch
-    assert torch.cuda.is_available(), "bench needs a GPU"
     cfg = W.config(a.workload)
     z = W.problem_normals(cfg)
+    # the CPU oracle first: its worker processes are forked before this
+    # process touches the GPU
+    cpu_line, oracle_lmp = None, None
+    if not a.no_cpu_baseline:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        cpu_line, oracle_lmp = cpu_baseline(cfg, z, a.cpu_seconds)
+    import torch
+    assert torch.cuda.is_available(), "bench needs a GPU"
     if a.copy_mib > 0:
         src = torch.ones(a.copy_mib << 17, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -450,6 +523,15 @@ def main():
     if not a.no_plain:
         print(f"[bench] {a.workload} plain form (dense U_B GEMMs)", file=sys.stderr, flush=True)
         plain = run_form(cfg, z, "dense", max(1, a.steps // 2), 1 if a.warmup else 0, max(2, a.hv_reps // 4))
+    # one choice at a time between the plain and the chosen form: the banded
+    # U_B, the second Nystrom pass, the FP32 sketch products
+    ablation = {}
+    if not a.no_plain:
+        for name, kw in (("banded_q1_fp64", dict(mixed=False, q=1)), ("banded_q2_fp64", dict(mixed=False, q=CHOSEN_Q))):
+            print(f"[bench] {a.workload} {name}", file=sys.stderr, flush=True)
+            r = run_form(cfg, z, "banded", max(1, a.steps // 2), 1 if a.warmup else 0, 2, **kw)
+            ablation[name] = {"value": round(r["solves_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 3),
+                              "iters_median": r["iters_median"], "all_converged": r["converged"]}
     bpc = pcg_kernel_bytes_per_col(cfg)
     # average launch from the sampled HIP-event pairs; bytes per launch from all
     # launches' active columns
@@ -469,7 +551,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64 (sketch products f32)",
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: Lorenz-96 n={cfg['n']}, window {cfg['nsteps']} steps, "
                                f"p={nt * nv} obs ({nt} times x {nv} vars), {cfg['members']} members + control, "
@@ -490,6 +572,14 @@ def main():
         "hessvec_per_s": {k: round(v, 1) for k, v in chosen["hessvec_per_s"].items()},
         "setup_s": round(chosen["setup_s"], 3),
     }
+    if ablation:
+        line["form_steps"] = {
+            "plain: dense U_B GEMMs, q=1, FP64": line.get("plain", {}).get("value") if plain is None else
+            round(plain["solves_per_s"], 3),
+            "banded U_B, q=1, FP64": ablation["banded_q1_fp64"]["value"],
+            f"banded U_B, q={CHOSEN_Q}, FP64": ablation["banded_q2_fp64"]["value"],
+            f"chosen: banded U_B, q={CHOSEN_Q}, FP32 sketch products": round(chosen["solves_per_s"], 3),
+            "iters_median": {k: v["iters_median"] for k, v in ablation.items()}}
     if plain:
         line["plain"] = {"value": round(plain["solves_per_s"], 3), "ms_per_step": round(plain["ms_per_step"], 3),
                          "hessvec_per_s": {k: round(v, 1) for k, v in plain["hessvec_per_s"].items()},
@@ -502,10 +592,8 @@ def main():
         lr = run_learned(a.learned_problems)
         if lr is not None:
             line["learned_sketch"] = lr
-    oracle_lmp = None
-    if not a.no_cpu_baseline:
-        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        line["cpu_baseline"], oracle_lmp = cpu_baseline(cfg, z, a.cpu_seconds)
+    if cpu_line is not None:
+        line["cpu_baseline"] = cpu_line
     g = chosen["problem"]
     line["sketch_ms"] = sketch_times(cfg, g)
     line["lmp_apply_us"] = lmp_times(cfg, g)

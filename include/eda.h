@@ -178,8 +178,10 @@ int eda_hessvec(eda_ctx *ctx, const int32_t *d_col_member, int32_t nb,
  * EDA_SKETCH_RHS_DIFF, which uses the first ell perturbed members' RHS
  * differences, ell <= L).  method EDA_METHOD_NYSTROM runs Algorithm 1 with q
  * passes (sketch Y = A Phi, CholQR2 of Y, W = Phi^T Y, Cholesky W = C^T C with
- * the shift nu = 2^-52 ||Y||_F on breakdown, T = R_Y C^-1, SVD T = U Sigma V^T,
- * S = Q_Y U, D = Sigma^2, truncation to k); EDA_METHOD_REVD runs
+ * the shift nu = u ||Y||_F on breakdown, u the unit roundoff of the sketch
+ * products (2^-52 in FP64, 2^-24 with EDA_HV_MIXED, 2^-8 with EDA_HV_BF16),
+ * T = R_Y C^-1, SVD T = U Sigma V^T, S = Q_Y U, D = Sigma^2 - nu, truncation
+ * to k); EDA_METHOD_REVD runs
  * Q = orth(A Phi), T = Q^T A Q, T = V D V^T, S = Q V (q ignored).
  * theta_rule: EDA_THETA_*.  flags: 0, EDA_HV_MIXED or EDA_HV_BF16 for the
  * sketch products (with BF16 operands the Cholesky of an ill-conditioned
@@ -419,7 +421,9 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
  * fails too (EDA_ERR_NOT_SPD: Phi numerically rank-deficient, e.g. ell close to
  * n), its members are solved by plain CG.  h_fallbacks (optional, 2 entries)
  * receives the number of problems whose sketch was redone and, of those, the
- * number solved without LMP.  Returns EDA_OK or a negative error. */
+ * number solved without LMP.  Returns EDA_OK, EDA_WARN_NOT_CONVERGED if any
+ * member of any problem did not converge (maxit or breakdown), or a negative
+ * error. */
 int eda_batch_solve(eda_batch *batch, int32_t k_cap, double rtol, int32_t maxit, int32_t use_lmp,
                     int32_t *h_fallbacks);
 

@@ -652,12 +652,15 @@ int eda_sketch_evd(eda_ctx *h, int32_t kind, const double *d_phi, int64_t ldphi,
         int32_t hinfo = 0;
         EDA_TRY(sync_read(c, &hinfo, c.sk_info, sizeof(int32_t)));
         if (hinfo != 0) {
-            // shift (Nystrom-variants appendix): Y <- Y + nu Phi, nu = eps ||Y||_F
+            // shift (Nystrom-variants appendix): Y <- Y + nu Phi, nu = u ||Y||_F
             HIP_TRY(gemm_f64(s, true, 1, 1, n * ell, c.sk_y, n * ell, c.sk_y, n * ell, dscal, 1, nullptr, 0,
                              nullptr, c.splitk, c.splitk_elems));
             double fro2 = 0.0;
             EDA_TRY(sync_read(c, &fro2, dscal, sizeof(double)));
-            nu = 2.220446049250313e-16 * std::sqrt(fro2);
+            // the unit roundoff of the products that formed Y: FP64, or FP32 / BF16 operands
+            const double u = (hvf & EDA_HV_BF16) ? std::ldexp(1.0, -8)
+                             : (hvf & EDA_HV_MIXED) ? std::ldexp(1.0, -24) : 2.220446049250313e-16;
+            nu = u * std::sqrt(fro2);
             HIP_TRY(launch_axpy_cols(s, n, ell, nu, c.sk_phi, n, c.sk_y, n));
             EDA_TRY(cholqr2(c, ell, c.sk_y, c.sk_q, RY));
             HIP_TRY(gemm_f64(s, true, ell, ell, n, c.sk_phi, n, c.sk_y, n, Wm, ell, nullptr, 0, nullptr, c.splitk,
@@ -1255,7 +1258,7 @@ BatchPlan batch_plan(eda_ctx *const *ctxs, int np) {
     P.off_chol = lay.take(sizeof(CholJob) * 3 * np);
     P.off_iptr = lay.take(sizeof(int32_t *) * np);
     P.off_flags = lay.take(sizeof(int32_t) * np);
-    P.off_titer = lay.take(sizeof(int32_t) * (st ? st : 1));
+    P.off_titer = lay.take(2 * sizeof(int32_t) * (st ? st : 1));
     P.total = lay.total;
     return P;
 }
@@ -2037,14 +2040,17 @@ int eda_batch_solve(eda_batch *b, int32_t k_cap, double rtol, int32_t maxit, int
     HIP_TRY(hipGraphLaunch(b->exec, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     const double t3 = now_ms();
+    bool not_converged = false;
     // queue layout of the next call from the measured cost of each column
     // (iterations x window length)
     {
         const int nt = (int)b->stasks.size();
-        std::vector<int32_t> its(nt);
+        std::vector<int32_t> its(2 * (size_t)nt);
         HIP_TRY(launch_task_iters(b->stream, nt, b->d_solve, b->d_stasks, b->d_titer));
-        HIP_TRY(hipMemcpyAsync(its.data(), b->d_titer, sizeof(int32_t) * nt, hipMemcpyDeviceToHost, b->stream));
+        HIP_TRY(hipMemcpyAsync(its.data(), b->d_titer, sizeof(int32_t) * 2 * nt, hipMemcpyDeviceToHost, b->stream));
         HIP_TRY(hipStreamSynchronize(b->stream));
+        for (int t = 0; t < nt; t++)
+            if (its[nt + t] != EDA_MEMBER_CONVERGED) not_converged = true;
         std::vector<long long> cost(nt);
         for (int t = 0; t < nt; t++) cost[t] = (long long)its[t] * batch_step_cost(*b, b->stasks[t].prob);
         EDA_TRY(batch_schedule(*b, cost));
@@ -2053,7 +2059,7 @@ int eda_batch_solve(eda_batch *b, int32_t k_cap, double rtol, int32_t maxit, int
     b->last_ms[0] = t1 - t0;
     b->last_ms[1] = t2 - t1;
     b->last_ms[2] = t3 - t2;
-    int warn = EDA_OK;
+    int warn = not_converged ? EDA_WARN_NOT_CONVERGED : EDA_OK;
     if (h_fallbacks) {
         h_fallbacks[0] = fallbacks;
         h_fallbacks[1] = unprec;

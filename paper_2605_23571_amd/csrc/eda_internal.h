@@ -292,7 +292,8 @@ hipError_t launch_solve(hipStream_t s, const TladArgs *d_probs, const TladGeom *
 // of problems sharing n: one workgroup per task.
 hipError_t launch_hv_multi(hipStream_t s, const TladArgs *d_probs, const SolveTask *d_tasks, int ntasks,
                            const TladGeom &g, size_t lds);
-// out[t] = iteration count of task t (probs[tasks[t].prob].pcg.iters[col]).
+// out[t] = iteration count of task t (probs[tasks[t].prob].pcg.iters[col]),
+// out[ntasks + t] = its status (out: 2 ntasks ints).
 hipError_t launch_task_iters(hipStream_t s, int ntasks, const TladArgs *d_probs, const SolveTask *d_tasks,
                              int32_t *d_out);
 // Workgroups of k_solve (waves waves each) one CU holds with this dynamic LDS.

@@ -894,11 +894,16 @@ __global__ __launch_bounds__(512) void k_solve(const TladArgs *__restrict__ prob
     }
 }
 
-// out[t] = iterations task t took in the last persistent solve.
+// out[t] = iterations task t took in the last persistent solve, and
+// out[ntasks + t] = its final status.
 __global__ void k_task_iters(int ntasks, const TladArgs *__restrict__ probs, const SolveTask *__restrict__ tasks,
                              int32_t *__restrict__ out) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < ntasks) out[t] = probs[tasks[t].prob].pcg.iters[tasks[t].col];
+    if (t < ntasks) {
+        const PcgCols &pc = probs[tasks[t].prob].pcg;
+        out[t] = pc.iters[tasks[t].col];
+        out[ntasks + t] = pc.status[tasks[t].col];
+    }
 }
 
 // Hessian products of (problem, column) tasks, one workgroup per task.

@@ -297,7 +297,7 @@ def eda_batch_solve(batch, k_cap: int, rtol: float, maxit: int, use_lmp: bool = 
     """Returns (problems redone on the host path, of those left without LMP)."""
     fb = (ctypes.c_int32 * 2)()
     _check("eda_batch_solve", lib().eda_batch_solve(batch, int(k_cap), float(rtol), int(maxit), int(bool(use_lmp)),
-                                                    fb))
+                                                    fb), ok=(EDA_OK, EDA_WARN_NOT_CONVERGED))
     return int(fb[0]), int(fb[1])
 
 

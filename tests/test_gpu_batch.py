@@ -4,6 +4,8 @@ and the CPU oracle.  The batch computes, per problem, what eda_sketch_evd
 compared with (a) the oracle's exact solution of (I + A_j) dz = b_j and (b) the
 single-problem GPU path (same operator, same preconditioner definition; the
 in-kernel LMP sums in another order, so iteration counts may differ by rounding)."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -48,6 +50,8 @@ def test_batch_solutions_match_exact():
     bt, cfgs, zs = st["b"], st["cfgs"], st["zs"]
     fb = bt.solve(k_cap=6, rtol=1e-10, maxit=3000)
     assert fb == (0, 0)
+    f2 = (ctypes.c_int32 * 2)()
+    assert eda.lib().eda_batch_solve(bt.b, 6, 1e-10, 3000, 1, f2) == eda.EDA_OK  # every member converged
     for p, (cfg, z) in enumerate(zip(cfgs, zs)):
         res = bt.result(p)
         assert (res["status"] == eda.EDA_MEMBER_CONVERGED).all(), (p, res["status"])
@@ -120,7 +124,9 @@ def test_batch_tuning_and_plain_cg():
 def test_batch_maxit_not_converged():
     st = batch_state()
     bt, cfgs = st["b"], st["cfgs"]
-    bt.solve(k_cap=6, rtol=1e-14, maxit=3)
+    fb = (ctypes.c_int32 * 2)()
+    code = eda.lib().eda_batch_solve(bt.b, 6, 1e-14, 3, 1, fb)
+    assert code == eda.EDA_WARN_NOT_CONVERGED  # some member stopped at maxit
     for p in range(len(cfgs)):
         r = bt.result(p, with_dz=False)
         assert (r["iters"] <= 3).all()

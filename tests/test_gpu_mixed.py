@@ -83,3 +83,31 @@ def test_reduced_precision_sketch_errors_c2_banded():
     it_64 = g.pcg(members, rtol=1e-6, maxit=3000)["iters"]
     assert (np.abs(it_mx - it_64) <= np.maximum(3, (0.05 * it_64).astype(int))).all(), (it_mx, it_64)
     g.close()
+
+
+def test_reduced_precision_sketch_near_full_rank_takes_the_shift():
+    # ell = 32 Gaussian sketch columns on a 40-point ring: W = Psi^T A Psi holds
+    # eigenvalues far below the FP32 rounding of the products, so with FP32
+    # products it is indefinite more often than not (a CPU emulation of FP32
+    # rounding in Y: 3 of 5 draws).  The Nystrom shift sized by the products'
+    # unit roundoff (2^-24 ||Y||_F) repairs that where the FP64-sized one
+    # (2^-52 ||Y||_F) does not (the same emulation: every indefinite draw still
+    # failed).  The leading eigenvalues, far above the shift, keep FP32-level
+    # agreement with the FP64 oracle; the LMP still gives the FP64 solution.
+    cfg = W.config("C1", members=32, ell=32, k=32, spinup=300)
+    z = W.problem_normals(cfg)
+    o = O.Problem(cfg, z)
+    psi = W.gaussian_matrix(cfg, cfg["n"], 32)          # 32 x n: row c is column c
+    S, D, info = O.nystrom(lambda V: o.A(V, [0] * V.shape[1]), psi.T, 32)
+    g = eda.Problem(cfg, z)
+    eig, th = g.sketch_evd("user", ell=32, k=32, mixed=True, phi=torch.from_numpy(psi).cuda())
+    lead = slice(0, 5)
+    e = np.abs(eig[lead] - D[lead]) / D[lead]
+    print(f"[mixed] n=40 ell=32 Gaussian, FP32 products: cond(core) {info['cond_core']:.1e}; "
+          f"leading eigenvalues max rel err {e.max():.1e}", flush=True)
+    assert np.all(np.isfinite(eig)) and np.all(eig >= 0) and e.max() < 1e-4
+    out = g.pcg(np.arange(cfg["members"] + 1), rtol=1e-10, maxit=3000)
+    assert (out["status"] == eda.EDA_MEMBER_CONVERGED).all()
+    ex = O.exact_solution(o, 5)
+    assert np.linalg.norm(out["dz"][5].cpu().numpy() - ex) / np.linalg.norm(ex) < 1e-6
+    g.close()
