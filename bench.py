@@ -37,6 +37,7 @@ import numpy as np  # noqa: E402
 import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TF = 78.6
 # HIP-event pairs around every 16th fused PCG launch: the average launch is
 # measured inside the timed steps while the event records (which sit between
 # kernels on the stream) stay out of most iterations
@@ -152,11 +153,23 @@ def run_form(cfg, z, ub_mode, steps, warmup, hv_reps, mixed=False, keep=False, q
             eda.eda_hessvec(g.ctx, n, cc, xx, yy, eda.EDA_HV_ADD_IDENTITY)
         torch.cuda.synchronize()
         hv[name] = xx.shape[0] * hv_reps / (time.perf_counter() - t1)
+    gemm = None
+    if ub_mode == "dense":
+        # the U_B GEMMs of member-mode products, each launch timed (HIP events)
+        eda.eda_profile_select(g.ctx, eda.EDA_PROF_UB_GEMM)
+        eda.eda_profile(g.ctx, 1)
+        for _ in range(hv_reps):
+            eda.eda_hessvec(g.ctx, n, cols, X, Y, eda.EDA_HV_ADD_IDENTITY)
+        timed, launches, ms = eda.eda_profile_read(g.ctx)
+        eda.eda_profile(g.ctx, 0)
+        eda.eda_profile_select(g.ctx, eda.EDA_PROF_TLAD)
+        flops = 2.0 * n * n * (L + 1)  # one n x n by n x (L + 1) product
+        gemm = {"avg_launch_ms": ms / max(1, timed), "flops_per_launch": flops, "launches": timed}
     it = np.concatenate([o["iters"] for o in outs])
     res = dict(solves_per_s=(L + 1) * steps / dt, ms_per_step=1e3 * dt / steps, setup_s=setup_s, converged=conv,
                iters_median=float(np.median(it)), iters_max=int(it.max()), iters_min=int(it.min()),
                tlad_timed=timed, tlad_launches=launches, tlad_ms=tlad_ms, hessvec_per_s=hv,
-               active_cols=iters_total)
+               active_cols=iters_total, gemm=gemm)
     res["last_dz"] = outs[-1]["dz"]
     res["last_iters"] = np.asarray(outs[-1]["iters"])
     res["problem"] = g if keep else None
@@ -580,6 +593,15 @@ def main():
             f"banded U_B, q={CHOSEN_Q}, FP64": ablation["banded_q2_fp64"]["value"],
             f"chosen: banded U_B, q={CHOSEN_Q}, FP32 sketch products": round(chosen["solves_per_s"], 3),
             "iters_median": {k: v["iters_median"] for k, v in ablation.items()}}
+    if plain and plain.get("gemm"):
+        gm = plain["gemm"]
+        tf = gm["flops_per_launch"] / (gm["avg_launch_ms"] * 1e-3) / 1e12
+        line["plain_roofline"] = {"bound": "mfma", "achieved": round(tf, 2), "peak": FP64_MFMA_PEAK_TF,
+                                  "unit": "TFLOP/s", "frac": round(tf / FP64_MFMA_PEAK_TF, 4),
+                                  "kernel": f"k_gemm (FP64 MFMA v_mfma_f64_16x16x4f64): U_B ({cfg['n']} x {cfg['n']}) "
+                                            f"times {cfg['members'] + 1} member columns, the plain form's U_B product",
+                                  "flops_per_launch": gm["flops_per_launch"],
+                                  "avg_launch_ms": round(gm["avg_launch_ms"], 4), "timed_launches": gm["launches"]}
     if plain:
         line["plain"] = {"value": round(plain["solves_per_s"], 3), "ms_per_step": round(plain["ms_per_step"], 3),
                          "hessvec_per_s": {k: round(v, 1) for k, v in plain["hessvec_per_s"].items()},

@@ -271,6 +271,15 @@ int eda_field(const eda_ctx *ctx, int32_t field, size_t *byte_offset, int64_t *c
 int eda_profile(eda_ctx *ctx, int32_t every);
 int eda_profile_read(eda_ctx *ctx, int64_t *timed, int64_t *launches, double *timed_ms);
 
+/* Which launches eda_profile times: EDA_PROF_TLAD (default) the kernels
+ * described above; EDA_PROF_UB_GEMM every U_B GEMM of the dense form (the
+ * first-level preconditioning product, FP64 MFMA, or FP32 / BF16 operands in
+ * reduced-precision sketch products), in any call.  Takes effect at the next
+ * eda_profile.  Errors: EDA_ERR_INVALID_ARG for other kinds. */
+#define EDA_PROF_TLAD     0
+#define EDA_PROF_UB_GEMM  1
+int eda_profile_select(eda_ctx *ctx, int32_t kind);
+
 /* ---- learned sketch ----
  * A small MLP maps the control member's right-hand side to k sketch directions
  * (there is no such component in the paper; it learns what its Nystrom finds):

@@ -221,17 +221,49 @@ T *at(char *ws, size_t off) {
     return reinterpret_cast<T *>(ws + off);
 }
 
+// Enqueues launch() with HIP events around it when profiling samples this
+// launch (kind EDA_PROF_TLAD: inside eda_pcg_solve only).
+template <typename F>
+int profiled(Ctx &c, int kind, F launch) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool rec = c.prof > 0 && c.prof_kind == kind && (kind != EDA_PROF_TLAD || c.in_pcg) &&
+                     c.prof_seen++ % c.prof == 0;
+    if (rec) {
+        if (c.ev_used + 2 > c.ev.size()) {
+            for (int i = 0; i < 64; i++) {
+                hipEvent_t e;
+                HIP_TRY(hipEventCreate(&e));
+                c.ev.push_back(e);
+            }
+        }
+        e0 = c.ev[c.ev_used];
+        e1 = c.ev[c.ev_used + 1];
+        c.ev_used += 2;
+        HIP_TRY(hipEventRecord(e0, c.stream));
+    }
+    HIP_TRY(launch());
+    if (rec) {
+        HIP_TRY(hipEventRecord(e1, c.stream));
+        c.prof_launches++;
+    }
+    return EDA_OK;
+}
+
 // Y = U_B X (+ Add), columns optionally masked.  lowp (reduced-precision
 // sketch): the dense product runs on the matrix cores with FP32 accumulation
 // and FP32 operands (1) or BF16 operands (2).
 int ub_apply(Ctx &c, int nb, const double *X, long long ldx, double *Y, long long ldy, const double *Add,
              long long ldadd, const int32_t *active, int lowp = 0) {
     if (c.cfg.ub_mode == EDA_UB_DENSE && lowp == 2) {
-        HIP_TRY(gemm_bf16(c.stream, c.n, nb, c.n, c.ub16, c.n, X, ldx, Y, ldy, Add, ldadd));
+        EDA_TRY(profiled(c, EDA_PROF_UB_GEMM,
+                         [&] { return gemm_bf16(c.stream, c.n, nb, c.n, c.ub16, c.n, X, ldx, Y, ldy, Add, ldadd); }));
     } else if (c.cfg.ub_mode == EDA_UB_DENSE && lowp == 1) {
-        HIP_TRY(gemm_f32in(c.stream, c.n, nb, c.n, c.ub32, c.n, X, ldx, Y, ldy, Add, ldadd));
+        EDA_TRY(profiled(c, EDA_PROF_UB_GEMM,
+                         [&] { return gemm_f32in(c.stream, c.n, nb, c.n, c.ub32, c.n, X, ldx, Y, ldy, Add, ldadd); }));
     } else if (c.cfg.ub_mode == EDA_UB_DENSE) {
-        HIP_TRY(gemm_f64(c.stream, false, c.n, nb, c.n, c.ub, c.n, X, ldx, Y, ldy, Add, ldadd, nullptr, nullptr, 0));
+        EDA_TRY(profiled(c, EDA_PROF_UB_GEMM, [&] {
+            return gemm_f64(c.stream, false, c.n, nb, c.n, c.ub, c.n, X, ldx, Y, ldy, Add, ldadd, nullptr, nullptr, 0);
+        }));
     } else {
         HIP_TRY(launch_band_conv(c.stream, c.n, nb, c.band_lo, c.band_hi, c.ubrow, X, ldx, Y, ldy, Add, ldadd,
                                  active));
@@ -267,55 +299,9 @@ TladArgs tlad_args(Ctx &c, int nb, const int32_t *cols, const int32_t *active) {
     return a;
 }
 
-// Enqueues launch() with HIP events around it when the PCG-loop profiling
-// samples this launch.
-template <typename F>
-int profiled(Ctx &c, F launch) {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool rec = c.prof > 0 && c.in_pcg && c.prof_seen++ % c.prof == 0;
-    if (rec) {
-        if (c.ev_used + 2 > c.ev.size()) {
-            for (int i = 0; i < 64; i++) {
-                hipEvent_t e;
-                HIP_TRY(hipEventCreate(&e));
-                c.ev.push_back(e);
-            }
-        }
-        e0 = c.ev[c.ev_used];
-        e1 = c.ev[c.ev_used + 1];
-        c.ev_used += 2;
-        HIP_TRY(hipEventRecord(e0, c.stream));
-    }
-    HIP_TRY(launch());
-    if (rec) {
-        HIP_TRY(hipEventRecord(e1, c.stream));
-        c.prof_launches++;
-    }
-    return EDA_OK;
-}
-
 int run_tlad(Ctx &c, const TladArgs &a, int mode, bool fp32, const SplitCols *sc = nullptr) {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool rec = c.prof > 0 && c.in_pcg && c.prof_seen++ % c.prof == 0;
-    if (rec) {
-        if (c.ev_used + 2 > c.ev.size()) {
-            for (int i = 0; i < 64; i++) {
-                hipEvent_t e;
-                HIP_TRY(hipEventCreate(&e));
-                c.ev.push_back(e);
-            }
-        }
-        e0 = c.ev[c.ev_used];
-        e1 = c.ev[c.ev_used + 1];
-        c.ev_used += 2;
-        HIP_TRY(hipEventRecord(e0, c.stream));
-    }
-    HIP_TRY(launch_tlad(c.stream, a, mode, fp32, c.geo_waves, c.geo_tb, sc));
-    if (rec) {
-        HIP_TRY(hipEventRecord(e1, c.stream));
-        c.prof_launches++;
-    }
-    return EDA_OK;
+    return profiled(c, EDA_PROF_TLAD,
+                    [&] { return launch_tlad(c.stream, a, mode, fp32, c.geo_waves, c.geo_tb, sc); });
 }
 
 // Pieces per column of a split launch over `columns` columns: the forced
@@ -931,7 +917,7 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                     lmp_blocks(n, &rows_, &nrb_);
                     xa.nrb = nrb_;
                     xa.nseg = c.xch_nseg;
-                    EDA_TRY(profiled(c, [&] { return launch_tlad_x(s, t, xa, xp, sc); }));
+                    EDA_TRY(profiled(c, EDA_PROF_TLAD, [&] { return launch_tlad_x(s, t, xa, xp, sc); }));
                     LmpFin f{};
                     f.q = c.pc_q;
                     f.p = pbuf[cur ^ 1];
@@ -1094,6 +1080,12 @@ int eda_profile(eda_ctx *h, int32_t every) {
     c.prof_seen = 0;
     c.prof_launches = 0;
     c.ev_used = 0;
+    return EDA_OK;
+}
+
+int eda_profile_select(eda_ctx *h, int32_t kind) {
+    if (!h || (kind != EDA_PROF_TLAD && kind != EDA_PROF_UB_GEMM)) return EDA_ERR_INVALID_ARG;
+    h->c.prof_kind = kind;
     return EDA_OK;
 }
 

@@ -88,7 +88,8 @@ struct Ctx {
     double theta = 1.0;
 
     // profiling of the TL/AD kernel inside eda_pcg_solve
-    int prof = 0;             // time every prof-th TL/AD launch inside PCG (0: off)
+    int prof = 0;             // time every prof-th launch of the profiled kind (0: off)
+    int prof_kind = EDA_PROF_TLAD;
     int64_t prof_seen = 0;
     bool in_pcg = false;
     int geo_waves = 0, geo_tb = 0;  // TL/AD launch geometry override (0: default)

@@ -1,6 +1,6 @@
 // Reduced-precision GEMMs on the matrix cores, column-major C = A B (+ Add),
-// FP32 accumulation: BF16 operands (v_mfma_f32_16x16x16_bf16) and FP32
-// operands (v_mfma_f32_16x16x4_f32).
+// FP32 accumulation: BF16 operands (gfx950's v_mfma_f32_16x16x32_bf16, 32 K
+// per instruction) and FP32 operands (v_mfma_f32_16x16x4_f32).
 // Used for the dense U_B products of the reduced-precision sketch: A is U_B
 // held in BF16 (converted once at set-up), B is an FP64 block converted to BF16
 // (round to nearest even) as it is staged, C and Add are FP64.  Each product
@@ -15,7 +15,8 @@
 namespace eda {
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short short8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float float4v __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 32;
@@ -80,27 +81,31 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const un
         __syncthreads();
         if (k0 + BK < K) load(k0 + BK);
 #pragma unroll
-        for (int ks = 0; ks < BK / 16; ks++) {
-            // lane l supplies k = 16 ks + 4 (l / 16) + e, e = 0..3
-            const int kb = ks * 16 + 4 * (lane >> 4);
-            bf16x4 av[2], bv[2];
+        for (int ks = 0; ks < BK / 32; ks++) {
+            // lane l supplies k = 32 ks + 8 (l / 16) + e, e = 0..7, for both
+            // operands (the same k for both, so the dot products are exact
+            // whatever order the unit sums them in)
+            const int kb = ks * 32 + 8 * (lane >> 4);
+            short8 av[2], bv[2];
 #pragma unroll
             for (int a = 0; a < 2; a++) {
                 const int m = wr * 32 + a * 16 + (lane & 15);
 #pragma unroll
-                for (int e = 0; e < 4; e++) av[a][e] = (short)As[kb + e][m];
+                for (int e = 0; e < 8; e++) av[a][e] = (short)As[kb + e][m];
             }
 #pragma unroll
             for (int b = 0; b < 2; b++) {
                 const int nn = wc * 32 + b * 16 + (lane & 15);
 #pragma unroll
-                for (int e = 0; e < 4; e++) bv[b][e] = (short)Bs[kb + e][nn];
+                for (int e = 0; e < 8; e++) bv[b][e] = (short)Bs[kb + e][nn];
             }
 #pragma unroll
             for (int a = 0; a < 2; a++)
 #pragma unroll
                 for (int b = 0; b < 2; b++)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bv[b], av[a], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, bv[b]),
+                                                                       __builtin_bit_cast(bf16x8, av[a]), acc[a][b],
+                                                                       0, 0, 0);
         }
         __syncthreads();
     }

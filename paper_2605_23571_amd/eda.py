@@ -37,6 +37,7 @@ EDA_METHOD_NYSTROM, EDA_METHOD_REVD = 0, 1
 EDA_THETA_MID, EDA_THETA_LAMK, EDA_THETA_ONE = 0, 1, 2
 EDA_LMP_P, EDA_LMP_U = 0, 1
 EDA_XCH_OFF, EDA_XCH_ON = 0, 1
+EDA_PROF_TLAD, EDA_PROF_UB_GEMM = 0, 1
 EDA_LMP_NOALLOC_SCRATCH_BYTES = 4194304
 FIELDS = dict(truth=0, xb=1, traj=2, y=3, d=4, b=5, costc=6, ubrow=7, S=8, eig=9)
 THETA_RULES = {"mid": EDA_THETA_MID, "lamk": EDA_THETA_LAMK, "one": EDA_THETA_ONE}
@@ -83,6 +84,7 @@ def lib():
             "eda_field": [vp, i32, ctypes.POINTER(sz), ctypes.POINTER(i64)],
             "eda_profile": [vp, i32],
             "eda_profile_read": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(dbl)],
+            "eda_profile_select": [vp, i32],
             "eda_destroy": [vp],
             "eda_set_geometry": [vp, i32, i32],
             "eda_set_split": [vp, i32],
@@ -259,6 +261,10 @@ def eda_profile_read(ctx):
     t, n, ms = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
     _check("eda_profile_read", lib().eda_profile_read(ctx, ctypes.byref(t), ctypes.byref(n), ctypes.byref(ms)))
     return t.value, n.value, ms.value
+
+
+def eda_profile_select(ctx, kind: int):
+    _check("eda_profile_select", lib().eda_profile_select(ctx, int(kind)))
 
 
 def eda_set_geometry(ctx, waves: int, tb: int):
