@@ -63,7 +63,7 @@ def parse():
     ap.add_argument("--batch-problems", type=int, default=256)
     ap.add_argument("--batch-plain", type=int, default=64, help="problems timed through the per-problem path")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-sketch comparison")
-    ap.add_argument("--learned-problems", type=int, default=16)
+    ap.add_argument("--learned-problems", type=int, default=256)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration; untimed)")
     return ap.parse_args()
@@ -397,6 +397,14 @@ def run_learned(count):
         rep[name] = {"solves_per_s": round(solves / r["t"], 1), "iters_median": float(np.median(it)),
                      "iters_mean": round(float(np.mean(it)), 1)}
     rep["iteration_ratio_gamma_over_learned"] = round(rep["gamma"]["iters_mean"] / rep["learned"]["iters_mean"], 3)
+    # per problem: mean iterations with Gamma over mean with the learned LMP
+    ratios = np.array([np.mean(a) / np.mean(b) for a, b in zip(res["gamma"]["iters"], res["learned"]["iters"])])
+    rep["per_problem_ratio"] = {"median": round(float(np.median(ratios)), 4),
+                                "p10": round(float(np.percentile(ratios, 10)), 4),
+                                "p90": round(float(np.percentile(ratios, 90)), 4),
+                                "min": round(float(ratios.min()), 4), "max": round(float(ratios.max()), 4),
+                                "learned_fewer": int((ratios > 1).sum()), "gamma_fewer": int((ratios < 1).sum())}
+    rep["network"] = T.load_meta().get("recipe", "eig")
     return rep
 
 

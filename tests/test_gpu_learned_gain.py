@@ -49,6 +49,12 @@ def test_learned_sketch_gain_on_test_problems():
             dz = sol["dz"].cpu().numpy()[0]
             assert np.linalg.norm(dz - ex) / np.linalg.norm(ex) < 1e-6
         g.close()
-    gain = np.median([r[2] / r[3] for r in rows])
-    print(f"[gain] median iteration ratio Gamma / learned = {gain:.3f}", flush=True)
+    ratios = np.array([r[2] / r[3] for r in rows])
+    gain = float(np.median(ratios))
+    print(f"[gain] iteration ratio Gamma / learned: median {gain:.3f}, min {ratios.min():.3f}, "
+          f"max {ratios.max():.3f}", flush=True)
     assert all(r[1] for r in rows)  # the network produced usable sketches
+    # the stated outcome: parity with the method's own Gamma sketch at equal
+    # sketch cost (32 Hessian products), within 3% in median; no gain is
+    # claimed (64 test problems measured 0.999, spread 0.985 to 1.014)
+    assert 0.97 <= gain
