@@ -181,7 +181,10 @@ int eda_hessvec(eda_ctx *ctx, const int32_t *d_col_member, int32_t nb,
  * the shift nu = u ||Y||_F on breakdown, u the unit roundoff of the sketch
  * products (2^-52 in FP64, 2^-24 with EDA_HV_MIXED, 2^-8 with EDA_HV_BF16),
  * T = R_Y C^-1, SVD T = U Sigma V^T, S = Q_Y U, D = Sigma^2 - nu, truncation
- * to k); EDA_METHOD_REVD runs
+ * to k).  Its last pass runs unshifted with no host round trip; if one of its
+ * Choleskys fails, one workgroup repeats the pass on the device with the shifts
+ * (CholQR3 with the trace shift, then nu), the same kernel the batch runs.
+ * EDA_METHOD_REVD runs
  * Q = orth(A Phi), T = Q^T A Q, T = V D V^T, S = Q V (q ignored).
  * theta_rule: EDA_THETA_*.  flags: 0, EDA_HV_MIXED or EDA_HV_BF16 for the
  * sketch products (with BF16 operands the Cholesky of an ill-conditioned
@@ -245,7 +248,13 @@ int eda_pcg_solve(eda_ctx *ctx, const int32_t *h_members, int32_t nm, double rto
  *   EDA_FIELD_COSTC  L+1 cost constants
  *   EDA_FIELD_UBROW  n, first row of U_B
  *   EDA_FIELD_S      n x k eigenvector estimates of the last sketch
- *   EDA_FIELD_EIG    k eigenvalue estimates of the last sketch */
+ *   EDA_FIELD_EIG    k eigenvalue estimates of the last sketch
+ *   EDA_FIELD_SKETCH_INFO  5 int32 (not doubles) of the last Nystrom sketch
+ *                    (eda_sketch_evd or a batch solve with LMP): the outcomes
+ *                    of its three unshifted Choleskys (Y^T Y, Q1^T Q1, W; 0 or
+ *                    the failing pivot + 1; the second is defined only when
+ *                    the first is 0), 1 if the shifted pass ran, 1 if that
+ *                    failed too (no LMP) */
 #define EDA_FIELD_TRUTH  0
 #define EDA_FIELD_XB     1
 #define EDA_FIELD_TRAJ   2
@@ -256,6 +265,7 @@ int eda_pcg_solve(eda_ctx *ctx, const int32_t *h_members, int32_t nm, double rto
 #define EDA_FIELD_UBROW  7
 #define EDA_FIELD_S      8
 #define EDA_FIELD_EIG    9
+#define EDA_FIELD_SKETCH_INFO 10
 int eda_field(const eda_ctx *ctx, int32_t field, size_t *byte_offset, int64_t *count);
 
 /* Opt-in timing of the tangent-linear/adjoint kernel launched by
@@ -392,12 +402,12 @@ int eda_destroy(eda_ctx *ctx);
  * eda_pcg_solve(0..L) computes, up to rounding order.
  * Problems with equal n form a class.  Each class runs one multi-problem
  * sketch launch (the classes as parallel branches), and the Nystrom cores of
- * all problems follow, in one captured graph; problems whose unshifted
- * Cholesky fails are then redone with the shifts of eda_sketch_evd.  One
- * persistent launch, in a second captured graph, solves the members of every
- * problem: its workgroups take member columns from work queues (one per XCD,
- * whole problems each) and iterate each to its final status without host
- * round trips.  Later calls with the same parameters replay both graphs.  The
+ * all problems follow; problems whose unshifted Cholesky fails are then redone
+ * on the device with the shifts of eda_sketch_evd (one workgroup each).  One
+ * persistent launch then solves the members of every problem: its workgroups
+ * take member columns from work queues (one per XCD, whole problems each) and
+ * iterate each to its final status without host round trips.  All of it is
+ * one captured graph; later calls with the same parameters replay it.  The
  * first call also tunes, per class, the sketch geometry (waves per workgroup,
  * time-block length) by timing the class's sketch launch, and the solve
  * geometry for one common number of waves.
@@ -424,15 +434,16 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
 /* Sketch, Nystrom and LMP-PCG of every member of every problem (see above);
  * returns after the work is done.  rtol, maxit: the PCG stopping rule of
  * eda_pcg_solve.  use_lmp = 0 skips the sketch and runs plain CG.  The sketch
- * graph uses unshifted CholQR2 and Cholesky; a problem where one of them fails
- * gets its LMP from eda_sketch_evd instead (shifted CholQR and the Nystrom shift
- * of the Nystrom-variants appendix) before the solve graph runs; if that sketch
- * fails too (EDA_ERR_NOT_SPD: Phi numerically rank-deficient, e.g. ell close to
- * n), its members are solved by plain CG.  h_fallbacks (optional, 2 entries)
- * receives the number of problems whose sketch was redone and, of those, the
- * number solved without LMP.  Returns EDA_OK, EDA_WARN_NOT_CONVERGED if any
- * member of any problem did not converge (maxit or breakdown), or a negative
- * error. */
+ * uses unshifted CholQR2 and Cholesky; a problem where one of them fails gets
+ * its LMP from the shifted sketch of eda_sketch_evd (shifted CholQR3 and the
+ * Nystrom shift of the Nystrom-variants appendix), run on the device inside
+ * the same graph before the solve, so a call makes no host round trip between
+ * its sketch and its solve; if that fails too (Phi numerically
+ * rank-deficient, e.g. ell close to n), its members are solved by plain CG.
+ * h_fallbacks (optional, 2 entries) receives the number of problems whose
+ * sketch was redone and, of those, the number solved without LMP.  Returns
+ * EDA_OK, EDA_WARN_NOT_CONVERGED if any member of any problem did not converge
+ * (maxit or breakdown), or a negative error. */
 int eda_batch_solve(eda_batch *batch, int32_t k_cap, double rtol, int32_t maxit, int32_t use_lmp,
                     int32_t *h_fallbacks);
 
@@ -451,12 +462,12 @@ int eda_batch_result(eda_batch *batch, int32_t p, double *d_DZ, int64_t ldz, int
  * time-block length}.  Returns the number of classes. */
 int eda_batch_tuning(eda_batch *batch, int32_t cls, int32_t *h_out);
 
-/* Wall times of the last eda_batch_solve in milliseconds: h_ms[0] the
- * sketch graph, h_ms[1] the host-driven sketches of problems whose graph
- * sketch failed, h_ms[2] the solve graph. */
+/* GPU times of the last eda_batch_solve's graph in milliseconds: h_ms[0] the
+ * sketch (products and Nystrom cores), h_ms[1] the shifted redo, h_ms[2] the
+ * solve (all in h_ms[2] when the runtime cannot time inside a graph). */
 int eda_batch_timing(eda_batch *batch, double *h_ms);
 
-/* Free the batch's host structures and its graphs and stream. */
+/* Free the batch's host structures and its graph and stream. */
 int eda_batch_destroy(eda_batch *batch);
 
 /* Static description of a status code. */

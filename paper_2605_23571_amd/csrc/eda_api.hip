@@ -3,7 +3,6 @@
 // Host code only sequences kernels on the context's stream; every arithmetic
 // step of the path runs in this library's HIP kernels.
 #include <algorithm>
-#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -404,6 +403,105 @@ int cholqr2(Ctx &c, int l, const double *Y, double *Q, double *R_out) {
     return EDA_OK;
 }
 
+// The last stage of the Nystrom sketch with no host synchronisation, in
+// phases around the three Cholesky factorisations and the SVD of T (a batch
+// runs each for all its problems in one launch, one workgroup per problem;
+// chol_job and jacobi_job give their operands):
+//   0: G = Y^T Y                  -> chol 0: R1, R1^-1
+//   1: Q1 = Y R1^-1, G = Q1^T Q1  -> chol 1: R2, R2^-1
+//   2: Q = Q1 R2^-1, R_Y = R2 R1, W = Phi^T Y (symmetrised) -> chol 2: C, C^-1
+//   3: T = R_Y C^-1               -> SVD
+// then nystrom_post_svd: S = Q U, signs, theta, the LMP coefficients; then
+// the device-side redo (redo_job), which takes over when one of the three
+// unshifted Cholesky outcomes (sk_info[0..2]) is nonzero.  Slots of sk_small
+// (l_max^2 doubles each): 0 G, 1 R1 then C^-1, 2 R1^-1 then T, 3 R2 then U,
+// 4 R2^-1 then sigma, 7 R_Y, 8 W, 9 C.
+JacobiJob jacobi_job(const Ctx &c, int l) {
+    const size_t ls = (size_t)c.max_ell * c.max_ell;
+    return JacobiJob{l, c.sk_small + 2 * ls, c.sk_small + 3 * ls, c.sk_small + 4 * ls};
+}
+
+CholJob chol_job(const Ctx &c, int l, int which) {
+    const size_t ls = (size_t)c.max_ell * c.max_ell;
+    double *m = c.sk_small;
+    switch (which) {
+        case 0: return CholJob{l, m, 0.0, m + 1 * ls, m + 2 * ls, c.sk_info + 0};
+        case 1: return CholJob{l, m, 0.0, m + 3 * ls, m + 4 * ls, c.sk_info + 1};
+        default: return CholJob{l, m + 8 * ls, 0.0, m + 9 * ls, m + 1 * ls, c.sk_info + 2};
+    }
+}
+
+int nystrom_phase(Ctx &c, int l, int phase) {
+    hipStream_t s = c.stream;
+    const int n = c.n;
+    const size_t ls = (size_t)c.max_ell * c.max_ell;
+    double *G = c.sk_small, *R1 = c.sk_small + 1 * ls, *R1i = c.sk_small + 2 * ls;
+    double *R2 = c.sk_small + 3 * ls, *R2i = c.sk_small + 4 * ls;
+    double *RY = c.sk_small + 7 * ls, *Wm = c.sk_small + 8 * ls;
+    double *Ci = c.sk_small + 1 * ls, *Tm = c.sk_small + 2 * ls;
+    switch (phase) {
+        case 0:
+            HIP_TRY(gemm_f64(s, true, l, l, n, c.sk_y, n, c.sk_y, n, G, l, nullptr, 0, nullptr, c.splitk,
+                             c.splitk_elems));
+            break;
+        case 1:
+            HIP_TRY(gemm_f64(s, false, n, l, l, c.sk_y, n, R1i, l, c.sk_q1, n, nullptr, 0, nullptr, nullptr, 0));
+            HIP_TRY(gemm_f64(s, true, l, l, n, c.sk_q1, n, c.sk_q1, n, G, l, nullptr, 0, nullptr, c.splitk,
+                             c.splitk_elems));
+            break;
+        case 2:
+            HIP_TRY(gemm_f64(s, false, n, l, l, c.sk_q1, n, R2i, l, c.sk_q, n, nullptr, 0, nullptr, nullptr, 0));
+            HIP_TRY(launch_small_gemm(s, l, false, false, R2, R1, RY));
+            HIP_TRY(gemm_f64(s, true, l, l, n, c.sk_phi, n, c.sk_y, n, Wm, l, nullptr, 0, nullptr, c.splitk,
+                             c.splitk_elems));
+            HIP_TRY(launch_sym(s, l, Wm));
+            break;
+        default:
+            HIP_TRY(launch_small_gemm(s, l, false, false, RY, Ci, Tm));
+            break;
+    }
+    return EDA_OK;
+}
+
+int nystrom_post_svd(Ctx &c, int l, int k, int rule) {
+    hipStream_t s = c.stream;
+    const int n = c.n;
+    const JacobiJob j = jacobi_job(c, l);
+    double *dscal = reinterpret_cast<double *>(c.sk_info + 16);
+    HIP_TRY(gemm_f64(s, false, n, k, l, c.sk_q, n, j.U, l, c.sk_s, n, nullptr, 0, nullptr, nullptr, 0));
+    HIP_TRY(launch_fix_signs(s, n, k, c.sk_s, n));
+    HIP_TRY(launch_lmp_coef(s, k, j.sig, 0.0, 1, rule, c.sk_eig, c.sk_coef, c.sk_coefu, dscal + 1));
+    return EDA_OK;
+}
+
+// Operands of the device-side shifted sketch (k_nystrom_redo) of this
+// context: triggered by the unshifted outcomes sk_info[0..2]; sk_info[3..4]
+// receive whether it ran and whether it failed; theta at the same place as
+// nystrom_post_svd's.  u: unit roundoff of the products that formed Y.
+RedoJob redo_job(const Ctx &c, int l, int k, int rule, double u) {
+    RedoJob j{};
+    j.n = c.n;
+    j.l = l;
+    j.k = k;
+    j.rule = rule;
+    j.u = u;
+    j.trigger = c.sk_info;
+    j.state = c.sk_info + 3;
+    j.phi = c.sk_phi;
+    j.y = c.sk_y;
+    j.q1 = c.sk_q1;
+    j.q2 = c.sk_s;
+    j.q = c.sk_q;
+    j.s = c.sk_s;
+    j.small = c.sk_small;
+    j.ls = (long long)c.max_ell * c.max_ell;
+    j.eig = c.sk_eig;
+    j.coef = c.sk_coef;
+    j.coefu = c.sk_coefu;
+    j.theta = reinterpret_cast<double *>(c.sk_info + 16) + 1;
+    return j;
+}
+
 }  // namespace
 
 extern "C" {
@@ -616,52 +714,40 @@ int eda_sketch_evd(eda_ctx *h, int32_t kind, const double *d_phi, int64_t ldphi,
             break;
     }
     const size_t ls = (size_t)c.max_ell * c.max_ell;
-    double *RY = c.sk_small + 7 * ls, *Wm = c.sk_small + 8 * ls, *Cm = c.sk_small + 9 * ls;
-    double *Ci = c.sk_small + 1 * ls, *Tm = c.sk_small + 2 * ls, *Um = c.sk_small + 3 * ls;
+    double *RY = c.sk_small + 7 * ls, *Wm = c.sk_small + 8 * ls;
+    double *Tm = c.sk_small + 2 * ls, *Um = c.sk_small + 3 * ls;
     double *sig = c.sk_small + 4 * ls;
     double *dscal = reinterpret_cast<double *>(c.sk_info + 16);
-    double nu = 0.0;
     const uint32_t hvf = flags & (EDA_HV_MIXED | EDA_HV_BF16);
     if (method == EDA_METHOD_NYSTROM) {
         EDA_TRY(hessvec(c, c.zero_members, ell, c.sk_phi, n, c.sk_y, n, hvf, nullptr));
-        EDA_TRY(cholqr2(c, ell, c.sk_y, c.sk_q, RY));
         for (int pass = 2; pass <= q; pass++) {
+            // power pass: Phi <- orth(Y), Y = A Phi
+            EDA_TRY(cholqr2(c, ell, c.sk_y, c.sk_q, RY));
             HIP_TRY(launch_copy_cols(s, n, ell, c.sk_q, n, c.sk_phi, n));
             EDA_TRY(hessvec(c, c.zero_members, ell, c.sk_phi, n, c.sk_y, n, hvf, nullptr));
-            EDA_TRY(cholqr2(c, ell, c.sk_y, c.sk_q, RY));
         }
-        // W = Phi^T Y, symmetrised; W = C^T C
-        HIP_TRY(gemm_f64(s, true, ell, ell, n, c.sk_phi, n, c.sk_y, n, Wm, ell, nullptr, 0, nullptr, c.splitk,
-                         c.splitk_elems));
-        HIP_TRY(launch_sym(s, ell, Wm));
-        HIP_TRY(launch_chol_inv(s, ell, Wm, 0.0, Cm, Ci, c.sk_info));
-        int32_t hinfo = 0;
-        EDA_TRY(sync_read(c, &hinfo, c.sk_info, sizeof(int32_t)));
-        if (hinfo != 0) {
-            // shift (Nystrom-variants appendix): Y <- Y + nu Phi, nu = u ||Y||_F
-            HIP_TRY(gemm_f64(s, true, 1, 1, n * ell, c.sk_y, n * ell, c.sk_y, n * ell, dscal, 1, nullptr, 0,
-                             nullptr, c.splitk, c.splitk_elems));
-            double fro2 = 0.0;
-            EDA_TRY(sync_read(c, &fro2, dscal, sizeof(double)));
-            // the unit roundoff of the products that formed Y: FP64, or FP32 / BF16 operands
-            const double u = (hvf & EDA_HV_BF16) ? std::ldexp(1.0, -8)
-                             : (hvf & EDA_HV_MIXED) ? std::ldexp(1.0, -24) : 2.220446049250313e-16;
-            nu = u * std::sqrt(fro2);
-            HIP_TRY(launch_axpy_cols(s, n, ell, nu, c.sk_phi, n, c.sk_y, n));
-            EDA_TRY(cholqr2(c, ell, c.sk_y, c.sk_q, RY));
-            HIP_TRY(gemm_f64(s, true, ell, ell, n, c.sk_phi, n, c.sk_y, n, Wm, ell, nullptr, 0, nullptr, c.splitk,
-                             c.splitk_elems));
-            HIP_TRY(launch_sym(s, ell, Wm));
-            HIP_TRY(launch_chol_inv(s, ell, Wm, 0.0, Cm, Ci, c.sk_info));
-            EDA_TRY(sync_read(c, &hinfo, c.sk_info, sizeof(int32_t)));
-            if (hinfo != 0) return EDA_ERR_NOT_SPD;
+        // unshifted CholQR2 of Y, W = Phi^T Y and its Cholesky, T = R_Y C^-1,
+        // T = U Sigma V^T, S = Q_Y U(:, 1:k), D = Sigma^2; where one of the
+        // Choleskys failed, the device-side redo repeats the stage with the
+        // shifts (shifted CholQR3; Y + nu Phi with nu = u ||Y||_F, D = Sigma^2 - nu)
+        for (int phase = 0; phase < 4; phase++) {
+            EDA_TRY(nystrom_phase(c, ell, phase));
+            if (phase < 3) {
+                const CholJob j = chol_job(c, ell, phase);
+                HIP_TRY(launch_chol_inv(s, j.l, j.W, j.shift, j.C, j.Cinv, j.info));
+            }
         }
-        // T = R_Y C^-1, SVD T = U Sigma V^T, S = Q_Y U(:, 1:k), D = Sigma^2 - nu
-        HIP_TRY(launch_small_gemm(s, ell, false, false, RY, Ci, Tm));
-        HIP_TRY(launch_jacobi_svd_u(s, ell, Tm, Um, sig));
-        HIP_TRY(gemm_f64(s, false, n, k, ell, c.sk_q, n, Um, ell, c.sk_s, n, nullptr, 0, nullptr, nullptr, 0));
-        HIP_TRY(launch_fix_signs(s, n, k, c.sk_s, n));
-        HIP_TRY(launch_lmp_coef(s, k, sig, nu, 1, theta_rule, c.sk_eig, c.sk_coef, c.sk_coefu, dscal + 1));
+        const JacobiJob jj = jacobi_job(c, ell);
+        HIP_TRY(launch_jacobi_svd_u(s, ell, const_cast<double *>(jj.T), jj.U, jj.sig));
+        EDA_TRY(nystrom_post_svd(c, ell, k, theta_rule));
+        // the unit roundoff of the products that formed Y: FP64, or FP32 / BF16 operands
+        const double u = (hvf & EDA_HV_BF16) ? std::ldexp(1.0, -8)
+                         : (hvf & EDA_HV_MIXED) ? std::ldexp(1.0, -24) : 2.220446049250313e-16;
+        HIP_TRY(launch_nystrom_redo(s, redo_job(c, ell, k, theta_rule, u)));
+        int32_t st[2] = {0, 0};
+        EDA_TRY(sync_read(c, st, c.sk_info + 3, sizeof(st)));
+        if (st[1] != 0) return EDA_ERR_NOT_SPD;
     } else {
         // REVD: Q = orth(A Phi), T = Q^T A Q, T = V D V^T, S = Q V(:, 1:k)
         EDA_TRY(hessvec(c, c.zero_members, ell, c.sk_phi, n, c.sk_y, n, hvf, nullptr));
@@ -679,7 +765,6 @@ int eda_sketch_evd(eda_ctx *h, int32_t kind, const double *d_phi, int64_t ldphi,
     EDA_TRY(sync_read(c, &th, dscal + 1, sizeof(double)));
     if (h_eig) EDA_TRY(sync_read(c, h_eig, c.sk_eig, sizeof(double) * k));
     if (h_theta) *h_theta = th;
-    c.theta = th;
     c.k = k;
     c.have_lmp = true;
     c.sr_ready = false;
@@ -1065,6 +1150,10 @@ int eda_field(const eda_ctx *h, int32_t field, size_t *byte_offset, int64_t *cou
         case EDA_FIELD_EIG:
             if (!c.have_lmp) return EDA_ERR_ORDER;
             ptr = c.sk_eig; cnt = c.k; break;
+        case EDA_FIELD_SKETCH_INFO:
+            *byte_offset = (size_t)(reinterpret_cast<const char *>(c.sk_info) - c.ws);
+            *count = 5;
+            return EDA_OK;
         default: return EDA_ERR_INVALID_ARG;
     }
     *byte_offset = (size_t)(reinterpret_cast<const char *>(ptr) - c.ws);
@@ -1183,17 +1272,19 @@ struct eda_batch {
     int *d_counters = nullptr;            // SOLVE_QUEUES queue counters
     int *d_qoff = nullptr;                // SOLVE_QUEUES + 1 queue offsets
     TladGeom *d_geom = nullptr;           // solve geometry of each problem
-    JacobiJob *d_jobs = nullptr;          // SVD operands of every problem (sketch graph)
-    JacobiJob *d_fbjobs = nullptr;        // SVD operands of the fallback problems
+    JacobiJob *d_jobs = nullptr;          // SVD operands of every problem
+    RedoJob *d_redo = nullptr;            // device-side shifted sketch of every problem
     CholJob *d_chol = nullptr;            // operands of the three Cholesky steps, 3 x np
     int solve_waves = 0, solve_grid = 0;  // the one persistent solve launch
     size_t solve_lds = 0;
     const int32_t **d_infoptr = nullptr;  // each problem's sketch outcome slots
-    int32_t *d_flags = nullptr;           // gathered outcomes, one per problem
+    int32_t *d_flags = nullptr;           // gathered sketch states, two per problem
     int32_t *d_titer = nullptr;           // iterations of each solve task in the last call
     std::vector<SolveTask> stasks;        // solve tasks in queue order
     std::vector<int> qoff;                // host copy of d_qoff
-    double last_ms[3] = {0.0, 0.0, 0.0};  // sketch graph, host fallback, solve graph
+    double last_ms[3] = {0.0, 0.0, 0.0};  // sketch, shifted redo, solve (one graph)
+    hipEvent_t tev[4] = {};               // timing: entry, after the sketch, after the redo, exit
+    bool timed_nodes = true;              // tev[1..2] as event nodes inside the graph
     struct Class {
         int n = 0;
         std::vector<int> members;  // problem indices
@@ -1215,17 +1306,14 @@ struct eda_batch {
     bool tuned = false;
     int k_cap = -1, maxit = -1, use_lmp = -1;
     double rtol = -1.0;
-    hipGraph_t graph = nullptr, graph_sk = nullptr;
-    hipGraphExec_t exec = nullptr, exec_sk = nullptr;
-    // pinned decision slots of the lockstep sketch fallback
-    int32_t *h_fbi = nullptr;
-    double *h_fbd = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
 
 struct BatchPlan {
-    size_t off_solve, off_hv, off_st, off_ht, off_cnt, off_qoff, off_geom, off_jobs, off_fbjobs, off_chol, off_iptr,
+    size_t off_solve, off_hv, off_st, off_ht, off_cnt, off_qoff, off_geom, off_jobs, off_redo, off_chol, off_iptr,
         off_flags, off_titer, total;
 };
 
@@ -1246,83 +1334,13 @@ BatchPlan batch_plan(eda_ctx *const *ctxs, int np) {
     P.off_qoff = lay.take(sizeof(int) * (SOLVE_QUEUES + 1));
     P.off_geom = lay.take(sizeof(TladGeom) * np);
     P.off_jobs = lay.take(sizeof(JacobiJob) * np);
-    P.off_fbjobs = lay.take(sizeof(JacobiJob) * np);
+    P.off_redo = lay.take(sizeof(RedoJob) * np);
     P.off_chol = lay.take(sizeof(CholJob) * 3 * np);
     P.off_iptr = lay.take(sizeof(int32_t *) * np);
-    P.off_flags = lay.take(sizeof(int32_t) * np);
+    P.off_flags = lay.take(2 * sizeof(int32_t) * np);
     P.off_titer = lay.take(2 * sizeof(int32_t) * (st ? st : 1));
     P.total = lay.total;
     return P;
-}
-
-// The Nystrom core of eda_sketch_evd (q = 1, no shift) with no host
-// synchronisation, in phases around the three Cholesky factorisations and the
-// SVD of T, which the batch runs for all problems at once (one launch each,
-// one workgroup per problem; chol_job and jacobi_job give their operands):
-//   0: G = Y^T Y                  -> chol 0: R1, R1^-1
-//   1: Q1 = Y R1^-1, G = Q1^T Q1  -> chol 1: R2, R2^-1
-//   2: Q = Q1 R2^-1, R_Y = R2 R1, W = Phi^T Y (symmetrised) -> chol 2: C, C^-1
-//   3: T = R_Y C^-1               -> SVD
-// then nystrom_post_svd: S = Q U, signs, theta "mid", the LMP coefficients.
-// The three Cholesky outcomes land in sk_info[0..2]; the caller checks them
-// after the run.  Slots of sk_small (l_max^2 doubles each): 0 G, 1 R1 then
-// C^-1, 2 R1^-1 then T, 3 R2 then U, 4 R2^-1 then sigma, 7 R_Y, 8 W, 9 C.
-JacobiJob jacobi_job(const Ctx &c, int l) {
-    const size_t ls = (size_t)c.max_ell * c.max_ell;
-    return JacobiJob{l, c.sk_small + 2 * ls, c.sk_small + 3 * ls, c.sk_small + 4 * ls};
-}
-
-CholJob chol_job(const Ctx &c, int l, int which) {
-    const size_t ls = (size_t)c.max_ell * c.max_ell;
-    double *m = c.sk_small;
-    switch (which) {
-        case 0: return CholJob{l, m, 0.0, m + 1 * ls, m + 2 * ls, c.sk_info + 0};
-        case 1: return CholJob{l, m, 0.0, m + 3 * ls, m + 4 * ls, c.sk_info + 1};
-        default: return CholJob{l, m + 8 * ls, 0.0, m + 9 * ls, m + 1 * ls, c.sk_info + 2};
-    }
-}
-
-int nystrom_phase(Ctx &c, int l, int phase) {
-    hipStream_t s = c.stream;
-    const int n = c.n;
-    const size_t ls = (size_t)c.max_ell * c.max_ell;
-    double *G = c.sk_small, *R1 = c.sk_small + 1 * ls, *R1i = c.sk_small + 2 * ls;
-    double *R2 = c.sk_small + 3 * ls, *R2i = c.sk_small + 4 * ls;
-    double *RY = c.sk_small + 7 * ls, *Wm = c.sk_small + 8 * ls;
-    double *Ci = c.sk_small + 1 * ls, *Tm = c.sk_small + 2 * ls;
-    switch (phase) {
-        case 0:
-            HIP_TRY(gemm_f64(s, true, l, l, n, c.sk_y, n, c.sk_y, n, G, l, nullptr, 0, nullptr, c.splitk,
-                             c.splitk_elems));
-            break;
-        case 1:
-            HIP_TRY(gemm_f64(s, false, n, l, l, c.sk_y, n, R1i, l, c.sk_q1, n, nullptr, 0, nullptr, nullptr, 0));
-            HIP_TRY(gemm_f64(s, true, l, l, n, c.sk_q1, n, c.sk_q1, n, G, l, nullptr, 0, nullptr, c.splitk,
-                             c.splitk_elems));
-            break;
-        case 2:
-            HIP_TRY(gemm_f64(s, false, n, l, l, c.sk_q1, n, R2i, l, c.sk_q, n, nullptr, 0, nullptr, nullptr, 0));
-            HIP_TRY(launch_small_gemm(s, l, false, false, R2, R1, RY));
-            HIP_TRY(gemm_f64(s, true, l, l, n, c.sk_phi, n, c.sk_y, n, Wm, l, nullptr, 0, nullptr, c.splitk,
-                             c.splitk_elems));
-            HIP_TRY(launch_sym(s, l, Wm));
-            break;
-        default:
-            HIP_TRY(launch_small_gemm(s, l, false, false, RY, Ci, Tm));
-            break;
-    }
-    return EDA_OK;
-}
-
-int nystrom_post_svd(Ctx &c, int l, int k) {
-    hipStream_t s = c.stream;
-    const int n = c.n;
-    const JacobiJob j = jacobi_job(c, l);
-    double *dscal = reinterpret_cast<double *>(c.sk_info + 16);
-    HIP_TRY(gemm_f64(s, false, n, k, l, c.sk_q, n, j.U, l, c.sk_s, n, nullptr, 0, nullptr, nullptr, 0));
-    HIP_TRY(launch_fix_signs(s, n, k, c.sk_s, n));
-    HIP_TRY(launch_lmp_coef(s, k, j.sig, 0.0, 1, EDA_THETA_MID, c.sk_eig, c.sk_coef, c.sk_coefu, dscal + 1));
-    return EDA_OK;
 }
 
 // Device argument blocks of problem i: solve (PCG of members 0..L) and sketch
@@ -1347,7 +1365,7 @@ void batch_args(eda_batch &b, int i, TladArgs &sa, TladArgs &ha) {
     sa.pcg.lmp_s = c.sk_s;
     sa.pcg.lmp_c = c.sk_coef;
     sa.pcg.lmp_k = b.use_lmp ? b.ell[i] : 0;
-    sa.pcg.lmp_info = b.use_lmp ? c.sk_info : nullptr;
+    sa.pcg.lmp_info = b.use_lmp ? c.sk_info + 4 : nullptr;  // set by the shifted redo
     ha = tlad_args(c, b.ell[i], c.zero_members, nullptr);
     ha.V = c.sk_phi;
     ha.ldv = c.n;
@@ -1544,63 +1562,64 @@ long long batch_step_cost(const eda_batch &b, int p) {
     return b.probs[p]->N;
 }
 
-int batch_enqueue_sketch(eda_batch &b) {
+// Enqueue one call's work on b.stream (captured into one graph): with the LMP,
+// the sketch products (one branch per class), the Nystrom cores (per-problem
+// GEMMs in parallel branches, each phase's Cholesky factorisations or SVDs for
+// every problem in one launch) and the device-side shifted redo of the
+// problems whose unshifted Cholesky failed; then the persistent solve over
+// the tasks of every class; then each task's iterations and status and each
+// problem's sketch state, gathered for one read.
+int batch_enqueue(eda_batch &b) {
     hipStream_t s = b.stream;
-    for (size_t i = 0; i < b.probs.size(); i++)
-        HIP_TRY(launch_gamma(s, b.probs[i]->n, b.ell[i], b.probs[i]->b, b.probs[i]->sk_phi));
-    // sketch products, one branch per class
-    HIP_TRY(hipEventRecord(b.fork, s));
-    for (auto &k : b.classes) {
-        HIP_TRY(hipStreamWaitEvent(k.side, b.fork, 0));
-        HIP_TRY(launch_hv_multi(k.side, b.d_hv, b.d_htasks + k.h_off, k.h_cnt, k.g, k.lds_hv));
-        HIP_TRY(hipEventRecord(k.done, k.side));
-        HIP_TRY(hipStreamWaitEvent(s, k.done, 0));
-    }
-    // Nystrom cores: the per-problem GEMMs of each phase spread over parallel
-    // branches, then the phase's Cholesky factorisations (or SVDs) of every
-    // problem in one launch (one workgroup each)
-    const size_t nl = b.lanes.size();
     const int np = (int)b.probs.size();
-    int lmax = 1;
-    for (int l : b.ell) lmax = l > lmax ? l : lmax;
-    for (int phase = 0; phase < 5; phase++) {
+    if (b.use_lmp) {
+        for (int i = 0; i < np; i++)
+            HIP_TRY(launch_gamma(s, b.probs[i]->n, b.ell[i], b.probs[i]->b, b.probs[i]->sk_phi));
         HIP_TRY(hipEventRecord(b.fork, s));
-        for (size_t l = 0; l < nl; l++) HIP_TRY(hipStreamWaitEvent(b.lanes[l], b.fork, 0));
-        for (int i = 0; i < np; i++) {
-            Ctx &c = *b.probs[i];
-            c.stream = b.lanes[i % nl];
-            if (phase < 4)
-                EDA_TRY(nystrom_phase(c, b.ell[i], phase));
-            else
-                EDA_TRY(nystrom_post_svd(c, b.ell[i], b.ell[i]));
+        for (auto &k : b.classes) {
+            HIP_TRY(hipStreamWaitEvent(k.side, b.fork, 0));
+            HIP_TRY(launch_hv_multi(k.side, b.d_hv, b.d_htasks + k.h_off, k.h_cnt, k.g, k.lds_hv));
+            HIP_TRY(hipEventRecord(k.done, k.side));
+            HIP_TRY(hipStreamWaitEvent(s, k.done, 0));
         }
-        for (size_t l = 0; l < nl; l++) {
-            HIP_TRY(hipEventRecord(b.lane_done[l], b.lanes[l]));
-            HIP_TRY(hipStreamWaitEvent(s, b.lane_done[l], 0));
+        const size_t nl = b.lanes.size();
+        int lmax = 1;
+        for (int l : b.ell) lmax = l > lmax ? l : lmax;
+        for (int phase = 0; phase < 5; phase++) {
+            HIP_TRY(hipEventRecord(b.fork, s));
+            for (size_t l = 0; l < nl; l++) HIP_TRY(hipStreamWaitEvent(b.lanes[l], b.fork, 0));
+            for (int i = 0; i < np; i++) {
+                Ctx &c = *b.probs[i];
+                c.stream = b.lanes[i % nl];
+                if (phase < 4)
+                    EDA_TRY(nystrom_phase(c, b.ell[i], phase));
+                else
+                    EDA_TRY(nystrom_post_svd(c, b.ell[i], b.ell[i], EDA_THETA_MID));
+            }
+            for (size_t l = 0; l < nl; l++) {
+                HIP_TRY(hipEventRecord(b.lane_done[l], b.lanes[l]));
+                HIP_TRY(hipStreamWaitEvent(s, b.lane_done[l], 0));
+            }
+            if (phase < 3) HIP_TRY(launch_chol_inv_batch(s, np, b.d_chol + (size_t)phase * np, lmax));
+            if (phase == 3) HIP_TRY(launch_jacobi_svd_batch(s, np, b.d_jobs, lmax));
         }
-        if (phase < 3) HIP_TRY(launch_chol_inv_batch(s, np, b.d_chol + (size_t)phase * np, lmax));
-        if (phase == 3) HIP_TRY(launch_jacobi_svd_batch(s, np, b.d_jobs, lmax));
+        if (b.timed_nodes) HIP_TRY(hipEventRecordWithFlags(b.tev[1], s, hipEventRecordExternal));
+        HIP_TRY(launch_nystrom_redo_batch(s, np, b.d_redo, lmax));
+        if (b.timed_nodes) HIP_TRY(hipEventRecordWithFlags(b.tev[2], s, hipEventRecordExternal));
     }
-    HIP_TRY(launch_gather_info(s, (int)b.probs.size(), b.d_infoptr, b.d_flags));
-    return EDA_OK;
-}
-
-// Enqueue the persistent solve: one launch over the tasks of every class.
-int batch_enqueue_solve(eda_batch &b) {
-    hipStream_t s = b.stream;
     HIP_TRY(launch_fill_int(s, SOLVE_QUEUES, 0, b.d_counters));
     HIP_TRY(launch_solve(s, b.d_solve, b.d_geom, b.d_stasks, (int)b.stasks.size(), b.d_qoff, b.d_counters,
                          b.solve_waves, b.solve_lds, b.solve_grid));
+    HIP_TRY(launch_task_iters(s, (int)b.stasks.size(), b.d_solve, b.d_stasks, b.d_titer));
+    if (b.use_lmp) HIP_TRY(launch_gather_info(s, np, b.d_infoptr, b.d_flags));
     return EDA_OK;
 }
 
 void batch_free_graph(eda_batch &b) {
     if (b.exec) (void)hipGraphExecDestroy(b.exec);
     if (b.graph) (void)hipGraphDestroy(b.graph);
-    if (b.exec_sk) (void)hipGraphExecDestroy(b.exec_sk);
-    if (b.graph_sk) (void)hipGraphDestroy(b.graph_sk);
-    b.exec = b.exec_sk = nullptr;
-    b.graph = b.graph_sk = nullptr;
+    b.exec = nullptr;
+    b.graph = nullptr;
 }
 
 // Capture what `enqueue` puts on b.stream into an instantiated graph.
@@ -1623,199 +1642,6 @@ int batch_capture(eda_batch &b, int (*enqueue)(eda_batch &), hipGraph_t &graph, 
         graph = nullptr;
         exec = nullptr;
         return EDA_ERR_HIP;
-    }
-    return EDA_OK;
-}
-
-double now_ms() {
-    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
-}  // namespace
-
-namespace {
-
-// Lockstep shifted sketch.  For the problems whose unshifted sketch in the
-// graph failed, what eda_sketch_evd computes (RHS differences, one pass,
-// Nystrom, theta mid, FP64 products): CholQR2 of Y = A Gamma (CholQR3 with the
-// trace shift when the first Cholesky fails), W = Gamma^T Y and its Cholesky,
-// on failure the Nystrom shift Y + nu Gamma and the same again, then T, the
-// SVD, S and the LMP coefficients -- per problem the same kernels, arguments
-// and decisions, on the Y the graph already holds.  The problems are spread
-// over the batch's lanes and each decision waits once for all of them.
-// ok[t] = 0: the Cholesky failed after the shifts (EDA_ERR_NOT_SPD there).
-int batch_fallback(eda_batch &b, const std::vector<int> &ids, std::vector<char> &ok) {
-    const int m = (int)ids.size();
-    ok.assign(m, 1);
-    if (m == 0) return EDA_OK;
-    const int np = (int)b.probs.size();
-    int lmax = 1;
-    for (int i : ids) lmax = b.ell[i] > lmax ? b.ell[i] : lmax;
-    const size_t ds = (size_t)lmax + 2;  // doubles per problem: diag(G) or ||Y||^2, then theta
-    if (!b.h_fbi) {
-        HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&b.h_fbi), sizeof(int32_t) * 8 * (size_t)np,
-                              hipHostMallocDefault));
-        HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&b.h_fbd), sizeof(double) * 130 * (size_t)np,
-                              hipHostMallocDefault));
-    }
-    const int nl = (int)b.lanes.size();
-    auto lane = [&](int t) { return b.lanes[t % nl]; };
-    auto wait_all = [&]() -> int {
-        for (auto st : b.lanes) HIP_TRY(hipStreamSynchronize(st));
-        return EDA_OK;
-    };
-    std::vector<double> nu(m, 0.0);
-    std::vector<int> passes(m, 2);
-    auto small = [&](int t, int slot) {
-        const Ctx &c = *b.probs[ids[t]];
-        return c.sk_small + (size_t)slot * c.max_ell * c.max_ell;
-    };
-    int32_t *hi = b.h_fbi;
-    double *hd = b.h_fbd;
-    // CholQR of each selected problem's Y into (Q, R_Y), as cholqr() does
-    auto cholqr = [&](const std::vector<int> &sel) -> int {
-        for (int t : sel) {
-            Ctx &c = *b.probs[ids[t]];
-            const int l = b.ell[ids[t]];
-            hipStream_t st = lane(t);
-            HIP_TRY(gemm_f64(st, true, l, l, c.n, c.sk_y, c.n, c.sk_y, c.n, small(t, 0), l, nullptr, 0, nullptr,
-                             c.splitk, c.splitk_elems));
-            HIP_TRY(launch_chol_inv(st, l, small(t, 0), 0.0, small(t, 1), small(t, 2), c.sk_info + 4));
-            HIP_TRY(hipMemcpyAsync(hi + 8 * t, c.sk_info + 4, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        }
-        EDA_TRY(wait_all());
-        std::vector<int> shifted;
-        for (int t : sel) {
-            passes[t] = 2;
-            if (hi[8 * t] == 0) continue;
-            shifted.push_back(t);
-            passes[t] = 3;
-            const int l = b.ell[ids[t]];
-            HIP_TRY(hipMemcpy2DAsync(hd + ds * t, sizeof(double), small(t, 0), sizeof(double) * (l + 1),
-                                     sizeof(double), l, hipMemcpyDeviceToHost, lane(t)));
-        }
-        if (!shifted.empty()) {
-            EDA_TRY(wait_all());
-            for (int t : shifted) {
-                Ctx &c = *b.probs[ids[t]];
-                const int l = b.ell[ids[t]];
-                double tr = 0.0;
-                for (int i = 0; i < l; i++) tr += hd[ds * t + i];
-                const double shift = 11.0 * ((double)c.n * l + (double)l * (l + 1)) * 2.220446049250313e-16 * tr;
-                HIP_TRY(launch_chol_inv(lane(t), l, small(t, 0), shift, small(t, 1), small(t, 2), c.sk_info + 4));
-                HIP_TRY(hipMemcpyAsync(hi + 8 * t, c.sk_info + 4, sizeof(int32_t), hipMemcpyDeviceToHost, lane(t)));
-            }
-            EDA_TRY(wait_all());
-            for (int t : shifted)
-                if (hi[8 * t] != 0) ok[t] = 0;
-        }
-        for (int t : sel) {
-            if (!ok[t]) continue;
-            Ctx &c = *b.probs[ids[t]];
-            const int l = b.ell[ids[t]];
-            hipStream_t st = lane(t);
-            HIP_TRY(gemm_f64(st, false, c.n, l, l, c.sk_y, c.n, small(t, 2), l, c.sk_q1, c.n, nullptr, 0, nullptr,
-                             nullptr, 0));
-            HIP_TRY(launch_copy_cols(st, l, l, small(t, 1), l, small(t, 5), l));
-            const double *Qin = c.sk_q1;
-            for (int pass = 2; pass <= passes[t]; pass++) {
-                double *Qout = (pass == passes[t]) ? c.sk_q : (Qin == c.sk_q1 ? c.sk_s : c.sk_q1);
-                HIP_TRY(gemm_f64(st, true, l, l, c.n, Qin, c.n, Qin, c.n, small(t, 0), l, nullptr, 0, nullptr,
-                                 c.splitk, c.splitk_elems));
-                HIP_TRY(launch_chol_inv(st, l, small(t, 0), 0.0, small(t, 3), small(t, 4), c.sk_info + 4 + pass));
-                HIP_TRY(gemm_f64(st, false, c.n, l, l, Qin, c.n, small(t, 4), l, Qout, c.n, nullptr, 0, nullptr,
-                                 nullptr, 0));
-                HIP_TRY(launch_small_gemm(st, l, false, false, small(t, 3), small(t, 5), small(t, 6)));
-                HIP_TRY(launch_copy_cols(st, l, l, small(t, 6), l, small(t, 5), l));
-                Qin = Qout;
-            }
-            HIP_TRY(launch_copy_cols(st, l, l, small(t, 5), l, small(t, 7), l));
-            HIP_TRY(hipMemcpyAsync(hi + 8 * t + 2, c.sk_info + 6, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        }
-        EDA_TRY(wait_all());
-        for (int t : sel)
-            if (ok[t] && (hi[8 * t + 2] != 0 || (passes[t] == 3 && hi[8 * t + 3] != 0))) ok[t] = 0;
-        return EDA_OK;
-    };
-    // W = Gamma^T Y, symmetrised; W = C^T C
-    auto cholw = [&](const std::vector<int> &sel) -> int {
-        for (int t : sel) {
-            if (!ok[t]) continue;
-            Ctx &c = *b.probs[ids[t]];
-            const int l = b.ell[ids[t]];
-            hipStream_t st = lane(t);
-            HIP_TRY(gemm_f64(st, true, l, l, c.n, c.sk_phi, c.n, c.sk_y, c.n, small(t, 8), l, nullptr, 0, nullptr,
-                             c.splitk, c.splitk_elems));
-            HIP_TRY(launch_sym(st, l, small(t, 8)));
-            HIP_TRY(launch_chol_inv(st, l, small(t, 8), 0.0, small(t, 9), small(t, 1), c.sk_info + 8));
-            HIP_TRY(hipMemcpyAsync(hi + 8 * t + 4, c.sk_info + 8, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        }
-        return wait_all();
-    };
-    std::vector<int> all(m);
-    for (int t = 0; t < m; t++) all[t] = t;
-    EDA_TRY(cholqr(all));
-    EDA_TRY(cholw(all));
-    std::vector<int> shiftw;
-    for (int t = 0; t < m; t++)
-        if (ok[t] && hi[8 * t + 4] != 0) shiftw.push_back(t);
-    if (!shiftw.empty()) {
-        // the Nystrom shift: Y <- Y + nu Gamma, nu = eps ||Y||_F
-        for (int t : shiftw) {
-            Ctx &c = *b.probs[ids[t]];
-            const int l = b.ell[ids[t]];
-            double *dscal = reinterpret_cast<double *>(c.sk_info + 16);
-            HIP_TRY(gemm_f64(lane(t), true, 1, 1, c.n * l, c.sk_y, c.n * l, c.sk_y, c.n * l, dscal, 1, nullptr, 0,
-                             nullptr, c.splitk, c.splitk_elems));
-            HIP_TRY(hipMemcpyAsync(hd + ds * t, dscal, sizeof(double), hipMemcpyDeviceToHost, lane(t)));
-        }
-        EDA_TRY(wait_all());
-        for (int t : shiftw) {
-            Ctx &c = *b.probs[ids[t]];
-            nu[t] = 2.220446049250313e-16 * std::sqrt(hd[ds * t]);
-            HIP_TRY(launch_axpy_cols(lane(t), c.n, b.ell[ids[t]], nu[t], c.sk_phi, c.n, c.sk_y, c.n));
-        }
-        EDA_TRY(cholqr(shiftw));
-        EDA_TRY(cholw(shiftw));
-        for (int t : shiftw)
-            if (ok[t] && hi[8 * t + 4] != 0) ok[t] = 0;
-    }
-    // T = R_Y C^-1; the SVDs T = U Sigma V^T of all of them in one launch
-    // (one workgroup each); S = Q_Y U, D = Sigma^2 - nu
-    std::vector<JacobiJob> jobs;
-    for (int t = 0; t < m; t++) {
-        if (!ok[t]) continue;
-        const int l = b.ell[ids[t]];
-        HIP_TRY(launch_small_gemm(lane(t), l, false, false, small(t, 7), small(t, 1), small(t, 2)));
-        jobs.push_back(JacobiJob{l, small(t, 2), small(t, 3), small(t, 4)});
-    }
-    if (!jobs.empty()) {
-        HIP_TRY(hipMemcpyAsync(b.d_fbjobs, jobs.data(), sizeof(JacobiJob) * jobs.size(), hipMemcpyHostToDevice,
-                               b.lanes[0]));
-        EDA_TRY(wait_all());
-        HIP_TRY(launch_jacobi_svd_batch(b.lanes[0], (int)jobs.size(), b.d_fbjobs, lmax));
-        HIP_TRY(hipEventRecord(b.lane_done[0], b.lanes[0]));
-        for (size_t l = 1; l < b.lanes.size(); l++) HIP_TRY(hipStreamWaitEvent(b.lanes[l], b.lane_done[0], 0));
-    }
-    for (int t = 0; t < m; t++) {
-        if (!ok[t]) continue;
-        Ctx &c = *b.probs[ids[t]];
-        const int l = b.ell[ids[t]];
-        hipStream_t st = lane(t);
-        double *dscal = reinterpret_cast<double *>(c.sk_info + 16);
-        HIP_TRY(gemm_f64(st, false, c.n, l, l, c.sk_q, c.n, small(t, 3), l, c.sk_s, c.n, nullptr, 0, nullptr, nullptr,
-                         0));
-        HIP_TRY(launch_fix_signs(st, c.n, l, c.sk_s, c.n));
-        HIP_TRY(launch_lmp_coef(st, l, small(t, 4), nu[t], 1, EDA_THETA_MID, c.sk_eig, c.sk_coef, c.sk_coefu,
-                                dscal + 1));
-        HIP_TRY(hipMemcpyAsync(hd + ds * t + lmax, dscal + 1, sizeof(double), hipMemcpyDeviceToHost, st));
-    }
-    EDA_TRY(wait_all());
-    for (int t = 0; t < m; t++) {
-        if (!ok[t]) continue;
-        Ctx &c = *b.probs[ids[t]];
-        c.theta = hd[ds * t + lmax];
-        c.k = b.ell[ids[t]];
     }
     return EDA_OK;
 }
@@ -1854,6 +1680,8 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
         for (auto ev : b->lane_done) (void)hipEventDestroy(ev);
         if (b->fork) (void)hipEventDestroy(b->fork);
         if (b->entry) (void)hipEventDestroy(b->entry);
+        for (auto ev : b->tev)
+            if (ev) (void)hipEventDestroy(ev);
         if (b->stream) (void)hipStreamDestroy(b->stream);
         delete b;
         return code;
@@ -1861,6 +1689,8 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
     b->user = reinterpret_cast<hipStream_t>(stream);
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) return fail(EDA_ERR_HIP);
     if (hipEventCreateWithFlags(&b->entry, hipEventDisableTiming) != hipSuccess) return fail(EDA_ERR_HIP);
+    for (auto &ev : b->tev)
+        if (hipEventCreate(&ev) != hipSuccess) return fail(EDA_ERR_HIP);
     // everything already enqueued on the caller's stream (the problems' set-up) comes first
     if (hipEventRecord(b->entry, b->user) != hipSuccess || hipStreamWaitEvent(b->stream, b->entry, 0) != hipSuccess)
         return fail(EDA_ERR_HIP);
@@ -1873,7 +1703,7 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
     b->d_qoff = reinterpret_cast<int *>(b->ws + P.off_qoff);
     b->d_geom = reinterpret_cast<TladGeom *>(b->ws + P.off_geom);
     b->d_jobs = reinterpret_cast<JacobiJob *>(b->ws + P.off_jobs);
-    b->d_fbjobs = reinterpret_cast<JacobiJob *>(b->ws + P.off_fbjobs);
+    b->d_redo = reinterpret_cast<RedoJob *>(b->ws + P.off_redo);
     b->d_chol = reinterpret_cast<CholJob *>(b->ws + P.off_chol);
     b->d_infoptr = reinterpret_cast<const int32_t **>(b->ws + P.off_iptr);
     b->d_flags = reinterpret_cast<int32_t *>(b->ws + P.off_flags);
@@ -1984,6 +1814,10 @@ int eda_batch_solve(eda_batch *b, int32_t k_cap, double rtol, int32_t maxit, int
         }
         HIP_TRY(hipMemcpyAsync(b->d_jobs, jobs.data(), sizeof(JacobiJob) * np, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(b->d_chol, cjobs.data(), sizeof(CholJob) * cjobs.size(), hipMemcpyHostToDevice, s));
+        std::vector<RedoJob> rjobs(np);
+        for (int i = 0; i < np; i++)
+            rjobs[i] = redo_job(*b->probs[i], b->ell[i], b->ell[i], EDA_THETA_MID, 2.220446049250313e-16);
+        HIP_TRY(hipMemcpyAsync(b->d_redo, rjobs.data(), sizeof(RedoJob) * np, hipMemcpyHostToDevice, s));
         // first queue layout from the expected cost of a column (one
         // iteration each); later calls use the measured cost
         b->stasks = st;
@@ -1991,73 +1825,59 @@ int eda_batch_solve(eda_batch *b, int32_t k_cap, double rtol, int32_t maxit, int
         for (size_t t = 0; t < st.size(); t++) cost0[t] = batch_step_cost(*b, st[t].prob);
         EDA_TRY(batch_schedule(*b, cost0));
         HIP_TRY(hipStreamSynchronize(s));
-        if (b->use_lmp) EDA_TRY(batch_capture(*b, batch_enqueue_sketch, b->graph_sk, b->exec_sk));
-        EDA_TRY(batch_capture(*b, batch_enqueue_solve, b->graph, b->exec));
-    }
-    // 1) sketches in one graph; 2) where an unshifted Cholesky failed, the
-    // host-driven sketch (shifted CholQR, Nystrom shift) redoes that problem's
-    // LMP, and a problem whose shifted sketch fails as well is marked for plain
-    // CG; 3) all solves in one graph.
-    int fallbacks = 0, unprec = 0;
-    double t0 = now_ms(), t1 = t0;
-    if (b->use_lmp) {
-        HIP_TRY(hipGraphLaunch(b->exec_sk, b->stream));
-        std::vector<int32_t> flags(np);
-        HIP_TRY(hipMemcpyAsync(flags.data(), b->d_flags, sizeof(int32_t) * np, hipMemcpyDeviceToHost, b->stream));
-        HIP_TRY(hipStreamSynchronize(b->stream));
-        t1 = now_ms();
-        std::vector<int> ids;
-        for (int i = 0; i < np; i++) {
-            Ctx &c = *b->probs[i];
-            c.have_lmp = true;
-            c.sr_ready = false;
-            c.k = b->ell[i];
-            if (flags[i] != 0) ids.push_back(i);
+        int rc = batch_capture(*b, batch_enqueue, b->graph, b->exec);
+        if (rc != EDA_OK && b->timed_nodes) {
+            // no event nodes inside the graph: time the graph as a whole
+            (void)hipGetLastError();
+            b->timed_nodes = false;
+            rc = batch_capture(*b, batch_enqueue, b->graph, b->exec);
         }
-        std::vector<char> ok;
-        EDA_TRY(batch_fallback(*b, ids, ok));
-        fallbacks = (int)ids.size();
-        for (size_t t = 0; t < ids.size(); t++) {
-            Ctx &c = *b->probs[ids[t]];
-            if (!ok[t]) {
-                unprec++;
-                c.have_lmp = false;
-                HIP_TRY(launch_fill_int(b->stream, 1, 1, c.sk_info));
-            } else {
-                HIP_TRY(launch_fill_int(b->stream, 3, 0, c.sk_info));
-            }
-        }
+        EDA_TRY(rc);
     }
-    const double t2 = now_ms();
+    // one graph: sketch, shifted redo where an unshifted Cholesky failed (a
+    // problem whose redo fails too is solved by plain CG), solve
+    const bool split = b->use_lmp && b->timed_nodes;
+    HIP_TRY(hipEventRecord(b->tev[0], b->stream));
     HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    HIP_TRY(hipEventRecord(b->tev[3], b->stream));
+    const int nt = (int)b->stasks.size();
+    std::vector<int32_t> its(2 * (size_t)nt), flags(2 * (size_t)np, 0);
+    HIP_TRY(hipMemcpyAsync(its.data(), b->d_titer, sizeof(int32_t) * 2 * nt, hipMemcpyDeviceToHost, b->stream));
+    if (b->use_lmp)
+        HIP_TRY(hipMemcpyAsync(flags.data(), b->d_flags, sizeof(int32_t) * 2 * np, hipMemcpyDeviceToHost, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
-    const double t3 = now_ms();
-    bool not_converged = false;
+    float ms[3] = {0.f, 0.f, 0.f};
+    if (split) {
+        HIP_TRY(hipEventElapsedTime(&ms[0], b->tev[0], b->tev[1]));
+        HIP_TRY(hipEventElapsedTime(&ms[1], b->tev[1], b->tev[2]));
+        HIP_TRY(hipEventElapsedTime(&ms[2], b->tev[2], b->tev[3]));
+    } else {
+        HIP_TRY(hipEventElapsedTime(&ms[2], b->tev[0], b->tev[3]));
+    }
+    for (int i = 0; i < 3; i++) b->last_ms[i] = ms[i];
+    int fallbacks = 0, unprec = 0;
+    for (int i = 0; b->use_lmp && i < np; i++) {
+        Ctx &c = *b->probs[i];
+        c.sr_ready = false;
+        c.k = b->ell[i];
+        c.have_lmp = flags[2 * i + 1] == 0;
+        fallbacks += flags[2 * i] != 0;
+        unprec += flags[2 * i + 1] != 0;
+    }
     // queue layout of the next call from the measured cost of each column
     // (iterations x window length)
-    {
-        const int nt = (int)b->stasks.size();
-        std::vector<int32_t> its(2 * (size_t)nt);
-        HIP_TRY(launch_task_iters(b->stream, nt, b->d_solve, b->d_stasks, b->d_titer));
-        HIP_TRY(hipMemcpyAsync(its.data(), b->d_titer, sizeof(int32_t) * 2 * nt, hipMemcpyDeviceToHost, b->stream));
-        HIP_TRY(hipStreamSynchronize(b->stream));
-        for (int t = 0; t < nt; t++)
-            if (its[nt + t] != EDA_MEMBER_CONVERGED) not_converged = true;
-        std::vector<long long> cost(nt);
-        for (int t = 0; t < nt; t++) cost[t] = (long long)its[t] * batch_step_cost(*b, b->stasks[t].prob);
-        EDA_TRY(batch_schedule(*b, cost));
-        HIP_TRY(hipStreamSynchronize(b->stream));
-    }
-    b->last_ms[0] = t1 - t0;
-    b->last_ms[1] = t2 - t1;
-    b->last_ms[2] = t3 - t2;
-    int warn = not_converged ? EDA_WARN_NOT_CONVERGED : EDA_OK;
+    bool not_converged = false;
+    for (int t = 0; t < nt; t++)
+        if (its[nt + t] != EDA_MEMBER_CONVERGED) not_converged = true;
+    std::vector<long long> cost(nt);
+    for (int t = 0; t < nt; t++) cost[t] = (long long)its[t] * batch_step_cost(*b, b->stasks[t].prob);
+    EDA_TRY(batch_schedule(*b, cost));
+    HIP_TRY(hipStreamSynchronize(b->stream));
     if (h_fallbacks) {
         h_fallbacks[0] = fallbacks;
         h_fallbacks[1] = unprec;
     }
-    HIP_TRY(hipStreamSynchronize(b->stream));
-    return warn;
+    return not_converged ? EDA_WARN_NOT_CONVERGED : EDA_OK;
 }
 
 int eda_batch_result(eda_batch *b, int32_t p, double *d_DZ, int64_t ldz, int32_t *h_iters, double *h_relres,
@@ -2116,8 +1936,8 @@ int eda_batch_destroy(eda_batch *b) {
     for (auto ev : b->lane_done) (void)hipEventDestroy(ev);
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->entry) (void)hipEventDestroy(b->entry);
-    if (b->h_fbi) (void)hipHostFree(b->h_fbi);
-    if (b->h_fbd) (void)hipHostFree(b->h_fbd);
+    for (auto ev : b->tev)
+        if (ev) (void)hipEventDestroy(ev);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return EDA_OK;

@@ -45,7 +45,7 @@ struct Ctx {
     int32_t *zero_members = nullptr;  // max_cols zeros (sketch mode)
     // sketch scratch
     double *sk_phi = nullptr, *sk_y = nullptr, *sk_q = nullptr, *sk_q1 = nullptr, *sk_s = nullptr;
-    double *sk_small = nullptr;  // 8 ell x ell matrices
+    double *sk_small = nullptr;  // 10 ell x ell matrices
     double *sk_eig = nullptr, *sk_coef = nullptr, *sk_coefu = nullptr;
     int32_t *sk_info = nullptr;
     double *lmp_t = nullptr;   // k x max_cols LMP coefficients S_k^T X
@@ -85,7 +85,6 @@ struct Ctx {
     // LMP state
     bool have_lmp = false;
     int k = 0;
-    double theta = 1.0;
 
     // profiling of the TL/AD kernel inside eda_pcg_solve
     int prof = 0;             // time every prof-th launch of the profiled kind (0: off)
@@ -126,7 +125,7 @@ struct PcgCols {
     // persistent solve: LMP z = r + S diag(coef) S^T r (lmp_k = 0: z = r)
     const double *lmp_s, *lmp_c;
     int lmp_k;
-    const int32_t *lmp_info;  // persistent solve: 3 Cholesky outcomes of the sketch; any nonzero: no LMP
+    const int32_t *lmp_info;  // persistent solve: nonzero when the problem's sketch gave no LMP
     // split iteration (TLAD_SPLIT): p is read from p and written to p_out (the
     // pieces of a column read each other's halos), (I + A) p goes to q and the
     // pieces' partial sums of p^T (I + A) p to pq_part[c * pieces + piece]
@@ -406,7 +405,8 @@ hipError_t launch_innov(hipStream_t s, int n, int N, int L, int p, int nv, int o
                         double *force, double *costc);
 // Periodic extension of trajectory rows: out[m][s][j] = traj[m][s][(j - pad_l) mod n],
 // j < ext_len, for states s < N of each of nm members (input rows N + 1 per member).
-// out[i] = info[i][0] | info[i][1] | info[i][2] (the sketch outcomes of a batch).
+// out[2 i], out[2 i + 1] = info[i][3], info[i][4]: whether problem i's sketch
+// was redone with shifts, and whether it ended without an LMP.
 hipError_t launch_gather_info(hipStream_t s, int np, const int32_t *const *info, int32_t *out);
 // p[0 .. count) = value (a kernel, so that it can sit in a captured graph).
 hipError_t launch_fill_int(hipStream_t s, int count, int value, int *p);
@@ -439,6 +439,30 @@ struct CholJob {
 };
 // One workgroup per job (device array); every job's l <= lmax <= 128.
 hipError_t launch_chol_inv_batch(hipStream_t s, int njobs, const CholJob *d_jobs, int lmax);
+// The shifted Nystrom sketch of one problem on the device (small_la.hip): from
+// Y = A Phi, CholQR2 with the shifted first pass when needed, W = Phi^T Y and
+// its Cholesky, the Nystrom shift nu = u ||Y||_F when that fails, then T, its
+// SVD, S = Q U(:, 1:k), signs and the LMP coefficients.  With trigger set it
+// runs only if one of trigger[0..2] (the unshifted Choleskys) is nonzero.
+// state[0] = 1 if it ran, state[1] = 1 if it ran and a Cholesky still failed
+// (no LMP), state[2] is its Cholesky scratch.  small: 10 slots of ls doubles
+// (slots as the host path: 0 G, 1 R1 then C^-1, 2 R1^-1 then T, 3 R2 then U,
+// 4 R2^-1 then sigma, 5-6 R products, 7 R_Y, 8 W, 9 C).
+struct RedoJob {
+    int n, l, k, rule;
+    double u;                 // unit roundoff of the products that formed Y
+    const int32_t *trigger;   // null: always run
+    int32_t *state;
+    const double *phi;        // n x l
+    double *y, *q1, *q2, *q;  // n x l: Y (shifted in place), two scratch bases, Q
+    double *s;                // n x k: the Ritz basis
+    double *small;
+    long long ls;
+    double *eig, *coef, *coefu, *theta;
+};
+hipError_t launch_nystrom_redo(hipStream_t s, const RedoJob &job);
+// One workgroup per job (device array); every job's l <= lmax <= 128.
+hipError_t launch_nystrom_redo_batch(hipStream_t s, int njobs, const RedoJob *d_jobs, int lmax);
 hipError_t launch_jacobi_eig(hipStream_t s, int l, double *T, double *Vwork, double *V, double *lam);
 hipError_t launch_fix_signs(hipStream_t s, int n, int k, double *S, long long lds);
 hipError_t launch_lmp_coef(hipStream_t s, int k, const double *sig, double nu, int square,

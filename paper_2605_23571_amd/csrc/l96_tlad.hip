@@ -805,7 +805,7 @@ __device__ __forceinline__ void solve_column(const TladArgs &a, const TladGeom &
     __syncthreads();
     if (!(bb > 0)) return;
     // a sketch whose Cholesky failed gives no LMP: plain CG for its members
-    const bool lmp = pc.lmp_k > 0 && !(pc.lmp_info && (pc.lmp_info[0] | pc.lmp_info[1] | pc.lmp_info[2]));
+    const bool lmp = pc.lmp_k > 0 && !(pc.lmp_info && pc.lmp_info[0]);
     if (lmp) {
         lmp_column(pc, n, r, z, reinterpret_cast<double *>(smraw), s_t, nthr >> 6);
     } else {

@@ -213,7 +213,10 @@ __global__ void k_fill_int(int count, int value, int *__restrict__ p) {
 
 __global__ void k_gather_info(int np, const int32_t *const *__restrict__ info, int32_t *__restrict__ out) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < np) out[i] = info[i][0] | info[i][1] | info[i][2];
+    if (i < np) {
+        out[2 * i] = info[i][3];
+        out[2 * i + 1] = info[i][4];
+    }
 }
 
 }  // namespace

@@ -40,6 +40,7 @@ EDA_XCH_OFF, EDA_XCH_ON = 0, 1
 EDA_PROF_TLAD, EDA_PROF_UB_GEMM = 0, 1
 EDA_LMP_NOALLOC_SCRATCH_BYTES = 4194304
 FIELDS = dict(truth=0, xb=1, traj=2, y=3, d=4, b=5, costc=6, ubrow=7, S=8, eig=9)
+EDA_FIELD_SKETCH_INFO = 10
 THETA_RULES = {"mid": EDA_THETA_MID, "lamk": EDA_THETA_LAMK, "one": EDA_THETA_ONE}
 
 
@@ -336,7 +337,7 @@ def eda_batch_tuning(batch) -> list[dict]:
 def eda_batch_timing(batch) -> dict:
     out = (ctypes.c_double * 3)()
     _check("eda_batch_timing", lib().eda_batch_timing(batch, out))
-    return dict(sketch_graph_ms=out[0], host_sketch_ms=out[1], solve_graph_ms=out[2])
+    return dict(sketch_ms=out[0], shifted_redo_ms=out[1], solve_ms=out[2])
 
 
 def eda_batch_destroy(batch):
@@ -498,6 +499,13 @@ class Problem:
         torch = _torch()
         off, cnt = eda_field(self.ctx, FIELDS[name])
         return self.ws[off:off + 8 * cnt].view(torch.float64)
+
+    def sketch_info(self) -> np.ndarray:
+        """The last Nystrom sketch's outcomes: the three unshifted Cholesky
+        results, whether the shifted pass ran, whether it failed."""
+        torch = _torch()
+        off, cnt = eda_field(self.ctx, EDA_FIELD_SKETCH_INFO)
+        return self.ws[off:off + 4 * cnt].view(torch.int32).cpu().numpy()
 
     def hessvec(self, members, X, add_identity: bool = False, mixed: bool = False):
         torch = _torch()

@@ -79,11 +79,16 @@ def test_batch_matches_single_problem_path():
         assert (ref["status"] == res["status"]).all()
         # same method; the LMP sums in another order, so the CG recurrences see
         # different rounding, and finite-precision CG iteration counts to a fixed
-        # tolerance drift with it: each member within 10% (at least 3), the
-        # median within 3%
-        tol = np.maximum(3, (0.10 * ref["iters"]).astype(int))
-        assert (np.abs(res["iters"] - ref["iters"]) <= tol).all(), (p, res["iters"], ref["iters"])
-        assert abs(np.median(res["iters"]) - np.median(ref["iters"])) <= max(2, 0.03 * np.median(ref["iters"]))
+        # tolerance drift with it (measured on MI355X: at most 3 iterations per
+        # member, 3% of the count above 30 iterations): each member within 5%
+        # (at least 3), the median within 2% (at least 2)
+        d = np.abs(res["iters"] - ref["iters"])
+        dm = abs(np.median(res["iters"]) - np.median(ref["iters"]))
+        print(f"[batch] problem {p}: iterations {int(np.median(ref['iters']))} (median), batch vs single "
+              f"max |diff| {int(d.max())}, max rel {float((d / ref['iters']).max()):.3f}, median diff {dm}", flush=True)
+        tol = np.maximum(3, (0.05 * ref["iters"]).astype(int))
+        assert (d <= tol).all(), (p, res["iters"], ref["iters"])
+        assert dm <= max(2, 0.02 * np.median(ref["iters"]))
         a, r = res["dz"].cpu().numpy(), ref["dz"].cpu().numpy()
         # both satisfy ||r|| <= 1e-6 ||b||; their difference is bounded by the
         # two solution errors
@@ -178,10 +183,11 @@ def test_batch_near_full_rank_sketch_still_solves():
 
 
 def test_batch_fallback_equals_single_problem_sketch():
-    # Problems whose unshifted sketch fails in the graph are redone in lockstep
-    # (shifted CholQR, Nystrom shift): per problem the kernels, arguments and
-    # decisions of eda_sketch_evd, so the eigenvalues and the Ritz basis are
-    # those of the single-problem sketch bit for bit (or both end NOT_SPD).
+    # Problems whose unshifted sketch fails in the graph are redone on the
+    # device (shifted CholQR3, Nystrom shift) by the kernel eda_sketch_evd runs
+    # on the same Y and Gamma, so the outcomes, the eigenvalues and the Ritz
+    # basis are those of the single-problem sketch bit for bit (or both end
+    # NOT_SPD).
     shapes = ((40, 10, 2.0), (40, 20, 2.0), (128, 10, 2.0), (64, 12, 2.0), (96, 8, 3.0))
     cfgs = [W.config("C2", n=n, nsteps=N, members=40, ell=32, k=32, len_b=lb, problem_id=300 + i, spinup=100)
             for i, (n, N, lb) in enumerate(shapes)]
@@ -201,7 +207,15 @@ def test_batch_fallback_equals_single_problem_sketch():
         except eda.EdaError as e:
             assert e.code == eda.EDA_ERR_NOT_SPD
             single_ok = False
+        info_s = g.sketch_info()
         g.close()
+        info_b = probs[p].sketch_info()
+        print(f"[batch] problem {p}: unshifted outcomes {info_b[:3].tolist()}, redone {info_b[3]}, "
+              f"failed {info_b[4]}", flush=True)
+        # the second outcome factors Q1^T Q1, Q1 = Y R1^-1: defined only when the first succeeded
+        same = [0, 2, 3, 4] + ([1] if info_b[0] == 0 else [])
+        assert np.array_equal(info_b[same], info_s[same]), (p, info_b, info_s)
+        assert info_b[3] == int(info_b[:3].any()) and info_b[4] == int(not single_ok)
         try:
             eig_b = probs[p].field("eig").cpu().numpy()
             S_b = probs[p].field("S").cpu().numpy()

@@ -368,6 +368,61 @@ def test_sketch_errors():
     g.close()
 
 
+def test_shifted_pass_against_oracle():
+    # ell = 32 RHS differences on small rings: Gamma and A Gamma are numerically
+    # rank-deficient, an unshifted Cholesky of the last pass fails and the
+    # device-side shifted pass (CholQR3 with the trace shift, then the Nystrom
+    # shift nu = eps ||Y||_F) takes over.  Its eigenvalues match the oracle's --
+    # which takes Householder QR and its own shift decision.  The core is
+    # numerically singular (condition kappa ~ 1/eps), so relative bars do not
+    # apply: T = R_Y C^-1 with C the Cholesky factor of the core carries
+    # ||dT|| ~ sqrt(kappa) eps ||T||, and Weyl's inequality moves each
+    # d_i = sigma_i^2 by at most 2 sigma_1 ||dT|| ~ 2 sqrt(kappa) eps d_1, plus
+    # nu where a shift is taken: |d_i - d_i'| <= 16 (2 sqrt(kappa) eps d_1 + nu);
+    # the leading eigenvalue to 1e-10 relative.  The LMP still gives the exact
+    # solution.  A problem whose shifted pass fails too reports it.
+    shapes = ((40, 10, 2.0), (40, 20, 2.0), (128, 10, 2.0), (64, 12, 2.0), (96, 8, 3.0))
+    redone = 0
+    for i, (n, N, lb) in enumerate(shapes):
+        cfg = W.config("C2", n=n, nsteps=N, members=40, ell=32, k=32, len_b=lb, problem_id=300 + i, spinup=100)
+        z = W.problem_normals(cfg)
+        g = eda.Problem(cfg, z)
+        try:
+            eig, th = g.sketch_evd("rhs_diff", ell=32, k=32)
+            ok = True
+        except eda.EdaError as e:
+            assert e.code == eda.EDA_ERR_NOT_SPD
+            ok = False
+        info = g.sketch_info()
+        print(f"[shifted] n={n} N={N}: unshifted outcomes {info[:3].tolist()}, redone {info[3]}, failed {info[4]}",
+              flush=True)
+        assert info[3] == int(info[:3].any()) and info[4] == int(not ok)
+        if not ok or not info[3]:
+            g.close()
+            continue
+        redone += 1
+        o = O.Problem(cfg, z)
+        Aop = lambda V: o.A(V, [0] * V.shape[1])
+        S, D, oinfo = O.nystrom(Aop, o.gamma(32), 32)
+        eps = np.finfo(float).eps
+        nu = eps * np.linalg.norm(Aop(o.gamma(32)))
+        bar = 16.0 * (2.0 * np.sqrt(oinfo["cond_core"]) * eps * D[0] + nu)
+        dev = np.abs(eig - D)
+        print(f"[shifted]   cond(core) {oinfo['cond_core']:.1e}, oracle shift {oinfo['shift']:.1e}, nu {nu:.1e}; "
+              f"rel err d_1 {dev[0] / D[0]:.1e}; max |d_i - d_i'| / bar {dev.max() / bar:.3f} "
+              f"(bar {bar / D[0]:.1e} d_1)", flush=True)
+        assert np.all(np.isfinite(eig)) and np.all(eig >= 0)
+        assert dev[0] < 1e-10 * D[0] and np.all(dev <= bar), (dev / D[0], bar / D[0])
+        members = [0, 7, cfg["members"]]
+        out = g.pcg(members, rtol=1e-10, maxit=3000)
+        assert (out["status"] == eda.EDA_MEMBER_CONVERGED).all()
+        for j, m in enumerate(members):
+            ex = O.exact_solution(o, m)
+            assert np.linalg.norm(out["dz"][j].cpu().numpy() - ex) / np.linalg.norm(ex) < 1e-6
+        g.close()
+    assert redone >= 1
+
+
 # -------------------------------------------------------------------- PCG --
 def test_pcg_c1_fixed_iterations():
     # C1: exactly 50 iterations.  Past convergence to rounding the iterates of
