@@ -107,7 +107,7 @@ def pcg_kernel_bytes_per_col(cfg):
     return 8 * (2 * N * n + 2 * nt * nv + 6 * n)
 
 
-def run_form(cfg, z, ub_mode, steps, warmup, hv_reps, mixed=False, keep=False, q=1):
+def run_form(cfg, z, ub_mode, steps, warmup, hv_reps, mixed=False, keep=False, q=1, lmp_form=None):
     import torch
     from paper_2605_23571_amd import eda
 
@@ -116,6 +116,8 @@ def run_form(cfg, z, ub_mode, steps, warmup, hv_reps, mixed=False, keep=False, q
     g = eda.Problem(cfg, z, ub_mode=ub_mode)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    if lmp_form is not None:
+        eda.eda_set_lmp_form(g.ctx, lmp_form)
     members = np.arange(L + 1)
 
     def step():
@@ -548,7 +550,10 @@ def main():
     # U_B, the second Nystrom pass, the FP32 sketch products
     ablation = {}
     if not a.no_plain:
-        for name, kw in (("banded_q1_fp64", dict(mixed=False, q=1)), ("banded_q2_fp64", dict(mixed=False, q=CHOSEN_Q))):
+        from paper_2605_23571_amd import eda
+        legs = (("banded_q1_fp64", dict(mixed=False, q=1)), ("banded_q2_fp64", dict(mixed=False, q=CHOSEN_Q)),
+                ("chosen_lmp_one_launch", dict(mixed=True, q=CHOSEN_Q, lmp_form=eda.EDA_LMP_FORM_ONE)))
+        for name, kw in legs:
             print(f"[bench] {a.workload} {name}", file=sys.stderr, flush=True)
             r = run_form(cfg, z, "banded", max(1, a.steps // 2), 1 if a.warmup else 0, 2, **kw)
             ablation[name] = {"value": round(r["solves_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 3),
@@ -600,6 +605,7 @@ def main():
             "banded U_B, q=1, FP64": ablation["banded_q1_fp64"]["value"],
             f"banded U_B, q={CHOSEN_Q}, FP64": ablation["banded_q2_fp64"]["value"],
             f"chosen: banded U_B, q={CHOSEN_Q}, FP32 sketch products": round(chosen["solves_per_s"], 3),
+            "chosen with the one-launch LMP (tile barriers)": ablation["chosen_lmp_one_launch"]["value"],
             "iters_median": {k: v["iters_median"] for k, v in ablation.items()}}
     if plain and plain.get("gemm"):
         gm = plain["gemm"]

@@ -90,6 +90,10 @@ extern "C" {
 #define EDA_LMP_P  0             /* apply P_theta                                            */
 #define EDA_LMP_U  1             /* apply the symmetric factor U_theta                       */
 
+#define EDA_LMP_FORM_TWO 0       /* eda_set_lmp_form: projection and expansion, two launches    */
+                                 /* (default)                                                   */
+#define EDA_LMP_FORM_ONE 1       /* eda_set_lmp_form: one launch with tile barriers             */
+
 /* ---- problem description ----
  * Lorenz-96 (numerical-experiments section): n >= 4 cyclic variables, forcing F,
  * RK4 step dt, window of nsteps steps.  Observations (direct, R = sigma_o^2 I)
@@ -382,11 +386,26 @@ int eda_set_split(eda_ctx *ctx, int32_t pieces);
  * whenever a launch shape exists for the running columns).  spin_limit:
  * polls of one wait before it gives up; < 0 restores the default (about a
  * second); 0 makes every wait give up at once (to exercise the error path).
- * A wait that gives up stops its member with EDA_MEMBER_BREAKDOWN and makes
+ * The limit also bounds the tile barriers of the single-launch LMP
+ * (eda_set_lmp_form).  A wait that gives up stops its member with
+ * EDA_MEMBER_BREAKDOWN (exchange) or voids the call's results (LMP) and makes
  * eda_pcg_solve return EDA_ERR_SYNC; so does a workgroup placed on an XCD other
  * than the one the layout assumes.  Solutions agree with the other forms to
  * rounding.  Errors: EDA_ERR_INVALID_ARG for other modes. */
 int eda_set_exchange(eda_ctx *ctx, int32_t mode, int64_t spin_limit);
+
+/* Form of the LMP inside eda_pcg_solve (the spectral LMP subsection: z = r +
+ * S_k diag(c) S_k^T r for every running member).  EDA_LMP_FORM_TWO (default):
+ * a projection launch and an expansion launch.  EDA_LMP_FORM_ONE: one launch,
+ * a workgroup per (256-row block, 16-column tile) computes its partial
+ * projection, the workgroups of a tile meet at a barrier in device memory
+ * (bounded wait, see eda_set_exchange), then each expands its rows -- used
+ * when the launch's workgroups fit the compute units at once (one each), else
+ * the two-launch form.  Both forms give the same bits; on MI355X the
+ * two-launch form is the faster one at the sizes measured (the barrier costs
+ * more than the launch boundary it replaces).  eda_lmp_apply always takes the
+ * two-launch form.  Errors: EDA_ERR_INVALID_ARG for other forms. */
+int eda_set_lmp_form(eda_ctx *ctx, int32_t form);
 
 /* Free the context's host structures (the workspace stays the caller's). */
 int eda_destroy(eda_ctx *ctx);

@@ -65,6 +65,7 @@ struct Plan {
     size_t off_x, off_r, off_z, off_pp, off_q, off_scal, off_status, off_iters, off_members, off_hist;
     size_t off_p2, off_pqp, off_fin;  // split PCG iterations (banded U_B)
     size_t off_xflags, off_xedges, off_xerr, off_xnseg, off_rzp;  // wave pieces with halo exchange
+    size_t off_lsync;                                             // single-launch LMP tile barriers
     size_t splitk_elems;
     size_t total;
 };
@@ -211,6 +212,7 @@ Plan make_plan(const eda_config *c) {
         P.off_xnseg = lay.take(mc * sizeof(int32_t));
         P.off_rzp = lay.take((size_t)LMP_RB_MAX * ((mc + 15) / 16 * 16) * d);
     }
+    P.off_lsync = lay.take(lmp_sync_words(P.maxc) * sizeof(unsigned int));
     P.total = lay.total;
     return P;
 }
@@ -598,6 +600,7 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
     c.xch_err = at<int32_t>(w, P.off_xerr);
     c.xch_nseg = at<int32_t>(w, P.off_xnseg);
     c.rz_part = at<double>(w, P.off_rzp);
+    c.lmp_sync = at<unsigned int>(w, P.off_lsync);
     band_taps(cfg, c.band_lo, c.band_hi);
     {
         int dev = 0;
@@ -623,7 +626,8 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
     // exchange flags start below every launch's phases; segment counts start empty
     if ((c.xch_flags && hipMemsetAsync(c.xch_flags, 0, sizeof(unsigned long long) * 9 * XCH_GRID_MAX, s) != hipSuccess) ||
         hipMemsetAsync(c.xch_nseg, 0, sizeof(int32_t) * c.max_cols, s) != hipSuccess ||
-        hipMemsetAsync(c.xch_err, 0, sizeof(int32_t), s) != hipSuccess)
+        hipMemsetAsync(c.xch_err, 0, sizeof(int32_t), s) != hipSuccess ||
+        hipMemsetAsync(c.lmp_sync, 0, sizeof(unsigned int) * lmp_sync_words(c.max_cols), s) != hipSuccess)
         return fail(EDA_ERR_HIP);
     // U_B
     if ((cfg->b_kind == EDA_B_DIFFUSION
@@ -777,14 +781,33 @@ namespace {
 
 // Y = X + S_k diag(coef) S_k^T X (coef: P_theta or U_theta coefficients);
 // inside PCG (status given) tiles of stopped members are skipped.
+// The tile barriers of the single-launch LMP (bounded waits report into the
+// exchange's error word, which eda_pcg_solve reads at its end).
+LmpSync lmp_sync(const Ctx &c) {
+    LmpSync y{};
+    const int tiles = (int)(lmp_sync_words(c.max_cols) / 2);
+    y.arrive = c.lmp_sync;
+    y.leave = c.lmp_sync + tiles;
+    y.tiles = tiles;
+    y.max_blocks = c.num_cus;
+    y.spin_max = c.xch_spin < 0 ? XCH_SPIN_DEFAULT : c.xch_spin;
+    y.err = c.xch_err;
+    return y;
+}
+
+// Inside eda_pcg_solve (pcg set) the LMP runs in the context's form; the
+// public eda_lmp_apply always takes the two-launch form, which has no wait.
 int lmp_apply(Ctx &c, int which, int nb, const double *X, long long ldx, double *Y, long long ldy,
-              const int32_t *status = nullptr, double *rz = nullptr) {
+              const int32_t *status = nullptr, double *rz = nullptr, bool pcg = false) {
     const double *coef = which == EDA_LMP_U ? c.sk_coefu : c.sk_coef;
     if (!c.sr_ready) {
         HIP_TRY(launch_lmp_rowmajor(c.stream, c.n, c.k, c.sk_s, c.sk_sr));
         c.sr_ready = true;
     }
-    HIP_TRY(launch_lmp(c.stream, c.n, c.k, nb, c.sk_s, c.sk_sr, coef, X, ldx, Y, ldy, status, c.lmp_work, rz));
+    const LmpSync sy = lmp_sync(c);
+    const bool one = pcg && c.lmp_form == EDA_LMP_FORM_ONE;
+    HIP_TRY(launch_lmp(c.stream, c.n, c.k, nb, c.sk_s, c.sk_sr, coef, X, ldx, Y, ldy, status, c.lmp_work, rz,
+                       one ? &sy : nullptr));
     return EDA_OK;
 }
 
@@ -816,8 +839,9 @@ int lmp_update(Ctx &c, int nb, const LmpFin &f) {
         HIP_TRY(launch_lmp_rowmajor(c.stream, c.n, c.k, c.sk_s, c.sk_sr));
         c.sr_ready = true;
     }
+    const LmpSync sy = lmp_sync(c);
     HIP_TRY(launch_lmp_fin(c.stream, c.n, c.k, nb, c.sk_s, c.sk_sr, c.sk_coef, c.pc_r, c.pc_z, c.pc_status,
-                           c.lmp_work, f, c.rz_part));
+                           c.lmp_work, f, c.rz_part, c.lmp_form == EDA_LMP_FORM_ONE ? &sy : nullptr));
     return EDA_OK;
 }
 
@@ -893,10 +917,13 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
     // update fused with the LMP of the new residual (which also leaves the
     // row-block partials of r^T z for the exchange form)
     const bool split = fused && use_lmp;
-    if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status, split ? c.rz_part : nullptr));
-    if (split) HIP_TRY(hipMemsetAsync(c.xch_err, 0, sizeof(int32_t), s));
+    if (use_lmp) {
+        // the bounded waits of this solve (halo exchange, LMP tile barriers) start clear
+        HIP_TRY(hipMemsetAsync(c.xch_err, 0, sizeof(int32_t), s));
+        HIP_TRY(hipMemsetAsync(c.lmp_sync, 0, sizeof(unsigned int) * lmp_sync_words(c.max_cols), s));
+        EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status, split ? c.rz_part : nullptr, true));
+    }
     const int xch_grid = (c.num_cus < XCH_GRID_MAX ? c.num_cus : XCH_GRID_MAX) & ~7;
-    bool xch_used = false;
     // Convergence checks are pipelined: every check_every iterations the status
     // array is copied to a pinned host slot behind an event; the host reads a
     // checkpoint once its event has completed, and waits only when more than
@@ -1022,12 +1049,11 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                     f.xbr_part = c.lmp_fin + lmp_fin_doubles(c.max_cols) / 2;
                     EDA_TRY(lmp_update(c, nm, f));
                     cur ^= 1;
-                    xch_used = true;
                 } else if (P == 1) {
                     // whole columns: the fused iteration (its update hidden under the
                     // TL/AD work), then the LMP of the new residual
                     EDA_TRY(fused_iteration(c, nm, a, pbuf[cur], rtol, it));
-                    EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status, c.rz_part));
+                    EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status, c.rz_part, true));
                 } else {
                     TladArgs t = tlad_args(c, nm, c.pc_members, nullptr);
                     t.obs = c.hv_obs;
@@ -1071,11 +1097,11 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
             } else if (fused) {
                 // one launch: p = z + beta p, q = (I + A) p, alpha, x, r, convergence
                 EDA_TRY(fused_iteration(c, nm, a, c.pc_p, rtol, it));
-                if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status));
+                if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status, nullptr, true));
             } else {
                 EDA_TRY(hessvec(c, c.pc_members, nm, c.pc_p, n, c.pc_q, n, EDA_HV_ADD_IDENTITY, c.pc_status));
                 HIP_TRY(launch_pcg_alpha(s, a, it));
-                if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status));
+                if (use_lmp) EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status, nullptr, true));
                 HIP_TRY(launch_pcg_beta(s, a));
             }
             if (it % check_every == 0 || it == maxit) {
@@ -1114,7 +1140,7 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
         h_relres[i] = scal[4 * i + 2];
         if (h_status[i] != EDA_MEMBER_CONVERGED) warn = EDA_WARN_NOT_CONVERGED;
     }
-    if (xch_used) {
+    if (use_lmp) {  // the exchange's or the LMP tile barriers' waits
         int32_t err = 0;
         EDA_TRY(sync_read(c, &err, c.xch_err, sizeof(int32_t)));
         if (err != 0) warn = EDA_ERR_SYNC;
@@ -1209,6 +1235,12 @@ int eda_set_exchange(eda_ctx *h, int32_t mode, int64_t spin_limit) {
     if (!h || (mode != EDA_XCH_ON && mode != EDA_XCH_OFF)) return EDA_ERR_INVALID_ARG;
     h->c.xch_mode = mode;
     h->c.xch_spin = spin_limit < 0 ? -1 : (long long)spin_limit;
+    return EDA_OK;
+}
+
+int eda_set_lmp_form(eda_ctx *h, int32_t form) {
+    if (!h || (form != EDA_LMP_FORM_TWO && form != EDA_LMP_FORM_ONE)) return EDA_ERR_INVALID_ARG;
+    h->c.lmp_form = form;
     return EDA_OK;
 }
 

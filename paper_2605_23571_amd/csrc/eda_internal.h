@@ -73,6 +73,8 @@ struct Ctx {
     double *xch_edges = nullptr;
     int32_t *xch_err = nullptr, *xch_nseg = nullptr;
     double *rz_part = nullptr;
+    unsigned int *lmp_sync = nullptr;  // tile barrier counters of the single-launch LMP (2 x tiles)
+    int lmp_form = EDA_LMP_FORM_TWO;
     unsigned long long xch_epoch = 0;
     int xch_mode = EDA_XCH_OFF;
     long long xch_spin = -1;
@@ -344,11 +346,24 @@ size_t lmp_work_doubles(int n, int k, int ncols);
 constexpr size_t LMP_NOALLOC_DOUBLES = (size_t)EDA_LMP_NOALLOC_SCRATCH_BYTES / sizeof(double);
 hipError_t lmp_noalloc_scratch(double **out);
 hipError_t launch_lmp_rowmajor(hipStream_t s, int n, int k, const double *S, double *Sr);
+// Tile barrier state of the single-launch LMP: per column tile an arrival and
+// a departure counter (zero between launches), the tiles provided, the most
+// workgroups that are resident at once (one per CU), the wait bound and the
+// error word (set to LMP_SYNC_ERR when a wait gives up).
+struct LmpSync {
+    unsigned int *arrive, *leave;
+    int tiles;
+    long long max_blocks, spin_max;
+    int32_t *err;
+};
+constexpr int32_t LMP_SYNC_ERR = 4;
+size_t lmp_sync_words(int ncols);
 // rz (optional): r^T z per (row block, column) with X = r and Y = z, rz[rb *
 // ldw + col], ldw = 16 ceil(nb / 16), summed over the block's rows in a fixed order.
+// sync (optional): one launch when the grid fits it, else (and without) two.
 hipError_t launch_lmp(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
                       const double *X, long long ldx, double *Y, long long ldy, const int32_t *status, double *work,
-                      double *rz = nullptr);
+                      double *rz = nullptr, const LmpSync *sync = nullptr);
 // The update half of a split PCG iteration, fused with the LMP of the new
 // residual: for every running column, alpha = rho / p^T (I + A) p (rho from
 // scal[4c + 3], the pieces' partial sums pq_part), x += alpha p, r -= alpha q,
@@ -366,7 +381,8 @@ struct LmpFin {
 };
 size_t lmp_fin_doubles(int ncols);
 hipError_t launch_lmp_fin(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
-                          double *r, double *z, int32_t *status, double *work, const LmpFin &f, double *rz = nullptr);
+                          double *r, double *z, int32_t *status, double *work, const LmpFin &f, double *rz = nullptr,
+                          const LmpSync *sync = nullptr);
 // BF16-operand, FP32-accumulate GEMM C = A B (+ Add): A in BF16 (M x K,
 // column-major), B, C, Add in FP64 (B rounded to BF16 as it is staged).
 hipError_t gemm_bf16(hipStream_t s, int M, int N, int K, const unsigned short *A, long long lda, const double *B,

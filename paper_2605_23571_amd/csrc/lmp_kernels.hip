@@ -4,16 +4,25 @@
 //   Y = X + S diag(coef) S^T X,   S: n x k orthonormal Ritz vectors (column-major),
 //                                 X, Y: n x nb (column-major, leading dims ldx, ldy).
 //
-// Two launches on the FP64 matrix cores (v_mfma_f64_16x16x4f64):
-//  * k_lmp_proj   -- workgroup (row block, tile of 16 columns): the partial
-//    projection S_b^T X_b of its rows onto every direction;
-//  * k_lmp_expand -- workgroup (256 rows, 16 columns): W = diag(coef) S^T X for
-//    its columns (the row blocks summed in block order, into LDS), then
-//    Y = X + S W.
-// Sums are taken in a fixed order, so results do not depend on scheduling; the
-// kernel boundary orders the two steps.  A column tile whose members have all
-// left the running state (status given) is skipped -- inside the PCG loop
-// converged members need no preconditioned residual.
+// Two steps on the FP64 matrix cores (v_mfma_f64_16x16x4f64), for a
+// workgroup per (row block of 256 rows, tile of 16 columns):
+//  * projection -- the partial projection S_b^T X_b of its rows onto every
+//    direction;
+//  * expansion -- W = diag(coef) S^T X for its columns (the row blocks summed
+//    in block order, into LDS), then Y = X + S W on its rows.
+// Either two launches (k_lmp_proj, k_lmp_expand: the kernel boundary orders
+// the steps) or one (k_lmp_one): the workgroups of a tile meet at a tile
+// barrier between the steps, which needs every workgroup of the launch
+// resident at once (one per CU; the host checks the grid against the CU
+// count).  Its waits are bounded: one that gives up sets an error word and
+// the results of that call are void.  Both forms do the same arithmetic in
+// the same order, so they give the same bits.  On MI355X the two launches are
+// the faster form (n = 4096, 129 columns: 7.5 + 9.2 us against 20.9 us; with
+// the update fused, 12.0 + 10.1 us against 29.2 us): the barrier's round trips
+// through device memory cost more than the launch boundary they replace.  Sums are taken in a fixed
+// order, so results do not depend on scheduling.  A column tile whose members
+// have all left the running state (status given) is skipped -- inside the
+// PCG loop converged members need no preconditioned residual.
 //
 // Operand layouts: in v_mfma_f64_16x16x4f64 lane l (g = l / 16, m = l % 16)
 // supplies A[m][g] and B[g][m]; element v of the accumulator is D[g + 4 v][m].
@@ -40,6 +49,37 @@ namespace {
 typedef double double4v __attribute__((ext_vector_type(4)));
 
 constexpr int CT = 16;         // columns per tile
+constexpr int RB = 256;        // rows per projection block
+constexpr int XP = RB + 1;     // odd row stride of the staged X: the 16 columns of one read fall in distinct banks
+
+// the projection step's LDS: staged X (xs[column][row]) and the waves' partial sums
+struct ProjLds {
+    double xs[CT][XP];
+    double red[8][4][4][64];  // [wave][j tile in group][v][lane]
+};
+template <int KM>
+struct ExpandLds {
+    double ws[KM][CT];
+    double rzs[8][CT];
+};
+
+// Device-scope (coherent across XCDs) loads and stores of the values that
+// the workgroups of a tile hand to each other in the single launch.
+__device__ __forceinline__ double load_agent(const double *p) {
+    return __longlong_as_double((long long)__hip_atomic_load(reinterpret_cast<const unsigned long long *>(p),
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void store_agent(double *p, double v) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// plain store, or device-scope store when the value crosses workgroups within a launch
+__device__ __forceinline__ void put(double *p, double v, bool shared) {
+    if (shared)
+        store_agent(p, v);
+    else
+        *p = v;
+}
 
 __device__ __forceinline__ bool tile_running(const int32_t *status, int c0, int nb) {
     if (!status) return true;
@@ -96,14 +136,15 @@ __global__ void k_lmp_rowmajor(int n, int k, const double *__restrict__ S, doubl
 //     are summed in wave order through LDS.
 // The first group's Sr operands are loaded before phase 1, so both phases wait
 // on one round trip to memory.
+// one: single launch (the partial sums go out as device-scope stores)
 template <bool FIN>
-__global__ __launch_bounds__(512) void k_lmp_proj(int n, int k, int nb, int rows, const double *__restrict__ Sr,
-                                                  double *X, long long ldx, const int32_t *__restrict__ status,
-                                                  double *__restrict__ part, int ldw, LmpFin f) {
-    constexpr int RB = 256, XP = RB + 1;  // odd row stride: the 16 columns of one read fall in distinct banks
-    __shared__ double xs[CT][XP];
-    __shared__ double red[8][4][4][64];  // [wave][j tile in group][v][lane]
-    const int rb = blockIdx.x, c0 = blockIdx.y * CT;
+__device__ __forceinline__ void lmp_proj(int rb, int tile, int n, int k, int nb, int rows,
+                                         const double *__restrict__ Sr, double *X, long long ldx,
+                                         const int32_t *__restrict__ status, double *__restrict__ part, int ldw,
+                                         const LmpFin &f, ProjLds &L, bool one) {
+    auto &xs = L.xs;
+    auto &red = L.red;
+    const int c0 = tile * CT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, m = lane & 15;
     const int r0 = rb * rows, r1 = min(n, r0 + rows);  // rows == RB
     const int w0 = r0 + wave * 32, w1 = min(r1, w0 + 32);
@@ -180,8 +221,8 @@ __global__ __launch_bounds__(512) void k_lmp_proj(int n, int k, int nb, int rows
                 xbr += __shfl_down(xbr, o, 32);
             }
             if (rl == 0 && colok) {
-                f.rr_part[(long long)rb * ldw + col] = rr;
-                f.xbr_part[(long long)rb * ldw + col] = xbr;
+                put(f.rr_part + (long long)rb * ldw + col, rr, one);
+                put(f.xbr_part + (long long)rb * ldw + col, xbr, one);
             }
         }
 #pragma unroll
@@ -218,11 +259,19 @@ __global__ __launch_bounds__(512) void k_lmp_proj(int n, int k, int nb, int rows
                 double s = 0.0;
 #pragma unroll
                 for (int w = 0; w < 8; w++) s += red[w][q][v][l];
-                part[((long long)rb * k + j) * ldw + c0 + (l & 15)] = s;
+                put(part + ((long long)rb * k + j) * ldw + c0 + (l & 15), s, one);
             }
         }
         __syncthreads();
     }
+}
+
+template <bool FIN>
+__global__ __launch_bounds__(512) void k_lmp_proj(int n, int k, int nb, int rows, const double *__restrict__ Sr,
+                                                  double *X, long long ldx, const int32_t *__restrict__ status,
+                                                  double *__restrict__ part, int ldw, LmpFin f) {
+    __shared__ ProjLds L;
+    lmp_proj<FIN>(blockIdx.x, blockIdx.y, n, k, nb, rows, Sr, X, ldx, status, part, ldw, f, L, false);
 }
 
 // Y = X + S W on 256 rows x 16 columns (eight waves).  Each thread loads, in
@@ -234,18 +283,22 @@ __global__ __launch_bounds__(512) void k_lmp_proj(int n, int k, int nb, int rows
 // column c0 + g + 4 v).  FIN: the first workgroup of the tile then ends the
 // iteration of its columns as the fused PCG kernel does (its inputs loaded at
 // the start).
+// xsl (single launch): X of this workgroup's rows, staged by its projection
+// step (X was updated there for FIN); the other workgroups' partial sums are
+// then read at device scope, past the CU's cache.
 template <int KM, bool FIN>
-__global__ __launch_bounds__(512) void k_lmp_expand(int n, int k, int nb, int nrb, const double *__restrict__ S,
-                                                    const double *__restrict__ coef, const double *X, long long ldx,
-                                                    double *Y, long long ldy, int32_t *status,
-                                                    const double *__restrict__ part, int ldw, LmpFin f,
-                                                    double *__restrict__ rz) {
+__device__ __forceinline__ void lmp_expand(int rbx, int tile, int n, int k, int nb, int nrb,
+                                           const double *__restrict__ S, const double *__restrict__ coef,
+                                           const double *X, long long ldx, double *Y, long long ldy,
+                                           int32_t *status, const double *__restrict__ part, int ldw,
+                                           const LmpFin &f, double *__restrict__ rz, ExpandLds<KM> &L,
+                                           const double (*xsl)[XP]) {
     constexpr int PE = KM * CT / 512;  // W entries per thread
-    __shared__ double ws[KM][CT];
-    __shared__ double rzs[8][CT];
-    const int c0 = blockIdx.y * CT;
+    auto &ws = L.ws;
+    auto &rzs = L.rzs;
+    const int c0 = tile * CT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, m = lane & 15;
-    const int ib = blockIdx.x * 256 + wave * 32;
+    const int ib = rbx * 256 + wave * 32;
     double pv[PE][LMP_RB_MAX];
 #pragma unroll
     for (int u = 0; u < PE; u++) {
@@ -253,7 +306,10 @@ __global__ __launch_bounds__(512) void k_lmp_expand(int n, int k, int nb, int nr
         const bool ok = e < k * CT;
         const double *pe = part + (long long)(ok ? e / CT : 0) * ldw + c0 + e % CT;
 #pragma unroll
-        for (int b = 0; b < LMP_RB_MAX; b++) pv[u][b] = (ok && b < nrb) ? pe[(long long)b * k * ldw] : 0.0;
+        for (int b = 0; b < LMP_RB_MAX; b++) {
+            const bool take = ok && b < nrb;
+            pv[u][b] = !take ? 0.0 : (xsl ? load_agent(pe + (long long)b * k * ldw) : pe[(long long)b * k * ldw]);
+        }
     }
     double xv[2][4];  // [row tile][v]
 #pragma unroll
@@ -261,18 +317,22 @@ __global__ __launch_bounds__(512) void k_lmp_expand(int n, int k, int nb, int nr
 #pragma unroll
         for (int v = 0; v < 4; v++) {
             const int i = ib + 16 * rt + m, col = c0 + g + 4 * v;
-            xv[rt][v] = (i < n && col < nb) ? X[(long long)col * ldx + i] : 0.0;
+            if (xsl)
+                xv[rt][v] = xsl[g + 4 * v][wave * 32 + 16 * rt + m];  // zero beyond n and nb
+            else
+                xv[rt][v] = (i < n && col < nb) ? X[(long long)col * ldx + i] : 0.0;
         }
     // FIN: the iteration-end inputs of column c0 + tid (first workgroup of the tile)
-    const bool fin_lane = FIN && blockIdx.x == 0 && tid < CT && c0 + tid < nb;
+    const bool fin_lane = FIN && rbx == 0 && tid < CT && c0 + tid < nb;
     const int fcol = fin_lane ? c0 + tid : 0;
     double rv[LMP_RB_MAX], xr[LMP_RB_MAX], fpq = 0.0, fbn = 0.0, frho = 0.0;
     int fst = 0;
     if (FIN) {
 #pragma unroll
         for (int b = 0; b < LMP_RB_MAX; b++) {
-            rv[b] = (fin_lane && b < nrb) ? f.rr_part[(long long)b * ldw + fcol] : 0.0;
-            xr[b] = (fin_lane && b < nrb && f.hist) ? f.xbr_part[(long long)b * ldw + fcol] : 0.0;
+            const double *pr = f.rr_part + (long long)b * ldw + fcol, *px = f.xbr_part + (long long)b * ldw + fcol;
+            rv[b] = (fin_lane && b < nrb) ? (xsl ? load_agent(pr) : *pr) : 0.0;
+            xr[b] = (fin_lane && b < nrb && f.hist) ? (xsl ? load_agent(px) : *px) : 0.0;
         }
         if (fin_lane) {
             fpq = pieces_sum(f, fcol);
@@ -346,7 +406,7 @@ __global__ __launch_bounds__(512) void k_lmp_expand(int n, int k, int nb, int nr
             double sum = 0.0;
 #pragma unroll
             for (int w = 0; w < 8; w++) sum += rzs[w][tid];
-            rz[(long long)blockIdx.x * ldw + c0 + tid] = sum;
+            rz[(long long)rbx * ldw + c0 + tid] = sum;
         }
     }
     if (FIN && fin_lane && fst == COL_RUNNING) {
@@ -372,6 +432,61 @@ __global__ __launch_bounds__(512) void k_lmp_expand(int n, int k, int nb, int nr
     }
 }
 
+template <int KM, bool FIN>
+__global__ __launch_bounds__(512) void k_lmp_expand(int n, int k, int nb, int nrb, const double *__restrict__ S,
+                                                    const double *__restrict__ coef, const double *X, long long ldx,
+                                                    double *Y, long long ldy, int32_t *status,
+                                                    const double *__restrict__ part, int ldw, LmpFin f,
+                                                    double *__restrict__ rz) {
+    __shared__ ExpandLds<KM> L;
+    lmp_expand<KM, FIN>(blockIdx.x, blockIdx.y, n, k, nb, nrb, S, coef, X, ldx, Y, ldy, status, part, ldw, f, rz, L,
+                        nullptr);
+}
+
+// The tile barrier of the single launch.  The values other workgroups read
+// (partial sums, FIN's row-block norms) went out as device-scope stores; each
+// thread waits until its stores have completed, then thread 0 raises the
+// tile's arrival counter and waits (bounded) until all nrb workgroups of the
+// tile have arrived.  The readers take those values with device-scope loads,
+// so no cache write-back or invalidation is needed.  The last workgroup to
+// leave resets both counters for the next launch.
+__device__ __forceinline__ void lmp_tile_barrier(const LmpSync &sy, int tile, int nrb) {
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(sy.arrive + tile, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bool ok = false;
+        for (long long it = 0; it < sy.spin_max; it++) {
+            if (__hip_atomic_load(sy.arrive + tile, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= (unsigned)nrb) {
+                ok = true;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (!ok) __hip_atomic_store(sy.err, LMP_SYNC_ERR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__hip_atomic_fetch_add(sy.leave + tile, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+            (unsigned)nrb - 1) {
+            __hip_atomic_store(sy.arrive + tile, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(sy.leave + tile, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    __syncthreads();
+}
+
+template <int KM, bool FIN>
+__global__ __launch_bounds__(512) void k_lmp_one(int n, int k, int nb, int rows, int nrb,
+                                                 const double *__restrict__ Sr, const double *__restrict__ S,
+                                                 const double *__restrict__ coef, double *X, long long ldx, double *Y,
+                                                 long long ldy, int32_t *status, double *__restrict__ part, int ldw,
+                                                 LmpFin f, double *__restrict__ rz, LmpSync sy) {
+    __shared__ ProjLds P;
+    __shared__ ExpandLds<KM> E;
+    lmp_proj<FIN>(blockIdx.x, blockIdx.y, n, k, nb, rows, Sr, X, ldx, status, part, ldw, f, P, true);
+    lmp_tile_barrier(sy, blockIdx.y, nrb);
+    lmp_expand<KM, FIN>(blockIdx.x, blockIdx.y, n, k, nb, nrb, S, coef, X, ldx, Y, ldy, status, part, ldw, f, rz,
+                        E, P.xs);
+}
+
 }  // namespace
 
 // Row blocks of the projection: 256 rows each (n <= 4096: at most LMP_RB_MAX).
@@ -394,19 +509,30 @@ hipError_t launch_lmp_rowmajor(hipStream_t s, int n, int k, const double *S, dou
     return hipGetLastError();
 }
 
+size_t lmp_sync_words(int ncols) { return 2 * (size_t)((ncols + CT - 1) / CT); }
+
 size_t lmp_fin_doubles(int ncols) { return 2 * (size_t)LMP_RB_MAX * ((size_t)(ncols + CT - 1) / CT * CT); }
 
 namespace {
 template <bool FIN>
 hipError_t lmp_launch(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
                       double *X, long long ldx, double *Y, long long ldy, int32_t *status, double *work,
-                      const LmpFin &f, double *rz) {
+                      const LmpFin &f, double *rz, const LmpSync *sync) {
     if (n <= 0 || nb <= 0) return hipSuccess;
     if (k <= 0 || k > LMP_K_MAX) return hipErrorInvalidValue;
     int rows, nrb;
     lmp_blocks(n, &rows, &nrb);
     if (nrb > LMP_RB_MAX) return hipErrorInvalidValue;
     const int tiles = (nb + CT - 1) / CT, ldw = tiles * CT;
+    if (sync && tiles <= sync->tiles && (long long)tiles * nrb <= sync->max_blocks) {
+        if (k <= 64)
+            hipLaunchKernelGGL((k_lmp_one<64, FIN>), dim3(nrb, tiles), dim3(512), 0, s, n, k, nb, rows, nrb, Sr, S,
+                               coef, X, ldx, Y, ldy, status, work, ldw, f, rz, *sync);
+        else
+            hipLaunchKernelGGL((k_lmp_one<LMP_K_MAX, FIN>), dim3(nrb, tiles), dim3(512), 0, s, n, k, nb, rows, nrb,
+                               Sr, S, coef, X, ldx, Y, ldy, status, work, ldw, f, rz, *sync);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_lmp_proj<FIN>, dim3(nrb, tiles), dim3(512), 0, s, n, k, nb, rows, Sr, X, ldx, status, work,
                        ldw, f);
     hipError_t e = hipGetLastError();
@@ -423,10 +549,10 @@ hipError_t lmp_launch(hipStream_t s, int n, int k, int nb, const double *S, cons
 
 hipError_t launch_lmp(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
                       const double *X, long long ldx, double *Y, long long ldy, const int32_t *status,
-                      double *work, double *rz) {
+                      double *work, double *rz, const LmpSync *sync) {
     // the plain form only reads X and status
     return lmp_launch<false>(s, n, k, nb, S, Sr, coef, const_cast<double *>(X), ldx, Y, ldy,
-                             const_cast<int32_t *>(status), work, LmpFin{}, rz);
+                             const_cast<int32_t *>(status), work, LmpFin{}, rz, sync);
 }
 
 // Device address of `scratch` on the current device, looked up once per device
@@ -451,9 +577,10 @@ hipError_t lmp_noalloc_scratch(double **out) {
 }
 
 hipError_t launch_lmp_fin(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
-                          double *r, double *z, int32_t *status, double *work, const LmpFin &f, double *rz) {
+                          double *r, double *z, int32_t *status, double *work, const LmpFin &f, double *rz,
+                          const LmpSync *sync) {
     if (!status || f.pieces < 0 || (f.pieces == 0 && !f.nseg)) return hipErrorInvalidValue;
-    return lmp_launch<true>(s, n, k, nb, S, Sr, coef, r, n, z, n, status, work, f, rz);
+    return lmp_launch<true>(s, n, k, nb, S, Sr, coef, r, n, z, n, status, work, f, rz, sync);
 }
 
 }  // namespace eda

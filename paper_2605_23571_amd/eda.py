@@ -37,6 +37,7 @@ EDA_METHOD_NYSTROM, EDA_METHOD_REVD = 0, 1
 EDA_THETA_MID, EDA_THETA_LAMK, EDA_THETA_ONE = 0, 1, 2
 EDA_LMP_P, EDA_LMP_U = 0, 1
 EDA_XCH_OFF, EDA_XCH_ON = 0, 1
+EDA_LMP_FORM_TWO, EDA_LMP_FORM_ONE = 0, 1
 EDA_PROF_TLAD, EDA_PROF_UB_GEMM = 0, 1
 EDA_LMP_NOALLOC_SCRATCH_BYTES = 4194304
 FIELDS = dict(truth=0, xb=1, traj=2, y=3, d=4, b=5, costc=6, ubrow=7, S=8, eig=9)
@@ -90,6 +91,7 @@ def lib():
             "eda_set_geometry": [vp, i32, i32],
             "eda_set_split": [vp, i32],
             "eda_set_exchange": [vp, i32, i64],
+            "eda_set_lmp_form": [vp, i32],
             "eda_mlp_param_count": [vp, ctypes.POINTER(i64)],
             "eda_mlp_workspace_bytes": [vp, i32, ctypes.POINTER(sz)],
             "eda_mlp_init": [vp, vp, vp, vp],
@@ -274,6 +276,10 @@ def eda_set_geometry(ctx, waves: int, tb: int):
 
 def eda_set_exchange(ctx, mode: int, spin_limit: int = -1):
     _check("eda_set_exchange", lib().eda_set_exchange(ctx, int(mode), int(spin_limit)))
+
+
+def eda_set_lmp_form(ctx, form: int):
+    _check("eda_set_lmp_form", lib().eda_set_lmp_form(ctx, int(form)))
 
 
 def eda_set_split(ctx, pieces: int):

@@ -597,6 +597,76 @@ def test_exchange_wait_limit_reports_sync_error():
     assert rel(off["dz"].cpu().numpy(), out["dz"].cpu().numpy()) < 1e-8
 
 
+def _lmp_form_problem(case):
+    if case in CASES:
+        cfg, g, _ = problem(case)
+        return cfg, g, False
+    cfg = LMP_CASES[case][0]
+    return cfg, eda.Problem(cfg, W.problem_normals(cfg), max_cols=cfg["members"] + 1), True
+
+
+@pytest.mark.parametrize("case", ["n1001", "n2049", "n4096"])
+def test_lmp_one_launch_matches_two_launches(case):
+    # The single-launch LMP (a barrier per column tile in device memory between
+    # the projection and the expansion) does the two-launch form's arithmetic in
+    # the same order: the PCG iterates are the same bits in every iteration form
+    # that applies the LMP -- whole columns (P = 1), ring pieces (P = 2, the LMP
+    # fused with the update), wave pieces with halo exchange -- and with the
+    # dense U_B.  n4096: 81 columns, 6 tiles x 16 row blocks in one launch.
+    cfg, g, own = _lmp_form_problem(case)
+    g.sketch_evd("rhs_diff")
+    members = np.arange(cfg["members"] + 1)
+    forms = [("whole columns", 1, eda.EDA_XCH_OFF), ("ring pieces", 2, eda.EDA_XCH_OFF),
+             ("wave pieces", 0, eda.EDA_XCH_ON)]
+    for label, P, xch in forms:
+        eda.eda_set_split(g.ctx, P)
+        eda.eda_set_exchange(g.ctx, xch)
+        out = {}
+        for form in (eda.EDA_LMP_FORM_TWO, eda.EDA_LMP_FORM_ONE):
+            eda.eda_set_lmp_form(g.ctx, form)
+            out[form] = g.pcg(members, rtol=0.0, maxit=6)
+        a, b = out[eda.EDA_LMP_FORM_TWO], out[eda.EDA_LMP_FORM_ONE]
+        same = torch.equal(a["dz"], b["dz"]) and np.array_equal(a["relres"], b["relres"])
+        print(f"[lmp form] {case} {label}: one launch == two launches: {same}", flush=True)
+        assert same, (case, label)
+    eda.eda_set_split(g.ctx, 0)
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OFF)
+    if case == "n1001":
+        cfg, gd, _ = problem(case, "dense")
+        gd.sketch_evd("rhs_diff")
+        res = []
+        for form in (eda.EDA_LMP_FORM_TWO, eda.EDA_LMP_FORM_ONE):
+            eda.eda_set_lmp_form(gd.ctx, form)
+            res.append(gd.pcg(members, rtol=1e-10, maxit=500)["dz"])
+        assert torch.equal(res[0], res[1])
+    if own:
+        g.close()
+
+
+def test_lmp_one_launch_wait_limit_reports_sync_error():
+    # Every tile-barrier wait gives up at once (limit 0, set from the host):
+    # the solve reports EDA_ERR_SYNC and every kernel runs to its end.  The
+    # two-launch form has no waits and solves normally under the same limit;
+    # with the default limit the single launch solves to the same bits.
+    cfg, g, o = problem("n1001")
+    g.sketch_evd("rhs_diff")
+    members = np.arange(cfg["members"] + 1)
+    eda.eda_set_split(g.ctx, 1)
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OFF, 0)
+    eda.eda_set_lmp_form(g.ctx, eda.EDA_LMP_FORM_ONE)
+    with pytest.raises(eda.EdaError) as ei:
+        g.pcg(members, rtol=1e-10, maxit=50)
+    assert ei.value.code == eda.EDA_ERR_SYNC
+    eda.eda_set_lmp_form(g.ctx, eda.EDA_LMP_FORM_TWO)
+    two = g.pcg(members, rtol=1e-10, maxit=500)
+    assert np.all(two["status"] == eda.EDA_MEMBER_CONVERGED)
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OFF, -1)
+    eda.eda_set_lmp_form(g.ctx, eda.EDA_LMP_FORM_ONE)
+    one = g.pcg(members, rtol=1e-10, maxit=500)
+    assert torch.equal(one["dz"], two["dz"])
+    eda.eda_set_split(g.ctx, 0)
+
+
 @pytest.mark.parametrize("case", ["n1001", "n2049"])
 def test_split_hessvec_matches_whole_columns(case):
     # Hessian products on P pieces per column (ring of the piece's states with
