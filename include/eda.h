@@ -481,9 +481,9 @@ int eda_batch_result(eda_batch *batch, int32_t p, double *d_DZ, int64_t ldz, int
  * time-block length}.  Returns the number of classes. */
 int eda_batch_tuning(eda_batch *batch, int32_t cls, int32_t *h_out);
 
-/* GPU times of the last eda_batch_solve's graph in milliseconds: h_ms[0] the
- * sketch (products and Nystrom cores), h_ms[1] the shifted redo, h_ms[2] the
- * solve (all in h_ms[2] when the runtime cannot time inside a graph). */
+/* GPU times of the last eda_batch_solve's graph in milliseconds, from clock
+ * stamps taken inside the graph: h_ms[0] the sketch (products and Nystrom
+ * cores), h_ms[1] the shifted redo, h_ms[2] the solve. */
 int eda_batch_timing(eda_batch *batch, double *h_ms);
 
 /* Free the batch's host structures and its graph and stream. */

@@ -1315,8 +1315,8 @@ struct eda_batch {
     std::vector<SolveTask> stasks;        // solve tasks in queue order
     std::vector<int> qoff;                // host copy of d_qoff
     double last_ms[3] = {0.0, 0.0, 0.0};  // sketch, shifted redo, solve (one graph)
-    hipEvent_t tev[4] = {};               // timing: entry, after the sketch, after the redo, exit
-    bool timed_nodes = true;              // tev[1..2] as event nodes inside the graph
+    long long *d_stamps = nullptr;        // clock at the graph's start, after the sketch, the redo, the solve
+    double clock_khz = 0.0;               // rate of that clock
     struct Class {
         int n = 0;
         std::vector<int> members;  // problem indices
@@ -1346,7 +1346,7 @@ namespace {
 
 struct BatchPlan {
     size_t off_solve, off_hv, off_st, off_ht, off_cnt, off_qoff, off_geom, off_jobs, off_redo, off_chol, off_iptr,
-        off_flags, off_titer, total;
+        off_flags, off_titer, off_stamps, total;
 };
 
 BatchPlan batch_plan(eda_ctx *const *ctxs, int np) {
@@ -1371,6 +1371,7 @@ BatchPlan batch_plan(eda_ctx *const *ctxs, int np) {
     P.off_iptr = lay.take(sizeof(int32_t *) * np);
     P.off_flags = lay.take(2 * sizeof(int32_t) * np);
     P.off_titer = lay.take(2 * sizeof(int32_t) * (st ? st : 1));
+    P.off_stamps = lay.take(4 * sizeof(long long));
     P.total = lay.total;
     return P;
 }
@@ -1604,6 +1605,7 @@ long long batch_step_cost(const eda_batch &b, int p) {
 int batch_enqueue(eda_batch &b) {
     hipStream_t s = b.stream;
     const int np = (int)b.probs.size();
+    HIP_TRY(launch_stamp(s, b.d_stamps + 0));
     if (b.use_lmp) {
         for (int i = 0; i < np; i++)
             HIP_TRY(launch_gamma(s, b.probs[i]->n, b.ell[i], b.probs[i]->b, b.probs[i]->sk_phi));
@@ -1635,13 +1637,14 @@ int batch_enqueue(eda_batch &b) {
             if (phase < 3) HIP_TRY(launch_chol_inv_batch(s, np, b.d_chol + (size_t)phase * np, lmax));
             if (phase == 3) HIP_TRY(launch_jacobi_svd_batch(s, np, b.d_jobs, lmax));
         }
-        if (b.timed_nodes) HIP_TRY(hipEventRecordWithFlags(b.tev[1], s, hipEventRecordExternal));
+        HIP_TRY(launch_stamp(s, b.d_stamps + 1));
         HIP_TRY(launch_nystrom_redo_batch(s, np, b.d_redo, lmax));
-        if (b.timed_nodes) HIP_TRY(hipEventRecordWithFlags(b.tev[2], s, hipEventRecordExternal));
     }
+    HIP_TRY(launch_stamp(s, b.d_stamps + 2));
     HIP_TRY(launch_fill_int(s, SOLVE_QUEUES, 0, b.d_counters));
     HIP_TRY(launch_solve(s, b.d_solve, b.d_geom, b.d_stasks, (int)b.stasks.size(), b.d_qoff, b.d_counters,
                          b.solve_waves, b.solve_lds, b.solve_grid));
+    HIP_TRY(launch_stamp(s, b.d_stamps + 3));
     HIP_TRY(launch_task_iters(s, (int)b.stasks.size(), b.d_solve, b.d_stasks, b.d_titer));
     if (b.use_lmp) HIP_TRY(launch_gather_info(s, np, b.d_infoptr, b.d_flags));
     return EDA_OK;
@@ -1712,8 +1715,6 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
         for (auto ev : b->lane_done) (void)hipEventDestroy(ev);
         if (b->fork) (void)hipEventDestroy(b->fork);
         if (b->entry) (void)hipEventDestroy(b->entry);
-        for (auto ev : b->tev)
-            if (ev) (void)hipEventDestroy(ev);
         if (b->stream) (void)hipStreamDestroy(b->stream);
         delete b;
         return code;
@@ -1721,8 +1722,13 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
     b->user = reinterpret_cast<hipStream_t>(stream);
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) return fail(EDA_ERR_HIP);
     if (hipEventCreateWithFlags(&b->entry, hipEventDisableTiming) != hipSuccess) return fail(EDA_ERR_HIP);
-    for (auto &ev : b->tev)
-        if (hipEventCreate(&ev) != hipSuccess) return fail(EDA_ERR_HIP);
+    {
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+            return fail(EDA_ERR_HIP);
+        b->clock_khz = khz;
+    }
     // everything already enqueued on the caller's stream (the problems' set-up) comes first
     if (hipEventRecord(b->entry, b->user) != hipSuccess || hipStreamWaitEvent(b->stream, b->entry, 0) != hipSuccess)
         return fail(EDA_ERR_HIP);
@@ -1740,6 +1746,7 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
     b->d_infoptr = reinterpret_cast<const int32_t **>(b->ws + P.off_iptr);
     b->d_flags = reinterpret_cast<int32_t *>(b->ws + P.off_flags);
     b->d_titer = reinterpret_cast<int32_t *>(b->ws + P.off_titer);
+    b->d_stamps = reinterpret_cast<long long *>(b->ws + P.off_stamps);
     for (int i = 0; i < np; i++) {
         b->probs.push_back(&ctxs[i]->c);
         b->handles.push_back(ctxs[i]);
@@ -1857,36 +1864,21 @@ int eda_batch_solve(eda_batch *b, int32_t k_cap, double rtol, int32_t maxit, int
         for (size_t t = 0; t < st.size(); t++) cost0[t] = batch_step_cost(*b, st[t].prob);
         EDA_TRY(batch_schedule(*b, cost0));
         HIP_TRY(hipStreamSynchronize(s));
-        int rc = batch_capture(*b, batch_enqueue, b->graph, b->exec);
-        if (rc != EDA_OK && b->timed_nodes) {
-            // no event nodes inside the graph: time the graph as a whole
-            (void)hipGetLastError();
-            b->timed_nodes = false;
-            rc = batch_capture(*b, batch_enqueue, b->graph, b->exec);
-        }
-        EDA_TRY(rc);
+        EDA_TRY(batch_capture(*b, batch_enqueue, b->graph, b->exec));
     }
     // one graph: sketch, shifted redo where an unshifted Cholesky failed (a
     // problem whose redo fails too is solved by plain CG), solve
-    const bool split = b->use_lmp && b->timed_nodes;
-    HIP_TRY(hipEventRecord(b->tev[0], b->stream));
     HIP_TRY(hipGraphLaunch(b->exec, b->stream));
-    HIP_TRY(hipEventRecord(b->tev[3], b->stream));
     const int nt = (int)b->stasks.size();
     std::vector<int32_t> its(2 * (size_t)nt), flags(2 * (size_t)np, 0);
+    long long stamps[4] = {0, 0, 0, 0};
     HIP_TRY(hipMemcpyAsync(its.data(), b->d_titer, sizeof(int32_t) * 2 * nt, hipMemcpyDeviceToHost, b->stream));
     if (b->use_lmp)
         HIP_TRY(hipMemcpyAsync(flags.data(), b->d_flags, sizeof(int32_t) * 2 * np, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipMemcpyAsync(stamps, b->d_stamps, sizeof(stamps), hipMemcpyDeviceToHost, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
-    float ms[3] = {0.f, 0.f, 0.f};
-    if (split) {
-        HIP_TRY(hipEventElapsedTime(&ms[0], b->tev[0], b->tev[1]));
-        HIP_TRY(hipEventElapsedTime(&ms[1], b->tev[1], b->tev[2]));
-        HIP_TRY(hipEventElapsedTime(&ms[2], b->tev[2], b->tev[3]));
-    } else {
-        HIP_TRY(hipEventElapsedTime(&ms[2], b->tev[0], b->tev[3]));
-    }
-    for (int i = 0; i < 3; i++) b->last_ms[i] = ms[i];
+    for (int i = 0; i < 3; i++) b->last_ms[i] = (double)(stamps[i + 1] - stamps[i]) / b->clock_khz;
+    if (!b->use_lmp) b->last_ms[0] = b->last_ms[1] = 0.0;
     int fallbacks = 0, unprec = 0;
     for (int i = 0; b->use_lmp && i < np; i++) {
         Ctx &c = *b->probs[i];
@@ -1968,8 +1960,6 @@ int eda_batch_destroy(eda_batch *b) {
     for (auto ev : b->lane_done) (void)hipEventDestroy(ev);
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->entry) (void)hipEventDestroy(b->entry);
-    for (auto ev : b->tev)
-        if (ev) (void)hipEventDestroy(ev);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return EDA_OK;

@@ -424,6 +424,9 @@ hipError_t launch_innov(hipStream_t s, int n, int N, int L, int p, int nv, int o
 // out[2 i], out[2 i + 1] = info[i][3], info[i][4]: whether problem i's sketch
 // was redone with shifts, and whether it ended without an LMP.
 hipError_t launch_gather_info(hipStream_t s, int np, const int32_t *const *info, int32_t *out);
+// *p = the device's constant-rate clock (wall_clock64) when the kernel runs:
+// a timestamp that can sit in a captured graph.
+hipError_t launch_stamp(hipStream_t s, long long *p);
 // p[0 .. count) = value (a kernel, so that it can sit in a captured graph).
 hipError_t launch_fill_int(hipStream_t s, int count, int value, int *p);
 hipError_t launch_pad_traj(hipStream_t s, int n, int N, int nm, const double *traj, int pad_l, int ext_len,

@@ -206,6 +206,9 @@ __global__ void k_pad_traj(int n, int N, int pad_l, int ext_len, const double *_
     }
 }
 
+// The device's constant-rate clock at the moment this (one-thread) kernel runs.
+__global__ void k_stamp(long long *p) { *p = wall_clock64(); }
+
 __global__ void k_fill_int(int count, int value, int *__restrict__ p) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = value;
@@ -224,6 +227,11 @@ __global__ void k_gather_info(int np, const int32_t *const *__restrict__ info, i
 hipError_t launch_gather_info(hipStream_t s, int np, const int32_t *const *info, int32_t *out) {
     if (np <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather_info, dim3((np + 255) / 256), dim3(256), 0, s, np, info, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stamp(hipStream_t s, long long *p) {
+    hipLaunchKernelGGL(k_stamp, dim3(1), dim3(1), 0, s, p);
     return hipGetLastError();
 }
 

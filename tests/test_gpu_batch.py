@@ -98,7 +98,15 @@ def test_batch_matches_single_problem_path():
 def test_batch_graph_replay_is_deterministic():
     st = batch_state()
     bt, cfgs = st["b"], st["cfgs"]
+    import time
+    t0 = time.perf_counter()
     bt.solve(k_cap=6, rtol=1e-8, maxit=3000)
+    wall_ms = 1e3 * (time.perf_counter() - t0)
+    # the phases of the one graph, from clock stamps inside it
+    ph = bt.timing()
+    print(f"[batch] graph phases {ph}, call {wall_ms:.2f} ms", flush=True)
+    assert ph["sketch_ms"] > 0 and ph["shifted_redo_ms"] >= 0 and ph["solve_ms"] > 0
+    assert sum(ph.values()) <= wall_ms
     first = [bt.result(p)["dz"].cpu().numpy() for p in range(len(cfgs))]
     it1 = [bt.result(p, with_dz=False)["iters"] for p in range(len(cfgs))]
     for _ in range(2):
