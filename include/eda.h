@@ -253,12 +253,14 @@ int eda_pcg_solve(eda_ctx *ctx, const int32_t *h_members, int32_t nm, double rto
  *   EDA_FIELD_UBROW  n, first row of U_B
  *   EDA_FIELD_S      n x k eigenvector estimates of the last sketch
  *   EDA_FIELD_EIG    k eigenvalue estimates of the last sketch
- *   EDA_FIELD_SKETCH_INFO  5 int32 (not doubles) of the last Nystrom sketch
+ *   EDA_FIELD_SKETCH_INFO  6 int32 (not doubles) of the last Nystrom sketch
  *                    (eda_sketch_evd or a batch solve with LMP): the outcomes
  *                    of its three unshifted Choleskys (Y^T Y, Q1^T Q1, W; 0 or
  *                    the failing pivot + 1; the second is defined only when
- *                    the first is 0), 1 if the shifted pass ran, 1 if that
- *                    failed too (no LMP) */
+ *                    the first is 0), 1 if the device-side pass with the
+ *                    shifts ran, 1 if that failed (no LMP), and the shifts it
+ *                    took (bit 0: the trace shift of CholQR3, bit 1: the
+ *                    Nystrom shift) */
 #define EDA_FIELD_TRUTH  0
 #define EDA_FIELD_XB     1
 #define EDA_FIELD_TRAJ   2

@@ -1178,7 +1178,7 @@ int eda_field(const eda_ctx *h, int32_t field, size_t *byte_offset, int64_t *cou
             ptr = c.sk_eig; cnt = c.k; break;
         case EDA_FIELD_SKETCH_INFO:
             *byte_offset = (size_t)(reinterpret_cast<const char *>(c.sk_info) - c.ws);
-            *count = 5;
+            *count = 6;
             return EDA_OK;
         default: return EDA_ERR_INVALID_ARG;
     }

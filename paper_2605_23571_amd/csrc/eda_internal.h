@@ -464,7 +464,8 @@ hipError_t launch_chol_inv_batch(hipStream_t s, int njobs, const CholJob *d_jobs
 // SVD, S = Q U(:, 1:k), signs and the LMP coefficients.  With trigger set it
 // runs only if one of trigger[0..2] (the unshifted Choleskys) is nonzero.
 // state[0] = 1 if it ran, state[1] = 1 if it ran and a Cholesky still failed
-// (no LMP), state[2] is its Cholesky scratch.  small: 10 slots of ls doubles
+// (no LMP), state[2] the shifts it took (bit 0: the trace shift of CholQR3,
+// bit 1: the Nystrom shift), state[3] its Cholesky scratch.  small: 10 slots of ls doubles
 // (slots as the host path: 0 G, 1 R1 then C^-1, 2 R1^-1 then T, 3 R2 then U,
 // 4 R2^-1 then sigma, 5-6 R products, 7 R_Y, 8 W, 9 C).
 struct RedoJob {
