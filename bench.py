@@ -356,7 +356,7 @@ def run_uneven_batch(count, reps, plain_count):
     it = np.concatenate(iters)
     return {"problems": count, "member_solves": cols, "value": round(cols / dt, 1), "unit": "solves/s",
             "s_per_batch": round(dt, 4), "first_call_s": round(first_s, 3), "setup_s": round(setup_s, 2),
-            "all_converged": conv, "host_redone_per_call": fb[0] / reps, "without_lmp_per_call": fb[1] / reps, "iters_median": float(np.median(it)), "iters_max": int(it.max()),
+            "all_converged": conv, "shifted_per_call": fb[0] / reps, "without_lmp_per_call": fb[1] / reps, "iters_median": float(np.median(it)), "iters_max": int(it.max()),
             "last_call_phases_ms": phases, "classes": tun,
             "plain": {"problems": pc, "member_solves": pcols, "value": round(pcols / plain_dt, 1),
                       "unit": "solves/s"}}

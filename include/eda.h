@@ -421,17 +421,20 @@ int eda_destroy(eda_ctx *ctx);
  * 0..L from dz = 0 (the system_with_CVT equation), i.e. per problem exactly
  * what eda_sketch_evd(RHS_DIFF, ell, ell, 1, NYSTROM, MID) followed by
  * eda_pcg_solve(0..L) computes, up to rounding order.
- * Problems with equal n form a class.  Each class runs one multi-problem
- * sketch launch (the classes as parallel branches), and the Nystrom cores of
- * all problems follow; problems whose unshifted Cholesky fails are then redone
- * on the device with the shifts of eda_sketch_evd (one workgroup each).  One
- * persistent launch then solves the members of every problem: its workgroups
- * take member columns from work queues (one per XCD, whole problems each) and
- * iterate each to its final status without host round trips.  All of it is
- * one captured graph; later calls with the same parameters replay it.  The
- * first call also tunes, per class, the sketch geometry (waves per workgroup,
- * time-block length) by timing the class's sketch launch, and the solve
- * geometry for one common number of waves.
+ * Problems with equal n form a class.  One persistent launch computes the
+ * sketch columns of every problem, (problem, column) tasks taken from one
+ * list; the workgroup that finishes a problem's last column runs that
+ * problem's last Nystrom pass on the device -- unshifted CholQR2 and Cholesky
+ * first, and where one of them fails the shifts of eda_sketch_evd (shifted
+ * CholQR3, the Nystrom shift), with the same routine and bits as
+ * eda_sketch_evd's shifted pass.  A second persistent launch then solves the
+ * members of every problem: its workgroups take member columns from work
+ * queues (one per XCD, whole problems each) and iterate each to its final
+ * status without host round trips.  Both are one captured graph; later calls
+ * with the same parameters replay it.  The first call also tunes, per class,
+ * the TL/AD geometry (waves per workgroup, time-block length) by timing a
+ * sketch launch of the class, and the solve geometry for one common number of
+ * waves, which the sketch launch uses too.
  * Every context must use the banded U_B (EDA_UB_BANDED), be set up and not be
  * used concurrently by other calls while the batch exists; a context appears
  * at most once.  The batch reuses each context's workspace for its sketch and
@@ -454,15 +457,12 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
 
 /* Sketch, Nystrom and LMP-PCG of every member of every problem (see above);
  * returns after the work is done.  rtol, maxit: the PCG stopping rule of
- * eda_pcg_solve.  use_lmp = 0 skips the sketch and runs plain CG.  The sketch
- * uses unshifted CholQR2 and Cholesky; a problem where one of them fails gets
- * its LMP from the shifted sketch of eda_sketch_evd (shifted CholQR3 and the
- * Nystrom shift of the Nystrom-variants appendix), run on the device inside
- * the same graph before the solve, so a call makes no host round trip between
- * its sketch and its solve; if that fails too (Phi numerically
- * rank-deficient, e.g. ell close to n), its members are solved by plain CG.
- * h_fallbacks (optional, 2 entries) receives the number of problems whose
- * sketch was redone and, of those, the number solved without LMP.  Returns
+ * eda_pcg_solve.  use_lmp = 0 skips the sketch and runs plain CG.  A call
+ * makes no host round trip between its sketch and its solve.  A problem whose
+ * shifted sketch fails (Phi numerically rank-deficient, e.g. ell close to n)
+ * has its members solved by plain CG.  h_fallbacks (optional, 2 entries)
+ * receives the number of problems whose last Nystrom pass took a shift and,
+ * of those, the number solved without LMP.  Returns
  * EDA_OK, EDA_WARN_NOT_CONVERGED if any member of any problem did not converge
  * (maxit or breakdown), or a negative error. */
 int eda_batch_solve(eda_batch *batch, int32_t k_cap, double rtol, int32_t maxit, int32_t use_lmp,
@@ -477,15 +477,17 @@ int eda_batch_result(eda_batch *batch, int32_t p, double *d_DZ, int64_t ldz, int
 
 /* Tuning outcome of class cls (classes in increasing n), valid after the first
  * eda_batch_solve: h_out[11] = {n, problems, solve waves per workgroup, solve
- * points per lane, solve time-block length, persistent grid (one solve launch
- * for all classes, the same for every class), member columns, tuned sketch
- * launch time in microseconds, sketch waves, sketch points per lane, sketch
- * time-block length}.  Returns the number of classes. */
+ * points per lane, solve time-block length (the geometry both persistent
+ * launches run the class with), persistent solve grid (the same for every
+ * class), member columns, and the class's fastest timed geometry for its
+ * sketch columns alone: its launch time in microseconds, waves, points per
+ * lane, time-block length}.  Returns the number of classes. */
 int eda_batch_tuning(eda_batch *batch, int32_t cls, int32_t *h_out);
 
 /* GPU times of the last eda_batch_solve's graph in milliseconds, from clock
- * stamps taken inside the graph: h_ms[0] the sketch (products and Nystrom
- * cores), h_ms[1] the shifted redo, h_ms[2] the solve. */
+ * stamps taken inside the graph: h_ms[0] the sketch launch (products and
+ * Nystrom passes), h_ms[1] the prelude (Gamma of every problem), h_ms[2] the
+ * solve launch. */
 int eda_batch_timing(eda_batch *batch, double *h_ms);
 
 /* Free the batch's host structures and its graph and stream. */

@@ -405,10 +405,9 @@ int cholqr2(Ctx &c, int l, const double *Y, double *Q, double *R_out) {
     return EDA_OK;
 }
 
-// The last stage of the Nystrom sketch with no host synchronisation, in
-// phases around the three Cholesky factorisations and the SVD of T (a batch
-// runs each for all its problems in one launch, one workgroup per problem;
-// chol_job and jacobi_job give their operands):
+// The last stage of the single-problem Nystrom sketch with no host
+// synchronisation, in phases around the three Cholesky factorisations and the
+// SVD of T (chol_job and jacobi_job give their operands):
 //   0: G = Y^T Y                  -> chol 0: R1, R1^-1
 //   1: Q1 = Y R1^-1, G = Q1^T Q1  -> chol 1: R2, R2^-1
 //   2: Q = Q1 R2^-1, R_Y = R2 R1, W = Phi^T Y (symmetrised) -> chol 2: C, C^-1
@@ -1304,18 +1303,19 @@ struct eda_batch {
     int *d_counters = nullptr;            // SOLVE_QUEUES queue counters
     int *d_qoff = nullptr;                // SOLVE_QUEUES + 1 queue offsets
     TladGeom *d_geom = nullptr;           // solve geometry of each problem
-    JacobiJob *d_jobs = nullptr;          // SVD operands of every problem
-    RedoJob *d_redo = nullptr;            // device-side shifted sketch of every problem
-    CholJob *d_chol = nullptr;            // operands of the three Cholesky steps, 3 x np
+    RedoJob *d_redo = nullptr;            // last Nystrom pass of every problem (in the sketch launch)
+    int *d_done = nullptr;                // finished sketch columns per problem
     int solve_waves = 0, solve_grid = 0;  // the one persistent solve launch
+    int sketch_grid = 0;                  // the one persistent sketch launch (solve_waves waves)
+    size_t sketch_lds = 0;
     size_t solve_lds = 0;
     const int32_t **d_infoptr = nullptr;  // each problem's sketch outcome slots
     int32_t *d_flags = nullptr;           // gathered sketch states, two per problem
     int32_t *d_titer = nullptr;           // iterations of each solve task in the last call
     std::vector<SolveTask> stasks;        // solve tasks in queue order
     std::vector<int> qoff;                // host copy of d_qoff
-    double last_ms[3] = {0.0, 0.0, 0.0};  // sketch, shifted redo, solve (one graph)
-    long long *d_stamps = nullptr;        // clock at the graph's start, after the sketch, the redo, the solve
+    double last_ms[3] = {0.0, 0.0, 0.0};  // sketch launch, prelude, solve launch (one graph)
+    long long *d_stamps = nullptr;        // clock at the graph's start, before the sketch, before and after the solve
     double clock_khz = 0.0;               // rate of that clock
     struct Class {
         int n = 0;
@@ -1326,14 +1326,8 @@ struct eda_batch {
         size_t lds_solve = 0, lds_hv = 0;
         double tune_us = 0.0;
         std::vector<std::pair<TladGeom, float>> timed;  // tuner candidates and their times
-        hipStream_t side = nullptr;
-        hipEvent_t done = nullptr;
     };
     std::vector<Class> classes;
-    hipEvent_t fork = nullptr;
-    // branches for the per-problem Nystrom cores (independent, one CU each)
-    std::vector<hipStream_t> lanes;
-    std::vector<hipEvent_t> lane_done;
     std::vector<int> ell;
     bool tuned = false;
     int k_cap = -1, maxit = -1, use_lmp = -1;
@@ -1345,8 +1339,8 @@ struct eda_batch {
 namespace {
 
 struct BatchPlan {
-    size_t off_solve, off_hv, off_st, off_ht, off_cnt, off_qoff, off_geom, off_jobs, off_redo, off_chol, off_iptr,
-        off_flags, off_titer, off_stamps, total;
+    size_t off_solve, off_hv, off_st, off_ht, off_cnt, off_qoff, off_geom, off_redo, off_iptr, off_flags, off_titer,
+        off_stamps, off_done, total;
 };
 
 BatchPlan batch_plan(eda_ctx *const *ctxs, int np) {
@@ -1362,16 +1356,15 @@ BatchPlan batch_plan(eda_ctx *const *ctxs, int np) {
     P.off_hv = lay.take(sizeof(TladArgs) * np);
     P.off_st = lay.take(sizeof(SolveTask) * (st ? st : 1));
     P.off_ht = lay.take(sizeof(SolveTask) * (ht ? ht : 1));
-    P.off_cnt = lay.take(sizeof(int) * SOLVE_QUEUES);
+    P.off_cnt = lay.take(sizeof(int) * (SOLVE_QUEUES + 1));
     P.off_qoff = lay.take(sizeof(int) * (SOLVE_QUEUES + 1));
     P.off_geom = lay.take(sizeof(TladGeom) * np);
-    P.off_jobs = lay.take(sizeof(JacobiJob) * np);
     P.off_redo = lay.take(sizeof(RedoJob) * np);
-    P.off_chol = lay.take(sizeof(CholJob) * 3 * np);
     P.off_iptr = lay.take(sizeof(int32_t *) * np);
     P.off_flags = lay.take(2 * sizeof(int32_t) * np);
     P.off_titer = lay.take(2 * sizeof(int32_t) * (st ? st : 1));
     P.off_stamps = lay.take(4 * sizeof(long long));
+    P.off_done = lay.take(sizeof(int) * np);
     P.total = lay.total;
     return P;
 }
@@ -1423,8 +1416,8 @@ int batch_class_lds(eda_batch &b, eda_batch::Class &k, const TladGeom &g, size_t
 // Dynamic LDS and grid of the one persistent solve launch from the classes'
 // solve geometries; each class's sketch LDS from its sketch geometry.
 int batch_solve_layout(eda_batch &b) {
-    size_t lds = 0;
-    int cols = 0;
+    size_t lds = 0, slds = 0;
+    int cols = 0, scols = 0;
     for (auto &k : b.classes) {
         size_t ls, lh, ls2, lh2;
         EDA_TRY(batch_class_lds(b, k, k.g, ls, lh));
@@ -1433,6 +1426,13 @@ int batch_solve_layout(eda_batch &b) {
         k.lds_solve = ls2;
         if (ls2 > lds) lds = ls2;
         cols += k.s_cnt;
+        // the sketch launch: columns on the solve geometry, and the last Nystrom pass
+        if (lh2 > slds) slds = lh2;
+        for (int i : k.members) {
+            const size_t r = redo_lds(b.ell[i]);
+            if (r > slds) slds = r;
+            scols += b.ell[i];
+        }
     }
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
@@ -1440,6 +1440,10 @@ int batch_solve_layout(eda_batch &b) {
     const int grid = (per_cu > 0 ? per_cu : 1) * cus;
     b.solve_lds = lds;
     b.solve_grid = grid < cols ? grid : cols;
+    const int sper_cu = sketch_blocks_per_cu(b.solve_waves, slds);
+    const int sgrid = (sper_cu > 0 ? sper_cu : 1) * cus;
+    b.sketch_lds = slds;
+    b.sketch_grid = sgrid < scols ? sgrid : scols;
     return EDA_OK;
 }
 
@@ -1595,53 +1599,39 @@ long long batch_step_cost(const eda_batch &b, int p) {
     return b.probs[p]->N;
 }
 
-// Enqueue one call's work on b.stream (captured into one graph): with the LMP,
-// the sketch products (one branch per class), the Nystrom cores (per-problem
-// GEMMs in parallel branches, each phase's Cholesky factorisations or SVDs for
-// every problem in one launch) and the device-side shifted redo of the
-// problems whose unshifted Cholesky failed; then the persistent solve over
-// the tasks of every class; then each task's iterations and status and each
-// problem's sketch state, gathered for one read.
+// The sketch launch's arguments.
+SolveSketch batch_sketch(const eda_batch &b) {
+    SolveSketch k{};
+    k.hv = b.d_hv;
+    k.core = b.d_redo;
+    k.done = b.d_done;
+    return k;
+}
+
+// Enqueue one call's work on b.stream (captured into one graph): with the
+// LMP, the prelude (Gamma of every problem, the per-call resets) and one
+// persistent sketch launch -- (problem, column) tasks, each problem's last
+// Nystrom pass on the workgroup that finishes its last column; then the one
+// persistent solve launch over the member columns of every class; then each
+// task's iterations and status and each problem's sketch state, gathered for
+// one read.  Clock stamps at the start and around the launches.
 int batch_enqueue(eda_batch &b) {
     hipStream_t s = b.stream;
     const int np = (int)b.probs.size();
     HIP_TRY(launch_stamp(s, b.d_stamps + 0));
+    HIP_TRY(launch_fill_int(s, SOLVE_QUEUES + 1, 0, b.d_counters));
     if (b.use_lmp) {
-        for (int i = 0; i < np; i++)
-            HIP_TRY(launch_gamma(s, b.probs[i]->n, b.ell[i], b.probs[i]->b, b.probs[i]->sk_phi));
-        HIP_TRY(hipEventRecord(b.fork, s));
-        for (auto &k : b.classes) {
-            HIP_TRY(hipStreamWaitEvent(k.side, b.fork, 0));
-            HIP_TRY(launch_hv_multi(k.side, b.d_hv, b.d_htasks + k.h_off, k.h_cnt, k.g, k.lds_hv));
-            HIP_TRY(hipEventRecord(k.done, k.side));
-            HIP_TRY(hipStreamWaitEvent(s, k.done, 0));
-        }
-        const size_t nl = b.lanes.size();
-        int lmax = 1;
-        for (int l : b.ell) lmax = l > lmax ? l : lmax;
-        for (int phase = 0; phase < 5; phase++) {
-            HIP_TRY(hipEventRecord(b.fork, s));
-            for (size_t l = 0; l < nl; l++) HIP_TRY(hipStreamWaitEvent(b.lanes[l], b.fork, 0));
-            for (int i = 0; i < np; i++) {
-                Ctx &c = *b.probs[i];
-                c.stream = b.lanes[i % nl];
-                if (phase < 4)
-                    EDA_TRY(nystrom_phase(c, b.ell[i], phase));
-                else
-                    EDA_TRY(nystrom_post_svd(c, b.ell[i], b.ell[i], EDA_THETA_MID));
-            }
-            for (size_t l = 0; l < nl; l++) {
-                HIP_TRY(hipEventRecord(b.lane_done[l], b.lanes[l]));
-                HIP_TRY(hipStreamWaitEvent(s, b.lane_done[l], 0));
-            }
-            if (phase < 3) HIP_TRY(launch_chol_inv_batch(s, np, b.d_chol + (size_t)phase * np, lmax));
-            if (phase == 3) HIP_TRY(launch_jacobi_svd_batch(s, np, b.d_jobs, lmax));
-        }
+        const SolveSketch sk = batch_sketch(b);
+        HIP_TRY(launch_solve_prelude(s, np, b.d_solve, sk));
         HIP_TRY(launch_stamp(s, b.d_stamps + 1));
-        HIP_TRY(launch_nystrom_redo_batch(s, np, b.d_redo, lmax));
+        int nh = 0;
+        for (const auto &k : b.classes) nh += k.h_cnt;
+        HIP_TRY(launch_sketch(s, b.d_geom, b.d_htasks, nh, b.d_counters + SOLVE_QUEUES, b.solve_waves, b.sketch_lds,
+                              b.sketch_grid, sk));
+    } else {
+        HIP_TRY(launch_stamp(s, b.d_stamps + 1));
     }
     HIP_TRY(launch_stamp(s, b.d_stamps + 2));
-    HIP_TRY(launch_fill_int(s, SOLVE_QUEUES, 0, b.d_counters));
     HIP_TRY(launch_solve(s, b.d_solve, b.d_geom, b.d_stasks, (int)b.stasks.size(), b.d_qoff, b.d_counters,
                          b.solve_waves, b.solve_lds, b.solve_grid));
     HIP_TRY(launch_stamp(s, b.d_stamps + 3));
@@ -1707,13 +1697,6 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
     eda_batch *b = new (std::nothrow) eda_batch();
     if (!b) return EDA_ERR_INVALID_ARG;
     auto fail = [&](int code) {
-        for (auto &k : b->classes) {
-            if (k.side) (void)hipStreamDestroy(k.side);
-            if (k.done) (void)hipEventDestroy(k.done);
-        }
-        for (auto st : b->lanes) (void)hipStreamDestroy(st);
-        for (auto ev : b->lane_done) (void)hipEventDestroy(ev);
-        if (b->fork) (void)hipEventDestroy(b->fork);
         if (b->entry) (void)hipEventDestroy(b->entry);
         if (b->stream) (void)hipStreamDestroy(b->stream);
         delete b;
@@ -1740,9 +1723,8 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
     b->d_counters = reinterpret_cast<int *>(b->ws + P.off_cnt);
     b->d_qoff = reinterpret_cast<int *>(b->ws + P.off_qoff);
     b->d_geom = reinterpret_cast<TladGeom *>(b->ws + P.off_geom);
-    b->d_jobs = reinterpret_cast<JacobiJob *>(b->ws + P.off_jobs);
     b->d_redo = reinterpret_cast<RedoJob *>(b->ws + P.off_redo);
-    b->d_chol = reinterpret_cast<CholJob *>(b->ws + P.off_chol);
+    b->d_done = reinterpret_cast<int *>(b->ws + P.off_done);
     b->d_infoptr = reinterpret_cast<const int32_t **>(b->ws + P.off_iptr);
     b->d_flags = reinterpret_cast<int32_t *>(b->ws + P.off_flags);
     b->d_titer = reinterpret_cast<int32_t *>(b->ws + P.off_titer);
@@ -1766,20 +1748,6 @@ int eda_batch_create(eda_ctx *const *ctxs, int32_t np, void *d_ws, size_t ws_byt
             if (b->probs[i]->n == v) k.members.push_back(i);
         k.g = tlad_geometry(v, 0);
         b->classes.push_back(k);
-    }
-    for (auto &k : b->classes) {
-        if (hipStreamCreateWithFlags(&k.side, hipStreamNonBlocking) != hipSuccess) return fail(EDA_ERR_HIP);
-        if (hipEventCreateWithFlags(&k.done, hipEventDisableTiming) != hipSuccess) return fail(EDA_ERR_HIP);
-    }
-    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) return fail(EDA_ERR_HIP);
-    const int nlanes = np < 16 ? np : 16;
-    for (int l = 0; l < nlanes; l++) {
-        hipStream_t st = nullptr;
-        hipEvent_t ev = nullptr;
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return fail(EDA_ERR_HIP);
-        b->lanes.push_back(st);
-        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return fail(EDA_ERR_HIP);
-        b->lane_done.push_back(ev);
     }
     // member lists 0..L of every problem
     std::vector<int32_t> m;
@@ -1845,17 +1813,13 @@ int eda_batch_solve(eda_batch *b, int32_t k_cap, double rtol, int32_t maxit, int
         for (const auto &k : b->classes)
             for (int i : k.members) geo[i] = k.gs;
         HIP_TRY(hipMemcpyAsync(b->d_geom, geo.data(), sizeof(TladGeom) * np, hipMemcpyHostToDevice, s));
-        std::vector<JacobiJob> jobs(np);
-        std::vector<CholJob> cjobs(3 * (size_t)np);
-        for (int i = 0; i < np; i++) {
-            jobs[i] = jacobi_job(*b->probs[i], b->ell[i]);
-            for (int w = 0; w < 3; w++) cjobs[(size_t)w * np + i] = chol_job(*b->probs[i], b->ell[i], w);
-        }
-        HIP_TRY(hipMemcpyAsync(b->d_jobs, jobs.data(), sizeof(JacobiJob) * np, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(b->d_chol, cjobs.data(), sizeof(CholJob) * cjobs.size(), hipMemcpyHostToDevice, s));
+        // every problem's last Nystrom pass runs inside the solve, always
+        // (the unshifted factorisations first, the shifts where they fail)
         std::vector<RedoJob> rjobs(np);
-        for (int i = 0; i < np; i++)
+        for (int i = 0; i < np; i++) {
             rjobs[i] = redo_job(*b->probs[i], b->ell[i], b->ell[i], EDA_THETA_MID, 2.220446049250313e-16);
+            rjobs[i].trigger = nullptr;
+        }
         HIP_TRY(hipMemcpyAsync(b->d_redo, rjobs.data(), sizeof(RedoJob) * np, hipMemcpyHostToDevice, s));
         // first queue layout from the expected cost of a column (one
         // iteration each); later calls use the measured cost
@@ -1866,8 +1830,9 @@ int eda_batch_solve(eda_batch *b, int32_t k_cap, double rtol, int32_t maxit, int
         HIP_TRY(hipStreamSynchronize(s));
         EDA_TRY(batch_capture(*b, batch_enqueue, b->graph, b->exec));
     }
-    // one graph: sketch, shifted redo where an unshifted Cholesky failed (a
-    // problem whose redo fails too is solved by plain CG), solve
+    // one graph: the sketch launch (sketch columns, each problem's last
+    // Nystrom pass with the shifts where a Cholesky fails; a problem whose
+    // shifted pass fails too is solved by plain CG), the solve launch
     HIP_TRY(hipGraphLaunch(b->exec, b->stream));
     const int nt = (int)b->stasks.size();
     std::vector<int32_t> its(2 * (size_t)nt), flags(2 * (size_t)np, 0);
@@ -1877,8 +1842,9 @@ int eda_batch_solve(eda_batch *b, int32_t k_cap, double rtol, int32_t maxit, int
         HIP_TRY(hipMemcpyAsync(flags.data(), b->d_flags, sizeof(int32_t) * 2 * np, hipMemcpyDeviceToHost, b->stream));
     HIP_TRY(hipMemcpyAsync(stamps, b->d_stamps, sizeof(stamps), hipMemcpyDeviceToHost, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
-    for (int i = 0; i < 3; i++) b->last_ms[i] = (double)(stamps[i + 1] - stamps[i]) / b->clock_khz;
-    if (!b->use_lmp) b->last_ms[0] = b->last_ms[1] = 0.0;
+    b->last_ms[0] = (double)(stamps[2] - stamps[1]) / b->clock_khz;
+    b->last_ms[1] = (double)(stamps[1] - stamps[0]) / b->clock_khz;
+    b->last_ms[2] = (double)(stamps[3] - stamps[2]) / b->clock_khz;
     int fallbacks = 0, unprec = 0;
     for (int i = 0; b->use_lmp && i < np; i++) {
         Ctx &c = *b->probs[i];
@@ -1952,13 +1918,6 @@ int eda_batch_timing(eda_batch *b, double *h_ms) {
 int eda_batch_destroy(eda_batch *b) {
     if (!b) return EDA_ERR_INVALID_ARG;
     batch_free_graph(*b);
-    for (auto &k : b->classes) {
-        if (k.side) (void)hipStreamDestroy(k.side);
-        if (k.done) (void)hipEventDestroy(k.done);
-    }
-    for (auto st : b->lanes) (void)hipStreamDestroy(st);
-    for (auto ev : b->lane_done) (void)hipEventDestroy(ev);
-    if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->entry) (void)hipEventDestroy(b->entry);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;

@@ -133,7 +133,8 @@ struct PcgCols {
     // pieces' partial sums of p^T (I + A) p to pq_part[c * pieces + piece]
     double *p_out, *q, *pq_part;
 };
-// One column of a batched persistent solve: problem index, PCG column.
+// One task of a batched persistent launch: problem index and column (a PCG
+// member column, or a sketch column).
 struct SolveTask {
     int prob, col;
 };
@@ -288,8 +289,28 @@ size_t tlad_lds_bytes(const TladArgs &a, const TladGeom &g, int mode);
 // geometry per problem (device memory); every geometry has `waves` waves, and
 // lds covers the largest problem's dynamic LDS.
 constexpr int SOLVE_QUEUES = 8;
+// The sketches of a batch (device memory): a task (p, j) computes column j
+// of problem p's Y = A Gamma (hv[p], Gamma already in hv[p].V); the
+// workgroup that finishes a problem's last column runs its last Nystrom pass
+// (core[p], trigger null).  done[] counts finished columns per problem (zero
+// at the start of a launch).
+struct RedoJob;
+struct SolveSketch {
+    const TladArgs *hv;
+    const RedoJob *core;
+    int *done;
+};
 hipError_t launch_solve(hipStream_t s, const TladArgs *d_probs, const TladGeom *d_geoms, const SolveTask *d_tasks,
                         int ntasks, const int *d_qoff, int *d_counters, int waves, size_t lds, int grid);
+// One persistent launch over the sketch tasks of every problem (tasks: ntasks
+// (problem, column) pairs, taken from the end; *d_counter zero before the
+// launch); geoms and lds as for launch_solve.
+hipError_t launch_sketch(hipStream_t s, const TladGeom *d_geoms, const SolveTask *d_tasks, int ntasks, int *d_counter,
+                         int waves, size_t lds, int grid, const SolveSketch &sk);
+int sketch_blocks_per_cu(int waves, size_t lds);
+// Before the sketch launch: Gamma of every problem (hv[p].V column j =
+// b_{j+1} - b_0, b = probs[p].pcg.b, ell[p] = core[p].l columns) and done[] = 0.
+hipError_t launch_solve_prelude(hipStream_t s, int np, const TladArgs *d_probs, const SolveSketch &sk);
 // Hessian products (banded U_B, HV mode) for a list of (problem, column) tasks
 // of problems sharing n: one workgroup per task.
 hipError_t launch_hv_multi(hipStream_t s, const TladArgs *d_probs, const SolveTask *d_tasks, int ntasks,
@@ -300,6 +321,8 @@ hipError_t launch_task_iters(hipStream_t s, int ntasks, const TladArgs *d_probs,
                              int32_t *d_out);
 // Workgroups of k_solve (waves waves each) one CU holds with this dynamic LDS.
 int solve_blocks_per_cu(int waves, size_t lds);
+// Bytes of LDS the last Nystrom pass (nystrom_dev.h) needs for ell <= lmax.
+size_t redo_lds(int lmax);
 // Pads of the periodic row extension that every wave window of the TL/AD
 // kernel fits in without wrapping: window points j in [-pad_l, n + pad_r).
 void tlad_pads(int n, int *pad_l, int *pad_r);
@@ -421,8 +444,8 @@ hipError_t launch_innov(hipStream_t s, int n, int N, int L, int p, int nv, int o
                         double *force, double *costc);
 // Periodic extension of trajectory rows: out[m][s][j] = traj[m][s][(j - pad_l) mod n],
 // j < ext_len, for states s < N of each of nm members (input rows N + 1 per member).
-// out[2 i], out[2 i + 1] = info[i][3], info[i][4]: whether problem i's sketch
-// was redone with shifts, and whether it ended without an LMP.
+// out[2 i], out[2 i + 1] = info[i][5], info[i][4]: the shifts problem i's last
+// Nystrom pass took, and whether it ended without an LMP.
 hipError_t launch_gather_info(hipStream_t s, int np, const int32_t *const *info, int32_t *out);
 // *p = the device's constant-rate clock (wall_clock64) when the kernel runs:
 // a timestamp that can sit in a captured graph.
@@ -440,15 +463,13 @@ hipError_t launch_sym(hipStream_t s, int l, double *W);
 hipError_t launch_small_gemm(hipStream_t s, int l, bool ta, bool tb, const double *A, const double *B,
                              double *C);
 hipError_t launch_jacobi_svd_u(hipStream_t s, int l, double *T, double *U, double *sig);
-// One Jacobi SVD of a batch: T (l x l) -> U, sig as launch_jacobi_svd_u.
+// Operands of one Jacobi SVD: T (l x l) -> U, sig as launch_jacobi_svd_u.
 struct JacobiJob {
     int l;
     const double *T;
     double *U, *sig;
 };
-// One workgroup per job (device array); every job's l <= lmax <= 128.
-hipError_t launch_jacobi_svd_batch(hipStream_t s, int njobs, const JacobiJob *d_jobs, int lmax);
-// One factorisation of a batch: as launch_chol_inv(l, W, shift, C, Cinv, info).
+// Operands of one factorisation: as launch_chol_inv(l, W, shift, C, Cinv, info).
 struct CholJob {
     int l;
     const double *W;
@@ -456,8 +477,6 @@ struct CholJob {
     double *C, *Cinv;
     int32_t *info;
 };
-// One workgroup per job (device array); every job's l <= lmax <= 128.
-hipError_t launch_chol_inv_batch(hipStream_t s, int njobs, const CholJob *d_jobs, int lmax);
 // The shifted Nystrom sketch of one problem on the device (small_la.hip): from
 // Y = A Phi, CholQR2 with the shifted first pass when needed, W = Phi^T Y and
 // its Cholesky, the Nystrom shift nu = u ||Y||_F when that fails, then T, its
@@ -481,8 +500,6 @@ struct RedoJob {
     double *eig, *coef, *coefu, *theta;
 };
 hipError_t launch_nystrom_redo(hipStream_t s, const RedoJob &job);
-// One workgroup per job (device array); every job's l <= lmax <= 128.
-hipError_t launch_nystrom_redo_batch(hipStream_t s, int njobs, const RedoJob *d_jobs, int lmax);
 hipError_t launch_jacobi_eig(hipStream_t s, int l, double *T, double *Vwork, double *V, double *lam);
 hipError_t launch_fix_signs(hipStream_t s, int n, int k, double *S, long long lds);
 hipError_t launch_lmp_coef(hipStream_t s, int k, const double *sig, double nu, int square,

@@ -33,6 +33,7 @@
 #include <type_traits>
 
 #include "eda_internal.h"
+#include "nystrom_dev.h"
 
 namespace eda {
 namespace {
@@ -838,6 +839,66 @@ __device__ __forceinline__ void solve_column(const TladArgs &a, const TladGeom &
     __syncthreads();
 }
 
+// One sketch column of problem p: y_j = A gamma_j on the control trajectory;
+// the workgroup that completes the problem's last column then runs its last
+// Nystrom pass (shifts on the device when a Cholesky fails), which leaves the
+// LMP.  Every wave releases its stores at device scope before the count, and
+// the finishing workgroup acquires before it reads the other workgroups'
+// columns.
+template <int Q>
+__device__ __forceinline__ void sketch_column(const SolveSketch &sk, int p, int j, const TladGeom &g,
+                                              unsigned char *smraw, nys::RedoLds &L, double *nrm, int &s_flag) {
+    const int tid = threadIdx.x;
+    tlad_column<double, Q, TLAD_HV>(sk.hv[p], g, j, 0, 0, smraw);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    const RedoJob &J = sk.core[p];
+    if (tid == 0) s_flag = __hip_atomic_fetch_add(sk.done + p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == J.l - 1;
+    __syncthreads();
+    const int last = s_flag;
+    __syncthreads();
+    if (!last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    nys::nystrom_redo(J, reinterpret_cast<double *>(smraw), L, nrm);
+    __syncthreads();
+}
+
+// The sketches of a batch in one persistent launch: the workgroups take
+// (problem, sketch column) tasks from one list, from its end (the list holds
+// the classes in increasing n, so the longest columns go first); the
+// workgroup that finishes a problem's last column runs its last Nystrom pass.
+// Every geometry has blockDim.x / 64 waves.  Every workgroup exits once the
+// list is exhausted.
+__global__ __launch_bounds__(512) void k_sketch(const TladGeom *__restrict__ geoms, const SolveTask *__restrict__ tasks,
+                                                int ntasks, int *counter, SolveSketch sk) {
+    extern __shared__ __align__(16) unsigned char smraw[];
+    __shared__ int s_task;
+    __shared__ double s_t[128];
+    __shared__ nys::RedoLds s_redo;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int u = atomicAdd(counter, 1);
+            s_task = u < ntasks ? ntasks - 1 - u : -1;
+        }
+        __syncthreads();
+        const int t = s_task;
+        __syncthreads();
+        if (t < 0) break;
+        const SolveTask task = tasks[t];
+        const TladGeom g = geoms[task.prob];
+        switch (g.q) {
+            case 2: sketch_column<2>(sk, task.prob, task.col, g, smraw, s_redo, s_t, s_task); break;
+            case 3: sketch_column<3>(sk, task.prob, task.col, g, smraw, s_redo, s_t, s_task); break;
+            case 4: sketch_column<4>(sk, task.prob, task.col, g, smraw, s_redo, s_t, s_task); break;
+            case 5: sketch_column<5>(sk, task.prob, task.col, g, smraw, s_redo, s_t, s_task); break;
+            case 6: sketch_column<6>(sk, task.prob, task.col, g, smraw, s_redo, s_t, s_task); break;
+            case 7: sketch_column<7>(sk, task.prob, task.col, g, smraw, s_redo, s_t, s_task); break;
+            case 8: sketch_column<8>(sk, task.prob, task.col, g, smraw, s_redo, s_t, s_task); break;
+            default: sketch_column<9>(sk, task.prob, task.col, g, smraw, s_redo, s_t, s_task); break;
+        }
+    }
+}
+
 // Persistent LMP-PCG over a task list, one solve_column per task.  One launch
 // serves problems of every n: geoms[p] is problem p's geometry (all with
 // blockDim.x / 64 waves), and the workgroup takes the matching points-per-lane
@@ -892,6 +953,22 @@ __global__ __launch_bounds__(512) void k_solve(const TladArgs *__restrict__ prob
             default: solve_column<9>(a, g, task.col, smraw, s_red, s_t); break;
         }
     }
+}
+
+// Gamma columns of every problem (block p: problem p) and the per-call resets
+// of the sketch launch.
+__global__ void k_solve_prelude(int np, const TladArgs *__restrict__ probs, SolveSketch sk) {
+    const int p = blockIdx.x;
+    if (p >= np) return;
+    const RedoJob &J = sk.core[p];
+    const int n = J.n;
+    const double *b = probs[p].pcg.b;
+    double *phi = const_cast<double *>(sk.hv[p].V);
+    for (long long idx = threadIdx.x; idx < (long long)n * J.l; idx += blockDim.x) {
+        const int i = (int)(idx % n), j = (int)(idx / n);
+        phi[idx] = b[(long long)(j + 1) * n + i] - b[i];
+    }
+    if (threadIdx.x == 0) sk.done[p] = 0;
 }
 
 // out[t] = iterations task t took in the last persistent solve, and
@@ -1269,6 +1346,8 @@ hipError_t launch_hv_multi_q(hipStream_t s, const TladArgs *d_probs, const Solve
 
 // static LDS of k_solve (task id, reduction slots, LMP coefficients)
 constexpr size_t SOLVE_STATIC_LDS = sizeof(int) + 16 * sizeof(double) + 128 * sizeof(double) + 64;
+// static LDS of k_sketch (task id, norms, pass scratch)
+constexpr size_t SKETCH_STATIC_LDS = sizeof(int) + 128 * sizeof(double) + sizeof(nys::RedoLds) + 64;
 
 }  // namespace
 
@@ -1293,6 +1372,26 @@ hipError_t launch_solve(hipStream_t s, const TladArgs *d_probs, const TladGeom *
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_solve, dim3(grid), dim3(64 * waves), lds, s, d_probs, d_geoms, d_tasks, d_qoff, d_counters);
     return hipGetLastError();
+}
+
+hipError_t launch_solve_prelude(hipStream_t s, int np, const TladArgs *d_probs, const SolveSketch &sk) {
+    if (np <= 0 || !sk.hv) return hipSuccess;
+    hipLaunchKernelGGL(k_solve_prelude, dim3(np), dim3(256), 0, s, np, d_probs, sk);
+    return hipGetLastError();
+}
+
+hipError_t launch_sketch(hipStream_t s, const TladGeom *d_geoms, const SolveTask *d_tasks, int ntasks, int *d_counter,
+                         int waves, size_t lds, int grid, const SolveSketch &sk) {
+    if (ntasks <= 0) return hipSuccess;
+    if (grid <= 0 || (waves != 1 && waves != 2 && waves != 4 && waves != 8) || lds + SKETCH_STATIC_LDS > 160 * 1024)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sketch, dim3(grid), dim3(64 * waves), lds, s, d_geoms, d_tasks, ntasks, d_counter, sk);
+    return hipGetLastError();
+}
+
+int sketch_blocks_per_cu(int waves, size_t lds) {
+    int nb = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sketch, 64 * waves, lds) == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_hv_multi(hipStream_t s, const TladArgs *d_probs, const SolveTask *d_tasks, int ntasks,

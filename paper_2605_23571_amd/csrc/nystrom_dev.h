@@ -1,6 +1,6 @@
 // Workgroup-level small linear algebra of the Nystrom core, shared by the
-// small-matrix kernels (small_la.hip) and the persistent batch solve
-// (l96_tlad.hip): ell x ell Cholesky with the inverse of its factor, the
+// small-matrix kernels (small_la.hip) and the batch's persistent sketch
+// launch (l96_tlad.hip): ell x ell Cholesky with the inverse of its factor, the
 // one-sided Jacobi SVD, and the whole last pass of the Nystrom algorithm with
 // its shifts (nystrom_redo).  Every function runs on the calling workgroup,
 // whatever its size (blockDim.x a multiple of 64, at least 64 threads), and

@@ -217,7 +217,7 @@ __global__ void k_fill_int(int count, int value, int *__restrict__ p) {
 __global__ void k_gather_info(int np, const int32_t *const *__restrict__ info, int32_t *__restrict__ out) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < np) {
-        out[2 * i] = info[i][3];
+        out[2 * i] = info[i][5];
         out[2 * i + 1] = info[i][4];
     }
 }

@@ -5,7 +5,7 @@
 // on one workgroup with the working matrix in LDS.  All orderings and
 // reductions are fixed, so results are reproducible run to run.  The
 // workgroup-level routines (Cholesky, Jacobi SVD, the shifted Nystrom pass)
-// live in nystrom_dev.h, which the persistent batch solve shares.
+// live in nystrom_dev.h, which the batch's persistent sketch launch shares.
 #include "nystrom_dev.h"
 
 namespace eda {
@@ -25,15 +25,6 @@ __global__ __launch_bounds__(SC) void k_chol_inv(int l, const double *__restrict
     extern __shared__ double S[];  // l x l, col-major; upper triangle becomes C; then X (l <= 64)
     __shared__ int fail;
     chol_inv(l, W, shift, C, Cinv, info, S, fail);
-}
-
-// Many independent factorisations in one launch, one workgroup each (the same
-// arithmetic as k_chol_inv, so the same bits).
-__global__ __launch_bounds__(SC) void k_chol_inv_batch(const CholJob *__restrict__ jobs) {
-    extern __shared__ double S[];
-    __shared__ int fail;
-    const CholJob j = jobs[blockIdx.x];
-    chol_inv(j.l, j.W, j.shift, j.C, j.Cinv, j.info, S, fail);
 }
 
 __global__ void k_sym(int l, double *W) {
@@ -68,16 +59,6 @@ __global__ __launch_bounds__(SJ) void k_jacobi_svd(int l, const double *__restri
     __shared__ int rotated;
     __shared__ double nrm[128];
     jacobi_svd(l, T, U, sig, A, rotated, nrm);
-}
-
-// Many independent SVDs in one launch, one workgroup each (the same
-// arithmetic as k_jacobi_svd, so the same bits).
-__global__ __launch_bounds__(SJ) void k_jacobi_svd_batch(const JacobiJob *__restrict__ jobs) {
-    extern __shared__ double A[];
-    __shared__ int rotated;
-    __shared__ double nrm[128];
-    const JacobiJob j = jobs[blockIdx.x];
-    jacobi_svd(j.l, j.T, j.U, j.sig, A, rotated, nrm);
 }
 
 // Two-sided cyclic Jacobi EVD of symmetric T (l x l), parallel ordering:
@@ -251,23 +232,13 @@ __global__ void k_lmp_coef(int k, const double *sig, double nu, int square, int 
     }
 }
 
-// The shifted last Nystrom pass (nys::nystrom_redo) of one problem per workgroup.
+// The last Nystrom pass with its shifts (nys::nystrom_redo) of one problem.
 __global__ __launch_bounds__(SC) void k_nystrom_redo(RedoJob J) {
     extern __shared__ double X[];
     __shared__ nys::RedoLds L;
     __shared__ double nrm[128];
     nys::nystrom_redo(J, X, L, nrm);
 }
-
-__global__ __launch_bounds__(SC) void k_nystrom_redo_batch(const RedoJob *__restrict__ jobs) {
-    extern __shared__ double X[];
-    __shared__ nys::RedoLds L;
-    __shared__ double nrm[128];
-    const RedoJob J = jobs[blockIdx.x];
-    nys::nystrom_redo(J, X, L, nrm);
-}
-
-size_t redo_lds(int lmax) { return sizeof(double) * nys::redo_lds_doubles(lmax); }
 
 __global__ void k_axpy_cols(int n, int nb, double alpha, const double *__restrict__ X, long long ldx,
                             double *__restrict__ Y, long long ldy) {
@@ -294,26 +265,11 @@ hipError_t launch_chol_inv(hipStream_t s, int l, const double *W, double shift, 
     return hipGetLastError();
 }
 
-hipError_t launch_chol_inv_batch(hipStream_t s, int njobs, const CholJob *d_jobs, int lmax) {
-    if (njobs <= 0) return hipSuccess;
-    if (lmax < 1 || lmax > 128) return hipErrorInvalidValue;
-    // every job fits: a job needs 2 l^2 doubles up to l = 64 and l^2 above
-    const int need = lmax <= 64 ? 2 * lmax * lmax : (lmax * lmax > 2 * 64 * 64 ? lmax * lmax : 2 * 64 * 64);
-    const size_t lds = sizeof(double) * need;
-    hipLaunchKernelGGL(k_chol_inv_batch, dim3(njobs), dim3(SC), lds, s, d_jobs);
-    return hipGetLastError();
-}
+size_t redo_lds(int lmax) { return sizeof(double) * nys::redo_lds_doubles(lmax); }
 
 hipError_t launch_nystrom_redo(hipStream_t s, const RedoJob &job) {
     if (job.l < 1 || job.l > 128 || job.k < 1 || job.k > job.l || job.n < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_nystrom_redo, dim3(1), dim3(SC), redo_lds(job.l), s, job);
-    return hipGetLastError();
-}
-
-hipError_t launch_nystrom_redo_batch(hipStream_t s, int njobs, const RedoJob *d_jobs, int lmax) {
-    if (njobs <= 0) return hipSuccess;
-    if (lmax < 1 || lmax > 128) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_nystrom_redo_batch, dim3(njobs), dim3(SC), redo_lds(lmax), s, d_jobs);
     return hipGetLastError();
 }
 
@@ -330,13 +286,6 @@ hipError_t launch_small_gemm(hipStream_t s, int l, bool ta, bool tb, const doubl
 hipError_t launch_jacobi_svd_u(hipStream_t s, int l, double *T, double *U, double *sig) {
     if (l > 128) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_jacobi_svd, dim3(1), dim3(SJ), sizeof(double) * l * l, s, l, T, U, sig);
-    return hipGetLastError();
-}
-
-hipError_t launch_jacobi_svd_batch(hipStream_t s, int njobs, const JacobiJob *d_jobs, int lmax) {
-    if (njobs <= 0) return hipSuccess;
-    if (lmax < 1 || lmax > 128) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_jacobi_svd_batch, dim3(njobs), dim3(SJ), sizeof(double) * lmax * lmax, s, d_jobs);
     return hipGetLastError();
 }
 

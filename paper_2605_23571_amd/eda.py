@@ -307,7 +307,7 @@ def eda_batch_create(ctxs, ws):
 
 
 def eda_batch_solve(batch, k_cap: int, rtol: float, maxit: int, use_lmp: bool = True) -> tuple[int, int]:
-    """Returns (problems redone on the host path, of those left without LMP)."""
+    """Returns (problems whose last Nystrom pass took a shift, of those left without LMP)."""
     fb = (ctypes.c_int32 * 2)()
     _check("eda_batch_solve", lib().eda_batch_solve(batch, int(k_cap), float(rtol), int(maxit), int(bool(use_lmp)),
                                                     fb), ok=(EDA_OK, EDA_WARN_NOT_CONVERGED))
@@ -343,7 +343,7 @@ def eda_batch_tuning(batch) -> list[dict]:
 def eda_batch_timing(batch) -> dict:
     out = (ctypes.c_double * 3)()
     _check("eda_batch_timing", lib().eda_batch_timing(batch, out))
-    return dict(sketch_ms=out[0], shifted_redo_ms=out[1], solve_ms=out[2])
+    return dict(sketch_ms=out[0], prelude_ms=out[1], solve_ms=out[2])
 
 
 def eda_batch_destroy(batch):
