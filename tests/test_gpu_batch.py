@@ -253,6 +253,44 @@ def test_batch_sketch_pass_equals_single_problem_shifted_pass():
         g.close()
 
 
+def test_batch_wide_sketches_against_oracle():
+    # ell = 72 and 128 (above 64): the last Nystrom pass in the sketch launch's
+    # 256-thread workgroups takes its large-ell paths (the Cholesky inverse in
+    # place, the SVD's matrix alone in LDS).  Eigenvalues against the oracle's
+    # Nystrom to the bar of two correct FP64 implementations (16 x 2 cond(core)
+    # eps sqrt(d_1 / d_i)), members to the exact solution.
+    # length scale 2 keeps U_B's spectrum wide enough for 128 well-determined directions at n = 512
+    cfgs = [W.config("C2", n=512, nsteps=10, obs_dt=5, members=L, ell=L, k=L, len_b=2.0, problem_id=400 + i,
+                     spinup=100) for i, L in enumerate((72, 130))]
+    zs = [W.problem_normals(c) for c in cfgs]
+    probs = [eda.Problem(c, z, max_ell=min(c["members"], 128)) for c, z in zip(cfgs, zs)]
+    bt = eda.Batch(probs)
+    shifted, unprec = bt.solve(k_cap=128, rtol=1e-10, maxit=3000)
+    print(f"[batch] shifted {shifted}, without LMP {unprec}", flush=True)
+    assert unprec == 0
+    eps = np.finfo(float).eps
+    for p, (cfg, z) in enumerate(zip(cfgs, zs)):
+        ell = min(cfg["members"], 128)
+        o = O.Problem(cfg, z)
+        S, D, info = O.nystrom(lambda V: o.A(V, [0] * V.shape[1]), o.gamma(ell), ell)
+        eig = probs[p].field("eig").cpu().numpy()
+        assert eig.size == ell
+        bars = np.maximum(1e-13, 32.0 * info["cond_core"] * eps * np.sqrt(D[0] / D))
+        err = np.abs(eig - D) / D
+        print(f"[batch] ell={ell}: shifts {probs[p].sketch_info()[5]}, cond(core) {info['cond_core']:.1e}, "
+              f"max err/bar {np.max(err / bars):.3f}, err[0] {err[0]:.1e}", flush=True)
+        assert np.all(err <= bars), (err, bars)
+        res = bt.result(p)
+        assert (res["status"] == eda.EDA_MEMBER_CONVERGED).all()
+        dz = res["dz"].cpu().numpy()
+        for m in (0, cfg["members"]):
+            ex = O.exact_solution(o, m)
+            assert np.linalg.norm(dz[m] - ex) / np.linalg.norm(ex) < 1e-6
+    bt.close()
+    for g in probs:
+        g.close()
+
+
 def test_batch_repeat_calls_bitwise_with_shared_cus():
     # the n = 2048 class of the 256-problem workload: more member columns than persistent workgroups,
     # two workgroups per CU, so each workgroup runs several columns in turn next
