@@ -83,9 +83,12 @@ extern "C" {
 #define EDA_THETA_LAMK  1        /* theta = lambda_k(I+A)                                    */
 #define EDA_THETA_ONE   2        /* theta = 1                                                */
 
-#define EDA_XCH_OFF   0          /* eda_set_exchange: never (default)                          */
+#define EDA_XCH_OFF   0          /* eda_set_exchange: independent ring pieces (full halos)     */
 #define EDA_XCH_ON    1          /* eda_set_exchange: wave pieces with halo exchange whenever  */
                                  /* a launch shape exists for the running columns             */
+#define EDA_XCH_OBS   2          /* eda_set_exchange: ring pieces that share the observed      */
+                                 /* increments: shorter halos, one wait per iteration         */
+                                 /* (default)                                                 */
 
 #define EDA_LMP_P  0             /* apply P_theta                                            */
 #define EDA_LMP_U  1             /* apply the symmetric factor U_theta                       */
@@ -375,22 +378,32 @@ int eda_set_geometry(eda_ctx *ctx, int32_t waves, int32_t tb);
  * the kernel supports); EDA_ERR_INVALID_ARG for other values. */
 int eda_set_split(eda_ctx *ctx, int32_t pieces);
 
-/* Wave pieces with halo exchange in the split iterations of eda_pcg_solve
- * (banded U_B with the LMP, n >= 512, pieces = 0 in eda_set_split).  Every
- * wave of a launch owns one segment of one running column; the segments of a
- * column exchange the edges of their TL and AD states through device memory
- * at every time-block boundary, so a column is spread over many compute units
- * with no recomputed halo (the integrations of the tangent linear and adjoint
- * models over the assimilation window, cost model of the Nystrom
- * subsection).  The launch takes one workgroup per compute unit, all
- * co-resident; waits are bounded.  mode: EDA_XCH_OFF (default; on MI355X
- * the ring pieces are faster at the sizes measured) or EDA_XCH_ON (used
- * whenever a launch shape exists for the running columns).  spin_limit:
+/* How the pieces of a member column exchange data in the split iterations of
+ * eda_pcg_solve (banded U_B with the LMP, n >= 512; the integrations of the
+ * tangent linear and adjoint models over the assimilation window, cost model
+ * of the Nystrom subsection).  mode:
+ *  EDA_XCH_OBS (default): ring pieces (eda_set_split) that share the
+ *    column's observed increments R^-1 H dx: each piece computes those of its
+ *    own states, then waits (bounded) for its two neighbours' before its AD
+ *    run, so its rings carry ceil(n / P) + 12 N + 2 w states instead of
+ *    ceil(n / P) + 24 N + 4 w (w: the U_B band half-width).  Used when every
+ *    piece of the launch is co-resident (pieces x running columns <= compute
+ *    units) and every piece has at least 8 N + w states; otherwise the
+ *    independent ring pieces run.
+ *  EDA_XCH_OFF: independent ring pieces (no waits).
+ *  EDA_XCH_ON: wave pieces with halo exchange, pieces = 0 in eda_set_split
+ *    only.  Every wave of a launch owns one segment of one running column;
+ *    the segments of a column exchange the edges of their TL and AD states
+ *    through device memory at every time-block boundary, so a column is
+ *    spread over many compute units with no recomputed halo.  The launch
+ *    takes one workgroup per compute unit, all co-resident.  On MI355X the
+ *    ring pieces are faster at the sizes measured.
+ * All waits are bounded.  spin_limit:
  * polls of one wait before it gives up; < 0 restores the default (about a
  * second); 0 makes every wait give up at once (to exercise the error path).
  * The limit also bounds the tile barriers of the single-launch LMP
  * (eda_set_lmp_form).  A wait that gives up stops its member with
- * EDA_MEMBER_BREAKDOWN (exchange) or voids the call's results (LMP) and makes
+ * EDA_MEMBER_BREAKDOWN (pieces) or voids the call's results (LMP) and makes
  * eda_pcg_solve return EDA_ERR_SYNC; so does a workgroup placed on an XCD other
  * than the one the layout assumes.  Solutions agree with the other forms to
  * rounding.  Errors: EDA_ERR_INVALID_ARG for other modes. */

@@ -1054,11 +1054,24 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                     EDA_TRY(fused_iteration(c, nm, a, pbuf[cur], rtol, it));
                     EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status, c.rz_part, true));
                 } else {
+                    // ring pieces; with EDA_XCH_OBS they share the observed
+                    // increments (shorter rings, one bounded wait) when every
+                    // piece of the launch is co-resident (one per compute unit)
+                    const int grid = (sc.count > 0 ? sc.count : nm) * P;
+                    const bool sh = c.xch_mode == EDA_XCH_OBS && c.xch_flags && grid <= c.num_cus &&
+                                    (long long)nm * SPLIT_PMAX <= 8ll * XCH_GRID_MAX &&
+                                    tlad_split_ring_sh(n, c.N, c.band_hi, P) > 0;
                     TladArgs t = tlad_args(c, nm, c.pc_members, nullptr);
                     t.obs = c.hv_obs;
                     t.pieces = P;
-                    t.ring = tlad_split_ring(n, c.N, c.band_hi, P);
-                    t.halo = tlad_split_halo(c.N, c.band_hi);
+                    t.ring = sh ? tlad_split_ring_sh(n, c.N, c.band_hi, P) : tlad_split_ring(n, c.N, c.band_hi, P);
+                    t.halo = sh ? tlad_split_halo_sh(c.N, c.band_hi) : tlad_split_halo(c.N, c.band_hi);
+                    if (sh) {
+                        t.pflags = c.xch_flags;
+                        t.want = (++c.xch_epoch) << 16;
+                        t.spin_max = c.xch_spin < 0 ? XCH_SPIN_DEFAULT : c.xch_spin;
+                        t.err = c.xch_err;
+                    }
                     t.pcg.members = c.pc_members;
                     t.pcg.b = c.b;
                     t.pcg.x = c.pc_x;
@@ -1073,7 +1086,7 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                     t.pcg.iters = c.pc_iters;
                     t.pcg.it = it;
                     t.pcg.first = it == 1 ? 1 : 0;
-                    EDA_TRY(run_tlad(c, t, TLAD_SPLIT, false, &sc));
+                    EDA_TRY(run_tlad(c, t, sh ? TLAD_SPLIT_SH : TLAD_SPLIT, false, &sc));
                     LmpFin f{};
                     f.q = c.pc_q;
                     f.p = pbuf[cur ^ 1];
@@ -1231,7 +1244,7 @@ int eda_set_geometry(eda_ctx *h, int32_t waves, int32_t tb) {
 }
 
 int eda_set_exchange(eda_ctx *h, int32_t mode, int64_t spin_limit) {
-    if (!h || (mode != EDA_XCH_ON && mode != EDA_XCH_OFF)) return EDA_ERR_INVALID_ARG;
+    if (!h || (mode != EDA_XCH_ON && mode != EDA_XCH_OFF && mode != EDA_XCH_OBS)) return EDA_ERR_INVALID_ARG;
     h->c.xch_mode = mode;
     h->c.xch_spin = spin_limit < 0 ? -1 : (long long)spin_limit;
     return EDA_OK;

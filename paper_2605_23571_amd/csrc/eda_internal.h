@@ -76,7 +76,7 @@ struct Ctx {
     unsigned int *lmp_sync = nullptr;  // tile barrier counters of the single-launch LMP (2 x tiles)
     int lmp_form = EDA_LMP_FORM_TWO;
     unsigned long long xch_epoch = 0;
-    int xch_mode = EDA_XCH_OFF;
+    int xch_mode = EDA_XCH_OBS;
     long long xch_spin = -1;
     int split_force = 0;  // pieces per column forced by eda_set_split (0: automatic)
     // pipelined PCG convergence checks: pinned host slots and their events
@@ -147,6 +147,7 @@ enum TladMode : int {
     TLAD_PCG = 3,   // one fused PCG iteration per member column (banded U_B), see k_tlad
     TLAD_SPLIT = 4, // the Hessian part of a PCG iteration on pieces of each member column, see tlad_column
     TLAD_SPLIT_HV = 5, // TLAD_HV on pieces of each column (ring, halos and pieces as TLAD_SPLIT)
+    TLAD_SPLIT_SH = 6, // TLAD_SPLIT with the pieces of a column sharing its observed increments
 };
 
 // A member column split into P pieces: piece i owns the states
@@ -165,6 +166,19 @@ struct SplitCols {
 };
 int tlad_split_halo(int N, int band_hi);
 int tlad_split_ring(int n, int N, int band_hi, int pieces);  // 0: not possible (ring longer than n)
+// Pieces that share the column's observed increments (TLAD_SPLIT_SH): piece i
+// writes R^-1 H dx at its owned states only, into the column's one buffer of
+// observed increments, then waits for its two neighbours' (one bounded wait
+// per launch).  Its TL run then needs exact states on the owned range only
+// (left halo 8 N + band_hi, right halo 4 N + band_hi: the TL cone grows 8
+// states left and 4 right per step, plus U_B), and its AD run, forced from the
+// shared buffer, exact lambda on the owned range widened by band_hi (left halo
+// 4 N + band_hi, right 8 N + band_hi).  Both rings hold ceil(n / P) + 12 N +
+// 2 band_hi points; the AD ring is the TL ring moved 4 N states right.  Every
+// piece is at least 8 N + band_hi states long, so the AD run only reads its
+// neighbours' increments.
+int tlad_split_halo_sh(int N, int band_hi);                     // left halo of the TL ring
+int tlad_split_ring_sh(int n, int N, int band_hi, int pieces);  // 0: not possible
 
 // ---- wave pieces with halo exchange (the Hessian part of a PCG iteration) ----
 // Every wave of the launch owns one segment of one running column and runs the
@@ -267,6 +281,13 @@ struct TladArgs {
     int band_lo, band_hi;
     int add_identity;     // HV: Y = U_B lambda_0 + X
     int pieces, ring, halo;  // TLAD_SPLIT: pieces per column, ring length, halo
+    // TLAD_SPLIT_SH: flags per (column, piece) (SPLIT_PMAX per column), the
+    // value this launch raises them to (above every earlier launch's), polls
+    // of the wait before it gives up, and the error word it then sets
+    unsigned long long *pflags;
+    unsigned long long want;
+    long long spin_max;
+    int32_t *err;
     PcgCols pcg;
 };
 // Launch geometry of the TL/AD kernel: waves per workgroup, ring segment owned

@@ -163,10 +163,12 @@ __device__ __forceinline__ void store_obs(double *o, const int *qi, const T (&dx
 // index off + j (mod n): ring position of its first point (base; the others
 // follow contiguously, wrapped), the mask of points inside the wave's owned
 // segment, and, in LDS (qi[q * 64 + lane]), the observation index of observed
-// points (-1 otherwise; owned points only if owned_obs_only).
+// points (-1 otherwise; if owned_obs_only, owned points at ring positions in
+// [obs_lo, obs_hi) only).
 template <int Q>
 __device__ __forceinline__ int window(const TladArgs &a, int w0, int own_lo, int own_hi, bool owned_obs_only,
-                                      unsigned &ownm, int *qi, int R, int off) {
+                                      unsigned &ownm, int *qi, int R, int off, int obs_lo = 0,
+                                      int obs_hi = 0x7fffffff) {
     const int n = a.n, lane = threadIdx.x & 63;
     int b = (w0 + lane * Q) % R;
     if (b < 0) b += R;
@@ -180,7 +182,8 @@ __device__ __forceinline__ int window(const TladArgs &a, int w0, int own_lo, int
         if (own) ownm |= 1u << q;
         const int r = p - a.obs_x0;
         const bool obs = r >= 0 && r % a.obs_dx == 0;
-        qi[q * 64 + lane] = (obs && (own || !owned_obs_only)) ? r / a.obs_dx : -1;
+        const bool keep = !owned_obs_only || (own && jw >= obs_lo && jw < obs_hi);
+        qi[q * 64 + lane] = (obs && keep) ? r / a.obs_dx : -1;
     }
     return b;
 }
@@ -387,18 +390,84 @@ __device__ __forceinline__ double block_sum(double v, double *red, int waves) {
     return s;
 }
 
+// Waits (bounded) until both flags reach `want`.
+__device__ __forceinline__ bool xch_wait(const unsigned long long *fa, const unsigned long long *fb,
+                                         unsigned long long want, long long spin_max) {
+    for (long long it = 0; it < spin_max; it++) {
+        const unsigned long long va = __hip_atomic_load(fa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long vb = __hip_atomic_load(fb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (va >= want && vb >= want) return true;
+    }
+    return false;
+}
+
+// Device-scope load and store of a double: they bypass the (per-XCD,
+// non-coherent) L2, so a value stored by a workgroup on one XCD is read by
+// one on another once the store has completed.
+__device__ __forceinline__ double load_dev(const double *p) {
+    return __longlong_as_double((long long)__hip_atomic_load(reinterpret_cast<const unsigned long long *>(p),
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+__device__ __forceinline__ void store_dev(double *p, double v) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Observed increments of this lane's owned observed points, stored at device
+// scope (TLAD_SPLIT_SH: the other pieces of the column read them).
+template <int Q>
+__device__ __forceinline__ void store_obs_dev(double *o, const int *qi, const double (&dx)[Q], double inv_s2) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        const int oi = qi[q * 64 + lane];
+        if (oi >= 0) store_dev(o + oi, dx[q] * inv_s2);
+    }
+}
+
+// TLAD_SPLIT_SH, between the TL and AD runs of piece `piece` of column c: the
+// piece has stored the observed increments of its owned states in its own
+// block, at device scope; every wave waits for its stores to complete, then
+// the piece raises its flag to this launch's value and waits (bounded) for
+// both neighbours' flags, after which their blocks can be read at device
+// scope.  (No cache line is written by two pieces, and a piece reads a
+// neighbour's block only after the flag, so no XCD's L2 holds a stale copy.)  (Device-scope release and acquire fences, which write
+// back and invalidate whole L2s, made the launch 10-25% slower.)  A wait that
+// gives up sets the error word and stops the member (its results are void);
+// the piece still raised its flag, so no neighbour waits on it.
+__device__ __forceinline__ void share_obs(const TladArgs &a, int c, int piece) {
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long *fl = a.pflags + (long long)c * SPLIT_PMAX;
+        __hip_atomic_store(fl + piece, a.want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int left = piece == 0 ? a.pieces - 1 : piece - 1;
+        const int right = piece == a.pieces - 1 ? 0 : piece + 1;
+        if (!xch_wait(fl + left, fl + right, a.want, a.spin_max)) {
+            __hip_atomic_store(a.err, 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            a.pcg.status[c] = EDA_MEMBER_BREAKDOWN;
+        }
+    }
+    __syncthreads();
+}
+
 // One column of one problem, all modes (the workgroup's whole job in k_tlad,
 // one step of the task loop in k_solve).  PCG mode runs iteration `it` (first:
 // p = z).  SPLIT mode runs the Hessian part of that iteration on piece `piece`
 // of the column: the ring is the piece's owned states [lo, hi) with a.halo
 // states on each side (ring position j = state lo - halo + j mod n); positions
 // whose dependency cone reaches the ring's seam are wrong, the owned ones
-// exact.  Every early exit is taken by the whole workgroup.
+// exact.  SPLIT_SH mode runs SPLIT with the pieces sharing the column's
+// observed increments (share_obs; the halos of tlad_split_ring_sh): a.halo is
+// then the TL ring's left halo, and the AD run uses the ring moved 4 N states
+// right.  Every early exit is taken by the whole workgroup.
 template <typename T, int Q, int MODE, bool EARLY = true>
 __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g, const int c, const int it,
                                             const int first, unsigned char *smraw, const int piece = 0) {
     constexpr bool SPLIT_HV = MODE == TLAD_SPLIT_HV;
-    constexpr bool SPLIT = MODE == TLAD_SPLIT || SPLIT_HV;  // ring of one piece
+    constexpr bool SHARE = MODE == TLAD_SPLIT_SH;  // pieces share the observed increments
+    constexpr bool SPLIT = MODE == TLAD_SPLIT || SPLIT_HV || SHARE;  // ring of one piece
     constexpr bool FUSED = (MODE == TLAD_HV || MODE == TLAD_PCG || SPLIT);
     const int n = a.n, N = a.N, p = a.nt * a.nv;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x, nthr = blockDim.x;
@@ -426,10 +495,12 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
     double *red = taps + W;
     double *lamd = reinterpret_cast<double *>(ring);  // ring reused as a double array for lambda_0
     const int own_lo = wave * g.S, own_hi = min(R, own_lo + g.S);
-    const int member = (MODE == TLAD_PCG || MODE == TLAD_SPLIT) ? a.pcg.members[c]
+    const int member = (MODE == TLAD_PCG || MODE == TLAD_SPLIT || SHARE) ? a.pcg.members[c]
                                                                : (a.col_member ? a.col_member[c] : 0);
     // row s of the member's padded trajectory, from ring position 0: trajm + s ext_len
     const double *trajm = a.trajx + (long long)member * a.trajx_stride + a.pad_l + off;
+    // this piece's block of observed increments (per column, per piece if SPLIT)
+    const long long obs_at = ((long long)c * (SPLIT ? a.pieces : 1) + piece) * p;
     const StepK<T> K{(T)a.h, (T)a.dt, (T)a.dt6, (T)a.dt3, (T)(a.h * a.F)};
     unsigned ownm;
     int rsel = 0;
@@ -489,7 +560,8 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
         // ---------------- TL forward run ----------------
         const int w0 = own_lo - g.hl_tl;
         prefetch_window<Q>(trajm + w0, xw);
-        int base = window<Q>(a, w0, own_lo, own_hi, true, ownm, qi, R, off);
+        int base = SHARE ? window<Q>(a, w0, own_lo, own_hi, true, ownm, qi, R, off, core_lo, core_hi)
+                         : window<Q>(a, w0, own_lo, own_hi, true, ownm, qi, R, off);
         T dx[Q];
         if (FUSED) {
             double v0[Q];
@@ -501,7 +573,7 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
 #pragma unroll
             for (int q = 0; q < Q; q++) dx[q] = (T)vcol[wpos(base, q, n)];
         }
-        double *obs = a.obs + ((long long)c * (SPLIT ? a.pieces : 1) + piece) * p;
+        double *obs = a.obs + obs_at;
         for (int s0 = 0; s0 < N; s0 += g.tb) {
             if (s0 > 0) {
                 __syncthreads();
@@ -511,8 +583,10 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
             const int s1 = min(N, s0 + g.tb);
             for (int s = s0; s < s1; s++) {
                 // observed increment of time s
-                if (s > 0 && s % a.obs_dt == 0)
-                    store_obs<T, Q>(obs + (long long)(s / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
+                if (s > 0 && s % a.obs_dt == 0) {
+                    if constexpr (SHARE) store_obs_dev<Q>(obs + (long long)(s / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
+                    else store_obs<T, Q>(obs + (long long)(s / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
+                }
                 tl_step<T, Q, EARLY>(K, xw, trajm + (long long)min(s + 1, N - 1) * a.ext_len + w0, s + 1 < N, dx);
             }
             if (s1 < N) {
@@ -522,8 +596,19 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
                 rsel ^= 1;
             }
         }
-        if (N % a.obs_dt == 0) store_obs<T, Q>(obs + (long long)(N / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
+        if (N % a.obs_dt == 0) {
+            if constexpr (SHARE) store_obs_dev<Q>(obs + (long long)(N / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
+            else store_obs<T, Q>(obs + (long long)(N / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
+        }
         __threadfence_block();  // observed increments visible to the whole workgroup
+    }
+    if constexpr (SHARE) {
+        share_obs(a, c, piece);
+        // the AD ring: the TL ring moved 4 N states right
+        off += 4 * N;
+        core_lo -= 4 * N;
+        core_hi -= 4 * N;
+        trajm += 4 * N;
     }
     __syncthreads();  // TL reads of the ring and of the observation indices are done
 
@@ -531,8 +616,22 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
     const int w0 = own_lo - g.hl_ad;
     prefetch_window<Q>(trajm + (long long)(N - 1) * a.ext_len + w0, xw);
     const int base = window<Q>(a, w0, own_lo, own_hi, false, ownm, qi, R, off);
+    // SHARE: the forcing of a window point is read from the block of the piece
+    // that owns its state (this one or a neighbour; the index into the column's
+    // blocks is folded into qi)
     const double *force = (MODE == TLAD_ADJ) ? a.force + (long long)c * p
-                                              : a.obs + ((long long)c * (SPLIT ? a.pieces : 1) + piece) * p;
+                          : SHARE            ? a.obs + (long long)c * a.pieces * p
+                                             : a.obs + obs_at;
+    if constexpr (SHARE) {
+        const int left = piece == 0 ? a.pieces - 1 : piece - 1;
+        const int right = piece == a.pieces - 1 ? 0 : piece + 1;
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+            const int jr = wpos(base, q, R);
+            int &e = qi[q * 64 + lane];
+            if (e >= 0) e += (jr < core_lo ? left : jr >= core_hi ? right : piece) * p;
+        }
+    }
     T lam[Q];
 #pragma unroll
     for (int q = 0; q < Q; q++) lam[q] = T(0);
@@ -549,7 +648,11 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
             #pragma unroll
                 for (int q = 0; q < Q; q++) {
                     const int oi = qi[q * 64 + lane];
-                    if (oi >= 0) lam[q] += (T)f[oi];
+                    if constexpr (SHARE) {
+                        if (oi >= 0) lam[q] += load_dev(f + oi);
+                    } else {
+                        if (oi >= 0) lam[q] += (T)f[oi];
+                    }
                 }
             }
             ad_step<T, Q, EARLY>(K, xw, trajm + (long long)max(s - 2, 0) * a.ext_len + w0, s >= 2, lam);
@@ -608,7 +711,7 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
         for (int q = 0; q < Q; q++) {
             const int j = wpos(base, q, R);
             if ((ownm & (1u << q)) && j >= core_lo && j < core_hi) {
-                const double pv = u[j];
+                const double pv = u[SHARE ? j + 4 * N : j];  // u is on the TL ring
                 y[q] += pv;
                 pq += pv * y[q];
                 a.pcg.q[cn + state(j)] = y[q];
@@ -689,6 +792,19 @@ __global__ __launch_bounds__(512) void k_tlad_split(TladArgs a, TladGeom g, Spli
     const int piece = blockIdx.x / m;
     if (a.pcg.status[c] != COL_RUNNING) return;
     tlad_column<double, Q, TLAD_SPLIT>(a, g, c, a.pcg.it, a.pcg.first, smraw, piece);
+}
+
+// The same with the pieces of a column sharing its observed increments
+// (TLAD_SPLIT_SH); every piece of a running column reaches share_obs (the
+// column's status and r^T z are the same for all of them).
+template <int Q>
+__global__ __launch_bounds__(512) void k_tlad_split_sh(TladArgs a, TladGeom g, SplitCols sc) {
+    extern __shared__ __align__(16) unsigned char smraw[];
+    const int m = sc.count > 0 ? sc.count : a.nb;
+    const int c = sc.count > 0 ? sc.col[blockIdx.x % m] : (int)(blockIdx.x % m);
+    const int piece = blockIdx.x / m;
+    if (a.pcg.status[c] != COL_RUNNING) return;
+    tlad_column<double, Q, TLAD_SPLIT_SH>(a, g, c, a.pcg.it, a.pcg.first, smraw, piece);
 }
 
 // Split Hessian products: workgroup b takes piece b / nb of column b % nb
@@ -1007,11 +1123,6 @@ __global__ __launch_bounds__(512) void k_hv_multi(const TladArgs *__restrict__ p
 // XCC_ID hardware register (id 20, bits 3:0): the XCD a wave runs on.
 __device__ __forceinline__ int xcc_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11)); }
 
-__device__ __forceinline__ double load_dev(const double *p) {
-    return __longlong_as_double((long long)__hip_atomic_load(reinterpret_cast<const unsigned long long *>(p),
-                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-}
-
 // Banded circulant product from a slice: out[q] = sum_m taps[m] us[l Q + q + m]
 // for this lane l (us: 64 Q + W - 1 values); a circular register buffer of Q
 // values keeps one LDS read per tap, the taps in ascending order.
@@ -1041,17 +1152,6 @@ __device__ __forceinline__ void band_slice(const double *us, const double *taps,
             for (int q = 0; q < Q; q++) out[q] += t * (mm + q < Q ? B[mm + q] : u[m0 + mm + q]);
         }
     }
-}
-
-// Waits (bounded) until both flags reach `want`.
-__device__ __forceinline__ bool xch_wait(const unsigned long long *fa, const unsigned long long *fb,
-                                         unsigned long long want, long long spin_max) {
-    for (long long it = 0; it < spin_max; it++) {
-        const unsigned long long va = __hip_atomic_load(fa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned long long vb = __hip_atomic_load(fb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (va >= want && vb >= want) return true;
-    }
-    return false;
 }
 
 // Raises this slot's flag to phase `ph` after the wave's earlier stores
@@ -1289,9 +1389,10 @@ hipError_t launch_x_q(hipStream_t s, const TladArgs &a, const XchArgs &x, const 
 
 template <typename T, int Q>
 size_t lds_bytes(const TladArgs &a, const TladGeom &g, int mode) {
-    const size_t R = (mode == TLAD_SPLIT || mode == TLAD_SPLIT_HV) ? (size_t)a.ring : (size_t)a.n;
+    const bool split = mode == TLAD_SPLIT || mode == TLAD_SPLIT_HV || mode == TLAD_SPLIT_SH;
+    const size_t R = split ? (size_t)a.ring : (size_t)a.n;
     size_t b = sizeof(T) * 2 * R + (sizeof(int) + sizeof(double)) * (size_t)g.waves * 64 * Q;
-    if (mode == TLAD_HV || mode == TLAD_PCG || mode == TLAD_SPLIT || mode == TLAD_SPLIT_HV)
+    if (mode == TLAD_HV || mode == TLAD_PCG || split)
         b += sizeof(double) * (R + (size_t)(a.band_hi - a.band_lo + 1) + 16);
     return b;
 }
@@ -1312,6 +1413,14 @@ hipError_t launch_q(hipStream_t s, const TladArgs &a, const TladGeom &g, int mod
             const SplitCols &cs = sc ? *sc : all;
             const int m = cs.count > 0 ? cs.count : a.nb;
             hipLaunchKernelGGL(k_tlad_split<Q>, dim3(m * a.pieces), block, lds, s, a, g, cs);
+            break;
+        }
+        case TLAD_SPLIT_SH: {
+            if (!std::is_same<T, double>::value) return hipErrorInvalidValue;
+            SplitCols all{};
+            const SplitCols &cs = sc ? *sc : all;
+            const int m = cs.count > 0 ? cs.count : a.nb;
+            hipLaunchKernelGGL(k_tlad_split_sh<Q>, dim3(m * a.pieces), block, lds, s, a, g, cs);
             break;
         }
         case TLAD_SPLIT_HV:
@@ -1458,6 +1567,16 @@ int tlad_split_ring(int n, int N, int band_hi, int pieces) {
     return (g.q <= 9 && g.tb >= 1) ? R : 0;
 }
 
+int tlad_split_halo_sh(int N, int band_hi) { return 8 * N + band_hi; }
+
+int tlad_split_ring_sh(int n, int N, int band_hi, int pieces) {
+    if (pieces < 2 || pieces > SPLIT_PMAX || n / pieces < 8 * N + band_hi) return 0;
+    const int R = (n + pieces - 1) / pieces + 12 * N + 2 * band_hi;
+    if (R > n) return 0;
+    const TladGeom g = tlad_geometry(R, 0);
+    return (g.q <= 9 && g.tb >= 1) ? R : 0;
+}
+
 // Reach of the windows on a ring of R points over every geometry the
 // launchers accept (any accepted wave count, any time-block length up to its
 // maximum): windows start up to *left points before ring position 0 and end up
@@ -1497,6 +1616,19 @@ void tlad_pads_split(int n, int N, int band_hi, int *pad_l, int *pad_r) {
         ring_reach(R, &l, &r);
         const int lo_last = (int)((long long)(P - 1) * n / P);
         const int left = H + l, right = (lo_last - H) + R + r - n;
+        if (left > pl) pl = left;
+        if (right > pr) pr = right;
+    }
+    // rings of pieces sharing the observed increments: the TL ring starts
+    // 8 N + band_hi states before the piece, the AD ring 4 N states later
+    const int Hs = tlad_split_halo_sh(N, band_hi);
+    for (int P = 2; P <= SPLIT_PMAX; P++) {
+        const int R = tlad_split_ring_sh(n, N, band_hi, P);
+        if (R == 0) continue;
+        int l, r;
+        ring_reach(R, &l, &r);
+        const int lo_last = (int)((long long)(P - 1) * n / P);
+        const int left = Hs + l, right = (lo_last - Hs + 4 * N) + R + r - n;
         if (left > pl) pl = left;
         if (right > pr) pr = right;
     }
@@ -1595,8 +1727,18 @@ hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32, in
         if (a.pieces == 1 ? (a.ring != a.n || a.halo != 0) : a.ring != tlad_split_ring(a.n, a.N, a.band_hi, a.pieces))
             return hipErrorInvalidValue;
     }
-    const int R = (mode == TLAD_SPLIT || mode == TLAD_SPLIT_HV) ? a.ring : a.n;
+    if (mode == TLAD_SPLIT_SH) {
+        if (fp32 || a.pieces < 2 || a.ring != tlad_split_ring_sh(a.n, a.N, a.band_hi, a.pieces) || a.ring == 0 ||
+            a.halo != tlad_split_halo_sh(a.N, a.band_hi) || !a.pflags || !a.err || a.spin_max < 0)
+            return hipErrorInvalidValue;
+    }
+    const bool split = mode == TLAD_SPLIT || mode == TLAD_SPLIT_HV || mode == TLAD_SPLIT_SH;
+    const int R = split ? a.ring : a.n;
     if (waves != 0 && !tlad_waves_ok(R, waves)) return hipErrorInvalidValue;
+    // rings of pieces take 8 waves where they fit: two waves per SIMD hide
+    // more latency (at n = 4096, N = 40 the 1094- to 1948-point rings ran
+    // 6-17% faster per iteration than on 4 waves with twice the points)
+    if (waves == 0 && split && tlad_waves_ok(R, 8)) waves = 8;
     TladGeom g = tlad_geometry(R, waves, tb);
     if (g.q > 9 || g.tb < 1) return hipErrorInvalidValue;
     if (mode == TLAD_PCG && fp32) return hipErrorInvalidValue;  // PCG recurrences stay FP64

@@ -36,7 +36,7 @@ EDA_SKETCH_RHS_DIFF, EDA_SKETCH_USER, EDA_SKETCH_B_PSI, EDA_SKETCH_UBT_PSI = 0, 
 EDA_METHOD_NYSTROM, EDA_METHOD_REVD = 0, 1
 EDA_THETA_MID, EDA_THETA_LAMK, EDA_THETA_ONE = 0, 1, 2
 EDA_LMP_P, EDA_LMP_U = 0, 1
-EDA_XCH_OFF, EDA_XCH_ON = 0, 1
+EDA_XCH_OFF, EDA_XCH_ON, EDA_XCH_OBS = 0, 1, 2
 EDA_LMP_FORM_TWO, EDA_LMP_FORM_ONE = 0, 1
 EDA_PROF_TLAD, EDA_PROF_UB_GEMM = 0, 1
 EDA_LMP_NOALLOC_SCRATCH_BYTES = 4194304

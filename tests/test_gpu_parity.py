@@ -485,37 +485,62 @@ def test_pcg_not_converged_and_deterministic():
 
 @pytest.mark.parametrize("case", ["n1001", "n2049"])
 def test_split_iterations_match_whole_columns(case):
-    # Split iterations (the Hessian part on P pieces per column, each with
-    # halos of 12 N + 2 w states) against whole columns (P = 1).  The pieces'
-    # outputs are the whole column's bits; only the order of the pieces'
-    # partial sums of p^T (I + A) p differs, so after 4 iterations the iterates
-    # agree to rounding; solved to rtol 1e-10 every P reaches the exact solution.
+    # Split iterations (the Hessian part on P pieces per column) against whole
+    # columns (P = 1): independent ring pieces (halos of 12 N + 2 w states on
+    # each side, EDA_XCH_OFF) and pieces that share the observed increments
+    # (EDA_XCH_OBS, the default: 12 N + 2 w halo states in all, one bounded
+    # wait between the TL and AD runs).  The pieces' outputs are the whole
+    # column's bits; only the order of the partial sums of p^T (I + A) p
+    # differs (it follows the pieces and each piece's lane layout), so after 4
+    # iterations the iterates agree to rounding; solved to rtol 1e-10 every
+    # form reaches the exact solution.  A wait limit of 0 makes the shared form
+    # report EDA_ERR_SYNC, which shows that it ran (it needs pieces of at least
+    # 8 N + w states; shorter ones fall back to independent pieces).
     cfg, g, o = problem(case)
     g.sketch_evd("rhs_diff")
     members = np.arange(cfg["members"] + 1)
     ref = None
+    shared = []
+    worst = 0.0
     for P in (1, 2, 3, 4, 5, 8):
         try:
             eda.eda_set_split(g.ctx, P)
         except eda.EdaError as e:  # a ring of ceil(n / P) + 2 halos longer than n
             assert e.code == eda.EDA_ERR_UNSUPPORTED and P > 2, (P, e.code)
             continue
-        dz = g.pcg(members, rtol=0.0, maxit=4)["dz"].cpu().numpy()
-        if ref is None:
-            ref = dz
-        else:
-            assert rel(dz, ref) < 1e-12, (P, rel(dz, ref))
-    for P in (1, 8):
+        for xch in (eda.EDA_XCH_OFF, eda.EDA_XCH_OBS) if P > 1 else (eda.EDA_XCH_OFF,):
+            eda.eda_set_exchange(g.ctx, xch)
+            dz = g.pcg(members, rtol=0.0, maxit=4)["dz"].cpu().numpy()
+            if ref is None:
+                ref = dz
+            else:
+                e = colrel(dz, ref)
+                worst = max(worst, e)
+                assert e < 1e-12, (P, xch, e)
+        if P > 1:
+            eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OBS, 0)
+            try:
+                g.pcg(members, rtol=0.0, maxit=2)
+            except eda.EdaError as e:
+                assert e.code == eda.EDA_ERR_SYNC, e.code
+                shared.append(P)
+            eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OBS, -1)
+    print(f"[split] {case}: 4 iterations vs whole columns {worst:.1e} (element-wise); shared-observation "
+          f"pieces ran for P = {shared}", flush=True)
+    assert 2 in shared and 3 in shared
+    for P, xch in ((1, eda.EDA_XCH_OFF), (8, eda.EDA_XCH_OFF), (2, eda.EDA_XCH_OBS), (shared[-1], eda.EDA_XCH_OBS)):
         eda.eda_set_split(g.ctx, P)
+        eda.eda_set_exchange(g.ctx, xch)
         out = g.pcg(members, rtol=1e-10, maxit=500, history=True)
         assert np.all(out["status"] == eda.EDA_MEMBER_CONVERGED)
         assert np.all(out["relres"] <= 1e-10)
         for m in (0, cfg["members"]):
             xe = O.exact_solution(o, m)
-            assert rel(out["dz"][m].cpu().numpy(), xe) < 1e-8, (P, m)
+            assert elrel(out["dz"][m].cpu().numpy(), xe) < 1e-8, (P, xch, m)
             h = out["hist"][m][: out["iters"][m] + 1]
             assert np.all(np.diff(h) <= 1e-10 * abs(h[-1]))  # the cost decreases
     eda.eda_set_split(g.ctx, 0)
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OBS)
     a = g.pcg(members, rtol=1e-8, maxit=500)
     b = g.pcg(members, rtol=1e-8, maxit=500)
     assert torch.equal(a["dz"], b["dz"])  # the automatic pieces do not depend on timing
@@ -547,7 +572,7 @@ def test_exchange_iterations_match_whole_columns(case):
     again = g.pcg(members, rtol=1e-10, maxit=500)
     print(f"[xch] {case}: 4 iterations vs whole columns {e4:.1e}; rtol 1e-10 in {out['iters'].tolist()} "
           f"iterations, element-wise error vs exact {max(errs):.1e}", flush=True)
-    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OFF)
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OBS)
     assert e4 < 1e-12 and max(errs) < 1e-8
     assert torch.equal(out["dz"], again["dz"])
 
@@ -595,6 +620,17 @@ def test_exchange_wait_limit_reports_sync_error():
     eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OFF)
     off = g.pcg(members, rtol=1e-10, maxit=500)
     assert rel(off["dz"].cpu().numpy(), out["dz"].cpu().numpy()) < 1e-8
+    # the same for the pieces that share the observed increments (the default)
+    eda.eda_set_split(g.ctx, 2)
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OBS, 0)
+    with pytest.raises(eda.EdaError) as ei:
+        g.pcg(members, rtol=1e-10, maxit=50)
+    assert ei.value.code == eda.EDA_ERR_SYNC
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OBS, -1)
+    sh = g.pcg(members, rtol=1e-10, maxit=500)
+    assert np.all(sh["status"] == eda.EDA_MEMBER_CONVERGED)
+    assert rel(sh["dz"].cpu().numpy(), out["dz"].cpu().numpy()) < 1e-8
+    eda.eda_set_split(g.ctx, 0)
 
 
 def _lmp_form_problem(case):
@@ -617,7 +653,7 @@ def test_lmp_one_launch_matches_two_launches(case):
     g.sketch_evd("rhs_diff")
     members = np.arange(cfg["members"] + 1)
     forms = [("whole columns", 1, eda.EDA_XCH_OFF), ("ring pieces", 2, eda.EDA_XCH_OFF),
-             ("wave pieces", 0, eda.EDA_XCH_ON)]
+             ("shared-observation pieces", 2, eda.EDA_XCH_OBS), ("wave pieces", 0, eda.EDA_XCH_ON)]
     for label, P, xch in forms:
         eda.eda_set_split(g.ctx, P)
         eda.eda_set_exchange(g.ctx, xch)
@@ -630,7 +666,7 @@ def test_lmp_one_launch_matches_two_launches(case):
         print(f"[lmp form] {case} {label}: one launch == two launches: {same}", flush=True)
         assert same, (case, label)
     eda.eda_set_split(g.ctx, 0)
-    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OFF)
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OBS)
     if case == "n1001":
         cfg, gd, _ = problem(case, "dense")
         gd.sketch_evd("rhs_diff")
@@ -660,7 +696,7 @@ def test_lmp_one_launch_wait_limit_reports_sync_error():
     eda.eda_set_lmp_form(g.ctx, eda.EDA_LMP_FORM_TWO)
     two = g.pcg(members, rtol=1e-10, maxit=500)
     assert np.all(two["status"] == eda.EDA_MEMBER_CONVERGED)
-    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OFF, -1)
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OBS, -1)
     eda.eda_set_lmp_form(g.ctx, eda.EDA_LMP_FORM_ONE)
     one = g.pcg(members, rtol=1e-10, maxit=500)
     assert torch.equal(one["dz"], two["dz"])
