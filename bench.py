@@ -107,7 +107,7 @@ def pcg_kernel_bytes_per_col(cfg):
     return 8 * (2 * N * n + 2 * nt * nv + 6 * n)
 
 
-def run_form(cfg, z, ub_mode, steps, warmup, hv_reps, mixed=False, keep=False, q=1, lmp_form=None):
+def run_form(cfg, z, ub_mode, steps, warmup, hv_reps, mixed=False, keep=False, q=1, lmp_form=None, xch=None):
     import torch
     from paper_2605_23571_amd import eda
 
@@ -118,6 +118,8 @@ def run_form(cfg, z, ub_mode, steps, warmup, hv_reps, mixed=False, keep=False, q
     setup_s = time.perf_counter() - t0
     if lmp_form is not None:
         eda.eda_set_lmp_form(g.ctx, lmp_form)
+    if xch is not None:
+        eda.eda_set_exchange(g.ctx, xch)
     members = np.arange(L + 1)
 
     def step():
@@ -552,7 +554,8 @@ def main():
     if not a.no_plain:
         from paper_2605_23571_amd import eda
         legs = (("banded_q1_fp64", dict(mixed=False, q=1)), ("banded_q2_fp64", dict(mixed=False, q=CHOSEN_Q)),
-                ("chosen_lmp_one_launch", dict(mixed=True, q=CHOSEN_Q, lmp_form=eda.EDA_LMP_FORM_ONE)))
+                ("chosen_lmp_one_launch", dict(mixed=True, q=CHOSEN_Q, lmp_form=eda.EDA_LMP_FORM_ONE)),
+                ("chosen_independent_pieces", dict(mixed=True, q=CHOSEN_Q, xch=eda.EDA_XCH_OFF)))
         for name, kw in legs:
             print(f"[bench] {a.workload} {name}", file=sys.stderr, flush=True)
             r = run_form(cfg, z, "banded", max(1, a.steps // 2), 1 if a.warmup else 0, 2, **kw)
@@ -587,8 +590,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(act_per_launch),
-                     "kernel": "k_tlad<double, Q, 3|4> (Hessian part of a PCG iteration: U_B, TL, AD, U_B, (I + A) p; "
-                               "3 = whole columns with the update fused, 4 = 2-8 pieces per column)",
+                     "kernel": "k_tlad<double, Q, 3> and k_tlad_split_sh<Q> (Hessian part of a PCG iteration: U_B, "
+                               "TL, AD, U_B, (I + A) p; whole columns with the update fused, or 2-8 pieces per "
+                               "column sharing the observed increments)",
                      "bytes_per_column": bpc, "avg_launch_ms": round(avg_ms, 4),
                      "launches": chosen["tlad_launches"], "timed_launches": chosen["tlad_timed"], "active_column_iterations": chosen["active_cols"],
                      "kernel_sha": kernel_sha(),
@@ -606,6 +610,8 @@ def main():
             f"banded U_B, q={CHOSEN_Q}, FP64": ablation["banded_q2_fp64"]["value"],
             f"chosen: banded U_B, q={CHOSEN_Q}, FP32 sketch products": round(chosen["solves_per_s"], 3),
             "chosen with the one-launch LMP (tile barriers)": ablation["chosen_lmp_one_launch"]["value"],
+            "chosen with independent ring pieces (full halos, no shared observed increments)":
+                ablation["chosen_independent_pieces"]["value"],
             "iters_median": {k: v["iters_median"] for k, v in ablation.items()}}
     if plain and plain.get("gemm"):
         gm = plain["gemm"]
