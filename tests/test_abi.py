@@ -89,3 +89,17 @@ def test_bench_refuses_more_than_one_gpu():
                        timeout=120, cwd=root)
     assert r.returncode == 2
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_python_constants_match_header():
+    # every integer #define of the header that the binding also names has the
+    # same value there (modes, flags, fields, error and status codes)
+    import os
+    import re
+    hdr = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "eda.h")
+    defs = dict(re.findall(r"^#define\s+(EDA_\w+)\s+\(?(-?\d+)\)?", open(hdr).read(), re.M))
+    shared = [k for k in defs if hasattr(eda, k)]
+    assert len(shared) >= 20
+    for k in shared:
+        assert getattr(eda, k) == int(defs[k]), k
+    assert {"EDA_XCH_OFF", "EDA_XCH_ON", "EDA_XCH_OBS"} <= set(shared)
