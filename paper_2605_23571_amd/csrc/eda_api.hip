@@ -186,6 +186,15 @@ Plan make_plan(const eda_config *c) {
     size_t sk = gemm_splitk_elems(P.maxl, P.maxl, P.n);
     size_t sk2 = gemm_splitk_elems(P.maxl, P.maxc, P.n);
     P.splitk_elems = sk > sk2 ? sk : sk2;
+    if (c->ub_mode == EDA_UB_DENSE) {
+        // the dense U_B products of up to max(maxl, maxc) columns, K split
+        const int nbmax = P.maxl > P.maxc ? P.maxl : P.maxc;
+        for (int nb = 1; nb <= nbmax; nb++) {
+            const size_t e1 = gemm_splitk_elems(P.n, nb, P.n), e2 = gemm_lowp_splitk_elems(P.n, nb, P.n);
+            if (e1 > P.splitk_elems) P.splitk_elems = e1;
+            if (e2 > P.splitk_elems) P.splitk_elems = e2;
+        }
+    }
     P.off_splitk = lay.take((P.splitk_elems ? P.splitk_elems : 1) * d);
     P.off_lmpt = lay.take(ml * mc * d);
     P.off_lmpw = lay.take(lmp_work_doubles(P.n, P.maxl, P.maxc) * d);
@@ -257,13 +266,20 @@ int ub_apply(Ctx &c, int nb, const double *X, long long ldx, double *Y, long lon
              long long ldadd, const int32_t *active, int lowp = 0) {
     if (c.cfg.ub_mode == EDA_UB_DENSE && lowp == 2) {
         EDA_TRY(profiled(c, EDA_PROF_UB_GEMM,
-                         [&] { return gemm_bf16(c.stream, c.n, nb, c.n, c.ub16, c.n, X, ldx, Y, ldy, Add, ldadd); }));
+                         [&] {
+                             return gemm_bf16(c.stream, c.n, nb, c.n, c.ub16, c.n, X, ldx, Y, ldy, Add, ldadd, c.splitk,
+                                              c.splitk_elems);
+                         }));
     } else if (c.cfg.ub_mode == EDA_UB_DENSE && lowp == 1) {
         EDA_TRY(profiled(c, EDA_PROF_UB_GEMM,
-                         [&] { return gemm_f32in(c.stream, c.n, nb, c.n, c.ub32, c.n, X, ldx, Y, ldy, Add, ldadd); }));
+                         [&] {
+                             return gemm_f32in(c.stream, c.n, nb, c.n, c.ub32, c.n, X, ldx, Y, ldy, Add, ldadd, c.splitk,
+                                               c.splitk_elems);
+                         }));
     } else if (c.cfg.ub_mode == EDA_UB_DENSE) {
         EDA_TRY(profiled(c, EDA_PROF_UB_GEMM, [&] {
-            return gemm_f64(c.stream, false, c.n, nb, c.n, c.ub, c.n, X, ldx, Y, ldy, Add, ldadd, nullptr, nullptr, 0);
+            return gemm_f64(c.stream, false, c.n, nb, c.n, c.ub, c.n, X, ldx, Y, ldy, Add, ldadd, nullptr, c.splitk,
+                            c.splitk_elems);
         }));
     } else {
         HIP_TRY(launch_band_conv(c.stream, c.n, nb, c.band_lo, c.band_hi, c.ubrow, X, ldx, Y, ldy, Add, ldadd,

@@ -376,6 +376,10 @@ hipError_t gemm_f64(hipStream_t s, bool trans_a, int M, int N, int K, const doub
                     const double *B, long long ldb, double *C, long long ldc, const double *Add,
                     long long ldadd, const double *rowscale, double *part, size_t part_elems);
 size_t gemm_splitk_elems(int M, int N, int K);
+// C = sum_z part[z] (+ Add), the nsplit partial products (M x N each, in
+// order z = 0, 1, ...) of a split-K GEMM.
+hipError_t launch_splitk_reduce(hipStream_t s, int M, int N, int nsplit, const double *part, double *C,
+                                long long ldc, const double *Add, long long ldadd);
 
 // Spectral LMP on a block: Y = X + S diag(coef) S^T X (S: n x k column-major,
 // Sr: the same row-major, from launch_lmp_rowmajor; X, Y: n x nb); column tiles
@@ -429,11 +433,16 @@ hipError_t launch_lmp_fin(hipStream_t s, int n, int k, int nb, const double *S, 
                           const LmpSync *sync = nullptr);
 // BF16-operand, FP32-accumulate GEMM C = A B (+ Add): A in BF16 (M x K,
 // column-major), B, C, Add in FP64 (B rounded to BF16 as it is staged).
+// part (optional, part_elems doubles): FP64 partials of a K split, taken when
+// the output has few tiles and part holds gemm_lowp_splitk_elems(M, N, K).
 hipError_t gemm_bf16(hipStream_t s, int M, int N, int K, const unsigned short *A, long long lda, const double *B,
-                     long long ldb, double *C, long long ldc, const double *Add, long long ldadd);
+                     long long ldb, double *C, long long ldc, const double *Add, long long ldadd,
+                     double *part = nullptr, size_t part_elems = 0);
 // The same with FP32 operands (A in FP32, B rounded to FP32 when staged).
 hipError_t gemm_f32in(hipStream_t s, int M, int N, int K, const float *A, long long lda, const double *B,
-                      long long ldb, double *C, long long ldc, const double *Add, long long ldadd);
+                      long long ldb, double *C, long long ldc, const double *Add, long long ldadd,
+                      double *part = nullptr, size_t part_elems = 0);
+size_t gemm_lowp_splitk_elems(int M, int N, int K);
 hipError_t launch_to_f32(hipStream_t s, long long count, const double *x, float *y);
 // ---- learned sketch (MLP) ----
 struct MlpLayout {

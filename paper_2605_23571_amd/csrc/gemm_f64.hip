@@ -150,6 +150,15 @@ int split_count(int M, int N, int K) {
 
 }  // namespace
 
+hipError_t launch_splitk_reduce(hipStream_t s, int M, int N, int nsplit, const double *part, double *C,
+                                long long ldc, const double *Add, long long ldadd) {
+    const long long tot = (long long)M * N;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, N, nsplit, part, C,
+                       ldc, Add, ldadd, nullptr);
+    return hipGetLastError();
+}
+
 size_t gemm_splitk_elems(int M, int N, int K) {
     int ns = split_count(M, N, K);
     return ns > 1 ? (size_t)ns * M * N : 0;
