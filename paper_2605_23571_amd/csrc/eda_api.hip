@@ -828,7 +828,9 @@ int lmp_apply(Ctx &c, int which, int nb, const double *X, long long ldx, double 
 
 // One fused PCG iteration (banded U_B) of every running column: p = z + beta p
 // (p updated in place), (I + A) p, alpha, x, r, the convergence test.
-int fused_iteration(Ctx &c, int nm, const PcgArgs &a, double *p, double rtol, int it) {
+// rz_part: the row-block sums of r^T z that the LMP left (null: summed in the kernel).
+int fused_iteration(Ctx &c, int nm, const PcgArgs &a, double *p, double rtol, int it,
+                    const double *rz_part = nullptr) {
     TladArgs t = tlad_args(c, nm, c.pc_members, nullptr);
     t.obs = c.hv_obs;
     t.pcg.members = c.pc_members;
@@ -845,6 +847,13 @@ int fused_iteration(Ctx &c, int nm, const PcgArgs &a, double *p, double rtol, in
     t.pcg.rtol = rtol;
     t.pcg.it = it;
     t.pcg.first = it == 1 ? 1 : 0;
+    if (rz_part) {
+        int rows, nrb;
+        lmp_blocks(c.n, &rows, &nrb);
+        t.pcg.rz_part = rz_part;
+        t.pcg.rz_ld = (nm + 15) / 16 * 16;
+        t.pcg.rz_nrb = nrb;
+    }
     return run_tlad(c, t, TLAD_PCG, false);
 }
 
@@ -1067,7 +1076,7 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                 } else if (P == 1) {
                     // whole columns: the fused iteration (its update hidden under the
                     // TL/AD work), then the LMP of the new residual
-                    EDA_TRY(fused_iteration(c, nm, a, pbuf[cur], rtol, it));
+                    EDA_TRY(fused_iteration(c, nm, a, pbuf[cur], rtol, it, c.rz_part));
                     EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status, c.rz_part, true));
                 } else {
                     // ring pieces; with EDA_XCH_OBS they share the observed
@@ -1102,6 +1111,13 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                     t.pcg.iters = c.pc_iters;
                     t.pcg.it = it;
                     t.pcg.first = it == 1 ? 1 : 0;
+                    {  // r^T z from the LMP's row-block sums
+                        int rows_, nrb_;
+                        lmp_blocks(n, &rows_, &nrb_);
+                        t.pcg.rz_part = c.rz_part;
+                        t.pcg.rz_ld = (nm + 15) / 16 * 16;
+                        t.pcg.rz_nrb = nrb_;
+                    }
                     EDA_TRY(run_tlad(c, t, sh ? TLAD_SPLIT_SH : TLAD_SPLIT, false, &sc));
                     LmpFin f{};
                     f.q = c.pc_q;

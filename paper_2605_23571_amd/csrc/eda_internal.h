@@ -132,6 +132,11 @@ struct PcgCols {
     // pieces of a column read each other's halos), (I + A) p goes to q and the
     // pieces' partial sums of p^T (I + A) p to pq_part[c * pieces + piece]
     double *p_out, *q, *pq_part;
+    // r^T z per (row block, column), rz_part[b * rz_ld + c] for b < rz_nrb,
+    // left by the LMP launch that made z (summed in block order); null: the
+    // kernel sums r^T z over the column itself
+    const double *rz_part;
+    int rz_ld, rz_nrb;
 };
 // One task of a batched persistent launch: problem index and column (a PCG
 // member column, or a sketch column).

@@ -521,11 +521,22 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
             for (int j = tid; j < R; j += nthr) u[j] = x[state(j)];
         } else {
             // p = z + beta p with beta = rho'/rho, rho' = r^T z; first iteration p = z
-            const double *r = a.pcg.r + cn, *z = a.pcg.z + cn;
+            const double *z = a.pcg.z + cn;
             double *pp = a.pcg.p + cn;
             double rz = 0.0;
-            for (int i = tid; i < n; i += nthr) rz += r[i] * z[i];
-            rz = block_sum(rz, red, g.waves);
+            if (a.pcg.rz_part) {
+                // the LMP's row-block sums, in block order (every thread the same bits)
+                double v[LMP_RB_MAX];
+#pragma unroll
+                for (int b = 0; b < LMP_RB_MAX; b++)
+                    v[b] = b < a.pcg.rz_nrb ? a.pcg.rz_part[(long long)b * a.pcg.rz_ld + c] : 0.0;
+#pragma unroll
+                for (int b = 0; b < LMP_RB_MAX; b++) rz += v[b];
+            } else {
+                const double *r = a.pcg.r + cn;
+                for (int i = tid; i < n; i += nthr) rz += r[i] * z[i];
+                rz = block_sum(rz, red, g.waves);
+            }
             double beta = 0.0;
             if (!first) {
                 if (!(rz > 0.0) || !isfinite(rz)) {
