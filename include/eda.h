@@ -239,7 +239,12 @@ int eda_lmp_apply_noalloc(eda_ctx *ctx, int32_t which, int32_t nb, const double 
  * or nm * (maxit + 1) doubles, row c holding J_i - c_m = -1/2 x_i^T (b + r_i)
  * for i = 0..iters (the quadratic cost of the incremental problem minus its
  * constant), NaN after the last iteration.  Synchronises the stream.
- * Returns EDA_WARN_NOT_CONVERGED if any member did not converge. */
+ * Returns EDA_WARN_NOT_CONVERGED if any member did not converge.  With the
+ * banded U_B, the pieces of a split iteration wait for each other
+ * (eda_set_exchange): they assume that the launch has the device to itself,
+ * so a solve whose kernels overlap other work on the device (other streams
+ * or contexts) may see a wait give up (EDA_ERR_SYNC); such callers set
+ * EDA_XCH_OFF, whose pieces never wait. */
 int eda_pcg_solve(eda_ctx *ctx, const int32_t *h_members, int32_t nm, double rtol, int32_t maxit,
                   int32_t use_lmp, double *d_DZ, int64_t ldz, int32_t *h_iters, double *h_relres,
                   int32_t *h_status, double *h_cost_hist);
