@@ -831,21 +831,30 @@ __global__ __launch_bounds__(512) void k_tlad_split_hv(TladArgs a, TladGeom g) {
 
 // z = P r = r + S diag(coef) S^T r for one column (in-kernel LMP of the
 // persistent solve).  r is first staged in LDS (rs, n doubles).  t = coef .*
-// (S^T r): the k dot products are split over the waves; lane l keeps eight
-// partial sums, partial u mod 8 taking rows l + 64 u of each 512-row stride in
-// turn, then a fixed shuffle tree.  z = r + S t: rows over the threads, the
-// columns of S in order.  S lives in HBM or the last-level cache, so each step
-// is one memory round trip: the loads of up to four strides (phase one) or 32
-// columns (phase two) are issued together before the sums that use them, in
-// the same summation order as a stride-at-a-time loop.  r and z are the
+// (S^T r): the k dot products are split over the waves, two directions per
+// wave at a time; lane l keeps eight partial sums per direction, partial
+// u mod 8 taking rows l + 64 u of each 512-row stride in turn, then a fixed
+// shuffle tree.  z = r + S t: rows over the threads, two rows per thread at a
+// time, the columns of S in order.  S lives in HBM or the last-level cache,
+// so each step is one memory round trip: the loads of up to four strides of
+// both directions (phase one) or of 32 columns for both rows (phase two) are
+// issued together before the sums that use them, in the same summation order
+// as a stride-at-a-time loop over one direction (one row).  r and z are the
 // column's global vectors, tsh k doubles of LDS.
 template <int U>
-__device__ __forceinline__ void lmp_dot_strides(const double *sj, const double *rs, int i, double (&acc)[8]) {
-    double sv[8 * U];
+__device__ __forceinline__ void lmp_dot_strides2(const double *sj, const double *sj2, const double *rs, int i,
+                                                 double (&acc)[8], double (&acc2)[8]) {
+    double sv[8 * U], sv2[8 * U];
 #pragma unroll
     for (int u = 0; u < 8 * U; u++) sv[u] = sj[i + u * 64];
 #pragma unroll
-    for (int u = 0; u < 8 * U; u++) acc[u & 7] += sv[u] * rs[i + u * 64];
+    for (int u = 0; u < 8 * U; u++) sv2[u] = sj2[i + u * 64];
+#pragma unroll
+    for (int u = 0; u < 8 * U; u++) {
+        const double rv = rs[i + u * 64];
+        acc[u & 7] += sv[u] * rv;
+        acc2[u & 7] += sv2[u] * rv;
+    }
 }
 
 __device__ __forceinline__ void lmp_column(const PcgCols &pc, int n, const double *r, double *z, double *rs,
@@ -854,47 +863,75 @@ __device__ __forceinline__ void lmp_column(const PcgCols &pc, int n, const doubl
     const int k = pc.lmp_k;
     for (int i = tid; i < n; i += nthr) rs[i] = r[i];
     __syncthreads();
-    for (int j = wave; j < k; j += waves) {
-        const double *sj = pc.lmp_s + (long long)j * n;
-        double acc[8];
+    for (int j = wave; j < k; j += 2 * waves) {
+        // directions j and j2 (j2 past k: a repeat of j whose sum is dropped)
+        const int j2 = j + waves < k ? j + waves : j;
+        const double *sj = pc.lmp_s + (long long)j * n, *sj2 = pc.lmp_s + (long long)j2 * n;
+        double acc[8], acc2[8];
 #pragma unroll
-        for (int u = 0; u < 8; u++) acc[u] = 0.0;
+        for (int u = 0; u < 8; u++) acc[u] = acc2[u] = 0.0;
         int i = lane;
-        for (; i + 31 * 64 < n; i += 32 * 64) lmp_dot_strides<4>(sj, rs, i, acc);
+        for (; i + 31 * 64 < n; i += 32 * 64) lmp_dot_strides2<4>(sj, sj2, rs, i, acc, acc2);
         if (i + 15 * 64 < n) {
-            lmp_dot_strides<2>(sj, rs, i, acc);
+            lmp_dot_strides2<2>(sj, sj2, rs, i, acc, acc2);
             i += 16 * 64;
         }
         if (i + 7 * 64 < n) {
-            lmp_dot_strides<1>(sj, rs, i, acc);
+            lmp_dot_strides2<1>(sj, sj2, rs, i, acc, acc2);
             i += 8 * 64;
         }
-        for (; i < n; i += 64) acc[0] += sj[i] * rs[i];
+        for (; i < n; i += 64) {
+            acc[0] += sj[i] * rs[i];
+            acc2[0] += sj2[i] * rs[i];
+        }
         double sum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-        for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
-        if (lane == 0) tsh[j] = pc.lmp_c[j] * sum;
+        double sum2 = ((acc2[0] + acc2[1]) + (acc2[2] + acc2[3])) + ((acc2[4] + acc2[5]) + (acc2[6] + acc2[7]));
+        for (int off = 32; off > 0; off >>= 1) {
+            sum += __shfl_down(sum, off, 64);
+            sum2 += __shfl_down(sum2, off, 64);
+        }
+        if (lane == 0) {
+            tsh[j] = pc.lmp_c[j] * sum;
+            if (j2 != j) tsh[j2] = pc.lmp_c[j2] * sum2;
+        }
     }
     __syncthreads();
-    for (int i = tid; i < n; i += nthr) {
-        const double *si = pc.lmp_s + i;
-        double v = rs[i];
+    for (int i = tid; i < n; i += 2 * nthr) {
+        // rows i and i2 (i2 past n: a repeat of i whose result is dropped)
+        const int i2 = i + nthr < n ? i + nthr : i;
+        const double *si = pc.lmp_s + i, *si2 = pc.lmp_s + i2;
+        double v = rs[i], v2 = rs[i2];
         int j = 0;
         for (; j + 32 <= k; j += 32) {
-            double sv[32];
+            double sv[32], sv2[32];
 #pragma unroll
             for (int u = 0; u < 32; u++) sv[u] = si[(long long)(j + u) * n];
 #pragma unroll
-            for (int u = 0; u < 32; u++) v += sv[u] * tsh[j + u];
+            for (int u = 0; u < 32; u++) sv2[u] = si2[(long long)(j + u) * n];
+#pragma unroll
+            for (int u = 0; u < 32; u++) {
+                v += sv[u] * tsh[j + u];
+                v2 += sv2[u] * tsh[j + u];
+            }
         }
         for (; j + 8 <= k; j += 8) {
-            double sv[8];
+            double sv[8], sv2[8];
 #pragma unroll
             for (int u = 0; u < 8; u++) sv[u] = si[(long long)(j + u) * n];
 #pragma unroll
-            for (int u = 0; u < 8; u++) v += sv[u] * tsh[j + u];
+            for (int u = 0; u < 8; u++) sv2[u] = si2[(long long)(j + u) * n];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                v += sv[u] * tsh[j + u];
+                v2 += sv2[u] * tsh[j + u];
+            }
         }
-        for (; j < k; j++) v += si[(long long)j * n] * tsh[j];
+        for (; j < k; j++) {
+            v += si[(long long)j * n] * tsh[j];
+            v2 += si2[(long long)j * n] * tsh[j];
+        }
         z[i] = v;
+        if (i2 != i) z[i2] = v2;
     }
     __syncthreads();
 }
