@@ -431,11 +431,12 @@ __device__ __forceinline__ void store_obs_dev(double *o, const int *qi, const do
 // block, at device scope; every wave waits for its stores to complete, then
 // the piece raises its flag to this launch's value and waits (bounded) for
 // both neighbours' flags, after which their blocks can be read at device
-// scope.  (No cache line is written by two pieces, and a piece reads a
-// neighbour's block only after the flag, so no XCD's L2 holds a stale copy.)  (Device-scope release and acquire fences, which write
-// back and invalidate whole L2s, made the launch 10-25% slower.)  A wait that
-// gives up sets the error word and stops the member (its results are void);
-// the piece still raised its flag, so no neighbour waits on it.
+// scope.  No cache line is written by two pieces, and a piece reads a
+// neighbour's block only after the flag, so no XCD's L2 holds a stale copy.
+// (Device-scope release and acquire fences, which write back and invalidate
+// whole L2s, made the launch 10-25% slower.)  A wait that gives up sets the
+// error word and stops the member (its results are void); the piece still
+// raised its flag, so no neighbour waits on it.
 __device__ __forceinline__ void share_obs(const TladArgs &a, int c, int piece) {
     __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
