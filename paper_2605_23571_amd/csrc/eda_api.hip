@@ -998,12 +998,13 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
         InPcg scope(c);
         for (int it = 1; it <= maxit; it++) {
             if (split) {
-                // running columns as of the checkpoint 16 .. 23 iterations back (waited
+                // running columns as of the checkpoint 8 .. 15 iterations back (waited
                 // for if need be, so that the pieces, and the rounding, of every
-                // iteration do not depend on timing): a superset of the running ones
+                // iteration do not depend on timing; at least 8 iterations stay
+                // queued): a superset of the running ones
                 SplitCols sc{};
                 int active = nm;
-                const int j = it / check_every - 3;
+                const int j = it / check_every - 2;
                 const std::vector<int16_t> *known = nullptr;
                 if (j >= 0 && j < ck_issued) {
                     while (ck_done <= j) EDA_TRY(consume(true));
