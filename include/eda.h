@@ -46,8 +46,9 @@ extern "C" {
 #define EDA_ERR_NOT_SPD        -4  /* Cholesky of Phi^T A Phi failed even after the shift      */
 #define EDA_ERR_ORDER          -5  /* LMP requested before eda_sketch_evd built one            */
 #define EDA_ERR_UNSUPPORTED    -6  /* option not supported by this build (sizes, modes)        */
-#define EDA_ERR_SYNC           -7  /* a wait between the exchange form's wave pieces gave up,  */
-                                   /* or the device placed workgroups unlike that form expects  */
+#define EDA_ERR_SYNC           -7  /* a bounded wait between the pieces of a column (or the   */
+                                   /* LMP's tiles) gave up, or the device placed workgroups     */
+                                   /* unlike the exchange form expects (eda_set_exchange)       */
 #define EDA_WARN_NOT_CONVERGED  1  /* eda_pcg_solve: some member hit maxit or broke down      */
 
 /* ---- per-member PCG outcome (h_status of eda_pcg_solve) ---- */
@@ -175,7 +176,13 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
  * takes BF16 operands for the dense U_B products (relative error of order 1e-3).
  * Both are meant for sketch products only; with the banded U_B the U_B products
  * stay FP64.  With the banded U_B, when few columns are given the columns run
- * on pieces (eda_set_split); the results are the same bit for bit. */
+ * on pieces (eda_set_split); the results are the same bit for bit.  With
+ * EDA_XCH_OBS (eda_set_exchange, the default) those pieces share the observed
+ * increments and wait for each other, bounded: a wait that gives up (only
+ * when other work holds the device's compute units) leaves NaN in that
+ * piece's rows of the column's product (the call does not synchronise, so
+ * this is how the failure shows; eda_sketch_evd reports EDA_ERR_SYNC for the
+ * waits of its own products). */
 int eda_hessvec(eda_ctx *ctx, const int32_t *d_col_member, int32_t nb,
                 const double *d_X, int64_t ldx, double *d_Y, int64_t ldy, uint32_t flags);
 
@@ -199,7 +206,9 @@ int eda_hessvec(eda_ctx *ctx, const int32_t *d_col_member, int32_t nb,
  * The context keeps S_k, D_k and theta for eda_lmp_apply / eda_pcg_solve.
  * h_eig (k doubles, may be NULL): D_k, descending; h_theta (may be NULL).
  * 1 <= k <= ell <= max_ell, q >= 1.  Synchronises the stream.
- * Errors: EDA_ERR_NOT_SPD if the shifted Cholesky fails too. */
+ * Errors: EDA_ERR_NOT_SPD if the shifted Cholesky fails too; EDA_ERR_SYNC if
+ * a wait between the pieces of its products gave up (eda_hessvec), and then
+ * the context holds no LMP. */
 int eda_sketch_evd(eda_ctx *ctx, int32_t kind, const double *d_phi, int64_t ldphi,
                    int32_t ell, int32_t k, int32_t q, int32_t method, int32_t theta_rule,
                    uint32_t flags, double *h_eig, double *h_theta);
@@ -388,7 +397,8 @@ int eda_set_split(eda_ctx *ctx, int32_t pieces);
  * tangent linear and adjoint models over the assimilation window, cost model
  * of the Nystrom subsection).  mode:
  *  EDA_XCH_OBS (default): ring pieces (eda_set_split) that share the
- *    column's observed increments R^-1 H dx: each piece computes those of its
+ *    column's observed increments R^-1 H dx (also in the Hessian products of
+ *    eda_hessvec and the sketches): each piece computes those of its
  *    own states, then waits (bounded) for its two neighbours' before its AD
  *    run, so its rings carry ceil(n / P) + 12 N + 2 w states instead of
  *    ceil(n / P) + 24 N + 4 w (w: the U_B band half-width).  Used when every

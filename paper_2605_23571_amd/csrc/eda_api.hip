@@ -351,10 +351,21 @@ int hessvec(Ctx &c, const int32_t *cols, int nb, const double *X, long long ldx,
         a.add_identity = add ? 1 : 0;
         const int P = split_pieces(c, nb);
         if (P > 1) {
+            // pieces sharing the observed increments when the exchange mode
+            // allows it (every piece co-resident, one per compute unit)
+            const bool sh = c.xch_mode == EDA_XCH_OBS && c.xch_flags && (long long)nb * P <= c.num_cus &&
+                            (long long)nb * SPLIT_PMAX <= 8ll * XCH_GRID_MAX &&
+                            tlad_split_ring_sh(c.n, c.N, c.band_hi, P) > 0;
             a.pieces = P;
-            a.ring = tlad_split_ring(c.n, c.N, c.band_hi, P);
-            a.halo = tlad_split_halo(c.N, c.band_hi);
-            return run_tlad(c, a, TLAD_SPLIT_HV, fp32);
+            a.ring = sh ? tlad_split_ring_sh(c.n, c.N, c.band_hi, P) : tlad_split_ring(c.n, c.N, c.band_hi, P);
+            a.halo = sh ? tlad_split_halo_sh(c.N, c.band_hi) : tlad_split_halo(c.N, c.band_hi);
+            if (sh) {
+                a.pflags = c.xch_flags;
+                a.want = (++c.xch_epoch) << 16;
+                a.spin_max = c.xch_spin < 0 ? XCH_SPIN_DEFAULT : c.xch_spin;
+                a.err = c.xch_err;
+            }
+            return run_tlad(c, a, sh ? TLAD_SPLIT_HV_SH : TLAD_SPLIT_HV, fp32);
         }
         return run_tlad(c, a, TLAD_HV, fp32);
     }
@@ -703,8 +714,9 @@ int eda_hessvec(eda_ctx *h, const int32_t *d_col_member, int32_t nb, const doubl
     return hessvec(c, d_col_member, nb, d_X, ldx, d_Y, ldy, flags, nullptr);
 }
 
-int eda_sketch_evd(eda_ctx *h, int32_t kind, const double *d_phi, int64_t ldphi, int32_t ell, int32_t k, int32_t q,
-                   int32_t method, int32_t theta_rule, uint32_t flags, double *h_eig, double *h_theta) {
+static int sketch_evd_impl(eda_ctx *h, int32_t kind, const double *d_phi, int64_t ldphi, int32_t ell, int32_t k,
+                           int32_t q, int32_t method, int32_t theta_rule, uint32_t flags, double *h_eig,
+                           double *h_theta) {
     if (!h) return EDA_ERR_INVALID_ARG;
     Ctx &c = h->c;
     if (ell < 1 || ell > c.max_ell || k < 1 || k > ell || q < 1) return EDA_ERR_INVALID_ARG;
@@ -788,6 +800,24 @@ int eda_sketch_evd(eda_ctx *h, int32_t kind, const double *d_phi, int64_t ldphi,
     c.have_lmp = true;
     c.sr_ready = false;
     return EDA_OK;
+}
+
+// The split products of a sketch wait for each other when their pieces share
+// the observed increments; a wait that gave up (NaN in its products) makes
+// the call return EDA_ERR_SYNC, whatever the factorisations then did.
+int eda_sketch_evd(eda_ctx *h, int32_t kind, const double *d_phi, int64_t ldphi, int32_t ell, int32_t k, int32_t q,
+                   int32_t method, int32_t theta_rule, uint32_t flags, double *h_eig, double *h_theta) {
+    if (!h) return EDA_ERR_INVALID_ARG;
+    Ctx &c = h->c;
+    HIP_TRY(hipMemsetAsync(c.xch_err, 0, sizeof(int32_t), c.stream));
+    const int rc = sketch_evd_impl(h, kind, d_phi, ldphi, ell, k, q, method, theta_rule, flags, h_eig, h_theta);
+    int32_t werr = 0;
+    EDA_TRY(sync_read(c, &werr, c.xch_err, sizeof(int32_t)));
+    if (werr != 0) {
+        c.have_lmp = false;
+        return EDA_ERR_SYNC;
+    }
+    return rc;
 }
 
 }  // extern "C"

@@ -153,6 +153,7 @@ enum TladMode : int {
     TLAD_SPLIT = 4, // the Hessian part of a PCG iteration on pieces of each member column, see tlad_column
     TLAD_SPLIT_HV = 5, // TLAD_HV on pieces of each column (ring, halos and pieces as TLAD_SPLIT)
     TLAD_SPLIT_SH = 6, // TLAD_SPLIT with the pieces of a column sharing its observed increments
+    TLAD_SPLIT_HV_SH = 7, // TLAD_SPLIT_HV with the pieces sharing the observed increments
 };
 
 // A member column split into P pieces: piece i owns the states
@@ -286,9 +287,10 @@ struct TladArgs {
     int band_lo, band_hi;
     int add_identity;     // HV: Y = U_B lambda_0 + X
     int pieces, ring, halo;  // TLAD_SPLIT: pieces per column, ring length, halo
-    // TLAD_SPLIT_SH: flags per (column, piece) (SPLIT_PMAX per column), the
-    // value this launch raises them to (above every earlier launch's), polls
-    // of the wait before it gives up, and the error word it then sets
+    // TLAD_SPLIT_SH, TLAD_SPLIT_HV_SH: flags per (column, piece) (SPLIT_PMAX
+    // per column), the value this launch raises them to (above every earlier
+    // launch's), polls of the wait before it gives up, and the error word it
+    // then sets
     unsigned long long *pflags;
     unsigned long long want;
     long long spin_max;

@@ -415,18 +415,19 @@ __device__ __forceinline__ void store_dev(double *p, double v) {
 }
 
 // Observed increments of this lane's owned observed points, stored at device
-// scope (TLAD_SPLIT_SH: the other pieces of the column read them).
-template <int Q>
-__device__ __forceinline__ void store_obs_dev(double *o, const int *qi, const double (&dx)[Q], double inv_s2) {
+// scope (shared-observation pieces: the other pieces of the column read them).
+template <typename T, int Q>
+__device__ __forceinline__ void store_obs_dev(double *o, const int *qi, const T (&dx)[Q], double inv_s2) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int q = 0; q < Q; q++) {
         const int oi = qi[q * 64 + lane];
-        if (oi >= 0) store_dev(o + oi, dx[q] * inv_s2);
+        if (oi >= 0) store_dev(o + oi, (double)dx[q] * inv_s2);
     }
 }
 
-// TLAD_SPLIT_SH, between the TL and AD runs of piece `piece` of column c: the
+// Shared-observation pieces (TLAD_SPLIT_SH, TLAD_SPLIT_HV_SH), between the TL
+// and AD runs of piece `piece` of column c: the
 // piece has stored the observed increments of its owned states in its own
 // block, at device scope; every wave waits for its stores to complete, then
 // the piece raises its flag to this launch's value and waits (bounded) for
@@ -435,9 +436,11 @@ __device__ __forceinline__ void store_obs_dev(double *o, const int *qi, const do
 // neighbour's block only after the flag, so no XCD's L2 holds a stale copy.
 // (Device-scope release and acquire fences, which write back and invalidate
 // whole L2s, made the launch 10-25% slower.)  A wait that gives up sets the
-// error word and stops the member (its results are void); the piece still
-// raised its flag, so no neighbour waits on it.
-__device__ __forceinline__ void share_obs(const TladArgs &a, int c, int piece) {
+// error word, stops the member in PCG (its results are void) and makes the
+// function return false; the piece still raised its flag, so no neighbour
+// waits on it.
+__device__ __forceinline__ bool share_obs(const TladArgs &a, int c, int piece) {
+    __shared__ int s_ok;
     __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -445,12 +448,15 @@ __device__ __forceinline__ void share_obs(const TladArgs &a, int c, int piece) {
         __hip_atomic_store(fl + piece, a.want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int left = piece == 0 ? a.pieces - 1 : piece - 1;
         const int right = piece == a.pieces - 1 ? 0 : piece + 1;
-        if (!xch_wait(fl + left, fl + right, a.want, a.spin_max)) {
+        const bool ok = xch_wait(fl + left, fl + right, a.want, a.spin_max);
+        if (!ok) {
             __hip_atomic_store(a.err, 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            a.pcg.status[c] = EDA_MEMBER_BREAKDOWN;
+            if (a.pcg.status) a.pcg.status[c] = EDA_MEMBER_BREAKDOWN;
         }
+        s_ok = ok ? 1 : 0;
     }
     __syncthreads();
+    return s_ok != 0;
 }
 
 // One column of one problem, all modes (the workgroup's whole job in k_tlad,
@@ -466,8 +472,8 @@ __device__ __forceinline__ void share_obs(const TladArgs &a, int c, int piece) {
 template <typename T, int Q, int MODE, bool EARLY = true>
 __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g, const int c, const int it,
                                             const int first, unsigned char *smraw, const int piece = 0) {
-    constexpr bool SPLIT_HV = MODE == TLAD_SPLIT_HV;
-    constexpr bool SHARE = MODE == TLAD_SPLIT_SH;  // pieces share the observed increments
+    constexpr bool SPLIT_HV = MODE == TLAD_SPLIT_HV || MODE == TLAD_SPLIT_HV_SH;
+    constexpr bool SHARE = MODE == TLAD_SPLIT_SH || MODE == TLAD_SPLIT_HV_SH;  // pieces share the observed increments
     constexpr bool SPLIT = MODE == TLAD_SPLIT || SPLIT_HV || SHARE;  // ring of one piece
     constexpr bool FUSED = (MODE == TLAD_HV || MODE == TLAD_PCG || SPLIT);
     const int n = a.n, N = a.N, p = a.nt * a.nv;
@@ -496,7 +502,7 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
     double *red = taps + W;
     double *lamd = reinterpret_cast<double *>(ring);  // ring reused as a double array for lambda_0
     const int own_lo = wave * g.S, own_hi = min(R, own_lo + g.S);
-    const int member = (MODE == TLAD_PCG || MODE == TLAD_SPLIT || SHARE) ? a.pcg.members[c]
+    const int member = (MODE == TLAD_PCG || MODE == TLAD_SPLIT || MODE == TLAD_SPLIT_SH) ? a.pcg.members[c]
                                                                : (a.col_member ? a.col_member[c] : 0);
     // row s of the member's padded trajectory, from ring position 0: trajm + s ext_len
     const double *trajm = a.trajx + (long long)member * a.trajx_stride + a.pad_l + off;
@@ -596,7 +602,7 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
             for (int s = s0; s < s1; s++) {
                 // observed increment of time s
                 if (s > 0 && s % a.obs_dt == 0) {
-                    if constexpr (SHARE) store_obs_dev<Q>(obs + (long long)(s / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
+                    if constexpr (SHARE) store_obs_dev<T, Q>(obs + (long long)(s / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
                     else store_obs<T, Q>(obs + (long long)(s / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
                 }
                 tl_step<T, Q, EARLY>(K, xw, trajm + (long long)min(s + 1, N - 1) * a.ext_len + w0, s + 1 < N, dx);
@@ -609,13 +615,14 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
             }
         }
         if (N % a.obs_dt == 0) {
-            if constexpr (SHARE) store_obs_dev<Q>(obs + (long long)(N / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
+            if constexpr (SHARE) store_obs_dev<T, Q>(obs + (long long)(N / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
             else store_obs<T, Q>(obs + (long long)(N / a.obs_dt - 1) * a.nv, qi, dx, a.inv_s2);
         }
         __threadfence_block();  // observed increments visible to the whole workgroup
     }
+    bool shared_ok = true;
     if constexpr (SHARE) {
-        share_obs(a, c, piece);
+        shared_ok = share_obs(a, c, piece);
         // the AD ring: the TL ring moved 4 N states right
         off += 4 * N;
         core_lo -= 4 * N;
@@ -661,7 +668,7 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
                 for (int q = 0; q < Q; q++) {
                     const int oi = qi[q * 64 + lane];
                     if constexpr (SHARE) {
-                        if (oi >= 0) lam[q] += load_dev(f + oi);
+                        if (oi >= 0) lam[q] += (T)load_dev(f + oi);
                     } else {
                         if (oi >= 0) lam[q] += (T)f[oi];
                     }
@@ -711,7 +718,11 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
 #pragma unroll
         for (int q = 0; q < Q; q++) {
             const int j = wpos(base, q, R);
-            if ((ownm & (1u << q)) && j >= core_lo && j < core_hi) out[state(j)] = a.add_identity ? y[q] + u[j] : y[q];
+            if ((ownm & (1u << q)) && j >= core_lo && j < core_hi) {
+                // (a shared-observation wait that gave up voids the product: NaN)
+                const double v = a.add_identity ? y[q] + u[SHARE ? j + 4 * N : j] : y[q];
+                out[state(j)] = shared_ok ? v : __builtin_nan("");
+            }
         }
         return;
     }
@@ -828,6 +839,17 @@ __global__ __launch_bounds__(512) void k_tlad_split_hv(TladArgs a, TladGeom g) {
     const int piece = (int)(blockIdx.x / a.nb);
     if (a.active && a.active[c] != COL_RUNNING) return;
     tlad_column<T, Q, TLAD_SPLIT_HV>(a, g, c, 0, 0, smraw, piece);
+}
+
+// The same with the pieces of a column sharing its observed increments
+// (TLAD_SPLIT_HV_SH); every piece of an active column reaches share_obs.
+template <typename T, int Q>
+__global__ __launch_bounds__(512) void k_tlad_split_hv_sh(TladArgs a, TladGeom g) {
+    extern __shared__ __align__(16) unsigned char smraw[];
+    const int c = (int)(blockIdx.x % a.nb);
+    const int piece = (int)(blockIdx.x / a.nb);
+    if (a.active && a.active[c] != COL_RUNNING) return;
+    tlad_column<T, Q, TLAD_SPLIT_HV_SH>(a, g, c, 0, 0, smraw, piece);
 }
 
 // z = P r = r + S diag(coef) S^T r for one column (in-kernel LMP of the
@@ -1438,7 +1460,7 @@ hipError_t launch_x_q(hipStream_t s, const TladArgs &a, const XchArgs &x, const 
 
 template <typename T, int Q>
 size_t lds_bytes(const TladArgs &a, const TladGeom &g, int mode) {
-    const bool split = mode == TLAD_SPLIT || mode == TLAD_SPLIT_HV || mode == TLAD_SPLIT_SH;
+    const bool split = mode == TLAD_SPLIT || mode == TLAD_SPLIT_HV || mode == TLAD_SPLIT_SH || mode == TLAD_SPLIT_HV_SH;
     const size_t R = split ? (size_t)a.ring : (size_t)a.n;
     size_t b = sizeof(T) * 2 * R + (sizeof(int) + sizeof(double)) * (size_t)g.waves * 64 * Q;
     if (mode == TLAD_HV || mode == TLAD_PCG || split)
@@ -1474,6 +1496,9 @@ hipError_t launch_q(hipStream_t s, const TladArgs &a, const TladGeom &g, int mod
         }
         case TLAD_SPLIT_HV:
             hipLaunchKernelGGL((k_tlad_split_hv<T, Q>), dim3(a.nb * a.pieces), block, lds, s, a, g);
+            break;
+        case TLAD_SPLIT_HV_SH:
+            hipLaunchKernelGGL((k_tlad_split_hv_sh<T, Q>), dim3(a.nb * a.pieces), block, lds, s, a, g);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -1776,12 +1801,13 @@ hipError_t launch_tlad(hipStream_t s, const TladArgs &a, int mode, bool fp32, in
         if (a.pieces == 1 ? (a.ring != a.n || a.halo != 0) : a.ring != tlad_split_ring(a.n, a.N, a.band_hi, a.pieces))
             return hipErrorInvalidValue;
     }
-    if (mode == TLAD_SPLIT_SH) {
-        if (fp32 || a.pieces < 2 || a.ring != tlad_split_ring_sh(a.n, a.N, a.band_hi, a.pieces) || a.ring == 0 ||
+    if (mode == TLAD_SPLIT_SH || mode == TLAD_SPLIT_HV_SH) {
+        if ((fp32 && mode == TLAD_SPLIT_SH) || a.pieces < 2 ||
+            a.ring != tlad_split_ring_sh(a.n, a.N, a.band_hi, a.pieces) || a.ring == 0 ||
             a.halo != tlad_split_halo_sh(a.N, a.band_hi) || !a.pflags || !a.err || a.spin_max < 0)
             return hipErrorInvalidValue;
     }
-    const bool split = mode == TLAD_SPLIT || mode == TLAD_SPLIT_HV || mode == TLAD_SPLIT_SH;
+    const bool split = mode == TLAD_SPLIT || mode == TLAD_SPLIT_HV || mode == TLAD_SPLIT_SH || mode == TLAD_SPLIT_HV_SH;
     const int R = split ? a.ring : a.n;
     if (waves != 0 && !tlad_waves_ok(R, waves)) return hipErrorInvalidValue;
     // rings of pieces take 8 waves where they fit: two waves per SIMD hide

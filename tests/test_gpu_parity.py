@@ -705,10 +705,12 @@ def test_lmp_one_launch_wait_limit_reports_sync_error():
 
 @pytest.mark.parametrize("case", ["n1001", "n2049"])
 def test_split_hessvec_matches_whole_columns(case):
-    # Hessian products on P pieces per column (ring of the piece's states with
-    # halos of 12 N + 2 w): every owned output is the whole column's, bit for
-    # bit, in member mode and in sketch mode, with and without the identity,
-    # with FP64 and with FP32 TL/AD runs; and the oracle agrees.
+    # Hessian products on P pieces per column (independent rings of the
+    # piece's states with halos of 12 N + 2 w on each side, and pieces that
+    # share the observed increments with 12 N + 2 w in all): every owned output
+    # is the whole column's, bit for bit, in member mode and in sketch mode,
+    # with and without the identity, with FP64 and with FP32 TL/AD runs; and
+    # the oracle agrees.
     cfg, g, o = problem(case)
     n, L = cfg["n"], cfg["members"]
     rng = np.random.default_rng(7)
@@ -726,11 +728,14 @@ def test_split_hessvec_matches_whole_columns(case):
                 except eda.EdaError as e:
                     assert e.code == eda.EDA_ERR_UNSUPPORTED and P > 2
                     continue
-                Y = g.hessvec(cc, X, add_identity=add, mixed=mixed)
-                assert torch.equal(Y, ref), (case, P, add, mixed)
+                for xch in (eda.EDA_XCH_OFF, eda.EDA_XCH_OBS):
+                    eda.eda_set_exchange(g.ctx, xch)
+                    Y = g.hessvec(cc, X, add_identity=add, mixed=mixed)
+                    assert torch.equal(Y, ref), (case, P, xch, add, mixed)
                 done += 1
             assert done >= 3
     eda.eda_set_split(g.ctx, 0)
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OBS)
     Yc = to_np_cols(g.hessvec(cols, X, add_identity=True), n)
     Xc = X.cpu().numpy().T
     assert colrel(Yc, o.hess(Xc, cols)) < 1e-12
@@ -751,6 +756,37 @@ def test_split_hessvec_matches_whole_columns(case):
     eda.eda_set_split(g.ctx, 0)
     Xs = Xw[:, :n].cpu().numpy().T
     assert colrel(to_np_cols(ref.contiguous(), n), o.hess(Xs, sel.cpu().numpy())) < 1e-12
+
+
+def test_shared_pieces_wait_limit_in_products_and_sketch():
+    # With a wait limit of 0 (set from the host) every wait of the pieces that
+    # share the observed increments gives up at once: a Hessian product on
+    # pieces then leaves NaN in the pieces' rows, and a sketch whose products
+    # ran on such pieces reports EDA_ERR_SYNC and keeps no LMP.  Every kernel
+    # still runs to its end, and with the default limit the same context gives
+    # the whole columns' bits again.
+    cfg, g, o = problem("n2049")
+    n, L = cfg["n"], cfg["members"]
+    X = torch.from_numpy(np.random.default_rng(3).standard_normal((L + 1, n))).cuda()
+    cols = np.arange(L + 1)
+    eda.eda_set_split(g.ctx, 1)
+    ref = g.hessvec(cols, X, add_identity=True).clone()
+    eda.eda_set_split(g.ctx, 2)
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OBS, 0)
+    Y = g.hessvec(cols, X, add_identity=True)
+    assert torch.isnan(Y).all(), "every piece's wait gave up: every row is NaN"
+    eda.eda_set_split(g.ctx, 0)
+    with pytest.raises(eda.EdaError) as ei:
+        g.sketch_evd("rhs_diff")
+    assert ei.value.code == eda.EDA_ERR_SYNC
+    with pytest.raises(eda.EdaError) as ei:
+        g.pcg(np.arange(L + 1), rtol=1e-8, maxit=10)
+    assert ei.value.code == eda.EDA_ERR_ORDER  # no LMP was kept
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OBS, -1)
+    eda.eda_set_split(g.ctx, 2)
+    assert torch.equal(g.hessvec(cols, X, add_identity=True), ref)
+    eda.eda_set_split(g.ctx, 0)
+    g.sketch_evd("rhs_diff")
 
 
 def test_split_errors():
