@@ -332,6 +332,28 @@ int split_pieces(const Ctx &c, int columns) {
     return P;
 }
 
+// Ring pieces of a split launch: P pieces per column of the `columns`
+// columns a launch of `grid` workgroups covers (grid = columns x P).  With
+// EDA_XCH_OBS the pieces share the observed increments (shorter rings, one
+// bounded wait) when every piece is co-resident (one per compute unit), the
+// flags cover the columns and every piece is long enough; otherwise they are
+// independent.  Returns whether they share.
+bool set_pieces(Ctx &c, TladArgs &a, int columns, int grid, int P) {
+    const bool sh = c.xch_mode == EDA_XCH_OBS && c.xch_flags && grid <= c.num_cus &&
+                    (long long)columns * SPLIT_PMAX <= 8ll * XCH_GRID_MAX &&
+                    tlad_split_ring_sh(c.n, c.N, c.band_hi, P) > 0;
+    a.pieces = P;
+    a.ring = sh ? tlad_split_ring_sh(c.n, c.N, c.band_hi, P) : tlad_split_ring(c.n, c.N, c.band_hi, P);
+    a.halo = sh ? tlad_split_halo_sh(c.N, c.band_hi) : tlad_split_halo(c.N, c.band_hi);
+    if (sh) {
+        a.pflags = c.xch_flags;
+        a.want = (++c.xch_epoch) << 16;
+        a.spin_max = c.xch_spin < 0 ? XCH_SPIN_DEFAULT : c.xch_spin;
+        a.err = c.xch_err;
+    }
+    return sh;
+}
+
 // Batched Hessian product.  Banded U_B: one fused launch (U_B, TL, AD, U_B,
 // identity) per call, on pieces of each column when fewer columns than CUs
 // run; dense U_B: FP64 MFMA GEMM, TL/AD, GEMM.
@@ -351,20 +373,7 @@ int hessvec(Ctx &c, const int32_t *cols, int nb, const double *X, long long ldx,
         a.add_identity = add ? 1 : 0;
         const int P = split_pieces(c, nb);
         if (P > 1) {
-            // pieces sharing the observed increments when the exchange mode
-            // allows it (every piece co-resident, one per compute unit)
-            const bool sh = c.xch_mode == EDA_XCH_OBS && c.xch_flags && (long long)nb * P <= c.num_cus &&
-                            (long long)nb * SPLIT_PMAX <= 8ll * XCH_GRID_MAX &&
-                            tlad_split_ring_sh(c.n, c.N, c.band_hi, P) > 0;
-            a.pieces = P;
-            a.ring = sh ? tlad_split_ring_sh(c.n, c.N, c.band_hi, P) : tlad_split_ring(c.n, c.N, c.band_hi, P);
-            a.halo = sh ? tlad_split_halo_sh(c.N, c.band_hi) : tlad_split_halo(c.N, c.band_hi);
-            if (sh) {
-                a.pflags = c.xch_flags;
-                a.want = (++c.xch_epoch) << 16;
-                a.spin_max = c.xch_spin < 0 ? XCH_SPIN_DEFAULT : c.xch_spin;
-                a.err = c.xch_err;
-            }
+            const bool sh = set_pieces(c, a, nb, nb * P, P);
             return run_tlad(c, a, sh ? TLAD_SPLIT_HV_SH : TLAD_SPLIT_HV, fp32);
         }
         return run_tlad(c, a, TLAD_HV, fp32);
@@ -1110,24 +1119,10 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                     EDA_TRY(fused_iteration(c, nm, a, pbuf[cur], rtol, it, c.rz_part));
                     EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status, c.rz_part, true));
                 } else {
-                    // ring pieces; with EDA_XCH_OBS they share the observed
-                    // increments (shorter rings, one bounded wait) when every
-                    // piece of the launch is co-resident (one per compute unit)
-                    const int grid = (sc.count > 0 ? sc.count : nm) * P;
-                    const bool sh = c.xch_mode == EDA_XCH_OBS && c.xch_flags && grid <= c.num_cus &&
-                                    (long long)nm * SPLIT_PMAX <= 8ll * XCH_GRID_MAX &&
-                                    tlad_split_ring_sh(n, c.N, c.band_hi, P) > 0;
+                    // ring pieces (the flags are indexed by the solve's column)
                     TladArgs t = tlad_args(c, nm, c.pc_members, nullptr);
                     t.obs = c.hv_obs;
-                    t.pieces = P;
-                    t.ring = sh ? tlad_split_ring_sh(n, c.N, c.band_hi, P) : tlad_split_ring(n, c.N, c.band_hi, P);
-                    t.halo = sh ? tlad_split_halo_sh(c.N, c.band_hi) : tlad_split_halo(c.N, c.band_hi);
-                    if (sh) {
-                        t.pflags = c.xch_flags;
-                        t.want = (++c.xch_epoch) << 16;
-                        t.spin_max = c.xch_spin < 0 ? XCH_SPIN_DEFAULT : c.xch_spin;
-                        t.err = c.xch_err;
-                    }
+                    const bool sh = set_pieces(c, t, nm, (sc.count > 0 ? sc.count : nm) * P, P);
                     t.pcg.members = c.pc_members;
                     t.pcg.b = c.b;
                     t.pcg.x = c.pc_x;
