@@ -378,18 +378,22 @@ int eda_set_geometry(eda_ctx *ctx, int32_t waves, int32_t tb);
 /* Pieces per column in the iterations of eda_pcg_solve with the banded U_B and
  * the LMP, and in eda_hessvec calls with the banded U_B.  The Hessian part
  * of such an iteration, or such a product, runs on P pieces of every running
- * column, one workgroup each: a piece integrates its share of
- * the n states plus a halo of 12 N + 2 w states on each side (w the half-width
- * of the banded U_B), the reach of the TL/AD runs over the window and of U_B
- * on both ends, so its own outputs are exact; the pieces' partial sums of
- * p^T (I + A) p are added in piece order.  pieces = 0 (the default): P is the
- * largest of 1, 2, 3, 4, 8 with P x (members still running at the last
- * convergence check, or columns of the product) <= the device's compute units;
- * 1 to 8: that P in every iteration and product.  Solutions agree with P = 1 to
- * rounding; Hessian products are bit-identical.  Errors:
- * EDA_ERR_UNSUPPORTED if the context is not banded, or P > 1 pieces do not fit
- * n (ring of ceil(n / P) + 2 halo states longer than n, or a window wider than
- * the kernel supports); EDA_ERR_INVALID_ARG for other values. */
+ * column, one workgroup each: a piece integrates its share of the n states
+ * plus halos covering the reach of the TL/AD runs over the window and of U_B
+ * (w its half-width), so its own outputs are exact: 12 N + 2 w states on each
+ * side for independent pieces, 12 N + 2 w in all for pieces that share the
+ * observed increments (eda_set_exchange); the pieces' partial sums of
+ * p^T (I + A) p are added in piece order.  pieces = 0 (the default): of 1, 2,
+ * 3, 4 and 8 with P x (members still running at a recent convergence check,
+ * or columns of the product) <= the device's compute units, the P whose ring
+ * is shortest; 1 to 8: that P in every iteration and product.  Solutions
+ * agree with P = 1 to rounding; Hessian products are bit-identical.  Errors:
+ * EDA_ERR_UNSUPPORTED if the context is not banded, or P > 1 pieces fit
+ * neither form (rings longer than n, pieces shorter than 8 N + w for the
+ * shared form, or windows wider than the kernel supports); a forced P that
+ * only the shared form fits makes a call that cannot share (EDA_XCH_OFF, or
+ * more pieces than compute units) return EDA_ERR_UNSUPPORTED;
+ * EDA_ERR_INVALID_ARG for other values. */
 int eda_set_split(eda_ctx *ctx, int32_t pieces);
 
 /* How the pieces of a member column exchange data in the split iterations of

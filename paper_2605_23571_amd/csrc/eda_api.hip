@@ -321,27 +321,43 @@ int run_tlad(Ctx &c, const TladArgs &a, int mode, bool fp32, const SplitCols *sc
                     [&] { return launch_tlad(c.stream, a, mode, fp32, c.geo_waves, c.geo_tb, sc); });
 }
 
+// Whether a launch of `grid` workgroups with P pieces per column can use
+// pieces that share the observed increments: EDA_XCH_OBS, flags for every
+// column of the context, every piece co-resident (one per compute unit), and
+// pieces long enough for their rings (tlad_split_ring_sh).
+bool can_share(const Ctx &c, long long grid, int P) {
+    return c.xch_mode == EDA_XCH_OBS && c.xch_flags && (long long)c.max_cols * SPLIT_PMAX <= 8ll * XCH_GRID_MAX &&
+           grid <= c.num_cus && tlad_split_ring_sh(c.n, c.N, c.band_hi, P) > 0;
+}
+
 // Pieces per column of a split launch over `columns` columns: the forced
-// count, else the largest of 1, 2, 3, 4, 8 with pieces x columns <= CUs whose
-// ring fits n (5 to 7 pieces were measured no faster than 4).
+// count, else, of 1, 2, 3, 4 and 8 pieces with pieces x columns <= CUs, the
+// one whose ring is shortest (shared where can_share, else independent; the
+// fewer pieces on a tie).  5 to 7 pieces were measured no faster than 4.
 int split_pieces(const Ctx &c, int columns) {
     if (c.split_force != 0) return c.split_force;
-    int P = 1;
-    for (int cand : {2, 3, 4, 8})
-        if ((long long)cand * columns <= c.num_cus && tlad_split_ring(c.n, c.N, c.band_hi, cand) > 0) P = cand;
+    int P = 1, best = c.n;
+    for (int cand : {2, 3, 4, 8}) {
+        const long long grid = (long long)cand * columns;
+        if (grid > c.num_cus) continue;
+        const int R = can_share(c, grid, cand) ? tlad_split_ring_sh(c.n, c.N, c.band_hi, cand)
+                                               : tlad_split_ring(c.n, c.N, c.band_hi, cand);
+        if (R > 0 && R < best) {
+            best = R;
+            P = cand;
+        }
+    }
     return P;
 }
 
-// Ring pieces of a split launch: P pieces per column of the `columns`
-// columns a launch of `grid` workgroups covers (grid = columns x P).  With
-// EDA_XCH_OBS the pieces share the observed increments (shorter rings, one
-// bounded wait) when every piece is co-resident (one per compute unit), the
-// flags cover the columns and every piece is long enough; otherwise they are
-// independent.  Returns whether they share.
-bool set_pieces(Ctx &c, TladArgs &a, int columns, int grid, int P) {
-    const bool sh = c.xch_mode == EDA_XCH_OBS && c.xch_flags && grid <= c.num_cus &&
-                    (long long)columns * SPLIT_PMAX <= 8ll * XCH_GRID_MAX &&
-                    tlad_split_ring_sh(c.n, c.N, c.band_hi, P) > 0;
+// Ring pieces of a split launch of `grid` workgroups, P pieces per column:
+// pieces that share the observed increments (shorter rings, one bounded wait)
+// when can_share, else independent ones.  Returns 1 (shared), 0
+// (independent) or -1 when neither ring fits (a forced P that only the
+// shared form fits, in a launch that cannot share).
+int set_pieces(Ctx &c, TladArgs &a, long long grid, int P) {
+    const bool sh = can_share(c, grid, P);
+    if (!sh && tlad_split_ring(c.n, c.N, c.band_hi, P) == 0) return -1;
     a.pieces = P;
     a.ring = sh ? tlad_split_ring_sh(c.n, c.N, c.band_hi, P) : tlad_split_ring(c.n, c.N, c.band_hi, P);
     a.halo = sh ? tlad_split_halo_sh(c.N, c.band_hi) : tlad_split_halo(c.N, c.band_hi);
@@ -351,7 +367,7 @@ bool set_pieces(Ctx &c, TladArgs &a, int columns, int grid, int P) {
         a.spin_max = c.xch_spin < 0 ? XCH_SPIN_DEFAULT : c.xch_spin;
         a.err = c.xch_err;
     }
-    return sh;
+    return sh ? 1 : 0;
 }
 
 // Batched Hessian product.  Banded U_B: one fused launch (U_B, TL, AD, U_B,
@@ -373,7 +389,8 @@ int hessvec(Ctx &c, const int32_t *cols, int nb, const double *X, long long ldx,
         a.add_identity = add ? 1 : 0;
         const int P = split_pieces(c, nb);
         if (P > 1) {
-            const bool sh = set_pieces(c, a, nb, nb * P, P);
+            const int sh = set_pieces(c, a, (long long)nb * P, P);
+            if (sh < 0) return EDA_ERR_UNSUPPORTED;
             return run_tlad(c, a, sh ? TLAD_SPLIT_HV_SH : TLAD_SPLIT_HV, fp32);
         }
         return run_tlad(c, a, TLAD_HV, fp32);
@@ -1122,7 +1139,8 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                     // ring pieces (the flags are indexed by the solve's column)
                     TladArgs t = tlad_args(c, nm, c.pc_members, nullptr);
                     t.obs = c.hv_obs;
-                    const bool sh = set_pieces(c, t, nm, (sc.count > 0 ? sc.count : nm) * P, P);
+                    const int sh = set_pieces(c, t, (long long)(sc.count > 0 ? sc.count : nm) * P, P);
+                    if (sh < 0) return EDA_ERR_UNSUPPORTED;
                     t.pcg.members = c.pc_members;
                     t.pcg.b = c.b;
                     t.pcg.x = c.pc_x;
@@ -1319,7 +1337,9 @@ int eda_set_split(eda_ctx *h, int32_t pieces) {
     Ctx &c = h->c;
     if (pieces < 0 || pieces > SPLIT_PMAX) return EDA_ERR_INVALID_ARG;
     if (c.cfg.ub_mode != EDA_UB_BANDED) return EDA_ERR_UNSUPPORTED;
-    if (pieces > 1 && tlad_split_ring(c.n, c.N, c.band_hi, pieces) == 0) return EDA_ERR_UNSUPPORTED;
+    if (pieces > 1 && tlad_split_ring(c.n, c.N, c.band_hi, pieces) == 0 &&
+        !(c.xch_flags && tlad_split_ring_sh(c.n, c.N, c.band_hi, pieces) > 0))
+        return EDA_ERR_UNSUPPORTED;
     c.split_force = pieces;
     return EDA_OK;
 }

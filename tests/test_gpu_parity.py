@@ -758,6 +758,53 @@ def test_split_hessvec_matches_whole_columns(case):
     assert colrel(to_np_cols(ref.contiguous(), n), o.hess(Xs, sel.cpu().numpy())) < 1e-12
 
 
+def test_pieces_that_only_the_shared_form_fits():
+    # n = 2048, N = 40: independent ring pieces need ceil(n / P) + 24 N + 4 w
+    # states, more than n for every P, so before the shared form no column of
+    # this shape was split; shared pieces need ceil(n / P) + 12 N + 2 w (1606
+    # for P = 2).  Forced P = 2 and the automatic choice solve like whole
+    # columns (to rounding; products bit for bit); a forced P that only the
+    # shared form fits is refused at the call when the exchange mode is OFF.
+    cfg = W.config("C3", n=2048, nsteps=40, members=5, ell=4, k=4, spinup=200)
+    g = eda.Problem(cfg, W.problem_normals(cfg))
+    n, L = cfg["n"], cfg["members"]
+    members = np.arange(L + 1)
+    g.sketch_evd("rhs_diff")
+    X = torch.from_numpy(np.random.default_rng(5).standard_normal((L + 1, n))).cuda()
+    eda.eda_set_split(g.ctx, 1)
+    ref = g.pcg(members, rtol=0.0, maxit=6)["dz"].cpu().numpy()
+    hv = g.hessvec(members, X, add_identity=True).clone()
+    eda.eda_set_split(g.ctx, 2)
+    dz = g.pcg(members, rtol=0.0, maxit=6)["dz"].cpu().numpy()
+    e = colrel(dz, ref)
+    assert torch.equal(g.hessvec(members, X, add_identity=True), hv)
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OFF)
+    with pytest.raises(eda.EdaError) as ei:
+        g.pcg(members, rtol=0.0, maxit=2)
+    assert ei.value.code == eda.EDA_ERR_UNSUPPORTED
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OBS)
+    eda.eda_set_split(g.ctx, 0)  # automatic: 4 shared pieces (8 would be shorter than 8 N + w)
+    auto = g.pcg(members, rtol=1e-9, maxit=4000)
+    eda.eda_set_split(g.ctx, 1)
+    whole = g.pcg(members, rtol=1e-9, maxit=4000)
+    eda.eda_set_split(g.ctx, 0)
+    ea = colrel(auto["dz"].cpu().numpy(), whole["dz"].cpu().numpy())
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OBS, 0)
+    with pytest.raises(eda.EdaError) as ei:  # the automatic choice ran shared pieces
+        g.pcg(members, rtol=0.0, maxit=2)
+    assert ei.value.code == eda.EDA_ERR_SYNC
+    eda.eda_set_exchange(g.ctx, eda.EDA_XCH_OBS, -1)
+    print(f"[only-shared] n=2048 N=40: 6 iterations P=2 vs whole {e:.1e}; rtol 1e-9 automatic vs whole {ea:.1e} "
+          f"(iterations {auto['iters'].tolist()} / {whole['iters'].tolist()})", flush=True)
+    # 6 iterations: the pieces' partial sums of p^T (I + A) p round otherwise
+    # (5e-13 measured); two solves to rtol 1e-9 of this stiffer shape differ
+    # by the conditioning times their residuals
+    assert e < 1e-11 and ea < 1e-6
+    assert np.all(auto["status"] == eda.EDA_MEMBER_CONVERGED)
+    assert np.all(whole["status"] == eda.EDA_MEMBER_CONVERGED)
+    g.close()
+
+
 def test_shared_pieces_wait_limit_in_products_and_sketch():
     # With a wait limit of 0 (set from the host) every wait of the pieces that
     # share the observed increments gives up at once: a Hessian product on
