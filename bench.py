@@ -164,11 +164,20 @@ def run_form(cfg, z, ub_mode, steps, warmup, hv_reps, mixed=False, keep=False, q
         eda.eda_profile(g.ctx, 1)
         for _ in range(hv_reps):
             eda.eda_hessvec(g.ctx, n, cols, X, Y, eda.EDA_HV_ADD_IDENTITY)
-        timed, launches, ms = eda.eda_profile_read(g.ctx)
+        g_timed, _, g_ms = eda.eda_profile_read(g.ctx)
         eda.eda_profile(g.ctx, 0)
-        eda.eda_profile_select(g.ctx, eda.EDA_PROF_TLAD)
         flops = 2.0 * n * n * (L + 1)  # one n x n by n x (L + 1) product
-        gemm = {"avg_launch_ms": ms / max(1, timed), "flops_per_launch": flops, "launches": timed}
+        gemm = {"avg_launch_ms": g_ms / max(1, g_timed), "flops_per_launch": flops, "launches": g_timed}
+        # the TL/AD core (a3 + a4) alone: its launches inside the same products
+        eda.eda_profile_select(g.ctx, eda.EDA_PROF_TLAD_ALL)
+        for name, (cc, xx, yy) in {"member_mode": (cols, X, Y), "sketch_mode": (zero, Xs, Ys)}.items():
+            eda.eda_profile(g.ctx, 1)
+            for _ in range(hv_reps):
+                eda.eda_hessvec(g.ctx, n, cc, xx, yy, eda.EDA_HV_ADD_IDENTITY)
+            t_n, _, t_ms = eda.eda_profile_read(g.ctx)
+            eda.eda_profile(g.ctx, 0)
+            hv[name + "_tlad_core"] = xx.shape[0] / (t_ms / max(1, t_n) / 1e3)
+        eda.eda_profile_select(g.ctx, eda.EDA_PROF_TLAD)
     it = np.concatenate([o["iters"] for o in outs])
     res = dict(solves_per_s=(L + 1) * steps / dt, ms_per_step=1e3 * dt / steps, setup_s=setup_s, converged=conv,
                iters_median=float(np.median(it)), iters_max=int(it.max()), iters_min=int(it.min()),

@@ -307,10 +307,13 @@ int eda_profile_read(eda_ctx *ctx, int64_t *timed, int64_t *launches, double *ti
 /* Which launches eda_profile times: EDA_PROF_TLAD (default) the kernels
  * described above; EDA_PROF_UB_GEMM every U_B GEMM of the dense form (the
  * first-level preconditioning product, FP64 MFMA, or FP32 / BF16 operands in
- * reduced-precision sketch products), in any call.  Takes effect at the next
- * eda_profile.  Errors: EDA_ERR_INVALID_ARG for other kinds. */
+ * reduced-precision sketch products), in any call; EDA_PROF_TLAD_ALL every
+ * TL/AD launch in any call (with the dense U_B, the TL/AD core of a Hessian
+ * product without its U_B GEMMs).  Takes effect at the next eda_profile.
+ * Errors: EDA_ERR_INVALID_ARG for other kinds. */
 #define EDA_PROF_TLAD     0
 #define EDA_PROF_UB_GEMM  1
+#define EDA_PROF_TLAD_ALL 2
 int eda_profile_select(eda_ctx *ctx, int32_t kind);
 
 /* ---- learned sketch ----

@@ -232,12 +232,14 @@ T *at(char *ws, size_t off) {
 }
 
 // Enqueues launch() with HIP events around it when profiling samples this
-// launch (kind EDA_PROF_TLAD: inside eda_pcg_solve only).
+// launch (kind EDA_PROF_TLAD: inside eda_pcg_solve only, unless
+// EDA_PROF_TLAD_ALL is selected).
 template <typename F>
 int profiled(Ctx &c, int kind, F launch) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool rec = c.prof > 0 && c.prof_kind == kind && (kind != EDA_PROF_TLAD || c.in_pcg) &&
-                     c.prof_seen++ % c.prof == 0;
+    const bool match = c.prof_kind == kind ? (kind != EDA_PROF_TLAD || c.in_pcg)
+                                           : (c.prof_kind == EDA_PROF_TLAD_ALL && kind == EDA_PROF_TLAD);
+    const bool rec = c.prof > 0 && match && c.prof_seen++ % c.prof == 0;
     if (rec) {
         if (c.ev_used + 2 > c.ev.size()) {
             for (int i = 0; i < 64; i++) {
@@ -1287,7 +1289,8 @@ int eda_profile(eda_ctx *h, int32_t every) {
 }
 
 int eda_profile_select(eda_ctx *h, int32_t kind) {
-    if (!h || (kind != EDA_PROF_TLAD && kind != EDA_PROF_UB_GEMM)) return EDA_ERR_INVALID_ARG;
+    if (!h || (kind != EDA_PROF_TLAD && kind != EDA_PROF_UB_GEMM && kind != EDA_PROF_TLAD_ALL))
+        return EDA_ERR_INVALID_ARG;
     h->c.prof_kind = kind;
     return EDA_OK;
 }

@@ -38,7 +38,7 @@ EDA_THETA_MID, EDA_THETA_LAMK, EDA_THETA_ONE = 0, 1, 2
 EDA_LMP_P, EDA_LMP_U = 0, 1
 EDA_XCH_OFF, EDA_XCH_ON, EDA_XCH_OBS = 0, 1, 2
 EDA_LMP_FORM_TWO, EDA_LMP_FORM_ONE = 0, 1
-EDA_PROF_TLAD, EDA_PROF_UB_GEMM = 0, 1
+EDA_PROF_TLAD, EDA_PROF_UB_GEMM, EDA_PROF_TLAD_ALL = 0, 1, 2
 EDA_LMP_NOALLOC_SCRATCH_BYTES = 4194304
 FIELDS = dict(truth=0, xb=1, traj=2, y=3, d=4, b=5, costc=6, ubrow=7, S=8, eig=9)
 EDA_FIELD_SKETCH_INFO = 10
