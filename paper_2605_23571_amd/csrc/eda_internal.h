@@ -161,10 +161,11 @@ enum TladMode : int {
 // around them, H = 12 N + 2 band_hi (the TL/AD dependency cone over the window
 // plus U_B on both sides), so its owned outputs are exact.
 constexpr int SPLIT_PMAX = 8;
-// Columns of a split launch: workgroup b works on piece b / count of column
-// col[b % count], so the running columns' workgroups are contiguous and the
-// XCDs (dealt workgroups in turn) get equal shares.  count = 0: every column
-// of the launch (col[i] = i).
+// Columns of a split launch: the running columns only (their workgroups are
+// contiguous), in groups of eight whose pieces run eight workgroups apart, so
+// a column's pieces share one XCD and the XCDs (dealt workgroups in turn) get
+// equal shares (split_slot in l96_tlad.hip).  count = 0: every column of the
+// launch (col[i] = i).
 constexpr int SPLIT_LIST_MAX = 256;
 struct SplitCols {
     int32_t count;

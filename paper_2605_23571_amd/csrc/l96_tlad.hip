@@ -805,14 +805,34 @@ __global__ __launch_bounds__(512) void k_tlad(TladArgs a, TladGeom g) {
     tlad_column<T, Q, MODE>(a, g, c, a.pcg.it, a.pcg.first, smraw);
 }
 
-// Split iterations: workgroup b takes piece b / m of column col[b % m]
-// (m = sc.count, or every column), pieces in piece-major order.
+// Workgroup b of a split launch over m columns of P pieces each: column
+// index ci (into the launch's column list) and piece.  Columns go in groups of
+// eight with their P pieces eight workgroups apart, so that a column's pieces
+// run on one XCD (the XCDs are dealt workgroups in turn) and read the
+// trajectory and vector values of their shared halos through one L2; the last
+// m mod 8 columns take their pieces in turn.  A bijection onto m x P.
+__device__ __forceinline__ void split_slot(int b, int m, int P, int &ci, int &piece) {
+    const int full = m & ~7;
+    if (b < full * P) {
+        const int grp = b >> 3;
+        ci = (grp / P) * 8 + (b & 7);
+        piece = grp % P;
+    } else {
+        const int r = m - full, e = b - full * P;
+        ci = full + e % r;
+        piece = e / r;
+    }
+}
+
+// Split iterations: the workgroups take the pieces of the listed columns (m =
+// sc.count, or every column) as split_slot deals them.
 template <int Q>
 __global__ __launch_bounds__(512) void k_tlad_split(TladArgs a, TladGeom g, SplitCols sc) {
     extern __shared__ __align__(16) unsigned char smraw[];
     const int m = sc.count > 0 ? sc.count : a.nb;
-    const int c = sc.count > 0 ? sc.col[blockIdx.x % m] : (int)(blockIdx.x % m);
-    const int piece = blockIdx.x / m;
+    int ci, piece;
+    split_slot(blockIdx.x, m, a.pieces, ci, piece);
+    const int c = sc.count > 0 ? sc.col[ci] : ci;
     if (a.pcg.status[c] != COL_RUNNING) return;
     tlad_column<double, Q, TLAD_SPLIT>(a, g, c, a.pcg.it, a.pcg.first, smraw, piece);
 }
@@ -824,19 +844,21 @@ template <int Q>
 __global__ __launch_bounds__(512) void k_tlad_split_sh(TladArgs a, TladGeom g, SplitCols sc) {
     extern __shared__ __align__(16) unsigned char smraw[];
     const int m = sc.count > 0 ? sc.count : a.nb;
-    const int c = sc.count > 0 ? sc.col[blockIdx.x % m] : (int)(blockIdx.x % m);
-    const int piece = blockIdx.x / m;
+    int ci, piece;
+    split_slot(blockIdx.x, m, a.pieces, ci, piece);
+    const int c = sc.count > 0 ? sc.col[ci] : ci;
     if (a.pcg.status[c] != COL_RUNNING) return;
     tlad_column<double, Q, TLAD_SPLIT_SH>(a, g, c, a.pcg.it, a.pcg.first, smraw, piece);
 }
 
-// Split Hessian products: workgroup b takes piece b / nb of column b % nb
-// (TL/AD in T; the U_B products and the trajectory stay FP64).
+// Split Hessian products: the workgroups take the pieces of the nb columns as
+// split_slot deals them (TL/AD in T; the U_B products and the trajectory stay
+// FP64).
 template <typename T, int Q>
 __global__ __launch_bounds__(512) void k_tlad_split_hv(TladArgs a, TladGeom g) {
     extern __shared__ __align__(16) unsigned char smraw[];
-    const int c = (int)(blockIdx.x % a.nb);
-    const int piece = (int)(blockIdx.x / a.nb);
+    int c, piece;
+    split_slot(blockIdx.x, a.nb, a.pieces, c, piece);
     if (a.active && a.active[c] != COL_RUNNING) return;
     tlad_column<T, Q, TLAD_SPLIT_HV>(a, g, c, 0, 0, smraw, piece);
 }
@@ -846,8 +868,8 @@ __global__ __launch_bounds__(512) void k_tlad_split_hv(TladArgs a, TladGeom g) {
 template <typename T, int Q>
 __global__ __launch_bounds__(512) void k_tlad_split_hv_sh(TladArgs a, TladGeom g) {
     extern __shared__ __align__(16) unsigned char smraw[];
-    const int c = (int)(blockIdx.x % a.nb);
-    const int piece = (int)(blockIdx.x / a.nb);
+    int c, piece;
+    split_slot(blockIdx.x, a.nb, a.pieces, c, piece);
     if (a.active && a.active[c] != COL_RUNNING) return;
     tlad_column<T, Q, TLAD_SPLIT_HV_SH>(a, g, c, 0, 0, smraw, piece);
 }
