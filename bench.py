@@ -532,7 +532,7 @@ def cpu_baseline(cfg, z, target_s):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: --gpus must be 1 (a single GPU holds one EDA "
+        print(json.dumps({"error": "the benchmark runs on one GPU: --gpus must be 1 (a single GPU holds one EDA "
                                    "problem's full member batch; multi-GPU member sharding is not built)"}))
         sys.exit(2)
     cfg = W.config(a.workload)

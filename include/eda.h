@@ -45,7 +45,7 @@ extern "C" {
 #define EDA_ERR_HIP            -3  /* a HIP runtime call failed                                */
 #define EDA_ERR_NOT_SPD        -4  /* Cholesky of Phi^T A Phi failed even after the shift      */
 #define EDA_ERR_ORDER          -5  /* LMP requested before eda_sketch_evd built one            */
-#define EDA_ERR_UNSUPPORTED    -6  /* option not supported by this build (sizes, modes)        */
+#define EDA_ERR_UNSUPPORTED    -6  /* option not supported by the library (sizes, modes)        */
 #define EDA_ERR_SYNC           -7  /* a bounded wait between the pieces of a column (or the   */
                                    /* LMP's tiles) gave up, or the device placed workgroups     */
                                    /* unlike the exchange form expects (eda_set_exchange)       */
