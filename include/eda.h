@@ -99,7 +99,8 @@ extern "C" {
 #define EDA_LMP_FORM_ONE 1       /* eda_set_lmp_form: one launch with tile barriers             */
 
 /* ---- problem description ----
- * Lorenz-96 (numerical-experiments section): n >= 4 cyclic variables, forcing F,
+ * Lorenz-96 (numerical-experiments section): 4 <= n <= 4096 cyclic variables
+ * (a whole column's ring fits one workgroup's registers), forcing F,
  * RK4 step dt, window of nsteps steps.  Observations (direct, R = sigma_o^2 I)
  * at steps s = obs_dt, 2 obs_dt, ..., <= nsteps (time 0 is not observed) of the
  * variables i = obs_x0 + q obs_dx < n.

@@ -38,7 +38,7 @@ def test_workspace_and_normals(name):
     assert b_band > traj + 8 * nt * nv * (cfg["members"] + 1) * 8
 
 
-@pytest.mark.parametrize("bad", [dict(n=3), dict(n=5000), dict(len_b=1.0), dict(obs_x0=40), dict(sigma_o=0.0),
+@pytest.mark.parametrize("bad", [dict(n=3), dict(n=4097), dict(n=5000), dict(len_b=1.0), dict(obs_x0=40), dict(sigma_o=0.0),
                                  dict(members=0), dict(nsteps=2, obs_dt=5),
                                  dict(b_kind="diffusion", diff_steps=9), dict(b_kind="diffusion", diff_steps=0),
                                  dict(b_kind="diffusion", diff_steps=66), dict(b_kind="diffusion", len_b=0.0)])
