@@ -1012,11 +1012,12 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
     // max_ahead checkpoints are outstanding, so the GPU always has queued work.
     // Iterations queued after every column stopped return at once.
     const int check_every = 8, max_ahead = 2;
-    if (!c.h_ck) {
+    // (the events first: a context keeps h_ck only with every event created)
+    for (int i = 0; i < Ctx::CK_SLOTS; i++)
+        if (!c.ck_ev[i]) HIP_TRY(hipEventCreateWithFlags(&c.ck_ev[i], hipEventDisableTiming));
+    if (!c.h_ck)
         HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&c.h_ck),
                               sizeof(int32_t) * Ctx::CK_SLOTS * (size_t)c.max_cols, hipHostMallocDefault));
-        for (int i = 0; i < Ctx::CK_SLOTS; i++) HIP_TRY(hipEventCreateWithFlags(&c.ck_ev[i], hipEventDisableTiming));
-    }
     int ck_issued = 0, ck_done = 0;
     std::vector<std::vector<int16_t>> ck_running;  // running columns at each checkpoint read
     bool none_running = false;
@@ -1353,9 +1354,9 @@ int eda_destroy(eda_ctx *h) {
     if (h->c.h_ck) {
         (void)hipStreamSynchronize(h->c.stream);
         (void)hipHostFree(h->c.h_ck);
-        for (hipEvent_t e : h->c.ck_ev)
-            if (e) (void)hipEventDestroy(e);
     }
+    for (hipEvent_t e : h->c.ck_ev)
+        if (e) (void)hipEventDestroy(e);
     delete h;
     return EDA_OK;
 }
@@ -1572,9 +1573,11 @@ int batch_tune(eda_batch &b) {
     hipStream_t s = b.stream;
     for (size_t i = 0; i < b.probs.size(); i++)
         HIP_TRY(launch_gamma(s, b.probs[i]->n, b.ell[i], b.probs[i]->b, b.probs[i]->sk_phi));
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return EDA_ERR_HIP;
+    }
     int rc = EDA_OK;
     for (auto &k : b.classes) {
         const TladGeom g0 = tlad_geometry(k.n, 0);
