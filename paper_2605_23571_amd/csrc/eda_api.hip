@@ -62,7 +62,7 @@ struct Plan {
     size_t off_hv_v, off_hv_obs, off_hv_lam, off_zero;
     size_t off_phi, off_sy, off_sq, off_sq1, off_ss, off_small, off_eig, off_coef, off_coefu, off_info, off_splitk,
         off_lmpt, off_lmpw, off_sr;
-    size_t off_x, off_r, off_z, off_pp, off_q, off_scal, off_status, off_iters, off_members, off_hist;
+    size_t off_x, off_r, off_z, off_pp, off_q, off_scal, off_status, off_iters, off_start, off_members, off_hist;
     size_t off_p2, off_pqp, off_fin;  // split PCG iterations (banded U_B)
     size_t off_xflags, off_xedges, off_xerr, off_xnseg, off_rzp;  // wave pieces with halo exchange
     size_t off_lsync;                                             // single-launch LMP tile barriers
@@ -207,6 +207,7 @@ Plan make_plan(const eda_config *c) {
     P.off_scal = lay.take(4 * mc * d);
     P.off_status = lay.take(mc * sizeof(int32_t));
     P.off_iters = lay.take(mc * sizeof(int32_t));
+    P.off_start = lay.take(mc * sizeof(int32_t));
     P.off_members = lay.take(mc * sizeof(int32_t));
     P.off_hist = lay.take(mc * (size_t)HIST_CAP * d);
     P.off_p2 = lay.take((banded ? n * mc : 1) * d);
@@ -640,6 +641,7 @@ int eda_setup(const eda_config *cfg, const double *d_normals, void *d_ws, size_t
     c.pc_scal = at<double>(w, P.off_scal);
     c.pc_status = at<int32_t>(w, P.off_status);
     c.pc_iters = at<int32_t>(w, P.off_iters);
+    c.pc_start = at<int32_t>(w, P.off_start);
     c.pc_members = at<int32_t>(w, P.off_members);
     c.pc_hist = at<double>(w, P.off_hist);
     c.hist_cap = HIST_CAP;
@@ -888,7 +890,7 @@ int lmp_apply(Ctx &c, int which, int nb, const double *X, long long ldx, double 
 // (p updated in place), (I + A) p, alpha, x, r, the convergence test.
 // rz_part: the row-block sums of r^T z that the LMP left (null: summed in the kernel).
 int fused_iteration(Ctx &c, int nm, const PcgArgs &a, double *p, double rtol, int it,
-                    const double *rz_part = nullptr) {
+                    const double *rz_part = nullptr, const int32_t *start = nullptr) {
     TladArgs t = tlad_args(c, nm, c.pc_members, nullptr);
     t.obs = c.hv_obs;
     t.pcg.members = c.pc_members;
@@ -905,6 +907,7 @@ int fused_iteration(Ctx &c, int nm, const PcgArgs &a, double *p, double rtol, in
     t.pcg.rtol = rtol;
     t.pcg.it = it;
     t.pcg.first = it == 1 ? 1 : 0;
+    t.pcg.start = start;
     if (rz_part) {
         int rows, nrb;
         lmp_blocks(c.n, &rows, &nrb);
@@ -1006,6 +1009,43 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
         EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status, split ? c.rz_part : nullptr, true));
     }
     const int xch_grid = (c.num_cus < XCH_GRID_MAX ? c.num_cus : XCH_GRID_MAX) & ~7;
+    // Admission.  With the automatic piece choice and shared pieces, more
+    // running columns than half the CUs would leave whole-column iterations,
+    // one column per CU, and so half the device idle.  The solve then starts
+    // only `cap` columns; the others wait (COL_PENDING) and are admitted as
+    // running ones stop, each from its own first iteration (start[c] holds the
+    // loop iteration before it; iteration counts and cost histories are the
+    // column's own).  The control member's columns wait first (with the LMP of
+    // the control's Hessian they need the fewest iterations), then the last
+    // columns; the waiting ones are admitted in column order, the control's
+    // last.  A column admitted at loop iteration s has maxit - s + 1 iterations
+    // left.  Decisions use the checkpoint lists, so they do not depend on timing.
+    const int cap = c.num_cus / 2;
+    const bool defer = split && c.split_force == 0 && nm > cap && nm <= SPLIT_LIST_MAX && cap >= 1 &&
+                       can_share(c, 2ll * cap, 2);
+    std::vector<int16_t> pending;                 // waiting columns, in admission order
+    size_t next_pending = 0;                      // pending[next_pending..] still wait
+    std::vector<std::pair<int, int16_t>> admits;  // (loop iteration, column) of each admission
+    std::vector<char> waits(nm, 0);
+    if (defer) {
+        std::vector<int16_t> order;  // which columns wait first
+        for (int i = 0; i < nm; i++)
+            if (h_members[i] == 0) order.push_back((int16_t)i);
+        for (int i = nm - 1; i >= 0; i--)
+            if (h_members[i] != 0) order.push_back((int16_t)i);
+        order.resize(nm - cap);
+        for (int16_t col : order) waits[col] = 1;
+        for (int i = 0; i < nm; i++)
+            if (waits[i] && h_members[i] != 0) pending.push_back((int16_t)i);
+        for (int i = 0; i < nm; i++)
+            if (waits[i] && h_members[i] == 0) pending.push_back((int16_t)i);
+        HIP_TRY(hipMemsetAsync(c.pc_start, 0, sizeof(int32_t) * nm, s));
+        SplitCols wl{};
+        wl.count = (int32_t)pending.size();
+        for (int i = 0; i < wl.count; i++) wl.col[i] = pending[i];
+        HIP_TRY(launch_col_status(s, wl, COL_RUNNING, COL_PENDING, c.pc_status, nullptr, 0));
+    }
+    const int32_t *d_start = defer ? c.pc_start : nullptr;
     // Convergence checks are pipelined: every check_every iterations the status
     // array is copied to a pinned host slot behind an event; the host reads a
     // checkpoint once its event has completed, and waits only when more than
@@ -1020,6 +1060,7 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                               sizeof(int32_t) * Ctx::CK_SLOTS * (size_t)c.max_cols, hipHostMallocDefault));
     int ck_issued = 0, ck_done = 0;
     std::vector<std::vector<int16_t>> ck_running;  // running columns at each checkpoint read
+    std::vector<int> ck_iter;                      // loop iteration after which each was taken
     bool none_running = false;
     auto consume = [&](bool block) -> int {  // read the oldest outstanding checkpoint
         const int slot = ck_done % Ctx::CK_SLOTS;
@@ -1039,7 +1080,10 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
             for (int i = 0; i < nm; i++)
                 if (st[i] == COL_RUNNING) running.push_back(0);  // only the count is used
         }
-        none_running |= running.empty();
+        // every column stopped: none ran at the checkpoint, none waits, none
+        // was admitted after it
+        const bool later = !admits.empty() && admits.back().first > ck_iter[ck_done];
+        none_running |= running.empty() && next_pending == pending.size() && !later;
         ck_running.push_back(std::move(running));
         ck_done++;
         return 1;
@@ -1070,7 +1114,33 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                     known = &ck_running[j];
                     active = (int)known->size();
                 }
-                if (nm <= SPLIT_LIST_MAX) {
+                if (defer) {
+                    // the list, the columns admitted after its checkpoint, and
+                    // admissions into the room left
+                    std::vector<int16_t> cols;
+                    if (known) {
+                        cols = *known;
+                        for (const auto &ad : admits)
+                            if (ad.first > ck_iter[j]) cols.push_back(ad.second);
+                    } else {
+                        for (int i = 0; i < nm; i++)
+                            if (!waits[i]) cols.push_back((int16_t)i);
+                    }
+                    SplitCols ad{};
+                    while ((int)cols.size() < cap && next_pending < pending.size()) {
+                        const int16_t col = pending[next_pending++];
+                        waits[col] = 0;
+                        admits.push_back({it, col});
+                        cols.push_back(col);
+                        ad.col[ad.count++] = col;
+                    }
+                    if (ad.count > 0)
+                        HIP_TRY(launch_col_status(s, ad, COL_PENDING, COL_RUNNING, c.pc_status, c.pc_start, it - 1));
+                    std::sort(cols.begin(), cols.end());
+                    sc.count = (int)cols.size();
+                    for (int i = 0; i < sc.count; i++) sc.col[i] = cols[i];
+                    active = sc.count;
+                } else if (nm <= SPLIT_LIST_MAX) {
                     sc.count = known ? (int)known->size() : nm;
                     for (int i = 0; i < sc.count; i++) sc.col[i] = known ? (*known)[i] : (int16_t)i;
                 }
@@ -1136,7 +1206,7 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                 } else if (P == 1) {
                     // whole columns: the fused iteration (its update hidden under the
                     // TL/AD work), then the LMP of the new residual
-                    EDA_TRY(fused_iteration(c, nm, a, pbuf[cur], rtol, it, c.rz_part));
+                    EDA_TRY(fused_iteration(c, nm, a, pbuf[cur], rtol, it, c.rz_part, d_start));
                     EDA_TRY(lmp_apply(c, EDA_LMP_P, nm, c.pc_r, n, c.pc_z, n, c.pc_status, c.rz_part, true));
                 } else {
                     // ring pieces (the flags are indexed by the solve's column)
@@ -1165,6 +1235,7 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                         t.pcg.rz_ld = (nm + 15) / 16 * 16;
                         t.pcg.rz_nrb = nrb_;
                     }
+                    t.pcg.start = d_start;
                     EDA_TRY(run_tlad(c, t, sh ? TLAD_SPLIT_SH : TLAD_SPLIT, false, &sc));
                     LmpFin f{};
                     f.q = c.pc_q;
@@ -1178,6 +1249,7 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                     f.iters = c.pc_iters;
                     f.pieces = P;
                     f.it = it;
+                    f.start = d_start;
                     f.hist_cap = c.hist_cap;
                     f.rtol = rtol;
                     f.rr_part = c.lmp_fin;
@@ -1201,6 +1273,7 @@ int eda_pcg_solve(eda_ctx *h, const int32_t *h_members, int32_t nm, double rtol,
                 HIP_TRY(hipMemcpyAsync(c.h_ck + (size_t)slot * c.max_cols, c.pc_status, sizeof(int32_t) * nm,
                                        hipMemcpyDeviceToHost, s));
                 HIP_TRY(hipEventRecord(c.ck_ev[slot], s));
+                ck_iter.push_back(it);
                 ck_issued++;
                 int r;
                 while (ck_done < ck_issued && (r = consume(false)) == 1) {

@@ -12,7 +12,9 @@
 namespace eda {
 
 // Device-side PCG column state.
-enum : int32_t { COL_RUNNING = -1 };
+// Column states besides the EDA_MEMBER_* outcomes: running, or waiting for a
+// free slot (a solve admits more columns than its launches hold as others stop).
+enum : int32_t { COL_RUNNING = -1, COL_PENDING = -2 };
 
 // Everything a context knows; device pointers point into the caller's workspace.
 struct Layout {
@@ -58,7 +60,7 @@ struct Ctx {
     // pcg scratch
     double *pc_x = nullptr, *pc_r = nullptr, *pc_z = nullptr, *pc_p = nullptr, *pc_q = nullptr;
     double *pc_scal = nullptr;  // per column: rho, bnorm, relres, spare
-    int32_t *pc_status = nullptr, *pc_iters = nullptr, *pc_members = nullptr;
+    int32_t *pc_status = nullptr, *pc_iters = nullptr, *pc_members = nullptr, *pc_start = nullptr;
     double *pc_hist = nullptr;
     int hist_cap = 0;
     // split PCG iterations: second p buffer, the pieces' p^T (I + A) p, the
@@ -137,6 +139,9 @@ struct PcgCols {
     // kernel sums r^T z over the column itself
     const double *rz_part;
     int rz_ld, rz_nrb;
+    // per column: the iteration (of this solve's loop) before the column's
+    // first, for columns admitted later; null: every column starts at 1
+    const int32_t *start;
 };
 // One task of a batched persistent launch: problem index and column (a PCG
 // member column, or a sketch column).
@@ -434,6 +439,7 @@ struct LmpFin {
     double rtol;
     double *rr_part, *xbr_part;  // LMP_RB_MAX x ldw each
     const int32_t *nseg;
+    const int32_t *start;  // as PcgCols::start
 };
 size_t lmp_fin_doubles(int ncols);
 hipError_t launch_lmp_fin(hipStream_t s, int n, int k, int nb, const double *S, const double *Sr, const double *coef,
@@ -564,5 +570,9 @@ hipError_t launch_pcg_start(hipStream_t s, const PcgArgs &a);
 hipError_t launch_pcg_alpha(hipStream_t s, const PcgArgs &a, int it);
 hipError_t launch_pcg_beta(hipStream_t s, const PcgArgs &a);
 hipError_t launch_pcg_finish(hipStream_t s, const PcgArgs &a);
+// For the listed columns whose status is `from`: status = to and, when start
+// is given, start[c] = start_it (columns made to wait, or admitted).
+hipError_t launch_col_status(hipStream_t s, const SplitCols &cols, int32_t from, int32_t to, int32_t *status,
+                             int32_t *start, int32_t start_it);
 
 }  // namespace eda

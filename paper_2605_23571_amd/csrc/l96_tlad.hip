@@ -544,8 +544,10 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
                 for (int i = tid; i < n; i += nthr) rz += r[i] * z[i];
                 rz = block_sum(rz, red, g.waves);
             }
+            // a column admitted later starts at its own first iteration
+            const bool first_c = a.pcg.start ? it - a.pcg.start[c] == 1 : first != 0;
             double beta = 0.0;
-            if (!first) {
+            if (!first_c) {
                 if (!(rz > 0.0) || !isfinite(rz)) {
                     if (tid == 0 && piece == 0) a.pcg.status[c] = EDA_MEMBER_BREAKDOWN;
                     return;
@@ -555,7 +557,7 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
             rho = rz;
             if (!SPLIT) {
                 for (int i = tid; i < n; i += nthr) {
-                    double v = first ? z[i] : z[i] + beta * pp[i];
+                    double v = first_c ? z[i] : z[i] + beta * pp[i];
                     pp[i] = v;
                     u[i] = v;
                 }
@@ -564,7 +566,7 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
                 double *pout = a.pcg.p_out + cn;
                 for (int j = tid; j < R; j += nthr) {
                     const int gi = state(j);
-                    const double v = first ? z[gi] : z[gi] + beta * pp[gi];
+                    const double v = first_c ? z[gi] : z[gi] + beta * pp[gi];
                     u[j] = v;
                     if (j >= core_lo && j < core_hi) pout[gi] = v;
                 }
@@ -756,10 +758,11 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
         }
     }
     pq = block_sum(pq, red, g.waves);
+    const int itc = it - (a.pcg.start ? a.pcg.start[c] : 0);  // the column's own iteration
     if (!(pq > 0.0) || !isfinite(pq)) {
         if (tid == 0) {
             a.pcg.status[c] = EDA_MEMBER_BREAKDOWN;
-            a.pcg.iters[c] = it - 1;
+            a.pcg.iters[c] = itc - 1;
         }
         return;
     }
@@ -786,8 +789,8 @@ __device__ __forceinline__ void tlad_column(const TladArgs &a, const TladGeom &g
         const double rn = sqrt(rr);
         a.pcg.scal[4 * c] = rho;
         a.pcg.scal[4 * c + 2] = rn / bnorm;
-        a.pcg.iters[c] = it;
-        if (a.pcg.hist && it < a.pcg.hist_cap) a.pcg.hist[(long long)c * a.pcg.hist_cap + it] = -0.5 * xbr;
+        a.pcg.iters[c] = itc;
+        if (a.pcg.hist && itc < a.pcg.hist_cap) a.pcg.hist[(long long)c * a.pcg.hist_cap + itc] = -0.5 * xbr;
         if (!isfinite(rn)) a.pcg.status[c] = EDA_MEMBER_BREAKDOWN;
         else if (rn <= a.pcg.rtol * bnorm) a.pcg.status[c] = EDA_MEMBER_CONVERGED;
     }

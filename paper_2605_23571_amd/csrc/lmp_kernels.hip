@@ -326,7 +326,7 @@ __device__ __forceinline__ void lmp_expand(int rbx, int tile, int n, int k, int 
     const bool fin_lane = FIN && rbx == 0 && tid < CT && c0 + tid < nb;
     const int fcol = fin_lane ? c0 + tid : 0;
     double rv[LMP_RB_MAX], xr[LMP_RB_MAX], fpq = 0.0, fbn = 0.0, frho = 0.0;
-    int fst = 0;
+    int fst = 0, fit = 0;  // fit: the column's own iteration
     if (FIN) {
 #pragma unroll
         for (int b = 0; b < LMP_RB_MAX; b++) {
@@ -339,6 +339,7 @@ __device__ __forceinline__ void lmp_expand(int rbx, int tile, int n, int k, int 
             fbn = f.scal[4 * fcol + 1];
             frho = f.scal[4 * fcol + 3];
             fst = status[fcol];
+            fit = f.it - (f.start ? f.start[fcol] : 0);
         }
     }
     double4v acc[2] = {double4v{0.0, 0.0, 0.0, 0.0}, double4v{0.0, 0.0, 0.0, 0.0}};
@@ -413,7 +414,7 @@ __device__ __forceinline__ void lmp_expand(int rbx, int tile, int n, int k, int 
         // the iteration's end for column fcol, as in the fused PCG kernel
         if (!(fpq > 0.0) || !isfinite(fpq)) {
             status[fcol] = EDA_MEMBER_BREAKDOWN;
-            f.iters[fcol] = f.it - 1;
+            f.iters[fcol] = fit - 1;
         } else {
             double rr = 0.0, xbr = 0.0;
 #pragma unroll
@@ -424,8 +425,8 @@ __device__ __forceinline__ void lmp_expand(int rbx, int tile, int n, int k, int 
             const double rn = sqrt(rr);
             f.scal[4 * fcol] = frho;
             f.scal[4 * fcol + 2] = rn / fbn;
-            f.iters[fcol] = f.it;
-            if (f.hist && f.it < f.hist_cap) f.hist[(long long)fcol * f.hist_cap + f.it] = -0.5 * xbr;
+            f.iters[fcol] = fit;
+            if (f.hist && fit < f.hist_cap) f.hist[(long long)fcol * f.hist_cap + fit] = -0.5 * xbr;
             if (!isfinite(rn)) status[fcol] = EDA_MEMBER_BREAKDOWN;
             else if (rn <= f.rtol * fbn) status[fcol] = EDA_MEMBER_CONVERGED;
         }

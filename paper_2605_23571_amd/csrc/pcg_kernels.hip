@@ -124,9 +124,21 @@ __global__ __launch_bounds__(PT) void k_pcg_beta(PcgArgs a) {
     if (threadIdx.x == 0) a.scal[4 * c] = rz;
 }
 
+// Columns still running, or never admitted, end as not converged.
 __global__ void k_pcg_finish(PcgArgs a) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < a.nb && a.status[c] == COL_RUNNING) a.status[c] = EDA_MEMBER_NOT_CONVERGED;
+    if (c < a.nb && (a.status[c] == COL_RUNNING || a.status[c] == COL_PENDING))
+        a.status[c] = EDA_MEMBER_NOT_CONVERGED;
+}
+
+__global__ void k_col_status(SplitCols cols, int32_t from, int32_t to, int32_t *status, int32_t *start,
+                             int32_t start_it) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cols.count) return;
+    const int c = cols.col[i];
+    if (status[c] != from) return;
+    status[c] = to;
+    if (start) start[c] = start_it;
 }
 
 }  // namespace
@@ -149,6 +161,12 @@ hipError_t launch_pcg_beta(hipStream_t s, const PcgArgs &a) {
 }
 hipError_t launch_pcg_finish(hipStream_t s, const PcgArgs &a) {
     hipLaunchKernelGGL(k_pcg_finish, dim3((a.nb + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_col_status(hipStream_t s, const SplitCols &cols, int32_t from, int32_t to, int32_t *status,
+                             int32_t *start, int32_t start_it) {
+    if (cols.count < 1 || cols.count > SPLIT_LIST_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_col_status, dim3(1), dim3(SPLIT_LIST_MAX), 0, s, cols, from, to, status, start, start_it);
     return hipGetLastError();
 }
 

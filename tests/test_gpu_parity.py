@@ -758,6 +758,62 @@ def test_split_hessvec_matches_whole_columns(case):
     assert colrel(to_np_cols(ref.contiguous(), n), o.hess(Xs, sel.cpu().numpy())) < 1e-12
 
 
+def test_columns_wait_for_a_free_slot():
+    # More columns than two pieces each hold on the device (141 columns; half
+    # the CUs is 128): 128 start, the control member's column and the last 12
+    # wait, and are admitted, each from its own first iteration, as running
+    # ones stop.  Every column reaches its own solution with its own
+    # iteration count and cost history (against the same members solved in
+    # calls of at most 128 columns, where nothing waits, and against the
+    # oracle's exact solution); a repeat gives the same bits; with a small
+    # maxit the waiting columns end not converged after 0 iterations.
+    cap = torch.cuda.get_device_properties(0).multi_processor_count // 2
+    cfg = W.config("C2", n=1001, nsteps=12, obs_dt=3, obs_dx=2, obs_x0=1, members=cap + 12, ell=16, k=16,
+                   spinup=200)
+    nm = cfg["members"] + 1
+    z = W.problem_normals(cfg)
+    g = eda.Problem(cfg, z)
+    g.sketch_evd("rhs_diff")
+    members = np.arange(nm)
+    waiting = [0] + list(range(cap + 1, nm))
+    print(f"[admit] n=1001, {nm} columns, {cap} slots; waiting {waiting}", flush=True)
+    out = g.pcg(members, rtol=1e-10, maxit=1000, history=True)
+    assert np.all(out["status"] == eda.EDA_MEMBER_CONVERGED)
+    assert np.all(out["relres"] <= 1e-10)
+    ref_it = np.zeros(nm, dtype=np.int64)
+    ref_dz = np.zeros((nm, cfg["n"]))
+    ref_h = {}
+    for part in (members[:cap], members[cap:]):
+        r = g.pcg(part, rtol=1e-10, maxit=1000, history=True)
+        assert np.all(r["status"] == eda.EDA_MEMBER_CONVERGED)
+        ref_it[part] = r["iters"]
+        ref_dz[part] = r["dz"].cpu().numpy()
+        for i, m in enumerate(part):
+            ref_h[m] = r["hist"][i]
+    d = np.abs(out["iters"] - ref_it)
+    dz = out["dz"].cpu().numpy()
+    e = max(elrel(dz[m], ref_dz[m]) for m in members)
+    print(f"[admit] iterations of the waiting columns {out['iters'][waiting].tolist()} (alone "
+          f"{ref_it[waiting].tolist()}); max |diff| over all {int(d.max())}; solutions vs calls without "
+          f"waiting {e:.1e} element-wise", flush=True)
+    assert (d <= np.maximum(3, (0.05 * ref_it).astype(int))).all()
+    assert e < 1e-8
+    o = O.Problem(cfg, z)
+    for m in (0, 1, nm - 1):
+        assert elrel(dz[m], O.exact_solution(o, m)) < 1e-8, m
+        h, hr = out["hist"][m][: out["iters"][m] + 1], ref_h[m][: ref_it[m] + 1]
+        assert h[0] == 0.0 and np.all(np.diff(h) <= 1e-10 * abs(h[-1]))  # the column's own history
+        k = min(h.size, hr.size) - 1
+        assert abs(h[k] - hr[k]) <= 1e-8 * abs(hr[k]), (m, h[k], hr[k])
+    again = g.pcg(members, rtol=1e-10, maxit=1000)
+    assert torch.equal(again["dz"], out["dz"])  # admissions do not depend on timing
+    few = g.pcg(members, rtol=1e-10, maxit=6)
+    assert np.all(few["status"] == eda.EDA_MEMBER_NOT_CONVERGED)
+    assert np.all(few["iters"][waiting] == 0)
+    assert np.all(np.delete(few["iters"], waiting) == 6)
+    g.close()
+
+
 def test_pieces_that_only_the_shared_form_fits():
     # n = 2048, N = 40: independent ring pieces need ceil(n / P) + 24 N + 4 w
     # states, more than n for every P, so before the shared form no column of
