@@ -599,9 +599,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(act_per_launch),
-                     "kernel": "k_tlad<double, Q, 3> and k_tlad_split_sh<Q> (Hessian part of a PCG iteration: U_B, "
-                               "TL, AD, U_B, (I + A) p; whole columns with the update fused, or 2-8 pieces per "
-                               "column sharing the observed increments)",
+                     "kernel": "k_tlad_split_sh<Q> (Hessian part of a PCG iteration: U_B, TL, AD, U_B, (I + A) p "
+                               "on 2-8 pieces per column sharing the observed increments; at most half the CUs' "
+                               "worth of columns run, the others wait for a free slot; k_tlad<double, Q, 3> whole "
+                               "columns where pieces do not fit)",
                      "bytes_per_column": bpc, "avg_launch_ms": round(avg_ms, 4),
                      "launches": chosen["tlad_launches"], "timed_launches": chosen["tlad_timed"], "active_column_iterations": chosen["active_cols"],
                      "kernel_sha": kernel_sha(),

@@ -254,7 +254,14 @@ int eda_lmp_apply_noalloc(eda_ctx *ctx, int32_t which, int32_t nb, const double 
  * (eda_set_exchange): they assume that the launch has the device to itself,
  * so a solve whose kernels overlap other work on the device (other streams
  * or contexts) may see a wait give up (EDA_ERR_SYNC); such callers set
- * EDA_XCH_OFF, whose pieces never wait. */
+ * EDA_XCH_OFF, whose pieces never wait.  Admission (banded U_B with the LMP,
+ * automatic pieces, EDA_XCH_OBS): when nm exceeds half the device's compute
+ * units (each running column then takes at least two pieces), only that many
+ * columns start; the control member's columns wait first, then the last ones,
+ * and waiting columns start, in column order with the control's last, as
+ * running ones stop.  A column's iteration count and cost history are its
+ * own; one that starts at loop iteration s has maxit - s + 1 iterations left,
+ * and one that never starts ends EDA_MEMBER_NOT_CONVERGED after 0. */
 int eda_pcg_solve(eda_ctx *ctx, const int32_t *h_members, int32_t nm, double rtol, int32_t maxit,
                   int32_t use_lmp, double *d_DZ, int64_t ldz, int32_t *h_iters, double *h_relres,
                   int32_t *h_status, double *h_cost_hist);
@@ -390,7 +397,8 @@ int eda_set_geometry(eda_ctx *ctx, int32_t waves, int32_t tb);
  * p^T (I + A) p are added in piece order.  pieces = 0 (the default): of 1, 2,
  * 3, 4 and 8 with P x (members still running at a recent convergence check,
  * or columns of the product) <= the device's compute units, the P whose ring
- * is shortest; 1 to 8: that P in every iteration and product.  Solutions
+ * is shortest (with the admission of eda_pcg_solve); 1 to 8: that P in
+ * every iteration and product, every column from the start.  Solutions
  * agree with P = 1 to rounding; Hessian products are bit-identical.  Errors:
  * EDA_ERR_UNSUPPORTED if the context is not banded, or P > 1 pieces fit
  * neither form (rings longer than n, pieces shorter than 8 N + w for the
